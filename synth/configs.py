@@ -1,0 +1,247 @@
+"""Seeded generators for the five synthetic workloads and for random test problems.
+
+The paper's own data (high-resolution photographs with user seeds, an MRI volume with CNN unaries, an ink
+drawing for the curvature experiment) is not available, so these generators stand in for it with the same
+structure: Gaussian log-likelihood-ratio unaries (Eq. 2), contrast-sensitive or constant Potts weights
+(Sec. 1, the Potts paragraph), 2D 4/8-connected and 3D 6-connected grids (the "kernel size 3" square /
+spherical neighbourhoods of the experimental setup), and a non-submodular grid with repulsive edges
+(the submodularity footnote of Sec. 1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+# ADMM schedule defaults in input-energy units (weights and unaries are x1000 integers).  The paper's
+# mu0 = 100 (2D) / 500 (3D) are in unstated units; with x1000 inputs the equivalent sweep picks these.
+DEFAULT_MU0_2D = 1000
+DEFAULT_MU0_3D = 5000
+DEFAULT_EPS_Q16 = 6554  # eps = 0.1 in Q16.16
+DEFAULT_MAX_ITER = 50
+
+
+def half_stencil(ndim: int, conn: int) -> List[Tuple[int, int, int]]:
+    """Half-stencil offsets (dx, dy, dz); the full stencil is these and their negations."""
+    if ndim == 2 and conn == 4:
+        return [(1, 0, 0), (0, 1, 0)]
+    if ndim == 2 and conn == 8:
+        return [(1, 0, 0), (0, 1, 0), (1, 1, 0), (-1, 1, 0)]
+    if ndim == 3 and conn == 6:
+        return [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    raise ValueError(f"unsupported stencil ndim={ndim} conn={conn}")
+
+
+def lambda_q8(lam: float) -> int:
+    """lambda quantised to 1/256, rounded half away from zero."""
+    v = abs(lam) * 256.0
+    q = int(math.floor(v + 0.5))
+    return q if lam >= 0 else -q
+
+
+def _round(x: np.ndarray) -> np.ndarray:
+    return np.floor(x + 0.5)
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    dims: Tuple[int, int, int]          # (W, H, D); D = 1 in 2D
+    ndim: int
+    conn: int
+    u: np.ndarray                       # int32[n]
+    w: np.ndarray                       # int32[h, n]
+    lam_q8: int
+    block: Tuple[int, int, int]
+    overlap: Tuple[int, int, int]
+    mu0: int
+    mu_num: int = 21
+    mu_den: int = 20
+    eps_q16: int = DEFAULT_EPS_Q16
+    max_iter: int = DEFAULT_MAX_ITER
+    solver: str = "maxflow"             # "maxflow" | "exhaustive"
+    truth: Optional[np.ndarray] = None  # generating foreground mask (for reporting only)
+
+    @property
+    def n(self) -> int:
+        return int(self.dims[0] * self.dims[1] * self.dims[2])
+
+    def offsets(self):
+        return half_stencil(self.ndim, self.conn)
+
+
+def _weights_from_features(feat: np.ndarray, ndim: int, conn: int, sigma_w: float,
+                           scale: float = 1000.0) -> np.ndarray:
+    """Contrast-sensitive weights w = round(scale * exp(-|dx|^2 / (2 sigma^2)) / d) on the half-stencil.
+
+    feat has shape (D, H, W, C).  d is the Euclidean length of the offset (1 or sqrt 2)."""
+    D, H, W, _ = feat.shape
+    offs = half_stencil(ndim, conn)
+    n = W * H * D
+    out = np.zeros((len(offs), n), dtype=np.int64)
+    for o, (dx, dy, dz) in enumerate(offs):
+        wv = np.zeros((D, H, W), dtype=np.float64)
+        z0, z1 = max(0, -dz), D - max(0, dz)
+        y0, y1 = max(0, -dy), H - max(0, dy)
+        x0, x1 = max(0, -dx), W - max(0, dx)
+        a = feat[z0:z1, y0:y1, x0:x1]
+        b = feat[z0 + dz:z1 + dz, y0 + dy:y1 + dy, x0 + dx:x1 + dx]
+        d2 = np.sum((a - b) ** 2, axis=-1)
+        dist = math.sqrt(dx * dx + dy * dy + dz * dz)
+        wv[z0:z1, y0:y1, x0:x1] = _round(scale * np.exp(-d2 / (2.0 * sigma_w ** 2)) / dist)
+        out[o] = wv.reshape(-1)
+    return out.astype(np.int32)
+
+
+def _constant_weights(dims, ndim, conn, value) -> np.ndarray:
+    W, H, D = dims
+    offs = half_stencil(ndim, conn)
+    out = np.zeros((len(offs), W * H * D), dtype=np.int32)
+    zz, yy, xx = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
+    for o, (dx, dy, dz) in enumerate(offs):
+        ok = ((xx + dx >= 0) & (xx + dx < W) & (yy + dy >= 0) & (yy + dy < H)
+              & (zz + dz >= 0) & (zz + dz < D))
+        out[o] = np.where(ok.reshape(-1), value, 0)
+    return out
+
+
+def _gauss_llr(img: np.ndarray, mu_fg: float, mu_bg: float, sigma: float, channels: bool = False) -> np.ndarray:
+    """u = 1000 * (log p(bg|x) - log p(fg|x)) for equal-variance Gaussians (summed over a last channel axis)."""
+    llr = ((img - mu_fg) ** 2 - (img - mu_bg) ** 2) / (2.0 * sigma ** 2)
+    if channels:
+        llr = llr.sum(axis=-1)
+    return _round(1000.0 * llr).reshape(-1).astype(np.int64)
+
+
+def config1(seed: int = 0, size: int = 64, mu0: int = DEFAULT_MU0_2D) -> Problem:
+    """64x64 grey disk (r = 20) + N(0, 0.15^2); 4-connected contrast Potts; lambda = 1; 16x16 blocks, o = 1."""
+    rng = np.random.default_rng(seed)
+    c = size / 2.0
+    r = 20.0 * size / 64.0
+    yy, xx = np.mgrid[0:size, 0:size]
+    fg = (xx - c) ** 2 + (yy - c) ** 2 <= r * r
+    img = np.where(fg, 0.7, 0.3) + rng.normal(0.0, 0.15, size=(size, size))
+    u = _gauss_llr(img, 0.7, 0.3, 0.15)
+    w = _weights_from_features(img[None, :, :, None], 2, 4, 0.1)
+    return Problem("config1_disk64_4conn", (size, size, 1), 2, 4, u.astype(np.int32), w,
+                   lambda_q8(1.0), (16, 16, 1), (1, 1, 0), mu0, max_iter=50,
+                   truth=fg.reshape(-1).astype(np.uint8))
+
+
+def _ellipse_mask(rng, W, H, count):
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    fg = np.zeros((H, W), dtype=bool)
+    for _ in range(count):
+        cx, cy = rng.uniform(0.0, W), rng.uniform(0.0, H)
+        a, b = rng.uniform(20.0, 120.0), rng.uniform(20.0, 120.0)
+        th = rng.uniform(0.0, math.pi)
+        dx, dy = xx - cx, yy - cy
+        xr = dx * math.cos(th) + dy * math.sin(th)
+        yr = -dx * math.sin(th) + dy * math.cos(th)
+        fg |= (xr / a) ** 2 + (yr / b) ** 2 <= 1.0
+    return fg
+
+
+def config2(seed: int = 0, W: int = 512, H: int = 512, mu0: int = DEFAULT_MU0_2D) -> Problem:
+    """512x512x3 image of 5 random ellipses + N(0, 0.1^2) per channel; 8-connected contrast weights
+    (scale 1000, diagonals / sqrt 2); lambda = 2; 32x32 blocks, o = 2."""
+    rng = np.random.default_rng(seed)
+    fg = _ellipse_mask(rng, W, H, 5)
+    base = np.where(fg, 0.7, 0.3)[:, :, None]
+    img = base + rng.normal(0.0, 0.1, size=(H, W, 3))
+    u = _gauss_llr(img, 0.7, 0.3, 0.1, channels=True)
+    w = _weights_from_features(img[None], 2, 8, 0.1)
+    return Problem(f"config2_ellipses{W}x{H}_8conn", (W, H, 1), 2, 8, u.astype(np.int32), w,
+                   lambda_q8(2.0), (32, 32, 1), (2, 2, 0), mu0,
+                   truth=fg.reshape(-1).astype(np.uint8))
+
+
+def config3(seed: int = 0, dims=(128, 128, 64), mu0: int = DEFAULT_MU0_3D) -> Problem:
+    """128x128x64 volume with 3 random spheres (r in U[8, 24]) + N(0, 0.2^2); 6-connected constant Potts
+    w = 1000; lambda = 1.5; 16^3 blocks, o = 1."""
+    W, H, D = dims
+    rng = np.random.default_rng(seed)
+    zz, yy, xx = np.mgrid[0:D, 0:H, 0:W].astype(np.float64)
+    fg = np.zeros((D, H, W), dtype=bool)
+    for _ in range(3):
+        cx, cy, cz = rng.uniform(0, W), rng.uniform(0, H), rng.uniform(0, D)
+        r = rng.uniform(8.0, 24.0)
+        fg |= (xx - cx) ** 2 + (yy - cy) ** 2 + (zz - cz) ** 2 <= r * r
+    img = np.where(fg, 0.7, 0.3) + rng.normal(0.0, 0.2, size=(D, H, W))
+    u = _gauss_llr(img, 0.7, 0.3, 0.2)
+    w = _constant_weights(dims, 3, 6, 1000)
+    return Problem(f"config3_spheres{W}x{H}x{D}_6conn", (W, H, D), 3, 6, u.astype(np.int32), w,
+                   lambda_q8(1.5), (16, 16, 16), (1, 1, 1), mu0,
+                   truth=fg.reshape(-1).astype(np.uint8))
+
+
+def config4(seed: int = 0, size: int = 256, mu0: int = DEFAULT_MU0_2D) -> Problem:
+    """Non-submodular 256x256 4-connected grid: u ~ U{-1000..1000}; each edge repulsive with p = 0.3
+    (w ~ U{-500..-50}) else attractive (w ~ U{50..500}); lambda = 1; 4x4 blocks, o = 1; exhaustive solver."""
+    rng = np.random.default_rng(seed)
+    n = size * size
+    u = rng.integers(-1000, 1001, size=n).astype(np.int32)
+    offs = half_stencil(2, 4)
+    w = np.zeros((len(offs), n), dtype=np.int32)
+    yy, xx = np.mgrid[0:size, 0:size]
+    for o, (dx, dy, _) in enumerate(offs):
+        rep = rng.random(n) < 0.3
+        neg = rng.integers(-500, -49, size=n)
+        pos = rng.integers(50, 501, size=n)
+        ok = ((xx + dx < size) & (yy + dy < size) & (xx + dx >= 0)).reshape(-1)
+        w[o] = np.where(ok, np.where(rep, neg, pos), 0)
+    return Problem(f"config4_nonsubmodular{size}_4conn", (size, size, 1), 2, 4, u, w, lambda_q8(1.0),
+                   (4, 4, 1), (1, 1, 0), mu0, solver="exhaustive")
+
+
+SERVE_SIDES = (128, 256, 512, 1024, 2048)
+
+
+def config5_request(r: int, mu0: int = DEFAULT_MU0_2D) -> Problem:
+    """Serving request r (seed r + 1): grey disk image as config 1 at H in {128..2048}, W = round(H * U[0.5, 2]),
+    disk radius 20 * min(H, W) / 64 centred; 8-connected contrast weights (sigma_w = 0.1, diagonals / sqrt 2);
+    lambda ~ U[0.5, 3].  The block partition is left to the caller (block = overlap = 0)."""
+    rng = np.random.default_rng(r + 1)
+    H = int(rng.choice(SERVE_SIDES))
+    W = int(_round(np.float64(H * rng.uniform(0.5, 2.0))))
+    lam = float(rng.uniform(0.5, 3.0))
+    cx, cy = W / 2.0, H / 2.0
+    rad = 20.0 * min(H, W) / 64.0
+    yy, xx = np.mgrid[0:H, 0:W]
+    fg = (xx - cx) ** 2 + (yy - cy) ** 2 <= rad * rad
+    img = np.where(fg, 0.7, 0.3) + rng.normal(0.0, 0.15, size=(H, W))
+    u = _gauss_llr(img, 0.7, 0.3, 0.15)
+    w = _weights_from_features(img[None, :, :, None], 2, 8, 0.1)
+    return Problem(f"config5_req{r}_{W}x{H}", (W, H, 1), 2, 8, u.astype(np.int32), w, lambda_q8(lam),
+                   (0, 0, 0), (0, 0, 0), mu0, truth=fg.reshape(-1).astype(np.uint8))
+
+
+def config5_trace(n_requests: int = 2000, mean_gap_s: float = 0.005, seed: int = 0) -> np.ndarray:
+    """Poisson arrival times (seconds) for the serving workload: exponential gaps, mean 5 ms (200 req/s)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(mean_gap_s, size=n_requests))
+
+
+def random_problem(seed: int, dims, conn: int, block, overlap, lam_q8: int = 256,
+                   u_range=(-3000, 3000), w_range=(0, 1000), neg_frac: float = 0.0,
+                   mu0: int = DEFAULT_MU0_2D, solver: str = "maxflow") -> Problem:
+    """Uniform random integer unaries and weights (a fraction neg_frac of edges negated) on any grid."""
+    rng = np.random.default_rng(seed)
+    W, H, D = dims
+    ndim = 3 if conn == 6 else 2
+    n = W * H * D
+    u = rng.integers(u_range[0], u_range[1] + 1, size=n).astype(np.int32)
+    offs = half_stencil(ndim, conn)
+    zz, yy, xx = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
+    w = np.zeros((len(offs), n), dtype=np.int32)
+    for o, (dx, dy, dz) in enumerate(offs):
+        ok = ((xx + dx >= 0) & (xx + dx < W) & (yy + dy >= 0) & (yy + dy < H)
+              & (zz + dz >= 0) & (zz + dz < D)).reshape(-1)
+        vals = rng.integers(w_range[0], w_range[1] + 1, size=n)
+        if neg_frac > 0:
+            vals = np.where(rng.random(n) < neg_frac, -vals, vals)
+        w[o] = np.where(ok, vals, 0)
+    return Problem(f"random{seed}_{W}x{H}x{D}_{conn}", (W, H, D), ndim, conn, u, w, lam_q8,
+                   tuple(block), tuple(overlap), mu0, solver=solver)

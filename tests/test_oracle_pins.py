@@ -1,0 +1,494 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics (no GPU).
+
+Each test names the passage it checks.  None of them re-types the oracle's own formula: they use exact
+rational identities from the proof of Theorem 1, closed forms derived by hand from the matrix definitions,
+a generic least-squares solve for Eq. (10), brute-force enumeration for the block solver, and special cases
+whose answer is known in closed form.
+"""
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dope
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+# --------------------------------------------------------------------------------------------------------
+# helpers written independently of the oracle's matrix code
+# --------------------------------------------------------------------------------------------------------
+
+def neighbours(problem):
+    """dict i -> list of (j, w_ij) from the half-stencil arrays directly (full stencil)."""
+    W_, H_, D_ = problem.dims
+    nb = {i: [] for i in range(problem.n)}
+    for o, (dx, dy, dz) in enumerate(synth.half_stencil(problem.ndim, problem.conn)):
+        for i in range(problem.n):
+            wv = int(problem.w[o][i])
+            if wv == 0:
+                continue
+            x, y, z = i % W_, (i // W_) % H_, i // (W_ * H_)
+            j = (x + dx) + W_ * ((y + dy) + H_ * (z + dz))
+            nb[i].append((j, wv))
+            nb[j].append((i, wv))
+    return nb
+
+
+def block_sets(problem):
+    blocks = dope.make_blocks(problem.dims, problem.block, problem.overlap)
+    return [list(map(int, b.idx)) for b in blocks]
+
+
+def multiplicities(problem, bsets):
+    q = [0] * problem.n
+    for b in bsets:
+        for i in b:
+            q[i] += 1
+    return q
+
+
+def tiny_problem(seed, dims, conn, block, overlap, neg_frac=0.0):
+    return synth.random_problem(seed, dims, conn, block, overlap, lam_q8=384, u_range=(-900, 900),
+                                w_range=(0, 700), neg_frac=neg_frac)
+
+
+TINY = [
+    ((5, 7, 1), 4, (3, 3, 1), (1, 1, 0)),
+    ((7, 5, 1), 8, (3, 4, 1), (1, 1, 0)),
+    ((6, 6, 1), 4, (4, 4, 1), (0, 0, 0)),
+    ((9, 7, 1), 8, (5, 5, 1), (2, 2, 0)),
+    ((4, 4, 4), 6, (3, 3, 3), (1, 1, 1)),
+    ((5, 4, 3), 6, (3, 2, 2), (1, 0, 0)),
+]
+
+
+# --------------------------------------------------------------------------------------------------------
+# block partition and Proposition 1
+# --------------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,B,o,count", [(64, 16, 1, 5), (512, 32, 2, 17), (128, 16, 1, 9), (64, 16, 1, 5),
+                                          (256, 4, 1, 85), (10, 16, 2, 1), (16, 16, 3, 1), (17, 16, 3, 2)])
+def test_partition_counts(N, B, o, count):
+    iv = dope.partition_axis(N, B, o)
+    assert len(iv) == count
+    assert iv[0][0] == 0 and iv[-1][1] == N
+    for (a0, a1), (b0, b1) in zip(iv, iv[1:]):
+        assert a1 - b0 == o                      # consecutive blocks share exactly o pixels
+        assert a1 - a0 == B
+    assert iv[-1][1] - iv[-1][0] > o or len(iv) == 1
+
+
+def test_partition_block_counts_of_workloads():
+    for dims, B, o, K in [((64, 64, 1), (16, 16, 1), (1, 1, 0), 25), ((512, 512, 1), (32, 32, 1), (2, 2, 0), 289),
+                          ((128, 128, 64), (16, 16, 16), (1, 1, 1), 405), ((256, 256, 1), (4, 4, 1), (1, 1, 0), 7225)]:
+        blocks = dope.make_blocks(dims, B, o)
+        assert len(blocks) == K
+    blocks = dope.make_blocks((64, 64, 1), (16, 16, 1), (1, 1, 0))
+    assert sum(len(b.idx) for b in blocks) == 4624
+
+
+@pytest.mark.parametrize("case", TINY)
+def test_q_counts_blocks(case):
+    """Q = sum_k S_k^T S_k is diagonal with q_ii = number of blocks containing pixel i (Prop. 1)."""
+    dims, conn, block, overlap = case
+    p = tiny_problem(1, dims, conn, block, overlap)
+    dec = dope.decompose(p)
+    bsets = block_sets(p)
+    assert list(dec.q) == multiplicities(p, bsets)
+    assert set(np.unique(dec.q)) <= {1, 2, 4, 8}
+
+
+# --------------------------------------------------------------------------------------------------------
+# Theorem 1: exact identity of the reformulation at a consistent point
+# --------------------------------------------------------------------------------------------------------
+
+def _dense_frac(m, scale=64):
+    d = m.toarray()
+    return [[Fraction(int(v), scale) for v in row] for row in d]
+
+
+@pytest.mark.parametrize("case", TINY)
+@pytest.mark.parametrize("neg", [0.0, 0.3])
+def test_theorem1_identity_exact(case, neg):
+    """With y^_k = S_k y, sum_k (u^_k + lam (C_k + R_k S_k) y)^T y^_k + lam sum_k y^_k^T L^_k y^_k equals
+    u^T y + lam y^T L y (Eq. 3), for binary y and for real y (Theorem 1, proof in the appendix)."""
+    dims, conn, block, overlap = case
+    p = tiny_problem(2, dims, conn, block, overlap, neg_frac=neg)
+    dec = dope.decompose(p)
+    nb = neighbours(p)
+    lam = Fraction(p.lam_q8, 256)
+    rng = np.random.default_rng(3)
+    for trial in range(3):
+        if trial == 0:
+            y = [Fraction(int(v)) for v in rng.integers(0, 2, p.n)]
+        else:
+            y = [Fraction(int(v), 7) for v in rng.integers(-7, 15, p.n)]
+        # right-hand side: Eq. (3) written from the edge list
+        rhs = sum(Fraction(int(p.u[i])) * y[i] for i in range(p.n))
+        for i in range(p.n):
+            for j, wv in nb[i]:
+                if i < j:
+                    rhs += lam * wv * (y[i] - y[j]) ** 2
+        lhs = Fraction(0)
+        for k, blk in enumerate(dec.blocks):
+            idx = list(map(int, blk.idx))
+            yk = [y[i] for i in idx]
+            M = _dense_frac(dec.M64[k])
+            What = _dense_frac(dec.W64[k])
+            for a, i in enumerate(idx):
+                uh = Fraction(int(p.u[i]), int(dec.q[i]))
+                g = sum(M[a][j] * y[j] for j in range(p.n) if M[a][j] != 0)
+                lhs += (uh + lam * g) * yk[a]
+            # y^T L^ y = sum_{a<b} W^_ab (y_a - y_b)^2
+            m = len(idx)
+            for a in range(m):
+                for b in range(a + 1, m):
+                    if What[a][b] != 0:
+                        lhs += lam * What[a][b] * (yk[a] - yk[b]) ** 2
+        assert lhs == rhs
+
+
+@pytest.mark.parametrize("case", TINY)
+def test_coupling_matches_hand_closed_form(case):
+    """[(C_k + R_k S_k) y]_i = sum_{j in N(i)} w_ij (q_j - [j in k]) / (q_i q_j) (y_i - y_j), and the transpose
+    [(C_k + R_k S_k)^T y^]_m = [m in k] y^_m sum_j w_mj (q_j - [j in k])/(q_m q_j)
+                               - (q_m - [m in k]) sum_{i in k, i in N(m)} w_im y^_i / (q_i q_m),
+    both derived by hand from the definitions of C_k and R_k in Theorem 1."""
+    dims, conn, block, overlap = case
+    p = tiny_problem(4, dims, conn, block, overlap, neg_frac=0.2)
+    dec = dope.decompose(p)
+    nb = neighbours(p)
+    bsets = block_sets(p)
+    q = multiplicities(p, bsets)
+    rng = np.random.default_rng(5)
+    y = rng.integers(-50000, 120000, p.n)
+    for k, idx in enumerate(bsets):
+        ink = set(idx)
+        # forward
+        got = dec.M64[k] @ y
+        for a, i in enumerate(idx):
+            exp = Fraction(0)
+            for j, wv in nb[i]:
+                exp += Fraction(wv * (q[j] - (j in ink)), q[i] * q[j]) * int(y[i] - y[j])
+            assert Fraction(int(got[a]), 64) == exp
+        # transpose
+        yh = rng.integers(0, 2, len(idx))
+        got_t = dec.M64[k].T @ yh
+        pos = {i: a for a, i in enumerate(idx)}
+        for m in range(p.n):
+            exp = Fraction(0)
+            if m in ink:
+                exp += int(yh[pos[m]]) * sum(Fraction(wv * (q[j] - (j in ink)), q[m] * q[j]) for j, wv in nb[m])
+            exp -= (q[m] - (m in ink)) * sum(Fraction(wv * int(yh[pos[i]]), q[i] * q[m])
+                                              for i, wv in nb[m] if i in ink)
+            assert Fraction(int(got_t[m]), 64) == exp
+
+
+def test_chain_micro_example():
+    """Chain 1-2-3 (weights 5 and 7), blocks {1,2} and {2,3}, q = (1, 2, 1):
+    g_{1,1} = (w12/2)(y1 - y2), g_{1,2} = (w23/2)(y2 - y3), g_{2,2} = (w12/2)(y2 - y1), g_{2,3} = (w23/2)(y3 - y2)."""
+    p = synth.Problem("chain3", (3, 1, 1), 2, 4, np.zeros(3, np.int32),
+                      np.array([[5, 7, 0], [0, 0, 0]], np.int32), 256, (2, 1, 1), (1, 0, 0), 1000)
+    dec = dope.decompose(p)
+    assert list(dec.q) == [1, 2, 1]
+    y = np.array([3, 11, 2], dtype=np.int64)
+    g1 = dec.M64[0] @ y
+    g2 = dec.M64[1] @ y
+    assert [Fraction(int(v), 64) for v in g1] == [Fraction(5, 2) * (3 - 11), Fraction(7, 2) * (11 - 2)]
+    assert [Fraction(int(v), 64) for v in g2] == [Fraction(5, 2) * (11 - 3), Fraction(7, 2) * (2 - 11)]
+
+
+# --------------------------------------------------------------------------------------------------------
+# Eq. (10) is the minimiser of Eq. (9); Eq. (11) update
+# --------------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", TINY[:4])
+def test_eq10_is_least_squares_minimiser(case):
+    """Minimise lam sum_k y^_k^T M_k y + mu/2 sum_k ||S_k y - (y^_k + a_k)||^2 with a generic least-squares
+    solver (the objective is written as an augmented least-squares system); the oracle's Q16.16 update must
+    equal floor(2^16 y*) up to the solver's rounding."""
+    dims, conn, block, overlap = case
+    p = tiny_problem(6, dims, conn, block, overlap)
+    dec = dope.decompose(p)
+    rng = np.random.default_rng(7)
+    tot = int(dec.offsets[-1])
+    yhat = rng.integers(0, 2, tot).astype(np.uint8)
+    A = rng.integers(-40000, 40000, tot).astype(np.int64)
+    M = 1234
+    lam = p.lam_q8 / 256.0
+    # stack rows sqrt(mu/2) (S_k y - b_k) and fold the linear term into the least-squares target:
+    # lam g^T y + mu/2 ||S y - b||^2 = mu/2 ||S y - (b - lam/mu Q^-1-free correction)||^2 is not separable,
+    # so solve the normal equations of the full quadratic with lstsq on [sqrt(mu) S] and target.
+    rows, tgt = [], []
+    lin = np.zeros(p.n)
+    for k, Sk in enumerate(dec.S):
+        a, b = dec.offsets[k], dec.offsets[k + 1]
+        Sd = Sk.toarray().astype(float)
+        rows.append(np.sqrt(M) * Sd)
+        tgt.append(np.sqrt(M) * (yhat[a:b] + A[a:b] / 65536.0))
+        lin += lam * (dec.M64[k].T @ yhat[a:b].astype(np.int64)) / 64.0
+    Amat = np.vstack(rows)
+    # gradient: Amat^T Amat y - Amat^T t + lin = 0  ->  least squares with shifted target
+    t = np.concatenate(tgt)
+    shift = np.linalg.lstsq(Amat.T, lin, rcond=None)[0]    # Amat^T shift = lin
+    ystar = np.linalg.lstsq(Amat, t - shift, rcond=None)[0]
+    got = dope.consensus(dec, yhat, A, M)
+    assert np.all(np.abs(got - np.floor(ystar * 65536.0)) <= 1)
+
+
+def test_iteration_applies_eq11():
+    p = tiny_problem(8, (9, 7, 1), 8, (5, 5, 1), (2, 2, 0))
+    dec = dope.decompose(p)
+    st = dope.initial_state(dec, 1500)
+    new, _ = dope.iterate(dec, st, threads=1)
+    for k, Sk in enumerate(dec.S):
+        a, b = dec.offsets[k], dec.offsets[k + 1]
+        assert np.array_equal(new.A[a:b], st.A[a:b] + 65536 * new.yhat[a:b].astype(np.int64) - Sk @ new.Y)
+    assert new.M == 1500 * 21 // 20
+
+
+# --------------------------------------------------------------------------------------------------------
+# block sub-problem solvers against brute force and duality
+# --------------------------------------------------------------------------------------------------------
+
+def brute_minimisers(un, edges):
+    n = len(un)
+    best, sols = None, []
+    for code in range(1 << n):
+        x = [(code >> i) & 1 for i in range(n)]
+        e = sum(un[i] * x[i] for i in range(n)) + sum(c * abs(x[a] - x[b]) for a, b, c in edges)
+        if best is None or e < best:
+            best, sols = e, [code]
+        elif e == best:
+            sols.append(code)
+    return best, sols
+
+
+def random_subproblem(rng, n, allow_neg=False, tie_prone=False):
+    scale = 3 if tie_prone else 1000
+    un = rng.integers(-scale, scale + 1, n)
+    edges = []
+    for a in range(n):
+        for b in range(a + 1, n):
+            if rng.random() < 0.35:
+                c = int(rng.integers(0, scale + 1))
+                if allow_neg and rng.random() < 0.3:
+                    c = -c
+                edges.append((a, b, c))
+    return un, edges
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_mincut_is_minimal_minimiser(seed):
+    """Max-flow labels = the intersection of all minimisers = the smallest-code minimiser; and
+    max-flow value - sum_{un<0} |un| = minimum energy (max-flow / min-cut duality)."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 12))
+    un, edges = random_subproblem(rng, n, tie_prone=(seed % 2 == 0))
+    ea = np.array([e[0] for e in edges], np.int32)
+    eb = np.array([e[1] for e in edges], np.int32)
+    cap = np.array([e[2] for e in edges], np.int64)
+    x, flow = dope.solve_subproblem(un, ea, eb, cap, "maxflow")
+    best, sols = brute_minimisers(list(map(int, un)), edges)
+    inter = (1 << n) - 1
+    for s in sols:
+        inter &= s
+    code = sum(int(x[i]) << i for i in range(n))
+    assert code == inter == min(sols)
+    assert flow - int(np.sum(np.maximum(-un, 0))) == best
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_enumeration_smallest_code(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 11))
+    un, edges = random_subproblem(rng, n, allow_neg=True, tie_prone=(seed % 3 == 0))
+    ea = np.array([e[0] for e in edges], np.int32)
+    eb = np.array([e[1] for e in edges], np.int32)
+    cap = np.array([e[2] for e in edges], np.int64)
+    x, emin = dope.solve_subproblem(un, ea, eb, cap, "exhaustive")
+    best, sols = brute_minimisers(list(map(int, un)), edges)
+    assert emin == best
+    assert sum(int(x[i]) << i for i in range(n)) == min(sols)
+
+
+def test_maxflow_rejects_non_submodular():
+    """Footnote of Sec. 1: a negative pairwise weight breaks submodularity; the graph-cut solver refuses it."""
+    with pytest.raises(ValueError):
+        dope.solve_subproblem(np.array([1, -1]), np.array([0], np.int32), np.array([1], np.int32),
+                              np.array([-5], np.int64), "maxflow")
+
+
+# --------------------------------------------------------------------------------------------------------
+# energy, global min cut
+# --------------------------------------------------------------------------------------------------------
+
+def test_energy_definition_eq1():
+    p = tiny_problem(9, (6, 5, 1), 8, (3, 3, 1), (1, 1, 0), neg_frac=0.3)
+    nb = neighbours(p)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        l = rng.integers(0, 2, p.n).astype(np.uint8)
+        exp = 256 * sum(int(p.u[i]) * int(l[i]) for i in range(p.n))
+        exp += p.lam_q8 * sum(wv * abs(int(l[i]) - int(l[j])) for i in range(p.n) for j, wv in nb[i] if i < j)
+        assert dope.energy_q(p, l) == exp
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_global_mincut_vs_bruteforce(seed):
+    p = tiny_problem(20 + seed, (4, 3, 1), 8 if seed % 2 else 4, (2, 2, 1), (0, 0, 0))
+    x, e = dope.global_mincut(p)
+    best, sols = None, []
+    for code in range(1 << p.n):
+        l = np.array([(code >> i) & 1 for i in range(p.n)], np.uint8)
+        v = dope.energy_q(p, l)
+        if best is None or v < best:
+            best, sols = v, [code]
+        elif v == best:
+            sols.append(code)
+    assert e == best
+    assert sum(int(x[i]) << i for i in range(p.n)) == min(sols)
+
+
+# --------------------------------------------------------------------------------------------------------
+# special cases of Algorithm 1
+# --------------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("conn,dims", [(4, (7, 6, 1)), (8, (6, 6, 1)), (6, (4, 3, 3))])
+def test_single_block_is_global_cut(conn, dims):
+    """K = 1: C = R = 0, so iteration 1 solves Eq. (3) exactly; y = y^ and the residual is 0 (stop at t = 1)."""
+    p = tiny_problem(30, dims, conn, (0, 0, 0), (0, 0, 0))
+    st, infos, _, dec = dope.run(p)
+    assert len(infos) == 1 and infos[0].converged
+    x, _ = dope.global_mincut(p)
+    assert np.array_equal(st.yhat, x)
+    assert np.array_equal(st.Y, 65536 * x.astype(np.int64))
+    assert np.all(st.A == 0)
+
+
+def test_zero_pairwise_gives_unary_sign():
+    """w = 0: every block problem is separable; labels = [u < 0] (ties at u = 0 -> 0), converged at t = 1."""
+    p = tiny_problem(31, (9, 8, 1), 8, (4, 4, 1), (1, 1, 0))
+    p.w[:] = 0
+    p.u[::7] = 0
+    st, infos, _, dec = dope.run(p)
+    assert len(infos) == 1 and infos[0].converged
+    assert np.array_equal(dope.labels(st.Y), (p.u < 0).astype(np.uint8))
+
+
+@pytest.mark.parametrize("case", TINY)
+def test_first_iteration_blocks_are_independent(case):
+    """At y = 1/2, a = 0 (Alg. 1 initialisation) the coupling and the mu-term vanish: block k solves
+    min sum_i 2^14 u_i/q_i y_i + sum_{(i,j) in k} lambda_q 64 w_ij/(q_i q_j) |y_i - y_j| (built here by loops)."""
+    dims, conn, block, overlap = case
+    p = tiny_problem(32, dims, conn, block, overlap)
+    dec = dope.decompose(p)
+    st = dope.initial_state(dec, 777)
+    new, _ = dope.iterate(dec, st, threads=1)
+    nb = neighbours(p)
+    bsets = block_sets(p)
+    q = multiplicities(p, bsets)
+    for k, idx in enumerate(bsets):
+        pos = {i: a for a, i in enumerate(idx)}
+        un = np.array([(1 << 14) * int(p.u[i]) // q[i] for i in idx], np.int64)
+        ea, eb, cap = [], [], []
+        for i in idx:
+            for j, wv in nb[i]:
+                if i < j and j in pos:
+                    ea.append(pos[i]); eb.append(pos[j]); cap.append(p.lam_q8 * wv * 64 // (q[i] * q[j]))
+        x, _ = dope.solve_subproblem(un, np.array(ea, np.int32), np.array(eb, np.int32), np.array(cap, np.int64))
+        assert np.array_equal(new.yhat[dec.offsets[k]:dec.offsets[k + 1]], x)
+
+
+def test_overflow_detected_with_tiny_mu():
+    """A tiny mu makes the lambda/mu term of Eq. (10) blow up: the run stops with an overflow flag and clamped state."""
+    p = synth.config1(mu0=1)
+    st, infos, _, _ = dope.run(p, n_iter=10)
+    assert infos[-1].overflow
+    assert np.max(np.abs(st.Y)) <= 1 << 22 and np.max(np.abs(st.A)) <= 1 << 22
+
+
+def test_mu_schedule():
+    M, seq = 1000, []
+    for _ in range(5):
+        M = dope.next_mu(M)
+        seq.append(M)
+    assert seq == [1050, 1102, 1157, 1214, 1274]
+    assert dope.next_mu((1 << 24) - 1) == (1 << 24) - 1
+
+
+# --------------------------------------------------------------------------------------------------------
+# fixed-point loop against a real-valued float64 implementation written from Eq. (8), (10), (11)
+# --------------------------------------------------------------------------------------------------------
+
+def float_dope(p, iters):
+    """Real-valued Algorithm 1 using the hand closed forms of the coupling terms (independent of the oracle)."""
+    nb = neighbours(p)
+    bsets = block_sets(p)
+    q = multiplicities(p, bsets)
+    lam = p.lam_q8 / 256.0
+    mu = float(p.mu0)
+    y = np.full(p.n, 0.5)
+    a = [np.zeros(len(b)) for b in bsets]
+    hist = []
+    for _ in range(iters):
+        yh = []
+        for k, idx in enumerate(bsets):
+            ink = set(idx)
+            pos = {i: t for t, i in enumerate(idx)}
+            un = np.zeros(len(idx))
+            ea, eb, cap = [], [], []
+            for t, i in enumerate(idx):
+                g = sum(wv * (q[j] - (j in ink)) / (q[i] * q[j]) * (y[i] - y[j]) for j, wv in nb[i])
+                un[t] = p.u[i] / q[i] + lam * g + mu * (a[k][t] - y[i] + 0.5)
+                for j, wv in nb[i]:
+                    if i < j and j in pos:
+                        ea.append(t); eb.append(pos[j]); cap.append(lam * wv / (q[i] * q[j]))
+            # solve with the oracle's integer solver after a fine scaling (labels only)
+            x, _ = dope.solve_subproblem(np.round(un * 2 ** 20).astype(np.int64), np.array(ea, np.int32),
+                                         np.array(eb, np.int32), np.round(np.array(cap) * 2 ** 20).astype(np.int64))
+            yh.append(x.astype(float))
+        num = np.zeros(p.n)
+        for k, idx in enumerate(bsets):
+            ink = set(idx)
+            pos = {i: t for t, i in enumerate(idx)}
+            for t, i in enumerate(idx):
+                num[i] += mu * (yh[k][t] + a[k][t])
+            for m in range(p.n):
+                h = 0.0
+                if m in ink:
+                    h += yh[k][pos[m]] * sum(wv * (q[j] - (j in ink)) / (q[m] * q[j]) for j, wv in nb[m])
+                h -= (q[m] - (m in ink)) * sum(wv * yh[k][pos[i]] / (q[i] * q[m]) for i, wv in nb[m] if i in ink)
+                num[m] -= lam * h
+        y = num / (mu * np.array(q))
+        for k, idx in enumerate(bsets):
+            a[k] = a[k] + yh[k] - y[idx]
+        mu = mu * 1.05
+        hist.append((np.concatenate(yh), y.copy()))
+    return hist
+
+
+def test_fixed_point_tracks_real_valued_loop():
+    p = synth.config1(size=24, mu0=1000)
+    p.block, p.overlap = (8, 8, 1), (1, 1, 0)
+    st, infos, states, dec = dope.run(p, n_iter=3, record=True)
+    hist = float_dope(p, 3)
+    for t in range(3):
+        yh_f, y_f = hist[t]
+        assert np.array_equal(states[t].yhat, yh_f.astype(np.uint8))
+        assert np.max(np.abs(states[t].Y / 65536.0 - y_f)) < 1e-3
+
+
+def test_energy_gap_invariant_and_quality():
+    """E_dope >= E_GC (the global cut is optimal); the paper reports Dice > 0.99 and small Delta E in 2D."""
+    p = synth.config1()
+    st, infos, _, dec = dope.run(p, n_iter=10)
+    l = dope.labels(st.Y)
+    x, egc = dope.global_mincut(p)
+    e = dope.energy_q(dec, l)
+    assert e >= egc
+    assert (e - egc) / abs(egc) < 0.01
+    assert 2 * np.sum(l & x) / (np.sum(l) + np.sum(x)) > 0.99
