@@ -1,0 +1,163 @@
+/*
+ * dope.h — C ABI of the MI355X (gfx950) DOPE library.
+ *
+ * DOPE (Dolz, Ben Ayed, Desrosiers, "DOPE: Distributed Optimization for Pairwise Energies") minimises a binary
+ * pairwise energy (the paper's Eq. 1)
+ *
+ *     E(y) = sum_i u_i y_i + lambda * sum_{edges (i,j)} w_ij |y_i - y_j|,        y in {0,1}^n,
+ *
+ * by splitting the grid into overlapping blocks (Sec. 2), rewriting the energy as a sum of per-block problems
+ * coupled through a relaxed global y (Theorem 1, Eq. 5), and running the ADMM loop of Algorithm 1: every block
+ * solves its multiplier-augmented binary problem (Eq. 8) in parallel, then the consensus y (Eq. 10) and the
+ * multipliers a_k (Eq. 11) are updated, and mu is multiplied by mu_fact.
+ *
+ * Arithmetic is exact integer fixed point, so results are bit-identical run to run:
+ *   * y and a are Q16.16 (Y = 2^16 y, A = 2^16 a); mu is an integer M in input-energy units; lambda = lambda_q8/256.
+ *   * Block k solves, scaled by 2^14,
+ *       min_{x in {0,1}^|block|}  sum_i Ut_i x_i + sum_{(i,j) in block} c_ij |x_i - x_j|,
+ *       Ut_i = u_i 2^14 / q_i + floor( (lambda_q8 G_i + 2^14 M (A_k,i - Y_i + 2^15)) / 2^16 ),
+ *       G_i  = sum_{j in N(i)} w_ij (64 / (q_i q_j)) (q_j - [j in block k]) (Y_i - Y_j),
+ *       c_ij = lambda_q8 w_ij 64 / (q_i q_j),
+ *     where q_i is the number of blocks containing pixel i (Proposition 1).  The returned block labelling is the
+ *     unique minimal minimiser (label 1 = source side of the minimal minimum cut) for the max-flow solver and
+ *     the smallest-code minimiser (bit p = local pixel p) for the exhaustive solver.
+ *   * Y_m <- floor( (M S_m - 4 Hc_m) / (M q_m) ),  S_m = sum_{k containing m} (2^16 yhat_k,m + A_k,m),
+ *     Hc_m = sum_{k containing m} yhat_k,m sum_{j in N(m)} c_mj (q_j - [j in k])
+ *            - sum_{j in N(m)} sum_{k containing j} (q_m - [m in k]) c_jm yhat_k,j      (Eq. 10)
+ *   * A_k,i <- A_k,i + 2^16 yhat_k,i - Y_i                                               (Eq. 11)
+ *   * residual r_k = sum_{i in block k} (2^16 yhat_k,i - Y_i)^2; converged when max_k r_k <= eps_q16^2
+ *     (the stopping rule of Algorithm 1); overflow when any |Y| or |A| >= 2^22.
+ *   * M <- min(floor(M mu_fact_num / mu_fact_den), 2^24 - 1).
+ *   * Output labels l_i = [Y_i > 2^15]; energy E_q = 256 sum u_i l_i + lambda_q8 sum_edges w_ij |l_i - l_j|.
+ *
+ * Layout: raster order, x fastest: i = x + W (y + H z).  Blocks: per axis of length N with block edge B and
+ * overlap o (0 <= o <= B/2): stride s = B - o, count 1 + max(0, ceil((N - B)/s)), block t covers
+ * [t s, min(t s + B, N)); B <= 0 or B >= N means one block along that axis.  Block order is x-fastest over the
+ * block grid; inside a block, local raster order is x-fastest.  Per-block vectors (A, yhat) are block-major,
+ * concatenated in block order.
+ *
+ * Conventions: every call returns a dope_status; no exception crosses the ABI.  A failed call leaves the
+ * state unchanged, except DOPE_EOVERFLOW and DOPE_ESOLVER, which stop the loop with the state of the failing
+ * iteration.  A context is not thread-safe; separate contexts are independent.  Work is ordered on the
+ * context's HIP stream; calls that return results to the host synchronise that stream before returning.
+ */
+#ifndef DOPE_H
+#define DOPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dope_ctx dope_ctx;
+
+typedef enum {
+    DOPE_OK = 0,
+    DOPE_EINVAL = -1,          /* bad argument, shape, or nonzero weight on an off-grid edge            */
+    DOPE_ENOMEM = -2,          /* device allocation failed or bound workspace too small                 */
+    DOPE_EDEVICE = -3,         /* a HIP runtime call failed                                              */
+    DOPE_ENOTSUBMODULAR = -4,  /* some w_ij < 0 with the max-flow solver (footnote on submodularity)      */
+    DOPE_EOVERFLOW = -5,       /* |Y| or |A| reached 2^22 (mu too small); state frozen at that iteration */
+    DOPE_ESOLVER = -6,         /* a block max-flow exceeded its round limit (watchdog)                   */
+    DOPE_ESTATE = -7,          /* call out of order (e.g. iterate before set_energy)                     */
+    DOPE_EBUSY = -8            /* serving: admission budget exhausted                                    */
+} dope_status;
+
+enum { DOPE_SOLVER_AUTO = 0, DOPE_SOLVER_MAXFLOW = 1, DOPE_SOLVER_EXHAUSTIVE = 2 };
+enum { DOPE_MEM_HOST = 0, DOPE_MEM_DEVICE = 1 };
+
+typedef struct {
+    int32_t ndim;              /* 2 or 3                                                                  */
+    int32_t dims[3];           /* W, H, D (D = 1 in 2D)                                                  */
+    int32_t connectivity;      /* 4 or 8 in 2D, 6 in 3D                                                  */
+    int32_t block[3];          /* block edge B per axis                                                  */
+    int32_t overlap[3];        /* overlap o per axis                                                     */
+    int64_t mu0;               /* initial mu, 1 <= mu0 <= 2^24 - 1, input-energy units                   */
+    int32_t mu_fact_num;       /* mu_fact = num / den (default 21 / 20)                                   */
+    int32_t mu_fact_den;
+    int32_t eps_q16;           /* epsilon of the stopping rule, Q16.16                                   */
+    int32_t max_iter;          /* iteration cap for dope_solve                                           */
+    int32_t solver;            /* DOPE_SOLVER_*                                                          */
+    void *stream;              /* hipStream_t to order work on; NULL = the library creates its own       */
+} dope_params;
+
+typedef struct {
+    int32_t iters_done;        /* t: iterations completed since the last reset                           */
+    int32_t converged;         /* 1 if the last completed iteration met the stopping rule                */
+    int64_t max_resid2;        /* max_k r_k of the last completed iteration (Q32.32)                     */
+    int64_t mu;                /* M for the next iteration                                               */
+} dope_info;
+
+/* Validate p and create a context (no device memory is taken until dope_set_energy or a bound workspace).
+ * Returns EINVAL for unsupported shapes (block bigger than 160 KiB of LDS, bad overlap, bad stencil). */
+dope_status dope_create(const dope_params *p, dope_ctx **out);
+
+/* Load the energy (Eq. 1) and reset the ADMM state of Algorithm 1's initialisation: Y = 2^15, A = 0,
+ * M = mu0, t = 0.
+ *   u: int32[n]; w: int32[h * n], offset-major over the half-stencil
+ *      2D: (+1,0), (0,+1), then for 8-connectivity (+1,+1), (-1,+1); 3D: (+1,0,0), (0,+1,0), (0,0,+1).
+ *      w[o*n + i] weights the edge i <-> i + offset[o] and must be 0 where that neighbour is off-grid.
+ *   lambda_q8 = round(256 lambda) >= 0.
+ *   mem_kind: DOPE_MEM_HOST (pageable or pinned host memory) or DOPE_MEM_DEVICE (device pointers).
+ * The inputs are copied; the caller keeps ownership.  Errors: EINVAL (off-grid weight, lambda < 0, weights so
+ * large that per-node sum_j |c_ij| >= 2^29), ENOTSUBMODULAR (w < 0 with the max-flow solver). */
+dope_status dope_set_energy(dope_ctx *ctx, const int32_t *u, const int32_t *w, int32_t lambda_q8, int32_t mem_kind);
+
+/* Run exactly n_iter iterations of Algorithm 1's main loop (stops early only on EOVERFLOW / ESOLVER). */
+dope_status dope_iterate(dope_ctx *ctx, int32_t n_iter, dope_info *out);
+
+/* Run until the stopping rule holds or t reaches max_iter.  out may be NULL. */
+dope_status dope_solve(dope_ctx *ctx, dope_info *out);
+
+/* Labels l_i = [Y_i > 2^15] (uint8[n]) to host or device memory. */
+dope_status dope_labels(dope_ctx *ctx, uint8_t *labels, int32_t mem_kind);
+
+/* E_q = 256 sum u_i l_i + lambda_q8 sum_edges w_ij |l_i - l_j| of the current labels (exact int64). */
+dope_status dope_energy(dope_ctx *ctx, int64_t *e_q8);
+
+/* Checkpoint / test access to the whole ADMM state (host memory).  Y: int32[n]; A: int32[sum |block|];
+ * yhat: uint8[sum |block|] (labels of the last block solve); mu: M for the next iteration; t: iterations. */
+dope_status dope_get_state(dope_ctx *ctx, int32_t *Y, int32_t *A, uint8_t *yhat, int64_t *mu, int32_t *t);
+dope_status dope_set_state(dope_ctx *ctx, const int32_t *Y, const int32_t *A, const uint8_t *yhat, int64_t mu,
+                           int32_t t);
+
+/* Per-block squared residuals r_k (int64[K]) of the last completed iteration. */
+dope_status dope_block_resid(dope_ctx *ctx, int64_t *resid);
+
+/* Per-block solver statistics of the last iteration, int32[K * 4]:
+ * {free nodes after forced-node elimination, push/relabel rounds, global relabels, forced-node cascade rounds}. */
+dope_status dope_block_stats(dope_ctx *ctx, int32_t *stats);
+
+/* Block geometry: *n_blocks = K; if table != NULL it receives 7 int32 per block:
+ * x0, y0, z0, ex, ey, ez, offset (start of the block in the block-major vectors). */
+dope_status dope_block_table(dope_ctx *ctx, int32_t *n_blocks, int32_t *table);
+
+/* Sizes: n pixels, K blocks, sum of block sizes, half-stencil size h. */
+dope_status dope_sizes(const dope_ctx *ctx, int64_t *n, int32_t *n_blocks, int64_t *total_block_px, int32_t *h);
+
+/* Device bytes the context needs for p (for caller-allocated workspaces and admission by HBM footprint). */
+size_t dope_workspace_bytes(const dope_params *p);
+
+/* Use caller-owned device memory (>= dope_workspace_bytes, 256-byte aligned) instead of allocating.
+ * Must be called before dope_set_energy; the memory must outlive the context. */
+dope_status dope_bind_workspace(dope_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Kernel timing with HIP events on the context stream.  While enabled, every block-solve and consensus launch
+ * is bracketed by events; dope_profile_read returns the summed milliseconds and launch counts since enable. */
+dope_status dope_profile_enable(dope_ctx *ctx, int32_t on);
+dope_status dope_profile_read(dope_ctx *ctx, double *solve_ms, int32_t *solve_launches, double *consensus_ms,
+                              int32_t *consensus_launches);
+
+/* Context-local message of the last error; never NULL.  With ctx == NULL: the calling thread's last
+ * dope_create validation message (empty when it succeeded). */
+const char *dope_last_error(const dope_ctx *ctx);
+
+void dope_destroy(dope_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOPE_H */

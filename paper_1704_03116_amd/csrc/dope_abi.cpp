@@ -1,0 +1,561 @@
+// Host runtime behind the C ABI of include/dope.h: parameter validation, block partition, device workspace,
+// stream-ordered launches of one ADMM iteration (block solves, then consensus and multiplier updates), and
+// checkpoint / inspection entry points.
+#include "../../include/dope.h"
+#include "dope_internal.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+using dope::Ctl;
+using dope::Geom;
+
+struct dope_ctx {
+    dope_params p{};
+    Geom g{};
+    int solver = 0;            // resolved: 1 max-flow, 2 exhaustive (0 until set_energy)
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    Ctl *ctl = nullptr;
+    int32_t *btab = nullptr, *u = nullptr, *w = nullptr, *cw = nullptr, *Y = nullptr, *A0 = nullptr, *A1 = nullptr;
+    int32_t *stats = nullptr;
+    uint8_t *yhat = nullptr, *labels = nullptr;
+    int64_t *resid = nullptr;
+    Ctl *hctl = nullptr;       // pinned host mirror of the control block
+    std::vector<int32_t> hbtab;
+    int32_t lam_q8 = 0;
+    bool energy_set = false;
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_solve, ev_cons;   // start/stop pairs
+    size_t n_solve = 0, n_cons = 0;
+    std::string err;
+};
+
+namespace {
+
+struct Layout {
+    size_t ctl, btab, u, w, cw, Y, A0, A1, yhat, resid, stats, labels, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout layout_for(const Geom &g) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+    L.ctl = take(sizeof(Ctl));
+    L.btab = take(size_t(g.K) * dope::BTAB_STRIDE * 4);
+    L.u = take(size_t(g.n) * 4);
+    L.w = take(size_t(g.n) * g.hs * 4);
+    L.cw = take(size_t(g.n) * g.hs * 4);
+    L.Y = take(size_t(g.n) * 4);
+    L.A0 = take(size_t(g.tot) * 4);
+    L.A1 = take(size_t(g.tot) * 4);
+    L.yhat = take(size_t(g.tot));
+    L.resid = take(size_t(g.K) * 8);
+    L.stats = take(size_t(g.K) * 16);
+    L.labels = take(size_t(g.n));
+    L.total = o;
+    return L;
+}
+
+int half_stencil_size(int ndim, int conn) {
+    if (ndim == 2 && conn == 4) return 2;
+    if (ndim == 2 && conn == 8) return 4;
+    if (ndim == 3 && conn == 6) return 3;
+    return 0;
+}
+
+// Builds the partition; returns an empty string on success or a message.
+std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab) {
+    if (!p) return "null params";
+    if (p->ndim != 2 && p->ndim != 3) return "ndim must be 2 or 3";
+    const int hs = half_stencil_size(p->ndim, p->connectivity);
+    if (!hs) return "connectivity must be 4 or 8 in 2D and 6 in 3D";
+    int32_t dims[3] = {p->dims[0], p->dims[1], p->ndim == 3 ? p->dims[2] : 1};
+    if (p->ndim == 2 && p->dims[2] != 1 && p->dims[2] != 0) return "dims[2] must be 1 in 2D";
+    int64_t n = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (dims[a] <= 0) return "dims must be positive";
+        n *= dims[a];
+    }
+    if (n >= (int64_t(1) << 31)) return "grid too large (n must be < 2^31)";
+    int64_t K = 1, max_np = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int N = dims[a];
+        const int B = (p->ndim == 2 && a == 2) ? 1 : p->block[a];
+        const int o = (p->ndim == 2 && a == 2) ? 0 : p->overlap[a];
+        dope::Axis ax;
+        if (B <= 0 || B >= N) {
+            ax = {N, N, N, 1};
+        } else {
+            if (o < 0 || 2 * o > B) return "overlap must satisfy 0 <= o <= B/2";
+            const int s = B - o;
+            ax = {N, B, s, 1 + (N - B + s - 1) / s};
+        }
+        g.ax[a] = ax;
+        K *= ax.nb;
+        max_np *= std::min(ax.B, N);
+    }
+    if (K >= (int64_t(1) << 28)) return "too many blocks";
+    g.W = dims[0];
+    g.H = dims[1];
+    g.D = dims[2];
+    g.conn = p->connectivity;
+    g.hs = hs;
+    g.K = int32_t(K);
+    g.max_np = int32_t(max_np);
+    g.n = n;
+    int64_t tot = 0;
+    if (btab) btab->assign(size_t(K) * dope::BTAB_STRIDE, 0);
+    int64_t k = 0;
+    for (int tz = 0; tz < g.ax[2].nb; ++tz)
+        for (int ty = 0; ty < g.ax[1].nb; ++ty)
+            for (int tx = 0; tx < g.ax[0].nb; ++tx, ++k) {
+                const int x0 = tx * g.ax[0].s, y0 = ty * g.ax[1].s, z0 = tz * g.ax[2].s;
+                const int ex = std::min(g.ax[0].B, g.W - x0), ey = std::min(g.ax[1].B, g.H - y0),
+                          ez = std::min(g.ax[2].B, g.D - z0);
+                if (btab) {
+                    int32_t *r = btab->data() + k * dope::BTAB_STRIDE;
+                    r[0] = x0; r[1] = y0; r[2] = z0; r[3] = ex; r[4] = ey; r[5] = ez; r[6] = int32_t(tot); r[7] = 0;
+                }
+                tot += int64_t(ex) * ey * ez;
+                if (tot >= (int64_t(1) << 31)) return "sum of block sizes must be < 2^31";
+            }
+    g.tot = tot;
+    if (p->mu0 < 1 || p->mu0 > dope::MU_MAX) return "mu0 must be in [1, 2^24 - 1]";
+    if (p->mu_fact_num < 0 || p->mu_fact_den < 0) return "mu_fact must be positive";
+    if ((p->mu_fact_num == 0) != (p->mu_fact_den == 0)) return "mu_fact numerator and denominator must both be set";
+    if (p->eps_q16 < 0) return "eps_q16 must be >= 0";
+    if (p->max_iter < 0) return "max_iter must be >= 0";
+    const bool fits_lds = dope::maxflow_lds_bytes(g.max_np, hs) <= dope::LDS_LIMIT;
+    switch (p->solver) {
+        case DOPE_SOLVER_MAXFLOW:
+            if (!fits_lds) return "block too large for the LDS-resident max-flow solver";
+            break;
+        case DOPE_SOLVER_EXHAUSTIVE:
+            if (g.max_np > 16) return "the exhaustive solver needs blocks of at most 16 pixels";
+            break;
+        case DOPE_SOLVER_AUTO:
+            if (!fits_lds && g.max_np > 16) return "block too large for the LDS-resident max-flow solver";
+            break;
+        default:
+            return "unknown solver";
+    }
+    return std::string();
+}
+
+thread_local std::string g_create_error;
+
+dope_status fail(dope_ctx *c, dope_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+dope_status hip_fail(dope_ctx *c, hipError_t e, const char *what) {
+    return fail(c, DOPE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr, what)                        \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+    } while (0)
+
+void assign_pointers(dope_ctx *c) {
+    const Layout L = layout_for(c->g);
+    char *b = c->ws;
+    c->ctl = reinterpret_cast<Ctl *>(b + L.ctl);
+    c->btab = reinterpret_cast<int32_t *>(b + L.btab);
+    c->u = reinterpret_cast<int32_t *>(b + L.u);
+    c->w = reinterpret_cast<int32_t *>(b + L.w);
+    c->cw = reinterpret_cast<int32_t *>(b + L.cw);
+    c->Y = reinterpret_cast<int32_t *>(b + L.Y);
+    c->A0 = reinterpret_cast<int32_t *>(b + L.A0);
+    c->A1 = reinterpret_cast<int32_t *>(b + L.A1);
+    c->yhat = reinterpret_cast<uint8_t *>(b + L.yhat);
+    c->resid = reinterpret_cast<int64_t *>(b + L.resid);
+    c->stats = reinterpret_cast<int32_t *>(b + L.stats);
+    c->labels = reinterpret_cast<uint8_t *>(b + L.labels);
+}
+
+dope_status ensure_workspace(dope_ctx *c) {
+    if (c->ws) return DOPE_OK;
+    const size_t bytes = layout_for(c->g).total;
+    void *ptr = nullptr;
+    if (hipMalloc(&ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, DOPE_ENOMEM, "hipMalloc of the workspace failed");
+    }
+    c->ws = static_cast<char *>(ptr);
+    c->ws_bytes = bytes;
+    c->own_ws = true;
+    assign_pointers(c);
+    HIP_TRY(c, hipMemcpyAsync(c->btab, c->hbtab.data(), c->hbtab.size() * 4, hipMemcpyHostToDevice, c->stream),
+            "block table upload");
+    return DOPE_OK;
+}
+
+dope_status sync_ctl(dope_ctx *c) {
+    HIP_TRY(c, hipMemcpyAsync(c->hctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream), "control readback");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return DOPE_OK;
+}
+
+void fill_info(const dope_ctx *c, dope_info *out) {
+    if (!out) return;
+    out->iters_done = c->hctl->t;
+    out->converged = c->hctl->converged;
+    out->max_resid2 = int64_t(c->hctl->last_max_resid);
+    out->mu = c->hctl->M;
+}
+
+hipEvent_t next_event(std::vector<hipEvent_t> &pool, size_t idx) {
+    while (pool.size() <= idx) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        pool.push_back(e);
+    }
+    return pool[idx];
+}
+
+dope_status enqueue_iterations(dope_ctx *c, int count) {
+    for (int it = 0; it < count; ++it) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->profiling) {
+            e0 = next_event(c->ev_solve, 2 * c->n_solve);
+            e1 = next_event(c->ev_solve, 2 * c->n_solve + 1);
+            if (e0 && e1) hipEventRecord(e0, c->stream);
+        }
+        HIP_TRY(c, dope::launch_block_solve(c->g, c->solver, c->u, c->cw, c->Y, c->A0, c->A1, c->btab, c->yhat,
+                                            c->stats, c->ctl, c->stream),
+                "block solve launch");
+        if (c->profiling && e0 && e1) {
+            hipEventRecord(e1, c->stream);
+            ++c->n_solve;
+            e0 = next_event(c->ev_cons, 2 * c->n_cons);
+            e1 = next_event(c->ev_cons, 2 * c->n_cons + 1);
+            if (e0 && e1) hipEventRecord(e0, c->stream);
+        }
+        HIP_TRY(c, dope::launch_consensus(c->g, c->cw, c->yhat, c->A0, c->A1, c->Y, c->btab, c->resid, c->ctl,
+                                          c->stream),
+                "consensus launch");
+        if (c->profiling && e0 && e1) {
+            hipEventRecord(e1, c->stream);
+            ++c->n_cons;
+        }
+    }
+    return DOPE_OK;
+}
+
+dope_status check_ready(dope_ctx *c) {
+    if (!c) return DOPE_EINVAL;
+    if (!c->energy_set) return fail(c, DOPE_ESTATE, "dope_set_energy has not been called");
+    return DOPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dope_status dope_create(const dope_params *p, dope_ctx **out) {
+    if (!out) return DOPE_EINVAL;
+    *out = nullptr;
+    Geom g{};
+    std::vector<int32_t> bt;
+    dope_params q = p ? *p : dope_params{};
+    if (p && q.mu_fact_num == 0 && q.mu_fact_den == 0) { q.mu_fact_num = 21; q.mu_fact_den = 20; }
+    const std::string msg = make_geom(p ? &q : nullptr, g, &bt);
+    g_create_error = msg;
+    if (!msg.empty()) return DOPE_EINVAL;
+    dope_ctx *c = new (std::nothrow) dope_ctx();
+    if (!c) return DOPE_ENOMEM;
+    c->p = q;
+    c->g = g;
+    c->hbtab.swap(bt);
+    if (q.stream) {
+        c->stream = static_cast<hipStream_t>(q.stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return DOPE_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    void *h = nullptr;
+    if (hipHostMalloc(&h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        if (c->own_stream) hipStreamDestroy(c->stream);
+        delete c;
+        return DOPE_EDEVICE;
+    }
+    c->hctl = static_cast<Ctl *>(h);
+    std::memset(c->hctl, 0, sizeof(Ctl));
+    *out = c;
+    return DOPE_OK;
+}
+
+size_t dope_workspace_bytes(const dope_params *p) {
+    Geom g{};
+    if (!p) return 0;
+    dope_params q = *p;
+    if (q.mu_fact_num == 0 && q.mu_fact_den == 0) { q.mu_fact_num = 21; q.mu_fact_den = 20; }
+    if (!make_geom(&q, g, nullptr).empty()) return 0;
+    return layout_for(g).total;
+}
+
+dope_status dope_bind_workspace(dope_ctx *c, void *dev_ptr, size_t bytes) {
+    if (!c || !dev_ptr) return DOPE_EINVAL;
+    if (c->ws) return fail(c, DOPE_ESTATE, "a workspace is already in use");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) & 255) return fail(c, DOPE_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < layout_for(c->g).total) return fail(c, DOPE_ENOMEM, "workspace smaller than dope_workspace_bytes");
+    c->ws = static_cast<char *>(dev_ptr);
+    c->ws_bytes = bytes;
+    c->own_ws = false;
+    assign_pointers(c);
+    HIP_TRY(c, hipMemcpyAsync(c->btab, c->hbtab.data(), c->hbtab.size() * 4, hipMemcpyHostToDevice, c->stream),
+            "block table upload");
+    return DOPE_OK;
+}
+
+dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int32_t lambda_q8, int32_t mem_kind) {
+    if (!c || !u || !w) return DOPE_EINVAL;
+    if (lambda_q8 < 0) return fail(c, DOPE_EINVAL, "lambda must be >= 0");
+    if (mem_kind != DOPE_MEM_HOST && mem_kind != DOPE_MEM_DEVICE) return fail(c, DOPE_EINVAL, "bad mem_kind");
+    dope_status st = ensure_workspace(c);
+    if (st != DOPE_OK) return st;
+    const hipMemcpyKind kind = mem_kind == DOPE_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const Geom &g = c->g;
+    HIP_TRY(c, hipMemcpyAsync(c->u, u, size_t(g.n) * 4, kind, c->stream), "unary upload");
+    HIP_TRY(c, hipMemcpyAsync(c->w, w, size_t(g.n) * g.hs * 4, kind, c->stream), "weight upload");
+    const uint64_t eps2 = uint64_t(c->p.eps_q16) * uint64_t(c->p.eps_q16);
+    HIP_TRY(c, dope::launch_init_state(g, c->Y, c->A0, c->A1, c->yhat, c->resid, c->ctl, c->p.mu0, c->p.mu_fact_num,
+                                       c->p.mu_fact_den, eps2, c->stream),
+            "state init launch");
+    HIP_TRY(c, dope::launch_prep_weights(g, c->w, c->cw, lambda_q8, c->ctl, c->stream), "weight prep launch");
+    st = sync_ctl(c);
+    if (st != DOPE_OK) return st;
+    c->energy_set = false;
+    const int32_t flags = c->hctl->flags;
+    if (flags & dope::FLAG_OFFGRID) return fail(c, DOPE_EINVAL, "nonzero weight on an off-grid edge");
+    if (flags & dope::FLAG_TOOBIG) return fail(c, DOPE_EINVAL, "weights too large: per-node sum |c_ij| >= 2^29");
+    int solver = c->p.solver;
+    if (flags & dope::FLAG_NEGATIVE) {
+        if (solver == DOPE_SOLVER_MAXFLOW) return fail(c, DOPE_ENOTSUBMODULAR, "negative weight with the max-flow solver");
+        if (solver == DOPE_SOLVER_AUTO) {
+            if (g.max_np > 16) return fail(c, DOPE_ENOTSUBMODULAR, "negative weight and blocks too large to enumerate");
+            solver = DOPE_SOLVER_EXHAUSTIVE;
+        }
+    } else if (solver == DOPE_SOLVER_AUTO) {
+        solver = dope::maxflow_lds_bytes(g.max_np, g.hs) <= dope::LDS_LIMIT ? DOPE_SOLVER_MAXFLOW : DOPE_SOLVER_EXHAUSTIVE;
+    }
+    c->solver = solver;
+    c->lam_q8 = lambda_q8;
+    c->energy_set = true;
+    c->err.clear();
+    return DOPE_OK;
+}
+
+dope_status dope_iterate(dope_ctx *c, int32_t n_iter, dope_info *out) {
+    dope_status st = check_ready(c);
+    if (st != DOPE_OK) return st;
+    if (n_iter < 0) return fail(c, DOPE_EINVAL, "n_iter must be >= 0");
+    if (c->hctl->status != 0) { fill_info(c, out); return dope_status(c->hctl->status); }
+    const int32_t t0 = c->hctl->t;
+    HIP_TRY(c, dope::launch_ctl_setup(c->ctl, t0 + n_iter, 0, 0, c->stream), "control setup launch");
+    st = enqueue_iterations(c, n_iter);
+    if (st != DOPE_OK) return st;
+    st = sync_ctl(c);
+    if (st != DOPE_OK) return st;
+    fill_info(c, out);
+    if (c->hctl->status != 0) {
+        return fail(c, dope_status(c->hctl->status),
+                    c->hctl->status == DOPE_EOVERFLOW ? "fixed-point overflow (|Y| or |A| >= 2^22): mu too small"
+                                                      : "block max-flow exceeded its round limit");
+    }
+    return DOPE_OK;
+}
+
+dope_status dope_solve(dope_ctx *c, dope_info *out) {
+    dope_status st = check_ready(c);
+    if (st != DOPE_OK) return st;
+    if (c->hctl->status != 0) { fill_info(c, out); return dope_status(c->hctl->status); }
+    if (c->hctl->t > 0 && c->hctl->converged) { fill_info(c, out); return DOPE_OK; }
+    const int32_t limit = c->p.max_iter;
+    HIP_TRY(c, dope::launch_ctl_setup(c->ctl, limit, 1, 0, c->stream), "control setup launch");
+    // One iteration per readback: no launch is ever enqueued past the stopping rule.
+    while (c->hctl->t < limit) {
+        st = enqueue_iterations(c, 1);
+        if (st != DOPE_OK) return st;
+        st = sync_ctl(c);
+        if (st != DOPE_OK) return st;
+        if (c->hctl->halted) break;
+    }
+    fill_info(c, out);
+    if (c->hctl->status != 0) {
+        return fail(c, dope_status(c->hctl->status),
+                    c->hctl->status == DOPE_EOVERFLOW ? "fixed-point overflow (|Y| or |A| >= 2^22): mu too small"
+                                                      : "block max-flow exceeded its round limit");
+    }
+    return DOPE_OK;
+}
+
+dope_status dope_labels(dope_ctx *c, uint8_t *labels, int32_t mem_kind) {
+    dope_status st = check_ready(c);
+    if (st != DOPE_OK) return st;
+    if (!labels) return fail(c, DOPE_EINVAL, "null labels");
+    uint8_t *dst = mem_kind == DOPE_MEM_DEVICE ? labels : c->labels;
+    HIP_TRY(c, dope::launch_ctl_setup(c->ctl, c->hctl->t, c->hctl->stop_on_converge, 1, c->stream), "control setup");
+    HIP_TRY(c, dope::launch_labels_energy(c->g, c->u, c->w, c->lam_q8, c->Y, dst, c->ctl, c->stream), "labels launch");
+    if (mem_kind != DOPE_MEM_DEVICE)
+        HIP_TRY(c, hipMemcpyAsync(labels, c->labels, size_t(c->g.n), hipMemcpyDeviceToHost, c->stream), "labels copy");
+    return sync_ctl(c);
+}
+
+dope_status dope_energy(dope_ctx *c, int64_t *e_q8) {
+    dope_status st = check_ready(c);
+    if (st != DOPE_OK) return st;
+    if (!e_q8) return fail(c, DOPE_EINVAL, "null output");
+    HIP_TRY(c, dope::launch_ctl_setup(c->ctl, c->hctl->t, c->hctl->stop_on_converge, 1, c->stream), "control setup");
+    HIP_TRY(c, dope::launch_labels_energy(c->g, c->u, c->w, c->lam_q8, c->Y, nullptr, c->ctl, c->stream),
+            "energy launch");
+    st = sync_ctl(c);
+    if (st != DOPE_OK) return st;
+    *e_q8 = c->hctl->energy;
+    return DOPE_OK;
+}
+
+dope_status dope_get_state(dope_ctx *c, int32_t *Y, int32_t *A, uint8_t *yhat, int64_t *mu, int32_t *t) {
+    dope_status st = check_ready(c);
+    if (st != DOPE_OK) return st;
+    st = sync_ctl(c);
+    if (st != DOPE_OK) return st;
+    const Geom &g = c->g;
+    const int32_t *Acur = (c->hctl->t & 1) ? c->A1 : c->A0;
+    if (Y) HIP_TRY(c, hipMemcpyAsync(Y, c->Y, size_t(g.n) * 4, hipMemcpyDeviceToHost, c->stream), "Y copy");
+    if (A) HIP_TRY(c, hipMemcpyAsync(A, Acur, size_t(g.tot) * 4, hipMemcpyDeviceToHost, c->stream), "A copy");
+    if (yhat) HIP_TRY(c, hipMemcpyAsync(yhat, c->yhat, size_t(g.tot), hipMemcpyDeviceToHost, c->stream), "yhat copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    if (mu) *mu = c->hctl->M;
+    if (t) *t = c->hctl->t;
+    return DOPE_OK;
+}
+
+dope_status dope_set_state(dope_ctx *c, const int32_t *Y, const int32_t *A, const uint8_t *yhat, int64_t mu,
+                           int32_t t) {
+    dope_status st = check_ready(c);
+    if (st != DOPE_OK) return st;
+    if (!Y || !A || !yhat) return fail(c, DOPE_EINVAL, "null state array");
+    if (mu < 1 || mu > dope::MU_MAX || t < 0) return fail(c, DOPE_EINVAL, "bad mu or t");
+    const Geom &g = c->g;
+    for (int64_t i = 0; i < g.n; ++i)
+        if (Y[i] >= dope::STATE_LIMIT || Y[i] <= -dope::STATE_LIMIT) return fail(c, DOPE_EINVAL, "Y out of range");
+    for (int64_t i = 0; i < g.tot; ++i)
+        if (A[i] >= dope::STATE_LIMIT || A[i] <= -dope::STATE_LIMIT) return fail(c, DOPE_EINVAL, "A out of range");
+    st = sync_ctl(c);
+    if (st != DOPE_OK) return st;
+    int32_t *Acur = (t & 1) ? c->A1 : c->A0;
+    HIP_TRY(c, hipMemcpyAsync(c->Y, Y, size_t(g.n) * 4, hipMemcpyHostToDevice, c->stream), "Y upload");
+    HIP_TRY(c, hipMemcpyAsync(Acur, A, size_t(g.tot) * 4, hipMemcpyHostToDevice, c->stream), "A upload");
+    HIP_TRY(c, hipMemcpyAsync(c->yhat, yhat, size_t(g.tot), hipMemcpyHostToDevice, c->stream), "yhat upload");
+    Ctl h = *c->hctl;
+    h.M = mu;
+    h.t = t;
+    h.t_limit = t;
+    h.halted = 0;
+    h.status = 0;
+    h.converged = 0;
+    h.max_resid = 0;
+    h.last_max_resid = 0;
+    h.ovf_pending = 0;
+    h.solver_err = 0;
+    h.wg_counter = 0;
+    *c->hctl = h;
+    HIP_TRY(c, hipMemcpyAsync(c->ctl, c->hctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream), "control upload");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return DOPE_OK;
+}
+
+dope_status dope_block_resid(dope_ctx *c, int64_t *resid) {
+    dope_status st = check_ready(c);
+    if (st != DOPE_OK) return st;
+    if (!resid) return fail(c, DOPE_EINVAL, "null output");
+    HIP_TRY(c, hipMemcpyAsync(resid, c->resid, size_t(c->g.K) * 8, hipMemcpyDeviceToHost, c->stream), "resid copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return DOPE_OK;
+}
+
+dope_status dope_block_stats(dope_ctx *c, int32_t *stats) {
+    dope_status st = check_ready(c);
+    if (st != DOPE_OK) return st;
+    if (!stats) return fail(c, DOPE_EINVAL, "null output");
+    HIP_TRY(c, hipMemcpyAsync(stats, c->stats, size_t(c->g.K) * 16, hipMemcpyDeviceToHost, c->stream), "stats copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return DOPE_OK;
+}
+
+dope_status dope_block_table(dope_ctx *c, int32_t *n_blocks, int32_t *table) {
+    if (!c || !n_blocks) return DOPE_EINVAL;
+    *n_blocks = c->g.K;
+    if (table)
+        for (int64_t k = 0; k < c->g.K; ++k)
+            std::memcpy(table + 7 * k, c->hbtab.data() + dope::BTAB_STRIDE * k, 7 * sizeof(int32_t));
+    return DOPE_OK;
+}
+
+dope_status dope_sizes(const dope_ctx *c, int64_t *n, int32_t *n_blocks, int64_t *total_block_px, int32_t *h) {
+    if (!c) return DOPE_EINVAL;
+    if (n) *n = c->g.n;
+    if (n_blocks) *n_blocks = c->g.K;
+    if (total_block_px) *total_block_px = c->g.tot;
+    if (h) *h = c->g.hs;
+    return DOPE_OK;
+}
+
+dope_status dope_profile_enable(dope_ctx *c, int32_t on) {
+    if (!c) return DOPE_EINVAL;
+    c->profiling = on != 0;
+    c->n_solve = c->n_cons = 0;
+    return DOPE_OK;
+}
+
+dope_status dope_profile_read(dope_ctx *c, double *solve_ms, int32_t *solve_launches, double *consensus_ms,
+                              int32_t *consensus_launches) {
+    if (!c) return DOPE_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    double ts = 0, tc = 0;
+    for (size_t i = 0; i < c->n_solve; ++i) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, c->ev_solve[2 * i], c->ev_solve[2 * i + 1]) == hipSuccess) ts += ms;
+    }
+    for (size_t i = 0; i < c->n_cons; ++i) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, c->ev_cons[2 * i], c->ev_cons[2 * i + 1]) == hipSuccess) tc += ms;
+    }
+    if (solve_ms) *solve_ms = ts;
+    if (solve_launches) *solve_launches = int32_t(c->n_solve);
+    if (consensus_ms) *consensus_ms = tc;
+    if (consensus_launches) *consensus_launches = int32_t(c->n_cons);
+    return DOPE_OK;
+}
+
+const char *dope_last_error(const dope_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+void dope_destroy(dope_ctx *c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev_solve) hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_cons) hipEventDestroy(e);
+    if (c->own_ws && c->ws) hipFree(c->ws);
+    if (c->hctl) hipHostFree(c->hctl);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

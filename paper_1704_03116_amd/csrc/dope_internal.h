@@ -1,0 +1,74 @@
+// Internal declarations shared by the DOPE host runtime and its gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dope {
+
+// One axis of the block partition: length N, block edge B, stride s = B - o, count nb.
+// A single-block axis has B = s = N and nb = 1.
+struct Axis {
+    int32_t N, B, s, nb;
+};
+
+struct Geom {
+    Axis ax[3];
+    int32_t W, H, D;
+    int32_t conn;       // 4, 8 or 6
+    int32_t hs;         // half-stencil size
+    int32_t K;          // number of blocks
+    int32_t max_np;     // largest block size in pixels
+    int64_t n;          // pixels
+    int64_t tot;        // sum of block sizes
+};
+
+// Device-resident loop control.  Written by the host only through k_ctl_* kernels or state uploads.
+struct Ctl {
+    int64_t M;                 // mu of the next iteration
+    uint64_t max_resid;        // running max_k r_k of the iteration in flight
+    uint64_t last_max_resid;   // max_k r_k of the last completed iteration
+    uint64_t eps2;             // eps_q16^2
+    int64_t energy;            // accumulator of the energy kernel
+    int32_t t;                 // completed iterations
+    int32_t t_limit;           // iterations with t >= t_limit are skipped
+    int32_t stop_on_converge;  // dope_solve: halt when the stopping rule holds
+    int32_t converged;
+    int32_t halted;            // sticky stop: error, or converged under stop_on_converge
+    int32_t status;            // 0 or a dope_status error code (sticky)
+    int32_t ovf_pending;
+    int32_t solver_err;
+    uint32_t wg_counter;       // last-workgroup detection in the consensus kernel
+    int32_t mu_num, mu_den;
+    int32_t flags;             // set_energy validation bits (see FLAG_*)
+};
+
+enum : int32_t { FLAG_OFFGRID = 1, FLAG_NEGATIVE = 2, FLAG_TOOBIG = 4 };
+
+constexpr int32_t Y_ONE = 1 << 16;
+constexpr int32_t Y_HALF = 1 << 15;
+constexpr int64_t STATE_LIMIT = 1 << 22;
+constexpr int64_t MU_MAX = (1 << 24) - 1;
+constexpr int64_t CAP_SUM_LIMIT = int64_t(1) << 29;
+constexpr int BTAB_STRIDE = 8;     // x0, y0, z0, ex, ey, ez, offset, pad
+
+// LDS bytes of the max-flow block kernel for a block of np pixels and half-stencil size hs.
+inline size_t maxflow_lds_bytes(int np, int hs) { return 64 + size_t(np) * (8 * hs + 8); }
+constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
+
+// Kernel launchers (dope_kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
+                               hipStream_t s);
+hipError_t launch_init_state(const Geom &g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid,
+                             Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2, hipStream_t s);
+hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy,
+                            hipStream_t s);
+hipError_t launch_block_solve(const Geom &g, int solver, const int32_t *u, const int32_t *cw, const int32_t *Y,
+                              const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat,
+                              int32_t *stats, Ctl *ctl, hipStream_t s);
+hipError_t launch_consensus(const Geom &g, const int32_t *cw, const uint8_t *yhat, int32_t *A0, int32_t *A1,
+                            int32_t *Y, const int32_t *btab, int64_t *resid, Ctl *ctl, hipStream_t s);
+hipError_t launch_labels_energy(const Geom &g, const int32_t *u, const int32_t *w, int32_t lam_q8,
+                                const int32_t *Y, uint8_t *labels, Ctl *ctl, hipStream_t s);
+
+}  // namespace dope

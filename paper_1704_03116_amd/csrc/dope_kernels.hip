@@ -1,0 +1,893 @@
+// gfx950 kernels of the DOPE ADMM iteration (Algorithm 1 of the paper).
+//
+//   k_block_solve       one workgroup per block: Eq. (8) unaries from Theorem 1's coupling terms, forced-node
+//                       elimination, push-relabel max preflow in LDS, canonical minimal cut -> yhat_k.
+//   k_block_exhaustive  one wavefront per block of <= 16 pixels: Gray-code enumeration of all labellings,
+//                       smallest-code minimiser (any sign of the pairwise weights).
+//   k_consensus         one thread per block pixel: Eq. (10) consensus Y, Eq. (11) multipliers, per-block
+//                       residual of the stopping rule; the last workgroup updates mu and the loop control.
+//   k_labels_energy     labels [Y > 1/2] and the Eq. (1) energy.
+//
+// All arithmetic is integer; every kernel first checks the device loop control and exits when the loop has
+// halted, so the host can enqueue several iterations ahead without reading anything back.
+#include "dope_internal.h"
+
+namespace dope {
+
+namespace {
+
+enum : uint8_t { ST_FIXED = 1, ST_LABEL = 2, ST_NEW = 4, ST_MARK = 8 };
+constexpr int16_t H_INF = 0x7FFF;
+
+template <int CONN> struct Sten;
+template <> struct Sten<4> { static constexpr int H = 2; };
+template <> struct Sten<8> { static constexpr int H = 4; };
+template <> struct Sten<6> { static constexpr int H = 3; };
+
+// Half-stencil offsets (must match the weight layout of the public header).
+template <int CONN>
+__device__ __forceinline__ int3 half_off(int o) {
+    if (CONN == 4) return o == 0 ? make_int3(1, 0, 0) : make_int3(0, 1, 0);
+    if (CONN == 8) {
+        switch (o) {
+            case 0: return make_int3(1, 0, 0);
+            case 1: return make_int3(0, 1, 0);
+            case 2: return make_int3(1, 1, 0);
+            default: return make_int3(-1, 1, 0);
+        }
+    }
+    switch (o) {
+        case 0: return make_int3(1, 0, 0);
+        case 1: return make_int3(0, 1, 0);
+        default: return make_int3(0, 0, 1);
+    }
+}
+
+// Full stencil: d < H is +half_off(d), d >= H is -half_off(d - H).
+template <int CONN>
+__device__ __forceinline__ int3 full_dir(int d) {
+    constexpr int H = Sten<CONN>::H;
+    int3 v = half_off<CONN>(d < H ? d : d - H);
+    if (d >= H) { v.x = -v.x; v.y = -v.y; v.z = -v.z; }
+    return v;
+}
+
+// Intervals of one axis containing coordinate x: t_hi always, t_hi - 1 when inside the overlap.
+__device__ __forceinline__ int axis_cover(const Axis &a, int x, int &t0, int &t1) {
+    int th = x / a.s;
+    if (th > a.nb - 1) th = a.nb - 1;
+    t0 = th;
+    if (th >= 1 && x < (th - 1) * a.s + a.B) { t1 = th - 1; return 2; }
+    t1 = th;
+    return 1;
+}
+
+__device__ __forceinline__ int axis_count(const Axis &a, int x) {
+    int t0, t1;
+    return axis_cover(a, x, t0, t1);
+}
+
+__device__ __forceinline__ int q_at(const Geom &g, int x, int y, int z) {
+    return axis_count(g.ax[0], x) * axis_count(g.ax[1], y) * axis_count(g.ax[2], z);
+}
+
+__device__ __forceinline__ int axis_extent(const Axis &a, int t) {
+    int e = a.N - t * a.s;
+    return e < a.B ? e : a.B;
+}
+
+__device__ __forceinline__ bool in_grid(const Geom &g, int x, int y, int z) {
+    return x >= 0 && x < g.W && y >= 0 && y < g.H && z >= 0 && z < g.D;
+}
+
+__device__ __forceinline__ int64_t lin(const Geom &g, int x, int y, int z) {
+    return int64_t(x) + int64_t(g.W) * (int64_t(y) + int64_t(g.H) * int64_t(z));
+}
+
+__device__ __forceinline__ bool ctl_skip(const Ctl *ctl) {
+    return ctl->halted != 0 || ctl->t >= ctl->t_limit;
+}
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {   // b > 0
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) --q;
+    return q;
+}
+
+// Eq. (8) unary of pixel p of block k (scaled by 2^14, unary floored) and the block-local edge data.
+// cap_out[o] = c for in-block half-edges (0 otherwise); mask bit d set for in-block neighbours with c != 0;
+// sumc = sum of |c| over in-block neighbours.
+template <int CONN>
+__device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__restrict__ u,
+                                               const int32_t *__restrict__ cw, const int32_t *__restrict__ Y,
+                                               int32_t a_ki, int64_t M, int gx, int gy, int gz, int lx, int ly,
+                                               int lz, int ex, int ey, int ez, int32_t *cap_out, unsigned &mask,
+                                               int64_t &sumc) {
+    constexpr int H = Sten<CONN>::H;
+    const int64_t i = lin(g, gx, gy, gz);
+    const int qi = q_at(g, gx, gy, gz);
+    const int32_t Yi = Y[i];
+    int64_t G = 0;
+    sumc = 0;
+    mask = 0;
+#pragma unroll
+    for (int d = 0; d < 2 * H; ++d) {
+        const int3 v = full_dir<CONN>(d);
+        const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
+        if (d < H) cap_out[d] = 0;
+        if (!in_grid(g, jx, jy, jz)) continue;
+        const int64_t j = lin(g, jx, jy, jz);
+        const int32_t c = (d < H) ? cw[int64_t(d) * g.n + i] : cw[int64_t(d - H) * g.n + j];
+        if (c == 0) continue;
+        const int mx = lx + v.x, my = ly + v.y, mz = lz + v.z;
+        const bool inb = mx >= 0 && mx < ex && my >= 0 && my < ey && mz >= 0 && mz < ez;
+        const int qj = q_at(g, jx, jy, jz);
+        G += int64_t(c) * int64_t(qj - (inb ? 1 : 0)) * int64_t(Yi - Y[j]);
+        if (inb) {
+            if (d < H) cap_out[d] = c;
+            sumc += c < 0 ? -int64_t(c) : int64_t(c);
+            mask |= 1u << d;
+        }
+    }
+    const int64_t mu_term = (M << 14) * int64_t(a_ki - Yi + Y_HALF);
+    return int64_t(u[i]) * int64_t(16384 / qi) + ((G + mu_term) >> 16);
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Max-flow block solve
+// ------------------------------------------------------------------------------------------------------------
+
+template <int CONN, int NT>
+__global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__restrict__ u,
+                                                    const int32_t *__restrict__ cw, const int32_t *__restrict__ Y,
+                                                    const int32_t *__restrict__ A0, const int32_t *__restrict__ A1,
+                                                    const int32_t *__restrict__ btab, uint8_t *__restrict__ yhat,
+                                                    int32_t *__restrict__ stats, Ctl *ctl, int32_t npmax,
+                                                    int32_t round_limit, int32_t relabel_period) {
+    constexpr int H = Sten<CONN>::H;
+    constexpr int ND = 2 * H;
+    if (ctl_skip(ctl)) return;
+    const int k = blockIdx.x;
+    const int32_t *bt = btab + BTAB_STRIDE * k;
+    const int x0 = bt[0], y0 = bt[1], z0 = bt[2], ex = bt[3], ey = bt[4], ez = bt[5];
+    const int64_t off = bt[6];
+    const int np = ex * ey * ez;
+    const int32_t *Ain = (ctl->t & 1) ? A1 : A0;
+    const int64_t M = ctl->M;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    int *s_ctr = reinterpret_cast<int *>(smem);                    // 16 ints of scalars
+    int32_t *cap = reinterpret_cast<int32_t *>(smem + 64);         // [H][npmax]
+    int32_t *flw = cap + H * npmax;                                 // [H][npmax]  flow p -> p + off_o
+    int32_t *dd = flw + H * npmax;                                  // excess minus sink residual
+    int16_t *hh = reinterpret_cast<int16_t *>(dd + npmax);          // heights
+    uint8_t *msk = reinterpret_cast<uint8_t *>(hh + npmax);         // live in-block directions
+    uint8_t *st = msk + npmax;                                      // ST_* bits
+    const int tid = threadIdx.x;
+
+    int loff[H];
+#pragma unroll
+    for (int o = 0; o < H; ++o) {
+        const int3 v = half_off<CONN>(o);
+        loff[o] = v.x + ex * (v.y + ey * v.z);
+    }
+    auto nbr = [&](int p, int d) -> int { return d < H ? p + loff[d] : p - loff[d - H]; };
+    auto capd = [&](int p, int d) -> int32_t { return d < H ? cap[d * npmax + p] : cap[(d - H) * npmax + p - loff[d - H]]; };
+    // residual of the arc p -> nbr(p, d)
+    auto res = [&](int p, int d) -> int32_t {
+        if (d < H) return cap[d * npmax + p] - flw[d * npmax + p];
+        const int v = p - loff[d - H];
+        return cap[(d - H) * npmax + v] + flw[(d - H) * npmax + v];
+    };
+    // residual of the arc nbr(p, d) -> p
+    auto res_in = [&](int p, int d) -> int32_t {
+        if (d < H) return cap[d * npmax + p] + flw[d * npmax + p];
+        const int v = p - loff[d - H];
+        return cap[(d - H) * npmax + v] - flw[(d - H) * npmax + v];
+    };
+    auto push = [&](int p, int d, int32_t delta) {
+        if (d < H) flw[d * npmax + p] += delta;
+        else flw[(d - H) * npmax + p - loff[d - H]] -= delta;
+    };
+
+    if (tid < 16) s_ctr[tid] = 0;
+    __syncthreads();
+
+    // ---- prologue: Eq. (8) unaries, in-block capacities, strictly forced nodes ----
+    for (int p = tid; p < np; p += NT) {
+        const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
+        int32_t cp[H];
+        unsigned m;
+        int64_t sumc;
+        const int64_t Ut = block_unary<CONN>(g, u, cw, Y, Ain[off + p], M, x0 + lx, y0 + ly, z0 + lz, lx, ly, lz,
+                                             ex, ey, ez, cp, m, sumc);
+#pragma unroll
+        for (int o = 0; o < H; ++o) {
+            cap[o * npmax + p] = cp[o];
+            flw[o * npmax + p] = 0;
+        }
+        uint8_t s = 0;
+        if (Ut < -sumc) s = ST_NEW | ST_LABEL;         // label 1 in every minimiser
+        else if (Ut > sumc) s = ST_NEW;                // label 0 in every minimiser
+        if (s) atomicAdd(&s_ctr[0], 1);
+        st[p] = s;
+        msk[p] = uint8_t(m);
+        dd[p] = s ? 0 : int32_t(Ut);                   // |Ut| <= sumc < 2^29 for free nodes
+    }
+    __syncthreads();
+
+    // ---- cascade: fold the pairwise terms of newly forced nodes into their free neighbours' unaries, then
+    //      look for nodes that the reduced problem forces; repeat until none ----
+    int cascades = 0;
+    for (;;) {
+        const int nnew = s_ctr[0];
+        __syncthreads();
+        if (nnew == 0) break;
+        ++cascades;
+        if (tid == 0) s_ctr[0] = 0;
+        for (int p = tid; p < np; p += NT) {
+            if (st[p] != 0) continue;
+            const unsigned m = msk[p];
+            int32_t U = dd[p];
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+                if ((m >> d) & 1u) {
+                    const uint8_t sv = st[nbr(p, d)];
+                    if (sv & ST_NEW) U += (sv & ST_LABEL) ? -capd(p, d) : capd(p, d);
+                }
+            dd[p] = U;
+        }
+        __syncthreads();
+        for (int p = tid; p < np; p += NT)
+            if (st[p] & ST_NEW) st[p] = ST_FIXED | (st[p] & ST_LABEL);
+        __syncthreads();
+        for (int p = tid; p < np; p += NT) {
+            if (st[p] & ST_FIXED) continue;
+            const unsigned m = msk[p];
+            int32_t S = 0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+                if ((m >> d) & 1u) {
+                    const int v = nbr(p, d);
+                    if (!(st[v] & ST_FIXED)) S += capd(p, d);
+                }
+            const int32_t U = dd[p];
+            if (U < -S) { st[p] = ST_NEW | ST_LABEL; atomicAdd(&s_ctr[0], 1); }
+            else if (U > S) { st[p] = ST_NEW; atomicAdd(&s_ctr[0], 1); }
+        }
+        __syncthreads();
+    }
+
+    // ---- flow network on the free nodes: source excess -U, sink capacity U folded into one signed value ----
+    for (int p = tid; p < np; p += NT) {
+        if (st[p] & ST_FIXED) {
+            msk[p] = 0;
+            dd[p] = 0;
+            hh[p] = H_INF;
+            continue;
+        }
+        unsigned m = msk[p];
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+            if (((m >> d) & 1u) && (st[nbr(p, d)] & ST_FIXED)) m &= ~(1u << d);
+        msk[p] = uint8_t(m);
+        dd[p] = -dd[p];
+        atomicAdd(&s_ctr[1], 1);
+    }
+    __syncthreads();
+    const int nfree = s_ctr[1];
+
+    // ---- push-relabel (max preflow) with periodic global relabelling by backward BFS from the sink ----
+    int rounds = 0, grel = 0;
+    bool fail = false;
+    if (nfree > 0) {
+        for (;;) {
+            for (int p = tid; p < np; p += NT)
+                if (!(st[p] & ST_FIXED)) hh[p] = dd[p] < 0 ? 1 : H_INF;
+            __syncthreads();
+            // exact distances to the sink in the residual graph by monotone relaxation to a fixed point
+            for (;;) {
+                int changed = 0;
+                for (int p = tid; p < np; p += NT) {
+                    const unsigned m = msk[p];
+                    if (!m) continue;
+                    const int h = hh[p];
+                    if (h == 1) continue;
+                    int best = h;
+#pragma unroll
+                    for (int d = 0; d < ND; ++d)
+                        if (((m >> d) & 1u) && res(p, d) > 0) {
+                            const int hv = hh[nbr(p, d)] + 1;
+                            if (hv < best) best = hv;
+                        }
+                    if (best < h) { hh[p] = int16_t(best); changed = 1; }
+                }
+                if (changed) s_ctr[2] = 1;
+                __syncthreads();
+                const int any = s_ctr[2];
+                __syncthreads();
+                if (!any) break;
+                if (tid == 0) s_ctr[2] = 0;
+                __syncthreads();
+            }
+            for (int p = tid; p < np; p += NT)
+                if (dd[p] > 0 && hh[p] < H_INF) { s_ctr[3] = 1; }
+            __syncthreads();
+            const int active = s_ctr[3];
+            __syncthreads();
+            if (!active) break;
+            if (tid == 0) s_ctr[3] = 0;
+            ++grel;
+            if (rounds >= round_limit) { fail = true; break; }
+            for (int r = 0; r < relabel_period; ++r) {
+                // push phase: heights are frozen; an edge can be admissible in one direction only
+                for (int p = tid; p < np; p += NT) {
+                    const int32_t e = dd[p];
+                    if (e <= 0) continue;
+                    const int h = hh[p];
+                    if (h >= H_INF) continue;
+                    const unsigned m = msk[p];
+                    int32_t rem = e;
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) {
+                        if (!((m >> d) & 1u) || rem == 0) continue;
+                        const int v = nbr(p, d);
+                        if (hh[v] != h - 1) continue;
+                        const int32_t rs = res(p, d);
+                        if (rs <= 0) continue;
+                        const int32_t delta = rem < rs ? rem : rs;
+                        push(p, d, delta);
+                        atomicAdd(&dd[v], delta);
+                        rem -= delta;
+                    }
+                    if (rem != e) atomicSub(&dd[p], e - rem);
+                }
+                __syncthreads();
+                // relabel phase: active nodes without an admissible arc rise to 1 + min residual neighbour
+                for (int p = tid; p < np; p += NT) {
+                    if (dd[p] <= 0) continue;
+                    const int h = hh[p];
+                    if (h >= H_INF) continue;
+                    const unsigned m = msk[p];
+                    int best = 1 << 30;
+                    bool adm = false;
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) {
+                        if (!((m >> d) & 1u) || adm) continue;
+                        if (res(p, d) <= 0) continue;
+                        const int hv = hh[nbr(p, d)];
+                        if (hv == h - 1) adm = true;
+                        else if (hv + 1 < best) best = hv + 1;
+                    }
+                    if (!adm) hh[p] = int16_t(best > nfree ? H_INF : best);
+                }
+                __syncthreads();
+                ++rounds;
+            }
+        }
+        // ---- canonical cut: nodes reachable in the residual graph from any node holding excess ----
+        for (int p = tid; p < np; p += NT)
+            if (!(st[p] & ST_FIXED) && dd[p] > 0) st[p] |= ST_MARK;
+        __syncthreads();
+        if (tid == 0) s_ctr[4] = 0;
+        __syncthreads();
+        for (;;) {
+            int changed = 0;
+            for (int p = tid; p < np; p += NT) {
+                if (st[p] & (ST_FIXED | ST_MARK)) continue;
+                const unsigned m = msk[p];
+#pragma unroll
+                for (int d = 0; d < ND; ++d)
+                    if (((m >> d) & 1u) && (st[nbr(p, d)] & ST_MARK) && res_in(p, d) > 0) {
+                        st[p] |= ST_MARK;
+                        changed = 1;
+                        break;
+                    }
+            }
+            if (changed) s_ctr[4] = 1;
+            __syncthreads();
+            const int any = s_ctr[4];
+            __syncthreads();
+            if (!any) break;
+            if (tid == 0) s_ctr[4] = 0;
+            __syncthreads();
+        }
+    }
+
+    for (int p = tid; p < np; p += NT) {
+        const uint8_t s = st[p];
+        yhat[off + p] = (s & ST_FIXED) ? ((s & ST_LABEL) ? 1 : 0) : ((s & ST_MARK) ? 1 : 0);
+    }
+    if (tid == 0) {
+        stats[4 * k + 0] = nfree;
+        stats[4 * k + 1] = rounds;
+        stats[4 * k + 2] = grel;
+        stats[4 * k + 3] = cascades;
+        if (fail) atomicOr(&ctl->solver_err, 1);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Exhaustive block solve (blocks of at most 16 pixels, any sign of the weights)
+// ------------------------------------------------------------------------------------------------------------
+
+constexpr int EX_WAVES = 4;   // blocks per 256-thread workgroup
+
+template <int CONN>
+__global__ __launch_bounds__(256) void k_block_exhaustive(Geom g, const int32_t *__restrict__ u,
+                                                          const int32_t *__restrict__ cw,
+                                                          const int32_t *__restrict__ Y,
+                                                          const int32_t *__restrict__ A0,
+                                                          const int32_t *__restrict__ A1,
+                                                          const int32_t *__restrict__ btab,
+                                                          uint8_t *__restrict__ yhat, int32_t *__restrict__ stats,
+                                                          Ctl *ctl) {
+    constexpr int H = Sten<CONN>::H;
+    constexpr int ND = 2 * H;
+    if (ctl_skip(ctl)) return;
+    __shared__ int32_t s_U[EX_WAVES][16];
+    __shared__ int32_t s_nc[EX_WAVES][16][ND];   // capacity towards full-stencil neighbour d (0 = none)
+    __shared__ int8_t s_nj[EX_WAVES][16][ND];    // local index of that neighbour
+    __shared__ uint8_t s_m[EX_WAVES][16];        // in-block neighbour mask
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int k = blockIdx.x * EX_WAVES + wave;
+    const bool live = k < g.K;
+    int np = 0;
+    int64_t off = 0;
+    if (live) {
+        const int32_t *bt = btab + BTAB_STRIDE * k;
+        const int x0 = bt[0], y0 = bt[1], z0 = bt[2], ex = bt[3], ey = bt[4], ez = bt[5];
+        off = bt[6];
+        np = ex * ey * ez;
+        const int32_t *Ain = (ctl->t & 1) ? A1 : A0;
+        if (lane < np) {
+            const int p = lane;
+            const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
+            int32_t cp[H];
+            unsigned m;
+            int64_t sumc;
+            int64_t Ut = block_unary<CONN>(g, u, cw, Y, Ain[off + p], ctl->M, x0 + lx, y0 + ly, z0 + lz, lx, ly,
+                                           lz, ex, ey, ez, cp, m, sumc);
+            // clamping a strictly forced unary to +-(sum |c| + 1) keeps the minimiser set
+            if (Ut > sumc + 1) Ut = sumc + 1;
+            if (Ut < -sumc - 1) Ut = -sumc - 1;
+            s_U[wave][p] = int32_t(Ut);
+            s_m[wave][p] = uint8_t(m);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const int3 v = full_dir<CONN>(d);
+                s_nj[wave][p][d] = int8_t(p + v.x + ex * (v.y + ey * v.z));
+                s_nc[wave][p][d] = (d < H && ((m >> d) & 1u)) ? cp[d] : 0;
+            }
+        }
+    }
+    __syncthreads();
+    // the capacity towards a negative direction is the neighbour's positive half-edge
+    if (live && lane < np) {
+        const int p = lane;
+        const unsigned m = s_m[wave][p];
+#pragma unroll
+        for (int d = H; d < ND; ++d)
+            if ((m >> d) & 1u) s_nc[wave][p][d] = s_nc[wave][s_nj[wave][p][d]][d - H];
+    }
+    __syncthreads();
+    if (!live) return;
+    const int L = np > 6 ? np - 6 : 0;               // enumerated low bits per lane
+    const int lanes_used = 1 << (np - L);
+    int64_t best = INT64_MAX;
+    uint32_t bestc = 0xFFFFFFFFu;
+    if (lane < lanes_used) {
+        uint32_t x = uint32_t(lane) << L;
+        int64_t E = 0;
+        for (int p = 0; p < np; ++p) {
+            const int xp = (x >> p) & 1;
+            if (xp) E += s_U[wave][p];
+#pragma unroll
+            for (int d = 0; d < H; ++d) {
+                const int32_t c = s_nc[wave][p][d];
+                if (c != 0) {
+                    const int q = s_nj[wave][p][d];
+                    if (xp != int((x >> q) & 1)) E += c;
+                }
+            }
+        }
+        best = E;
+        bestc = x;
+        const uint32_t cnt = 1u << L;
+        for (uint32_t gi = 1; gi < cnt; ++gi) {
+            const int b = __builtin_ctz(gi);
+            const int xb = (x >> b) & 1;
+            x ^= 1u << b;
+            int64_t t = s_U[wave][b];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const int32_t c = s_nc[wave][b][d];
+                if (c != 0) t += ((x >> s_nj[wave][b][d]) & 1u) ? -int64_t(c) : int64_t(c);
+            }
+            E += xb ? -t : t;
+            if (E < best || (E == best && x < bestc)) { best = E; bestc = x; }
+        }
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const int64_t oE = __shfl_xor(best, s);
+        const uint32_t oc = __shfl_xor(bestc, s);
+        if (oE < best || (oE == best && oc < bestc)) { best = oE; bestc = oc; }
+    }
+    if (lane < np) yhat[off + lane] = uint8_t((bestc >> lane) & 1u);
+    if (lane == 0) {
+        stats[4 * k + 0] = np;
+        stats[4 * k + 1] = 0;
+        stats[4 * k + 2] = 0;
+        stats[4 * k + 3] = 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Consensus (Eq. 10), multipliers (Eq. 11), residual and loop control
+// ------------------------------------------------------------------------------------------------------------
+
+constexpr int CONS_NT = 256;
+constexpr int CONS_MAX_BPW = 64;
+
+template <int CONN>
+__global__ __launch_bounds__(CONS_NT) void k_consensus(Geom g, const int32_t *__restrict__ cw,
+                                                       const uint8_t *__restrict__ yhat, int32_t *A0, int32_t *A1,
+                                                       int32_t *__restrict__ Y, const int32_t *__restrict__ btab,
+                                                       int64_t *__restrict__ resid, Ctl *ctl, int32_t bpw) {
+    constexpr int H = Sten<CONN>::H;
+    constexpr int ND = 2 * H;
+    if (ctl_skip(ctl)) return;
+    __shared__ unsigned long long s_res[CONS_MAX_BPW];
+    __shared__ int s_ovf, s_last;
+    const int tid = threadIdx.x;
+    const int par = ctl->t & 1;
+    const int32_t *Ain = par ? A1 : A0;
+    int32_t *Aout = par ? A0 : A1;
+    const int64_t M = ctl->M;
+    const int k0 = blockIdx.x * bpw;
+    const int k1 = min(k0 + bpw, g.K);
+    if (tid < CONS_MAX_BPW) s_res[tid] = 0;
+    if (tid == 0) s_ovf = 0;
+    __syncthreads();
+    const int64_t c0 = btab[BTAB_STRIDE * k0 + 6];
+    const int64_t c1 = (k1 < g.K) ? int64_t(btab[BTAB_STRIDE * k1 + 6]) : g.tot;
+    const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
+    int kk = k0;
+    int ovf = 0;
+    for (int64_t c = c0 + tid; c < c1; c += CONS_NT) {
+        while (kk + 1 < k1 && int64_t(btab[BTAB_STRIDE * (kk + 1) + 6]) <= c) ++kk;
+        const int32_t *bt = btab + BTAB_STRIDE * kk;
+        const int ex = bt[3], ey = bt[4];
+        const int p = int(c - bt[6]);
+        const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
+        const int gx = bt[0] + lx, gy = bt[1] + ly, gz = bt[2] + lz;
+        // blocks containing m
+        int tx[2], ty[2], tz[2];
+        const int cxn = axis_cover(AX, gx, tx[0], tx[1]);
+        const int cyn = axis_cover(AY, gy, ty[0], ty[1]);
+        const int czn = axis_cover(AZ, gz, tz[0], tz[1]);
+        const int qm = cxn * cyn * czn;
+        const int64_t m = lin(g, gx, gy, gz);
+        int64_t S = 0, HC = 0;
+        for (int a = 0; a < czn; ++a)
+            for (int b = 0; b < cyn; ++b)
+                for (int e = 0; e < cxn; ++e) {
+                    const int kb = tx[e] + AX.nb * (ty[b] + AY.nb * tz[a]);
+                    const int bx0 = tx[e] * AX.s, by0 = ty[b] * AY.s, bz0 = tz[a] * AZ.s;
+                    const int bex = axis_extent(AX, tx[e]), bey = axis_extent(AY, ty[b]), bez = axis_extent(AZ, tz[a]);
+                    const int64_t cc = int64_t(btab[BTAB_STRIDE * kb + 6]) + (gx - bx0) +
+                                       int64_t(bex) * ((gy - by0) + int64_t(bey) * (gz - bz0));
+                    const int yv = yhat[cc];
+                    S += int64_t(yv) * Y_ONE + Ain[cc];
+                    if (yv) {
+#pragma unroll
+                        for (int d = 0; d < ND; ++d) {
+                            const int3 v = full_dir<CONN>(d);
+                            const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
+                            if (!in_grid(g, jx, jy, jz)) continue;
+                            const int32_t cmj = (d < H) ? cw[int64_t(d) * g.n + m]
+                                                        : cw[int64_t(d - H) * g.n + lin(g, jx, jy, jz)];
+                            if (cmj == 0) continue;
+                            const bool inb = jx >= bx0 && jx < bx0 + bex && jy >= by0 && jy < by0 + bey &&
+                                             jz >= bz0 && jz < bz0 + bez;
+                            HC += int64_t(cmj) * (q_at(g, jx, jy, jz) - (inb ? 1 : 0));
+                        }
+                    }
+                }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const int3 v = full_dir<CONN>(d);
+            const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
+            if (!in_grid(g, jx, jy, jz)) continue;
+            const int64_t j = lin(g, jx, jy, jz);
+            const int32_t cjm = (d < H) ? cw[int64_t(d) * g.n + m] : cw[int64_t(d - H) * g.n + j];
+            if (cjm == 0) continue;
+            int ux[2], uy[2], uz[2];
+            const int nx = axis_cover(AX, jx, ux[0], ux[1]);
+            const int ny = axis_cover(AY, jy, uy[0], uy[1]);
+            const int nz = axis_cover(AZ, jz, uz[0], uz[1]);
+            for (int a = 0; a < nz; ++a)
+                for (int b = 0; b < ny; ++b)
+                    for (int e = 0; e < nx; ++e) {
+                        const int kb = ux[e] + AX.nb * (uy[b] + AY.nb * uz[a]);
+                        const int bx0 = ux[e] * AX.s, by0 = uy[b] * AY.s, bz0 = uz[a] * AZ.s;
+                        const int bex = axis_extent(AX, ux[e]), bey = axis_extent(AY, uy[b]), bez = axis_extent(AZ, uz[a]);
+                        const int64_t cc = int64_t(btab[BTAB_STRIDE * kb + 6]) + (jx - bx0) +
+                                           int64_t(bex) * ((jy - by0) + int64_t(bey) * (jz - bz0));
+                        if (!yhat[cc]) continue;
+                        const bool m_in = gx >= bx0 && gx < bx0 + bex && gy >= by0 && gy < by0 + bey &&
+                                          gz >= bz0 && gz < bz0 + bez;
+                        HC -= int64_t(qm - (m_in ? 1 : 0)) * int64_t(cjm);
+                    }
+        }
+        // floor((M S - 4 HC) / (M q)) = floor(floor((M S - 4 HC) / M) / q), q a power of two
+        int64_t Yn = floor_div(M * S - 4 * HC, M);
+        Yn >>= (qm == 1 ? 0 : qm == 2 ? 1 : qm == 4 ? 2 : 3);
+        const int yk = yhat[c];
+        int64_t An = int64_t(Ain[c]) + int64_t(yk) * Y_ONE - Yn;
+        if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT || An >= STATE_LIMIT || An <= -STATE_LIMIT) ovf = 1;
+        const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
+        const int64_t Ac = An > STATE_LIMIT ? STATE_LIMIT : (An < -STATE_LIMIT ? -STATE_LIMIT : An);
+        Aout[c] = int32_t(Ac);
+        // the block with the highest index along every axis writes the shared Y
+        if (tx[0] == kk % AX.nb && ty[0] == (kk / AX.nb) % AY.nb && tz[0] == kk / (AX.nb * AY.nb)) Y[m] = int32_t(Yc);
+        const int64_t rr = int64_t(yk) * Y_ONE - Yc;
+        atomicAdd(&s_res[kk - k0], (unsigned long long)(rr * rr));
+    }
+    if (ovf) s_ovf = 1;
+    __syncthreads();
+    if (tid < k1 - k0) {
+        const unsigned long long rv = s_res[tid];
+        resid[k0 + tid] = int64_t(rv);
+        atomicMax((unsigned long long *)&ctl->max_resid, rv);
+    }
+    if (tid == 0 && s_ovf) atomicOr(&ctl->ovf_pending, 1);
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&ctl->wg_counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (s_last && tid == 0) {
+        __threadfence();
+        const unsigned long long mr = atomicAdd((unsigned long long *)&ctl->max_resid, 0ull);
+        const int ov = atomicOr(&ctl->ovf_pending, 0);
+        const int se = atomicOr(&ctl->solver_err, 0);
+        ctl->last_max_resid = mr;
+        const int conv = mr <= ctl->eps2 ? 1 : 0;
+        ctl->converged = conv;
+        if (se) { ctl->status = -6; ctl->halted = 1; }
+        if (ov) { ctl->status = -5; ctl->halted = 1; }
+        if (ctl->stop_on_converge && conv) ctl->halted = 1;
+        int64_t Mn = (M * ctl->mu_num) / ctl->mu_den;
+        ctl->M = Mn > MU_MAX ? MU_MAX : Mn;
+        ctl->t = ctl->t + 1;
+        ctl->max_resid = 0;
+        ctl->ovf_pending = 0;
+        ctl->solver_err = 0;
+        ctl->wg_counter = 0;
+        __threadfence();
+    }
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Setup, labels and energy
+// ------------------------------------------------------------------------------------------------------------
+
+template <int CONN>
+__global__ void k_prep_weights(Geom g, const int32_t *__restrict__ w, int32_t *__restrict__ cw, int32_t lam,
+                               Ctl *ctl) {
+    constexpr int H = Sten<CONN>::H;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= g.n * H) return;
+    const int o = int(idx / g.n);
+    const int64_t i = idx - int64_t(o) * g.n;
+    const int gx = int(i % g.W), gy = int((i / g.W) % g.H), gz = int(i / (int64_t(g.W) * g.H));
+    const int3 v = half_off<CONN>(o);
+    const int32_t wv = w[idx];
+    int flags = 0;
+    int32_t c = 0;
+    if (!in_grid(g, gx + v.x, gy + v.y, gz + v.z)) {
+        if (wv != 0) flags |= FLAG_OFFGRID;
+    } else if (wv != 0) {
+        if (wv < 0) flags |= FLAG_NEGATIVE;
+        const int qq = q_at(g, gx, gy, gz) * q_at(g, gx + v.x, gy + v.y, gz + v.z);
+        const int64_t cv = int64_t(lam) * int64_t(wv) * int64_t(64 / qq);
+        if (cv >= CAP_SUM_LIMIT || cv <= -CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
+        else c = int32_t(cv);
+    }
+    cw[idx] = c;
+    if (flags) atomicOr(&ctl->flags, flags);
+}
+
+template <int CONN>
+__global__ void k_check_capsum(Geom g, const int32_t *__restrict__ cw, Ctl *ctl) {
+    constexpr int H = Sten<CONN>::H;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const int gx = int(i % g.W), gy = int((i / g.W) % g.H), gz = int(i / (int64_t(g.W) * g.H));
+    int64_t s = 0;
+#pragma unroll
+    for (int d = 0; d < 2 * H; ++d) {
+        const int3 v = full_dir<CONN>(d);
+        if (!in_grid(g, gx + v.x, gy + v.y, gz + v.z)) continue;
+        const int32_t c = d < H ? cw[int64_t(d) * g.n + i] : cw[int64_t(d - H) * g.n + lin(g, gx + v.x, gy + v.y, gz + v.z)];
+        s += c < 0 ? -int64_t(c) : int64_t(c);
+    }
+    if (s >= CAP_SUM_LIMIT) atomicOr(&ctl->flags, FLAG_TOOBIG);
+}
+
+__global__ void k_init_state(Geom g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid, Ctl *ctl,
+                             int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = idx; i < g.n; i += stride) Y[i] = Y_HALF;
+    for (int64_t i = idx; i < g.tot; i += stride) { A0[i] = 0; A1[i] = 0; yhat[i] = 0; }
+    for (int64_t i = idx; i < g.K; i += stride) resid[i] = 0;
+    if (idx == 0) {
+        ctl->M = mu0;
+        ctl->max_resid = 0;
+        ctl->last_max_resid = 0;
+        ctl->eps2 = eps2;
+        ctl->energy = 0;
+        ctl->t = 0;
+        ctl->t_limit = 0;
+        ctl->stop_on_converge = 0;
+        ctl->converged = 0;
+        ctl->halted = 0;
+        ctl->status = 0;
+        ctl->ovf_pending = 0;
+        ctl->solver_err = 0;
+        ctl->wg_counter = 0;
+        ctl->mu_num = mu_num;
+        ctl->mu_den = mu_den;
+        ctl->flags = 0;
+    }
+}
+
+__global__ void k_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->t_limit = t_limit;
+        ctl->stop_on_converge = stop_on_converge;
+        if (ctl->status == 0) ctl->halted = 0;
+        if (clear_energy) ctl->energy = 0;
+    }
+}
+
+template <int CONN>
+__global__ __launch_bounds__(256) void k_labels_energy(Geom g, const int32_t *__restrict__ u,
+                                                       const int32_t *__restrict__ w, int32_t lam,
+                                                       const int32_t *__restrict__ Y, uint8_t *__restrict__ labels,
+                                                       Ctl *ctl) {
+    constexpr int H = Sten<CONN>::H;
+    __shared__ long long s_sum[8];
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    long long e = 0;
+    if (i < g.n) {
+        const int li = Y[i] > Y_HALF;
+        if (labels) labels[i] = uint8_t(li);
+        e = 256ll * u[i] * li;
+        const int gx = int(i % g.W), gy = int((i / g.W) % g.H), gz = int(i / (int64_t(g.W) * g.H));
+#pragma unroll
+        for (int o = 0; o < H; ++o) {
+            const int3 v = half_off<CONN>(o);
+            if (!in_grid(g, gx + v.x, gy + v.y, gz + v.z)) continue;
+            const int lj = Y[lin(g, gx + v.x, gy + v.y, gz + v.z)] > Y_HALF;
+            if (li != lj) e += (long long)lam * w[int64_t(o) * g.n + i];
+        }
+    }
+    for (int s = 32; s >= 1; s >>= 1) e += __shfl_xor(e, s);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int wv = 0; wv < int(blockDim.x >> 6); ++wv) t += s_sum[wv];
+        atomicAdd((unsigned long long *)&ctl->energy, (unsigned long long)t);
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int nt) { return unsigned((n + nt - 1) / nt); }
+
+template <int CONN>
+hipError_t solve_conn(const Geom &g, int solver, const int32_t *u, const int32_t *cw, const int32_t *Y,
+                      const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat, int32_t *stats,
+                      Ctl *ctl, hipStream_t s) {
+    constexpr int H = Sten<CONN>::H;
+    if (solver == 2) {
+        hipLaunchKernelGGL(k_block_exhaustive<CONN>, dim3(blocks_for(g.K, EX_WAVES)), dim3(256), 0, s, g, u, cw, Y,
+                           A0, A1, btab, yhat, stats, ctl);
+        return hipGetLastError();
+    }
+    constexpr int NT = 256;
+    const size_t lds = maxflow_lds_bytes(g.max_np, H);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_block_solve<CONN, NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(LDS_LIMIT));
+        attr_set = true;
+    }
+    const int32_t round_limit = 65536 + 64 * g.max_np;
+    hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(g.K), dim3(NT), lds, s, g, u, cw, Y, A0, A1, btab, yhat,
+                       stats, ctl, g.max_np, round_limit, 8);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
+                               hipStream_t s) {
+    const int64_t nh = g.n * g.hs;
+    switch (g.conn) {
+        case 4:
+            hipLaunchKernelGGL(k_prep_weights<4>, dim3(blocks_for(nh, 256)), dim3(256), 0, s, g, w, cw, lam_q8, ctl);
+            hipLaunchKernelGGL(k_check_capsum<4>, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g, cw, ctl);
+            break;
+        case 8:
+            hipLaunchKernelGGL(k_prep_weights<8>, dim3(blocks_for(nh, 256)), dim3(256), 0, s, g, w, cw, lam_q8, ctl);
+            hipLaunchKernelGGL(k_check_capsum<8>, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g, cw, ctl);
+            break;
+        default:
+            hipLaunchKernelGGL(k_prep_weights<6>, dim3(blocks_for(nh, 256)), dim3(256), 0, s, g, w, cw, lam_q8, ctl);
+            hipLaunchKernelGGL(k_check_capsum<6>, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g, cw, ctl);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(const Geom &g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid,
+                             Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2, hipStream_t s) {
+    int64_t m = g.n > g.tot ? g.n : g.tot;
+    unsigned nb = blocks_for(m, 256);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_init_state, dim3(nb), dim3(256), 0, s, g, Y, A0, A1, yhat, resid, ctl, mu0, mu_num, mu_den,
+                       eps2);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_setup, dim3(1), dim3(64), 0, s, ctl, t_limit, stop_on_converge, clear_energy);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_solve(const Geom &g, int solver, const int32_t *u, const int32_t *cw, const int32_t *Y,
+                              const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat,
+                              int32_t *stats, Ctl *ctl, hipStream_t s) {
+    switch (g.conn) {
+        case 4: return solve_conn<4>(g, solver, u, cw, Y, A0, A1, btab, yhat, stats, ctl, s);
+        case 8: return solve_conn<8>(g, solver, u, cw, Y, A0, A1, btab, yhat, stats, ctl, s);
+        default: return solve_conn<6>(g, solver, u, cw, Y, A0, A1, btab, yhat, stats, ctl, s);
+    }
+}
+
+hipError_t launch_consensus(const Geom &g, const int32_t *cw, const uint8_t *yhat, int32_t *A0, int32_t *A1,
+                            int32_t *Y, const int32_t *btab, int64_t *resid, Ctl *ctl, hipStream_t s) {
+    int bpw = CONS_NT / (g.max_np > 0 ? g.max_np : 1);
+    if (bpw < 1) bpw = 1;
+    if (bpw > CONS_MAX_BPW) bpw = CONS_MAX_BPW;
+    const unsigned grid = unsigned((g.K + bpw - 1) / bpw);
+    switch (g.conn) {
+        case 4:
+            hipLaunchKernelGGL(k_consensus<4>, dim3(grid), dim3(CONS_NT), 0, s, g, cw, yhat, A0, A1, Y, btab, resid, ctl, bpw);
+            break;
+        case 8:
+            hipLaunchKernelGGL(k_consensus<8>, dim3(grid), dim3(CONS_NT), 0, s, g, cw, yhat, A0, A1, Y, btab, resid, ctl, bpw);
+            break;
+        default:
+            hipLaunchKernelGGL(k_consensus<6>, dim3(grid), dim3(CONS_NT), 0, s, g, cw, yhat, A0, A1, Y, btab, resid, ctl, bpw);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_labels_energy(const Geom &g, const int32_t *u, const int32_t *w, int32_t lam_q8,
+                                const int32_t *Y, uint8_t *labels, Ctl *ctl, hipStream_t s) {
+    const unsigned grid = blocks_for(g.n, 256);
+    switch (g.conn) {
+        case 4: hipLaunchKernelGGL(k_labels_energy<4>, dim3(grid), dim3(256), 0, s, g, u, w, lam_q8, Y, labels, ctl); break;
+        case 8: hipLaunchKernelGGL(k_labels_energy<8>, dim3(grid), dim3(256), 0, s, g, u, w, lam_q8, Y, labels, ctl); break;
+        default: hipLaunchKernelGGL(k_labels_energy<6>, dim3(grid), dim3(256), 0, s, g, u, w, lam_q8, Y, labels, ctl); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dope

@@ -1,0 +1,175 @@
+"""Thin Python wrapper over the C ABI: owns a dope_ctx and marshals numpy arrays (host) or torch tensors
+(device) into the library's entry points.  No arithmetic of the method happens here."""
+import ctypes
+
+import numpy as np
+
+from . import _native as N
+
+
+def _ptr(a):
+    """Data pointer and memory kind of a numpy array or a torch tensor."""
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return ctypes.c_void_p(a.ctypes.data), N.DOPE_MEM_HOST
+    import torch
+    if not isinstance(a, torch.Tensor) or not a.is_contiguous():
+        raise ValueError("expected a contiguous numpy array or torch tensor")
+    return ctypes.c_void_p(a.data_ptr()), (N.DOPE_MEM_DEVICE if a.is_cuda else N.DOPE_MEM_HOST)
+
+
+class Dope:
+    """One DOPE solve context (see include/dope.h)."""
+
+    def __init__(self, dims, connectivity, block, overlap, mu0, *, ndim=None, mu_fact=(21, 20), eps_q16=6554,
+                 max_iter=50, solver="auto", stream=None, torch_workspace=True):
+        p = N.dope_params()
+        dims = tuple(int(d) for d in dims) + (1,) * (3 - len(dims))
+        p.ndim = ndim if ndim is not None else (3 if connectivity == 6 else 2)
+        p.dims[:] = dims
+        p.connectivity = int(connectivity)
+        p.block[:] = tuple(int(b) for b in block) + (1,) * (3 - len(block))
+        p.overlap[:] = tuple(int(o) for o in overlap) + (0,) * (3 - len(overlap))
+        p.mu0 = int(mu0)
+        p.mu_fact_num, p.mu_fact_den = int(mu_fact[0]), int(mu_fact[1])
+        p.eps_q16 = int(eps_q16)
+        p.max_iter = int(max_iter)
+        p.solver = {"auto": N.DOPE_SOLVER_AUTO, "maxflow": N.DOPE_SOLVER_MAXFLOW,
+                    "exhaustive": N.DOPE_SOLVER_EXHAUSTIVE}[solver]
+        self._workspace = None
+        if stream is None and torch_workspace:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        p.stream = ctypes.c_void_p(stream) if stream else None
+        self.params = p
+        ctx = ctypes.c_void_p()
+        st = N.dope_create(ctypes.byref(p), ctypes.byref(ctx))
+        if st != N.DOPE_OK:
+            raise N.DopeError(st, N.dope_last_error(None).decode())
+        self.ctx = ctx
+        n = ctypes.c_int64()
+        K = ctypes.c_int32()
+        tot = ctypes.c_int64()
+        h = ctypes.c_int32()
+        N.check(N.dope_sizes(ctx, ctypes.byref(n), ctypes.byref(K), ctypes.byref(tot), ctypes.byref(h)), ctx)
+        self.n, self.K, self.tot, self.h = n.value, K.value, tot.value, h.value
+        if torch_workspace:
+            import torch
+            nbytes = N.dope_workspace_bytes(ctypes.byref(p))
+            # torch's caching allocator returns 256-byte aligned blocks
+            self._workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            base = self._workspace.data_ptr()
+            aligned = (base + 255) & ~255
+            N.check(N.dope_bind_workspace(ctx, ctypes.c_void_p(aligned), ctypes.c_size_t(nbytes)), ctx)
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        kw.setdefault("mu_fact", (prob.mu_num, prob.mu_den))
+        kw.setdefault("eps_q16", prob.eps_q16)
+        kw.setdefault("max_iter", prob.max_iter)
+        kw.setdefault("solver", prob.solver)
+        return cls(prob.dims, prob.conn, prob.block, prob.overlap, prob.mu0, ndim=prob.ndim, **kw)
+
+    def close(self):
+        if self.ctx:
+            N.dope_destroy(self.ctx)
+            self.ctx = None
+            self._workspace = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- entry points ----
+    def set_energy(self, u, w, lambda_q8):
+        pu, ku = _ptr(u)
+        pw, kw = _ptr(w)
+        if ku != kw:
+            raise ValueError("u and w must live in the same memory")
+        N.check(N.dope_set_energy(self.ctx, pu, pw, int(lambda_q8), ku), self.ctx)
+
+    def iterate(self, n_iter=1):
+        info = N.dope_info()
+        N.check(N.dope_iterate(self.ctx, int(n_iter), ctypes.byref(info)), self.ctx)
+        return _info(info)
+
+    def iterate_status(self, n_iter=1):
+        """Like iterate() but returns (status, info) instead of raising."""
+        info = N.dope_info()
+        st = N.dope_iterate(self.ctx, int(n_iter), ctypes.byref(info))
+        return st, _info(info)
+
+    def solve(self):
+        info = N.dope_info()
+        N.check(N.dope_solve(self.ctx, ctypes.byref(info)), self.ctx)
+        return _info(info)
+
+    def labels(self, out=None):
+        if out is None:
+            out = np.zeros(self.n, dtype=np.uint8)
+        p, k = _ptr(out)
+        N.check(N.dope_labels(self.ctx, p, k), self.ctx)
+        return out
+
+    def energy(self):
+        e = ctypes.c_int64()
+        N.check(N.dope_energy(self.ctx, ctypes.byref(e)), self.ctx)
+        return e.value
+
+    def get_state(self):
+        Y = np.zeros(self.n, dtype=np.int32)
+        A = np.zeros(self.tot, dtype=np.int32)
+        yh = np.zeros(self.tot, dtype=np.uint8)
+        mu = ctypes.c_int64()
+        t = ctypes.c_int32()
+        N.check(N.dope_get_state(self.ctx, ctypes.c_void_p(Y.ctypes.data), ctypes.c_void_p(A.ctypes.data),
+                                 ctypes.c_void_p(yh.ctypes.data), ctypes.byref(mu), ctypes.byref(t)), self.ctx)
+        return Y, A, yh, mu.value, t.value
+
+    def set_state(self, Y, A, yhat, mu, t):
+        Y = np.ascontiguousarray(Y, dtype=np.int32)
+        A = np.ascontiguousarray(A, dtype=np.int32)
+        yhat = np.ascontiguousarray(yhat, dtype=np.uint8)
+        N.check(N.dope_set_state(self.ctx, ctypes.c_void_p(Y.ctypes.data), ctypes.c_void_p(A.ctypes.data),
+                                 ctypes.c_void_p(yhat.ctypes.data), int(mu), int(t)), self.ctx)
+
+    def block_resid(self):
+        r = np.zeros(self.K, dtype=np.int64)
+        N.check(N.dope_block_resid(self.ctx, ctypes.c_void_p(r.ctypes.data)), self.ctx)
+        return r
+
+    def block_stats(self):
+        s = np.zeros((self.K, 4), dtype=np.int32)
+        N.check(N.dope_block_stats(self.ctx, ctypes.c_void_p(s.ctypes.data)), self.ctx)
+        return s
+
+    def block_table(self):
+        K = ctypes.c_int32()
+        tab = np.zeros((self.K, 7), dtype=np.int32)
+        N.check(N.dope_block_table(self.ctx, ctypes.byref(K), ctypes.c_void_p(tab.ctypes.data)), self.ctx)
+        return tab
+
+    def profile_enable(self, on=True):
+        N.check(N.dope_profile_enable(self.ctx, 1 if on else 0), self.ctx)
+
+    def profile_read(self):
+        sm, cm = ctypes.c_double(), ctypes.c_double()
+        sl, cl = ctypes.c_int32(), ctypes.c_int32()
+        N.check(N.dope_profile_read(self.ctx, ctypes.byref(sm), ctypes.byref(sl), ctypes.byref(cm),
+                                    ctypes.byref(cl)), self.ctx)
+        return {"solve_ms": sm.value, "solve_launches": sl.value, "consensus_ms": cm.value,
+                "consensus_launches": cl.value}
+
+
+def _info(info):
+    return {"iters_done": info.iters_done, "converged": bool(info.converged), "max_resid2": info.max_resid2,
+            "mu": info.mu}

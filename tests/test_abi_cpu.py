@@ -1,0 +1,101 @@
+"""Host-side checks of the C-ABI library (no GPU): it builds, loads, exports every entry point that
+include/dope.h declares, and its parameter validation / workspace sizing behave as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dope.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dope_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_1704_03116_amd import _native as N
+    if not os.path.exists(N.LIB_PATH):
+        from paper_1704_03116_amd import build as B
+        B.build()
+    N.lib()
+    return N
+
+
+def test_header_declares_the_core_entry_points():
+    names = header_functions()
+    for core in ("dope_create", "dope_set_energy", "dope_iterate", "dope_solve", "dope_labels", "dope_energy",
+                 "dope_destroy"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol(native):
+    L = native.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+
+
+def test_binding_covers_the_header(native):
+    assert sorted(native.SIGNATURES) == header_functions()
+
+
+def _params(native, dims=(512, 512, 1), conn=8, block=(32, 32, 1), overlap=(2, 2, 0), mu0=1000, solver=0, ndim=2):
+    p = native.dope_params()
+    p.ndim = ndim
+    p.dims[:] = dims
+    p.connectivity = conn
+    p.block[:] = block
+    p.overlap[:] = overlap
+    p.mu0 = mu0
+    p.mu_fact_num, p.mu_fact_den = 21, 20
+    p.eps_q16 = 6554
+    p.max_iter = 50
+    p.solver = solver
+    return p
+
+
+def _workspace_model(n, h, K, tot):
+    a = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    return (a(128) + a(K * 32) + a(4 * n) + 2 * a(4 * h * n) + a(4 * n) + 2 * a(4 * tot) + a(tot) + a(8 * K)
+            + a(16 * K) + a(n))
+
+
+@pytest.mark.parametrize("dims,conn,block,overlap,ndim", [
+    ((512, 512, 1), 8, (32, 32, 1), (2, 2, 0), 2),
+    ((64, 64, 1), 4, (16, 16, 1), (1, 1, 0), 2),
+    ((128, 128, 64), 6, (16, 16, 16), (1, 1, 1), 3),
+    ((257, 131, 1), 8, (32, 16, 1), (3, 1, 0), 2),
+])
+def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, ndim):
+    from oracle import dope as od
+    p = _params(native, dims, conn, block, overlap, ndim=ndim)
+    blocks = od.make_blocks(dims, block, overlap)
+    n = dims[0] * dims[1] * dims[2]
+    h = {4: 2, 8: 4, 6: 3}[conn]
+    tot = sum(len(b.idx) for b in blocks)
+    assert native.dope_workspace_bytes(ctypes.byref(p)) == _workspace_model(n, h, len(blocks), tot)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(overlap=(17, 2, 0)), "overlap"),
+    (dict(conn=6), "connectivity"),
+    (dict(mu0=0), "mu0"),
+    (dict(block=(64, 64, 1)), "LDS"),                     # 64x64 8-connected exceeds 160 KiB of LDS
+    (dict(block=(32, 32, 1), solver=2), "exhaustive"),    # enumeration needs <= 16 pixels
+    (dict(dims=(0, 5, 1)), "dims"),
+])
+def test_create_rejects_bad_params(native, kw, msg):
+    p = _params(native, **kw)
+    ctx = ctypes.c_void_p()
+    assert native.dope_create(ctypes.byref(p), ctypes.byref(ctx)) == native.DOPE_EINVAL
+    assert msg in native.dope_last_error(None).decode()
+    assert native.dope_workspace_bytes(ctypes.byref(p)) == 0
+
+
+def test_last_error_null_safe(native):
+    assert isinstance(native.dope_last_error(None), bytes)

@@ -1,0 +1,293 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, bit-exact at every ADMM iteration.
+
+Small problems are compared on the whole state (Y, A, block labels, mu, t, per-block residuals) after every
+iteration.  Full-size workloads are compared on sampled block solves and on the complete consensus /
+multiplier update, both recomputed by the oracle from the GPU's own state of the previous iteration."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dope as od
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1704_03116_amd import _native as N
+    N.lib()   # raises when the library is missing: no fallback
+
+
+def make_ctx(p, **kw):
+    from paper_1704_03116_amd.solver import Dope
+    d = Dope.from_problem(p, **kw)
+    d.set_energy(np.ascontiguousarray(p.u, np.int32), np.ascontiguousarray(p.w, np.int32), p.lam_q8)
+    return d
+
+
+def first_mismatch(a, b):
+    idx = np.flatnonzero(np.asarray(a) != np.asarray(b))
+    return None if len(idx) == 0 else (int(idx[0]), a[idx[0]], b[idx[0]], len(idx))
+
+
+def assert_state_equal(d, S, info_o, t, dec):
+    Y, A, yh, mu, tt = d.get_state()
+    assert tt == S.t == t, (tt, S.t, t)
+    mm = first_mismatch(yh, S.yhat)
+    if mm is not None:
+        k = int(np.searchsorted(dec.offsets, mm[0], side="right") - 1)
+        raise AssertionError(f"iteration {t}: block labels differ at {mm} (block {k})")
+    assert first_mismatch(Y, S.Y) is None, f"iteration {t}: Y differs {first_mismatch(Y, S.Y)}"
+    assert first_mismatch(A, S.A) is None, f"iteration {t}: A differs {first_mismatch(A, S.A)}"
+    assert mu == S.M
+    assert np.array_equal(d.block_resid(), info_o.resid2), f"iteration {t}: residuals differ"
+
+
+def run_parity(p, n_iter, label):
+    announce(f"{label}: dims={p.dims} conn={p.conn} block={p.block} overlap={p.overlap} mu0={p.mu0} "
+             f"solver={p.solver} iters={n_iter}")
+    st_o, infos, states, dec = od.run(p, n_iter=n_iter, record=True)
+    d = make_ctx(p)
+    try:
+        for t, (S, inf) in enumerate(zip(states, infos), start=1):
+            status, info = d.iterate_status(1)
+            if inf.overflow:
+                assert status == -5, f"oracle overflowed at iteration {t}, GPU status {status}"
+                assert_state_equal(d, S, inf, t, dec)
+                return d, st_o, dec
+            assert status == 0, f"iteration {t}: status {status}"
+            assert info["converged"] == (int(np.max(inf.resid2)) <= p.eps_q16 ** 2)
+            assert_state_equal(d, S, inf, t, dec)
+        return d, st_o, dec
+    except Exception:
+        d.close()
+        raise
+
+
+def test_config1_every_iteration():
+    """64x64 disk, 4-connected, 16x16 blocks with 1-px overlap, 50 iterations."""
+    p = synth.config1()
+    d, st_o, dec = run_parity(p, 50, "config1")
+    l = d.labels()
+    assert np.array_equal(l, od.labels(st_o.Y))
+    assert d.energy() == od.energy_q(dec, od.labels(st_o.Y))
+    d.close()
+
+
+@pytest.mark.parametrize("W,H,seed", [(100, 90, 0), (131, 67, 3)])
+def test_config2_small_every_iteration(W, H, seed):
+    """config-2 construction (3-channel ellipses, 8-connected contrast weights, lambda 2, 32x32 / o = 2) on
+    grids with ragged edge blocks."""
+    p = synth.config2(seed=seed, W=W, H=H)
+    p.mu0 = 300   # a smaller mu keeps several iterations non-trivial
+    d, _, _ = run_parity(p, 8, f"config2 {W}x{H}")
+    d.close()
+
+
+def test_config3_small_every_iteration():
+    p = synth.config3(dims=(40, 36, 20))
+    d, _, _ = run_parity(p, 6, "config3 40x36x20")
+    d.close()
+
+
+CASES = [
+    # dims, conn, block, overlap, lam_q8, mu0
+    ((17, 13, 1), 4, (5, 4, 1), (1, 1, 0), 256, 1000),
+    ((33, 29, 1), 8, (8, 8, 1), (2, 3, 0), 600, 2000),
+    ((19, 23, 1), 8, (16, 16, 1), (8, 8, 0), 300, 500),     # overlap = B/2 (q up to 4 everywhere)
+    ((9, 11, 7), 6, (4, 5, 3), (1, 2, 1), 384, 5000),      # 3D, 8 copies at corners
+    ((1, 40, 1), 4, (1, 8, 1), (0, 2, 0), 256, 1000),      # one-pixel-wide grid
+    ((45, 3, 1), 8, (16, 3, 1), (1, 0, 0), 900, 1500),     # single block along y
+    ((21, 21, 1), 4, (0, 0, 0), (0, 0, 0), 256, 1000),     # one block: global cut
+    ((50, 40, 1), 8, (32, 32, 1), (2, 2, 0), 1000, 100),   # strong smoothing, small mu
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_random_shapes_every_iteration(case):
+    dims, conn, block, overlap, lam, mu0 = case
+    p = synth.random_problem(11, dims, conn, block, overlap, lam_q8=lam, u_range=(-2500, 2500),
+                             w_range=(0, 900), mu0=mu0)
+    d, _, _ = run_parity(p, 5, f"random {case}")
+    d.close()
+
+
+def test_smoothing_dominated_blocks():
+    """Weak unaries, strong edges: almost no node is forced, so push-relabel does all the work."""
+    p = synth.random_problem(12, (48, 40, 1), 8, (16, 16, 1), (1, 1, 0), lam_q8=768, u_range=(-400, 400),
+                             w_range=(200, 1000), mu0=800)
+    d, _, _ = run_parity(p, 6, "smoothing dominated")
+    stats = d.block_stats()
+    assert stats[:, 0].sum() > 0 and stats[:, 1].sum() > 0
+    d.close()
+
+
+def test_exhaustive_nonsubmodular_every_iteration():
+    p = synth.config4(size=40)
+    d, _, _ = run_parity(p, 5, "config4 40x40 exhaustive")
+    d.close()
+
+
+def test_exhaustive_equals_maxflow_on_submodular():
+    p = synth.random_problem(13, (23, 18, 1), 4, (4, 4, 1), (1, 1, 0), lam_q8=256, mu0=1000)
+    d1, _, _ = run_parity(p, 4, "maxflow 4x4")
+    p.solver = "exhaustive"
+    d2, _, _ = run_parity(p, 4, "exhaustive 4x4")
+    assert np.array_equal(d1.get_state()[2], d2.get_state()[2])
+    d1.close()
+    d2.close()
+
+
+def test_overflow_matches_oracle():
+    p = synth.config1(mu0=1)
+    d, _, _ = run_parity(p, 10, "overflow mu0=1")
+    status, _ = d.iterate_status(1)
+    assert status == -5     # frozen: later calls keep reporting the overflow
+    d.close()
+
+
+def test_solve_to_convergence_and_energy():
+    p = synth.config2(W=160, H=160)
+    announce("solve config2 160x160")
+    st_o, infos, _, dec = od.run(p)
+    d = make_ctx(p)
+    info = d.solve()
+    assert info["iters_done"] == len(infos)
+    assert info["converged"] == infos[-1].converged
+    Y, A, yh, mu, t = d.get_state()
+    assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+    l = d.labels()
+    assert np.array_equal(l, od.labels(st_o.Y))
+    assert d.energy() == od.energy_q(dec, l)
+    d.close()
+
+
+def test_error_paths():
+    from paper_1704_03116_amd import _native as N
+    from paper_1704_03116_amd.solver import Dope
+    announce("error paths")
+    p = synth.random_problem(14, (20, 20, 1), 4, (8, 8, 1), (1, 1, 0), neg_frac=0.3)
+    with Dope.from_problem(p, solver="maxflow") as d:
+        with pytest.raises(N.DopeError) as e:
+            d.set_energy(p.u, p.w, p.lam_q8)
+        assert e.value.status == N.DOPE_ENOTSUBMODULAR
+        with pytest.raises(N.DopeError) as e:
+            d.iterate(1)
+        assert e.value.status == N.DOPE_ESTATE
+    q = synth.random_problem(15, (20, 20, 1), 4, (8, 8, 1), (1, 1, 0))
+    w = q.w.copy()
+    w[0, 19] = 5     # edge leaving the grid on the right
+    with Dope.from_problem(q) as d:
+        with pytest.raises(N.DopeError) as e:
+            d.set_energy(q.u, w, q.lam_q8)
+        assert e.value.status == N.DOPE_EINVAL
+        with pytest.raises(N.DopeError) as e:
+            d.set_energy(q.u, q.w, -1)
+        assert e.value.status == N.DOPE_EINVAL
+
+
+def test_checkpoint_resume_and_determinism():
+    p = synth.config1()
+    announce("checkpoint / resume")
+    a = make_ctx(p)
+    a.iterate(7)
+    straight = a.get_state()
+    b = make_ctx(p)
+    b.iterate(3)
+    Y, A, yh, mu, t = b.get_state()
+    c = make_ctx(p)
+    c.set_state(Y, A, yh, mu, t)
+    c.iterate(4)
+    resumed = c.get_state()
+    for x, y in zip(straight, resumed):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    a2 = make_ctx(p)
+    a2.iterate(7)
+    again = a2.get_state()
+    for x, y in zip(straight, again):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    for d in (a, b, c, a2):
+        d.close()
+
+
+def test_block_table_matches_partition():
+    p = synth.config3(dims=(40, 36, 20))
+    d = make_ctx(p)
+    tab = d.block_table()
+    blocks = od.make_blocks(p.dims, p.block, p.overlap)
+    assert len(tab) == len(blocks)
+    off = 0
+    for row, b in zip(tab, blocks):
+        assert tuple(row[:3]) == b.origin and tuple(row[3:6]) == b.extent and row[6] == off
+        off += len(b.idx)
+    d.close()
+
+
+def test_device_inputs_and_labels():
+    """Inputs already resident in HBM (torch tensors), labels written to a device tensor."""
+    import torch
+    p = synth.config1()
+    announce("device-resident inputs")
+    from paper_1704_03116_amd.solver import Dope
+    d = Dope.from_problem(p)
+    u = torch.from_numpy(np.ascontiguousarray(p.u, np.int32)).cuda()
+    w = torch.from_numpy(np.ascontiguousarray(p.w, np.int32)).cuda()
+    d.set_energy(u, w, p.lam_q8)
+    d.iterate(5)
+    lab = torch.zeros(p.n, dtype=torch.uint8, device="cuda")
+    d.labels(lab)
+    st_o, _, _, _ = od.run(p, n_iter=5)
+    assert np.array_equal(lab.cpu().numpy(), od.labels(st_o.Y))
+    d.close()
+
+
+# ------------------------------------------------------------------------------------------------------------
+# full-size workloads: sampled block solves + complete consensus, from the GPU's own previous state
+# ------------------------------------------------------------------------------------------------------------
+
+def sampled_parity(p, n_iter, n_sample, label, seed=0):
+    announce(f"{label}: full size {p.dims}, {n_iter} iterations, {n_sample} sampled blocks per iteration")
+    dec = od.decompose(p)
+    d = make_ctx(p)
+    rng = np.random.default_rng(seed)
+    K = len(dec.blocks)
+    prev = d.get_state()
+    for t in range(1, n_iter + 1):
+        status, info = d.iterate_status(1)
+        assert status == 0
+        cur = d.get_state()
+        Y0, A0, _, M0, _ = prev
+        Y1, A1, yh1, M1, t1 = cur
+        assert t1 == t and M1 == od.next_mu(M0, p.mu_num, p.mu_den)
+        sample = rng.choice(K, size=min(n_sample, K), replace=False)
+        for k in sample:
+            a, b = dec.offsets[k], dec.offsets[k + 1]
+            Ut, ea, eb, cap = od.block_subproblem(dec, int(k), Y0.astype(np.int64), A0[a:b].astype(np.int64), M0)
+            x, _ = od.solve_subproblem(Ut, ea, eb, cap, "maxflow" if p.solver == "maxflow" else "exhaustive")
+            assert np.array_equal(yh1[a:b], x), f"iteration {t}: block {k} labels differ"
+        st = od.State(Y0.astype(np.int64), A0.astype(np.int64), yh1.copy(), M0, t - 1)
+        new, inf = od.iterate(dec, st, yhat_override=yh1, mu_num=p.mu_num, mu_den=p.mu_den, eps_q16=p.eps_q16)
+        assert np.array_equal(Y1, new.Y), f"iteration {t}: consensus differs"
+        assert np.array_equal(A1, new.A), f"iteration {t}: multipliers differ"
+        assert np.array_equal(d.block_resid(), inf.resid2)
+        prev = cur
+    d.close()
+
+
+def test_config2_full_size_sampled():
+    sampled_parity(synth.config2(), 4, 40, "config2 512x512")
+
+
+def test_config3_full_size_sampled():
+    sampled_parity(synth.config3(), 3, 12, "config3 128x128x64")
+
+
+def test_config4_full_size_sampled():
+    sampled_parity(synth.config4(), 2, 150, "config4 256x256 exhaustive")
