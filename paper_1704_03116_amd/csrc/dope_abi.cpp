@@ -25,11 +25,12 @@ struct dope_ctx {
     bool own_ws = false;
     Ctl *ctl = nullptr;
     int32_t *btab = nullptr, *u = nullptr, *w = nullptr, *cw = nullptr, *Y = nullptr, *A0 = nullptr, *A1 = nullptr;
-    int32_t *stats = nullptr;
+    int32_t *stats = nullptr, *cov = nullptr, *chunk_k0 = nullptr;
     uint8_t *yhat = nullptr, *labels = nullptr;
-    int64_t *resid = nullptr;
+    int64_t *resid = nullptr, *epart = nullptr;
     Ctl *hctl = nullptr;       // pinned host mirror of the control block
-    std::vector<int32_t> hbtab;
+    std::vector<int32_t> hbtab, hcov, hchunk;
+    dope::Tables tables{};
     int32_t lam_q8 = 0;
     bool energy_set = false;
     bool profiling = false;
@@ -41,7 +42,7 @@ struct dope_ctx {
 namespace {
 
 struct Layout {
-    size_t ctl, btab, u, w, cw, Y, A0, A1, yhat, resid, stats, labels, total;
+    size_t ctl, btab, cov, chunk, u, w, cw, Y, A0, A1, yhat, resid, stats, labels, epart, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -52,6 +53,8 @@ Layout layout_for(const Geom &g) {
     auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
     L.ctl = take(sizeof(Ctl));
     L.btab = take(size_t(g.K) * dope::BTAB_STRIDE * 4);
+    L.cov = take(size_t(g.W + g.H + g.D) * 4);
+    L.chunk = take(size_t((g.tot + dope::CHUNK - 1) / dope::CHUNK) * 4);
     L.u = take(size_t(g.n) * 4);
     L.w = take(size_t(g.n) * g.hs * 4);
     L.cw = take(size_t(g.n) * g.hs * 4);
@@ -62,6 +65,7 @@ Layout layout_for(const Geom &g) {
     L.resid = take(size_t(g.K) * 8);
     L.stats = take(size_t(g.K) * 16);
     L.labels = take(size_t(g.n));
+    L.epart = take(size_t(dope::ENERGY_PARTS) * 8);
     L.total = o;
     return L;
 }
@@ -154,6 +158,29 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
 
 thread_local std::string g_create_error;
 
+// cov[x] = t_hi | (1 << 30 if x also lies in interval t_hi - 1), per axis, back to back (W, H, D entries);
+// chunk[c] = block containing block-major copy c * CHUNK.
+void build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<int32_t> &cov,
+                  std::vector<int32_t> &chunk) {
+    cov.clear();
+    for (int a = 0; a < 3; ++a) {
+        const dope::Axis &ax = g.ax[a];
+        for (int x = 0; x < ax.N; ++x) {
+            int th = std::min(x / ax.s, ax.nb - 1);
+            const bool two = th >= 1 && x < (th - 1) * ax.s + ax.B;
+            cov.push_back(th | (two ? (1 << 30) : 0));
+        }
+    }
+    const int64_t nch = (g.tot + dope::CHUNK - 1) / dope::CHUNK;
+    chunk.assign(size_t(nch), 0);
+    int64_t k = 0;
+    for (int64_t ch = 0; ch < nch; ++ch) {
+        const int64_t first = ch * dope::CHUNK;
+        while (k + 1 < g.K && btab[size_t(k + 1) * dope::BTAB_STRIDE + 6] <= first) ++k;
+        chunk[size_t(ch)] = int32_t(k);
+    }
+}
+
 dope_status fail(dope_ctx *c, dope_status s, const std::string &msg) {
     if (c) c->err = msg;
     return s;
@@ -174,6 +201,11 @@ void assign_pointers(dope_ctx *c) {
     char *b = c->ws;
     c->ctl = reinterpret_cast<Ctl *>(b + L.ctl);
     c->btab = reinterpret_cast<int32_t *>(b + L.btab);
+    c->cov = reinterpret_cast<int32_t *>(b + L.cov);
+    c->chunk_k0 = reinterpret_cast<int32_t *>(b + L.chunk);
+    c->tables.cov = c->cov;
+    c->tables.chunk_k0 = c->chunk_k0;
+    c->tables.n_chunks = int32_t(c->hchunk.size());
     c->u = reinterpret_cast<int32_t *>(b + L.u);
     c->w = reinterpret_cast<int32_t *>(b + L.w);
     c->cw = reinterpret_cast<int32_t *>(b + L.cw);
@@ -184,6 +216,17 @@ void assign_pointers(dope_ctx *c) {
     c->resid = reinterpret_cast<int64_t *>(b + L.resid);
     c->stats = reinterpret_cast<int32_t *>(b + L.stats);
     c->labels = reinterpret_cast<uint8_t *>(b + L.labels);
+    c->epart = reinterpret_cast<int64_t *>(b + L.epart);
+}
+
+dope_status upload_tables(dope_ctx *c) {
+    HIP_TRY(c, hipMemcpyAsync(c->btab, c->hbtab.data(), c->hbtab.size() * 4, hipMemcpyHostToDevice, c->stream),
+            "block table upload");
+    HIP_TRY(c, hipMemcpyAsync(c->cov, c->hcov.data(), c->hcov.size() * 4, hipMemcpyHostToDevice, c->stream),
+            "cover table upload");
+    HIP_TRY(c, hipMemcpyAsync(c->chunk_k0, c->hchunk.data(), c->hchunk.size() * 4, hipMemcpyHostToDevice, c->stream),
+            "chunk table upload");
+    return DOPE_OK;
 }
 
 dope_status ensure_workspace(dope_ctx *c) {
@@ -198,9 +241,7 @@ dope_status ensure_workspace(dope_ctx *c) {
     c->ws_bytes = bytes;
     c->own_ws = true;
     assign_pointers(c);
-    HIP_TRY(c, hipMemcpyAsync(c->btab, c->hbtab.data(), c->hbtab.size() * 4, hipMemcpyHostToDevice, c->stream),
-            "block table upload");
-    return DOPE_OK;
+    return upload_tables(c);
 }
 
 dope_status sync_ctl(dope_ctx *c) {
@@ -232,23 +273,23 @@ dope_status enqueue_iterations(dope_ctx *c, int count) {
         if (c->profiling) {
             e0 = next_event(c->ev_solve, 2 * c->n_solve);
             e1 = next_event(c->ev_solve, 2 * c->n_solve + 1);
-            if (e0 && e1) hipEventRecord(e0, c->stream);
+            if (e0 && e1) (void)hipEventRecord(e0, c->stream);
         }
-        HIP_TRY(c, dope::launch_block_solve(c->g, c->solver, c->u, c->cw, c->Y, c->A0, c->A1, c->btab, c->yhat,
-                                            c->stats, c->ctl, c->stream),
+        HIP_TRY(c, dope::launch_block_solve(c->g, c->tables, c->solver, c->u, c->cw, c->Y, c->A0, c->A1, c->btab,
+                                            c->yhat, c->stats, c->resid, c->ctl, c->stream),
                 "block solve launch");
         if (c->profiling && e0 && e1) {
-            hipEventRecord(e1, c->stream);
+            (void)hipEventRecord(e1, c->stream);
             ++c->n_solve;
             e0 = next_event(c->ev_cons, 2 * c->n_cons);
             e1 = next_event(c->ev_cons, 2 * c->n_cons + 1);
-            if (e0 && e1) hipEventRecord(e0, c->stream);
+            if (e0 && e1) (void)hipEventRecord(e0, c->stream);
         }
-        HIP_TRY(c, dope::launch_consensus(c->g, c->cw, c->yhat, c->A0, c->A1, c->Y, c->btab, c->resid, c->ctl,
-                                          c->stream),
+        HIP_TRY(c, dope::launch_consensus(c->g, c->tables, c->cw, c->yhat, c->A0, c->A1, c->Y, c->btab, c->resid,
+                                          c->ctl, c->stream),
                 "consensus launch");
         if (c->profiling && e0 && e1) {
-            hipEventRecord(e1, c->stream);
+            (void)hipEventRecord(e1, c->stream);
             ++c->n_cons;
         }
     }
@@ -280,6 +321,7 @@ dope_status dope_create(const dope_params *p, dope_ctx **out) {
     c->p = q;
     c->g = g;
     c->hbtab.swap(bt);
+    build_tables(c->g, c->hbtab, c->hcov, c->hchunk);
     if (q.stream) {
         c->stream = static_cast<hipStream_t>(q.stream);
     } else {
@@ -291,7 +333,7 @@ dope_status dope_create(const dope_params *p, dope_ctx **out) {
     }
     void *h = nullptr;
     if (hipHostMalloc(&h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
-        if (c->own_stream) hipStreamDestroy(c->stream);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return DOPE_EDEVICE;
     }
@@ -319,9 +361,7 @@ dope_status dope_bind_workspace(dope_ctx *c, void *dev_ptr, size_t bytes) {
     c->ws_bytes = bytes;
     c->own_ws = false;
     assign_pointers(c);
-    HIP_TRY(c, hipMemcpyAsync(c->btab, c->hbtab.data(), c->hbtab.size() * 4, hipMemcpyHostToDevice, c->stream),
-            "block table upload");
-    return DOPE_OK;
+    return upload_tables(c);
 }
 
 dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int32_t lambda_q8, int32_t mem_kind) {
@@ -338,7 +378,7 @@ dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int
     HIP_TRY(c, dope::launch_init_state(g, c->Y, c->A0, c->A1, c->yhat, c->resid, c->ctl, c->p.mu0, c->p.mu_fact_num,
                                        c->p.mu_fact_den, eps2, c->stream),
             "state init launch");
-    HIP_TRY(c, dope::launch_prep_weights(g, c->w, c->cw, lambda_q8, c->ctl, c->stream), "weight prep launch");
+    HIP_TRY(c, dope::launch_prep_weights(g, c->tables, c->w, c->cw, lambda_q8, c->ctl, c->stream), "weight prep launch");
     st = sync_ctl(c);
     if (st != DOPE_OK) return st;
     c->energy_set = false;
@@ -411,20 +451,18 @@ dope_status dope_labels(dope_ctx *c, uint8_t *labels, int32_t mem_kind) {
     if (st != DOPE_OK) return st;
     if (!labels) return fail(c, DOPE_EINVAL, "null labels");
     uint8_t *dst = mem_kind == DOPE_MEM_DEVICE ? labels : c->labels;
-    HIP_TRY(c, dope::launch_ctl_setup(c->ctl, c->hctl->t, c->hctl->stop_on_converge, 1, c->stream), "control setup");
-    HIP_TRY(c, dope::launch_labels_energy(c->g, c->u, c->w, c->lam_q8, c->Y, dst, c->ctl, c->stream), "labels launch");
+    HIP_TRY(c, dope::launch_labels(c->g, c->Y, dst, c->stream), "labels launch");
     if (mem_kind != DOPE_MEM_DEVICE)
         HIP_TRY(c, hipMemcpyAsync(labels, c->labels, size_t(c->g.n), hipMemcpyDeviceToHost, c->stream), "labels copy");
-    return sync_ctl(c);
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return DOPE_OK;
 }
 
 dope_status dope_energy(dope_ctx *c, int64_t *e_q8) {
     dope_status st = check_ready(c);
     if (st != DOPE_OK) return st;
     if (!e_q8) return fail(c, DOPE_EINVAL, "null output");
-    HIP_TRY(c, dope::launch_ctl_setup(c->ctl, c->hctl->t, c->hctl->stop_on_converge, 1, c->stream), "control setup");
-    HIP_TRY(c, dope::launch_labels_energy(c->g, c->u, c->w, c->lam_q8, c->Y, nullptr, c->ctl, c->stream),
-            "energy launch");
+    HIP_TRY(c, dope::launch_energy(c->g, c->u, c->w, c->lam_q8, c->Y, c->epart, c->ctl, c->stream), "energy launch");
     st = sync_ctl(c);
     if (st != DOPE_OK) return st;
     *e_q8 = c->hctl->energy;
@@ -549,12 +587,12 @@ const char *dope_last_error(const dope_ctx *c) { return c ? c->err.c_str() : g_c
 
 void dope_destroy(dope_ctx *c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
-    for (hipEvent_t e : c->ev_solve) hipEventDestroy(e);
-    for (hipEvent_t e : c->ev_cons) hipEventDestroy(e);
-    if (c->own_ws && c->ws) hipFree(c->ws);
-    if (c->hctl) hipHostFree(c->hctl);
-    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev_solve) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_cons) (void)hipEventDestroy(e);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->hctl) (void)hipHostFree(c->hctl);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 

@@ -56,19 +56,31 @@ constexpr int BTAB_STRIDE = 8;     // x0, y0, z0, ex, ey, ez, offset, pad
 inline size_t maxflow_lds_bytes(int np, int hs) { return 64 + size_t(np) * (8 * hs + 8); }
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
 
+// Device lookup tables built on the host with the partition.
+struct Tables {
+    const int32_t *cov;        // per-axis cover tables (W + H + D entries), see dope_kernels.hip
+    const int32_t *chunk_k0;   // block containing the first copy of every 256-copy chunk
+    int32_t n_chunks;
+};
+
+constexpr int CHUNK = 256;
+
 // Kernel launchers (dope_kernels.hip).  All return hipSuccess or the launch error.
-hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
-                               hipStream_t s);
+hipError_t launch_prep_weights(const Geom &g, const Tables &tb, const int32_t *w, int32_t *cw, int32_t lam_q8,
+                               Ctl *ctl, hipStream_t s);
 hipError_t launch_init_state(const Geom &g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid,
                              Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2, hipStream_t s);
 hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy,
                             hipStream_t s);
-hipError_t launch_block_solve(const Geom &g, int solver, const int32_t *u, const int32_t *cw, const int32_t *Y,
-                              const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat,
-                              int32_t *stats, Ctl *ctl, hipStream_t s);
-hipError_t launch_consensus(const Geom &g, const int32_t *cw, const uint8_t *yhat, int32_t *A0, int32_t *A1,
-                            int32_t *Y, const int32_t *btab, int64_t *resid, Ctl *ctl, hipStream_t s);
-hipError_t launch_labels_energy(const Geom &g, const int32_t *u, const int32_t *w, int32_t lam_q8,
-                                const int32_t *Y, uint8_t *labels, Ctl *ctl, hipStream_t s);
+hipError_t launch_block_solve(const Geom &g, const Tables &tb, int solver, const int32_t *u, const int32_t *cw,
+                              const int32_t *Y, const int32_t *A0, const int32_t *A1, const int32_t *btab,
+                              uint8_t *yhat, int32_t *stats, int64_t *resid, Ctl *ctl, hipStream_t s);
+hipError_t launch_consensus(const Geom &g, const Tables &tb, const int32_t *cw, const uint8_t *yhat, int32_t *A0,
+                            int32_t *A1, int32_t *Y, const int32_t *btab, int64_t *resid, Ctl *ctl, hipStream_t s);
+hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s);
+// part: ENERGY_PARTS int64 of scratch.
+hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *w, int32_t lam_q8, const int32_t *Y,
+                         int64_t *part, Ctl *ctl, hipStream_t s);
+constexpr int ENERGY_PARTS = 256;
 
 }  // namespace dope

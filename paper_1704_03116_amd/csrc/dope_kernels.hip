@@ -52,23 +52,18 @@ __device__ __forceinline__ int3 full_dir(int d) {
     return v;
 }
 
-// Intervals of one axis containing coordinate x: t_hi always, t_hi - 1 when inside the overlap.
-__device__ __forceinline__ int axis_cover(const Axis &a, int x, int &t0, int &t1) {
-    int th = x / a.s;
-    if (th > a.nb - 1) th = a.nb - 1;
-    t0 = th;
-    if (th >= 1 && x < (th - 1) * a.s + a.B) { t1 = th - 1; return 2; }
-    t1 = th;
-    return 1;
-}
+// Per-axis cover tables: cov[x] = t_hi | (1 << 30 when x also lies in interval t_hi - 1), where t_hi is the
+// highest-index block interval containing coordinate x.  Three tables back to back: W, H, D entries.
+struct Cov {
+    const int32_t *x, *y, *z;
+};
 
-__device__ __forceinline__ int axis_count(const Axis &a, int x) {
-    int t0, t1;
-    return axis_cover(a, x, t0, t1);
-}
+__device__ __forceinline__ Cov cov_of(const Geom &g, const int32_t *cov) { return Cov{cov, cov + g.W, cov + g.W + g.H}; }
+__device__ __forceinline__ int cov_cnt(int32_t c) { return 1 + ((c >> 30) & 1); }
+__device__ __forceinline__ int cov_hi(int32_t c) { return c & 0x3FFFFFFF; }
 
-__device__ __forceinline__ int q_at(const Geom &g, int x, int y, int z) {
-    return axis_count(g.ax[0], x) * axis_count(g.ax[1], y) * axis_count(g.ax[2], z);
+__device__ __forceinline__ int q_at(const Cov &cv, int x, int y, int z) {
+    return cov_cnt(cv.x[x]) * cov_cnt(cv.y[y]) * cov_cnt(cv.z[z]);
 }
 
 __device__ __forceinline__ int axis_extent(const Axis &a, int t) {
@@ -88,9 +83,13 @@ __device__ __forceinline__ bool ctl_skip(const Ctl *ctl) {
     return ctl->halted != 0 || ctl->t >= ctl->t_limit;
 }
 
-__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {   // b > 0
-    int64_t q = a / b;
-    if ((a % b != 0) && (a < 0)) --q;
+// floor(n / M) for M >= 1 and |n| < 2^53: a double-precision estimate within +-2 of the quotient, then an exact
+// integer correction.
+__device__ __forceinline__ int64_t floor_div_est(int64_t n, int64_t M, double invM) {
+    int64_t q = int64_t(floor(double(n) * invM));
+    int64_t r = n - q * M;
+    while (r < 0) { --q; r += M; }
+    while (r >= M) { ++q; r -= M; }
     return q;
 }
 
@@ -98,14 +97,14 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {   // b > 0
 // cap_out[o] = c for in-block half-edges (0 otherwise); mask bit d set for in-block neighbours with c != 0;
 // sumc = sum of |c| over in-block neighbours.
 template <int CONN>
-__device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__restrict__ u,
+__device__ __forceinline__ int64_t block_unary(const Geom &g, const Cov &cv, const int32_t *__restrict__ u,
                                                const int32_t *__restrict__ cw, const int32_t *__restrict__ Y,
                                                int32_t a_ki, int64_t M, int gx, int gy, int gz, int lx, int ly,
                                                int lz, int ex, int ey, int ez, int32_t *cap_out, unsigned &mask,
                                                int64_t &sumc) {
     constexpr int H = Sten<CONN>::H;
     const int64_t i = lin(g, gx, gy, gz);
-    const int qi = q_at(g, gx, gy, gz);
+    const int qi = q_at(cv, gx, gy, gz);
     const int32_t Yi = Y[i];
     int64_t G = 0;
     sumc = 0;
@@ -121,7 +120,7 @@ __device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__r
         if (c == 0) continue;
         const int mx = lx + v.x, my = ly + v.y, mz = lz + v.z;
         const bool inb = mx >= 0 && mx < ex && my >= 0 && my < ey && mz >= 0 && mz < ez;
-        const int qj = q_at(g, jx, jy, jz);
+        const int qj = q_at(cv, jx, jy, jz);
         G += int64_t(c) * int64_t(qj - (inb ? 1 : 0)) * int64_t(Yi - Y[j]);
         if (inb) {
             if (d < H) cap_out[d] = c;
@@ -138,12 +137,14 @@ __device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__r
 // ------------------------------------------------------------------------------------------------------------
 
 template <int CONN, int NT>
-__global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__restrict__ u,
+__global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__restrict__ cov,
+                                                    const int32_t *__restrict__ u,
                                                     const int32_t *__restrict__ cw, const int32_t *__restrict__ Y,
                                                     const int32_t *__restrict__ A0, const int32_t *__restrict__ A1,
                                                     const int32_t *__restrict__ btab, uint8_t *__restrict__ yhat,
-                                                    int32_t *__restrict__ stats, Ctl *ctl, int32_t npmax,
-                                                    int32_t round_limit, int32_t relabel_period) {
+                                                    int32_t *__restrict__ stats, int64_t *__restrict__ resid,
+                                                    Ctl *ctl, int32_t npmax, int32_t round_limit,
+                                                    int32_t relabel_period) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
     if (ctl_skip(ctl)) return;
@@ -154,6 +155,8 @@ __global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__res
     const int np = ex * ey * ez;
     const int32_t *Ain = (ctl->t & 1) ? A1 : A0;
     const int64_t M = ctl->M;
+    const Cov cv = cov_of(g, cov);
+    if (threadIdx.x == 0) resid[k] = 0;     // accumulated by the consensus kernel of this iteration
 
     extern __shared__ __align__(16) unsigned char smem[];
     int *s_ctr = reinterpret_cast<int *>(smem);                    // 16 ints of scalars
@@ -199,8 +202,8 @@ __global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__res
         int32_t cp[H];
         unsigned m;
         int64_t sumc;
-        const int64_t Ut = block_unary<CONN>(g, u, cw, Y, Ain[off + p], M, x0 + lx, y0 + ly, z0 + lz, lx, ly, lz,
-                                             ex, ey, ez, cp, m, sumc);
+        const int64_t Ut = block_unary<CONN>(g, cv, u, cw, Y, Ain[off + p], M, x0 + lx, y0 + ly, z0 + lz, lx, ly,
+                                             lz, ex, ey, ez, cp, m, sumc);
 #pragma unroll
         for (int o = 0; o < H; ++o) {
             cap[o * npmax + p] = cp[o];
@@ -414,14 +417,15 @@ __global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__res
 constexpr int EX_WAVES = 4;   // blocks per 256-thread workgroup
 
 template <int CONN>
-__global__ __launch_bounds__(256) void k_block_exhaustive(Geom g, const int32_t *__restrict__ u,
+__global__ __launch_bounds__(256) void k_block_exhaustive(Geom g, const int32_t *__restrict__ cov,
+                                                          const int32_t *__restrict__ u,
                                                           const int32_t *__restrict__ cw,
                                                           const int32_t *__restrict__ Y,
                                                           const int32_t *__restrict__ A0,
                                                           const int32_t *__restrict__ A1,
                                                           const int32_t *__restrict__ btab,
                                                           uint8_t *__restrict__ yhat, int32_t *__restrict__ stats,
-                                                          Ctl *ctl) {
+                                                          int64_t *__restrict__ resid, Ctl *ctl) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
     if (ctl_skip(ctl)) return;
@@ -446,8 +450,8 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(Geom g, const int32_t 
             int32_t cp[H];
             unsigned m;
             int64_t sumc;
-            int64_t Ut = block_unary<CONN>(g, u, cw, Y, Ain[off + p], ctl->M, x0 + lx, y0 + ly, z0 + lz, lx, ly,
-                                           lz, ex, ey, ez, cp, m, sumc);
+            int64_t Ut = block_unary<CONN>(g, cov_of(g, cov), u, cw, Y, Ain[off + p], ctl->M, x0 + lx, y0 + ly,
+                                           z0 + lz, lx, ly, lz, ex, ey, ez, cp, m, sumc);
             // clamping a strictly forced unary to +-(sum |c| + 1) keeps the minimiser set
             if (Ut > sumc + 1) Ut = sumc + 1;
             if (Ut < -sumc - 1) Ut = -sumc - 1;
@@ -516,6 +520,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(Geom g, const int32_t 
     }
     if (lane < np) yhat[off + lane] = uint8_t((bestc >> lane) & 1u);
     if (lane == 0) {
+        resid[k] = 0;
         stats[4 * k + 0] = np;
         stats[4 * k + 1] = 0;
         stats[4 * k + 2] = 0;
@@ -527,55 +532,60 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(Geom g, const int32_t 
 // Consensus (Eq. 10), multipliers (Eq. 11), residual and loop control
 // ------------------------------------------------------------------------------------------------------------
 
-constexpr int CONS_NT = 256;
-constexpr int CONS_MAX_BPW = 64;
+constexpr int CONS_NT = CHUNK;   // block-pixel copies per workgroup
 
+// One thread per block pixel (k, m): recomputes Y_m from every copy of m and of its stencil neighbours (each
+// copy of m computes the same value), writes its own multiplier A_k,m, and accumulates r_k.  The copy in the
+// block with the highest index along every axis writes Y_m.  The last workgroup to finish reduces max_k r_k,
+// decides convergence / overflow, advances mu and t.
 template <int CONN>
-__global__ __launch_bounds__(CONS_NT) void k_consensus(Geom g, const int32_t *__restrict__ cw,
+__global__ __launch_bounds__(CONS_NT) void k_consensus(Geom g, const int32_t *__restrict__ cov,
+                                                       const int32_t *__restrict__ cw,
                                                        const uint8_t *__restrict__ yhat, int32_t *A0, int32_t *A1,
                                                        int32_t *__restrict__ Y, const int32_t *__restrict__ btab,
-                                                       int64_t *__restrict__ resid, Ctl *ctl, int32_t bpw) {
+                                                       const int32_t *__restrict__ chunk_k0, int64_t *resid,
+                                                       Ctl *ctl) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
     if (ctl_skip(ctl)) return;
-    __shared__ unsigned long long s_res[CONS_MAX_BPW];
-    __shared__ int s_ovf, s_last;
+    __shared__ unsigned long long s_res[CONS_NT];
+    __shared__ int s_ovf;
     const int tid = threadIdx.x;
     const int par = ctl->t & 1;
     const int32_t *Ain = par ? A1 : A0;
     int32_t *Aout = par ? A0 : A1;
     const int64_t M = ctl->M;
-    const int k0 = blockIdx.x * bpw;
-    const int k1 = min(k0 + bpw, g.K);
-    if (tid < CONS_MAX_BPW) s_res[tid] = 0;
+    const double invM = 1.0 / double(M);
+    const Cov cv = cov_of(g, cov);
+    const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
+    const int kfirst = chunk_k0[blockIdx.x];
+    s_res[tid] = 0;
     if (tid == 0) s_ovf = 0;
     __syncthreads();
-    const int64_t c0 = btab[BTAB_STRIDE * k0 + 6];
-    const int64_t c1 = (k1 < g.K) ? int64_t(btab[BTAB_STRIDE * k1 + 6]) : g.tot;
-    const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
-    int kk = k0;
+    const int64_t c = int64_t(blockIdx.x) * CONS_NT + tid;
     int ovf = 0;
-    for (int64_t c = c0 + tid; c < c1; c += CONS_NT) {
-        while (kk + 1 < k1 && int64_t(btab[BTAB_STRIDE * (kk + 1) + 6]) <= c) ++kk;
+    if (c < g.tot) {
+        int kk = kfirst;
+        while (kk + 1 < g.K && int64_t(btab[BTAB_STRIDE * (kk + 1) + 6]) <= c) ++kk;
         const int32_t *bt = btab + BTAB_STRIDE * kk;
         const int ex = bt[3], ey = bt[4];
         const int p = int(c - bt[6]);
         const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
         const int gx = bt[0] + lx, gy = bt[1] + ly, gz = bt[2] + lz;
-        // blocks containing m
-        int tx[2], ty[2], tz[2];
-        const int cxn = axis_cover(AX, gx, tx[0], tx[1]);
-        const int cyn = axis_cover(AY, gy, ty[0], ty[1]);
-        const int czn = axis_cover(AZ, gz, tz[0], tz[1]);
-        const int qm = cxn * cyn * czn;
+        const int32_t cvx = cv.x[gx], cvy = cv.y[gy], cvz = cv.z[gz];
+        const int nxm = cov_cnt(cvx), nym = cov_cnt(cvy), nzm = cov_cnt(cvz);
+        const int txh = cov_hi(cvx), tyh = cov_hi(cvy), tzh = cov_hi(cvz);
+        const int qm = nxm * nym * nzm;
         const int64_t m = lin(g, gx, gy, gz);
         int64_t S = 0, HC = 0;
-        for (int a = 0; a < czn; ++a)
-            for (int b = 0; b < cyn; ++b)
-                for (int e = 0; e < cxn; ++e) {
-                    const int kb = tx[e] + AX.nb * (ty[b] + AY.nb * tz[a]);
-                    const int bx0 = tx[e] * AX.s, by0 = ty[b] * AY.s, bz0 = tz[a] * AZ.s;
-                    const int bex = axis_extent(AX, tx[e]), bey = axis_extent(AY, ty[b]), bez = axis_extent(AZ, tz[a]);
+        // copies of m: S_m and the first term of Hc_m
+        for (int a = 0; a < nzm; ++a)
+            for (int b = 0; b < nym; ++b)
+                for (int e = 0; e < nxm; ++e) {
+                    const int tx = txh - e, ty = tyh - b, tz = tzh - a;
+                    const int kb = tx + AX.nb * (ty + AY.nb * tz);
+                    const int bx0 = tx * AX.s, by0 = ty * AY.s, bz0 = tz * AZ.s;
+                    const int bex = axis_extent(AX, tx), bey = axis_extent(AY, ty), bez = axis_extent(AZ, tz);
                     const int64_t cc = int64_t(btab[BTAB_STRIDE * kb + 6]) + (gx - bx0) +
                                        int64_t(bex) * ((gy - by0) + int64_t(bey) * (gz - bz0));
                     const int yv = yhat[cc];
@@ -591,10 +601,11 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(Geom g, const int32_t *__
                             if (cmj == 0) continue;
                             const bool inb = jx >= bx0 && jx < bx0 + bex && jy >= by0 && jy < by0 + bey &&
                                              jz >= bz0 && jz < bz0 + bez;
-                            HC += int64_t(cmj) * (q_at(g, jx, jy, jz) - (inb ? 1 : 0));
+                            HC += int64_t(cmj) * (q_at(cv, jx, jy, jz) - (inb ? 1 : 0));
                         }
                     }
                 }
+        // second term of Hc_m: copies of every stencil neighbour j
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
@@ -603,16 +614,15 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(Geom g, const int32_t *__
             const int64_t j = lin(g, jx, jy, jz);
             const int32_t cjm = (d < H) ? cw[int64_t(d) * g.n + m] : cw[int64_t(d - H) * g.n + j];
             if (cjm == 0) continue;
-            int ux[2], uy[2], uz[2];
-            const int nx = axis_cover(AX, jx, ux[0], ux[1]);
-            const int ny = axis_cover(AY, jy, uy[0], uy[1]);
-            const int nz = axis_cover(AZ, jz, uz[0], uz[1]);
+            const int32_t cjx = cv.x[jx], cjy = cv.y[jy], cjz = cv.z[jz];
+            const int nx = cov_cnt(cjx), ny = cov_cnt(cjy), nz = cov_cnt(cjz);
             for (int a = 0; a < nz; ++a)
                 for (int b = 0; b < ny; ++b)
                     for (int e = 0; e < nx; ++e) {
-                        const int kb = ux[e] + AX.nb * (uy[b] + AY.nb * uz[a]);
-                        const int bx0 = ux[e] * AX.s, by0 = uy[b] * AY.s, bz0 = uz[a] * AZ.s;
-                        const int bex = axis_extent(AX, ux[e]), bey = axis_extent(AY, uy[b]), bez = axis_extent(AZ, uz[a]);
+                        const int tx = cov_hi(cjx) - e, ty = cov_hi(cjy) - b, tz = cov_hi(cjz) - a;
+                        const int kb = tx + AX.nb * (ty + AY.nb * tz);
+                        const int bx0 = tx * AX.s, by0 = ty * AY.s, bz0 = tz * AZ.s;
+                        const int bex = axis_extent(AX, tx), bey = axis_extent(AY, ty), bez = axis_extent(AZ, tz);
                         const int64_t cc = int64_t(btab[BTAB_STRIDE * kb + 6]) + (jx - bx0) +
                                            int64_t(bex) * ((jy - by0) + int64_t(bey) * (jz - bz0));
                         if (!yhat[cc]) continue;
@@ -621,51 +631,64 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(Geom g, const int32_t *__
                         HC -= int64_t(qm - (m_in ? 1 : 0)) * int64_t(cjm);
                     }
         }
-        // floor((M S - 4 HC) / (M q)) = floor(floor((M S - 4 HC) / M) / q), q a power of two
-        int64_t Yn = floor_div(M * S - 4 * HC, M);
+        // floor((M S - 4 Hc) / (M q)) = floor(floor((M S - 4 Hc) / M) / q), q a power of two
+        int64_t Yn = floor_div_est(M * S - 4 * HC, M, invM);
         Yn >>= (qm == 1 ? 0 : qm == 2 ? 1 : qm == 4 ? 2 : 3);
         const int yk = yhat[c];
-        int64_t An = int64_t(Ain[c]) + int64_t(yk) * Y_ONE - Yn;
+        const int64_t An = int64_t(Ain[c]) + int64_t(yk) * Y_ONE - Yn;
         if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT || An >= STATE_LIMIT || An <= -STATE_LIMIT) ovf = 1;
         const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
         const int64_t Ac = An > STATE_LIMIT ? STATE_LIMIT : (An < -STATE_LIMIT ? -STATE_LIMIT : An);
         Aout[c] = int32_t(Ac);
-        // the block with the highest index along every axis writes the shared Y
-        if (tx[0] == kk % AX.nb && ty[0] == (kk / AX.nb) % AY.nb && tz[0] == kk / (AX.nb * AY.nb)) Y[m] = int32_t(Yc);
+        const int kx = kk % AX.nb, ky = (kk / AX.nb) % AY.nb, kz = kk / (AX.nb * AY.nb);
+        if (kx == txh && ky == tyh && kz == tzh) Y[m] = int32_t(Yc);
         const int64_t rr = int64_t(yk) * Y_ONE - Yc;
-        atomicAdd(&s_res[kk - k0], (unsigned long long)(rr * rr));
+        atomicAdd(&s_res[kk - kfirst], (unsigned long long)(rr * rr));
     }
     if (ovf) s_ovf = 1;
     __syncthreads();
-    if (tid < k1 - k0) {
-        const unsigned long long rv = s_res[tid];
-        resid[k0 + tid] = int64_t(rv);
-        atomicMax((unsigned long long *)&ctl->max_resid, rv);
+    {
+        const int klast = (blockIdx.x + 1 < gridDim.x) ? chunk_k0[blockIdx.x + 1] : g.K - 1;
+        const int span = min(klast - kfirst + 1, CONS_NT);
+        for (int b = tid; b < span; b += CONS_NT)
+            if (s_res[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&resid[kfirst + b]), s_res[b]);
     }
     if (tid == 0 && s_ovf) atomicOr(&ctl->ovf_pending, 1);
-    __threadfence();
+}
+
+// Loop control after the consensus of one iteration (a single workgroup): max_k r_k, stopping rule, overflow
+// and solver errors, mu <- mu * mu_fact, t <- t + 1.  A separate launch instead of a last-workgroup handshake
+// inside k_consensus: a device-scope fence per workgroup costs L2 write-backs on every XCD.
+__global__ __launch_bounds__(256) void k_finalize(Geom g, const int64_t *__restrict__ resid, Ctl *ctl) {
+    if (ctl_skip(ctl)) return;
+    __shared__ unsigned long long s_max[4];
+    const int tid = threadIdx.x;
+    unsigned long long mx = 0;
+    for (int k = tid; k < g.K; k += 256) {
+        const unsigned long long v = static_cast<unsigned long long>(resid[k]);
+        mx = v > mx ? v : mx;
+    }
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) {
+        const unsigned long long o = __shfl_xor(mx, sft);
+        mx = o > mx ? o : mx;
+    }
+    if ((tid & 63) == 0) s_max[tid >> 6] = mx;
     __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(&ctl->wg_counter, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (s_last && tid == 0) {
-        __threadfence();
-        const unsigned long long mr = atomicAdd((unsigned long long *)&ctl->max_resid, 0ull);
-        const int ov = atomicOr(&ctl->ovf_pending, 0);
-        const int se = atomicOr(&ctl->solver_err, 0);
-        ctl->last_max_resid = mr;
-        const int conv = mr <= ctl->eps2 ? 1 : 0;
+    if (tid == 0) {
+        for (int wv = 0; wv < 4; ++wv) mx = s_max[wv] > mx ? s_max[wv] : mx;
+        const int64_t M = ctl->M;
+        ctl->last_max_resid = mx;
+        const int conv = mx <= ctl->eps2 ? 1 : 0;
         ctl->converged = conv;
-        if (se) { ctl->status = -6; ctl->halted = 1; }
-        if (ov) { ctl->status = -5; ctl->halted = 1; }
+        if (ctl->solver_err) { ctl->status = -6; ctl->halted = 1; }
+        if (ctl->ovf_pending) { ctl->status = -5; ctl->halted = 1; }
         if (ctl->stop_on_converge && conv) ctl->halted = 1;
-        int64_t Mn = (M * ctl->mu_num) / ctl->mu_den;
+        const int64_t Mn = (M * ctl->mu_num) / ctl->mu_den;
         ctl->M = Mn > MU_MAX ? MU_MAX : Mn;
         ctl->t = ctl->t + 1;
-        ctl->max_resid = 0;
         ctl->ovf_pending = 0;
         ctl->solver_err = 0;
-        ctl->wg_counter = 0;
-        __threadfence();
     }
 }
 
@@ -673,47 +696,45 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(Geom g, const int32_t *__
 // Setup, labels and energy
 // ------------------------------------------------------------------------------------------------------------
 
+// c_ij = lambda_q8 w_ij 64 / (q_i q_j) for the half-stencil edges of every pixel, with validation: nonzero weight
+// on an off-grid edge, negative weight, and per-node sum_j |c_ij| >= 2^29 raise flags.  grid: (ceil(W/256), H*D).
 template <int CONN>
-__global__ void k_prep_weights(Geom g, const int32_t *__restrict__ w, int32_t *__restrict__ cw, int32_t lam,
-                               Ctl *ctl) {
+__global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict__ cov,
+                                              const int32_t *__restrict__ w, int32_t *__restrict__ cw, int32_t lam,
+                                              Ctl *ctl) {
     constexpr int H = Sten<CONN>::H;
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= g.n * H) return;
-    const int o = int(idx / g.n);
-    const int64_t i = idx - int64_t(o) * g.n;
-    const int gx = int(i % g.W), gy = int((i / g.W) % g.H), gz = int(i / (int64_t(g.W) * g.H));
-    const int3 v = half_off<CONN>(o);
-    const int32_t wv = w[idx];
+    const int gx = blockIdx.x * 256 + threadIdx.x;
+    if (gx >= g.W) return;
+    const int gy = int(blockIdx.y) % g.H, gz = int(blockIdx.y) / g.H;
+    const Cov cv = cov_of(g, cov);
+    const int64_t i = lin(g, gx, gy, gz);
+    const int qi = q_at(cv, gx, gy, gz);
     int flags = 0;
-    int32_t c = 0;
-    if (!in_grid(g, gx + v.x, gy + v.y, gz + v.z)) {
-        if (wv != 0) flags |= FLAG_OFFGRID;
-    } else if (wv != 0) {
-        if (wv < 0) flags |= FLAG_NEGATIVE;
-        const int qq = q_at(g, gx, gy, gz) * q_at(g, gx + v.x, gy + v.y, gz + v.z);
-        const int64_t cv = int64_t(lam) * int64_t(wv) * int64_t(64 / qq);
-        if (cv >= CAP_SUM_LIMIT || cv <= -CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
-        else c = int32_t(cv);
-    }
-    cw[idx] = c;
-    if (flags) atomicOr(&ctl->flags, flags);
-}
-
-template <int CONN>
-__global__ void k_check_capsum(Geom g, const int32_t *__restrict__ cw, Ctl *ctl) {
-    constexpr int H = Sten<CONN>::H;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= g.n) return;
-    const int gx = int(i % g.W), gy = int((i / g.W) % g.H), gz = int(i / (int64_t(g.W) * g.H));
-    int64_t s = 0;
+    int64_t sum = 0;
 #pragma unroll
     for (int d = 0; d < 2 * H; ++d) {
         const int3 v = full_dir<CONN>(d);
-        if (!in_grid(g, gx + v.x, gy + v.y, gz + v.z)) continue;
-        const int32_t c = d < H ? cw[int64_t(d) * g.n + i] : cw[int64_t(d - H) * g.n + lin(g, gx + v.x, gy + v.y, gz + v.z)];
-        s += c < 0 ? -int64_t(c) : int64_t(c);
+        const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
+        const bool ing = in_grid(g, jx, jy, jz);
+        // the edge's weight lives at the pixel holding its positive half-edge
+        int32_t wv;
+        if (d < H) wv = w[int64_t(d) * g.n + i];
+        else wv = ing ? w[int64_t(d - H) * g.n + lin(g, jx, jy, jz)] : 0;
+        int32_t c = 0;
+        if (!ing) {
+            if (wv != 0) flags |= FLAG_OFFGRID;
+        } else if (wv != 0) {
+            if (wv < 0) flags |= FLAG_NEGATIVE;
+            const int qq = qi * q_at(cv, jx, jy, jz);
+            const int64_t cvv = int64_t(lam) * int64_t(wv) * int64_t(64 / qq);
+            if (cvv >= CAP_SUM_LIMIT || cvv <= -CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
+            else c = int32_t(cvv);
+            sum += cvv < 0 ? -cvv : cvv;
+        }
+        if (d < H) cw[int64_t(d) * g.n + i] = c;
     }
-    if (s >= CAP_SUM_LIMIT) atomicOr(&ctl->flags, FLAG_TOOBIG);
+    if (sum >= CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
+    if (flags) atomicOr(&ctl->flags, flags);
 }
 
 __global__ void k_init_state(Geom g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid, Ctl *ctl,
@@ -753,51 +774,67 @@ __global__ void k_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge,
     }
 }
 
+// Labels [Y > 2^15].  grid: (ceil(W/256), H*D).
+__global__ __launch_bounds__(256) void k_labels(Geom g, const int32_t *__restrict__ Y, uint8_t *__restrict__ labels) {
+    const int gx = blockIdx.x * 256 + threadIdx.x;
+    if (gx >= g.W) return;
+    const int gy = int(blockIdx.y) % g.H, gz = int(blockIdx.y) / g.H;
+    const int64_t i = lin(g, gx, gy, gz);
+    labels[i] = uint8_t(Y[i] > Y_HALF);
+}
+
+constexpr int ENERGY_WGS = 256;
+
+// Per-workgroup partial sums of E_q = 256 u.l + lambda_q8 sum_edges w |l_i - l_j| (grid-stride over pixels,
+// ENERGY_WGS workgroups, no atomics); k_energy_sum adds the partials into ctl->energy.
 template <int CONN>
-__global__ __launch_bounds__(256) void k_labels_energy(Geom g, const int32_t *__restrict__ u,
-                                                       const int32_t *__restrict__ w, int32_t lam,
-                                                       const int32_t *__restrict__ Y, uint8_t *__restrict__ labels,
-                                                       Ctl *ctl) {
+__global__ __launch_bounds__(256) void k_energy(Geom g, const int32_t *__restrict__ u, const int32_t *__restrict__ w,
+                                                int32_t lam, const int32_t *__restrict__ Y,
+                                                int64_t *__restrict__ part) {
     constexpr int H = Sten<CONN>::H;
-    __shared__ long long s_sum[8];
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    __shared__ long long s_sum[4];
     long long e = 0;
-    if (i < g.n) {
-        const int li = Y[i] > Y_HALF;
-        if (labels) labels[i] = uint8_t(li);
-        e = 256ll * u[i] * li;
-        const int gx = int(i % g.W), gy = int((i / g.W) % g.H), gz = int(i / (int64_t(g.W) * g.H));
+    const int64_t rows = int64_t(g.H) * g.D;
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int gy = int(row % g.H), gz = int(row / g.H);
+        for (int gx = threadIdx.x; gx < g.W; gx += 256) {
+            const int64_t i = lin(g, gx, gy, gz);
+            const int li = Y[i] > Y_HALF;
+            if (li) e += 256ll * u[i];
 #pragma unroll
-        for (int o = 0; o < H; ++o) {
-            const int3 v = half_off<CONN>(o);
-            if (!in_grid(g, gx + v.x, gy + v.y, gz + v.z)) continue;
-            const int lj = Y[lin(g, gx + v.x, gy + v.y, gz + v.z)] > Y_HALF;
-            if (li != lj) e += (long long)lam * w[int64_t(o) * g.n + i];
+            for (int o = 0; o < H; ++o) {
+                const int3 v = half_off<CONN>(o);
+                if (!in_grid(g, gx + v.x, gy + v.y, gz + v.z)) continue;
+                const int lj = Y[lin(g, gx + v.x, gy + v.y, gz + v.z)] > Y_HALF;
+                if (li != lj) e += (long long)lam * w[int64_t(o) * g.n + i];
+            }
         }
     }
-    for (int s = 32; s >= 1; s >>= 1) e += __shfl_xor(e, s);
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) e += __shfl_xor(e, sft);
     if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = e;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        long long t = 0;
-        for (int wv = 0; wv < int(blockDim.x >> 6); ++wv) t += s_sum[wv];
-        atomicAdd((unsigned long long *)&ctl->energy, (unsigned long long)t);
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+}
+
+__global__ __launch_bounds__(256) void k_energy_sum(const int64_t *__restrict__ part, int n, Ctl *ctl) {
+    __shared__ long long s_sum[4];
+    long long e = 0;
+    for (int i = threadIdx.x; i < n; i += 256) e += part[i];
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) e += __shfl_xor(e, sft);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) ctl->energy = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
 }
 
 inline unsigned blocks_for(int64_t n, int nt) { return unsigned((n + nt - 1) / nt); }
 
-template <int CONN>
-hipError_t solve_conn(const Geom &g, int solver, const int32_t *u, const int32_t *cw, const int32_t *Y,
-                      const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat, int32_t *stats,
-                      Ctl *ctl, hipStream_t s) {
+template <int CONN, int NT>
+hipError_t launch_maxflow(const Geom &g, const Tables &tb, const int32_t *u, const int32_t *cw, const int32_t *Y,
+                          const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat, int32_t *stats,
+                          int64_t *resid, Ctl *ctl, hipStream_t s) {
     constexpr int H = Sten<CONN>::H;
-    if (solver == 2) {
-        hipLaunchKernelGGL(k_block_exhaustive<CONN>, dim3(blocks_for(g.K, EX_WAVES)), dim3(256), 0, s, g, u, cw, Y,
-                           A0, A1, btab, yhat, stats, ctl);
-        return hipGetLastError();
-    }
-    constexpr int NT = 256;
     const size_t lds = maxflow_lds_bytes(g.max_np, H);
     static bool attr_set = false;
     if (!attr_set) {
@@ -806,29 +843,34 @@ hipError_t solve_conn(const Geom &g, int solver, const int32_t *u, const int32_t
         attr_set = true;
     }
     const int32_t round_limit = 65536 + 64 * g.max_np;
-    hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(g.K), dim3(NT), lds, s, g, u, cw, Y, A0, A1, btab, yhat,
-                       stats, ctl, g.max_np, round_limit, 8);
+    hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(g.K), dim3(NT), lds, s, g, tb.cov, u, cw, Y, A0, A1, btab,
+                       yhat, stats, resid, ctl, g.max_np, round_limit, 8);
     return hipGetLastError();
+}
+
+template <int CONN>
+hipError_t solve_conn(const Geom &g, const Tables &tb, int solver, const int32_t *u, const int32_t *cw,
+                      const int32_t *Y, const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat,
+                      int32_t *stats, int64_t *resid, Ctl *ctl, hipStream_t s) {
+    if (solver == 2) {
+        hipLaunchKernelGGL(k_block_exhaustive<CONN>, dim3(blocks_for(g.K, EX_WAVES)), dim3(256), 0, s, g, tb.cov, u,
+                           cw, Y, A0, A1, btab, yhat, stats, resid, ctl);
+        return hipGetLastError();
+    }
+    if (g.max_np > 512)
+        return launch_maxflow<CONN, 1024>(g, tb, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
+    return launch_maxflow<CONN, 256>(g, tb, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
 }
 
 }  // namespace
 
-hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
-                               hipStream_t s) {
-    const int64_t nh = g.n * g.hs;
+hipError_t launch_prep_weights(const Geom &g, const Tables &tb, const int32_t *w, int32_t *cw, int32_t lam_q8,
+                               Ctl *ctl, hipStream_t s) {
+    const dim3 grid(blocks_for(g.W, 256), unsigned(g.H) * unsigned(g.D));
     switch (g.conn) {
-        case 4:
-            hipLaunchKernelGGL(k_prep_weights<4>, dim3(blocks_for(nh, 256)), dim3(256), 0, s, g, w, cw, lam_q8, ctl);
-            hipLaunchKernelGGL(k_check_capsum<4>, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g, cw, ctl);
-            break;
-        case 8:
-            hipLaunchKernelGGL(k_prep_weights<8>, dim3(blocks_for(nh, 256)), dim3(256), 0, s, g, w, cw, lam_q8, ctl);
-            hipLaunchKernelGGL(k_check_capsum<8>, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g, cw, ctl);
-            break;
-        default:
-            hipLaunchKernelGGL(k_prep_weights<6>, dim3(blocks_for(nh, 256)), dim3(256), 0, s, g, w, cw, lam_q8, ctl);
-            hipLaunchKernelGGL(k_check_capsum<6>, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g, cw, ctl);
-            break;
+        case 4: hipLaunchKernelGGL(k_prep<4>, grid, dim3(256), 0, s, g, tb.cov, w, cw, lam_q8, ctl); break;
+        case 8: hipLaunchKernelGGL(k_prep<8>, grid, dim3(256), 0, s, g, tb.cov, w, cw, lam_q8, ctl); break;
+        default: hipLaunchKernelGGL(k_prep<6>, grid, dim3(256), 0, s, g, tb.cov, w, cw, lam_q8, ctl); break;
     }
     return hipGetLastError();
 }
@@ -849,44 +891,53 @@ hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge,
     return hipGetLastError();
 }
 
-hipError_t launch_block_solve(const Geom &g, int solver, const int32_t *u, const int32_t *cw, const int32_t *Y,
-                              const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat,
-                              int32_t *stats, Ctl *ctl, hipStream_t s) {
+hipError_t launch_block_solve(const Geom &g, const Tables &tb, int solver, const int32_t *u, const int32_t *cw,
+                              const int32_t *Y, const int32_t *A0, const int32_t *A1, const int32_t *btab,
+                              uint8_t *yhat, int32_t *stats, int64_t *resid, Ctl *ctl, hipStream_t s) {
     switch (g.conn) {
-        case 4: return solve_conn<4>(g, solver, u, cw, Y, A0, A1, btab, yhat, stats, ctl, s);
-        case 8: return solve_conn<8>(g, solver, u, cw, Y, A0, A1, btab, yhat, stats, ctl, s);
-        default: return solve_conn<6>(g, solver, u, cw, Y, A0, A1, btab, yhat, stats, ctl, s);
+        case 4: return solve_conn<4>(g, tb, solver, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
+        case 8: return solve_conn<8>(g, tb, solver, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
+        default: return solve_conn<6>(g, tb, solver, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
     }
 }
 
-hipError_t launch_consensus(const Geom &g, const int32_t *cw, const uint8_t *yhat, int32_t *A0, int32_t *A1,
-                            int32_t *Y, const int32_t *btab, int64_t *resid, Ctl *ctl, hipStream_t s) {
-    int bpw = CONS_NT / (g.max_np > 0 ? g.max_np : 1);
-    if (bpw < 1) bpw = 1;
-    if (bpw > CONS_MAX_BPW) bpw = CONS_MAX_BPW;
-    const unsigned grid = unsigned((g.K + bpw - 1) / bpw);
+hipError_t launch_consensus(const Geom &g, const Tables &tb, const int32_t *cw, const uint8_t *yhat, int32_t *A0,
+                            int32_t *A1, int32_t *Y, const int32_t *btab, int64_t *resid, Ctl *ctl, hipStream_t s) {
+    const unsigned grid = unsigned(tb.n_chunks);
     switch (g.conn) {
         case 4:
-            hipLaunchKernelGGL(k_consensus<4>, dim3(grid), dim3(CONS_NT), 0, s, g, cw, yhat, A0, A1, Y, btab, resid, ctl, bpw);
+            hipLaunchKernelGGL(k_consensus<4>, dim3(grid), dim3(CONS_NT), 0, s, g, tb.cov, cw, yhat, A0, A1, Y, btab,
+                               tb.chunk_k0, resid, ctl);
             break;
         case 8:
-            hipLaunchKernelGGL(k_consensus<8>, dim3(grid), dim3(CONS_NT), 0, s, g, cw, yhat, A0, A1, Y, btab, resid, ctl, bpw);
+            hipLaunchKernelGGL(k_consensus<8>, dim3(grid), dim3(CONS_NT), 0, s, g, tb.cov, cw, yhat, A0, A1, Y, btab,
+                               tb.chunk_k0, resid, ctl);
             break;
         default:
-            hipLaunchKernelGGL(k_consensus<6>, dim3(grid), dim3(CONS_NT), 0, s, g, cw, yhat, A0, A1, Y, btab, resid, ctl, bpw);
+            hipLaunchKernelGGL(k_consensus<6>, dim3(grid), dim3(CONS_NT), 0, s, g, tb.cov, cw, yhat, A0, A1, Y, btab,
+                               tb.chunk_k0, resid, ctl);
             break;
     }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, g, resid, ctl);
     return hipGetLastError();
 }
 
-hipError_t launch_labels_energy(const Geom &g, const int32_t *u, const int32_t *w, int32_t lam_q8,
-                                const int32_t *Y, uint8_t *labels, Ctl *ctl, hipStream_t s) {
-    const unsigned grid = blocks_for(g.n, 256);
+hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s) {
+    const dim3 grid(blocks_for(g.W, 256), unsigned(g.H) * unsigned(g.D));
+    hipLaunchKernelGGL(k_labels, grid, dim3(256), 0, s, g, Y, labels);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *w, int32_t lam_q8, const int32_t *Y,
+                         int64_t *part, Ctl *ctl, hipStream_t s) {
+    const int64_t rows = int64_t(g.H) * g.D;
+    const unsigned wgs = unsigned(rows < ENERGY_WGS ? rows : ENERGY_WGS);
     switch (g.conn) {
-        case 4: hipLaunchKernelGGL(k_labels_energy<4>, dim3(grid), dim3(256), 0, s, g, u, w, lam_q8, Y, labels, ctl); break;
-        case 8: hipLaunchKernelGGL(k_labels_energy<8>, dim3(grid), dim3(256), 0, s, g, u, w, lam_q8, Y, labels, ctl); break;
-        default: hipLaunchKernelGGL(k_labels_energy<6>, dim3(grid), dim3(256), 0, s, g, u, w, lam_q8, Y, labels, ctl); break;
+        case 4: hipLaunchKernelGGL(k_energy<4>, dim3(wgs), dim3(256), 0, s, g, u, w, lam_q8, Y, part); break;
+        case 8: hipLaunchKernelGGL(k_energy<8>, dim3(wgs), dim3(256), 0, s, g, u, w, lam_q8, Y, part); break;
+        default: hipLaunchKernelGGL(k_energy<6>, dim3(wgs), dim3(256), 0, s, g, u, w, lam_q8, Y, part); break;
     }
+    hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s, part, int(wgs), ctl);
     return hipGetLastError();
 }
 

@@ -59,10 +59,12 @@ def _params(native, dims=(512, 512, 1), conn=8, block=(32, 32, 1), overlap=(2, 2
     return p
 
 
-def _workspace_model(n, h, K, tot):
+def _workspace_model(dims, h, K, tot):
     a = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    return (a(128) + a(K * 32) + a(4 * n) + 2 * a(4 * h * n) + a(4 * n) + 2 * a(4 * tot) + a(tot) + a(8 * K)
-            + a(16 * K) + a(n))
+    n = dims[0] * dims[1] * dims[2]
+    chunks = (tot + 255) // 256
+    return (a(128) + a(K * 32) + a(4 * sum(dims)) + a(4 * chunks) + a(4 * n) + 2 * a(4 * h * n) + a(4 * n)
+            + 2 * a(4 * tot) + a(tot) + a(8 * K) + a(16 * K) + a(n) + a(8 * 256))
 
 
 @pytest.mark.parametrize("dims,conn,block,overlap,ndim", [
@@ -78,7 +80,7 @@ def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, n
     n = dims[0] * dims[1] * dims[2]
     h = {4: 2, 8: 4, 6: 3}[conn]
     tot = sum(len(b.idx) for b in blocks)
-    assert native.dope_workspace_bytes(ctypes.byref(p)) == _workspace_model(n, h, len(blocks), tot)
+    assert native.dope_workspace_bytes(ctypes.byref(p)) == _workspace_model(dims, h, len(blocks), tot)
 
 
 @pytest.mark.parametrize("kw,msg", [
