@@ -150,6 +150,31 @@ dope_status dope_profile_enable(dope_ctx *ctx, int32_t on);
 dope_status dope_profile_read(dope_ctx *ctx, double *solve_ms, int32_t *solve_launches, double *consensus_ms,
                               int32_t *consensus_launches);
 
+/* ---- Batched iterations (many images, one launch per phase) ------------------------------------------------
+ * A batch groups contexts so that every ADMM iteration runs as three launches for all of them together: a
+ * persistent block-solve launch whose workgroups take (image, block) items from a device work queue (blocks of
+ * images of uneven sizes and uneven max-flow cost share the GPU), one consensus / multiplier launch over all
+ * their block pixels, and one loop-control launch.  Each image keeps its own state, stopping rule, iteration cap
+ * and error status, and its results are bit-identical to running it alone (Algorithm 1 applied per image).
+ * All contexts must share connectivity and resolved solver and have their energy set; the batch does not own
+ * them and they must outlive it.  Work is ordered on the first context's stream. */
+typedef struct dope_batch dope_batch;
+
+dope_status dope_batch_create(dope_ctx *const *ctxs, int32_t n, dope_batch **out);
+/* exactly n_iter iterations for every image whose loop has not stopped on an error */
+dope_status dope_batch_iterate(dope_batch *b, int32_t n_iter);
+/* until every image meets its stopping rule or reaches its max_iter (an image that fails stops alone; the call
+ * then returns that image's error after the others finish) */
+dope_status dope_batch_solve(dope_batch *b);
+/* on != 0: capture one iteration in a hipGraph and replay it (fewer launches per iteration) */
+dope_status dope_batch_set_graph(dope_batch *b, int32_t on);
+/* workgroups of the persistent block-solve launch; 0 = one per block item */
+dope_status dope_batch_set_workers(dope_batch *b, int32_t n);
+/* per-image loop information, n entries in context order */
+dope_status dope_batch_info(dope_batch *b, dope_info *infos);
+const char *dope_batch_last_error(const dope_batch *b);
+void dope_batch_destroy(dope_batch *b);
+
 /* Context-local message of the last error; never NULL.  With ctx == NULL: the calling thread's last
  * dope_create validation message (empty when it succeeded). */
 const char *dope_last_error(const dope_ctx *ctx);

@@ -64,6 +64,14 @@ SIGNATURES = {
     "dope_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "dope_profile_read": (ctypes.c_int, [_P, _DP, _I32P, _DP, _I32P]),
     "dope_last_error": (ctypes.c_char_p, [_P]),
+    "dope_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "dope_batch_iterate": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "dope_batch_solve": (ctypes.c_int, [_P]),
+    "dope_batch_set_graph": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "dope_batch_set_workers": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "dope_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(dope_info)]),
+    "dope_batch_last_error": (ctypes.c_char_p, [_P]),
+    "dope_batch_destroy": (None, [_P]),
     "dope_destroy": (None, [_P]),
 }
 
@@ -125,3 +133,11 @@ dope_profile_enable = _fn("dope_profile_enable")
 dope_profile_read = _fn("dope_profile_read")
 dope_last_error = _fn("dope_last_error")
 dope_destroy = _fn("dope_destroy")
+dope_batch_create = _fn("dope_batch_create")
+dope_batch_iterate = _fn("dope_batch_iterate")
+dope_batch_solve = _fn("dope_batch_solve")
+dope_batch_set_graph = _fn("dope_batch_set_graph")
+dope_batch_set_workers = _fn("dope_batch_set_workers")
+dope_batch_info = _fn("dope_batch_info")
+dope_batch_last_error = _fn("dope_batch_last_error")
+dope_batch_destroy = _fn("dope_batch_destroy")

@@ -25,12 +25,16 @@ struct dope_ctx {
     bool own_ws = false;
     Ctl *ctl = nullptr;
     int32_t *btab = nullptr, *u = nullptr, *w = nullptr, *cw = nullptr, *Y = nullptr, *A0 = nullptr, *A1 = nullptr;
-    int32_t *stats = nullptr, *cov = nullptr, *chunk_k0 = nullptr;
+    int32_t *stats = nullptr, *chunk_k0 = nullptr;
     uint8_t *yhat = nullptr, *labels = nullptr;
     int64_t *resid = nullptr, *epart = nullptr;
     Ctl *hctl = nullptr;       // pinned host mirror of the control block
-    std::vector<int32_t> hbtab, hcov, hchunk;
-    dope::Tables tables{};
+    std::vector<int32_t> hbtab, hchunk;
+    dope::Img *dimg = nullptr;          // this context's descriptor (device)
+    dope::Item *blk_items = nullptr, *chk_items = nullptr;
+    dope::Queue *queue = nullptr;
+    dope::Group grp{};                  // one-image launch group
+    bool dirty = false;                 // device state advanced by a batch: refresh the host mirror
     int32_t lam_q8 = 0;
     bool energy_set = false;
     bool profiling = false;
@@ -42,7 +46,7 @@ struct dope_ctx {
 namespace {
 
 struct Layout {
-    size_t ctl, btab, cov, chunk, u, w, cw, Y, A0, A1, yhat, resid, stats, labels, epart, total;
+    size_t ctl, img, bitems, citems, queue, btab, chunk, u, w, cw, Y, A0, A1, yhat, resid, stats, labels, epart, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -52,8 +56,11 @@ Layout layout_for(const Geom &g) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
     L.ctl = take(sizeof(Ctl));
+    L.img = take(sizeof(dope::Img));
+    L.bitems = take(size_t(g.K) * sizeof(dope::Item));
+    L.citems = take(size_t((g.tot + dope::CHUNK - 1) / dope::CHUNK) * sizeof(dope::Item));
+    L.queue = take(sizeof(dope::Queue));
     L.btab = take(size_t(g.K) * dope::BTAB_STRIDE * 4);
-    L.cov = take(size_t(g.W + g.H + g.D) * 4);
     L.chunk = take(size_t((g.tot + dope::CHUNK - 1) / dope::CHUNK) * 4);
     L.u = take(size_t(g.n) * 4);
     L.w = take(size_t(g.n) * g.hs * 4);
@@ -134,6 +141,17 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
                 if (tot >= (int64_t(1) << 31)) return "sum of block sizes must be < 2^31";
             }
     g.tot = tot;
+    for (int a = 0; a < 3; ++a)
+        g.span[a] = int64_t(g.ax[a].nb - 1) * g.ax[a].B + dope::axis_ext(g.ax[a], g.ax[a].nb - 1);
+    if (btab) {
+        // the kernels locate blocks by the closed form; it must agree with the enumeration above
+        int64_t kk = 0;
+        for (int tz = 0; tz < g.ax[2].nb; ++tz)
+            for (int ty = 0; ty < g.ax[1].nb; ++ty)
+                for (int tx = 0; tx < g.ax[0].nb; ++tx, ++kk)
+                    if (dope::block_offset(g, tx, ty, tz) != (*btab)[size_t(kk) * dope::BTAB_STRIDE + 6])
+                        return "internal: block offset formula disagrees with the partition";
+    }
     if (p->mu0 < 1 || p->mu0 > dope::MU_MAX) return "mu0 must be in [1, 2^24 - 1]";
     if (p->mu_fact_num < 0 || p->mu_fact_den < 0) return "mu_fact must be positive";
     if ((p->mu_fact_num == 0) != (p->mu_fact_den == 0)) return "mu_fact numerator and denominator must both be set";
@@ -158,19 +176,8 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
 
 thread_local std::string g_create_error;
 
-// cov[x] = t_hi | (1 << 30 if x also lies in interval t_hi - 1), per axis, back to back (W, H, D entries);
 // chunk[c] = block containing block-major copy c * CHUNK.
-void build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<int32_t> &cov,
-                  std::vector<int32_t> &chunk) {
-    cov.clear();
-    for (int a = 0; a < 3; ++a) {
-        const dope::Axis &ax = g.ax[a];
-        for (int x = 0; x < ax.N; ++x) {
-            int th = std::min(x / ax.s, ax.nb - 1);
-            const bool two = th >= 1 && x < (th - 1) * ax.s + ax.B;
-            cov.push_back(th | (two ? (1 << 30) : 0));
-        }
-    }
+void build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<int32_t> &chunk) {
     const int64_t nch = (g.tot + dope::CHUNK - 1) / dope::CHUNK;
     chunk.assign(size_t(nch), 0);
     int64_t k = 0;
@@ -201,11 +208,11 @@ void assign_pointers(dope_ctx *c) {
     char *b = c->ws;
     c->ctl = reinterpret_cast<Ctl *>(b + L.ctl);
     c->btab = reinterpret_cast<int32_t *>(b + L.btab);
-    c->cov = reinterpret_cast<int32_t *>(b + L.cov);
     c->chunk_k0 = reinterpret_cast<int32_t *>(b + L.chunk);
-    c->tables.cov = c->cov;
-    c->tables.chunk_k0 = c->chunk_k0;
-    c->tables.n_chunks = int32_t(c->hchunk.size());
+    c->dimg = reinterpret_cast<dope::Img *>(b + L.img);
+    c->blk_items = reinterpret_cast<dope::Item *>(b + L.bitems);
+    c->chk_items = reinterpret_cast<dope::Item *>(b + L.citems);
+    c->queue = reinterpret_cast<dope::Queue *>(b + L.queue);
     c->u = reinterpret_cast<int32_t *>(b + L.u);
     c->w = reinterpret_cast<int32_t *>(b + L.w);
     c->cw = reinterpret_cast<int32_t *>(b + L.cw);
@@ -219,13 +226,47 @@ void assign_pointers(dope_ctx *c) {
     c->epart = reinterpret_cast<int64_t *>(b + L.epart);
 }
 
+dope::Img host_img(const dope_ctx *c) {
+    dope::Img im{};
+    im.g = c->g;
+    im.u = c->u;
+    im.w = c->w;
+    im.cw = c->cw;
+    im.btab = c->btab;
+    im.chunk_k0 = c->chunk_k0;
+    im.Y = c->Y;
+    im.A0 = c->A0;
+    im.A1 = c->A1;
+    im.stats = c->stats;
+    im.yhat = c->yhat;
+    im.resid = c->resid;
+    im.ctl = c->ctl;
+    im.summary = nullptr;
+    im.n_chunks = int32_t(c->hchunk.size());
+    return im;
+}
+
 dope_status upload_tables(dope_ctx *c) {
     HIP_TRY(c, hipMemcpyAsync(c->btab, c->hbtab.data(), c->hbtab.size() * 4, hipMemcpyHostToDevice, c->stream),
             "block table upload");
-    HIP_TRY(c, hipMemcpyAsync(c->cov, c->hcov.data(), c->hcov.size() * 4, hipMemcpyHostToDevice, c->stream),
-            "cover table upload");
     HIP_TRY(c, hipMemcpyAsync(c->chunk_k0, c->hchunk.data(), c->hchunk.size() * 4, hipMemcpyHostToDevice, c->stream),
             "chunk table upload");
+    // one-image launch group: descriptor, work items, zeroed queue (staged in host memory that stays alive
+    // until the synchronisation at the end of this function)
+    const dope::Img im = host_img(c);
+    std::vector<dope::Item> bi(size_t(c->g.K)), ci(c->hchunk.size());
+    for (size_t k = 0; k < bi.size(); ++k) bi[k] = dope::Item{0, int32_t(k)};
+    for (size_t k = 0; k < ci.size(); ++k) ci[k] = dope::Item{0, int32_t(k)};
+    const dope::Queue q{};
+    HIP_TRY(c, hipMemcpyAsync(c->dimg, &im, sizeof(im), hipMemcpyHostToDevice, c->stream), "descriptor upload");
+    HIP_TRY(c, hipMemcpyAsync(c->blk_items, bi.data(), bi.size() * sizeof(dope::Item), hipMemcpyHostToDevice,
+                              c->stream), "item upload");
+    HIP_TRY(c, hipMemcpyAsync(c->chk_items, ci.data(), ci.size() * sizeof(dope::Item), hipMemcpyHostToDevice,
+                              c->stream), "item upload");
+    HIP_TRY(c, hipMemcpyAsync(c->queue, &q, sizeof(q), hipMemcpyHostToDevice, c->stream), "queue upload");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    c->grp = dope::Group{c->dimg, 1, c->blk_items, c->g.K, c->chk_items, int32_t(ci.size()), c->queue,
+                         c->g.conn, 0, c->g.max_np, 0};
     return DOPE_OK;
 }
 
@@ -268,27 +309,24 @@ hipEvent_t next_event(std::vector<hipEvent_t> &pool, size_t idx) {
 }
 
 dope_status enqueue_iterations(dope_ctx *c, int count) {
+    c->grp.solver = c->solver;
     for (int it = 0; it < count; ++it) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->profiling) {
-            e0 = next_event(c->ev_solve, 2 * c->n_solve);
-            e1 = next_event(c->ev_solve, 2 * c->n_solve + 1);
-            if (e0 && e1) (void)hipEventRecord(e0, c->stream);
+        if (!c->profiling) {
+            HIP_TRY(c, dope::launch_iteration(c->grp, c->stream), "iteration launch");
+            continue;
         }
-        HIP_TRY(c, dope::launch_block_solve(c->g, c->tables, c->solver, c->u, c->cw, c->Y, c->A0, c->A1, c->btab,
-                                            c->yhat, c->stats, c->resid, c->ctl, c->stream),
-                "block solve launch");
-        if (c->profiling && e0 && e1) {
+        hipEvent_t e0 = next_event(c->ev_solve, 2 * c->n_solve), e1 = next_event(c->ev_solve, 2 * c->n_solve + 1);
+        if (e0 && e1) (void)hipEventRecord(e0, c->stream);
+        HIP_TRY(c, dope::launch_solve_phase(c->grp, c->stream), "block solve launch");
+        if (e0 && e1) {
             (void)hipEventRecord(e1, c->stream);
             ++c->n_solve;
-            e0 = next_event(c->ev_cons, 2 * c->n_cons);
-            e1 = next_event(c->ev_cons, 2 * c->n_cons + 1);
-            if (e0 && e1) (void)hipEventRecord(e0, c->stream);
         }
-        HIP_TRY(c, dope::launch_consensus(c->g, c->tables, c->cw, c->yhat, c->A0, c->A1, c->Y, c->btab, c->resid,
-                                          c->ctl, c->stream),
-                "consensus launch");
-        if (c->profiling && e0 && e1) {
+        e0 = next_event(c->ev_cons, 2 * c->n_cons);
+        e1 = next_event(c->ev_cons, 2 * c->n_cons + 1);
+        if (e0 && e1) (void)hipEventRecord(e0, c->stream);
+        HIP_TRY(c, dope::launch_consensus_phase(c->grp, c->stream), "consensus launch");
+        if (e0 && e1) {
             (void)hipEventRecord(e1, c->stream);
             ++c->n_cons;
         }
@@ -299,6 +337,10 @@ dope_status enqueue_iterations(dope_ctx *c, int count) {
 dope_status check_ready(dope_ctx *c) {
     if (!c) return DOPE_EINVAL;
     if (!c->energy_set) return fail(c, DOPE_ESTATE, "dope_set_energy has not been called");
+    if (c->dirty) {
+        c->dirty = false;
+        return sync_ctl(c);
+    }
     return DOPE_OK;
 }
 
@@ -321,11 +363,12 @@ dope_status dope_create(const dope_params *p, dope_ctx **out) {
     c->p = q;
     c->g = g;
     c->hbtab.swap(bt);
-    build_tables(c->g, c->hbtab, c->hcov, c->hchunk);
+    build_tables(c->g, c->hbtab, c->hchunk);
     if (q.stream) {
         c->stream = static_cast<hipStream_t>(q.stream);
     } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        // a blocking stream: ordered with work that PyTorch issues on the default stream
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
             delete c;
             return DOPE_EDEVICE;
         }
@@ -378,7 +421,7 @@ dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int
     HIP_TRY(c, dope::launch_init_state(g, c->Y, c->A0, c->A1, c->yhat, c->resid, c->ctl, c->p.mu0, c->p.mu_fact_num,
                                        c->p.mu_fact_den, eps2, c->stream),
             "state init launch");
-    HIP_TRY(c, dope::launch_prep_weights(g, c->tables, c->w, c->cw, lambda_q8, c->ctl, c->stream), "weight prep launch");
+    HIP_TRY(c, dope::launch_prep_weights(g, c->w, c->cw, lambda_q8, c->ctl, c->stream), "weight prep launch");
     st = sync_ctl(c);
     if (st != DOPE_OK) return st;
     c->energy_set = false;
@@ -594,6 +637,258 @@ void dope_destroy(dope_ctx *c) {
     if (c->hctl) (void)hipHostFree(c->hctl);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------------------
+// Batches
+// ------------------------------------------------------------------------------------------------------------
+
+struct dope_batch {
+    std::vector<dope_ctx *> ctxs;
+    hipStream_t stream = nullptr;
+    char *dbuf = nullptr;
+    dope::Img *imgs = nullptr;
+    int32_t *dsum = nullptr, *dparams = nullptr;
+    dope::Group grp{};
+    int32_t *hsum = nullptr;       // pinned: {t, halted, converged, status} per image
+    int32_t *hparams = nullptr;    // pinned: {t_limit, stop} per image
+    bool use_graph = false, graph_ready = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+dope_status bfail(dope_batch *b, dope_status s, const std::string &msg) {
+    if (b) b->err = msg;
+    return s;
+}
+
+#define BHIP_TRY(b, expr, what)                                                                         \
+    do {                                                                                                \
+        hipError_t _e = (expr);                                                                         \
+        if (_e != hipSuccess) return bfail(b, DOPE_EDEVICE, std::string(what) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+dope_status batch_run_iteration(dope_batch *b) {
+    if (b->use_graph) {
+        if (!b->graph_ready) {
+            BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed), "graph capture begin");
+            const hipError_t le = dope::launch_iteration(b->grp, b->stream);
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+            if (le != hipSuccess || ce != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return bfail(b, DOPE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ce));
+            }
+            b->graph = g;
+            BHIP_TRY(b, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+            b->graph_ready = true;
+        }
+        BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream), "graph launch");
+        return DOPE_OK;
+    }
+    BHIP_TRY(b, dope::launch_iteration(b->grp, b->stream), "iteration launch");
+    return DOPE_OK;
+}
+
+dope_status batch_sync(dope_batch *b) {
+    const size_t n = b->ctxs.size();
+    BHIP_TRY(b, hipMemcpyAsync(b->hsum, b->dsum, n * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream),
+             "summary readback");
+    BHIP_TRY(b, hipStreamSynchronize(b->stream), "stream synchronize");
+    for (dope_ctx *c : b->ctxs) c->dirty = true;
+    return DOPE_OK;
+}
+
+dope_status batch_setup(dope_batch *b) {
+    const size_t n = b->ctxs.size();
+    BHIP_TRY(b, hipMemcpyAsync(b->dparams, b->hparams, n * 2 * sizeof(int32_t), hipMemcpyHostToDevice, b->stream),
+             "parameter upload");
+    BHIP_TRY(b, dope::launch_batch_setup(b->imgs, int32_t(n), b->dparams, b->stream), "batch setup launch");
+    return DOPE_OK;
+}
+
+dope_status batch_status(dope_batch *b) {
+    for (size_t i = 0; i < b->ctxs.size(); ++i)
+        if (b->hsum[4 * i + 3] != 0)
+            return bfail(b, dope_status(b->hsum[4 * i + 3]), "image " + std::to_string(i) + " stopped with an error");
+    return DOPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dope_status dope_batch_create(dope_ctx *const *ctxs, int32_t n, dope_batch **out) {
+    if (!ctxs || n <= 0 || !out) return DOPE_EINVAL;
+    *out = nullptr;
+    int conn = 0, solver = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        dope_ctx *c = ctxs[i];
+        if (!c) return DOPE_EINVAL;
+        dope_status st = check_ready(c);
+        if (st != DOPE_OK) return st;
+        if (i == 0) { conn = c->g.conn; solver = c->solver; }
+        if (c->g.conn != conn || c->solver != solver) return fail(c, DOPE_EINVAL, "batch members must share connectivity and solver");
+    }
+    dope_batch *b = new (std::nothrow) dope_batch();
+    if (!b) return DOPE_ENOMEM;
+    b->ctxs.assign(ctxs, ctxs + n);
+    b->stream = ctxs[0]->stream;
+    // device buffer: descriptors, block items, chunk items, queue, summaries, parameters
+    int64_t nblk = 0, nchk = 0;
+    int32_t npmax = 0;
+    for (dope_ctx *c : b->ctxs) {
+        nblk += c->g.K;
+        nchk += int64_t(c->hchunk.size());
+        npmax = std::max(npmax, c->g.max_np);
+    }
+    if (nblk >= (int64_t(1) << 31) || nchk >= (int64_t(1) << 31)) { delete b; return DOPE_EINVAL; }
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+    const size_t o_img = take(size_t(n) * sizeof(dope::Img)), o_bi = take(size_t(nblk) * sizeof(dope::Item)),
+                 o_ci = take(size_t(nchk) * sizeof(dope::Item)), o_q = take(sizeof(dope::Queue)),
+                 o_sum = take(size_t(n) * 16), o_par = take(size_t(n) * 8);
+    void *ptr = nullptr;
+    if (hipMalloc(&ptr, o) != hipSuccess) { (void)hipGetLastError(); delete b; return DOPE_ENOMEM; }
+    b->dbuf = static_cast<char *>(ptr);
+    void *hs = nullptr, *hp = nullptr;
+    if (hipHostMalloc(&hs, size_t(n) * 16, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&hp, size_t(n) * 8, hipHostMallocDefault) != hipSuccess) {
+        if (hs) (void)hipHostFree(hs);
+        (void)hipFree(ptr);
+        delete b;
+        return DOPE_ENOMEM;
+    }
+    b->hsum = static_cast<int32_t *>(hs);
+    b->hparams = static_cast<int32_t *>(hp);
+    b->imgs = reinterpret_cast<dope::Img *>(b->dbuf + o_img);
+    auto *bi = reinterpret_cast<dope::Item *>(b->dbuf + o_bi);
+    auto *ci = reinterpret_cast<dope::Item *>(b->dbuf + o_ci);
+    auto *q = reinterpret_cast<dope::Queue *>(b->dbuf + o_q);
+    b->dsum = reinterpret_cast<int32_t *>(b->dbuf + o_sum);
+    b->dparams = reinterpret_cast<int32_t *>(b->dbuf + o_par);
+    std::vector<dope::Img> himg(static_cast<size_t>(n));
+    std::vector<dope::Item> hbi, hci;
+    hbi.reserve(size_t(nblk));
+    hci.reserve(size_t(nchk));
+    for (int32_t i = 0; i < n; ++i) {
+        dope_ctx *c = b->ctxs[size_t(i)];
+        himg[size_t(i)] = host_img(c);
+        himg[size_t(i)].summary = b->dsum + 4 * i;
+        for (int32_t k = 0; k < c->g.K; ++k) hbi.push_back(dope::Item{i, k});
+        for (size_t k = 0; k < c->hchunk.size(); ++k) hci.push_back(dope::Item{i, int32_t(k)});
+        b->hsum[4 * i + 0] = c->hctl->t;
+        b->hsum[4 * i + 1] = c->hctl->halted;
+        b->hsum[4 * i + 2] = c->hctl->converged;
+        b->hsum[4 * i + 3] = c->hctl->status;
+    }
+    const dope::Queue hq{};
+    hipError_t e = hipMemcpyAsync(b->imgs, himg.data(), himg.size() * sizeof(dope::Img), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(bi, hbi.data(), hbi.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ci, hci.data(), hci.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(q, &hq, sizeof(hq), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->dsum, b->hsum, size_t(n) * 16, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        dope_batch_destroy(b);
+        return DOPE_EDEVICE;
+    }
+    b->grp = dope::Group{b->imgs, n, bi, int32_t(nblk), ci, int32_t(nchk), q, conn, solver, npmax, 0};
+    *out = b;
+    return DOPE_OK;
+}
+
+dope_status dope_batch_iterate(dope_batch *b, int32_t n_iter) {
+    if (!b || n_iter < 0) return DOPE_EINVAL;
+    const size_t n = b->ctxs.size();
+    for (size_t i = 0; i < n; ++i) {
+        b->hparams[2 * i] = b->hsum[4 * i] + n_iter;
+        b->hparams[2 * i + 1] = 0;
+    }
+    dope_status st = batch_setup(b);
+    if (st != DOPE_OK) return st;
+    for (int32_t it = 0; it < n_iter; ++it) {
+        st = batch_run_iteration(b);
+        if (st != DOPE_OK) return st;
+    }
+    st = batch_sync(b);
+    if (st != DOPE_OK) return st;
+    return batch_status(b);
+}
+
+dope_status dope_batch_solve(dope_batch *b) {
+    if (!b) return DOPE_EINVAL;
+    const size_t n = b->ctxs.size();
+    int32_t most = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const dope_ctx *c = b->ctxs[i];
+        const bool done = b->hsum[4 * i + 3] != 0 || (b->hsum[4 * i] > 0 && b->hsum[4 * i + 2]);
+        b->hparams[2 * i] = done ? b->hsum[4 * i] : c->p.max_iter;   // finished images take no more iterations
+        b->hparams[2 * i + 1] = 1;
+        most = std::max(most, c->p.max_iter);
+    }
+    dope_status st = batch_setup(b);
+    if (st != DOPE_OK) return st;
+    for (int32_t it = 0; it < most; ++it) {
+        st = batch_run_iteration(b);
+        if (st != DOPE_OK) return st;
+        st = batch_sync(b);
+        if (st != DOPE_OK) return st;
+        bool running = false;
+        for (size_t i = 0; i < n && !running; ++i)
+            running = !b->hsum[4 * i + 1] && b->hsum[4 * i] < b->hparams[2 * i];
+        if (!running) break;
+    }
+    return batch_status(b);
+}
+
+dope_status dope_batch_set_graph(dope_batch *b, int32_t on) {
+    if (!b) return DOPE_EINVAL;
+    b->use_graph = on != 0;
+    return DOPE_OK;
+}
+
+dope_status dope_batch_set_workers(dope_batch *b, int32_t nw) {
+    if (!b || nw < 0) return DOPE_EINVAL;
+    b->grp.n_workers = nw;
+    if (b->graph_ready) {   // the captured launch has the old grid
+        (void)hipGraphExecDestroy(b->gexec);
+        (void)hipGraphDestroy(b->graph);
+        b->gexec = nullptr;
+        b->graph = nullptr;
+        b->graph_ready = false;
+    }
+    return DOPE_OK;
+}
+
+dope_status dope_batch_info(dope_batch *b, dope_info *infos) {
+    if (!b || !infos) return DOPE_EINVAL;
+    for (size_t i = 0; i < b->ctxs.size(); ++i) {
+        dope_ctx *c = b->ctxs[i];
+        c->dirty = false;
+        dope_status st = sync_ctl(c);
+        if (st != DOPE_OK) return st;
+        fill_info(c, &infos[i]);
+    }
+    return DOPE_OK;
+}
+
+const char *dope_batch_last_error(const dope_batch *b) { return b ? b->err.c_str() : ""; }
+
+void dope_batch_destroy(dope_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->dbuf) (void)hipFree(b->dbuf);
+    if (b->hsum) (void)hipHostFree(b->hsum);
+    if (b->hparams) (void)hipHostFree(b->hparams);
+    delete b;
 }
 
 }  // extern "C"

@@ -21,7 +21,21 @@ struct Geom {
     int32_t max_np;     // largest block size in pixels
     int64_t n;          // pixels
     int64_t tot;        // sum of block sizes
+    int64_t span[3];    // sum of block extents along each axis
 };
+
+inline __host__ __device__ int32_t axis_ext(const Axis &a, int32_t t) {
+    const int32_t e = a.N - t * a.s;
+    return e < a.B ? e : a.B;
+}
+
+// Start of block (tx, ty, tz) in the block-major vectors.  Blocks are ordered x-fastest and only the last block
+// along an axis can be clipped, so the blocks before index t along an axis cover t * B pixels of that axis.
+inline __host__ __device__ int64_t block_offset(const Geom &g, int32_t tx, int32_t ty, int32_t tz) {
+    const int64_t Px = int64_t(tx) * g.ax[0].B, Py = int64_t(ty) * g.ax[1].B, Pz = int64_t(tz) * g.ax[2].B;
+    const int64_t Ey = axis_ext(g.ax[1], ty), Ez = axis_ext(g.ax[2], tz);
+    return Pz * g.span[1] * g.span[0] + Ez * (Py * g.span[0] + Ey * Px);
+}
 
 // Device-resident loop control.  Written by the host only through k_ctl_* kernels or state uploads.
 struct Ctl {
@@ -58,25 +72,63 @@ constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
 
 // Device lookup tables built on the host with the partition.
 struct Tables {
-    const int32_t *cov;        // per-axis cover tables (W + H + D entries), see dope_kernels.hip
     const int32_t *chunk_k0;   // block containing the first copy of every 256-copy chunk
     int32_t n_chunks;
 };
 
 constexpr int CHUNK = 256;
 
-// Kernel launchers (dope_kernels.hip).  All return hipSuccess or the launch error.
-hipError_t launch_prep_weights(const Geom &g, const Tables &tb, const int32_t *w, int32_t *cw, int32_t lam_q8,
-                               Ctl *ctl, hipStream_t s);
+// Everything a kernel needs to work on one image; an array of these lives in device memory so that one launch
+// can serve many images.
+struct Img {
+    Geom g;
+    const int32_t *u, *w, *cw, *btab, *chunk_k0;
+    int32_t *Y, *A0, *A1, *stats;
+    uint8_t *yhat;
+    int64_t *resid;
+    Ctl *ctl;
+    int32_t *summary;   // optional: {t, halted, converged, status} written after every iteration
+    int32_t n_chunks;
+    int32_t pad;
+};
+
+struct Item {
+    int32_t img, idx;   // image, and block (solve) or 256-copy chunk (consensus)
+};
+
+// Device work queue of the persistent block-solve launch; reset by the finalize kernel of each iteration.
+struct Queue {
+    uint32_t next;
+    uint32_t pad[63];
+};
+
+// Device arrays describing one launch group (all images share connectivity and solver).
+struct Group {
+    const Img *imgs;
+    int32_t n_imgs;
+    const Item *blk_items;
+    int32_t n_blk_items;
+    const Item *chk_items;
+    int32_t n_chk_items;
+    Queue *queue;
+    int32_t conn, solver, npmax;
+    int32_t n_workers;   // workgroups of the persistent block-solve launch (0 = one per item)
+};
+
+// One ADMM iteration (block solves, consensus and multipliers, loop control) for every image of the group.
+hipError_t launch_iteration(const Group &grp, hipStream_t s);
+// Per-image loop setup of a batch: params[2 i] = t_limit, params[2 i + 1] = stop_on_converge.
+hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params, hipStream_t s);
+// Individual phases (used for per-kernel timing).
+hipError_t launch_solve_phase(const Group &grp, hipStream_t s);
+hipError_t launch_consensus_phase(const Group &grp, hipStream_t s);
+
+hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
+                               hipStream_t s);
 hipError_t launch_init_state(const Geom &g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid,
                              Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2, hipStream_t s);
 hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy,
                             hipStream_t s);
-hipError_t launch_block_solve(const Geom &g, const Tables &tb, int solver, const int32_t *u, const int32_t *cw,
-                              const int32_t *Y, const int32_t *A0, const int32_t *A1, const int32_t *btab,
-                              uint8_t *yhat, int32_t *stats, int64_t *resid, Ctl *ctl, hipStream_t s);
-hipError_t launch_consensus(const Geom &g, const Tables &tb, const int32_t *cw, const uint8_t *yhat, int32_t *A0,
-                            int32_t *A1, int32_t *Y, const int32_t *btab, int64_t *resid, Ctl *ctl, hipStream_t s);
 hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s);
 // part: ENERGY_PARTS int64 of scratch.
 hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *w, int32_t lam_q8, const int32_t *Y,

@@ -52,23 +52,24 @@ __device__ __forceinline__ int3 full_dir(int d) {
     return v;
 }
 
-// Per-axis cover tables: cov[x] = t_hi | (1 << 30 when x also lies in interval t_hi - 1), where t_hi is the
-// highest-index block interval containing coordinate x.  Three tables back to back: W, H, D entries.
-struct Cov {
-    const int32_t *x, *y, *z;
+// Block intervals containing coordinate x of one axis: t_hi and, when cnt == 2, also t_hi - 1.  Coordinates
+// outside the axis return cnt = 0.
+struct AxCov {
+    int thi, cnt;
 };
 
-__device__ __forceinline__ Cov cov_of(const Geom &g, const int32_t *cov) { return Cov{cov, cov + g.W, cov + g.W + g.H}; }
-__device__ __forceinline__ int cov_cnt(int32_t c) { return 1 + ((c >> 30) & 1); }
-__device__ __forceinline__ int cov_hi(int32_t c) { return c & 0x3FFFFFFF; }
-
-__device__ __forceinline__ int q_at(const Cov &cv, int x, int y, int z) {
-    return cov_cnt(cv.x[x]) * cov_cnt(cv.y[y]) * cov_cnt(cv.z[z]);
+__device__ __forceinline__ AxCov axis_cov(const Axis &a, int x) {
+    if (x < 0 || x >= a.N) return AxCov{0, 0};
+    int th = x / a.s;
+    if (th > a.nb - 1) th = a.nb - 1;
+    const int two = (th >= 1 && x < (th - 1) * a.s + a.B) ? 1 : 0;
+    return AxCov{th, 1 + two};
 }
 
-__device__ __forceinline__ int axis_extent(const Axis &a, int t) {
-    int e = a.N - t * a.s;
-    return e < a.B ? e : a.B;
+__device__ __forceinline__ bool in_axis(const AxCov &c, int t) { return t == c.thi || (c.cnt == 2 && t == c.thi - 1); }
+
+__device__ __forceinline__ int q_at(const Geom &g, int x, int y, int z) {
+    return axis_cov(g.ax[0], x).cnt * axis_cov(g.ax[1], y).cnt * axis_cov(g.ax[2], z).cnt;
 }
 
 __device__ __forceinline__ bool in_grid(const Geom &g, int x, int y, int z) {
@@ -95,33 +96,52 @@ __device__ __forceinline__ int64_t floor_div_est(int64_t n, int64_t M, double in
 
 // Eq. (8) unary of pixel p of block k (scaled by 2^14, unary floored) and the block-local edge data.
 // cap_out[o] = c for in-block half-edges (0 otherwise); mask bit d set for in-block neighbours with c != 0;
-// sumc = sum of |c| over in-block neighbours.
+// sumc = sum of |c| over in-block neighbours.  All global loads are issued before any is used.
 template <int CONN>
-__device__ __forceinline__ int64_t block_unary(const Geom &g, const Cov &cv, const int32_t *__restrict__ u,
+__device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__restrict__ u,
                                                const int32_t *__restrict__ cw, const int32_t *__restrict__ Y,
                                                int32_t a_ki, int64_t M, int gx, int gy, int gz, int lx, int ly,
                                                int lz, int ex, int ey, int ez, int32_t *cap_out, unsigned &mask,
                                                int64_t &sumc) {
     constexpr int H = Sten<CONN>::H;
+    constexpr int ND = 2 * H;
     const int64_t i = lin(g, gx, gy, gz);
-    const int qi = q_at(cv, gx, gy, gz);
+    const int32_t ui = u[i];
     const int32_t Yi = Y[i];
+    int32_t cv[ND], yj[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int3 v = full_dir<CONN>(d);
+        const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
+        cv[d] = 0;
+        yj[d] = 0;
+        if (in_grid(g, jx, jy, jz)) {
+            const int64_t j = lin(g, jx, jy, jz);
+            cv[d] = (d < H) ? cw[int64_t(d) * g.n + i] : cw[int64_t(d - H) * g.n + j];
+            yj[d] = Y[j];
+        }
+    }
+    AxCov cx[3], cy[3], cz[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        cx[t] = axis_cov(g.ax[0], gx + t - 1);
+        cy[t] = axis_cov(g.ax[1], gy + t - 1);
+        cz[t] = CONN == 6 ? axis_cov(g.ax[2], gz + t - 1) : AxCov{0, 1};
+    }
+    const int qi = cx[1].cnt * cy[1].cnt * cz[1].cnt;
     int64_t G = 0;
     sumc = 0;
     mask = 0;
 #pragma unroll
-    for (int d = 0; d < 2 * H; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
-        const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
+        const int32_t c = cv[d];
         if (d < H) cap_out[d] = 0;
-        if (!in_grid(g, jx, jy, jz)) continue;
-        const int64_t j = lin(g, jx, jy, jz);
-        const int32_t c = (d < H) ? cw[int64_t(d) * g.n + i] : cw[int64_t(d - H) * g.n + j];
         if (c == 0) continue;
         const int mx = lx + v.x, my = ly + v.y, mz = lz + v.z;
         const bool inb = mx >= 0 && mx < ex && my >= 0 && my < ey && mz >= 0 && mz < ez;
-        const int qj = q_at(cv, jx, jy, jz);
-        G += int64_t(c) * int64_t(qj - (inb ? 1 : 0)) * int64_t(Yi - Y[j]);
+        const int qj = cx[v.x + 1].cnt * cy[v.y + 1].cnt * cz[v.z + 1].cnt;
+        G += int64_t(c) * int64_t(qj - (inb ? 1 : 0)) * int64_t(Yi - yj[d]);
         if (inb) {
             if (d < H) cap_out[d] = c;
             sumc += c < 0 ? -int64_t(c) : int64_t(c);
@@ -129,7 +149,7 @@ __device__ __forceinline__ int64_t block_unary(const Geom &g, const Cov &cv, con
         }
     }
     const int64_t mu_term = (M << 14) * int64_t(a_ki - Yi + Y_HALF);
-    return int64_t(u[i]) * int64_t(16384 / qi) + ((G + mu_term) >> 16);
+    return int64_t(ui) * int64_t(16384 / qi) + ((G + mu_term) >> 16);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -137,28 +157,23 @@ __device__ __forceinline__ int64_t block_unary(const Geom &g, const Cov &cv, con
 // ------------------------------------------------------------------------------------------------------------
 
 template <int CONN, int NT>
-__global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__restrict__ cov,
-                                                    const int32_t *__restrict__ u,
-                                                    const int32_t *__restrict__ cw, const int32_t *__restrict__ Y,
-                                                    const int32_t *__restrict__ A0, const int32_t *__restrict__ A1,
-                                                    const int32_t *__restrict__ btab, uint8_t *__restrict__ yhat,
-                                                    int32_t *__restrict__ stats, int64_t *__restrict__ resid,
-                                                    Ctl *ctl, int32_t npmax, int32_t round_limit,
-                                                    int32_t relabel_period) {
+__device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned char *smem, int32_t npmax,
+                                              int32_t round_limit, int32_t relabel_period) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
-    if (ctl_skip(ctl)) return;
-    const int k = blockIdx.x;
-    const int32_t *bt = btab + BTAB_STRIDE * k;
+    const Geom &g = im.g;
+    const int32_t *__restrict__ u = im.u;
+    const int32_t *__restrict__ cw = im.cw;
+    const int32_t *__restrict__ Y = im.Y;
+    const Ctl *ctl = im.ctl;
+    const int32_t *bt = im.btab + BTAB_STRIDE * k;
     const int x0 = bt[0], y0 = bt[1], z0 = bt[2], ex = bt[3], ey = bt[4], ez = bt[5];
     const int64_t off = bt[6];
     const int np = ex * ey * ez;
-    const int32_t *Ain = (ctl->t & 1) ? A1 : A0;
+    const int32_t *Ain = (ctl->t & 1) ? im.A1 : im.A0;
     const int64_t M = ctl->M;
-    const Cov cv = cov_of(g, cov);
-    if (threadIdx.x == 0) resid[k] = 0;     // accumulated by the consensus kernel of this iteration
+    if (threadIdx.x == 0) im.resid[k] = 0;     // accumulated by the consensus kernel of this iteration
 
-    extern __shared__ __align__(16) unsigned char smem[];
     int *s_ctr = reinterpret_cast<int *>(smem);                    // 16 ints of scalars
     int32_t *cap = reinterpret_cast<int32_t *>(smem + 64);         // [H][npmax]
     int32_t *flw = cap + H * npmax;                                 // [H][npmax]  flow p -> p + off_o
@@ -193,7 +208,7 @@ __global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__res
         else flw[(d - H) * npmax + p - loff[d - H]] -= delta;
     };
 
-    if (tid < 16) s_ctr[tid] = 0;
+    if (tid < 15) s_ctr[tid] = 0;
     __syncthreads();
 
     // ---- prologue: Eq. (8) unaries, in-block capacities, strictly forced nodes ----
@@ -202,8 +217,8 @@ __global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__res
         int32_t cp[H];
         unsigned m;
         int64_t sumc;
-        const int64_t Ut = block_unary<CONN>(g, cv, u, cw, Y, Ain[off + p], M, x0 + lx, y0 + ly, z0 + lz, lx, ly,
-                                             lz, ex, ey, ez, cp, m, sumc);
+        const int64_t Ut = block_unary<CONN>(g, u, cw, Y, Ain[off + p], M, x0 + lx, y0 + ly, z0 + lz, lx, ly, lz,
+                                             ex, ey, ez, cp, m, sumc);
 #pragma unroll
         for (int o = 0; o < H; ++o) {
             cap[o * npmax + p] = cp[o];
@@ -399,14 +414,35 @@ __global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__res
 
     for (int p = tid; p < np; p += NT) {
         const uint8_t s = st[p];
-        yhat[off + p] = (s & ST_FIXED) ? ((s & ST_LABEL) ? 1 : 0) : ((s & ST_MARK) ? 1 : 0);
+        im.yhat[off + p] = (s & ST_FIXED) ? ((s & ST_LABEL) ? 1 : 0) : ((s & ST_MARK) ? 1 : 0);
     }
     if (tid == 0) {
-        stats[4 * k + 0] = nfree;
-        stats[4 * k + 1] = rounds;
-        stats[4 * k + 2] = grel;
-        stats[4 * k + 3] = cascades;
-        if (fail) atomicOr(&ctl->solver_err, 1);
+        im.stats[4 * k + 0] = nfree;
+        im.stats[4 * k + 1] = rounds;
+        im.stats[4 * k + 2] = grel;
+        im.stats[4 * k + 3] = cascades;
+        if (fail) atomicOr(&im.ctl->solver_err, 1);
+    }
+}
+
+// Persistent block-solve launch: every workgroup takes (image, block) items from the device work queue until it
+// is empty, so blocks of many images of uneven sizes and uneven max-flow cost share one launch.
+template <int CONN, int NT>
+__global__ __launch_bounds__(NT) void k_block_solve(const Img *__restrict__ imgs, const Item *__restrict__ items,
+                                                    int32_t n_items, Queue *queue, int32_t npmax,
+                                                    int32_t round_limit, int32_t relabel_period) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int *s_item = reinterpret_cast<int *>(smem) + 15;   // the block solver uses scalar slots 0..14
+    for (;;) {
+        if (threadIdx.x == 0) *s_item = int(atomicAdd(&queue->next, 1u));
+        __syncthreads();
+        const int it = *s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const Item wi = items[it];
+        const Img &im = imgs[wi.img];
+        if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period);
+        __syncthreads();   // the LDS of this item is reused by the next one
     }
 }
 
@@ -417,41 +453,38 @@ __global__ __launch_bounds__(NT) void k_block_solve(Geom g, const int32_t *__res
 constexpr int EX_WAVES = 4;   // blocks per 256-thread workgroup
 
 template <int CONN>
-__global__ __launch_bounds__(256) void k_block_exhaustive(Geom g, const int32_t *__restrict__ cov,
-                                                          const int32_t *__restrict__ u,
-                                                          const int32_t *__restrict__ cw,
-                                                          const int32_t *__restrict__ Y,
-                                                          const int32_t *__restrict__ A0,
-                                                          const int32_t *__restrict__ A1,
-                                                          const int32_t *__restrict__ btab,
-                                                          uint8_t *__restrict__ yhat, int32_t *__restrict__ stats,
-                                                          int64_t *__restrict__ resid, Ctl *ctl) {
+__global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict__ imgs,
+                                                          const Item *__restrict__ items, int32_t n_items) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
-    if (ctl_skip(ctl)) return;
     __shared__ int32_t s_U[EX_WAVES][16];
     __shared__ int32_t s_nc[EX_WAVES][16][ND];   // capacity towards full-stencil neighbour d (0 = none)
     __shared__ int8_t s_nj[EX_WAVES][16][ND];    // local index of that neighbour
     __shared__ uint8_t s_m[EX_WAVES][16];        // in-block neighbour mask
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int k = blockIdx.x * EX_WAVES + wave;
-    const bool live = k < g.K;
+    const int it = blockIdx.x * EX_WAVES + wave;
+    const Item wi = it < n_items ? items[it] : Item{0, 0};
+    const Img &im = imgs[wi.img];
+    const Geom &g = im.g;
+    const Ctl *ctl = im.ctl;
+    const int k = wi.idx;
+    const bool live = it < n_items && !ctl_skip(ctl);
     int np = 0;
     int64_t off = 0;
     if (live) {
-        const int32_t *bt = btab + BTAB_STRIDE * k;
+        const int32_t *bt = im.btab + BTAB_STRIDE * k;
         const int x0 = bt[0], y0 = bt[1], z0 = bt[2], ex = bt[3], ey = bt[4], ez = bt[5];
         off = bt[6];
         np = ex * ey * ez;
-        const int32_t *Ain = (ctl->t & 1) ? A1 : A0;
+        const int32_t *Ain = (ctl->t & 1) ? im.A1 : im.A0;
         if (lane < np) {
             const int p = lane;
             const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
             int32_t cp[H];
             unsigned m;
             int64_t sumc;
-            int64_t Ut = block_unary<CONN>(g, cov_of(g, cov), u, cw, Y, Ain[off + p], ctl->M, x0 + lx, y0 + ly,
-                                           z0 + lz, lx, ly, lz, ex, ey, ez, cp, m, sumc);
+            int64_t Ut = block_unary<CONN>(g, im.u, im.cw, im.Y, Ain[off + p], ctl->M, x0 + lx, y0 + ly, z0 + lz,
+                                           lx, ly, lz, ex, ey, ez, cp, m, sumc);
             // clamping a strictly forced unary to +-(sum |c| + 1) keeps the minimiser set
             if (Ut > sumc + 1) Ut = sumc + 1;
             if (Ut < -sumc - 1) Ut = -sumc - 1;
@@ -518,13 +551,13 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(Geom g, const int32_t 
         const uint32_t oc = __shfl_xor(bestc, s);
         if (oE < best || (oE == best && oc < bestc)) { best = oE; bestc = oc; }
     }
-    if (lane < np) yhat[off + lane] = uint8_t((bestc >> lane) & 1u);
+    if (lane < np) im.yhat[off + lane] = uint8_t((bestc >> lane) & 1u);
     if (lane == 0) {
-        resid[k] = 0;
-        stats[4 * k + 0] = np;
-        stats[4 * k + 1] = 0;
-        stats[4 * k + 2] = 0;
-        stats[4 * k + 3] = 0;
+        im.resid[k] = 0;
+        im.stats[4 * k + 0] = np;
+        im.stats[4 * k + 1] = 0;
+        im.stats[4 * k + 2] = 0;
+        im.stats[4 * k + 3] = 0;
     }
 }
 
@@ -539,116 +572,159 @@ constexpr int CONS_NT = CHUNK;   // block-pixel copies per workgroup
 // block with the highest index along every axis writes Y_m.  The last workgroup to finish reduces max_k r_k,
 // decides convergence / overflow, advances mu and t.
 template <int CONN>
-__global__ __launch_bounds__(CONS_NT) void k_consensus(Geom g, const int32_t *__restrict__ cov,
-                                                       const int32_t *__restrict__ cw,
-                                                       const uint8_t *__restrict__ yhat, int32_t *A0, int32_t *A1,
-                                                       int32_t *__restrict__ Y, const int32_t *__restrict__ btab,
-                                                       const int32_t *__restrict__ chunk_k0, int64_t *resid,
-                                                       Ctl *ctl) {
+__global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ imgs, const Item *__restrict__ items) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
+    constexpr int NDIM = CONN == 6 ? 3 : 2;
+    constexpr int MAXC = 1 << NDIM;   // most blocks a pixel can lie in
+    const Item wi = items[blockIdx.x];
+    const Img &im = imgs[wi.img];
+    const Geom &g = im.g;
+    Ctl *ctl = im.ctl;
     if (ctl_skip(ctl)) return;
+    const int32_t *__restrict__ cw = im.cw;
+    const uint8_t *__restrict__ yhat = im.yhat;
+    const int32_t *__restrict__ btab = im.btab;
+    int32_t *__restrict__ Y = im.Y;
+    int64_t *resid = im.resid;
+    const int chunk = wi.idx;
     __shared__ unsigned long long s_res[CONS_NT];
     __shared__ int s_ovf;
     const int tid = threadIdx.x;
     const int par = ctl->t & 1;
-    const int32_t *Ain = par ? A1 : A0;
-    int32_t *Aout = par ? A0 : A1;
+    const int32_t *Ain = par ? im.A1 : im.A0;
+    int32_t *Aout = par ? im.A0 : im.A1;
     const int64_t M = ctl->M;
     const double invM = 1.0 / double(M);
-    const Cov cv = cov_of(g, cov);
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
-    const int kfirst = chunk_k0[blockIdx.x];
+    const int kfirst = im.chunk_k0[chunk];
     s_res[tid] = 0;
     if (tid == 0) s_ovf = 0;
     __syncthreads();
-    const int64_t c = int64_t(blockIdx.x) * CONS_NT + tid;
+    const int64_t c = int64_t(chunk) * CONS_NT + tid;
     int ovf = 0;
+    int kk = kfirst;
+    int64_t r2 = 0;
     if (c < g.tot) {
-        int kk = kfirst;
         while (kk + 1 < g.K && int64_t(btab[BTAB_STRIDE * (kk + 1) + 6]) <= c) ++kk;
         const int32_t *bt = btab + BTAB_STRIDE * kk;
         const int ex = bt[3], ey = bt[4];
         const int p = int(c - bt[6]);
         const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
         const int gx = bt[0] + lx, gy = bt[1] + ly, gz = bt[2] + lz;
-        const int32_t cvx = cv.x[gx], cvy = cv.y[gy], cvz = cv.z[gz];
-        const int nxm = cov_cnt(cvx), nym = cov_cnt(cvy), nzm = cov_cnt(cvz);
-        const int txh = cov_hi(cvx), tyh = cov_hi(cvy), tzh = cov_hi(cvz);
-        const int qm = nxm * nym * nzm;
+        const int kx = kk % AX.nb, ky = (kk / AX.nb) % AY.nb, kz = kk / (AX.nb * AY.nb);
         const int64_t m = lin(g, gx, gy, gz);
-        int64_t S = 0, HC = 0;
-        // copies of m: S_m and the first term of Hc_m
-        for (int a = 0; a < nzm; ++a)
-            for (int b = 0; b < nym; ++b)
-                for (int e = 0; e < nxm; ++e) {
-                    const int tx = txh - e, ty = tyh - b, tz = tzh - a;
-                    const int kb = tx + AX.nb * (ty + AY.nb * tz);
-                    const int bx0 = tx * AX.s, by0 = ty * AY.s, bz0 = tz * AZ.s;
-                    const int bex = axis_extent(AX, tx), bey = axis_extent(AY, ty), bez = axis_extent(AZ, tz);
-                    const int64_t cc = int64_t(btab[BTAB_STRIDE * kb + 6]) + (gx - bx0) +
-                                       int64_t(bex) * ((gy - by0) + int64_t(bey) * (gz - bz0));
-                    const int yv = yhat[cc];
-                    S += int64_t(yv) * Y_ONE + Ain[cc];
-                    if (yv) {
+        // block intervals of the coordinates x-1, x, x+1 along each axis (index 1 = m itself)
+        AxCov cx[3], cy[3], cz[3];
 #pragma unroll
-                        for (int d = 0; d < ND; ++d) {
-                            const int3 v = full_dir<CONN>(d);
-                            const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
-                            if (!in_grid(g, jx, jy, jz)) continue;
-                            const int32_t cmj = (d < H) ? cw[int64_t(d) * g.n + m]
-                                                        : cw[int64_t(d - H) * g.n + lin(g, jx, jy, jz)];
-                            if (cmj == 0) continue;
-                            const bool inb = jx >= bx0 && jx < bx0 + bex && jy >= by0 && jy < by0 + bey &&
-                                             jz >= bz0 && jz < bz0 + bez;
-                            HC += int64_t(cmj) * (q_at(cv, jx, jy, jz) - (inb ? 1 : 0));
-                        }
-                    }
-                }
-        // second term of Hc_m: copies of every stencil neighbour j
+        for (int t = 0; t < 3; ++t) {
+            cx[t] = axis_cov(AX, gx + t - 1);
+            cy[t] = axis_cov(AY, gy + t - 1);
+            cz[t] = NDIM == 3 ? axis_cov(AZ, gz + t - 1) : AxCov{0, 1};
+        }
+        const int qm = cx[1].cnt * cy[1].cnt * cz[1].cnt;
+        // ---- every load of this copy is issued before any of them is used ----
+        const int yk = yhat[c];
+        const int32_t a_old = Ain[c];
+        int yv_own[MAXC];
+        int32_t a_own[MAXC];
+#pragma unroll
+        for (int q = 0; q < MAXC; ++q) {
+            const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
+            yv_own[q] = 0;
+            a_own[q] = 0;
+            if (e < cx[1].cnt && b < cy[1].cnt && a < cz[1].cnt) {
+                const int tx = cx[1].thi - e, ty = cy[1].thi - b, tz = cz[1].thi - a;
+                const int64_t cc = block_offset(g, tx, ty, tz) + (gx - tx * AX.s) +
+                                   int64_t(axis_ext(AX, tx)) * ((gy - ty * AY.s) + int64_t(axis_ext(AY, ty)) * (gz - tz * AZ.s));
+                yv_own[q] = yhat[cc];
+                a_own[q] = Ain[cc];
+            }
+        }
+        int32_t cwv[ND];
+        int yv_nb[ND][MAXC];
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
             const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
-            if (!in_grid(g, jx, jy, jz)) continue;
-            const int64_t j = lin(g, jx, jy, jz);
-            const int32_t cjm = (d < H) ? cw[int64_t(d) * g.n + m] : cw[int64_t(d - H) * g.n + j];
-            if (cjm == 0) continue;
-            const int32_t cjx = cv.x[jx], cjy = cv.y[jy], cjz = cv.z[jz];
-            const int nx = cov_cnt(cjx), ny = cov_cnt(cjy), nz = cov_cnt(cjz);
-            for (int a = 0; a < nz; ++a)
-                for (int b = 0; b < ny; ++b)
-                    for (int e = 0; e < nx; ++e) {
-                        const int tx = cov_hi(cjx) - e, ty = cov_hi(cjy) - b, tz = cov_hi(cjz) - a;
-                        const int kb = tx + AX.nb * (ty + AY.nb * tz);
-                        const int bx0 = tx * AX.s, by0 = ty * AY.s, bz0 = tz * AZ.s;
-                        const int bex = axis_extent(AX, tx), bey = axis_extent(AY, ty), bez = axis_extent(AZ, tz);
-                        const int64_t cc = int64_t(btab[BTAB_STRIDE * kb + 6]) + (jx - bx0) +
-                                           int64_t(bex) * ((jy - by0) + int64_t(bey) * (jz - bz0));
-                        if (!yhat[cc]) continue;
-                        const bool m_in = gx >= bx0 && gx < bx0 + bex && gy >= by0 && gy < by0 + bey &&
-                                          gz >= bz0 && gz < bz0 + bez;
-                        HC -= int64_t(qm - (m_in ? 1 : 0)) * int64_t(cjm);
-                    }
+            const bool ing = in_grid(g, jx, jy, jz);
+            cwv[d] = 0;
+            if (ing) cwv[d] = (d < H) ? cw[int64_t(d) * g.n + m] : cw[int64_t(d - H) * g.n + lin(g, jx, jy, jz)];
+            const AxCov &ax = cx[v.x + 1], &ay = cy[v.y + 1], &az = cz[v.z + 1];
+#pragma unroll
+            for (int q = 0; q < MAXC; ++q) {
+                const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
+                yv_nb[d][q] = 0;
+                if (ing && e < ax.cnt && b < ay.cnt && a < az.cnt) {
+                    const int tx = ax.thi - e, ty = ay.thi - b, tz = az.thi - a;
+                    const int64_t cc = block_offset(g, tx, ty, tz) + (jx - tx * AX.s) +
+                                       int64_t(axis_ext(AX, tx)) * ((jy - ty * AY.s) + int64_t(axis_ext(AY, ty)) * (jz - tz * AZ.s));
+                    yv_nb[d][q] = yhat[cc];
+                }
+            }
+        }
+        // ---- S_m and Hc_m ----
+        int64_t S = 0, HC = 0;
+#pragma unroll
+        for (int q = 0; q < MAXC; ++q) {
+            const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
+            if (!(e < cx[1].cnt && b < cy[1].cnt && a < cz[1].cnt)) continue;
+            S += int64_t(yv_own[q]) * Y_ONE + a_own[q];
+            if (!yv_own[q]) continue;
+            // first term: sum_j c_mj (q_j - [j in k]) for this copy's block k
+            const int tx = cx[1].thi - e, ty = cy[1].thi - b, tz = cz[1].thi - a;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const int3 v = full_dir<CONN>(d);
+                const AxCov &ax = cx[v.x + 1], &ay = cy[v.y + 1], &az = cz[v.z + 1];
+                // j lies in block (tx, ty, tz) iff that block is one of j's intervals on every axis
+                const bool inb = in_axis(ax, tx) && in_axis(ay, ty) && in_axis(az, tz);
+                HC += int64_t(cwv[d]) * (ax.cnt * ay.cnt * az.cnt - (inb ? 1 : 0));
+            }
+        }
+        // second term: sum over copies of each neighbour j of (q_m - [m in that block]) c_jm
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const int3 v = full_dir<CONN>(d);
+            const AxCov &ax = cx[v.x + 1], &ay = cy[v.y + 1], &az = cz[v.z + 1];
+#pragma unroll
+            for (int q = 0; q < MAXC; ++q) {
+                if (!yv_nb[d][q]) continue;
+                const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
+                const int tx = ax.thi - e, ty = ay.thi - b, tz = az.thi - a;
+                const bool m_in = in_axis(cx[1], tx) && in_axis(cy[1], ty) && in_axis(cz[1], tz);
+                HC -= int64_t(qm - (m_in ? 1 : 0)) * int64_t(cwv[d]);
+            }
         }
         // floor((M S - 4 Hc) / (M q)) = floor(floor((M S - 4 Hc) / M) / q), q a power of two
         int64_t Yn = floor_div_est(M * S - 4 * HC, M, invM);
         Yn >>= (qm == 1 ? 0 : qm == 2 ? 1 : qm == 4 ? 2 : 3);
-        const int yk = yhat[c];
-        const int64_t An = int64_t(Ain[c]) + int64_t(yk) * Y_ONE - Yn;
+        const int64_t An = int64_t(a_old) + int64_t(yk) * Y_ONE - Yn;
         if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT || An >= STATE_LIMIT || An <= -STATE_LIMIT) ovf = 1;
         const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
         const int64_t Ac = An > STATE_LIMIT ? STATE_LIMIT : (An < -STATE_LIMIT ? -STATE_LIMIT : An);
         Aout[c] = int32_t(Ac);
-        const int kx = kk % AX.nb, ky = (kk / AX.nb) % AY.nb, kz = kk / (AX.nb * AY.nb);
-        if (kx == txh && ky == tyh && kz == tzh) Y[m] = int32_t(Yc);
+        if (kx == cx[1].thi && ky == cy[1].thi && kz == cz[1].thi) Y[m] = int32_t(Yc);
         const int64_t rr = int64_t(yk) * Y_ONE - Yc;
-        atomicAdd(&s_res[kk - kfirst], (unsigned long long)(rr * rr));
+        r2 = rr * rr;
+    }
+    // per-block residual: one LDS atomic per wavefront when all its lanes share a block
+    {
+        const int k0 = __shfl(kk, 0);
+        const bool same = __all(kk == k0);
+        if (same) {
+            unsigned long long v = (unsigned long long)r2;
+#pragma unroll
+            for (int sft = 32; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft);
+            if ((tid & 63) == 0 && v) atomicAdd(&s_res[k0 - kfirst], v);
+        } else if (r2) {
+            atomicAdd(&s_res[kk - kfirst], (unsigned long long)r2);
+        }
     }
     if (ovf) s_ovf = 1;
     __syncthreads();
     {
-        const int klast = (blockIdx.x + 1 < gridDim.x) ? chunk_k0[blockIdx.x + 1] : g.K - 1;
+        const int klast = (chunk + 1 < im.n_chunks) ? im.chunk_k0[chunk + 1] : g.K - 1;
         const int span = min(klast - kfirst + 1, CONS_NT);
         for (int b = tid; b < span; b += CONS_NT)
             if (s_res[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&resid[kfirst + b]), s_res[b]);
@@ -659,13 +735,16 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(Geom g, const int32_t *__
 // Loop control after the consensus of one iteration (a single workgroup): max_k r_k, stopping rule, overflow
 // and solver errors, mu <- mu * mu_fact, t <- t + 1.  A separate launch instead of a last-workgroup handshake
 // inside k_consensus: a device-scope fence per workgroup costs L2 write-backs on every XCD.
-__global__ __launch_bounds__(256) void k_finalize(Geom g, const int64_t *__restrict__ resid, Ctl *ctl) {
+__global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, Queue *queue) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) queue->next = 0;   // next iteration's block-solve queue
+    const Img &im = imgs[blockIdx.x];
+    Ctl *ctl = im.ctl;
     if (ctl_skip(ctl)) return;
     __shared__ unsigned long long s_max[4];
     const int tid = threadIdx.x;
     unsigned long long mx = 0;
-    for (int k = tid; k < g.K; k += 256) {
-        const unsigned long long v = static_cast<unsigned long long>(resid[k]);
+    for (int k = tid; k < im.g.K; k += 256) {
+        const unsigned long long v = static_cast<unsigned long long>(im.resid[k]);
         mx = v > mx ? v : mx;
     }
 #pragma unroll
@@ -689,6 +768,12 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, const int64_t *__restr
         ctl->t = ctl->t + 1;
         ctl->ovf_pending = 0;
         ctl->solver_err = 0;
+        if (im.summary) {
+            im.summary[0] = ctl->t;
+            im.summary[1] = ctl->halted;
+            im.summary[2] = conv;
+            im.summary[3] = ctl->status;
+        }
     }
 }
 
@@ -699,16 +784,14 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, const int64_t *__restr
 // c_ij = lambda_q8 w_ij 64 / (q_i q_j) for the half-stencil edges of every pixel, with validation: nonzero weight
 // on an off-grid edge, negative weight, and per-node sum_j |c_ij| >= 2^29 raise flags.  grid: (ceil(W/256), H*D).
 template <int CONN>
-__global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict__ cov,
-                                              const int32_t *__restrict__ w, int32_t *__restrict__ cw, int32_t lam,
+__global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict__ w, int32_t *__restrict__ cw, int32_t lam,
                                               Ctl *ctl) {
     constexpr int H = Sten<CONN>::H;
     const int gx = blockIdx.x * 256 + threadIdx.x;
     if (gx >= g.W) return;
     const int gy = int(blockIdx.y) % g.H, gz = int(blockIdx.y) / g.H;
-    const Cov cv = cov_of(g, cov);
     const int64_t i = lin(g, gx, gy, gz);
-    const int qi = q_at(cv, gx, gy, gz);
+    const int qi = q_at(g, gx, gy, gz);
     int flags = 0;
     int64_t sum = 0;
 #pragma unroll
@@ -725,7 +808,7 @@ __global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict_
             if (wv != 0) flags |= FLAG_OFFGRID;
         } else if (wv != 0) {
             if (wv < 0) flags |= FLAG_NEGATIVE;
-            const int qq = qi * q_at(cv, jx, jy, jz);
+            const int qq = qi * q_at(g, jx, jy, jz);
             const int64_t cvv = int64_t(lam) * int64_t(wv) * int64_t(64 / qq);
             if (cvv >= CAP_SUM_LIMIT || cvv <= -CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
             else c = int32_t(cvv);
@@ -763,6 +846,15 @@ __global__ void k_init_state(Geom g, int32_t *Y, int32_t *A0, int32_t *A1, uint8
         ctl->mu_den = mu_den;
         ctl->flags = 0;
     }
+}
+
+__global__ void k_batch_setup(const Img *__restrict__ imgs, int32_t n, const int32_t *__restrict__ params) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Ctl *ctl = imgs[i].ctl;
+    ctl->t_limit = params[2 * i];
+    ctl->stop_on_converge = params[2 * i + 1];
+    if (ctl->status == 0) ctl->halted = 0;
 }
 
 __global__ void k_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy) {
@@ -831,46 +923,44 @@ __global__ __launch_bounds__(256) void k_energy_sum(const int64_t *__restrict__ 
 inline unsigned blocks_for(int64_t n, int nt) { return unsigned((n + nt - 1) / nt); }
 
 template <int CONN, int NT>
-hipError_t launch_maxflow(const Geom &g, const Tables &tb, const int32_t *u, const int32_t *cw, const int32_t *Y,
-                          const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat, int32_t *stats,
-                          int64_t *resid, Ctl *ctl, hipStream_t s) {
+hipError_t launch_maxflow(const Group &grp, hipStream_t s) {
     constexpr int H = Sten<CONN>::H;
-    const size_t lds = maxflow_lds_bytes(g.max_np, H);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_block_solve<CONN, NT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(LDS_LIMIT));
-        attr_set = true;
+    const size_t lds = maxflow_lds_bytes(grp.npmax, H);
+    static size_t lds_set = 0;
+    if (lds > lds_set) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_block_solve<CONN, NT>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        lds_set = lds;
     }
-    const int32_t round_limit = 65536 + 64 * g.max_np;
-    hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(g.K), dim3(NT), lds, s, g, tb.cov, u, cw, Y, A0, A1, btab,
-                       yhat, stats, resid, ctl, g.max_np, round_limit, 8);
+    const int32_t round_limit = 65536 + 64 * grp.npmax;
+    const int32_t workers = grp.n_workers > 0 ? (grp.n_workers < grp.n_blk_items ? grp.n_workers : grp.n_blk_items)
+                                              : grp.n_blk_items;
+    hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(workers), dim3(NT), lds, s, grp.imgs, grp.blk_items,
+                       grp.n_blk_items, grp.queue, grp.npmax, round_limit, 8);
     return hipGetLastError();
 }
 
 template <int CONN>
-hipError_t solve_conn(const Geom &g, const Tables &tb, int solver, const int32_t *u, const int32_t *cw,
-                      const int32_t *Y, const int32_t *A0, const int32_t *A1, const int32_t *btab, uint8_t *yhat,
-                      int32_t *stats, int64_t *resid, Ctl *ctl, hipStream_t s) {
-    if (solver == 2) {
-        hipLaunchKernelGGL(k_block_exhaustive<CONN>, dim3(blocks_for(g.K, EX_WAVES)), dim3(256), 0, s, g, tb.cov, u,
-                           cw, Y, A0, A1, btab, yhat, stats, resid, ctl);
+hipError_t solve_phase(const Group &grp, hipStream_t s) {
+    if (grp.solver == 2) {
+        hipLaunchKernelGGL(k_block_exhaustive<CONN>, dim3(blocks_for(grp.n_blk_items, EX_WAVES)), dim3(256), 0, s,
+                           grp.imgs, grp.blk_items, grp.n_blk_items);
         return hipGetLastError();
     }
-    if (g.max_np > 512)
-        return launch_maxflow<CONN, 1024>(g, tb, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
-    return launch_maxflow<CONN, 256>(g, tb, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
+    if (grp.npmax > 512) return launch_maxflow<CONN, 1024>(grp, s);
+    return launch_maxflow<CONN, 256>(grp, s);
 }
 
 }  // namespace
 
-hipError_t launch_prep_weights(const Geom &g, const Tables &tb, const int32_t *w, int32_t *cw, int32_t lam_q8,
-                               Ctl *ctl, hipStream_t s) {
+hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
+                               hipStream_t s) {
     const dim3 grid(blocks_for(g.W, 256), unsigned(g.H) * unsigned(g.D));
     switch (g.conn) {
-        case 4: hipLaunchKernelGGL(k_prep<4>, grid, dim3(256), 0, s, g, tb.cov, w, cw, lam_q8, ctl); break;
-        case 8: hipLaunchKernelGGL(k_prep<8>, grid, dim3(256), 0, s, g, tb.cov, w, cw, lam_q8, ctl); break;
-        default: hipLaunchKernelGGL(k_prep<6>, grid, dim3(256), 0, s, g, tb.cov, w, cw, lam_q8, ctl); break;
+        case 4: hipLaunchKernelGGL(k_prep<4>, grid, dim3(256), 0, s, g, w, cw, lam_q8, ctl); break;
+        case 8: hipLaunchKernelGGL(k_prep<8>, grid, dim3(256), 0, s, g, w, cw, lam_q8, ctl); break;
+        default: hipLaunchKernelGGL(k_prep<6>, grid, dim3(256), 0, s, g, w, cw, lam_q8, ctl); break;
     }
     return hipGetLastError();
 }
@@ -891,35 +981,34 @@ hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge,
     return hipGetLastError();
 }
 
-hipError_t launch_block_solve(const Geom &g, const Tables &tb, int solver, const int32_t *u, const int32_t *cw,
-                              const int32_t *Y, const int32_t *A0, const int32_t *A1, const int32_t *btab,
-                              uint8_t *yhat, int32_t *stats, int64_t *resid, Ctl *ctl, hipStream_t s) {
-    switch (g.conn) {
-        case 4: return solve_conn<4>(g, tb, solver, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
-        case 8: return solve_conn<8>(g, tb, solver, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
-        default: return solve_conn<6>(g, tb, solver, u, cw, Y, A0, A1, btab, yhat, stats, resid, ctl, s);
+hipError_t launch_solve_phase(const Group &grp, hipStream_t s) {
+    switch (grp.conn) {
+        case 4: return solve_phase<4>(grp, s);
+        case 8: return solve_phase<8>(grp, s);
+        default: return solve_phase<6>(grp, s);
     }
 }
 
-hipError_t launch_consensus(const Geom &g, const Tables &tb, const int32_t *cw, const uint8_t *yhat, int32_t *A0,
-                            int32_t *A1, int32_t *Y, const int32_t *btab, int64_t *resid, Ctl *ctl, hipStream_t s) {
-    const unsigned grid = unsigned(tb.n_chunks);
-    switch (g.conn) {
-        case 4:
-            hipLaunchKernelGGL(k_consensus<4>, dim3(grid), dim3(CONS_NT), 0, s, g, tb.cov, cw, yhat, A0, A1, Y, btab,
-                               tb.chunk_k0, resid, ctl);
-            break;
-        case 8:
-            hipLaunchKernelGGL(k_consensus<8>, dim3(grid), dim3(CONS_NT), 0, s, g, tb.cov, cw, yhat, A0, A1, Y, btab,
-                               tb.chunk_k0, resid, ctl);
-            break;
-        default:
-            hipLaunchKernelGGL(k_consensus<6>, dim3(grid), dim3(CONS_NT), 0, s, g, tb.cov, cw, yhat, A0, A1, Y, btab,
-                               tb.chunk_k0, resid, ctl);
-            break;
+hipError_t launch_consensus_phase(const Group &grp, hipStream_t s) {
+    const dim3 grid(unsigned(grp.n_chk_items));
+    switch (grp.conn) {
+        case 4: hipLaunchKernelGGL(k_consensus<4>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
+        case 8: hipLaunchKernelGGL(k_consensus<8>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
+        default: hipLaunchKernelGGL(k_consensus<6>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, g, resid, ctl);
+    hipLaunchKernelGGL(k_finalize, dim3(unsigned(grp.n_imgs)), dim3(256), 0, s, grp.imgs, grp.queue);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_setup, dim3(blocks_for(n, 256)), dim3(256), 0, s, imgs, n, params);
+    return hipGetLastError();
+}
+
+hipError_t launch_iteration(const Group &grp, hipStream_t s) {
+    hipError_t e = launch_solve_phase(grp, s);
+    if (e != hipSuccess) return e;
+    return launch_consensus_phase(grp, s);
 }
 
 hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s) {

@@ -173,3 +173,55 @@ class Dope:
 def _info(info):
     return {"iters_done": info.iters_done, "converged": bool(info.converged), "max_resid2": info.max_resid2,
             "mu": info.mu}
+
+
+class Batch:
+    """A dope_batch over existing Dope contexts (which must outlive it)."""
+
+    def __init__(self, members, graph=False, workers=0):
+        self.members = list(members)
+        arr = (ctypes.c_void_p * len(self.members))(*[m.ctx.value for m in self.members])
+        b = ctypes.c_void_p()
+        st = N.dope_batch_create(arr, len(self.members), ctypes.byref(b))
+        if st != N.DOPE_OK:
+            raise N.DopeError(st, N.dope_last_error(self.members[0].ctx).decode())
+        self.b = b
+        if graph:
+            self._check(N.dope_batch_set_graph(b, 1))
+        if workers:
+            self._check(N.dope_batch_set_workers(b, int(workers)))
+
+    def _check(self, st):
+        if st != N.DOPE_OK:
+            raise N.DopeError(st, N.dope_batch_last_error(self.b).decode())
+
+    def iterate(self, n_iter=1):
+        self._check(N.dope_batch_iterate(self.b, int(n_iter)))
+
+    def iterate_status(self, n_iter=1):
+        return N.dope_batch_iterate(self.b, int(n_iter))
+
+    def solve(self):
+        self._check(N.dope_batch_solve(self.b))
+
+    def info(self):
+        arr = (N.dope_info * len(self.members))()
+        self._check(N.dope_batch_info(self.b, arr))
+        return [_info(x) for x in arr]
+
+    def close(self):
+        if getattr(self, "b", None):
+            N.dope_batch_destroy(self.b)
+            self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -63,7 +63,7 @@ def _workspace_model(dims, h, K, tot):
     a = lambda x: (x + 255) // 256 * 256  # noqa: E731
     n = dims[0] * dims[1] * dims[2]
     chunks = (tot + 255) // 256
-    return (a(128) + a(K * 32) + a(4 * sum(dims)) + a(4 * chunks) + a(4 * n) + 2 * a(4 * h * n) + a(4 * n)
+    return (a(128) + a(256) + a(8 * K) + a(8 * chunks) + a(256) + a(K * 32) + a(4 * chunks) + a(4 * n) + 2 * a(4 * h * n) + a(4 * n)
             + 2 * a(4 * tot) + a(tot) + a(8 * K) + a(16 * K) + a(n) + a(8 * 256))
 
 

@@ -291,3 +291,86 @@ def test_config3_full_size_sampled():
 
 def test_config4_full_size_sampled():
     sampled_parity(synth.config4(), 2, 150, "config4 256x256 exhaustive")
+
+
+# ------------------------------------------------------------------------------------------------------------
+# batched launches: many images, one launch per phase; each image bit-identical to running alone
+# ------------------------------------------------------------------------------------------------------------
+
+def _batch_problems():
+    out = [synth.config2(seed=s, W=W, H=H) for s, (W, H) in enumerate([(96, 80), (150, 61), (64, 64), (33, 190)])]
+    for p in out:
+        p.mu0 = 300
+    return out
+
+
+@pytest.mark.parametrize("graph,workers", [(False, 0), (True, 0), (True, 16)])
+def test_batch_iterate_matches_alone_and_oracle(graph, workers):
+    from paper_1704_03116_amd.solver import Batch
+    probs = _batch_problems()
+    announce(f"batch of {len(probs)} images, graph={graph} workers={workers}")
+    ctxs = [make_ctx(p) for p in probs]
+    alone = [make_ctx(p) for p in probs]
+    with Batch(ctxs, graph=graph, workers=workers) as b:
+        for t in range(1, 6):
+            b.iterate(1)
+            for p, c, a in zip(probs, ctxs, alone):
+                a.iterate(1)
+                sc, sa = c.get_state(), a.get_state()
+                for x, y in zip(sc, sa):
+                    assert np.array_equal(np.asarray(x), np.asarray(y)), f"iteration {t}: batch != alone ({p.name})"
+        infos = b.info()
+        assert all(i["iters_done"] == 5 for i in infos)
+    for p, c in zip(probs, ctxs):
+        st_o, _, _, _ = od.run(p, n_iter=5)
+        Y, A, yh, mu, t = c.get_state()
+        assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+    for c in ctxs + alone:
+        c.close()
+
+
+def test_batch_solve_per_image_stopping():
+    """Images converge at different iterations; each stops alone and matches the oracle's own stopping point."""
+    from paper_1704_03116_amd.solver import Batch
+    probs = _batch_problems()
+    probs[1].max_iter = 3
+    probs[2].mu0 = 5000
+    announce("batch solve with per-image stopping")
+    ctxs = [make_ctx(p) for p in probs]
+    with Batch(ctxs, graph=True) as b:
+        b.solve()
+        infos = b.info()
+    for p, c, inf in zip(probs, ctxs, infos):
+        st_o, infos_o, _, dec = od.run(p)
+        assert inf["iters_done"] == len(infos_o), p.name
+        assert inf["converged"] == infos_o[-1].converged
+        Y, A, yh, mu, t = c.get_state()
+        assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+        assert np.array_equal(c.labels(), od.labels(st_o.Y))
+        c.close()
+
+
+def test_batch_exhaustive_nonsubmodular():
+    from paper_1704_03116_amd.solver import Batch
+    probs = [synth.config4(seed=s, size=sz) for s, sz in enumerate([24, 37, 16])]
+    announce("exhaustive batch")
+    ctxs = [make_ctx(p) for p in probs]
+    with Batch(ctxs, graph=True) as b:
+        b.iterate(3)
+    for p, c in zip(probs, ctxs):
+        st_o, _, _, _ = od.run(p, n_iter=3)
+        Y, A, yh, mu, t = c.get_state()
+        assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+        c.close()
+
+
+def test_batch_rejects_mixed_connectivity():
+    from paper_1704_03116_amd import _native as N
+    from paper_1704_03116_amd.solver import Batch
+    a = make_ctx(synth.config1(size=32))
+    b = make_ctx(synth.config2(W=40, H=40))
+    with pytest.raises(N.DopeError) as e:
+        Batch([a, b])
+    assert e.value.status == N.DOPE_EINVAL
+    a.close()
+    b.close()
