@@ -21,16 +21,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def workload(name):
+def workload(name, seed=0):
     import synth
     if name == "config2":
-        return synth.config2()
+        return synth.config2(seed=seed)
     if name == "config3":
-        return synth.config3()
+        return synth.config3(seed=seed)
     if name == "config1":
-        return synth.config1()
+        return synth.config1(seed=seed)
     if name == "config4":
-        return synth.config4()
+        return synth.config4(seed=seed)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -49,6 +49,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="config2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=16, help="images of the batched measurement (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only: the DOPE path here is a single-GPU "
@@ -57,7 +58,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_1704_03116_amd.solver import Dope
+    from paper_1704_03116_amd.solver import Batch, Dope
 
     torch.cuda.set_device(0)
     p = workload(args.workload)
@@ -68,7 +69,7 @@ def main():
     lab = torch.empty(p.n, dtype=torch.uint8, device="cuda")
 
     def step():
-        d.set_energy(u, w, p.lam_q8)
+        d.set_energy_async(u, w, p.lam_q8)
         info = d.solve()
         d.labels(lab)
         return info
@@ -88,12 +89,23 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = p.n * args.steps / elapsed / 1e6
 
-    K, tot, h = d.K, d.tot, d.h
-    bytes_per_launch = tot * (13 + 4 * h)
-    avg_ms = prof["solve_ms"] / max(prof["solve_launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    cons_avg_ms = prof["consensus_ms"] / max(prof["consensus_launches"], 1)
+    K, tot, h, n = d.K, d.tot, d.h, p.n
+    kernels = {
+        # per block pixel: u 4 + weights 4h + Y 4 + A 4 read, block label 1 written
+        "k_block_solve": (tot * (13 + 4 * h), prof["solve_ms"], prof["solve_launches"]),
+        # per block pixel: block label 1 + A 4 read, A 4 written; per pixel: weights 4h read, Y 4 written
+        "k_consensus+k_finalize": (tot * 9 + n * (4 * h + 4), prof["consensus_ms"], prof["consensus_launches"]),
+    }
 
+    def roof(name):
+        nbytes, ms, launches = kernels[name]
+        avg_ms = ms / max(launches, 1)
+        achieved = nbytes / (avg_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "avg_launch_ms": round(avg_ms, 5),
+                "launches": launches, "bytes_per_launch": int(nbytes), "total_ms": round(ms, 4)}
+
+    names = sorted(kernels, key=lambda k: -kernels[k][1])
     out = {
         "metric": "Mpixel/s to converged bit-exact labelling",
         "value": round(value, 3),
@@ -108,23 +120,55 @@ def main():
         "dtype": "i32",
         "data": "synthetic",
         "config": {
-            "workload": p.name, "grid": list(p.dims[:p.ndim]), "connectivity": p.conn, "block": list(p.block[:p.ndim]),
-            "overlap": list(p.overlap[:p.ndim]), "lambda_q8": p.lam_q8, "mu0": p.mu0, "eps_q16": p.eps_q16,
-            "max_iter": p.max_iter, "blocks": K, "iterations": info["iters_done"], "converged": info["converged"],
-            "solver": p.solver,
+            "workload": p.name, "path": "plain (one image per launch sequence)", "grid": list(p.dims[:p.ndim]),
+            "connectivity": p.conn, "block": list(p.block[:p.ndim]), "overlap": list(p.overlap[:p.ndim]),
+            "lambda_q8": p.lam_q8, "mu0": p.mu0, "eps_q16": p.eps_q16, "max_iter": p.max_iter, "blocks": K,
+            "iterations": info["iters_done"], "converged": info["converged"], "solver": p.solver,
         },
-        "roofline": {
-            "bound": "hbm", "kernel": "k_block_solve", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-            "avg_launch_ms": round(avg_ms, 5), "launches": prof["solve_launches"],
-            "bytes_per_launch": int(bytes_per_launch),
-            "consensus_avg_launch_ms": round(cons_avg_ms, 5),
-        },
+        "roofline": roof(names[0]),
+        "roofline_next": roof(names[1]),
         "workload_stats": {
             "free_nodes_frac_last_iter": round(float(stats[:, 0].sum()) / tot, 5),
             "pushrelabel_rounds_max": int(stats[:, 1].max()), "global_relabels_max": int(stats[:, 2].max()),
         },
     }
+    d.close()
+
+    if args.batch > 0:
+        probs = [workload(args.workload, seed=s) for s in range(args.batch)]
+        ctxs = [Dope.from_problem(q) for q in probs]
+        ins = [(torch.from_numpy(np.ascontiguousarray(q.u, np.int32)).cuda(),
+                torch.from_numpy(np.ascontiguousarray(q.w, np.int32)).cuda()) for q in probs]
+        labs = [torch.empty(q.n, dtype=torch.uint8, device="cuda") for q in probs]
+        for c, q, (uu, ww) in zip(ctxs, probs, ins):
+            c.set_energy(uu, ww, q.lam_q8)
+        b = Batch(ctxs, graph=True)
+
+        def bstep():
+            for c, q, (uu, ww) in zip(ctxs, probs, ins):
+                c.set_energy_async(uu, ww, q.lam_q8)
+            b.solve()
+            for c, lb in zip(ctxs, labs):
+                c.labels(lb)
+
+        for _ in range(args.warmup):
+            bstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bstep()
+        torch.cuda.synchronize()
+        bel = time.perf_counter() - t0
+        binfo = b.info()
+        bval = sum(q.n for q in probs) * args.steps / bel / 1e6
+        out["batched"] = {"images": args.batch, "value": round(bval, 3), "unit": "Mpixel/s",
+                          "ms_per_step": round(bel * 1e3 / args.steps, 4), "vs_plain": round(bval / value, 3),
+                          "graph": True, "seeds": f"0..{args.batch - 1}",
+                          "iterations": [i["iters_done"] for i in binfo]}
+        b.close()
+        for c in ctxs:
+            c.close()
+
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         el, st_o, infos, dec = cpu_baseline(p, threads)
@@ -137,7 +181,6 @@ def main():
                       f"{el:.2f} s",
         }
         out["labels_match_oracle"] = same
-    d.close()
     print(json.dumps(out), flush=True)
 
 

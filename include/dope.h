@@ -105,13 +105,21 @@ dope_status dope_create(const dope_params *p, dope_ctx **out);
  * large that per-node sum_j |c_ij| >= 2^29), ENOTSUBMODULAR (w < 0 with the max-flow solver). */
 dope_status dope_set_energy(dope_ctx *ctx, const int32_t *u, const int32_t *w, int32_t lambda_q8, int32_t mem_kind);
 
+/* Same as dope_set_energy but without waiting: the copies, state reset and weight preparation are only
+ * enqueued on the context stream (device inputs must stay valid until that work has run).  DOPE_SOLVER_AUTO
+ * resolves to max-flow when the block fits the LDS budget, else to the exhaustive solver.  Validation errors
+ * (EINVAL, ENOTSUBMODULAR) stop the loop on the device and are returned by the next call that reads the state
+ * back (dope_iterate, dope_solve, dope_get_state, a batch call, ...). */
+dope_status dope_set_energy_async(dope_ctx *ctx, const int32_t *u, const int32_t *w, int32_t lambda_q8,
+                                  int32_t mem_kind);
+
 /* Run exactly n_iter iterations of Algorithm 1's main loop (stops early only on EOVERFLOW / ESOLVER). */
 dope_status dope_iterate(dope_ctx *ctx, int32_t n_iter, dope_info *out);
 
 /* Run until the stopping rule holds or t reaches max_iter.  out may be NULL. */
 dope_status dope_solve(dope_ctx *ctx, dope_info *out);
 
-/* Labels l_i = [Y_i > 2^15] (uint8[n]) to host or device memory. */
+/* Labels l_i = [Y_i > 2^15] (uint8[n]) to host memory (waits) or device memory (stream-ordered, returns at once). */
 dope_status dope_labels(dope_ctx *ctx, uint8_t *labels, int32_t mem_kind);
 
 /* E_q = 256 sum u_i l_i + lambda_q8 sum_edges w_ij |l_i - l_j| of the current labels (exact int64). */

@@ -49,6 +49,7 @@ _DP = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "dope_create": (ctypes.c_int, [ctypes.POINTER(dope_params), ctypes.POINTER(_P)]),
     "dope_set_energy": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32]),
+    "dope_set_energy_async": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32]),
     "dope_iterate": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(dope_info)]),
     "dope_solve": (ctypes.c_int, [_P, ctypes.POINTER(dope_info)]),
     "dope_labels": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
@@ -117,6 +118,7 @@ def _fn(name):
 
 dope_create = _fn("dope_create")
 dope_set_energy = _fn("dope_set_energy")
+dope_set_energy_async = _fn("dope_set_energy_async")
 dope_iterate = _fn("dope_iterate")
 dope_solve = _fn("dope_solve")
 dope_labels = _fn("dope_labels")

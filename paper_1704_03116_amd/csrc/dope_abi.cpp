@@ -407,7 +407,13 @@ dope_status dope_bind_workspace(dope_ctx *c, void *dev_ptr, size_t bytes) {
     return upload_tables(c);
 }
 
-dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int32_t lambda_q8, int32_t mem_kind) {
+}  // extern "C"
+
+namespace {
+
+// Copies u and w, resets the state and enqueues the weight preparation and validation; no synchronisation.
+dope_status enqueue_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int32_t lambda_q8, int32_t mem_kind,
+                           int32_t allow_negative) {
     if (!c || !u || !w) return DOPE_EINVAL;
     if (lambda_q8 < 0) return fail(c, DOPE_EINVAL, "lambda must be >= 0");
     if (mem_kind != DOPE_MEM_HOST && mem_kind != DOPE_MEM_DEVICE) return fail(c, DOPE_EINVAL, "bad mem_kind");
@@ -421,10 +427,36 @@ dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int
     HIP_TRY(c, dope::launch_init_state(g, c->Y, c->A0, c->A1, c->yhat, c->resid, c->ctl, c->p.mu0, c->p.mu_fact_num,
                                        c->p.mu_fact_den, eps2, c->stream),
             "state init launch");
-    HIP_TRY(c, dope::launch_prep_weights(g, c->w, c->cw, lambda_q8, c->ctl, c->stream), "weight prep launch");
+    HIP_TRY(c, dope::launch_prep_weights(g, c->w, c->cw, lambda_q8, c->ctl, allow_negative, c->stream),
+            "weight prep launch");
+    return DOPE_OK;
+}
+
+const char *status_message(int32_t status, int32_t flags) {
+    switch (status) {
+        case DOPE_EOVERFLOW: return "fixed-point overflow (|Y| or |A| >= 2^22): mu too small";
+        case DOPE_ESOLVER: return "block max-flow exceeded its round limit";
+        case DOPE_ENOTSUBMODULAR: return "negative weight with the max-flow solver";
+        case DOPE_EINVAL:
+            return (flags & dope::FLAG_OFFGRID) ? "nonzero weight on an off-grid edge"
+                                                : "weights too large: per-node sum |c_ij| >= 2^29";
+        default: return "error";
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int32_t lambda_q8, int32_t mem_kind) {
+    if (!c) return DOPE_EINVAL;
+    c->energy_set = false;
+    dope_status st = enqueue_energy(c, u, w, lambda_q8, mem_kind, c->p.solver != DOPE_SOLVER_MAXFLOW);
+    if (st != DOPE_OK) return st;
+    c->dirty = false;
     st = sync_ctl(c);
     if (st != DOPE_OK) return st;
-    c->energy_set = false;
+    const Geom &g = c->g;
     const int32_t flags = c->hctl->flags;
     if (flags & dope::FLAG_OFFGRID) return fail(c, DOPE_EINVAL, "nonzero weight on an off-grid edge");
     if (flags & dope::FLAG_TOOBIG) return fail(c, DOPE_EINVAL, "weights too large: per-node sum |c_ij| >= 2^29");
@@ -445,6 +477,31 @@ dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int
     return DOPE_OK;
 }
 
+dope_status dope_set_energy_async(dope_ctx *c, const int32_t *u, const int32_t *w, int32_t lambda_q8,
+                                  int32_t mem_kind) {
+    if (!c) return DOPE_EINVAL;
+    int solver = c->p.solver;
+    if (solver == DOPE_SOLVER_AUTO)
+        solver = dope::maxflow_lds_bytes(c->g.max_np, c->g.hs) <= dope::LDS_LIMIT ? DOPE_SOLVER_MAXFLOW
+                                                                                  : DOPE_SOLVER_EXHAUSTIVE;
+    c->energy_set = false;
+    dope_status st = enqueue_energy(c, u, w, lambda_q8, mem_kind, solver == DOPE_SOLVER_EXHAUSTIVE);
+    if (st != DOPE_OK) return st;
+    // host mirror of the reset state; a validation failure shows up at the next readback
+    Ctl h{};
+    h.M = c->p.mu0;
+    h.eps2 = uint64_t(c->p.eps_q16) * uint64_t(c->p.eps_q16);
+    h.mu_num = c->p.mu_fact_num;
+    h.mu_den = c->p.mu_fact_den;
+    *c->hctl = h;
+    c->dirty = false;
+    c->solver = solver;
+    c->lam_q8 = lambda_q8;
+    c->energy_set = true;
+    c->err.clear();
+    return DOPE_OK;
+}
+
 dope_status dope_iterate(dope_ctx *c, int32_t n_iter, dope_info *out) {
     dope_status st = check_ready(c);
     if (st != DOPE_OK) return st;
@@ -457,11 +514,8 @@ dope_status dope_iterate(dope_ctx *c, int32_t n_iter, dope_info *out) {
     st = sync_ctl(c);
     if (st != DOPE_OK) return st;
     fill_info(c, out);
-    if (c->hctl->status != 0) {
-        return fail(c, dope_status(c->hctl->status),
-                    c->hctl->status == DOPE_EOVERFLOW ? "fixed-point overflow (|Y| or |A| >= 2^22): mu too small"
-                                                      : "block max-flow exceeded its round limit");
-    }
+    if (c->hctl->status != 0)
+        return fail(c, dope_status(c->hctl->status), status_message(c->hctl->status, c->hctl->flags));
     return DOPE_OK;
 }
 
@@ -481,11 +535,8 @@ dope_status dope_solve(dope_ctx *c, dope_info *out) {
         if (c->hctl->halted) break;
     }
     fill_info(c, out);
-    if (c->hctl->status != 0) {
-        return fail(c, dope_status(c->hctl->status),
-                    c->hctl->status == DOPE_EOVERFLOW ? "fixed-point overflow (|Y| or |A| >= 2^22): mu too small"
-                                                      : "block max-flow exceeded its round limit");
-    }
+    if (c->hctl->status != 0)
+        return fail(c, dope_status(c->hctl->status), status_message(c->hctl->status, c->hctl->flags));
     return DOPE_OK;
 }
 
@@ -495,8 +546,8 @@ dope_status dope_labels(dope_ctx *c, uint8_t *labels, int32_t mem_kind) {
     if (!labels) return fail(c, DOPE_EINVAL, "null labels");
     uint8_t *dst = mem_kind == DOPE_MEM_DEVICE ? labels : c->labels;
     HIP_TRY(c, dope::launch_labels(c->g, c->Y, dst, c->stream), "labels launch");
-    if (mem_kind != DOPE_MEM_DEVICE)
-        HIP_TRY(c, hipMemcpyAsync(labels, c->labels, size_t(c->g.n), hipMemcpyDeviceToHost, c->stream), "labels copy");
+    if (mem_kind == DOPE_MEM_DEVICE) return DOPE_OK;    // stream-ordered, no wait
+    HIP_TRY(c, hipMemcpyAsync(labels, c->labels, size_t(c->g.n), hipMemcpyDeviceToHost, c->stream), "labels copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
     return DOPE_OK;
 }

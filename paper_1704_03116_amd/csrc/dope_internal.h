@@ -123,8 +123,9 @@ hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params,
 hipError_t launch_solve_phase(const Group &grp, hipStream_t s);
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s);
 
+// c_ij from w and the validation verdict (status / halted set on the device when the energy is invalid).
 hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
-                               hipStream_t s);
+                               int32_t allow_negative, hipStream_t s);
 hipError_t launch_init_state(const Geom &g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid,
                              Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2, hipStream_t s);
 hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy,

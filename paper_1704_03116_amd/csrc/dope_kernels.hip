@@ -820,6 +820,20 @@ __global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict_
     if (flags) atomicOr(&ctl->flags, flags);
 }
 
+// Energy validation verdict after k_prep: off-grid or oversized weights -> EINVAL; a negative weight when the
+// resolved solver is max-flow -> ENOTSUBMODULAR.  Stops the loop before any iteration runs.
+__global__ void k_validate(Ctl *ctl, int32_t allow_negative) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int32_t f = ctl->flags;
+    int32_t st = 0;
+    if (f & (FLAG_OFFGRID | FLAG_TOOBIG)) st = -1;
+    else if ((f & FLAG_NEGATIVE) && !allow_negative) st = -4;
+    if (st) {
+        ctl->status = st;
+        ctl->halted = 1;
+    }
+}
+
 __global__ void k_init_state(Geom g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid, Ctl *ctl,
                              int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -955,13 +969,14 @@ hipError_t solve_phase(const Group &grp, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
-                               hipStream_t s) {
+                               int32_t allow_negative, hipStream_t s) {
     const dim3 grid(blocks_for(g.W, 256), unsigned(g.H) * unsigned(g.D));
     switch (g.conn) {
         case 4: hipLaunchKernelGGL(k_prep<4>, grid, dim3(256), 0, s, g, w, cw, lam_q8, ctl); break;
         case 8: hipLaunchKernelGGL(k_prep<8>, grid, dim3(256), 0, s, g, w, cw, lam_q8, ctl); break;
         default: hipLaunchKernelGGL(k_prep<6>, grid, dim3(256), 0, s, g, w, cw, lam_q8, ctl); break;
     }
+    hipLaunchKernelGGL(k_validate, dim3(1), dim3(64), 0, s, ctl, allow_negative);
     return hipGetLastError();
 }
 

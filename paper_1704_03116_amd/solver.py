@@ -97,6 +97,13 @@ class Dope:
             raise ValueError("u and w must live in the same memory")
         N.check(N.dope_set_energy(self.ctx, pu, pw, int(lambda_q8), ku), self.ctx)
 
+    def set_energy_async(self, u, w, lambda_q8):
+        pu, ku = _ptr(u)
+        pw, kw = _ptr(w)
+        if ku != kw:
+            raise ValueError("u and w must live in the same memory")
+        N.check(N.dope_set_energy_async(self.ctx, pu, pw, int(lambda_q8), ku), self.ctx)
+
     def iterate(self, n_iter=1):
         info = N.dope_info()
         N.check(N.dope_iterate(self.ctx, int(n_iter), ctypes.byref(info)), self.ctx)
@@ -194,6 +201,13 @@ class Batch:
     def _check(self, st):
         if st != N.DOPE_OK:
             raise N.DopeError(st, N.dope_batch_last_error(self.b).decode())
+
+    def set_energy_async(self, u, w, lambda_q8):
+        pu, ku = _ptr(u)
+        pw, kw = _ptr(w)
+        if ku != kw:
+            raise ValueError("u and w must live in the same memory")
+        N.check(N.dope_set_energy_async(self.ctx, pu, pw, int(lambda_q8), ku), self.ctx)
 
     def iterate(self, n_iter=1):
         self._check(N.dope_batch_iterate(self.b, int(n_iter)))

@@ -374,3 +374,26 @@ def test_batch_rejects_mixed_connectivity():
     assert e.value.status == N.DOPE_EINVAL
     a.close()
     b.close()
+
+
+def test_async_energy_upload_and_deferred_validation():
+    from paper_1704_03116_amd import _native as N
+    from paper_1704_03116_amd.solver import Dope
+    import torch
+    announce("asynchronous energy upload")
+    p = synth.config1()
+    d = Dope.from_problem(p)
+    d.set_energy_async(torch.from_numpy(np.ascontiguousarray(p.u)).cuda(),
+                       torch.from_numpy(np.ascontiguousarray(p.w)).cuda(), p.lam_q8)
+    d.iterate(4)
+    st_o, _, _, _ = od.run(p, n_iter=4)
+    Y, A, yh, mu, t = d.get_state()
+    assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+    d.close()
+    q = synth.random_problem(16, (20, 20, 1), 4, (8, 8, 1), (1, 1, 0), neg_frac=0.3)
+    with Dope.from_problem(q, solver="maxflow") as e:
+        e.set_energy_async(q.u, q.w, q.lam_q8)          # returns at once; the verdict comes with the next readback
+        with pytest.raises(N.DopeError) as err:
+            e.iterate(1)
+        assert err.value.status == N.DOPE_ENOTSUBMODULAR
+        assert e.get_state()[4] == 0                     # no iteration ran
