@@ -183,6 +183,42 @@ dope_status dope_batch_info(dope_batch *b, dope_info *infos);
 const char *dope_batch_last_error(const dope_batch *b);
 void dope_batch_destroy(dope_batch *b);
 
+/* ---- Serving: continuous batching of solve requests -----------------------------------------------------
+ * A server owns one device arena of hbm_budget bytes.  Submitted requests wait in arrival order; each call to
+ * dope_server_step admits waiting requests while their workspace (dope_workspace_bytes) fits in the free arena
+ * and fewer than max_active are admitted, runs ONE batched ADMM iteration for all admitted requests together
+ * (requests join and leave between iterations), and retires the requests that met their stopping rule, reached
+ * max_iter or failed, writing their labels.  Their ADMM state stays resident on the device between steps.
+ * Every request's result is the one it gets when solved alone.  All requests of a server share connectivity;
+ * the solver of each request resolves as in dope_set_energy_async.  A server is not thread-safe. */
+typedef struct dope_server dope_server;
+
+typedef struct {
+    size_t hbm_budget;         /* bytes of device memory for request workspaces                           */
+    int32_t max_active;        /* most requests admitted at once                                          */
+    int32_t pad;
+    void *stream;              /* hipStream_t; NULL = the server creates its own                          */
+} dope_server_params;
+
+dope_status dope_server_create(const dope_server_params *sp, dope_server **out);
+/* Queue one solve.  The server borrows u, w (layout as dope_set_energy, in mem_kind memory) and labels_out
+ * (uint8[n] in labels_mem_kind memory): they must stay valid until the request has finished.  p->stream is
+ * ignored.  Returns EBUSY when the request alone needs more than hbm_budget, EINVAL for bad parameters or a
+ * connectivity different from earlier requests.  *ticket identifies the request. */
+dope_status dope_server_submit(dope_server *s, const dope_params *p, const int32_t *u, const int32_t *w,
+                               int32_t lambda_q8, int32_t mem_kind, uint8_t *labels_out, int32_t labels_mem_kind,
+                               int64_t *ticket);
+/* One tick (admit, one batched iteration, retire).  The tickets finished during the tick are written to
+ * finished (at most max_finished; *n_finished receives their number).  Labels written to device memory are
+ * ordered on the server stream; to host memory they are complete on return. */
+dope_status dope_server_step(dope_server *s, int64_t *finished, int32_t max_finished, int32_t *n_finished);
+/* Loop information and status of a finished request (EINVAL for unknown or unfinished tickets). */
+dope_status dope_server_result(dope_server *s, int64_t ticket, dope_info *info, int32_t *status);
+/* Requests waiting and admitted, and arena bytes in use. */
+dope_status dope_server_load(const dope_server *s, int32_t *waiting, int32_t *active, size_t *hbm_in_use);
+const char *dope_server_last_error(const dope_server *s);
+void dope_server_destroy(dope_server *s);
+
 /* Context-local message of the last error; never NULL.  With ctx == NULL: the calling thread's last
  * dope_create validation message (empty when it succeeded). */
 const char *dope_last_error(const dope_ctx *ctx);

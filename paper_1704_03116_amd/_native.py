@@ -34,6 +34,11 @@ class dope_params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("solver", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
+class dope_server_params(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
 class dope_info(ctypes.Structure):
     _fields_ = [("iters_done", ctypes.c_int32), ("converged", ctypes.c_int32), ("max_resid2", ctypes.c_int64),
                 ("mu", ctypes.c_int64)]
@@ -73,6 +78,14 @@ SIGNATURES = {
     "dope_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(dope_info)]),
     "dope_batch_last_error": (ctypes.c_char_p, [_P]),
     "dope_batch_destroy": (None, [_P]),
+    "dope_server_create": (ctypes.c_int, [ctypes.POINTER(dope_server_params), ctypes.POINTER(_P)]),
+    "dope_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(dope_params), _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                          _P, ctypes.c_int32, _I64P]),
+    "dope_server_step": (ctypes.c_int, [_P, _I64P, ctypes.c_int32, _I32P]),
+    "dope_server_result": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(dope_info), _I32P]),
+    "dope_server_load": (ctypes.c_int, [_P, _I32P, _I32P, ctypes.POINTER(ctypes.c_size_t)]),
+    "dope_server_last_error": (ctypes.c_char_p, [_P]),
+    "dope_server_destroy": (None, [_P]),
     "dope_destroy": (None, [_P]),
 }
 
@@ -143,3 +156,10 @@ dope_batch_set_workers = _fn("dope_batch_set_workers")
 dope_batch_info = _fn("dope_batch_info")
 dope_batch_last_error = _fn("dope_batch_last_error")
 dope_batch_destroy = _fn("dope_batch_destroy")
+dope_server_create = _fn("dope_server_create")
+dope_server_submit = _fn("dope_server_submit")
+dope_server_step = _fn("dope_server_step")
+dope_server_result = _fn("dope_server_result")
+dope_server_load = _fn("dope_server_load")
+dope_server_last_error = _fn("dope_server_last_error")
+dope_server_destroy = _fn("dope_server_destroy")

@@ -7,7 +7,11 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -700,6 +704,7 @@ struct dope_batch {
     std::vector<dope_ctx *> ctxs;
     hipStream_t stream = nullptr;
     char *dbuf = nullptr;
+    size_t dcap = 0, hcap = 0;     // capacities of dbuf (bytes) and of the pinned arrays (images)
     dope::Img *imgs = nullptr;
     int32_t *dsum = nullptr, *dparams = nullptr;
     dope::Group grp{};
@@ -774,49 +779,72 @@ dope_status batch_status(dope_batch *b) {
 
 extern "C" {
 
-dope_status dope_batch_create(dope_ctx *const *ctxs, int32_t n, dope_batch **out) {
-    if (!ctxs || n <= 0 || !out) return DOPE_EINVAL;
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+void batch_drop_graph(dope_batch *b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->graph_ready = false;
+}
+
+// (Re)builds the batch's device arrays for ctxs, reusing its buffers when they are large enough.
+dope_status batch_bind(dope_batch *b, dope_ctx *const *ctxs, int32_t n) {
     int conn = 0, solver = 0;
     for (int32_t i = 0; i < n; ++i) {
         dope_ctx *c = ctxs[i];
-        if (!c) return DOPE_EINVAL;
+        if (!c) return bfail(b, DOPE_EINVAL, "null context");
         dope_status st = check_ready(c);
-        if (st != DOPE_OK) return st;
+        if (st != DOPE_OK) return bfail(b, st, c->err);
         if (i == 0) { conn = c->g.conn; solver = c->solver; }
-        if (c->g.conn != conn || c->solver != solver) return fail(c, DOPE_EINVAL, "batch members must share connectivity and solver");
+        if (c->g.conn != conn || c->solver != solver)
+            return bfail(b, DOPE_EINVAL, "batch members must share connectivity and solver");
     }
-    dope_batch *b = new (std::nothrow) dope_batch();
-    if (!b) return DOPE_ENOMEM;
-    b->ctxs.assign(ctxs, ctxs + n);
-    b->stream = ctxs[0]->stream;
-    // device buffer: descriptors, block items, chunk items, queue, summaries, parameters
     int64_t nblk = 0, nchk = 0;
     int32_t npmax = 0;
-    for (dope_ctx *c : b->ctxs) {
-        nblk += c->g.K;
-        nchk += int64_t(c->hchunk.size());
-        npmax = std::max(npmax, c->g.max_np);
+    for (int32_t i = 0; i < n; ++i) {
+        nblk += ctxs[i]->g.K;
+        nchk += int64_t(ctxs[i]->hchunk.size());
+        npmax = std::max(npmax, ctxs[i]->g.max_np);
     }
-    if (nblk >= (int64_t(1) << 31) || nchk >= (int64_t(1) << 31)) { delete b; return DOPE_EINVAL; }
+    if (nblk >= (int64_t(1) << 31) || nchk >= (int64_t(1) << 31)) return bfail(b, DOPE_EINVAL, "batch too large");
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
     const size_t o_img = take(size_t(n) * sizeof(dope::Img)), o_bi = take(size_t(nblk) * sizeof(dope::Item)),
                  o_ci = take(size_t(nchk) * sizeof(dope::Item)), o_q = take(sizeof(dope::Queue)),
                  o_sum = take(size_t(n) * 16), o_par = take(size_t(n) * 8);
-    void *ptr = nullptr;
-    if (hipMalloc(&ptr, o) != hipSuccess) { (void)hipGetLastError(); delete b; return DOPE_ENOMEM; }
-    b->dbuf = static_cast<char *>(ptr);
-    void *hs = nullptr, *hp = nullptr;
-    if (hipHostMalloc(&hs, size_t(n) * 16, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&hp, size_t(n) * 8, hipHostMallocDefault) != hipSuccess) {
-        if (hs) (void)hipHostFree(hs);
-        (void)hipFree(ptr);
-        delete b;
-        return DOPE_ENOMEM;
+    if (o > b->dcap) {
+        if (b->dbuf) (void)hipFree(b->dbuf);
+        b->dbuf = nullptr;
+        b->dcap = 0;
+        void *ptr = nullptr;
+        if (hipMalloc(&ptr, o + o / 2) != hipSuccess) {
+            (void)hipGetLastError();
+            return bfail(b, DOPE_ENOMEM, "batch buffer allocation failed");
+        }
+        b->dbuf = static_cast<char *>(ptr);
+        b->dcap = o + o / 2;
     }
-    b->hsum = static_cast<int32_t *>(hs);
-    b->hparams = static_cast<int32_t *>(hp);
+    if (size_t(n) > b->hcap) {
+        if (b->hsum) (void)hipHostFree(b->hsum);
+        if (b->hparams) (void)hipHostFree(b->hparams);
+        b->hsum = b->hparams = nullptr;
+        b->hcap = 0;
+        void *hs = nullptr, *hp = nullptr;
+        const size_t cap = size_t(n) + size_t(n) / 2;
+        if (hipHostMalloc(&hs, cap * 16, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&hp, cap * 8, hipHostMallocDefault) != hipSuccess) {
+            if (hs) (void)hipHostFree(hs);
+            return bfail(b, DOPE_ENOMEM, "pinned host allocation failed");
+        }
+        b->hsum = static_cast<int32_t *>(hs);
+        b->hparams = static_cast<int32_t *>(hp);
+        b->hcap = cap;
+    }
+    b->ctxs.assign(ctxs, ctxs + n);
     b->imgs = reinterpret_cast<dope::Img *>(b->dbuf + o_img);
     auto *bi = reinterpret_cast<dope::Item *>(b->dbuf + o_bi);
     auto *ci = reinterpret_cast<dope::Item *>(b->dbuf + o_ci);
@@ -828,7 +856,7 @@ dope_status dope_batch_create(dope_ctx *const *ctxs, int32_t n, dope_batch **out
     hbi.reserve(size_t(nblk));
     hci.reserve(size_t(nchk));
     for (int32_t i = 0; i < n; ++i) {
-        dope_ctx *c = b->ctxs[size_t(i)];
+        dope_ctx *c = ctxs[i];
         himg[size_t(i)] = host_img(c);
         himg[size_t(i)].summary = b->dsum + 4 * i;
         for (int32_t k = 0; k < c->g.K; ++k) hbi.push_back(dope::Item{i, k});
@@ -839,17 +867,39 @@ dope_status dope_batch_create(dope_ctx *const *ctxs, int32_t n, dope_batch **out
         b->hsum[4 * i + 3] = c->hctl->status;
     }
     const dope::Queue hq{};
-    hipError_t e = hipMemcpyAsync(b->imgs, himg.data(), himg.size() * sizeof(dope::Img), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(bi, hbi.data(), hbi.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ci, hci.data(), hci.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(q, &hq, sizeof(hq), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->dsum, b->hsum, size_t(n) * 16, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
+    BHIP_TRY(b, hipMemcpyAsync(b->imgs, himg.data(), himg.size() * sizeof(dope::Img), hipMemcpyHostToDevice, b->stream),
+             "descriptor upload");
+    BHIP_TRY(b, hipMemcpyAsync(bi, hbi.data(), hbi.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream),
+             "item upload");
+    BHIP_TRY(b, hipMemcpyAsync(ci, hci.data(), hci.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream),
+             "item upload");
+    BHIP_TRY(b, hipMemcpyAsync(q, &hq, sizeof(hq), hipMemcpyHostToDevice, b->stream), "queue upload");
+    BHIP_TRY(b, hipMemcpyAsync(b->dsum, b->hsum, size_t(n) * 16, hipMemcpyHostToDevice, b->stream), "summary upload");
+    BHIP_TRY(b, hipStreamSynchronize(b->stream), "stream synchronize");
+    const int32_t workers = b->grp.n_workers;
+    b->grp = dope::Group{b->imgs, n, bi, int32_t(nblk), ci, int32_t(nchk), q, conn, solver, npmax, workers};
+    batch_drop_graph(b);
+    return DOPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dope_status dope_batch_create(dope_ctx *const *ctxs, int32_t n, dope_batch **out) {
+    if (!ctxs || n <= 0 || !out) return DOPE_EINVAL;
+    *out = nullptr;
+    for (int32_t i = 0; i < n; ++i)
+        if (!ctxs[i]) return DOPE_EINVAL;
+    dope_batch *b = new (std::nothrow) dope_batch();
+    if (!b) return DOPE_ENOMEM;
+    b->stream = ctxs[0]->stream;
+    const dope_status st = batch_bind(b, ctxs, n);
+    if (st != DOPE_OK) {
+        ctxs[0]->err = b->err;
         dope_batch_destroy(b);
-        return DOPE_EDEVICE;
+        return st;
     }
-    b->grp = dope::Group{b->imgs, n, bi, int32_t(nblk), ci, int32_t(nchk), q, conn, solver, npmax, 0};
     *out = b;
     return DOPE_OK;
 }
@@ -907,13 +957,7 @@ dope_status dope_batch_set_graph(dope_batch *b, int32_t on) {
 dope_status dope_batch_set_workers(dope_batch *b, int32_t nw) {
     if (!b || nw < 0) return DOPE_EINVAL;
     b->grp.n_workers = nw;
-    if (b->graph_ready) {   // the captured launch has the old grid
-        (void)hipGraphExecDestroy(b->gexec);
-        (void)hipGraphDestroy(b->graph);
-        b->gexec = nullptr;
-        b->graph = nullptr;
-        b->graph_ready = false;
-    }
+    batch_drop_graph(b);   // the captured launch has the old grid
     return DOPE_OK;
 }
 
@@ -940,6 +984,261 @@ void dope_batch_destroy(dope_batch *b) {
     if (b->hsum) (void)hipHostFree(b->hsum);
     if (b->hparams) (void)hipHostFree(b->hparams);
     delete b;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------------------
+// Serving: FIFO admission by HBM footprint into one arena, one batched iteration per tick
+// ------------------------------------------------------------------------------------------------------------
+
+namespace {
+
+struct SrvReq {
+    int64_t ticket = 0;
+    dope_params p{};
+    const int32_t *u = nullptr, *w = nullptr;
+    int32_t lam = 0, mem = 0;
+    uint8_t *lab = nullptr;
+    int32_t lab_mem = 0;
+    size_t bytes = 0, off = 0;
+    dope_ctx *ctx = nullptr;
+    dope_info info{};
+    int32_t status = 0;
+    bool finished = false;
+};
+
+}  // namespace
+
+struct dope_server {
+    size_t budget = 0;
+    int32_t max_active = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *arena = nullptr;
+    std::map<size_t, size_t> free_blocks;   // offset -> size
+    size_t in_use = 0;
+    std::deque<SrvReq *> waiting;
+    std::vector<SrvReq *> active;
+    std::unordered_map<int64_t, std::unique_ptr<SrvReq>> reqs;
+    dope_batch *batch = nullptr;
+    bool dirty = true;
+    int64_t next_ticket = 1;
+    int32_t conn = 0;
+    std::string err;
+};
+
+namespace {
+
+dope_status sfail(dope_server *s, dope_status st, const std::string &msg) {
+    if (s) s->err = msg;
+    return st;
+}
+
+bool arena_alloc(dope_server *s, size_t bytes, size_t *off) {
+    for (auto it = s->free_blocks.begin(); it != s->free_blocks.end(); ++it) {
+        if (it->second < bytes) continue;
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t at = it->first + bytes;
+        s->free_blocks.erase(it);
+        if (rest) s->free_blocks[at] = rest;
+        s->in_use += bytes;
+        return true;
+    }
+    return false;
+}
+
+void arena_free(dope_server *s, size_t off, size_t bytes) {
+    s->in_use -= bytes;
+    auto it = s->free_blocks.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != s->free_blocks.end() && it->first + it->second == next->first) {
+        it->second += next->second;
+        s->free_blocks.erase(next);
+    }
+    if (it != s->free_blocks.begin()) {
+        auto prev = std::prev(it);
+        if (prev->first + prev->second == it->first) {
+            prev->second += it->second;
+            s->free_blocks.erase(it);
+        }
+    }
+}
+
+// Retire one admitted request: labels, final info, context and arena space released.
+void srv_retire(dope_server *s, SrvReq *r, int32_t status) {
+    dope_ctx *c = r->ctx;
+    if (status == 0) (void)dope_labels(c, r->lab, r->lab_mem);
+    c->dirty = false;
+    if (sync_ctl(c) == DOPE_OK) fill_info(c, &r->info);
+    r->status = status;
+    r->finished = true;
+    dope_destroy(c);
+    r->ctx = nullptr;
+    arena_free(s, r->off, r->bytes);
+}
+
+}  // namespace
+
+extern "C" {
+
+dope_status dope_server_create(const dope_server_params *sp, dope_server **out) {
+    if (!sp || !out || sp->hbm_budget == 0 || sp->max_active <= 0) return DOPE_EINVAL;
+    *out = nullptr;
+    dope_server *s = new (std::nothrow) dope_server();
+    if (!s) return DOPE_ENOMEM;
+    s->budget = sp->hbm_budget & ~size_t(255);
+    s->max_active = sp->max_active;
+    if (sp->stream) {
+        s->stream = static_cast<hipStream_t>(sp->stream);
+    } else {
+        if (hipStreamCreate(&s->stream) != hipSuccess) { delete s; return DOPE_EDEVICE; }
+        s->own_stream = true;
+    }
+    void *ptr = nullptr;
+    if (hipMalloc(&ptr, s->budget) != hipSuccess) {
+        (void)hipGetLastError();
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        return DOPE_ENOMEM;
+    }
+    s->arena = static_cast<char *>(ptr);
+    s->free_blocks[0] = s->budget;
+    s->batch = new (std::nothrow) dope_batch();
+    if (!s->batch) { dope_server_destroy(s); return DOPE_ENOMEM; }
+    s->batch->stream = s->stream;
+    *out = s;
+    return DOPE_OK;
+}
+
+dope_status dope_server_submit(dope_server *s, const dope_params *p, const int32_t *u, const int32_t *w,
+                               int32_t lambda_q8, int32_t mem_kind, uint8_t *labels_out, int32_t labels_mem_kind,
+                               int64_t *ticket) {
+    if (!s || !p || !u || !w || !labels_out || !ticket) return DOPE_EINVAL;
+    dope_params q = *p;
+    q.stream = s->stream;
+    const size_t bytes = dope_workspace_bytes(&q);
+    if (bytes == 0) return sfail(s, DOPE_EINVAL, "invalid request parameters");
+    if (s->conn == 0) s->conn = q.connectivity;
+    if (q.connectivity != s->conn) return sfail(s, DOPE_EINVAL, "requests of a server must share connectivity");
+    const size_t need = align256(bytes);
+    if (need > s->budget) return sfail(s, DOPE_EBUSY, "request workspace exceeds the HBM budget");
+    auto r = std::make_unique<SrvReq>();
+    r->ticket = s->next_ticket++;
+    r->p = q;
+    r->u = u;
+    r->w = w;
+    r->lam = lambda_q8;
+    r->mem = mem_kind;
+    r->lab = labels_out;
+    r->lab_mem = labels_mem_kind;
+    r->bytes = need;
+    *ticket = r->ticket;
+    s->waiting.push_back(r.get());
+    s->reqs.emplace(r->ticket, std::move(r));
+    return DOPE_OK;
+}
+
+dope_status dope_server_step(dope_server *s, int64_t *finished, int32_t max_finished, int32_t *n_finished) {
+    if (!s) return DOPE_EINVAL;
+    int32_t nf = 0;
+    auto report = [&](int64_t t) {
+        if (finished && nf < max_finished) finished[nf] = t;
+        ++nf;
+    };
+    // admission: arrival order while the arena and the slot count allow
+    while (!s->waiting.empty() && int32_t(s->active.size()) < s->max_active) {
+        SrvReq *r = s->waiting.front();
+        size_t off = 0;
+        if (!arena_alloc(s, r->bytes, &off)) break;
+        s->waiting.pop_front();
+        dope_ctx *c = nullptr;
+        dope_status st = dope_create(&r->p, &c);
+        if (st == DOPE_OK) st = dope_bind_workspace(c, s->arena + off, r->bytes);
+        if (st == DOPE_OK) st = dope_set_energy_async(c, r->u, r->w, r->lam, r->mem);
+        if (st != DOPE_OK) {
+            if (c) dope_destroy(c);
+            arena_free(s, off, r->bytes);
+            r->status = st;
+            r->finished = true;
+            report(r->ticket);
+            continue;
+        }
+        r->ctx = c;
+        r->off = off;
+        s->active.push_back(r);
+        s->dirty = true;
+    }
+    if (s->active.empty()) {
+        if (n_finished) *n_finished = nf;
+        return DOPE_OK;
+    }
+    dope_batch *b = s->batch;
+    if (s->dirty) {
+        std::vector<dope_ctx *> cs;
+        cs.reserve(s->active.size());
+        for (SrvReq *r : s->active) cs.push_back(r->ctx);
+        dope_status st = batch_bind(b, cs.data(), int32_t(cs.size()));
+        if (st != DOPE_OK) return sfail(s, st, b->err);
+        for (size_t i = 0; i < cs.size(); ++i) {
+            b->hparams[2 * i] = cs[i]->p.max_iter;
+            b->hparams[2 * i + 1] = 1;
+        }
+        st = batch_setup(b);
+        if (st != DOPE_OK) return sfail(s, st, b->err);
+        s->dirty = false;
+    }
+    dope_status st = batch_run_iteration(b);
+    if (st == DOPE_OK) st = batch_sync(b);
+    if (st != DOPE_OK) return sfail(s, st, b->err);
+    // retire
+    std::vector<SrvReq *> keep;
+    keep.reserve(s->active.size());
+    for (size_t i = 0; i < s->active.size(); ++i) {
+        SrvReq *r = s->active[i];
+        const int32_t t = b->hsum[4 * i], halted = b->hsum[4 * i + 1], status = b->hsum[4 * i + 3];
+        if (halted || t >= r->p.max_iter) {
+            srv_retire(s, r, status);
+            report(r->ticket);
+            s->dirty = true;
+        } else {
+            keep.push_back(r);
+        }
+    }
+    s->active.swap(keep);
+    if (n_finished) *n_finished = nf;
+    return DOPE_OK;
+}
+
+dope_status dope_server_result(dope_server *s, int64_t ticket, dope_info *info, int32_t *status) {
+    if (!s) return DOPE_EINVAL;
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end() || !it->second->finished) return sfail(s, DOPE_EINVAL, "unknown or unfinished ticket");
+    if (info) *info = it->second->info;
+    if (status) *status = it->second->status;
+    return DOPE_OK;
+}
+
+dope_status dope_server_load(const dope_server *s, int32_t *waiting, int32_t *active, size_t *hbm_in_use) {
+    if (!s) return DOPE_EINVAL;
+    if (waiting) *waiting = int32_t(s->waiting.size());
+    if (active) *active = int32_t(s->active.size());
+    if (hbm_in_use) *hbm_in_use = s->in_use;
+    return DOPE_OK;
+}
+
+const char *dope_server_last_error(const dope_server *s) { return s ? s->err.c_str() : ""; }
+
+void dope_server_destroy(dope_server *s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (SrvReq *r : s->active)
+        if (r->ctx) dope_destroy(r->ctx);
+    if (s->batch) dope_batch_destroy(s->batch);
+    if (s->arena) (void)hipFree(s->arena);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
 }
 
 }  // extern "C"

@@ -19,6 +19,31 @@ def _ptr(a):
     return ctypes.c_void_p(a.data_ptr()), (N.DOPE_MEM_DEVICE if a.is_cuda else N.DOPE_MEM_HOST)
 
 
+def make_params(dims, connectivity, block, overlap, mu0, *, ndim=None, mu_fact=(21, 20), eps_q16=6554,
+                max_iter=50, solver="auto"):
+    p = N.dope_params()
+    dims = tuple(int(d) for d in dims) + (1,) * (3 - len(dims))
+    p.ndim = ndim if ndim is not None else (3 if connectivity == 6 else 2)
+    p.dims[:] = dims
+    p.connectivity = int(connectivity)
+    p.block[:] = tuple(int(b) for b in block) + (1,) * (3 - len(block))
+    p.overlap[:] = tuple(int(o) for o in overlap) + (0,) * (3 - len(overlap))
+    p.mu0 = int(mu0)
+    p.mu_fact_num, p.mu_fact_den = int(mu_fact[0]), int(mu_fact[1])
+    p.eps_q16 = int(eps_q16)
+    p.max_iter = int(max_iter)
+    p.solver = {"auto": N.DOPE_SOLVER_AUTO, "maxflow": N.DOPE_SOLVER_MAXFLOW,
+                "exhaustive": N.DOPE_SOLVER_EXHAUSTIVE}[solver]
+    return p
+
+
+def params_from_problem(prob, block=None, overlap=None):
+    return make_params(prob.dims, prob.conn, block if block is not None else prob.block,
+                       overlap if overlap is not None else prob.overlap, prob.mu0, ndim=prob.ndim,
+                       mu_fact=(prob.mu_num, prob.mu_den), eps_q16=prob.eps_q16, max_iter=prob.max_iter,
+                       solver=prob.solver)
+
+
 class Dope:
     """One DOPE solve context (see include/dope.h)."""
 
@@ -227,6 +252,74 @@ class Batch:
         if getattr(self, "b", None):
             N.dope_batch_destroy(self.b)
             self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A dope_server: FIFO admission by HBM footprint, one batched iteration per step()."""
+
+    def __init__(self, hbm_budget, max_active):
+        sp = N.dope_server_params()
+        sp.hbm_budget = int(hbm_budget)
+        sp.max_active = int(max_active)
+        sp.stream = None
+        s = ctypes.c_void_p()
+        st = N.dope_server_create(ctypes.byref(sp), ctypes.byref(s))
+        if st != N.DOPE_OK:
+            raise N.DopeError(st, "dope_server_create failed")
+        self.s = s
+        self._held = {}   # ticket -> borrowed buffers kept alive until the request finishes
+
+    def _check(self, st):
+        if st != N.DOPE_OK:
+            raise N.DopeError(st, N.dope_server_last_error(self.s).decode())
+
+    def submit(self, params, u, w, lambda_q8, labels_out):
+        pu, ku = _ptr(u)
+        pw, kw = _ptr(w)
+        pl, kl = _ptr(labels_out)
+        t = ctypes.c_int64()
+        self._check(N.dope_server_submit(self.s, ctypes.byref(params), pu, pw, int(lambda_q8), ku, pl, kl,
+                                         ctypes.byref(t)))
+        self._held[t.value] = (u, w, labels_out)
+        return t.value
+
+    def step(self, max_finished=4096):
+        buf = (ctypes.c_int64 * max_finished)()
+        nf = ctypes.c_int32()
+        self._check(N.dope_server_step(self.s, buf, max_finished, ctypes.byref(nf)))
+        done = [buf[i] for i in range(min(nf.value, max_finished))]
+        for t in done:
+            self._held.pop(t, None)
+        return done
+
+    def result(self, ticket):
+        info = N.dope_info()
+        st = ctypes.c_int32()
+        self._check(N.dope_server_result(self.s, int(ticket), ctypes.byref(info), ctypes.byref(st)))
+        return st.value, _info(info)
+
+    def load(self):
+        w, a = ctypes.c_int32(), ctypes.c_int32()
+        used = ctypes.c_size_t()
+        self._check(N.dope_server_load(self.s, ctypes.byref(w), ctypes.byref(a), ctypes.byref(used)))
+        return w.value, a.value, used.value
+
+    def close(self):
+        if getattr(self, "s", None):
+            N.dope_server_destroy(self.s)
+            self.s = None
 
     def __enter__(self):
         return self

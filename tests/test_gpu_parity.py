@@ -397,3 +397,89 @@ def test_async_energy_upload_and_deferred_validation():
             e.iterate(1)
         assert err.value.status == N.DOPE_ENOTSUBMODULAR
         assert e.get_state()[4] == 0                     # no iteration ran
+
+
+# ------------------------------------------------------------------------------------------------------------
+# serving: continuous batching; every request equals its solve alone; admission within the HBM budget
+# ------------------------------------------------------------------------------------------------------------
+
+def _serve_requests():
+    reqs = []
+    for r, (W, H, B) in enumerate([(70, 50, 16), (40, 90, 16), (128, 96, 32), (33, 33, 16), (150, 40, 32),
+                                   (64, 64, 16), (96, 120, 32), (48, 48, 16)]):
+        p = synth.config2(seed=40 + r, W=W, H=H)
+        p.block, p.overlap = (B, B, 1), ((2, 2, 0) if B == 32 else (1, 1, 0))
+        p.mu0 = 250
+        p.max_iter = 12
+        reqs.append(p)
+    return reqs
+
+
+def test_serving_mix_equals_alone():
+    import torch
+    from paper_1704_03116_amd.solver import Server, params_from_problem
+    reqs = _serve_requests()
+    announce(f"serving {len(reqs)} requests, staggered submission")
+    outs = [torch.zeros(p.n, dtype=torch.uint8, device="cuda") for p in reqs]
+    ins = [(torch.from_numpy(np.ascontiguousarray(p.u)).cuda(), torch.from_numpy(np.ascontiguousarray(p.w)).cuda())
+           for p in reqs]
+    torch.cuda.synchronize()
+    done, tickets = {}, {}
+    with Server(hbm_budget=64 << 20, max_active=5) as srv:
+        nxt = 0
+        for tick in range(200):
+            if nxt < len(reqs) and tick % 2 == 0:            # a request arrives every other tick
+                p = reqs[nxt]
+                tickets[srv.submit(params_from_problem(p), ins[nxt][0], ins[nxt][1], p.lam_q8, outs[nxt])] = nxt
+                nxt += 1
+            for t in srv.step():
+                done[tickets[t]] = srv.result(t)
+            waiting, active, used = srv.load()
+            assert active <= 5 and used <= 64 << 20
+            if len(done) == len(reqs):
+                break
+    torch.cuda.synchronize()
+    assert len(done) == len(reqs)
+    for i, p in enumerate(reqs):
+        status, info = done[i]
+        assert status == 0
+        d = make_ctx(p)
+        alone = d.solve()
+        assert info["iters_done"] == alone["iters_done"] and info["converged"] == alone["converged"], p.name
+        assert np.array_equal(outs[i].cpu().numpy(), d.labels()), f"request {i}: served labels differ from alone"
+        d.close()
+    # and against the oracle for two of them
+    for i in (0, 2):
+        st_o, infos, _, _ = od.run(reqs[i])
+        assert np.array_equal(outs[i].cpu().numpy(), od.labels(st_o.Y))
+
+
+def test_serving_admission_budget_and_busy():
+    import torch
+    from paper_1704_03116_amd import _native as N
+    from paper_1704_03116_amd.solver import Server, params_from_problem
+    from paper_1704_03116_amd._native import dope_workspace_bytes
+    import ctypes
+    reqs = _serve_requests()[:6]
+    need = [dope_workspace_bytes(ctypes.byref(params_from_problem(p))) for p in reqs]
+    budget = (sorted(need)[-1] + sorted(need)[-2] + 1024) // 256 * 256 + 512
+    announce(f"serving with a budget of {budget} bytes")
+    outs = [torch.zeros(p.n, dtype=torch.uint8, device="cuda") for p in reqs]
+    with Server(hbm_budget=budget, max_active=16) as srv:
+        tk = {}
+        for i, p in enumerate(reqs):
+            tk[srv.submit(params_from_problem(p), np.ascontiguousarray(p.u), np.ascontiguousarray(p.w), p.lam_q8,
+                          outs[i])] = i
+        big = synth.config2(W=900, H=900)
+        with pytest.raises(N.DopeError) as e:
+            srv.submit(params_from_problem(big), np.ascontiguousarray(big.u), np.ascontiguousarray(big.w),
+                       big.lam_q8, torch.zeros(big.n, dtype=torch.uint8, device="cuda"))
+        assert e.value.status == N.DOPE_EBUSY
+        finished = 0
+        for _ in range(400):
+            finished += len(srv.step())
+            waiting, active, used = srv.load()
+            assert used <= budget
+            if finished == len(reqs):
+                break
+        assert finished == len(reqs)
