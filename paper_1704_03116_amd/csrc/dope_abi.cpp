@@ -390,6 +390,23 @@ dope_status dope_create(const dope_params *p, dope_ctx **out) {
     return DOPE_OK;
 }
 
+dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectivity, int32_t block[3],
+                          int32_t overlap[3]) {
+    if (!dims || !block || !overlap) return DOPE_EINVAL;
+    if (!half_stencil_size(ndim, connectivity)) return DOPE_EINVAL;
+    if (ndim == 3) {
+        for (int a = 0; a < 3; ++a) { block[a] = 16; overlap[a] = 1; }
+        return DOPE_OK;
+    }
+    const int32_t short_side = std::min(dims[0], dims[1]);
+    const int32_t B = short_side <= 256 ? 16 : 32;
+    block[0] = block[1] = B;
+    overlap[0] = overlap[1] = 1;
+    block[2] = 1;
+    overlap[2] = 0;
+    return DOPE_OK;
+}
+
 size_t dope_workspace_bytes(const dope_params *p) {
     Geom g{};
     if (!p) return 0;

@@ -67,8 +67,9 @@ constexpr int64_t CAP_SUM_LIMIT = int64_t(1) << 29;
 constexpr int BTAB_STRIDE = 8;     // x0, y0, z0, ex, ey, ez, offset, pad
 
 // LDS bytes of the max-flow block kernel for a block of np pixels and half-stencil size hs.
-inline size_t maxflow_lds_bytes(int np, int hs) { return 64 + size_t(np) * (8 * hs + 8); }
+inline size_t maxflow_lds_bytes(int np, int hs) { return 64 + size_t(np) * (8 * hs + 10); }
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
+constexpr int NUM_CUS = 256;          // MI355X compute units
 
 // Device lookup tables built on the host with the partition.
 struct Tables {

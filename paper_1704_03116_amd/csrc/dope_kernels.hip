@@ -16,7 +16,7 @@ namespace dope {
 
 namespace {
 
-enum : uint8_t { ST_FIXED = 1, ST_LABEL = 2, ST_NEW = 4, ST_MARK = 8 };
+enum : uint8_t { ST_FIXED = 1, ST_LABEL = 2, ST_MARK = 8 };
 constexpr int16_t H_INF = 0x7FFF;
 
 template <int CONN> struct Sten;
@@ -156,15 +156,241 @@ __device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__r
 // Max-flow block solve
 // ------------------------------------------------------------------------------------------------------------
 
+// Synchronisation of one phase of the flow computation over the free-node list.  BlockSync: the whole
+// workgroup takes part (barriers, one per OR-reduction thanks to three rotating flag slots in LDS).  WaveSync: a
+// single wavefront does the work with wave-scope fences and ballots, so no workgroup barrier is paid per pass.
+struct BlockSync {
+    int idx, step;
+    int *slots;
+    int phase;
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+    __device__ __forceinline__ bool any(bool f) {
+        int *sl = slots + phase;
+        if (f) *sl = 1;
+        __syncthreads();
+        const bool r = *sl != 0;
+        if (threadIdx.x == 0) slots[(phase + 2) % 3] = 0;   // the slot of the call after next
+        phase = (phase + 1) % 3;
+        return r;
+    }
+};
+
+struct WaveSync {
+    int idx, step;
+    __device__ __forceinline__ void sync() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __device__ __forceinline__ bool any(bool f) {
+        sync();
+        return __any(f ? 1 : 0) != 0;
+    }
+};
+
+// LDS-resident block graph (see maxflow_lds_bytes).
+template <int CONN>
+struct BlockLds {
+    static constexpr int H = Sten<CONN>::H;
+    int32_t *cap;      // [H][npmax] capacity of the half-edge p -> p + off_o (0 when absent)
+    int32_t *flw;      // [H][npmax] flow on that half-edge
+    int32_t *dd;       // unary during elimination, then excess minus sink residual
+    int16_t *hh;       // heights
+    int16_t *lst;      // free nodes after the prologue's forcing test
+    uint8_t *msk;      // live in-block directions
+    uint8_t *st;       // ST_* bits
+    int npmax;
+    int loff[H];
+
+    __device__ __forceinline__ int nbr(int p, int d) const { return d < H ? p + loff[d] : p - loff[d - H]; }
+    __device__ __forceinline__ int32_t capd(int p, int d) const {
+        return d < H ? cap[d * npmax + p] : cap[(d - H) * npmax + p - loff[d - H]];
+    }
+    // residual of the arc p -> nbr(p, d)
+    __device__ __forceinline__ int32_t res(int p, int d) const {
+        if (d < H) return cap[d * npmax + p] - flw[d * npmax + p];
+        const int v = p - loff[d - H];
+        return cap[(d - H) * npmax + v] + flw[(d - H) * npmax + v];
+    }
+    // residual of the arc nbr(p, d) -> p
+    __device__ __forceinline__ int32_t res_in(int p, int d) const {
+        if (d < H) return cap[d * npmax + p] + flw[d * npmax + p];
+        const int v = p - loff[d - H];
+        return cap[(d - H) * npmax + v] - flw[(d - H) * npmax + v];
+    }
+    __device__ __forceinline__ void push(int p, int d, int32_t delta) {
+        if (d < H) flw[d * npmax + p] += delta;
+        else flw[(d - H) * npmax + p - loff[d - H]] -= delta;
+    }
+};
+
+struct FlowStats {
+    int rounds, grel, casc;
+    bool fail;
+};
+
+// Everything after the prologue for the nfree nodes of lst: elimination of the nodes that the reduced problem
+// forces, push-relabel to a max preflow, and the canonical cut (ST_MARK = label 1).
+template <int CONN, class Sync>
+__device__ void flow_on_list(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t round_limit, int32_t relabel_period,
+                             FlowStats &fs) {
+    constexpr int ND = 2 * Sten<CONN>::H;
+    // (1) a node is forced when its unary, with the pairwise terms of its fixed neighbours folded in, exceeds the
+    //     total capacity towards its free neighbours.  Forcing only grows as neighbours get fixed, so passes may
+    //     see each other's updates in any order and still reach the same fixed point.
+    for (;;) {
+        bool ch = false;
+        for (int i = sy.idx; i < nfree; i += sy.step) {
+            const int p = L.lst[i];
+            if (L.st[p] & ST_FIXED) continue;
+            const unsigned m = L.msk[p];
+            int32_t U = L.dd[p], S = 0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+                if ((m >> d) & 1u) {
+                    const uint8_t sv = L.st[L.nbr(p, d)];
+                    const int32_t c = L.capd(p, d);
+                    if (sv & ST_FIXED) U += (sv & ST_LABEL) ? -c : c;
+                    else S += c;
+                }
+            if (U < -S) { L.st[p] = ST_FIXED | ST_LABEL; ch = true; }
+            else if (U > S) { L.st[p] = ST_FIXED; ch = true; }
+        }
+        ++fs.casc;
+        if (!sy.any(ch)) break;
+    }
+    // (2) flow network of the remaining free nodes: source excess -U and sink capacity U in one signed value
+    for (int i = sy.idx; i < nfree; i += sy.step) {
+        const int p = L.lst[i];
+        if (L.st[p] & ST_FIXED) continue;
+        const unsigned m = L.msk[p];
+        unsigned live = 0;
+        int32_t U = L.dd[p];
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+            if ((m >> d) & 1u) {
+                const uint8_t sv = L.st[L.nbr(p, d)];
+                if (sv & ST_FIXED) U += (sv & ST_LABEL) ? -L.capd(p, d) : L.capd(p, d);
+                else live |= 1u << d;
+            }
+        L.msk[p] = uint8_t(live);
+        L.dd[p] = -U;
+    }
+    sy.sync();
+    // (3) push-relabel with periodic global relabelling (exact distances to the sink by monotone relaxation)
+    for (;;) {
+        for (int i = sy.idx; i < nfree; i += sy.step) {
+            const int p = L.lst[i];
+            if (!(L.st[p] & ST_FIXED)) L.hh[p] = L.dd[p] < 0 ? 1 : H_INF;
+        }
+        sy.sync();
+        for (;;) {
+            bool ch = false;
+            for (int i = sy.idx; i < nfree; i += sy.step) {
+                const int p = L.lst[i];
+                if (L.st[p] & ST_FIXED) continue;
+                const unsigned m = L.msk[p];
+                const int h = L.hh[p];
+                if (!m || h == 1) continue;
+                int best = h;
+#pragma unroll
+                for (int d = 0; d < ND; ++d)
+                    if (((m >> d) & 1u) && L.res(p, d) > 0) {
+                        const int hv = L.hh[L.nbr(p, d)] + 1;
+                        if (hv < best) best = hv;
+                    }
+                if (best < h) { L.hh[p] = int16_t(best); ch = true; }
+            }
+            if (!sy.any(ch)) break;
+        }
+        bool act = false;
+        for (int i = sy.idx; i < nfree; i += sy.step) {
+            const int p = L.lst[i];
+            if (!(L.st[p] & ST_FIXED) && L.dd[p] > 0 && L.hh[p] < H_INF) act = true;
+        }
+        if (!sy.any(act)) break;
+        ++fs.grel;
+        if (fs.rounds >= round_limit) { fs.fail = true; break; }
+        for (int r = 0; r < relabel_period; ++r) {
+            // push: heights are frozen, so an edge is admissible in one direction only
+            for (int i = sy.idx; i < nfree; i += sy.step) {
+                const int p = L.lst[i];
+                if (L.st[p] & ST_FIXED) continue;
+                const int32_t e = L.dd[p];
+                const int h = L.hh[p];
+                if (e <= 0 || h >= H_INF) continue;
+                const unsigned m = L.msk[p];
+                int32_t rem = e;
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    if (!((m >> d) & 1u) || rem == 0) continue;
+                    const int v = L.nbr(p, d);
+                    if (L.hh[v] != h - 1) continue;
+                    const int32_t rs = L.res(p, d);
+                    if (rs <= 0) continue;
+                    const int32_t delta = rem < rs ? rem : rs;
+                    L.push(p, d, delta);
+                    atomicAdd(&L.dd[v], delta);
+                    rem -= delta;
+                }
+                if (rem != e) atomicSub(&L.dd[p], e - rem);
+            }
+            sy.sync();
+            // relabel: active nodes without an admissible arc rise to 1 + the lowest residual neighbour
+            for (int i = sy.idx; i < nfree; i += sy.step) {
+                const int p = L.lst[i];
+                if (L.st[p] & ST_FIXED) continue;
+                const int h = L.hh[p];
+                if (L.dd[p] <= 0 || h >= H_INF) continue;
+                const unsigned m = L.msk[p];
+                int best = 1 << 30;
+                bool adm = false;
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    if (!((m >> d) & 1u) || adm) continue;
+                    if (L.res(p, d) <= 0) continue;
+                    const int hv = L.hh[L.nbr(p, d)];
+                    if (hv == h - 1) adm = true;
+                    else if (hv + 1 < best) best = hv + 1;
+                }
+                if (!adm) L.hh[p] = int16_t(best > nfree ? H_INF : best);   // no path of that length exists
+            }
+            sy.sync();
+            ++fs.rounds;
+        }
+    }
+    // (4) canonical cut: nodes reachable in the residual graph from any node holding excess
+    for (int i = sy.idx; i < nfree; i += sy.step) {
+        const int p = L.lst[i];
+        if (!(L.st[p] & ST_FIXED) && L.dd[p] > 0) L.st[p] |= ST_MARK;
+    }
+    sy.sync();
+    for (;;) {
+        bool ch = false;
+        for (int i = sy.idx; i < nfree; i += sy.step) {
+            const int p = L.lst[i];
+            if (L.st[p] & (ST_FIXED | ST_MARK)) continue;
+            const unsigned m = L.msk[p];
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+                if (((m >> d) & 1u) && (L.st[L.nbr(p, d)] & ST_MARK) && L.res_in(p, d) > 0) {
+                    L.st[p] |= ST_MARK;
+                    ch = true;
+                    break;
+                }
+        }
+        if (!sy.any(ch)) break;
+    }
+}
+
+// Free nodes up to this count are handled by one wavefront (wave-level synchronisation only).
+constexpr int WAVE_FLOW_MAX = 64;
+
 template <int CONN, int NT>
 __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned char *smem, int32_t npmax,
                                               int32_t round_limit, int32_t relabel_period) {
     constexpr int H = Sten<CONN>::H;
-    constexpr int ND = 2 * H;
     const Geom &g = im.g;
-    const int32_t *__restrict__ u = im.u;
-    const int32_t *__restrict__ cw = im.cw;
-    const int32_t *__restrict__ Y = im.Y;
     const Ctl *ctl = im.ctl;
     const int32_t *bt = im.btab + BTAB_STRIDE * k;
     const int x0 = bt[0], y0 = bt[1], z0 = bt[2], ex = bt[3], ey = bt[4], ez = bt[5];
@@ -172,256 +398,73 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     const int np = ex * ey * ez;
     const int32_t *Ain = (ctl->t & 1) ? im.A1 : im.A0;
     const int64_t M = ctl->M;
-    if (threadIdx.x == 0) im.resid[k] = 0;     // accumulated by the consensus kernel of this iteration
-
-    int *s_ctr = reinterpret_cast<int *>(smem);                    // 16 ints of scalars
-    int32_t *cap = reinterpret_cast<int32_t *>(smem + 64);         // [H][npmax]
-    int32_t *flw = cap + H * npmax;                                 // [H][npmax]  flow p -> p + off_o
-    int32_t *dd = flw + H * npmax;                                  // excess minus sink residual
-    int16_t *hh = reinterpret_cast<int16_t *>(dd + npmax);          // heights
-    uint8_t *msk = reinterpret_cast<uint8_t *>(hh + npmax);         // live in-block directions
-    uint8_t *st = msk + npmax;                                      // ST_* bits
     const int tid = threadIdx.x;
+    if (tid == 0) im.resid[k] = 0;     // accumulated by the consensus kernel of this iteration
 
-    int loff[H];
+    int *s_ctr = reinterpret_cast<int *>(smem);                    // scalar slots 0..14
+    BlockLds<CONN> L;
+    L.npmax = npmax;
+    L.cap = reinterpret_cast<int32_t *>(smem + 64);
+    L.flw = L.cap + H * npmax;
+    L.dd = L.flw + H * npmax;
+    L.hh = reinterpret_cast<int16_t *>(L.dd + npmax);
+    L.lst = L.hh + npmax;
+    L.msk = reinterpret_cast<uint8_t *>(L.lst + npmax);
+    L.st = L.msk + npmax;
 #pragma unroll
     for (int o = 0; o < H; ++o) {
         const int3 v = half_off<CONN>(o);
-        loff[o] = v.x + ex * (v.y + ey * v.z);
+        L.loff[o] = v.x + ex * (v.y + ey * v.z);
     }
-    auto nbr = [&](int p, int d) -> int { return d < H ? p + loff[d] : p - loff[d - H]; };
-    auto capd = [&](int p, int d) -> int32_t { return d < H ? cap[d * npmax + p] : cap[(d - H) * npmax + p - loff[d - H]]; };
-    // residual of the arc p -> nbr(p, d)
-    auto res = [&](int p, int d) -> int32_t {
-        if (d < H) return cap[d * npmax + p] - flw[d * npmax + p];
-        const int v = p - loff[d - H];
-        return cap[(d - H) * npmax + v] + flw[(d - H) * npmax + v];
-    };
-    // residual of the arc nbr(p, d) -> p
-    auto res_in = [&](int p, int d) -> int32_t {
-        if (d < H) return cap[d * npmax + p] + flw[d * npmax + p];
-        const int v = p - loff[d - H];
-        return cap[(d - H) * npmax + v] - flw[(d - H) * npmax + v];
-    };
-    auto push = [&](int p, int d, int32_t delta) {
-        if (d < H) flw[d * npmax + p] += delta;
-        else flw[(d - H) * npmax + p - loff[d - H]] -= delta;
-    };
-
     if (tid < 15) s_ctr[tid] = 0;
     __syncthreads();
 
-    // ---- prologue: Eq. (8) unaries, in-block capacities, strictly forced nodes ----
+    // ---- prologue: Eq. (8) unaries, in-block capacities, strictly forced nodes, list of the others ----
     for (int p = tid; p < np; p += NT) {
         const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
         int32_t cp[H];
         unsigned m;
         int64_t sumc;
-        const int64_t Ut = block_unary<CONN>(g, u, cw, Y, Ain[off + p], M, x0 + lx, y0 + ly, z0 + lz, lx, ly, lz,
-                                             ex, ey, ez, cp, m, sumc);
+        const int64_t Ut = block_unary<CONN>(g, im.u, im.cw, im.Y, Ain[off + p], M, x0 + lx, y0 + ly, z0 + lz,
+                                             lx, ly, lz, ex, ey, ez, cp, m, sumc);
 #pragma unroll
         for (int o = 0; o < H; ++o) {
-            cap[o * npmax + p] = cp[o];
-            flw[o * npmax + p] = 0;
+            L.cap[o * npmax + p] = cp[o];
+            L.flw[o * npmax + p] = 0;
         }
-        uint8_t s = 0;
-        if (Ut < -sumc) s = ST_NEW | ST_LABEL;         // label 1 in every minimiser
-        else if (Ut > sumc) s = ST_NEW;                // label 0 in every minimiser
-        if (s) atomicAdd(&s_ctr[0], 1);
-        st[p] = s;
-        msk[p] = uint8_t(m);
-        dd[p] = s ? 0 : int32_t(Ut);                   // |Ut| <= sumc < 2^29 for free nodes
-    }
-    __syncthreads();
-
-    // ---- cascade: fold the pairwise terms of newly forced nodes into their free neighbours' unaries, then
-    //      look for nodes that the reduced problem forces; repeat until none ----
-    int cascades = 0;
-    for (;;) {
-        const int nnew = s_ctr[0];
-        __syncthreads();
-        if (nnew == 0) break;
-        ++cascades;
-        if (tid == 0) s_ctr[0] = 0;
-        for (int p = tid; p < np; p += NT) {
-            if (st[p] != 0) continue;
-            const unsigned m = msk[p];
-            int32_t U = dd[p];
-#pragma unroll
-            for (int d = 0; d < ND; ++d)
-                if ((m >> d) & 1u) {
-                    const uint8_t sv = st[nbr(p, d)];
-                    if (sv & ST_NEW) U += (sv & ST_LABEL) ? -capd(p, d) : capd(p, d);
-                }
-            dd[p] = U;
-        }
-        __syncthreads();
-        for (int p = tid; p < np; p += NT)
-            if (st[p] & ST_NEW) st[p] = ST_FIXED | (st[p] & ST_LABEL);
-        __syncthreads();
-        for (int p = tid; p < np; p += NT) {
-            if (st[p] & ST_FIXED) continue;
-            const unsigned m = msk[p];
-            int32_t S = 0;
-#pragma unroll
-            for (int d = 0; d < ND; ++d)
-                if ((m >> d) & 1u) {
-                    const int v = nbr(p, d);
-                    if (!(st[v] & ST_FIXED)) S += capd(p, d);
-                }
-            const int32_t U = dd[p];
-            if (U < -S) { st[p] = ST_NEW | ST_LABEL; atomicAdd(&s_ctr[0], 1); }
-            else if (U > S) { st[p] = ST_NEW; atomicAdd(&s_ctr[0], 1); }
-        }
-        __syncthreads();
-    }
-
-    // ---- flow network on the free nodes: source excess -U, sink capacity U folded into one signed value ----
-    for (int p = tid; p < np; p += NT) {
-        if (st[p] & ST_FIXED) {
-            msk[p] = 0;
-            dd[p] = 0;
-            hh[p] = H_INF;
-            continue;
-        }
-        unsigned m = msk[p];
-#pragma unroll
-        for (int d = 0; d < ND; ++d)
-            if (((m >> d) & 1u) && (st[nbr(p, d)] & ST_FIXED)) m &= ~(1u << d);
-        msk[p] = uint8_t(m);
-        dd[p] = -dd[p];
-        atomicAdd(&s_ctr[1], 1);
+        uint8_t sbits = 0;
+        if (Ut < -sumc) sbits = ST_FIXED | ST_LABEL;       // label 1 in every minimiser
+        else if (Ut > sumc) sbits = ST_FIXED;              // label 0 in every minimiser
+        L.st[p] = sbits;
+        L.msk[p] = uint8_t(m);
+        L.dd[p] = sbits ? 0 : int32_t(Ut);                 // |Ut| <= sumc < 2^29 for free nodes
+        if (!sbits) L.lst[atomicAdd(&s_ctr[1], 1)] = int16_t(p);
     }
     __syncthreads();
     const int nfree = s_ctr[1];
 
-    // ---- push-relabel (max preflow) with periodic global relabelling by backward BFS from the sink ----
-    int rounds = 0, grel = 0;
-    bool fail = false;
-    if (nfree > 0) {
-        for (;;) {
-            for (int p = tid; p < np; p += NT)
-                if (!(st[p] & ST_FIXED)) hh[p] = dd[p] < 0 ? 1 : H_INF;
-            __syncthreads();
-            // exact distances to the sink in the residual graph by monotone relaxation to a fixed point
-            for (;;) {
-                int changed = 0;
-                for (int p = tid; p < np; p += NT) {
-                    const unsigned m = msk[p];
-                    if (!m) continue;
-                    const int h = hh[p];
-                    if (h == 1) continue;
-                    int best = h;
-#pragma unroll
-                    for (int d = 0; d < ND; ++d)
-                        if (((m >> d) & 1u) && res(p, d) > 0) {
-                            const int hv = hh[nbr(p, d)] + 1;
-                            if (hv < best) best = hv;
-                        }
-                    if (best < h) { hh[p] = int16_t(best); changed = 1; }
-                }
-                if (changed) s_ctr[2] = 1;
-                __syncthreads();
-                const int any = s_ctr[2];
-                __syncthreads();
-                if (!any) break;
-                if (tid == 0) s_ctr[2] = 0;
-                __syncthreads();
-            }
-            for (int p = tid; p < np; p += NT)
-                if (dd[p] > 0 && hh[p] < H_INF) { s_ctr[3] = 1; }
-            __syncthreads();
-            const int active = s_ctr[3];
-            __syncthreads();
-            if (!active) break;
-            if (tid == 0) s_ctr[3] = 0;
-            ++grel;
-            if (rounds >= round_limit) { fail = true; break; }
-            for (int r = 0; r < relabel_period; ++r) {
-                // push phase: heights are frozen; an edge can be admissible in one direction only
-                for (int p = tid; p < np; p += NT) {
-                    const int32_t e = dd[p];
-                    if (e <= 0) continue;
-                    const int h = hh[p];
-                    if (h >= H_INF) continue;
-                    const unsigned m = msk[p];
-                    int32_t rem = e;
-#pragma unroll
-                    for (int d = 0; d < ND; ++d) {
-                        if (!((m >> d) & 1u) || rem == 0) continue;
-                        const int v = nbr(p, d);
-                        if (hh[v] != h - 1) continue;
-                        const int32_t rs = res(p, d);
-                        if (rs <= 0) continue;
-                        const int32_t delta = rem < rs ? rem : rs;
-                        push(p, d, delta);
-                        atomicAdd(&dd[v], delta);
-                        rem -= delta;
-                    }
-                    if (rem != e) atomicSub(&dd[p], e - rem);
-                }
-                __syncthreads();
-                // relabel phase: active nodes without an admissible arc rise to 1 + min residual neighbour
-                for (int p = tid; p < np; p += NT) {
-                    if (dd[p] <= 0) continue;
-                    const int h = hh[p];
-                    if (h >= H_INF) continue;
-                    const unsigned m = msk[p];
-                    int best = 1 << 30;
-                    bool adm = false;
-#pragma unroll
-                    for (int d = 0; d < ND; ++d) {
-                        if (!((m >> d) & 1u) || adm) continue;
-                        if (res(p, d) <= 0) continue;
-                        const int hv = hh[nbr(p, d)];
-                        if (hv == h - 1) adm = true;
-                        else if (hv + 1 < best) best = hv + 1;
-                    }
-                    if (!adm) hh[p] = int16_t(best > nfree ? H_INF : best);
-                }
-                __syncthreads();
-                ++rounds;
-            }
+    FlowStats fs{0, 0, 0, false};
+    if (nfree > 0 && nfree <= WAVE_FLOW_MAX) {
+        if (tid < 64) {
+            WaveSync sy{tid, 64};
+            flow_on_list<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
         }
-        // ---- canonical cut: nodes reachable in the residual graph from any node holding excess ----
-        for (int p = tid; p < np; p += NT)
-            if (!(st[p] & ST_FIXED) && dd[p] > 0) st[p] |= ST_MARK;
-        __syncthreads();
-        if (tid == 0) s_ctr[4] = 0;
-        __syncthreads();
-        for (;;) {
-            int changed = 0;
-            for (int p = tid; p < np; p += NT) {
-                if (st[p] & (ST_FIXED | ST_MARK)) continue;
-                const unsigned m = msk[p];
-#pragma unroll
-                for (int d = 0; d < ND; ++d)
-                    if (((m >> d) & 1u) && (st[nbr(p, d)] & ST_MARK) && res_in(p, d) > 0) {
-                        st[p] |= ST_MARK;
-                        changed = 1;
-                        break;
-                    }
-            }
-            if (changed) s_ctr[4] = 1;
-            __syncthreads();
-            const int any = s_ctr[4];
-            __syncthreads();
-            if (!any) break;
-            if (tid == 0) s_ctr[4] = 0;
-            __syncthreads();
-        }
+    } else if (nfree > 0) {
+        BlockSync sy{tid, NT, s_ctr + 2, 0};
+        flow_on_list<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
     }
+    __syncthreads();
 
     for (int p = tid; p < np; p += NT) {
-        const uint8_t s = st[p];
-        im.yhat[off + p] = (s & ST_FIXED) ? ((s & ST_LABEL) ? 1 : 0) : ((s & ST_MARK) ? 1 : 0);
+        const uint8_t sb = L.st[p];
+        im.yhat[off + p] = (sb & ST_FIXED) ? ((sb & ST_LABEL) ? 1 : 0) : ((sb & ST_MARK) ? 1 : 0);
     }
     if (tid == 0) {
         im.stats[4 * k + 0] = nfree;
-        im.stats[4 * k + 1] = rounds;
-        im.stats[4 * k + 2] = grel;
-        im.stats[4 * k + 3] = cascades;
-        if (fail) atomicOr(&im.ctl->solver_err, 1);
+        im.stats[4 * k + 1] = fs.rounds;
+        im.stats[4 * k + 2] = fs.grel;
+        im.stats[4 * k + 3] = fs.casc;
+        if (fs.fail) atomicOr(&im.ctl->solver_err, 1);
     }
 }
 
@@ -951,7 +994,7 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s) {
     const int32_t workers = grp.n_workers > 0 ? (grp.n_workers < grp.n_blk_items ? grp.n_workers : grp.n_blk_items)
                                               : grp.n_blk_items;
     hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(workers), dim3(NT), lds, s, grp.imgs, grp.blk_items,
-                       grp.n_blk_items, grp.queue, grp.npmax, round_limit, 8);
+                       grp.n_blk_items, grp.queue, grp.npmax, round_limit, grp.npmax > 2048 ? 8 : 4);
     return hipGetLastError();
 }
 
@@ -962,7 +1005,15 @@ hipError_t solve_phase(const Group &grp, hipStream_t s) {
                            grp.imgs, grp.blk_items, grp.n_blk_items);
         return hipGetLastError();
     }
-    if (grp.npmax > 512) return launch_maxflow<CONN, 1024>(grp, s);
+    // Workgroup size: blocks of more than 512 pixels use 1024 threads when about one block per CU is available
+    // (or when the LDS footprint allows only one block per CU), otherwise 512 threads so that three blocks share
+    // a CU and hide each other's barrier and LDS latency.  Measured on MI355X with 32x32 8-connected blocks:
+    // 289 blocks favour 1024 threads, 1089 blocks favour 512.
+    if (grp.npmax > 512) {
+        const bool one_per_cu = maxflow_lds_bytes(grp.npmax, Sten<CONN>::H) > LDS_LIMIT / 2;
+        if (one_per_cu || grp.n_blk_items <= 2 * NUM_CUS) return launch_maxflow<CONN, 1024>(grp, s);
+        return launch_maxflow<CONN, 512>(grp, s);
+    }
     return launch_maxflow<CONN, 256>(grp, s);
 }
 

@@ -44,6 +44,15 @@ def params_from_problem(prob, block=None, overlap=None):
                        solver=prob.solver)
 
 
+def autotune(ndim, dims, connectivity):
+    """(block, overlap) chosen by the library for this image shape (pure function of shape and stencil)."""
+    d = (ctypes.c_int32 * 3)(*(tuple(int(x) for x in dims) + (1,) * (3 - len(dims))))
+    b = (ctypes.c_int32 * 3)()
+    o = (ctypes.c_int32 * 3)()
+    N.check(N.dope_autotune(int(ndim), d, int(connectivity), b, o))
+    return tuple(b), tuple(o)
+
+
 class Dope:
     """One DOPE solve context (see include/dope.h)."""
 
