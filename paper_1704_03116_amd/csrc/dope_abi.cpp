@@ -29,11 +29,11 @@ struct dope_ctx {
     bool own_ws = false;
     Ctl *ctl = nullptr;
     int32_t *btab = nullptr, *u = nullptr, *w = nullptr, *cw = nullptr, *Y = nullptr, *A0 = nullptr, *A1 = nullptr;
-    int32_t *stats = nullptr, *chunk_k0 = nullptr;
+    int32_t *stats = nullptr, *chunk_k0 = nullptr, *blist = nullptr;
     uint8_t *yhat = nullptr, *labels = nullptr;
     int64_t *resid = nullptr, *epart = nullptr;
     Ctl *hctl = nullptr;       // pinned host mirror of the control block
-    std::vector<int32_t> hbtab, hchunk;
+    std::vector<int32_t> hbtab, hchunk, hblist;
     dope::Img *dimg = nullptr;          // this context's descriptor (device)
     dope::Item *blk_items = nullptr, *chk_items = nullptr;
     dope::Queue *queue = nullptr;
@@ -50,7 +50,7 @@ struct dope_ctx {
 namespace {
 
 struct Layout {
-    size_t ctl, img, bitems, citems, queue, btab, chunk, u, w, cw, Y, A0, A1, yhat, resid, stats, labels, epart, total;
+    size_t ctl, img, bitems, citems, queue, btab, chunk, blist, u, w, cw, Y, A0, A1, yhat, resid, stats, labels, epart, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -62,10 +62,12 @@ Layout layout_for(const Geom &g) {
     L.ctl = take(sizeof(Ctl));
     L.img = take(sizeof(dope::Img));
     L.bitems = take(size_t(g.K) * sizeof(dope::Item));
-    L.citems = take(size_t((g.tot + dope::CHUNK - 1) / dope::CHUNK) * sizeof(dope::Item));
+    const int64_t nbl = g.tot - g.n_interior;
+    L.citems = take(size_t((nbl + dope::CHUNK - 1) / dope::CHUNK) * sizeof(dope::Item));
     L.queue = take(sizeof(dope::Queue));
     L.btab = take(size_t(g.K) * dope::BTAB_STRIDE * 4);
-    L.chunk = take(size_t((g.tot + dope::CHUNK - 1) / dope::CHUNK) * 4);
+    L.chunk = take(size_t((nbl + dope::CHUNK - 1) / dope::CHUNK) * 4);
+    L.blist = take(size_t(nbl) * 4);
     L.u = take(size_t(g.n) * 4);
     L.w = take(size_t(g.n) * g.hs * 4);
     L.cw = take(size_t(g.n) * g.hs * 4);
@@ -147,6 +149,18 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
     g.tot = tot;
     for (int a = 0; a < 3; ++a)
         g.span[a] = int64_t(g.ax[a].nb - 1) * g.ax[a].B + dope::axis_ext(g.ax[a], g.ax[a].nb - 1);
+    g.n_interior = 1;   // the interior rule is separable: product over axes of the interior counts
+    for (int a = 0; a < 3; ++a) {
+        const dope::Axis &ax = g.ax[a];
+        int64_t cnt = 0;
+        for (int t = 0; t < ax.nb; ++t) {
+            const int32_t start = t * ax.s, o = ax.B - ax.s;
+            const int32_t lo = t > 0 ? start + o + 1 : 0;
+            const int32_t hi = t < ax.nb - 1 ? start + dope::axis_ext(ax, t) - o - 1 : ax.N;
+            cnt += std::max(0, hi - lo);
+        }
+        g.n_interior *= cnt;
+    }
     if (btab) {
         // the kernels locate blocks by the closed form; it must agree with the enumeration above
         int64_t kk = 0;
@@ -180,16 +194,31 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
 
 thread_local std::string g_create_error;
 
-// chunk[c] = block containing block-major copy c * CHUNK.
-void build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<int32_t> &chunk) {
-    const int64_t nch = (g.tot + dope::CHUNK - 1) / dope::CHUNK;
-    chunk.assign(size_t(nch), 0);
+// blist = block-major indices of the copies that are not interior to their block (the consensus kernel's work;
+// interior copies are finished by the block-solve kernel); chunk[c] = block of blist entry c * CHUNK.
+void build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<int32_t> &blist,
+                  std::vector<int32_t> &chunk) {
+    blist.clear();
+    blist.reserve(size_t(g.tot - g.n_interior));
+    std::vector<int32_t> blk;
+    blk.reserve(size_t(g.tot - g.n_interior));
     int64_t k = 0;
-    for (int64_t ch = 0; ch < nch; ++ch) {
-        const int64_t first = ch * dope::CHUNK;
-        while (k + 1 < g.K && btab[size_t(k + 1) * dope::BTAB_STRIDE + 6] <= first) ++k;
-        chunk[size_t(ch)] = int32_t(k);
-    }
+    for (int tz = 0; tz < g.ax[2].nb; ++tz)
+        for (int ty = 0; ty < g.ax[1].nb; ++ty)
+            for (int tx = 0; tx < g.ax[0].nb; ++tx, ++k) {
+                const int32_t *r = btab.data() + size_t(k) * dope::BTAB_STRIDE;
+                int32_t c = r[6];
+                for (int lz = 0; lz < r[5]; ++lz)
+                    for (int ly = 0; ly < r[4]; ++ly)
+                        for (int lx = 0; lx < r[3]; ++lx, ++c)
+                            if (!dope::is_interior(g, tx, ty, tz, r[0] + lx, r[1] + ly, r[2] + lz)) {
+                                blist.push_back(c);
+                                blk.push_back(int32_t(k));
+                            }
+            }
+    const size_t nch = (blist.size() + dope::CHUNK - 1) / dope::CHUNK;
+    chunk.assign(nch, 0);
+    for (size_t ch = 0; ch < nch; ++ch) chunk[ch] = blk[ch * dope::CHUNK];
 }
 
 dope_status fail(dope_ctx *c, dope_status s, const std::string &msg) {
@@ -213,6 +242,7 @@ void assign_pointers(dope_ctx *c) {
     c->ctl = reinterpret_cast<Ctl *>(b + L.ctl);
     c->btab = reinterpret_cast<int32_t *>(b + L.btab);
     c->chunk_k0 = reinterpret_cast<int32_t *>(b + L.chunk);
+    c->blist = reinterpret_cast<int32_t *>(b + L.blist);
     c->dimg = reinterpret_cast<dope::Img *>(b + L.img);
     c->blk_items = reinterpret_cast<dope::Item *>(b + L.bitems);
     c->chk_items = reinterpret_cast<dope::Item *>(b + L.citems);
@@ -238,6 +268,7 @@ dope::Img host_img(const dope_ctx *c) {
     im.cw = c->cw;
     im.btab = c->btab;
     im.chunk_k0 = c->chunk_k0;
+    im.blist = c->blist;
     im.Y = c->Y;
     im.A0 = c->A0;
     im.A1 = c->A1;
@@ -247,14 +278,19 @@ dope::Img host_img(const dope_ctx *c) {
     im.ctl = c->ctl;
     im.summary = nullptr;
     im.n_chunks = int32_t(c->hchunk.size());
+    im.n_blist = int32_t(c->hblist.size());
     return im;
 }
 
 dope_status upload_tables(dope_ctx *c) {
     HIP_TRY(c, hipMemcpyAsync(c->btab, c->hbtab.data(), c->hbtab.size() * 4, hipMemcpyHostToDevice, c->stream),
             "block table upload");
-    HIP_TRY(c, hipMemcpyAsync(c->chunk_k0, c->hchunk.data(), c->hchunk.size() * 4, hipMemcpyHostToDevice, c->stream),
-            "chunk table upload");
+    if (!c->hchunk.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->chunk_k0, c->hchunk.data(), c->hchunk.size() * 4, hipMemcpyHostToDevice,
+                                  c->stream), "chunk table upload");
+    if (!c->hblist.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->blist, c->hblist.data(), c->hblist.size() * 4, hipMemcpyHostToDevice,
+                                  c->stream), "boundary list upload");
     // one-image launch group: descriptor, work items, zeroed queue (staged in host memory that stays alive
     // until the synchronisation at the end of this function)
     const dope::Img im = host_img(c);
@@ -265,8 +301,9 @@ dope_status upload_tables(dope_ctx *c) {
     HIP_TRY(c, hipMemcpyAsync(c->dimg, &im, sizeof(im), hipMemcpyHostToDevice, c->stream), "descriptor upload");
     HIP_TRY(c, hipMemcpyAsync(c->blk_items, bi.data(), bi.size() * sizeof(dope::Item), hipMemcpyHostToDevice,
                               c->stream), "item upload");
-    HIP_TRY(c, hipMemcpyAsync(c->chk_items, ci.data(), ci.size() * sizeof(dope::Item), hipMemcpyHostToDevice,
-                              c->stream), "item upload");
+    if (!ci.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->chk_items, ci.data(), ci.size() * sizeof(dope::Item), hipMemcpyHostToDevice,
+                                  c->stream), "item upload");
     HIP_TRY(c, hipMemcpyAsync(c->queue, &q, sizeof(q), hipMemcpyHostToDevice, c->stream), "queue upload");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
     c->grp = dope::Group{c->dimg, 1, c->blk_items, c->g.K, c->chk_items, int32_t(ci.size()), c->queue,
@@ -367,7 +404,7 @@ dope_status dope_create(const dope_params *p, dope_ctx **out) {
     c->p = q;
     c->g = g;
     c->hbtab.swap(bt);
-    build_tables(c->g, c->hbtab, c->hchunk);
+    build_tables(c->g, c->hbtab, c->hblist, c->hchunk);
     if (q.stream) {
         c->stream = static_cast<hipStream_t>(q.stream);
     } else {
@@ -888,8 +925,9 @@ dope_status batch_bind(dope_batch *b, dope_ctx *const *ctxs, int32_t n) {
              "descriptor upload");
     BHIP_TRY(b, hipMemcpyAsync(bi, hbi.data(), hbi.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream),
              "item upload");
-    BHIP_TRY(b, hipMemcpyAsync(ci, hci.data(), hci.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream),
-             "item upload");
+    if (!hci.empty())
+        BHIP_TRY(b, hipMemcpyAsync(ci, hci.data(), hci.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream),
+                 "item upload");
     BHIP_TRY(b, hipMemcpyAsync(q, &hq, sizeof(hq), hipMemcpyHostToDevice, b->stream), "queue upload");
     BHIP_TRY(b, hipMemcpyAsync(b->dsum, b->hsum, size_t(n) * 16, hipMemcpyHostToDevice, b->stream), "summary upload");
     BHIP_TRY(b, hipStreamSynchronize(b->stream), "stream synchronize");

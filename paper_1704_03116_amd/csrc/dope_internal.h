@@ -22,11 +22,24 @@ struct Geom {
     int64_t n;          // pixels
     int64_t tot;        // sum of block sizes
     int64_t span[3];    // sum of block extents along each axis
+    int64_t n_interior; // block pixels interior to their block (see is_interior)
 };
 
 inline __host__ __device__ int32_t axis_ext(const Axis &a, int32_t t) {
     const int32_t e = a.N - t * a.s;
     return e < a.B ? e : a.B;
+}
+
+// A pixel is interior to block (tx, ty, tz) when it and every pixel of its 3x3(x3) neighbourhood lie in that
+// block only.  Then both Hc terms of Eq. (10) vanish for it, S_m is its single copy, and no other block reads
+// it.  Along one axis: lo <= x < hi with lo = start + o + 1 (0 for the first block), hi = end - o - 1 (N for the
+// last block), o = B - s.
+inline __host__ __device__ bool axis_interior(const Axis &a, int32_t t, int32_t x) {
+    const int32_t start = t * a.s;
+    const int32_t o = a.B - a.s;
+    const int32_t lo = t > 0 ? start + o + 1 : 0;
+    const int32_t hi = t < a.nb - 1 ? start + axis_ext(a, t) - o - 1 : a.N;
+    return x >= lo && x < hi;
 }
 
 // Start of block (tx, ty, tz) in the block-major vectors.  Blocks are ordered x-fastest and only the last block
@@ -35,6 +48,11 @@ inline __host__ __device__ int64_t block_offset(const Geom &g, int32_t tx, int32
     const int64_t Px = int64_t(tx) * g.ax[0].B, Py = int64_t(ty) * g.ax[1].B, Pz = int64_t(tz) * g.ax[2].B;
     const int64_t Ey = axis_ext(g.ax[1], ty), Ez = axis_ext(g.ax[2], tz);
     return Pz * g.span[1] * g.span[0] + Ez * (Py * g.span[0] + Ey * Px);
+}
+
+inline __host__ __device__ bool is_interior(const Geom &g, int32_t tx, int32_t ty, int32_t tz, int32_t x, int32_t y,
+                                            int32_t z) {
+    return axis_interior(g.ax[0], tx, x) && axis_interior(g.ax[1], ty, y) && axis_interior(g.ax[2], tz, z);
 }
 
 // Device-resident loop control.  Written by the host only through k_ctl_* kernels or state uploads.
@@ -71,11 +89,6 @@ inline size_t maxflow_lds_bytes(int np, int hs) { return 64 + size_t(np) * (8 * 
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
 constexpr int NUM_CUS = 256;          // MI355X compute units
 
-// Device lookup tables built on the host with the partition.
-struct Tables {
-    const int32_t *chunk_k0;   // block containing the first copy of every 256-copy chunk
-    int32_t n_chunks;
-};
 
 constexpr int CHUNK = 256;
 
@@ -83,14 +96,16 @@ constexpr int CHUNK = 256;
 // can serve many images.
 struct Img {
     Geom g;
-    const int32_t *u, *w, *cw, *btab, *chunk_k0;
+    const int32_t *u, *w, *cw, *btab;
+    const int32_t *blist;      // block-major indices of the copies that are not interior to their block
+    const int32_t *chunk_k0;   // block of the first entry of every CHUNK entries of blist
     int32_t *Y, *A0, *A1, *stats;
     uint8_t *yhat;
     int64_t *resid;
     Ctl *ctl;
     int32_t *summary;   // optional: {t, halted, converged, status} written after every iteration
     int32_t n_chunks;
-    int32_t pad;
+    int32_t n_blist;
 };
 
 struct Item {

@@ -399,9 +399,8 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     const int32_t *Ain = (ctl->t & 1) ? im.A1 : im.A0;
     const int64_t M = ctl->M;
     const int tid = threadIdx.x;
-    if (tid == 0) im.resid[k] = 0;     // accumulated by the consensus kernel of this iteration
 
-    int *s_ctr = reinterpret_cast<int *>(smem);                    // scalar slots 0..14
+    int *s_ctr = reinterpret_cast<int *>(smem);    // scalar slots 0..14 (6..7: a 64-bit residual sum)
     BlockLds<CONN> L;
     L.npmax = npmax;
     L.cap = reinterpret_cast<int32_t *>(smem + 64);
@@ -455,11 +454,35 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     }
     __syncthreads();
 
+    // ---- labels; consensus and multipliers of the pixels interior to this block (Eq. 10 reduces to
+    //      Y = 2^16 yhat + A and Eq. 11 to A = 0 there, and no other block reads them) ----
+    const int tx = k % g.ax[0].nb, ty = (k / g.ax[0].nb) % g.ax[1].nb, tz = k / (g.ax[0].nb * g.ax[1].nb);
+    int32_t *Aout = (ctl->t & 1) ? im.A0 : im.A1;
+    unsigned long long r2 = 0;
+    bool ovf = false;
     for (int p = tid; p < np; p += NT) {
         const uint8_t sb = L.st[p];
-        im.yhat[off + p] = (sb & ST_FIXED) ? ((sb & ST_LABEL) ? 1 : 0) : ((sb & ST_MARK) ? 1 : 0);
+        const int yv = (sb & ST_FIXED) ? ((sb & ST_LABEL) ? 1 : 0) : ((sb & ST_MARK) ? 1 : 0);
+        im.yhat[off + p] = uint8_t(yv);
+        const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
+        if (is_interior(g, tx, ty, tz, x0 + lx, y0 + ly, z0 + lz)) {
+            const int64_t Yn = int64_t(yv) * Y_ONE + Ain[off + p];
+            if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = true;
+            const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
+            im.Y[lin(g, x0 + lx, y0 + ly, z0 + lz)] = int32_t(Yc);
+            Aout[off + p] = 0;
+            const int64_t rr = int64_t(yv) * Y_ONE - Yc;
+            r2 += (unsigned long long)(rr * rr);
+        }
     }
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) r2 += __shfl_xor(r2, sft);
+    unsigned long long *s_r2 = reinterpret_cast<unsigned long long *>(s_ctr + 6);
+    if ((tid & 63) == 0 && r2) atomicAdd(s_r2, r2);
+    if (ovf) atomicOr(&im.ctl->ovf_pending, 1);
+    __syncthreads();
     if (tid == 0) {
+        im.resid[k] = int64_t(*s_r2);    // the consensus kernel adds the other pixels of the block
         im.stats[4 * k + 0] = nfree;
         im.stats[4 * k + 1] = fs.rounds;
         im.stats[4 * k + 2] = fs.grel;
@@ -594,9 +617,30 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
         const uint32_t oc = __shfl_xor(bestc, s);
         if (oE < best || (oE == best && oc < bestc)) { best = oE; bestc = oc; }
     }
-    if (lane < np) im.yhat[off + lane] = uint8_t((bestc >> lane) & 1u);
+    unsigned long long r2 = 0;
+    if (lane < np) {
+        const int yv = int((bestc >> lane) & 1u);
+        im.yhat[off + lane] = uint8_t(yv);
+        const int32_t *bt = im.btab + BTAB_STRIDE * k;
+        const int ex = bt[3], ey = bt[4];
+        const int lx = lane % ex, r = lane / ex, ly = r % ey, lz = r / ey;
+        const int tx = k % g.ax[0].nb, ty = (k / g.ax[0].nb) % g.ax[1].nb, tz = k / (g.ax[0].nb * g.ax[1].nb);
+        if (is_interior(g, tx, ty, tz, bt[0] + lx, bt[1] + ly, bt[2] + lz)) {
+            const int32_t *Ain = (ctl->t & 1) ? im.A1 : im.A0;
+            int32_t *Aout = (ctl->t & 1) ? im.A0 : im.A1;
+            const int64_t Yn = int64_t(yv) * Y_ONE + Ain[off + lane];
+            if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) atomicOr(&im.ctl->ovf_pending, 1);
+            const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
+            im.Y[lin(g, bt[0] + lx, bt[1] + ly, bt[2] + lz)] = int32_t(Yc);
+            Aout[off + lane] = 0;
+            const int64_t rr = int64_t(yv) * Y_ONE - Yc;
+            r2 = (unsigned long long)(rr * rr);
+        }
+    }
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) r2 += __shfl_xor(r2, sft);
     if (lane == 0) {
-        im.resid[k] = 0;
+        im.resid[k] = int64_t(r2);
         im.stats[4 * k + 0] = np;
         im.stats[4 * k + 1] = 0;
         im.stats[4 * k + 2] = 0;
@@ -644,11 +688,12 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
     s_res[tid] = 0;
     if (tid == 0) s_ovf = 0;
     __syncthreads();
-    const int64_t c = int64_t(chunk) * CONS_NT + tid;
+    const int64_t li = int64_t(chunk) * CONS_NT + tid;
     int ovf = 0;
     int kk = kfirst;
     int64_t r2 = 0;
-    if (c < g.tot) {
+    if (li < im.n_blist) {
+        const int64_t c = im.blist[li];
         while (kk + 1 < g.K && int64_t(btab[BTAB_STRIDE * (kk + 1) + 6]) <= c) ++kk;
         const int32_t *bt = btab + BTAB_STRIDE * kk;
         const int ex = bt[3], ey = bt[4];
@@ -1057,7 +1102,7 @@ hipError_t launch_solve_phase(const Group &grp, hipStream_t s) {
 
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s) {
     const dim3 grid(unsigned(grp.n_chk_items));
-    switch (grp.conn) {
+    if (grp.n_chk_items > 0) switch (grp.conn) {
         case 4: hipLaunchKernelGGL(k_consensus<4>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
         case 8: hipLaunchKernelGGL(k_consensus<8>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
         default: hipLaunchKernelGGL(k_consensus<6>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;

@@ -59,12 +59,30 @@ def _params(native, dims=(512, 512, 1), conn=8, block=(32, 32, 1), overlap=(2, 2
     return p
 
 
-def _workspace_model(dims, h, K, tot):
+def _interior_count(dims, block, overlap):
+    """Pixels whose 3x3(x3) neighbourhood lies in their own block only (the block-solve kernel finishes them)."""
+    from oracle import dope as od
+    total = 1
+    for N, B, o in zip(dims, block, overlap):
+        iv = od.partition_axis(N, B, o)
+        oo = 0 if len(iv) == 1 else o
+        cnt = 0
+        for t, (a, b) in enumerate(iv):
+            lo = a + oo + 1 if t > 0 else 0
+            hi = b - oo - 1 if t < len(iv) - 1 else N
+            cnt += max(0, hi - lo)
+        total *= cnt
+    return total
+
+
+def _workspace_model(dims, h, K, tot, n_int):
     a = lambda x: (x + 255) // 256 * 256  # noqa: E731
     n = dims[0] * dims[1] * dims[2]
-    chunks = (tot + 255) // 256
-    return (a(128) + a(256) + a(8 * K) + a(8 * chunks) + a(256) + a(K * 32) + a(4 * chunks) + a(4 * n) + 2 * a(4 * h * n) + a(4 * n)
-            + 2 * a(4 * tot) + a(tot) + a(8 * K) + a(16 * K) + a(n) + a(8 * 256))
+    nbl = tot - n_int
+    chunks = (nbl + 255) // 256
+    return (a(128) + a(256) + a(8 * K) + a(8 * chunks) + a(256) + a(K * 32) + a(4 * chunks) + a(4 * nbl)
+            + a(4 * n) + 2 * a(4 * h * n) + a(4 * n) + 2 * a(4 * tot) + a(tot) + a(8 * K) + a(16 * K) + a(n)
+            + a(8 * 256))
 
 
 @pytest.mark.parametrize("dims,conn,block,overlap,ndim", [
@@ -80,7 +98,8 @@ def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, n
     n = dims[0] * dims[1] * dims[2]
     h = {4: 2, 8: 4, 6: 3}[conn]
     tot = sum(len(b.idx) for b in blocks)
-    assert native.dope_workspace_bytes(ctypes.byref(p)) == _workspace_model(dims, h, len(blocks), tot)
+    assert native.dope_workspace_bytes(ctypes.byref(p)) == _workspace_model(dims, h, len(blocks), tot,
+                                                                     _interior_count(dims, block, overlap))
 
 
 @pytest.mark.parametrize("kw,msg", [
@@ -101,3 +120,14 @@ def test_create_rejects_bad_params(native, kw, msg):
 
 def test_last_error_null_safe(native):
     assert isinstance(native.dope_last_error(None), bytes)
+
+
+def test_autotune_is_a_pure_function_of_shape(native):
+    from paper_1704_03116_amd.solver import autotune
+    assert autotune(2, (128, 128), 8) == ((16, 16, 1), (1, 1, 0))
+    assert autotune(2, (4096, 256), 8) == ((16, 16, 1), (1, 1, 0))
+    assert autotune(2, (512, 300), 8) == ((32, 32, 1), (1, 1, 0))
+    assert autotune(3, (128, 128, 64), 6) == ((16, 16, 16), (1, 1, 1))
+    assert autotune(2, (512, 512), 8) == autotune(2, (512, 512), 8)
+    with pytest.raises(Exception):
+        autotune(2, (64, 64), 6)
