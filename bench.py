@@ -34,12 +34,117 @@ def workload(name, seed=0):
     raise SystemExit(f"unknown workload {name}")
 
 
+def interior_count(dims, block, overlap):
+    """Block pixels whose 3x3(x3) neighbourhood lies in their own block only (finished by the block-solve
+    kernel): per axis, block t contributes [start + o + 1 (0 for t = 0), end - o - 1 (N for the last block))."""
+    total = 1
+    for N, B, o in zip(dims, block, overlap):
+        if B <= 0 or B >= N:
+            total *= N
+            continue
+        s = B - o
+        count = 1 + -(-(N - B) // s)
+        c = 0
+        for t in range(count):
+            a, b = t * s, min(t * s + B, N)
+            lo = a + o + 1 if t > 0 else 0
+            hi = b - o - 1 if t < count - 1 else N
+            c += max(0, hi - lo)
+        total *= c
+    return total
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary, only while the kernel source is the
+    one that was measured (FETCH_SIZE and WRITE_SIZE scaled by a 256 MiB copy's readings)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_config2_512x512.json")
+    src = os.path.join(ROOT, "paper_1704_03116_amd", "csrc", "dope_kernels.hip")
+    if not workload_name.startswith("config2") or not os.path.exists(path):
+        return {}
+    rec = json.load(open(path))
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
+        return {}
+    out = {}
+    for k, v in rec["per_dispatch"].items():
+        out[k.split("<")[0]] = v["hbm_bytes"]
+    return out
+
+
 def cpu_baseline(p, threads):
     from oracle import dope as od
     t0 = time.perf_counter()
     st, infos, _, dec = od.run(p, threads=threads)
     el = time.perf_counter() - t0
     return el, st, infos, dec
+
+
+def serve_replay(n_req, slots):
+    """Replay the first n_req requests of the serving trace (Poisson arrivals, 200 req/s) twice: continuous
+    batching (up to `slots` requests admitted, one batched ADMM iteration per tick) and the plain path (one request
+    at a time, FIFO).  Also runs both closed-loop (every request queued at t = 0) for capacity.  Request inputs are
+    staged in HBM before the replay; block partitions come from dope_autotune."""
+    import numpy as np
+    import torch
+    import synth
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1704_03116_amd.solver import Server, autotune, params_from_problem
+
+    arrivals = synth.config5_trace()[:n_req]
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        probs = list(ex.map(synth.config5_request, range(n_req)))
+    staged = []
+    for p in probs:
+        p.block, p.overlap = autotune(2, p.dims, p.conn)
+        staged.append((params_from_problem(p), torch.from_numpy(np.ascontiguousarray(p.u)).cuda(),
+                       torch.from_numpy(np.ascontiguousarray(p.w)).cuda(),
+                       torch.empty(p.n, dtype=torch.uint8, device="cuda")))
+    torch.cuda.synchronize()
+    total_px = sum(p.n for p in probs)
+
+    def run(max_active, closed):
+        budget = 96 << 30
+        srv = Server(budget, max_active)
+        lat = [None] * n_req
+        owner = {}
+        t0 = time.perf_counter()
+        nxt, done, last = 0, 0, 0.0
+        while done < n_req:
+            now = time.perf_counter() - t0
+            while nxt < n_req and (closed or arrivals[nxt] <= now):
+                prm, u, w, lab = staged[nxt]
+                owner[srv.submit(prm, u, w, probs[nxt].lam_q8, lab)] = nxt
+                nxt += 1
+            waiting, active, _ = srv.load()
+            if waiting == 0 and active == 0:
+                time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+                continue
+            fin = srv.step()
+            tn = time.perf_counter() - t0
+            for t in fin:
+                i = owner[t]
+                lat[i] = tn - (0.0 if closed else arrivals[i])
+                done += 1
+                last = tn
+        srv.close()
+        first = 0.0 if closed else float(arrivals[0])
+        lat_ms = np.array(lat) * 1e3
+        return {"p50_ms": round(float(np.percentile(lat_ms, 50)), 2), "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
+                "mpx_s": round(total_px / (last - first) / 1e6, 2), "makespan_s": round(last - first, 3)}
+
+    run(slots, True)   # warm-up (kernels, allocator)
+    served = run(slots, False)
+    plain = run(1, False)
+    served_cap = run(slots, True)
+    plain_cap = run(1, True)
+    return {
+        "requests": n_req, "trace": "Poisson 200 req/s, sides {128..2048}, aspect U[0.5, 2], 8-connected, lambda U[0.5, 3]",
+        "mpx_total": round(total_px / 1e6, 1), "slots": slots,
+        "served_p50_ms": served["p50_ms"], "served_p99_ms": served["p99_ms"], "served_mpx_s": served["mpx_s"],
+        "plain_p50_ms": plain["p50_ms"], "plain_p99_ms": plain["p99_ms"], "plain_mpx_s": plain["mpx_s"],
+        "served_capacity_mpx_s": served_cap["mpx_s"], "plain_capacity_mpx_s": plain_cap["mpx_s"],
+        "capacity_vs_plain": round(served_cap["mpx_s"] / plain_cap["mpx_s"], 3),
+    }
 
 
 def main():
@@ -50,6 +155,11 @@ def main():
     ap.add_argument("--workload", default="config2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=16, help="images of the batched measurement (0 = skip)")
+    ap.add_argument("--serve", type=int, default=200,
+                    help="requests of the serving replay (first requests of the 2000-request trace; 0 = skip)")
+    ap.add_argument("--serve-slots", type=int, default=64, help="max admitted requests when serving")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a 256 MiB device-to-device copy three times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only: the DOPE path here is a single-GPU "
@@ -61,6 +171,13 @@ def main():
     from paper_1704_03116_amd.solver import Batch, Dope
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p = workload(args.workload)
     print(f"[bench] workload {p.name} n={p.n} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     d = Dope.from_problem(p)
@@ -90,20 +207,25 @@ def main():
     value = p.n * args.steps / elapsed / 1e6
 
     K, tot, h, n = d.K, d.tot, d.h, p.n
+    n_int = interior_count(p.dims, p.block, p.overlap)
+    n_bl = tot - n_int
     kernels = {
-        # per block pixel: u 4 + weights 4h + Y 4 + A 4 read, block label 1 written
-        "k_block_solve": (tot * (13 + 4 * h), prof["solve_ms"], prof["solve_launches"]),
-        # per block pixel: block label 1 + A 4 read, A 4 written; per pixel: weights 4h read, Y 4 written
-        "k_consensus+k_finalize": (tot * 9 + n * (4 * h + 4), prof["consensus_ms"], prof["consensus_launches"]),
+        # per block pixel: u 4 + weights 4h + Y 4 + A 4 read, block label 1 written; per interior pixel (finished
+        # in this kernel): Y 4 + A 4 written
+        "k_block_solve": (tot * (13 + 4 * h) + n_int * 8, prof["solve_ms"], prof["solve_launches"]),
+        # per boundary copy: block label 1 + A 4 read, A 4 written; per boundary pixel: weights 4h read, Y 4 written
+        "k_consensus": (n_bl * 9 + (n - n_int) * (4 * h + 4), prof["consensus_ms"], prof["consensus_launches"]),
     }
+    traffic = measured_traffic(p.name)
 
     def roof(name):
         nbytes, ms, launches = kernels[name]
         avg_ms = ms / max(launches, 1)
         achieved = nbytes / (avg_ms * 1e-3) / 1e9
         return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "avg_launch_ms": round(avg_ms, 5),
-                "launches": launches, "bytes_per_launch": int(nbytes), "total_ms": round(ms, 4)}
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic.get(name),
+                "avg_launch_ms": round(avg_ms, 5), "launches": launches, "bytes_per_launch": int(nbytes),
+                "total_ms": round(ms, 4)}
 
     names = sorted(kernels, key=lambda k: -kernels[k][1])
     out = {
@@ -168,6 +290,9 @@ def main():
         b.close()
         for c in ctxs:
             c.close()
+
+    if args.serve > 0:
+        out["served"] = serve_replay(args.serve, args.serve_slots)
 
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)

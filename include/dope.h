@@ -152,11 +152,20 @@ size_t dope_workspace_bytes(const dope_params *p);
  * Must be called before dope_set_energy; the memory must outlive the context. */
 dope_status dope_bind_workspace(dope_ctx *ctx, void *dev_ptr, size_t bytes);
 
-/* Kernel timing with HIP events on the context stream.  While enabled, every block-solve and consensus launch
- * is bracketed by events; dope_profile_read returns the summed milliseconds and launch counts since enable. */
+/* Kernel timing with HIP events on the context stream.  While enabled, every block-solve launch and every
+ * consensus launch (not the loop-control launch that follows it) is bracketed by events; dope_profile_read
+ * returns the summed milliseconds and launch counts since enable. */
 dope_status dope_profile_enable(dope_ctx *ctx, int32_t on);
 dope_status dope_profile_read(dope_ctx *ctx, double *solve_ms, int32_t *solve_launches, double *consensus_ms,
                               int32_t *consensus_launches);
+
+/* Block partition for an image: a pure function of (ndim, dims, connectivity), never of load, so that a
+ * request's result does not depend on what else is running.  Chosen from measured MI355X throughput of the
+ * max-flow path: 8- and 4-connected 2D images use 16x16 blocks with 1-pixel overlap when the shorter side is
+ * at most 256 pixels and 32x32 blocks with 1-pixel overlap otherwise; 6-connected 3D volumes use 16^3 blocks
+ * with 1-voxel overlap.  Writes block[3] and overlap[3]; EINVAL for an unsupported stencil. */
+dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectivity, int32_t block[3],
+                          int32_t overlap[3]);
 
 /* ---- Batched iterations (many images, one launch per phase) ------------------------------------------------
  * A batch groups contexts so that every ADMM iteration runs as three launches for all of them together: a

@@ -371,6 +371,7 @@ dope_status enqueue_iterations(dope_ctx *c, int count) {
             (void)hipEventRecord(e1, c->stream);
             ++c->n_cons;
         }
+        HIP_TRY(c, dope::launch_finalize_phase(c->grp, c->stream), "finalize launch");
     }
     return DOPE_OK;
 }

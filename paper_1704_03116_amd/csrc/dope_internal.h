@@ -138,6 +138,7 @@ hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params,
 // Individual phases (used for per-kernel timing).
 hipError_t launch_solve_phase(const Group &grp, hipStream_t s);
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s);
+hipError_t launch_finalize_phase(const Group &grp, hipStream_t s);
 
 // c_ij from w and the validation verdict (status / halted set on the device when the energy is invalid).
 hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,

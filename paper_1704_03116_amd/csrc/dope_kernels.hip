@@ -1107,6 +1107,10 @@ hipError_t launch_consensus_phase(const Group &grp, hipStream_t s) {
         case 8: hipLaunchKernelGGL(k_consensus<8>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
         default: hipLaunchKernelGGL(k_consensus<6>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_phase(const Group &grp, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(unsigned(grp.n_imgs)), dim3(256), 0, s, grp.imgs, grp.queue);
     return hipGetLastError();
 }
@@ -1118,8 +1122,9 @@ hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params,
 
 hipError_t launch_iteration(const Group &grp, hipStream_t s) {
     hipError_t e = launch_solve_phase(grp, s);
-    if (e != hipSuccess) return e;
-    return launch_consensus_phase(grp, s);
+    if (e == hipSuccess) e = launch_consensus_phase(grp, s);
+    if (e == hipSuccess) e = launch_finalize_phase(grp, s);
+    return e;
 }
 
 hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s) {
