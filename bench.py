@@ -218,14 +218,18 @@ def main():
     }
     traffic = measured_traffic(p.name)
 
+    # Every step runs the same number of iterations (same input); launches beyond that were enqueued after the
+    # stopping rule held and skipped on the device, so they count for time but not for bytes.
+    working = info["iters_done"] * args.steps
+
     def roof(name):
         nbytes, ms, launches = kernels[name]
         avg_ms = ms / max(launches, 1)
-        achieved = nbytes / (avg_ms * 1e-3) / 1e9
+        achieved = nbytes * min(working, launches) / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic.get(name),
-                "avg_launch_ms": round(avg_ms, 5), "launches": launches, "bytes_per_launch": int(nbytes),
-                "total_ms": round(ms, 4)}
+                "avg_launch_ms": round(avg_ms, 5), "launches": launches, "working_launches": min(working, launches),
+                "bytes_per_launch": int(nbytes), "total_ms": round(ms, 4)}
 
     names = sorted(kernels, key=lambda k: -kernels[k][1])
     out = {

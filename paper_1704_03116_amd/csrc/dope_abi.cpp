@@ -29,7 +29,8 @@ struct dope_ctx {
     bool own_ws = false;
     Ctl *ctl = nullptr;
     int32_t *btab = nullptr, *u = nullptr, *w = nullptr, *cw = nullptr, *Y = nullptr, *A0 = nullptr, *A1 = nullptr;
-    int32_t *stats = nullptr, *chunk_k0 = nullptr, *blist = nullptr;
+    int32_t *stats = nullptr, *chunk_k0 = nullptr;
+    int2 *blist = nullptr;
     uint8_t *yhat = nullptr, *labels = nullptr;
     int64_t *resid = nullptr, *epart = nullptr;
     Ctl *hctl = nullptr;       // pinned host mirror of the control block
@@ -67,7 +68,7 @@ Layout layout_for(const Geom &g) {
     L.queue = take(sizeof(dope::Queue));
     L.btab = take(size_t(g.K) * dope::BTAB_STRIDE * 4);
     L.chunk = take(size_t((nbl + dope::CHUNK - 1) / dope::CHUNK) * 4);
-    L.blist = take(size_t(nbl) * 4);
+    L.blist = take(size_t(nbl) * 8);
     L.u = take(size_t(g.n) * 4);
     L.w = take(size_t(g.n) * g.hs * 4);
     L.cw = take(size_t(g.n) * g.hs * 4);
@@ -196,12 +197,12 @@ thread_local std::string g_create_error;
 
 // blist = block-major indices of the copies that are not interior to their block (the consensus kernel's work;
 // interior copies are finished by the block-solve kernel); chunk[c] = block of blist entry c * CHUNK.
+// blist: (block-major index, block) of every copy that is not interior to its block, in block-major order;
+// chunk: block of the first entry of every CHUNK entries.
 void build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<int32_t> &blist,
                   std::vector<int32_t> &chunk) {
     blist.clear();
-    blist.reserve(size_t(g.tot - g.n_interior));
-    std::vector<int32_t> blk;
-    blk.reserve(size_t(g.tot - g.n_interior));
+    blist.reserve(2 * size_t(g.tot - g.n_interior));
     int64_t k = 0;
     for (int tz = 0; tz < g.ax[2].nb; ++tz)
         for (int ty = 0; ty < g.ax[1].nb; ++ty)
@@ -213,12 +214,13 @@ void build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<i
                         for (int lx = 0; lx < r[3]; ++lx, ++c)
                             if (!dope::is_interior(g, tx, ty, tz, r[0] + lx, r[1] + ly, r[2] + lz)) {
                                 blist.push_back(c);
-                                blk.push_back(int32_t(k));
+                                blist.push_back(int32_t(k));
                             }
             }
-    const size_t nch = (blist.size() + dope::CHUNK - 1) / dope::CHUNK;
+    const size_t nbl = blist.size() / 2;
+    const size_t nch = (nbl + dope::CHUNK - 1) / dope::CHUNK;
     chunk.assign(nch, 0);
-    for (size_t ch = 0; ch < nch; ++ch) chunk[ch] = blk[ch * dope::CHUNK];
+    for (size_t ch = 0; ch < nch; ++ch) chunk[ch] = blist[2 * ch * dope::CHUNK + 1];
 }
 
 dope_status fail(dope_ctx *c, dope_status s, const std::string &msg) {
@@ -242,7 +244,7 @@ void assign_pointers(dope_ctx *c) {
     c->ctl = reinterpret_cast<Ctl *>(b + L.ctl);
     c->btab = reinterpret_cast<int32_t *>(b + L.btab);
     c->chunk_k0 = reinterpret_cast<int32_t *>(b + L.chunk);
-    c->blist = reinterpret_cast<int32_t *>(b + L.blist);
+    c->blist = reinterpret_cast<int2 *>(b + L.blist);
     c->dimg = reinterpret_cast<dope::Img *>(b + L.img);
     c->blk_items = reinterpret_cast<dope::Item *>(b + L.bitems);
     c->chk_items = reinterpret_cast<dope::Item *>(b + L.citems);
@@ -278,7 +280,7 @@ dope::Img host_img(const dope_ctx *c) {
     im.ctl = c->ctl;
     im.summary = nullptr;
     im.n_chunks = int32_t(c->hchunk.size());
-    im.n_blist = int32_t(c->hblist.size());
+    im.n_blist = int32_t(c->hblist.size() / 2);
     return im;
 }
 
@@ -585,13 +587,18 @@ dope_status dope_solve(dope_ctx *c, dope_info *out) {
     if (c->hctl->t > 0 && c->hctl->converged) { fill_info(c, out); return DOPE_OK; }
     const int32_t limit = c->p.max_iter;
     HIP_TRY(c, dope::launch_ctl_setup(c->ctl, limit, 1, 0, c->stream), "control setup launch");
-    // One iteration per readback: no launch is ever enqueued past the stopping rule.
+    // Iterations are enqueued in chunks of 2, 2, 4, 8, ... with one readback per chunk.  An iteration enqueued
+    // after the stopping rule held is skipped on the device (Ctl::halted), so the result is that of one
+    // iteration per readback; only a few empty launches are spent.
+    int chunk = 2, n_chunks = 0;
     while (c->hctl->t < limit) {
-        st = enqueue_iterations(c, 1);
+        const int count = std::min(chunk, limit - c->hctl->t);
+        st = enqueue_iterations(c, count);
         if (st != DOPE_OK) return st;
         st = sync_ctl(c);
         if (st != DOPE_OK) return st;
         if (c->hctl->halted) break;
+        if (++n_chunks >= 2) chunk = std::min(2 * chunk, 64);
     }
     fill_info(c, out);
     if (c->hctl->status != 0)

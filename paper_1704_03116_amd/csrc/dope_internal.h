@@ -97,7 +97,7 @@ constexpr int CHUNK = 256;
 struct Img {
     Geom g;
     const int32_t *u, *w, *cw, *btab;
-    const int32_t *blist;      // block-major indices of the copies that are not interior to their block
+    const int2 *blist;         // (block-major index, block) of the copies that are not interior to their block
     const int32_t *chunk_k0;   // block of the first entry of every CHUNK entries of blist
     int32_t *Y, *A0, *A1, *stats;
     uint8_t *yhat;

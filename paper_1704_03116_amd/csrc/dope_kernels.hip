@@ -58,19 +58,22 @@ struct AxCov {
     int thi, cnt;
 };
 
-__device__ __forceinline__ AxCov axis_cov(const Axis &a, int x) {
-    if (x < 0 || x >= a.N) return AxCov{0, 0};
-    int th = x / a.s;
-    if (th > a.nb - 1) th = a.nb - 1;
-    const int two = (th >= 1 && x < (th - 1) * a.s + a.B) ? 1 : 0;
-    return AxCov{th, 1 + two};
+// Covers of x - 1, x and x + 1 (0 <= x < N) from one division: floor((x -+ 1) / s) differs from floor(x / s)
+// only when x sits on the first / last coordinate of a stride period.
+__device__ __forceinline__ void axis_cov3(const Axis &a, int x, AxCov c[3]) {
+    const int tr = x / a.s;
+    const int rem = x - tr * a.s;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int xx = x + t - 1;
+        int th = t == 0 ? tr - (rem == 0 ? 1 : 0) : (t == 2 ? tr + (rem == a.s - 1 ? 1 : 0) : tr);
+        if (th > a.nb - 1) th = a.nb - 1;
+        const int two = (th >= 1 && xx < (th - 1) * a.s + a.B) ? 1 : 0;
+        c[t] = (xx < 0 || xx >= a.N) ? AxCov{0, 0} : AxCov{th, 1 + two};
+    }
 }
 
 __device__ __forceinline__ bool in_axis(const AxCov &c, int t) { return t == c.thi || (c.cnt == 2 && t == c.thi - 1); }
-
-__device__ __forceinline__ int q_at(const Geom &g, int x, int y, int z) {
-    return axis_cov(g.ax[0], x).cnt * axis_cov(g.ax[1], y).cnt * axis_cov(g.ax[2], z).cnt;
-}
 
 __device__ __forceinline__ bool in_grid(const Geom &g, int x, int y, int z) {
     return x >= 0 && x < g.W && y >= 0 && y < g.H && z >= 0 && z < g.D;
@@ -122,12 +125,10 @@ __device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__r
         }
     }
     AxCov cx[3], cy[3], cz[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        cx[t] = axis_cov(g.ax[0], gx + t - 1);
-        cy[t] = axis_cov(g.ax[1], gy + t - 1);
-        cz[t] = CONN == 6 ? axis_cov(g.ax[2], gz + t - 1) : AxCov{0, 1};
-    }
+    axis_cov3(g.ax[0], gx, cx);
+    axis_cov3(g.ax[1], gy, cy);
+    if (CONN == 6) axis_cov3(g.ax[2], gz, cz);
+    else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
     const int qi = cx[1].cnt * cy[1].cnt * cz[1].cnt;
     int64_t G = 0;
     sumc = 0;
@@ -149,7 +150,7 @@ __device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__r
         }
     }
     const int64_t mu_term = (M << 14) * int64_t(a_ki - Yi + Y_HALF);
-    return int64_t(ui) * int64_t(16384 / qi) + ((G + mu_term) >> 16);
+    return int64_t(ui) * int64_t(16384 >> __builtin_ctz(unsigned(qi))) + ((G + mu_term) >> 16);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -392,9 +393,11 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     constexpr int H = Sten<CONN>::H;
     const Geom &g = im.g;
     const Ctl *ctl = im.ctl;
-    const int32_t *bt = im.btab + BTAB_STRIDE * k;
-    const int x0 = bt[0], y0 = bt[1], z0 = bt[2], ex = bt[3], ey = bt[4], ez = bt[5];
-    const int64_t off = bt[6];
+    // block geometry from the closed-form partition (no table load on the critical path)
+    const int kx = k % g.ax[0].nb, ky = (k / g.ax[0].nb) % g.ax[1].nb, kz = k / (g.ax[0].nb * g.ax[1].nb);
+    const int x0 = kx * g.ax[0].s, y0 = ky * g.ax[1].s, z0 = kz * g.ax[2].s;
+    const int ex = axis_ext(g.ax[0], kx), ey = axis_ext(g.ax[1], ky), ez = axis_ext(g.ax[2], kz);
+    const int64_t off = block_offset(g, kx, ky, kz);
     const int np = ex * ey * ez;
     const int32_t *Ain = (ctl->t & 1) ? im.A1 : im.A0;
     const int64_t M = ctl->M;
@@ -456,7 +459,6 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
 
     // ---- labels; consensus and multipliers of the pixels interior to this block (Eq. 10 reduces to
     //      Y = 2^16 yhat + A and Eq. 11 to A = 0 there, and no other block reads them) ----
-    const int tx = k % g.ax[0].nb, ty = (k / g.ax[0].nb) % g.ax[1].nb, tz = k / (g.ax[0].nb * g.ax[1].nb);
     int32_t *Aout = (ctl->t & 1) ? im.A0 : im.A1;
     unsigned long long r2 = 0;
     bool ovf = false;
@@ -465,7 +467,7 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         const int yv = (sb & ST_FIXED) ? ((sb & ST_LABEL) ? 1 : 0) : ((sb & ST_MARK) ? 1 : 0);
         im.yhat[off + p] = uint8_t(yv);
         const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
-        if (is_interior(g, tx, ty, tz, x0 + lx, y0 + ly, z0 + lz)) {
+        if (is_interior(g, kx, ky, kz, x0 + lx, y0 + ly, z0 + lz)) {
             const int64_t Yn = int64_t(yv) * Y_ONE + Ain[off + p];
             if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = true;
             const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
@@ -492,12 +494,19 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
 }
 
 // Persistent block-solve launch: every workgroup takes (image, block) items from the device work queue until it
-// is empty, so blocks of many images of uneven sizes and uneven max-flow cost share one launch.
+// is empty, so blocks of many images of uneven sizes and uneven max-flow cost share one launch.  With one
+// workgroup per item (direct != 0) workgroup b takes item b and the queue is not touched.
 template <int CONN, int NT>
 __global__ __launch_bounds__(NT) void k_block_solve(const Img *__restrict__ imgs, const Item *__restrict__ items,
                                                     int32_t n_items, Queue *queue, int32_t npmax,
-                                                    int32_t round_limit, int32_t relabel_period) {
+                                                    int32_t round_limit, int32_t relabel_period, int32_t direct) {
     extern __shared__ __align__(16) unsigned char smem[];
+    if (direct) {
+        const Item wi = items[blockIdx.x];
+        const Img &im = imgs[wi.img];
+        if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period);
+        return;
+    }
     int *s_item = reinterpret_cast<int *>(smem) + 15;   // the block solver uses scalar slots 0..14
     for (;;) {
         if (threadIdx.x == 0) *s_item = int(atomicAdd(&queue->next, 1u));
@@ -671,7 +680,6 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
     if (ctl_skip(ctl)) return;
     const int32_t *__restrict__ cw = im.cw;
     const uint8_t *__restrict__ yhat = im.yhat;
-    const int32_t *__restrict__ btab = im.btab;
     int32_t *__restrict__ Y = im.Y;
     int64_t *resid = im.resid;
     const int chunk = wi.idx;
@@ -693,23 +701,22 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
     int kk = kfirst;
     int64_t r2 = 0;
     if (li < im.n_blist) {
-        const int64_t c = im.blist[li];
-        while (kk + 1 < g.K && int64_t(btab[BTAB_STRIDE * (kk + 1) + 6]) <= c) ++kk;
-        const int32_t *bt = btab + BTAB_STRIDE * kk;
-        const int ex = bt[3], ey = bt[4];
-        const int p = int(c - bt[6]);
-        const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
-        const int gx = bt[0] + lx, gy = bt[1] + ly, gz = bt[2] + lz;
+        // the copy and its block; its coordinates follow from the closed-form block layout
+        const int2 rec = im.blist[li];
+        const int64_t c = rec.x;
+        kk = rec.y;
         const int kx = kk % AX.nb, ky = (kk / AX.nb) % AY.nb, kz = kk / (AX.nb * AY.nb);
+        const int ex = axis_ext(AX, kx), ey = axis_ext(AY, ky);
+        const int p = int(c - block_offset(g, kx, ky, kz));
+        const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
+        const int gx = kx * AX.s + lx, gy = ky * AY.s + ly, gz = kz * AZ.s + lz;
         const int64_t m = lin(g, gx, gy, gz);
         // block intervals of the coordinates x-1, x, x+1 along each axis (index 1 = m itself)
         AxCov cx[3], cy[3], cz[3];
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            cx[t] = axis_cov(AX, gx + t - 1);
-            cy[t] = axis_cov(AY, gy + t - 1);
-            cz[t] = NDIM == 3 ? axis_cov(AZ, gz + t - 1) : AxCov{0, 1};
-        }
+        axis_cov3(AX, gx, cx);
+        axis_cov3(AY, gy, cy);
+        if (NDIM == 3) axis_cov3(AZ, gz, cz);
+        else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
         const int qm = cx[1].cnt * cy[1].cnt * cz[1].cnt;
         // ---- every load of this copy is issued before any of them is used ----
         const int yk = yhat[c];
@@ -879,7 +886,13 @@ __global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict_
     if (gx >= g.W) return;
     const int gy = int(blockIdx.y) % g.H, gz = int(blockIdx.y) / g.H;
     const int64_t i = lin(g, gx, gy, gz);
-    const int qi = q_at(g, gx, gy, gz);
+    AxCov cx[3], cy[3], cz[3];
+    axis_cov3(g.ax[0], gx, cx);
+    axis_cov3(g.ax[1], gy, cy);
+    if (CONN == 6) axis_cov3(g.ax[2], gz, cz);
+    else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
+    // log2 q of this pixel (every cover count is 1 or 2)
+    const int lqi = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);
     int flags = 0;
     int64_t sum = 0;
 #pragma unroll
@@ -896,8 +909,8 @@ __global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict_
             if (wv != 0) flags |= FLAG_OFFGRID;
         } else if (wv != 0) {
             if (wv < 0) flags |= FLAG_NEGATIVE;
-            const int qq = qi * q_at(g, jx, jy, jz);
-            const int64_t cvv = int64_t(lam) * int64_t(wv) * int64_t(64 / qq);
+            const int lqj = (cx[v.x + 1].cnt - 1) + (cy[v.y + 1].cnt - 1) + (cz[v.z + 1].cnt - 1);
+            const int64_t cvv = int64_t(lam) * int64_t(wv) * int64_t(64 >> (lqi + lqj));   // 64 / (q_i q_j)
             if (cvv >= CAP_SUM_LIMIT || cvv <= -CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
             else c = int32_t(cvv);
             sum += cvv < 0 ? -cvv : cvv;
@@ -1039,7 +1052,8 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s) {
     const int32_t workers = grp.n_workers > 0 ? (grp.n_workers < grp.n_blk_items ? grp.n_workers : grp.n_blk_items)
                                               : grp.n_blk_items;
     hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(workers), dim3(NT), lds, s, grp.imgs, grp.blk_items,
-                       grp.n_blk_items, grp.queue, grp.npmax, round_limit, grp.npmax > 2048 ? 8 : 4);
+                       grp.n_blk_items, grp.queue, grp.npmax, round_limit, grp.npmax > 2048 ? 8 : 4,
+                       int32_t(workers == grp.n_blk_items ? 1 : 0));
     return hipGetLastError();
 }
 

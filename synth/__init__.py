@@ -21,6 +21,7 @@ from .configs import (  # noqa: F401
     config3,
     config4,
     config5_request,
+    config5_image,
     config5_trace,
     random_problem,
     lambda_q8,

@@ -207,6 +207,15 @@ def config5_request(r: int, mu0: int = DEFAULT_MU0_2D) -> Problem:
     H = int(rng.choice(SERVE_SIDES))
     W = int(_round(np.float64(H * rng.uniform(0.5, 2.0))))
     lam = float(rng.uniform(0.5, 3.0))
+    return _disk_request(rng, W, H, lam, f"config5_req{r}_{W}x{H}", mu0)
+
+
+def config5_image(W: int, H: int, lam: float = 1.5, seed: int = 0, mu0: int = DEFAULT_MU0_2D) -> Problem:
+    """A serving-style image of a chosen size (used to tune the block partition per image shape)."""
+    return _disk_request(np.random.default_rng(seed), W, H, lam, f"config5_image_{W}x{H}", mu0)
+
+
+def _disk_request(rng, W, H, lam, name, mu0) -> Problem:
     cx, cy = W / 2.0, H / 2.0
     rad = 20.0 * min(H, W) / 64.0
     yy, xx = np.mgrid[0:H, 0:W]
@@ -214,7 +223,7 @@ def config5_request(r: int, mu0: int = DEFAULT_MU0_2D) -> Problem:
     img = np.where(fg, 0.7, 0.3) + rng.normal(0.0, 0.15, size=(H, W))
     u = _gauss_llr(img, 0.7, 0.3, 0.15)
     w = _weights_from_features(img[None, :, :, None], 2, 8, 0.1)
-    return Problem(f"config5_req{r}_{W}x{H}", (W, H, 1), 2, 8, u.astype(np.int32), w, lambda_q8(lam),
+    return Problem(name, (W, H, 1), 2, 8, u.astype(np.int32), w, lambda_q8(lam),
                    (0, 0, 0), (0, 0, 0), mu0, truth=fg.reshape(-1).astype(np.uint8))
 
 
