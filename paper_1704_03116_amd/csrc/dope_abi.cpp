@@ -307,6 +307,9 @@ dope_status upload_tables(dope_ctx *c) {
         HIP_TRY(c, hipMemcpyAsync(c->chk_items, ci.data(), ci.size() * sizeof(dope::Item), hipMemcpyHostToDevice,
                                   c->stream), "item upload");
     HIP_TRY(c, hipMemcpyAsync(c->queue, &q, sizeof(q), hipMemcpyHostToDevice, c->stream), "queue upload");
+    // a zeroed loop control: the setup kernel initialises every field except the validation accumulator
+    const dope::Ctl zc{};
+    HIP_TRY(c, hipMemcpyAsync(c->ctl, &zc, sizeof(zc), hipMemcpyHostToDevice, c->stream), "control reset");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
     c->grp = dope::Group{c->dimg, 1, c->blk_items, c->g.K, c->chk_items, int32_t(ci.size()), c->queue,
                          c->g.conn, 0, c->g.max_np, 0};
@@ -480,16 +483,20 @@ dope_status enqueue_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int3
     if (mem_kind != DOPE_MEM_HOST && mem_kind != DOPE_MEM_DEVICE) return fail(c, DOPE_EINVAL, "bad mem_kind");
     dope_status st = ensure_workspace(c);
     if (st != DOPE_OK) return st;
-    const hipMemcpyKind kind = mem_kind == DOPE_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const Geom &g = c->g;
-    HIP_TRY(c, hipMemcpyAsync(c->u, u, size_t(g.n) * 4, kind, c->stream), "unary upload");
-    HIP_TRY(c, hipMemcpyAsync(c->w, w, size_t(g.n) * g.hs * 4, kind, c->stream), "weight upload");
+    // host inputs are uploaded into the workspace copies; device inputs are read (and copied) by the setup kernel
+    const int32_t *u_src = u, *w_src = w;
+    if (mem_kind == DOPE_MEM_HOST) {
+        HIP_TRY(c, hipMemcpyAsync(c->u, u, size_t(g.n) * 4, hipMemcpyHostToDevice, c->stream), "unary upload");
+        HIP_TRY(c, hipMemcpyAsync(c->w, w, size_t(g.n) * g.hs * 4, hipMemcpyHostToDevice, c->stream), "weight upload");
+        u_src = c->u;
+        w_src = c->w;
+    }
     const uint64_t eps2 = uint64_t(c->p.eps_q16) * uint64_t(c->p.eps_q16);
-    HIP_TRY(c, dope::launch_init_state(g, c->Y, c->A0, c->A1, c->yhat, c->resid, c->ctl, c->p.mu0, c->p.mu_fact_num,
-                                       c->p.mu_fact_den, eps2, c->stream),
-            "state init launch");
-    HIP_TRY(c, dope::launch_prep_weights(g, c->w, c->cw, lambda_q8, c->ctl, allow_negative, c->stream),
-            "weight prep launch");
+    HIP_TRY(c, dope::launch_setup(g, u_src, w_src, c->u, c->w, c->cw, lambda_q8, c->Y, c->A0, c->A1, c->yhat, c->resid,
+                                  c->ctl, c->p.mu0, c->p.mu_fact_num, c->p.mu_fact_den, eps2, allow_negative,
+                                  c->stream),
+            "setup launch");
     return DOPE_OK;
 }
 
@@ -518,7 +525,7 @@ dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int
     st = sync_ctl(c);
     if (st != DOPE_OK) return st;
     const Geom &g = c->g;
-    const int32_t flags = c->hctl->flags;
+    const int32_t flags = c->hctl->vflags;
     if (flags & dope::FLAG_OFFGRID) return fail(c, DOPE_EINVAL, "nonzero weight on an off-grid edge");
     if (flags & dope::FLAG_TOOBIG) return fail(c, DOPE_EINVAL, "weights too large: per-node sum |c_ij| >= 2^29");
     int solver = c->p.solver;
@@ -576,7 +583,7 @@ dope_status dope_iterate(dope_ctx *c, int32_t n_iter, dope_info *out) {
     if (st != DOPE_OK) return st;
     fill_info(c, out);
     if (c->hctl->status != 0)
-        return fail(c, dope_status(c->hctl->status), status_message(c->hctl->status, c->hctl->flags));
+        return fail(c, dope_status(c->hctl->status), status_message(c->hctl->status, c->hctl->vflags));
     return DOPE_OK;
 }
 
@@ -602,7 +609,7 @@ dope_status dope_solve(dope_ctx *c, dope_info *out) {
     }
     fill_info(c, out);
     if (c->hctl->status != 0)
-        return fail(c, dope_status(c->hctl->status), status_message(c->hctl->status, c->hctl->flags));
+        return fail(c, dope_status(c->hctl->status), status_message(c->hctl->status, c->hctl->vflags));
     return DOPE_OK;
 }
 

@@ -72,7 +72,8 @@ struct Ctl {
     int32_t solver_err;
     uint32_t wg_counter;       // last-workgroup detection in the consensus kernel
     int32_t mu_num, mu_den;
-    int32_t flags;             // set_energy validation bits (see FLAG_*)
+    int32_t flags;             // set_energy validation bits being accumulated (see FLAG_*); cleared by validation
+    int32_t vflags;            // validation bits of the last set_energy
 };
 
 enum : int32_t { FLAG_OFFGRID = 1, FLAG_NEGATIVE = 2, FLAG_TOOBIG = 4 };
@@ -140,11 +141,12 @@ hipError_t launch_solve_phase(const Group &grp, hipStream_t s);
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s);
 hipError_t launch_finalize_phase(const Group &grp, hipStream_t s);
 
-// c_ij from w and the validation verdict (status / halted set on the device when the energy is invalid).
-hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
-                               int32_t allow_negative, hipStream_t s);
-hipError_t launch_init_state(const Geom &g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid,
-                             Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2, hipStream_t s);
+// set_energy on the device: workspace copies of u and w (src != ws), c_ij, initial state and loop control, then
+// the validation verdict (status / halted set on the device when the energy is invalid).
+hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *w_ws,
+                        int32_t *cw, int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
+                        int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,
+                        int32_t allow_negative, hipStream_t s);
 hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy,
                             hipStream_t s);
 hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s);

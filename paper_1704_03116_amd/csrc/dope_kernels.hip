@@ -16,6 +16,13 @@ namespace dope {
 
 namespace {
 
+// Pointers read from an image descriptor are generic (flat) to the compiler.  Cast to the global address space
+// they give global loads and stores, which the scalar-load wait counter does not track, so gathers stay in flight
+// across the scalar loads of descriptor fields instead of being drained before each of them.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL T *gp(T *p) { return (GLOBAL T *)p; }
+
 enum : uint8_t { ST_FIXED = 1, ST_LABEL = 2, ST_MARK = 8 };
 constexpr int16_t H_INF = 0x7FFF;
 
@@ -84,7 +91,8 @@ __device__ __forceinline__ int64_t lin(const Geom &g, int x, int y, int z) {
 }
 
 __device__ __forceinline__ bool ctl_skip(const Ctl *ctl) {
-    return ctl->halted != 0 || ctl->t >= ctl->t_limit;
+    const GLOBAL Ctl *c = gp(ctl);
+    return c->halted != 0 || c->t >= c->t_limit;
 }
 
 // floor(n / M) for M >= 1 and |n| < 2^53: a double-precision estimate within +-2 of the quotient, then an exact
@@ -101,8 +109,9 @@ __device__ __forceinline__ int64_t floor_div_est(int64_t n, int64_t M, double in
 // cap_out[o] = c for in-block half-edges (0 otherwise); mask bit d set for in-block neighbours with c != 0;
 // sumc = sum of |c| over in-block neighbours.  All global loads are issued before any is used.
 template <int CONN>
-__device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__restrict__ u,
-                                               const int32_t *__restrict__ cw, const int32_t *__restrict__ Y,
+__device__ __forceinline__ int64_t block_unary(const Geom &g, const GLOBAL int32_t *__restrict__ u,
+                                               const GLOBAL int32_t *__restrict__ cw,
+                                               const GLOBAL int32_t *__restrict__ Y,
                                                int32_t a_ki, int64_t M, int gx, int gy, int gz, int lx, int ly,
                                                int lz, int ex, int ey, int ez, int32_t *cap_out, unsigned &mask,
                                                int64_t &sumc) {
@@ -111,19 +120,21 @@ __device__ __forceinline__ int64_t block_unary(const Geom &g, const int32_t *__r
     const int64_t i = lin(g, gx, gy, gz);
     const int32_t ui = u[i];
     const int32_t Yi = Y[i];
+    // unconditional loads (an off-grid neighbour reads pixel i itself and is masked afterwards)
     int32_t cv[ND], yj[ND];
+    bool ing[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
         const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
-        cv[d] = 0;
-        yj[d] = 0;
-        if (in_grid(g, jx, jy, jz)) {
-            const int64_t j = lin(g, jx, jy, jz);
-            cv[d] = (d < H) ? cw[int64_t(d) * g.n + i] : cw[int64_t(d - H) * g.n + j];
-            yj[d] = Y[j];
-        }
+        ing[d] = in_grid(g, jx, jy, jz);
+        const int64_t j = ing[d] ? lin(g, jx, jy, jz) : i;
+        cv[d] = (d < H) ? cw[int64_t(d) * g.n + i] : cw[int64_t(d - H) * g.n + j];
+        yj[d] = Y[j];
     }
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+        if (!ing[d]) cv[d] = 0;
     AxCov cx[3], cy[3], cz[3];
     axis_cov3(g.ax[0], gx, cx);
     axis_cov3(g.ax[1], gy, cy);
@@ -392,14 +403,14 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
                                               int32_t round_limit, int32_t relabel_period) {
     constexpr int H = Sten<CONN>::H;
     const Geom &g = im.g;
-    const Ctl *ctl = im.ctl;
+    const GLOBAL Ctl *ctl = gp(im.ctl);
     // block geometry from the closed-form partition (no table load on the critical path)
     const int kx = k % g.ax[0].nb, ky = (k / g.ax[0].nb) % g.ax[1].nb, kz = k / (g.ax[0].nb * g.ax[1].nb);
     const int x0 = kx * g.ax[0].s, y0 = ky * g.ax[1].s, z0 = kz * g.ax[2].s;
     const int ex = axis_ext(g.ax[0], kx), ey = axis_ext(g.ax[1], ky), ez = axis_ext(g.ax[2], kz);
     const int64_t off = block_offset(g, kx, ky, kz);
     const int np = ex * ey * ez;
-    const int32_t *Ain = (ctl->t & 1) ? im.A1 : im.A0;
+    const GLOBAL int32_t *Ain = gp((ctl->t & 1) ? im.A1 : im.A0);
     const int64_t M = ctl->M;
     const int tid = threadIdx.x;
 
@@ -427,8 +438,8 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         int32_t cp[H];
         unsigned m;
         int64_t sumc;
-        const int64_t Ut = block_unary<CONN>(g, im.u, im.cw, im.Y, Ain[off + p], M, x0 + lx, y0 + ly, z0 + lz,
-                                             lx, ly, lz, ex, ey, ez, cp, m, sumc);
+        const int64_t Ut = block_unary<CONN>(g, gp(im.u), gp(im.cw), gp(im.Y), Ain[off + p], M, x0 + lx, y0 + ly,
+                                             z0 + lz, lx, ly, lz, ex, ey, ez, cp, m, sumc);
 #pragma unroll
         for (int o = 0; o < H; ++o) {
             L.cap[o * npmax + p] = cp[o];
@@ -459,19 +470,21 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
 
     // ---- labels; consensus and multipliers of the pixels interior to this block (Eq. 10 reduces to
     //      Y = 2^16 yhat + A and Eq. 11 to A = 0 there, and no other block reads them) ----
-    int32_t *Aout = (ctl->t & 1) ? im.A0 : im.A1;
+    GLOBAL int32_t *Aout = gp((ctl->t & 1) ? im.A0 : im.A1);
+    GLOBAL uint8_t *yhat = gp(im.yhat);
+    GLOBAL int32_t *Yg = gp(im.Y);
     unsigned long long r2 = 0;
     bool ovf = false;
     for (int p = tid; p < np; p += NT) {
         const uint8_t sb = L.st[p];
         const int yv = (sb & ST_FIXED) ? ((sb & ST_LABEL) ? 1 : 0) : ((sb & ST_MARK) ? 1 : 0);
-        im.yhat[off + p] = uint8_t(yv);
+        yhat[off + p] = uint8_t(yv);
         const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
         if (is_interior(g, kx, ky, kz, x0 + lx, y0 + ly, z0 + lz)) {
             const int64_t Yn = int64_t(yv) * Y_ONE + Ain[off + p];
             if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = true;
             const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
-            im.Y[lin(g, x0 + lx, y0 + ly, z0 + lz)] = int32_t(Yc);
+            Yg[lin(g, x0 + lx, y0 + ly, z0 + lz)] = int32_t(Yc);
             Aout[off + p] = 0;
             const int64_t rr = int64_t(yv) * Y_ONE - Yc;
             r2 += (unsigned long long)(rr * rr);
@@ -481,15 +494,16 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     for (int sft = 32; sft >= 1; sft >>= 1) r2 += __shfl_xor(r2, sft);
     unsigned long long *s_r2 = reinterpret_cast<unsigned long long *>(s_ctr + 6);
     if ((tid & 63) == 0 && r2) atomicAdd(s_r2, r2);
-    if (ovf) atomicOr(&im.ctl->ovf_pending, 1);
+    if (ovf) atomicOr((int32_t *)gp(&im.ctl->ovf_pending), 1);
     __syncthreads();
     if (tid == 0) {
-        im.resid[k] = int64_t(*s_r2);    // the consensus kernel adds the other pixels of the block
-        im.stats[4 * k + 0] = nfree;
-        im.stats[4 * k + 1] = fs.rounds;
-        im.stats[4 * k + 2] = fs.grel;
-        im.stats[4 * k + 3] = fs.casc;
-        if (fs.fail) atomicOr(&im.ctl->solver_err, 1);
+        gp(im.resid)[k] = int64_t(*s_r2);    // the consensus kernel adds the other pixels of the block
+        GLOBAL int32_t *st = gp(im.stats) + 4 * k;
+        st[0] = nfree;
+        st[1] = fs.rounds;
+        st[2] = fs.grel;
+        st[3] = fs.casc;
+        if (fs.fail) atomicOr((int32_t *)gp(&im.ctl->solver_err), 1);
     }
 }
 
@@ -551,15 +565,15 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
         const int x0 = bt[0], y0 = bt[1], z0 = bt[2], ex = bt[3], ey = bt[4], ez = bt[5];
         off = bt[6];
         np = ex * ey * ez;
-        const int32_t *Ain = (ctl->t & 1) ? im.A1 : im.A0;
+        const GLOBAL int32_t *Ain = gp((ctl->t & 1) ? im.A1 : im.A0);
         if (lane < np) {
             const int p = lane;
             const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
             int32_t cp[H];
             unsigned m;
             int64_t sumc;
-            int64_t Ut = block_unary<CONN>(g, im.u, im.cw, im.Y, Ain[off + p], ctl->M, x0 + lx, y0 + ly, z0 + lz,
-                                           lx, ly, lz, ex, ey, ez, cp, m, sumc);
+            int64_t Ut = block_unary<CONN>(g, gp(im.u), gp(im.cw), gp(im.Y), Ain[off + p], gp(ctl)->M, x0 + lx,
+                                           y0 + ly, z0 + lz, lx, ly, lz, ex, ey, ez, cp, m, sumc);
             // clamping a strictly forced unary to +-(sum |c| + 1) keeps the minimiser set
             if (Ut > sumc + 1) Ut = sumc + 1;
             if (Ut < -sumc - 1) Ut = -sumc - 1;
@@ -629,18 +643,18 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
     unsigned long long r2 = 0;
     if (lane < np) {
         const int yv = int((bestc >> lane) & 1u);
-        im.yhat[off + lane] = uint8_t(yv);
+        gp(im.yhat)[off + lane] = uint8_t(yv);
         const int32_t *bt = im.btab + BTAB_STRIDE * k;
         const int ex = bt[3], ey = bt[4];
         const int lx = lane % ex, r = lane / ex, ly = r % ey, lz = r / ey;
         const int tx = k % g.ax[0].nb, ty = (k / g.ax[0].nb) % g.ax[1].nb, tz = k / (g.ax[0].nb * g.ax[1].nb);
         if (is_interior(g, tx, ty, tz, bt[0] + lx, bt[1] + ly, bt[2] + lz)) {
-            const int32_t *Ain = (ctl->t & 1) ? im.A1 : im.A0;
-            int32_t *Aout = (ctl->t & 1) ? im.A0 : im.A1;
+            const GLOBAL int32_t *Ain = gp((ctl->t & 1) ? im.A1 : im.A0);
+            GLOBAL int32_t *Aout = gp((ctl->t & 1) ? im.A0 : im.A1);
             const int64_t Yn = int64_t(yv) * Y_ONE + Ain[off + lane];
-            if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) atomicOr(&im.ctl->ovf_pending, 1);
+            if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) atomicOr((int32_t *)gp(&im.ctl->ovf_pending), 1);
             const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
-            im.Y[lin(g, bt[0] + lx, bt[1] + ly, bt[2] + lz)] = int32_t(Yc);
+            gp(im.Y)[lin(g, bt[0] + lx, bt[1] + ly, bt[2] + lz)] = int32_t(Yc);
             Aout[off + lane] = 0;
             const int64_t rr = int64_t(yv) * Y_ONE - Yc;
             r2 = (unsigned long long)(rr * rr);
@@ -649,11 +663,12 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
 #pragma unroll
     for (int sft = 32; sft >= 1; sft >>= 1) r2 += __shfl_xor(r2, sft);
     if (lane == 0) {
-        im.resid[k] = int64_t(r2);
-        im.stats[4 * k + 0] = np;
-        im.stats[4 * k + 1] = 0;
-        im.stats[4 * k + 2] = 0;
-        im.stats[4 * k + 3] = 0;
+        gp(im.resid)[k] = int64_t(r2);
+        GLOBAL int32_t *st = gp(im.stats) + 4 * k;
+        st[0] = np;
+        st[1] = 0;
+        st[2] = 0;
+        st[3] = 0;
     }
 }
 
@@ -673,26 +688,25 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
     constexpr int ND = 2 * H;
     constexpr int NDIM = CONN == 6 ? 3 : 2;
     constexpr int MAXC = 1 << NDIM;   // most blocks a pixel can lie in
+    static_assert(ND * MAXC <= 64, "neighbour-copy mask is 64 bits");
     const Item wi = items[blockIdx.x];
     const Img &im = imgs[wi.img];
     const Geom &g = im.g;
-    Ctl *ctl = im.ctl;
-    if (ctl_skip(ctl)) return;
-    const int32_t *__restrict__ cw = im.cw;
-    const uint8_t *__restrict__ yhat = im.yhat;
-    int32_t *__restrict__ Y = im.Y;
-    int64_t *resid = im.resid;
+    const GLOBAL Ctl *ctl = gp(im.ctl);
+    if (ctl_skip(im.ctl)) return;
+    const GLOBAL uint8_t *__restrict__ yhat = gp(im.yhat);
+    GLOBAL int32_t *__restrict__ Y = gp(im.Y);
     const int chunk = wi.idx;
     __shared__ unsigned long long s_res[CONS_NT];
     __shared__ int s_ovf;
     const int tid = threadIdx.x;
     const int par = ctl->t & 1;
-    const int32_t *Ain = par ? im.A1 : im.A0;
-    int32_t *Aout = par ? im.A0 : im.A1;
+    const GLOBAL int32_t *Ain = gp(par ? im.A1 : im.A0);
+    GLOBAL int32_t *Aout = gp(par ? im.A0 : im.A1);
     const int64_t M = ctl->M;
     const double invM = 1.0 / double(M);
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
-    const int kfirst = im.chunk_k0[chunk];
+    const int kfirst = gp(im.chunk_k0)[chunk];
     s_res[tid] = 0;
     if (tid == 0) s_ovf = 0;
     __syncthreads();
@@ -702,15 +716,15 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
     int64_t r2 = 0;
     if (li < im.n_blist) {
         // the copy and its block; its coordinates follow from the closed-form block layout
-        const int2 rec = im.blist[li];
-        const int64_t c = rec.x;
-        kk = rec.y;
+        const GLOBAL int32_t *rec = gp(reinterpret_cast<const int32_t *>(im.blist)) + 2 * li;
+        const int32_t c = rec[0];
+        kk = rec[1];
         const int kx = kk % AX.nb, ky = (kk / AX.nb) % AY.nb, kz = kk / (AX.nb * AY.nb);
         const int ex = axis_ext(AX, kx), ey = axis_ext(AY, ky);
         const int p = int(c - block_offset(g, kx, ky, kz));
         const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
         const int gx = kx * AX.s + lx, gy = ky * AY.s + ly, gz = kz * AZ.s + lz;
-        const int64_t m = lin(g, gx, gy, gz);
+        const int32_t m = int32_t(lin(g, gx, gy, gz));
         // block intervals of the coordinates x-1, x, x+1 along each axis (index 1 = m itself)
         AxCov cx[3], cy[3], cz[3];
         axis_cov3(AX, gx, cx);
@@ -718,55 +732,79 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
         if (NDIM == 3) axis_cov3(AZ, gz, cz);
         else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
         const int qm = cx[1].cnt * cy[1].cnt * cz[1].cnt;
+        // Block-major index of pixel (x, y, z) in block (tx, ty, tz), or this copy's own index when that block
+        // does not exist: every gather below is issued unconditionally and masked afterwards.
+        // Indices are below 2^31 (sum of block sizes, pixel count), so 32-bit offsets from a uniform base.  The
+        // index is computed for every candidate block in wrapping 32-bit arithmetic and replaced by this copy's
+        // own index when the block does not exist, so no branch separates the gathers.
+        const uint32_t s0 = uint32_t(g.span[0]), s1 = uint32_t(g.span[1]);
+        auto copy_at = [&](bool valid, int tx, int ty, int tz, int x, int y, int z) -> uint32_t {
+            const uint32_t ex_t = uint32_t(axis_ext(AX, tx)), ey_t = uint32_t(axis_ext(AY, ty));
+            const uint32_t ez_t = uint32_t(axis_ext(AZ, tz));
+            const uint32_t boff = uint32_t(tz) * uint32_t(AZ.B) * s1 * s0 +
+                                  ez_t * (uint32_t(ty) * uint32_t(AY.B) * s0 + ey_t * uint32_t(tx) * uint32_t(AX.B));
+            const uint32_t cc = boff + uint32_t(x - tx * AX.s) +
+                                ex_t * (uint32_t(y - ty * AY.s) + ey_t * uint32_t(z - tz * AZ.s));
+            uint32_t r = valid ? cc : uint32_t(c);
+            // optimisation barrier only (no instruction): keeps the compiler from turning the select back into a
+            // branch around the load, which would serialise the gathers
+            asm volatile("" : "+v"(r));
+            return r;
+        };
         // ---- every load of this copy is issued before any of them is used ----
-        const int yk = yhat[c];
-        const int32_t a_old = Ain[c];
+        const int yk = yhat[uint32_t(c)];
+        const int32_t a_old = Ain[uint32_t(c)];
         int yv_own[MAXC];
         int32_t a_own[MAXC];
+        bool v_own[MAXC];
 #pragma unroll
         for (int q = 0; q < MAXC; ++q) {
             const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
-            yv_own[q] = 0;
-            a_own[q] = 0;
-            if (e < cx[1].cnt && b < cy[1].cnt && a < cz[1].cnt) {
-                const int tx = cx[1].thi - e, ty = cy[1].thi - b, tz = cz[1].thi - a;
-                const int64_t cc = block_offset(g, tx, ty, tz) + (gx - tx * AX.s) +
-                                   int64_t(axis_ext(AX, tx)) * ((gy - ty * AY.s) + int64_t(axis_ext(AY, ty)) * (gz - tz * AZ.s));
-                yv_own[q] = yhat[cc];
-                a_own[q] = Ain[cc];
-            }
+            v_own[q] = e < cx[1].cnt && b < cy[1].cnt && a < cz[1].cnt;
+            const uint32_t cc = copy_at(v_own[q], cx[1].thi - e, cy[1].thi - b, cz[1].thi - a, gx, gy, gz);
+            yv_own[q] = yhat[cc];
+            a_own[q] = Ain[cc];
         }
         int32_t cwv[ND];
+        bool ing[ND];
         int yv_nb[ND][MAXC];
+        uint64_t nb_ok = 0;   // bit d * MAXC + q (< 48): copy q of neighbour d exists
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
             const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
-            const bool ing = in_grid(g, jx, jy, jz);
-            cwv[d] = 0;
-            if (ing) cwv[d] = (d < H) ? cw[int64_t(d) * g.n + m] : cw[int64_t(d - H) * g.n + lin(g, jx, jy, jz)];
+            ing[d] = in_grid(g, jx, jy, jz);
+            const uint32_t j = ing[d] ? uint32_t(lin(g, jx, jy, jz)) : uint32_t(m);
+            const GLOBAL int32_t *cwd = gp(im.cw) + int64_t(d < H ? d : d - H) * g.n;
+            cwv[d] = cwd[d < H ? uint32_t(m) : j];
             const AxCov &ax = cx[v.x + 1], &ay = cy[v.y + 1], &az = cz[v.z + 1];
 #pragma unroll
             for (int q = 0; q < MAXC; ++q) {
                 const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
-                yv_nb[d][q] = 0;
-                if (ing && e < ax.cnt && b < ay.cnt && a < az.cnt) {
-                    const int tx = ax.thi - e, ty = ay.thi - b, tz = az.thi - a;
-                    const int64_t cc = block_offset(g, tx, ty, tz) + (jx - tx * AX.s) +
-                                       int64_t(axis_ext(AX, tx)) * ((jy - ty * AY.s) + int64_t(axis_ext(AY, ty)) * (jz - tz * AZ.s));
-                    yv_nb[d][q] = yhat[cc];
-                }
+                const bool ok = ing[d] && e < ax.cnt && b < ay.cnt && a < az.cnt;
+                if (ok) nb_ok |= uint64_t(1) << (d * MAXC + q);
+                yv_nb[d][q] = yhat[copy_at(ok, ax.thi - e, ay.thi - b, az.thi - a, jx, jy, jz)];
             }
+        }
+#pragma unroll
+        for (int q = 0; q < MAXC; ++q)
+            if (!v_own[q]) { yv_own[q] = 0; a_own[q] = 0; }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            if (!ing[d]) cwv[d] = 0;
+#pragma unroll
+            for (int q = 0; q < MAXC; ++q)
+                if (!((nb_ok >> (d * MAXC + q)) & 1u)) yv_nb[d][q] = 0;
         }
         // ---- S_m and Hc_m ----
         int64_t S = 0, HC = 0;
 #pragma unroll
         for (int q = 0; q < MAXC; ++q) {
-            const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
-            if (!(e < cx[1].cnt && b < cy[1].cnt && a < cz[1].cnt)) continue;
+            if (!v_own[q]) continue;
             S += int64_t(yv_own[q]) * Y_ONE + a_own[q];
             if (!yv_own[q]) continue;
             // first term: sum_j c_mj (q_j - [j in k]) for this copy's block k
+            const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
             const int tx = cx[1].thi - e, ty = cy[1].thi - b, tz = cz[1].thi - a;
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
@@ -798,8 +836,8 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
         if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT || An >= STATE_LIMIT || An <= -STATE_LIMIT) ovf = 1;
         const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
         const int64_t Ac = An > STATE_LIMIT ? STATE_LIMIT : (An < -STATE_LIMIT ? -STATE_LIMIT : An);
-        Aout[c] = int32_t(Ac);
-        if (kx == cx[1].thi && ky == cy[1].thi && kz == cz[1].thi) Y[m] = int32_t(Yc);
+        Aout[uint32_t(c)] = int32_t(Ac);
+        if (kx == cx[1].thi && ky == cy[1].thi && kz == cz[1].thi) Y[uint32_t(m)] = int32_t(Yc);
         const int64_t rr = int64_t(yk) * Y_ONE - Yc;
         r2 = rr * rr;
     }
@@ -819,12 +857,12 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
     if (ovf) s_ovf = 1;
     __syncthreads();
     {
-        const int klast = (chunk + 1 < im.n_chunks) ? im.chunk_k0[chunk + 1] : g.K - 1;
+        const int klast = (chunk + 1 < im.n_chunks) ? gp(im.chunk_k0)[chunk + 1] : g.K - 1;
         const int span = min(klast - kfirst + 1, CONS_NT);
         for (int b = tid; b < span; b += CONS_NT)
-            if (s_res[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&resid[kfirst + b]), s_res[b]);
+            if (s_res[b]) atomicAdd((unsigned long long *)gp(im.resid + kfirst + b), s_res[b]);
     }
-    if (tid == 0 && s_ovf) atomicOr(&ctl->ovf_pending, 1);
+    if (tid == 0 && s_ovf) atomicOr((int32_t *)gp(&im.ctl->ovf_pending), 1);
 }
 
 // Loop control after the consensus of one iteration (a single workgroup): max_k r_k, stopping rule, overflow
@@ -833,13 +871,14 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
 __global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, Queue *queue) {
     if (blockIdx.x == 0 && threadIdx.x == 0) queue->next = 0;   // next iteration's block-solve queue
     const Img &im = imgs[blockIdx.x];
-    Ctl *ctl = im.ctl;
-    if (ctl_skip(ctl)) return;
+    GLOBAL Ctl *ctl = gp(im.ctl);
+    if (ctl_skip(im.ctl)) return;
     __shared__ unsigned long long s_max[4];
     const int tid = threadIdx.x;
     unsigned long long mx = 0;
+    const GLOBAL int64_t *resid = gp(im.resid);
     for (int k = tid; k < im.g.K; k += 256) {
-        const unsigned long long v = static_cast<unsigned long long>(im.resid[k]);
+        const unsigned long long v = static_cast<unsigned long long>(resid[k]);
         mx = v > mx ? v : mx;
     }
 #pragma unroll
@@ -864,10 +903,11 @@ __global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, 
         ctl->ovf_pending = 0;
         ctl->solver_err = 0;
         if (im.summary) {
-            im.summary[0] = ctl->t;
-            im.summary[1] = ctl->halted;
-            im.summary[2] = conv;
-            im.summary[3] = ctl->status;
+            GLOBAL int32_t *sm = gp(im.summary);
+            sm[0] = ctl->t;
+            sm[1] = ctl->halted;
+            sm[2] = conv;
+            sm[3] = ctl->status;
         }
     }
 }
@@ -876,15 +916,24 @@ __global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, 
 // Setup, labels and energy
 // ------------------------------------------------------------------------------------------------------------
 
-// c_ij = lambda_q8 w_ij 64 / (q_i q_j) for the half-stencil edges of every pixel, with validation: nonzero weight
-// on an off-grid edge, negative weight, and per-node sum_j |c_ij| >= 2^29 raise flags.  grid: (ceil(W/256), H*D).
+// Everything set_energy puts on the device, in one launch over the pixel grid (grid: (ceil(W/256), H*D)):
+//   - copies of u and w into the workspace (skipped when the source already is the workspace copy),
+//   - c_ij = lambda_q8 w_ij 64 / (q_i q_j) for the half-stencil edges of every pixel, with validation bits (nonzero
+//     weight on an off-grid edge, negative weight, per-node sum_j |c_ij| >= 2^29) OR-ed into ctl->flags,
+//   - the initial ADMM state (Y = 1/2, A = 0, yhat = 0, r_k = 0; a grid-stride pass over the block-major arrays),
+//   - the loop control (workgroup (0, 0)); ctl->flags is left alone: k_validate consumes and clears it.
+struct StateInit {
+    int64_t mu0;
+    uint64_t eps2;
+    int32_t mu_num, mu_den;
+};
+
 template <int CONN>
-__global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict__ w, int32_t *__restrict__ cw, int32_t lam,
-                                              Ctl *ctl) {
+__device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int gz, const int32_t *__restrict__ u_src,
+                                            const int32_t *__restrict__ w_src, int32_t *__restrict__ u_ws,
+                                            int32_t *__restrict__ w_ws, int32_t *__restrict__ cw, int32_t lam,
+                                            int32_t *__restrict__ Y, Ctl *ctl) {
     constexpr int H = Sten<CONN>::H;
-    const int gx = blockIdx.x * 256 + threadIdx.x;
-    if (gx >= g.W) return;
-    const int gy = int(blockIdx.y) % g.H, gz = int(blockIdx.y) / g.H;
     const int64_t i = lin(g, gx, gy, gz);
     AxCov cx[3], cy[3], cz[3];
     axis_cov3(g.ax[0], gx, cx);
@@ -893,17 +942,27 @@ __global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict_
     else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
     // log2 q of this pixel (every cover count is 1 or 2)
     const int lqi = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);
+    // all loads first (an off-grid neighbour reads pixel i itself and is masked); the edge's weight lives at the
+    // pixel holding its positive half-edge
+    const int32_t ui = u_src[i];
+    int32_t wl[2 * H];
+#pragma unroll
+    for (int d = 0; d < 2 * H; ++d) {
+        const int3 v = full_dir<CONN>(d);
+        const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
+        int64_t j = (d >= H && in_grid(g, jx, jy, jz)) ? lin(g, jx, jy, jz) : i;
+        asm volatile("" : "+v"(j));   // optimisation barrier only: keeps the loads unconditional
+        wl[d] = w_src[int64_t(d < H ? d : d - H) * g.n + j];
+    }
     int flags = 0;
     int64_t sum = 0;
+    int32_t cl[H];
 #pragma unroll
     for (int d = 0; d < 2 * H; ++d) {
         const int3 v = full_dir<CONN>(d);
         const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
         const bool ing = in_grid(g, jx, jy, jz);
-        // the edge's weight lives at the pixel holding its positive half-edge
-        int32_t wv;
-        if (d < H) wv = w[int64_t(d) * g.n + i];
-        else wv = ing ? w[int64_t(d - H) * g.n + lin(g, jx, jy, jz)] : 0;
+        const int32_t wv = (d < H || ing) ? wl[d] : 0;
         int32_t c = 0;
         if (!ing) {
             if (wv != 0) flags |= FLAG_OFFGRID;
@@ -915,51 +974,76 @@ __global__ __launch_bounds__(256) void k_prep(Geom g, const int32_t *__restrict_
             else c = int32_t(cvv);
             sum += cvv < 0 ? -cvv : cvv;
         }
-        if (d < H) cw[int64_t(d) * g.n + i] = c;
+        if (d < H) cl[d] = c;
     }
+#pragma unroll
+    for (int d = 0; d < H; ++d) cw[int64_t(d) * g.n + i] = cl[d];
+    if (w_src != w_ws) {
+#pragma unroll
+        for (int d = 0; d < H; ++d) w_ws[int64_t(d) * g.n + i] = wl[d];
+    }
+    if (u_src != u_ws) u_ws[i] = ui;
+    Y[i] = Y_HALF;
     if (sum >= CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
-    if (flags) atomicOr(&ctl->flags, flags);
+    if (flags) atomicOr((int32_t *)gp(&ctl->flags), flags);
 }
 
-// Energy validation verdict after k_prep: off-grid or oversized weights -> EINVAL; a negative weight when the
-// resolved solver is max-flow -> ENOTSUBMODULAR.  Stops the loop before any iteration runs.
+template <int CONN>
+__global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict__ u_src,
+                                               const int32_t *__restrict__ w_src, int32_t *__restrict__ u_ws,
+                                               int32_t *__restrict__ w_ws, int32_t *__restrict__ cw, int32_t lam,
+                                               int32_t *__restrict__ Y, int32_t *__restrict__ A0,
+                                               int32_t *__restrict__ A1, uint8_t *__restrict__ yhat,
+                                               int64_t *__restrict__ resid, Ctl *ctl, StateInit si) {
+    // block-major arrays and the loop control
+    {
+        const int64_t T = int64_t(gridDim.x) * gridDim.y * 256;
+        const int64_t t0 = (int64_t(blockIdx.y) * gridDim.x + blockIdx.x) * 256 + threadIdx.x;
+        for (int64_t i = t0; i < g.tot; i += T) { A0[i] = 0; A1[i] = 0; yhat[i] = 0; }
+        for (int64_t i = t0; i < g.K; i += T) resid[i] = 0;
+        if (t0 == 0) {
+            GLOBAL Ctl *c = gp(ctl);
+            c->M = si.mu0;
+            c->max_resid = 0;
+            c->last_max_resid = 0;
+            c->eps2 = si.eps2;
+            c->energy = 0;
+            c->t = 0;
+            c->t_limit = 0;
+            c->stop_on_converge = 0;
+            c->converged = 0;
+            c->halted = 0;
+            c->status = 0;
+            c->ovf_pending = 0;
+            c->solver_err = 0;
+            c->wg_counter = 0;
+            c->mu_num = si.mu_num;
+            c->mu_den = si.mu_den;
+            c->vflags = 0;
+        }
+    }
+    const int gx = blockIdx.x * 256 + threadIdx.x;
+    if (gx >= g.W) return;
+    const int rows = g.H * g.D;
+    for (int row = blockIdx.y; row < rows; row += gridDim.y)
+        setup_pixel<CONN>(g, gx, row % g.H, row / g.H, u_src, w_src, u_ws, w_ws, cw, lam, Y, ctl);
+}
+
+// Energy validation verdict after k_setup: off-grid or oversized weights -> EINVAL; a negative weight when the
+// resolved solver is max-flow -> ENOTSUBMODULAR.  Stops the loop before any iteration runs.  The accumulated bits
+// move to ctl->vflags (read by the host for the error message) and the accumulator is cleared for the next setup.
 __global__ void k_validate(Ctl *ctl, int32_t allow_negative) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int32_t f = ctl->flags;
+    GLOBAL Ctl *c = gp(ctl);
+    const int32_t f = c->flags;
+    c->vflags = f;
+    c->flags = 0;
     int32_t st = 0;
     if (f & (FLAG_OFFGRID | FLAG_TOOBIG)) st = -1;
     else if ((f & FLAG_NEGATIVE) && !allow_negative) st = -4;
     if (st) {
-        ctl->status = st;
-        ctl->halted = 1;
-    }
-}
-
-__global__ void k_init_state(Geom g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid, Ctl *ctl,
-                             int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2) {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = idx; i < g.n; i += stride) Y[i] = Y_HALF;
-    for (int64_t i = idx; i < g.tot; i += stride) { A0[i] = 0; A1[i] = 0; yhat[i] = 0; }
-    for (int64_t i = idx; i < g.K; i += stride) resid[i] = 0;
-    if (idx == 0) {
-        ctl->M = mu0;
-        ctl->max_resid = 0;
-        ctl->last_max_resid = 0;
-        ctl->eps2 = eps2;
-        ctl->energy = 0;
-        ctl->t = 0;
-        ctl->t_limit = 0;
-        ctl->stop_on_converge = 0;
-        ctl->converged = 0;
-        ctl->halted = 0;
-        ctl->status = 0;
-        ctl->ovf_pending = 0;
-        ctl->solver_err = 0;
-        ctl->wg_counter = 0;
-        ctl->mu_num = mu_num;
-        ctl->mu_den = mu_den;
-        ctl->flags = 0;
+        c->status = st;
+        c->halted = 1;
     }
 }
 
@@ -981,13 +1065,15 @@ __global__ void k_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge,
     }
 }
 
-// Labels [Y > 2^15].  grid: (ceil(W/256), H*D).
+// Labels [Y > 2^15].  grid: (ceil(W/256), rows), rows strided over H*D.
 __global__ __launch_bounds__(256) void k_labels(Geom g, const int32_t *__restrict__ Y, uint8_t *__restrict__ labels) {
     const int gx = blockIdx.x * 256 + threadIdx.x;
     if (gx >= g.W) return;
-    const int gy = int(blockIdx.y) % g.H, gz = int(blockIdx.y) / g.H;
-    const int64_t i = lin(g, gx, gy, gz);
-    labels[i] = uint8_t(Y[i] > Y_HALF);
+    const int rows = g.H * g.D;
+    for (int row = blockIdx.y; row < rows; row += gridDim.y) {
+        const int64_t i = int64_t(gx) + int64_t(g.W) * row;
+        labels[i] = uint8_t(Y[i] > Y_HALF);
+    }
 }
 
 constexpr int ENERGY_WGS = 256;
@@ -1036,6 +1122,11 @@ __global__ __launch_bounds__(256) void k_energy_sum(const int64_t *__restrict__ 
 }
 
 inline unsigned blocks_for(int64_t n, int nt) { return unsigned((n + nt - 1) / nt); }
+// Grid rows of the pixel kernels: one per image row up to the grid's y limit; kernels stride over the rest.
+inline unsigned row_blocks(const Geom &g) {
+    const int64_t rows = int64_t(g.H) * g.D;
+    return unsigned(rows < 65535 ? rows : 65535);
+}
 
 template <int CONN, int NT>
 hipError_t launch_maxflow(const Group &grp, hipStream_t s) {
@@ -1064,13 +1155,13 @@ hipError_t solve_phase(const Group &grp, hipStream_t s) {
                            grp.imgs, grp.blk_items, grp.n_blk_items);
         return hipGetLastError();
     }
-    // Workgroup size: blocks of more than 512 pixels use 1024 threads when about one block per CU is available
-    // (or when the LDS footprint allows only one block per CU), otherwise 512 threads so that three blocks share
-    // a CU and hide each other's barrier and LDS latency.  Measured on MI355X with 32x32 8-connected blocks:
-    // 289 blocks favour 1024 threads, 1089 blocks favour 512.
+    // Workgroup size: blocks of more than 512 pixels use 1024 threads when every block gets a CU of its own
+    // (or when the LDS footprint allows only one block per CU), otherwise 512 threads so that all blocks are
+    // resident at once and neighbours on a CU hide each other's barrier and LDS latency.  Measured on MI355X with
+    // 32x32 8-connected blocks: 289 and 1089 blocks both favour 512 threads.
     if (grp.npmax > 512) {
         const bool one_per_cu = maxflow_lds_bytes(grp.npmax, Sten<CONN>::H) > LDS_LIMIT / 2;
-        if (one_per_cu || grp.n_blk_items <= 2 * NUM_CUS) return launch_maxflow<CONN, 1024>(grp, s);
+        if (one_per_cu || grp.n_blk_items <= NUM_CUS) return launch_maxflow<CONN, 1024>(grp, s);
         return launch_maxflow<CONN, 512>(grp, s);
     }
     return launch_maxflow<CONN, 256>(grp, s);
@@ -1078,25 +1169,21 @@ hipError_t solve_phase(const Group &grp, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_prep_weights(const Geom &g, const int32_t *w, int32_t *cw, int32_t lam_q8, Ctl *ctl,
-                               int32_t allow_negative, hipStream_t s) {
-    const dim3 grid(blocks_for(g.W, 256), unsigned(g.H) * unsigned(g.D));
+hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *w_ws,
+                        int32_t *cw, int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
+                        int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,
+                        int32_t allow_negative, hipStream_t s) {
+    const dim3 grid(blocks_for(g.W, 256), row_blocks(g));
+    const StateInit si{mu0, eps2, mu_num, mu_den};
     switch (g.conn) {
-        case 4: hipLaunchKernelGGL(k_prep<4>, grid, dim3(256), 0, s, g, w, cw, lam_q8, ctl); break;
-        case 8: hipLaunchKernelGGL(k_prep<8>, grid, dim3(256), 0, s, g, w, cw, lam_q8, ctl); break;
-        default: hipLaunchKernelGGL(k_prep<6>, grid, dim3(256), 0, s, g, w, cw, lam_q8, ctl); break;
+        case 4: hipLaunchKernelGGL(k_setup<4>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, w_ws, cw, lam_q8, Y, A0,
+                                   A1, yhat, resid, ctl, si); break;
+        case 8: hipLaunchKernelGGL(k_setup<8>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, w_ws, cw, lam_q8, Y, A0,
+                                   A1, yhat, resid, ctl, si); break;
+        default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, w_ws, cw, lam_q8, Y,
+                                    A0, A1, yhat, resid, ctl, si); break;
     }
     hipLaunchKernelGGL(k_validate, dim3(1), dim3(64), 0, s, ctl, allow_negative);
-    return hipGetLastError();
-}
-
-hipError_t launch_init_state(const Geom &g, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid,
-                             Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2, hipStream_t s) {
-    int64_t m = g.n > g.tot ? g.n : g.tot;
-    unsigned nb = blocks_for(m, 256);
-    if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_init_state, dim3(nb), dim3(256), 0, s, g, Y, A0, A1, yhat, resid, ctl, mu0, mu_num, mu_den,
-                       eps2);
     return hipGetLastError();
 }
 
@@ -1142,7 +1229,7 @@ hipError_t launch_iteration(const Group &grp, hipStream_t s) {
 }
 
 hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s) {
-    const dim3 grid(blocks_for(g.W, 256), unsigned(g.H) * unsigned(g.D));
+    const dim3 grid(blocks_for(g.W, 256), row_blocks(g));
     hipLaunchKernelGGL(k_labels, grid, dim3(256), 0, s, g, Y, labels);
     return hipGetLastError();
 }
