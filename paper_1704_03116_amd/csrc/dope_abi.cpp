@@ -28,6 +28,7 @@ struct dope_ctx {
     size_t ws_bytes = 0;
     bool own_ws = false;
     Ctl *ctl = nullptr;
+    dope::Img himg{};          // host copy of the device image descriptor (kernel argument of one-image launches)
     int32_t *btab = nullptr, *u = nullptr, *w = nullptr, *cw = nullptr, *Y = nullptr, *A0 = nullptr, *A1 = nullptr;
     int32_t *stats = nullptr, *chunk_k0 = nullptr;
     int2 *blist = nullptr;
@@ -112,11 +113,11 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
         const int o = (p->ndim == 2 && a == 2) ? 0 : p->overlap[a];
         dope::Axis ax;
         if (B <= 0 || B >= N) {
-            ax = {N, N, N, 1};
+            ax = dope::make_axis(N, N, N, 1);
         } else {
             if (o < 0 || 2 * o > B) return "overlap must satisfy 0 <= o <= B/2";
             const int s = B - o;
-            ax = {N, B, s, 1 + (N - B + s - 1) / s};
+            ax = dope::make_axis(N, B, s, 1 + (N - B + s - 1) / s);
         }
         g.ax[a] = ax;
         K *= ax.nb;
@@ -296,6 +297,7 @@ dope_status upload_tables(dope_ctx *c) {
     // one-image launch group: descriptor, work items, zeroed queue (staged in host memory that stays alive
     // until the synchronisation at the end of this function)
     const dope::Img im = host_img(c);
+    c->himg = im;
     std::vector<dope::Item> bi(size_t(c->g.K)), ci(c->hchunk.size());
     for (size_t k = 0; k < bi.size(); ++k) bi[k] = dope::Item{0, int32_t(k)};
     for (size_t k = 0; k < ci.size(); ++k) ci[k] = dope::Item{0, int32_t(k)};
@@ -354,9 +356,12 @@ hipEvent_t next_event(std::vector<hipEvent_t> &pool, size_t idx) {
     return pool[idx];
 }
 
+// Enqueues count iterations after the c->hctl->t completed ones (the host mirror is current whenever this runs).
 dope_status enqueue_iterations(dope_ctx *c, int count) {
     c->grp.solver = c->solver;
+    c->grp.one = &c->himg;
     for (int it = 0; it < count; ++it) {
+        c->grp.par = (c->hctl->t + it) & 1;
         if (!c->profiling) {
             HIP_TRY(c, dope::launch_iteration(c->grp, c->stream), "iteration launch");
             continue;

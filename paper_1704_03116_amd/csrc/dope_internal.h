@@ -7,10 +7,17 @@
 namespace dope {
 
 // One axis of the block partition: length N, block edge B, stride s = B - o, count nb.
-// A single-block axis has B = s = N and nb = 1.
+// A single-block axis has B = s = N and nb = 1.  The reciprocals (of s, nb, B and the extent of the last block)
+// let kernels divide by these with a double-precision estimate and an integer fix-up (see qdiv).
 struct Axis {
     int32_t N, B, s, nb;
+    double inv_s, inv_nb, inv_B, inv_last;
 };
+
+inline Axis make_axis(int32_t N, int32_t B, int32_t s, int32_t nb) {
+    const int32_t last = N - (nb - 1) * s;
+    return Axis{N, B, s, nb, 1.0 / s, 1.0 / nb, 1.0 / B, 1.0 / (last < B ? last : B)};
+}
 
 struct Geom {
     Axis ax[3];
@@ -130,6 +137,10 @@ struct Group {
     Queue *queue;
     int32_t conn, solver, npmax;
     int32_t n_workers;   // workgroups of the persistent block-solve launch (0 = one per item)
+    // One-image groups: host copy of the image descriptor, passed to the kernels by value, and the multiplier
+    // buffer parity (t & 1) of the iteration being enqueued.  Null for batches (read from device memory).
+    const Img *one = nullptr;
+    int32_t par = 0;
 };
 
 // One ADMM iteration (block solves, consensus and multipliers, loop control) for every image of the group.

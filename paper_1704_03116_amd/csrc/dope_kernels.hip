@@ -65,11 +65,34 @@ struct AxCov {
     int thi, cnt;
 };
 
+// q = floor(n / d) and rem = n - q d for 0 <= n < 2^31 and d >= 1, given inv = 1.0 / d: the double-precision
+// estimate n * inv is within 2^-21 of n / d, so its truncation is q or q - 1 (q + 1 only in the limit) and one
+// integer fix-up makes it exact.  About ten instructions against some forty for an integer division.
+__device__ __forceinline__ int qdiv(int n, int d, double inv, int &rem) {
+    int q = int(double(n) * inv);
+    int r = n - q * d;
+    if (r < 0) { --q; r += d; }
+    else if (r >= d) { ++q; r -= d; }
+    rem = r;
+    return q;
+}
+
+// Reciprocal of the extent of block t along an axis (only the last block can be clipped).
+__device__ __forceinline__ double axis_inv_ext(const Axis &a, int t) { return t == a.nb - 1 ? a.inv_last : a.inv_B; }
+
+// Local coordinates of position p of a block with extents ex, ey (x fastest).
+__device__ __forceinline__ int3 block_local(int p, int ex, int ey, double inv_ex, double inv_ey) {
+    int lx, ly;
+    const int r = qdiv(p, ex, inv_ex, lx);
+    const int lz = qdiv(r, ey, inv_ey, ly);
+    return make_int3(lx, ly, lz);
+}
+
 // Covers of x - 1, x and x + 1 (0 <= x < N) from one division: floor((x -+ 1) / s) differs from floor(x / s)
 // only when x sits on the first / last coordinate of a stride period.
 __device__ __forceinline__ void axis_cov3(const Axis &a, int x, AxCov c[3]) {
-    const int tr = x / a.s;
-    const int rem = x - tr * a.s;
+    int rem;
+    const int tr = qdiv(x, a.s, a.inv_s, rem);
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         const int xx = x + t - 1;
@@ -105,63 +128,93 @@ __device__ __forceinline__ int64_t floor_div_est(int64_t n, int64_t M, double in
     return q;
 }
 
-// Eq. (8) unary of pixel p of block k (scaled by 2^14, unary floored) and the block-local edge data.
-// cap_out[o] = c for in-block half-edges (0 otherwise); mask bit d set for in-block neighbours with c != 0;
-// sumc = sum of |c| over in-block neighbours.  All global loads are issued before any is used.
+// Bit d set when full-stencil neighbour d of (x, y, z) lies inside [0, X) x [0, Y) x [0, Z) (the grid, or a
+// block in local coordinates).  The stencil is a compile-time constant, so this is six comparisons.
 template <int CONN>
-__device__ __forceinline__ int64_t block_unary(const Geom &g, const GLOBAL int32_t *__restrict__ u,
-                                               const GLOBAL int32_t *__restrict__ cw,
-                                               const GLOBAL int32_t *__restrict__ Y,
-                                               int32_t a_ki, int64_t M, int gx, int gy, int gz, int lx, int ly,
-                                               int lz, int ex, int ey, int ez, int32_t *cap_out, unsigned &mask,
-                                               int64_t &sumc) {
+__device__ __forceinline__ unsigned inside_mask(int x, int y, int z, int X, int Y, int Z) {
+    const bool xl = x > 0, xh = x < X - 1, yl = y > 0, yh = y < Y - 1, zl = z > 0, zh = z < Z - 1;
+    unsigned m = 0;
+#pragma unroll
+    for (int d = 0; d < 2 * Sten<CONN>::H; ++d) {
+        const int3 v = full_dir<CONN>(d);
+        const bool ok = (v.x < 0 ? xl : (v.x > 0 ? xh : true)) && (v.y < 0 ? yl : (v.y > 0 ? yh : true)) &&
+                        (v.z < 0 ? zl : (v.z > 0 ? zh : true));
+        m |= ok ? (1u << d) : 0u;
+    }
+    return m;
+}
+
+// Global inputs of the Eq. (8) unary of one block pixel: u_i, Y_i, the pixel's multiplier, c_ij and Y_j of its
+// full-stencil neighbours (bit d of ing: neighbour d is on the grid).
+template <int CONN>
+struct PixLoads {
+    static constexpr int ND = 2 * Sten<CONN>::H;
+    int32_t u, Y, a;
+    int32_t cv[ND], yj[ND];
+    unsigned ing;
+};
+
+// Issues every load of PixLoads without waiting for any (an off-grid neighbour reads pixel i itself and is
+// masked when the values are used).  Pixel and copy indices are below 2^31.
+template <int CONN>
+__device__ __forceinline__ void unary_loads(const Geom &g, const GLOBAL int32_t *__restrict__ u,
+                                            const GLOBAL int32_t *__restrict__ cw,
+                                            const GLOBAL int32_t *__restrict__ Y, const GLOBAL int32_t *__restrict__ A,
+                                            uint32_t ci, int gx, int gy, int gz, PixLoads<CONN> &ld) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
-    const int64_t i = lin(g, gx, gy, gz);
-    const int32_t ui = u[i];
-    const int32_t Yi = Y[i];
-    // unconditional loads (an off-grid neighbour reads pixel i itself and is masked afterwards)
-    int32_t cv[ND], yj[ND];
-    bool ing[ND];
+    const uint32_t i = uint32_t(gx) + uint32_t(g.W) * (uint32_t(gy) + uint32_t(g.H) * uint32_t(gz));
+    ld.ing = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
+    ld.u = u[i];
+    ld.Y = Y[i];
+    ld.a = A[ci];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
-        const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
-        ing[d] = in_grid(g, jx, jy, jz);
-        const int64_t j = ing[d] ? lin(g, jx, jy, jz) : i;
-        cv[d] = (d < H) ? cw[int64_t(d) * g.n + i] : cw[int64_t(d - H) * g.n + j];
-        yj[d] = Y[j];
+        const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
+        const uint32_t j = ((ld.ing >> d) & 1u) ? i + uint32_t(dl) : i;
+        const GLOBAL int32_t *cwo = cw + int64_t(d < H ? d : d - H) * g.n;
+        ld.cv[d] = cwo[d < H ? i : j];
+        ld.yj[d] = Y[j];
     }
-#pragma unroll
-    for (int d = 0; d < ND; ++d)
-        if (!ing[d]) cv[d] = 0;
+}
+
+// Eq. (8) unary of a block pixel (scaled by 2^14, unary floored) and its block-local edge data, from its loads.
+// cap_out[o] = c for in-block half-edges (0 otherwise); mask bit d set for in-block neighbours with c != 0;
+// sumc = sum of |c| over in-block neighbours.  q_j is a power of two, so (q_j - [j in k]) c (Y_i - Y_j) is a
+// 32 x 32 -> 64-bit product, a shift and a conditional subtraction.
+template <int CONN>
+__device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN> &ld, int64_t M, int gx, int gy,
+                                              int gz, int lx, int ly, int lz, int ex, int ey, int ez,
+                                              int32_t *cap_out, unsigned &mask, int64_t &sumc) {
+    constexpr int H = Sten<CONN>::H;
+    constexpr int ND = 2 * H;
     AxCov cx[3], cy[3], cz[3];
     axis_cov3(g.ax[0], gx, cx);
     axis_cov3(g.ax[1], gy, cy);
     if (CONN == 6) axis_cov3(g.ax[2], gz, cz);
     else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
-    const int qi = cx[1].cnt * cy[1].cnt * cz[1].cnt;
+    const int lqi = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);
+    const unsigned inb_m = inside_mask<CONN>(lx, ly, lz, ex, ey, ez);   // in the block implies on the grid
     int64_t G = 0;
     sumc = 0;
     mask = 0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
-        const int32_t c = cv[d];
-        if (d < H) cap_out[d] = 0;
-        if (c == 0) continue;
-        const int mx = lx + v.x, my = ly + v.y, mz = lz + v.z;
-        const bool inb = mx >= 0 && mx < ex && my >= 0 && my < ey && mz >= 0 && mz < ez;
-        const int qj = cx[v.x + 1].cnt * cy[v.y + 1].cnt * cz[v.z + 1].cnt;
-        G += int64_t(c) * int64_t(qj - (inb ? 1 : 0)) * int64_t(Yi - yj[d]);
-        if (inb) {
-            if (d < H) cap_out[d] = c;
+        const int32_t c = ((ld.ing >> d) & 1u) ? ld.cv[d] : 0;
+        const bool inb = (inb_m >> d) & 1u;
+        const int lqj = (cx[v.x + 1].cnt - 1) + (cy[v.y + 1].cnt - 1) + (cz[v.z + 1].cnt - 1);
+        const int64_t t = int64_t(c) * int64_t(ld.Y - ld.yj[d]);
+        G += (t << lqj) - (inb ? t : 0);
+        if (d < H) cap_out[d] = inb ? c : 0;
+        if (inb && c != 0) {
             sumc += c < 0 ? -int64_t(c) : int64_t(c);
             mask |= 1u << d;
         }
     }
-    const int64_t mu_term = (M << 14) * int64_t(a_ki - Yi + Y_HALF);
-    return int64_t(ui) * int64_t(16384 >> __builtin_ctz(unsigned(qi))) + ((G + mu_term) >> 16);
+    const int64_t mu_term = (M << 14) * int64_t(ld.a - ld.Y + Y_HALF);
+    return int64_t(ld.u) * int64_t(16384 >> lqi) + ((G + mu_term) >> 16);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -398,19 +451,23 @@ __device__ void flow_on_list(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
 // Free nodes up to this count are handled by one wavefront (wave-level synchronisation only).
 constexpr int WAVE_FLOW_MAX = 64;
 
+// par: multiplier buffer parity (t & 1), or -1 to read it from the loop control.  spec: the caller has not
+// checked the loop control; the gathers are issued first and the block stops before its first global store when
+// the iteration is skipped.
 template <int CONN, int NT>
 __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned char *smem, int32_t npmax,
-                                              int32_t round_limit, int32_t relabel_period) {
+                                              int32_t round_limit, int32_t relabel_period, int par, bool spec) {
     constexpr int H = Sten<CONN>::H;
     const Geom &g = im.g;
     const GLOBAL Ctl *ctl = gp(im.ctl);
+    const int parity = par >= 0 ? par : (ctl->t & 1);
     // block geometry from the closed-form partition (no table load on the critical path)
     const int kx = k % g.ax[0].nb, ky = (k / g.ax[0].nb) % g.ax[1].nb, kz = k / (g.ax[0].nb * g.ax[1].nb);
     const int x0 = kx * g.ax[0].s, y0 = ky * g.ax[1].s, z0 = kz * g.ax[2].s;
     const int ex = axis_ext(g.ax[0], kx), ey = axis_ext(g.ax[1], ky), ez = axis_ext(g.ax[2], kz);
     const int64_t off = block_offset(g, kx, ky, kz);
     const int np = ex * ey * ez;
-    const GLOBAL int32_t *Ain = gp((ctl->t & 1) ? im.A1 : im.A0);
+    const GLOBAL int32_t *Ain = gp(parity ? im.A1 : im.A0);
     const int64_t M = ctl->M;
     const int tid = threadIdx.x;
 
@@ -433,13 +490,17 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     __syncthreads();
 
     // ---- prologue: Eq. (8) unaries, in-block capacities, strictly forced nodes, list of the others ----
+    const GLOBAL int32_t *gu = gp(im.u), *gcw = gp(im.cw), *gY = gp(im.Y);
+    const double inv_ex = axis_inv_ext(g.ax[0], kx), inv_ey = axis_inv_ext(g.ax[1], ky);
     for (int p = tid; p < np; p += NT) {
-        const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
+        const int3 l = block_local(p, ex, ey, inv_ex, inv_ey);
+        PixLoads<CONN> ld;
+        unary_loads<CONN>(g, gu, gcw, gY, Ain, uint32_t(off + p), x0 + l.x, y0 + l.y, z0 + l.z, ld);
         int32_t cp[H];
         unsigned m;
         int64_t sumc;
-        const int64_t Ut = block_unary<CONN>(g, gp(im.u), gp(im.cw), gp(im.Y), Ain[off + p], M, x0 + lx, y0 + ly,
-                                             z0 + lz, lx, ly, lz, ex, ey, ez, cp, m, sumc);
+        const int64_t Ut = unary_from<CONN>(g, ld, M, x0 + l.x, y0 + l.y, z0 + l.z, l.x, l.y, l.z, ex, ey, ez, cp, m,
+                                            sumc);
 #pragma unroll
         for (int o = 0; o < H; ++o) {
             L.cap[o * npmax + p] = cp[o];
@@ -454,6 +515,7 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         if (!sbits) L.lst[atomicAdd(&s_ctr[1], 1)] = int16_t(p);
     }
     __syncthreads();
+    if (spec && ctl_skip(im.ctl)) return;   // uniform: every thread reads the same loop control
     const int nfree = s_ctr[1];
 
     FlowStats fs{0, 0, 0, false};
@@ -470,7 +532,7 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
 
     // ---- labels; consensus and multipliers of the pixels interior to this block (Eq. 10 reduces to
     //      Y = 2^16 yhat + A and Eq. 11 to A = 0 there, and no other block reads them) ----
-    GLOBAL int32_t *Aout = gp((ctl->t & 1) ? im.A0 : im.A1);
+    GLOBAL int32_t *Aout = gp(parity ? im.A0 : im.A1);
     GLOBAL uint8_t *yhat = gp(im.yhat);
     GLOBAL int32_t *Yg = gp(im.Y);
     unsigned long long r2 = 0;
@@ -479,7 +541,8 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         const uint8_t sb = L.st[p];
         const int yv = (sb & ST_FIXED) ? ((sb & ST_LABEL) ? 1 : 0) : ((sb & ST_MARK) ? 1 : 0);
         yhat[off + p] = uint8_t(yv);
-        const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
+        const int3 l = block_local(p, ex, ey, inv_ex, inv_ey);
+        const int lx = l.x, ly = l.y, lz = l.z;
         if (is_interior(g, kx, ky, kz, x0 + lx, y0 + ly, z0 + lz)) {
             const int64_t Yn = int64_t(yv) * Y_ONE + Ain[off + p];
             if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = true;
@@ -509,16 +572,23 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
 
 // Persistent block-solve launch: every workgroup takes (image, block) items from the device work queue until it
 // is empty, so blocks of many images of uneven sizes and uneven max-flow cost share one launch.  With one
-// workgroup per item (direct != 0) workgroup b takes item b and the queue is not touched.
+// workgroup per item (direct != 0) workgroup b takes item b and the queue is not touched.  A one-image launch
+// (one_par >= 0) gets the image descriptor and the multiplier parity as kernel arguments: workgroup b solves
+// block b, and no descriptor or loop-control load stands between the launch and the gathers.
 template <int CONN, int NT>
 __global__ __launch_bounds__(NT) void k_block_solve(const Img *__restrict__ imgs, const Item *__restrict__ items,
                                                     int32_t n_items, Queue *queue, int32_t npmax,
-                                                    int32_t round_limit, int32_t relabel_period, int32_t direct) {
+                                                    int32_t round_limit, int32_t relabel_period, int32_t direct,
+                                                    const Img one, int32_t one_par) {
     extern __shared__ __align__(16) unsigned char smem[];
+    if (one_par >= 0) {
+        block_maxflow<CONN, NT>(one, blockIdx.x, smem, npmax, round_limit, relabel_period, one_par, true);
+        return;
+    }
     if (direct) {
         const Item wi = items[blockIdx.x];
         const Img &im = imgs[wi.img];
-        if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period);
+        if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period, -1, false);
         return;
     }
     int *s_item = reinterpret_cast<int *>(smem) + 15;   // the block solver uses scalar slots 0..14
@@ -530,7 +600,7 @@ __global__ __launch_bounds__(NT) void k_block_solve(const Img *__restrict__ imgs
         if (it >= n_items) break;
         const Item wi = items[it];
         const Img &im = imgs[wi.img];
-        if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period);
+        if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period, -1, false);
         __syncthreads();   // the LDS of this item is reused by the next one
     }
 }
@@ -572,8 +642,11 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
             int32_t cp[H];
             unsigned m;
             int64_t sumc;
-            int64_t Ut = block_unary<CONN>(g, gp(im.u), gp(im.cw), gp(im.Y), Ain[off + p], gp(ctl)->M, x0 + lx,
-                                           y0 + ly, z0 + lz, lx, ly, lz, ex, ey, ez, cp, m, sumc);
+            PixLoads<CONN> ld;
+            unary_loads<CONN>(g, gp(im.u), gp(im.cw), gp(im.Y), Ain, uint32_t(off + p), x0 + lx, y0 + ly, z0 + lz,
+                              ld);
+            int64_t Ut = unary_from<CONN>(g, ld, gp(ctl)->M, x0 + lx, y0 + ly, z0 + lz, lx, ly, lz, ex, ey, ez, cp, m,
+                                          sumc);
             // clamping a strictly forced unary to +-(sum |c| + 1) keeps the minimiser set
             if (Ut > sumc + 1) Ut = sumc + 1;
             if (Ut < -sumc - 1) Ut = -sumc - 1;
@@ -683,24 +756,23 @@ constexpr int CONS_NT = CHUNK;   // block-pixel copies per workgroup
 // block with the highest index along every axis writes Y_m.  The last workgroup to finish reduces max_k r_k,
 // decides convergence / overflow, advances mu and t.
 template <int CONN>
-__global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ imgs, const Item *__restrict__ items) {
+__device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int par, bool spec) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
     constexpr int NDIM = CONN == 6 ? 3 : 2;
     constexpr int MAXC = 1 << NDIM;   // most blocks a pixel can lie in
     static_assert(ND * MAXC <= 64, "neighbour-copy mask is 64 bits");
-    const Item wi = items[blockIdx.x];
-    const Img &im = imgs[wi.img];
     const Geom &g = im.g;
     const GLOBAL Ctl *ctl = gp(im.ctl);
-    if (ctl_skip(im.ctl)) return;
+    if (!spec && ctl_skip(im.ctl)) return;
+    // speculative chunk: the loop control is read here but only the stores wait for it
+    const bool skip = spec && ctl_skip(im.ctl);
     const GLOBAL uint8_t *__restrict__ yhat = gp(im.yhat);
     GLOBAL int32_t *__restrict__ Y = gp(im.Y);
-    const int chunk = wi.idx;
     __shared__ unsigned long long s_res[CONS_NT];
     __shared__ int s_ovf;
     const int tid = threadIdx.x;
-    const int par = ctl->t & 1;
+    if (par < 0) par = ctl->t & 1;
     const GLOBAL int32_t *Ain = gp(par ? im.A1 : im.A0);
     GLOBAL int32_t *Aout = gp(par ? im.A0 : im.A1);
     const int64_t M = ctl->M;
@@ -719,10 +791,13 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
         const GLOBAL int32_t *rec = gp(reinterpret_cast<const int32_t *>(im.blist)) + 2 * li;
         const int32_t c = rec[0];
         kk = rec[1];
-        const int kx = kk % AX.nb, ky = (kk / AX.nb) % AY.nb, kz = kk / (AX.nb * AY.nb);
+        int kx, ky;
+        const int kyz = qdiv(kk, AX.nb, AX.inv_nb, kx);
+        const int kz = qdiv(kyz, AY.nb, AY.inv_nb, ky);
         const int ex = axis_ext(AX, kx), ey = axis_ext(AY, ky);
         const int p = int(c - block_offset(g, kx, ky, kz));
-        const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
+        const int3 l = block_local(p, ex, ey, axis_inv_ext(AX, kx), axis_inv_ext(AY, ky));
+        const int lx = l.x, ly = l.y, lz = l.z;
         const int gx = kx * AX.s + lx, gy = ky * AY.s + ly, gz = kz * AZ.s + lz;
         const int32_t m = int32_t(lin(g, gx, gy, gz));
         // block intervals of the coordinates x-1, x, x+1 along each axis (index 1 = m itself)
@@ -836,8 +911,10 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
         if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT || An >= STATE_LIMIT || An <= -STATE_LIMIT) ovf = 1;
         const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
         const int64_t Ac = An > STATE_LIMIT ? STATE_LIMIT : (An < -STATE_LIMIT ? -STATE_LIMIT : An);
-        Aout[uint32_t(c)] = int32_t(Ac);
-        if (kx == cx[1].thi && ky == cy[1].thi && kz == cz[1].thi) Y[uint32_t(m)] = int32_t(Yc);
+        if (!skip) {
+            Aout[uint32_t(c)] = int32_t(Ac);
+            if (kx == cx[1].thi && ky == cy[1].thi && kz == cz[1].thi) Y[uint32_t(m)] = int32_t(Yc);
+        }
         const int64_t rr = int64_t(yk) * Y_ONE - Yc;
         r2 = rr * rr;
     }
@@ -856,6 +933,7 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
     }
     if (ovf) s_ovf = 1;
     __syncthreads();
+    if (skip) return;   // uniform
     {
         const int klast = (chunk + 1 < im.n_chunks) ? gp(im.chunk_k0)[chunk + 1] : g.K - 1;
         const int span = min(klast - kfirst + 1, CONS_NT);
@@ -865,12 +943,23 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ i
     if (tid == 0 && s_ovf) atomicOr((int32_t *)gp(&im.ctl->ovf_pending), 1);
 }
 
+// One workgroup per 256-copy chunk of the boundary list.  A one-image launch (one_par >= 0) gets the descriptor
+// and the multiplier parity as kernel arguments.
+template <int CONN>
+__global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ imgs, const Item *__restrict__ items,
+                                                       const Img one, int32_t one_par) {
+    if (one_par >= 0) {
+        consensus_chunk<CONN>(one, int(blockIdx.x), one_par, true);
+        return;
+    }
+    const Item wi = items[blockIdx.x];
+    consensus_chunk<CONN>(imgs[wi.img], wi.idx, -1, false);
+}
+
 // Loop control after the consensus of one iteration (a single workgroup): max_k r_k, stopping rule, overflow
 // and solver errors, mu <- mu * mu_fact, t <- t + 1.  A separate launch instead of a last-workgroup handshake
 // inside k_consensus: a device-scope fence per workgroup costs L2 write-backs on every XCD.
-__global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, Queue *queue) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) queue->next = 0;   // next iteration's block-solve queue
-    const Img &im = imgs[blockIdx.x];
+__device__ __forceinline__ void finalize_image(const Img &im) {
     GLOBAL Ctl *ctl = gp(im.ctl);
     if (ctl_skip(im.ctl)) return;
     __shared__ unsigned long long s_max[4];
@@ -910,6 +999,14 @@ __global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, 
             sm[3] = ctl->status;
         }
     }
+}
+
+// One workgroup per image (one = the only image's descriptor when single != 0).
+__global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, Queue *queue, const Img one,
+                                                  int32_t single) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) queue->next = 0;   // next iteration's block-solve queue
+    if (single) finalize_image(one);
+    else finalize_image(imgs[blockIdx.x]);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -1142,9 +1239,12 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s) {
     const int32_t round_limit = 65536 + 64 * grp.npmax;
     const int32_t workers = grp.n_workers > 0 ? (grp.n_workers < grp.n_blk_items ? grp.n_workers : grp.n_blk_items)
                                               : grp.n_blk_items;
+    const int32_t direct = workers == grp.n_blk_items ? 1 : 0;
+    const Img one = grp.one ? *grp.one : Img{};
+    const int32_t one_par = (grp.one && direct) ? grp.par : -1;
     hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(workers), dim3(NT), lds, s, grp.imgs, grp.blk_items,
-                       grp.n_blk_items, grp.queue, grp.npmax, round_limit, grp.npmax > 2048 ? 8 : 4,
-                       int32_t(workers == grp.n_blk_items ? 1 : 0));
+                       grp.n_blk_items, grp.queue, grp.npmax, round_limit, grp.npmax > 2048 ? 8 : 4, direct, one,
+                       one_par);
     return hipGetLastError();
 }
 
@@ -1203,16 +1303,20 @@ hipError_t launch_solve_phase(const Group &grp, hipStream_t s) {
 
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s) {
     const dim3 grid(unsigned(grp.n_chk_items));
+    const Img one = grp.one ? *grp.one : Img{};
+    const int32_t one_par = grp.one ? grp.par : -1;
     if (grp.n_chk_items > 0) switch (grp.conn) {
-        case 4: hipLaunchKernelGGL(k_consensus<4>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
-        case 8: hipLaunchKernelGGL(k_consensus<8>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
-        default: hipLaunchKernelGGL(k_consensus<6>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items); break;
+        case 4: hipLaunchKernelGGL(k_consensus<4>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items, one, one_par); break;
+        case 8: hipLaunchKernelGGL(k_consensus<8>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items, one, one_par); break;
+        default: hipLaunchKernelGGL(k_consensus<6>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items, one, one_par); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_finalize_phase(const Group &grp, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(unsigned(grp.n_imgs)), dim3(256), 0, s, grp.imgs, grp.queue);
+    const Img one = grp.one ? *grp.one : Img{};
+    hipLaunchKernelGGL(k_finalize, dim3(unsigned(grp.n_imgs)), dim3(256), 0, s, grp.imgs, grp.queue, one,
+                       int32_t(grp.one ? 1 : 0));
     return hipGetLastError();
 }
 

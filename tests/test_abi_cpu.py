@@ -80,7 +80,7 @@ def _workspace_model(dims, h, K, tot, n_int):
     n = dims[0] * dims[1] * dims[2]
     nbl = tot - n_int
     chunks = (nbl + 255) // 256
-    return (a(128) + a(256) + a(8 * K) + a(8 * chunks) + a(256) + a(K * 32) + a(4 * chunks) + a(8 * nbl)
+    return (a(128) + a(512) + a(8 * K) + a(8 * chunks) + a(256) + a(K * 32) + a(4 * chunks) + a(8 * nbl)
             + a(4 * n) + 2 * a(4 * h * n) + a(4 * n) + 2 * a(4 * tot) + a(tot) + a(8 * K) + a(16 * K) + a(n)
             + a(8 * 256))
 
