@@ -64,7 +64,7 @@ Layout layout_for(const Geom &g) {
     L.ctl = take(sizeof(Ctl));
     L.img = take(sizeof(dope::Img));
     L.bitems = take(size_t(g.K) * sizeof(dope::Item));
-    const int64_t nbl = g.tot - g.n_interior;
+    const int64_t nbl = g.n - g.n_interior;   // boundary pixels
     L.citems = take(size_t((nbl + dope::CHUNK - 1) / dope::CHUNK) * sizeof(dope::Item));
     L.queue = take(sizeof(dope::Queue));
     L.btab = take(size_t(g.K) * dope::BTAB_STRIDE * 4);
@@ -198,12 +198,17 @@ thread_local std::string g_create_error;
 
 // blist = block-major indices of the copies that are not interior to their block (the consensus kernel's work;
 // interior copies are finished by the block-solve kernel); chunk[c] = block of blist entry c * CHUNK.
-// blist: (block-major index, block) of every copy that is not interior to its block, in block-major order;
-// chunk: block of the first entry of every CHUNK entries.
-void build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<int32_t> &blist,
+// Highest block index along an axis whose interval contains coordinate x.
+int top_block(const dope::Axis &a, int x) { return std::min(x / a.s, a.nb - 1); }
+
+// blist: (block-major index, block) of the owner copy of every pixel that is not interior to its block, in
+// block-major order; the owner copy is the one in the block with the highest index along every axis.  chunk:
+// block of the first entry of every CHUNK entries.  Every block owns at least one such pixel when there are two
+// or more blocks, so the owners within a chunk are consecutive block indices (checked).
+bool build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<int32_t> &blist,
                   std::vector<int32_t> &chunk) {
     blist.clear();
-    blist.reserve(2 * size_t(g.tot - g.n_interior));
+    blist.reserve(2 * size_t(g.n - g.n_interior));
     int64_t k = 0;
     for (int tz = 0; tz < g.ax[2].nb; ++tz)
         for (int ty = 0; ty < g.ax[1].nb; ++ty)
@@ -212,16 +217,24 @@ void build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<i
                 int32_t c = r[6];
                 for (int lz = 0; lz < r[5]; ++lz)
                     for (int ly = 0; ly < r[4]; ++ly)
-                        for (int lx = 0; lx < r[3]; ++lx, ++c)
-                            if (!dope::is_interior(g, tx, ty, tz, r[0] + lx, r[1] + ly, r[2] + lz)) {
-                                blist.push_back(c);
-                                blist.push_back(int32_t(k));
-                            }
+                        for (int lx = 0; lx < r[3]; ++lx, ++c) {
+                            const int x = r[0] + lx, y = r[1] + ly, z = r[2] + lz;
+                            if (dope::is_interior(g, tx, ty, tz, x, y, z)) continue;
+                            if (top_block(g.ax[0], x) != tx || top_block(g.ax[1], y) != ty ||
+                                top_block(g.ax[2], z) != tz)
+                                continue;
+                            blist.push_back(c);
+                            blist.push_back(int32_t(k));
+                        }
             }
     const size_t nbl = blist.size() / 2;
+    if (int64_t(nbl) != g.n - g.n_interior) return false;
+    for (size_t e = 1; e < nbl; ++e)
+        if (blist[2 * e + 1] - blist[2 * e - 1] > 1) return false;
     const size_t nch = (nbl + dope::CHUNK - 1) / dope::CHUNK;
     chunk.assign(nch, 0);
     for (size_t ch = 0; ch < nch; ++ch) chunk[ch] = blist[2 * ch * dope::CHUNK + 1];
+    return true;
 }
 
 dope_status fail(dope_ctx *c, dope_status s, const std::string &msg) {
@@ -415,7 +428,11 @@ dope_status dope_create(const dope_params *p, dope_ctx **out) {
     c->p = q;
     c->g = g;
     c->hbtab.swap(bt);
-    build_tables(c->g, c->hbtab, c->hblist, c->hchunk);
+    if (!build_tables(c->g, c->hbtab, c->hblist, c->hchunk)) {
+        g_create_error = "internal: boundary pixel table inconsistent with the partition";
+        delete c;
+        return DOPE_EINVAL;
+    }
     if (q.stream) {
         c->stream = static_cast<hipStream_t>(q.stream);
     } else {

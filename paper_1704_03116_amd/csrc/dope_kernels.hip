@@ -113,6 +113,17 @@ __device__ __forceinline__ int64_t lin(const Geom &g, int x, int y, int z) {
     return int64_t(x) + int64_t(g.W) * (int64_t(y) + int64_t(g.H) * int64_t(z));
 }
 
+// Workgroups of a launch are dispatched to the XCDs round-robin (workgroup b runs on XCD b % 8) and every XCD
+// has its own L2.  Workgroup b takes item xcd_item(b, n): XCD j gets the contiguous item range starting at
+// j * (n / 8) + min(j, n % 8), so neighbouring blocks or chunks, which read the same halo lines, share an L2
+// instead of fetching those lines once per XCD.  A bijection of [0, n).
+constexpr int NUM_XCDS = 8;
+__device__ __forceinline__ int xcd_item(int b, int n) {
+    const int j = b % NUM_XCDS, slot = b / NUM_XCDS;
+    const int base = n / NUM_XCDS, rem = n % NUM_XCDS;
+    return j * base + (j < rem ? j : rem) + slot;
+}
+
 __device__ __forceinline__ bool ctl_skip(const Ctl *ctl) {
     const GLOBAL Ctl *c = gp(ctl);
     return c->halted != 0 || c->t >= c->t_limit;
@@ -582,11 +593,12 @@ __global__ __launch_bounds__(NT) void k_block_solve(const Img *__restrict__ imgs
                                                     const Img one, int32_t one_par) {
     extern __shared__ __align__(16) unsigned char smem[];
     if (one_par >= 0) {
-        block_maxflow<CONN, NT>(one, blockIdx.x, smem, npmax, round_limit, relabel_period, one_par, true);
+        block_maxflow<CONN, NT>(one, xcd_item(blockIdx.x, gridDim.x), smem, npmax, round_limit, relabel_period,
+                                one_par, true);
         return;
     }
     if (direct) {
-        const Item wi = items[blockIdx.x];
+        const Item wi = items[xcd_item(blockIdx.x, gridDim.x)];
         const Img &im = imgs[wi.img];
         if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period, -1, false);
         return;
@@ -749,12 +761,13 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
 // Consensus (Eq. 10), multipliers (Eq. 11), residual and loop control
 // ------------------------------------------------------------------------------------------------------------
 
-constexpr int CONS_NT = CHUNK;   // block-pixel copies per workgroup
+constexpr int CONS_NT = CHUNK;   // boundary pixels per workgroup
 
-// One thread per block pixel (k, m): recomputes Y_m from every copy of m and of its stencil neighbours (each
-// copy of m computes the same value), writes its own multiplier A_k,m, and accumulates r_k.  The copy in the
-// block with the highest index along every axis writes Y_m.  The last workgroup to finish reduces max_k r_k,
-// decides convergence / overflow, advances mu and t.
+// One thread per boundary pixel m (a pixel that is not interior to its block), listed through its owner copy:
+// the copy in the block with the highest index along every axis.  The thread gathers yhat and A of every copy
+// of m and yhat of every copy of its stencil neighbours, computes Y_m (Eq. 10) once, writes it, writes the
+// multiplier of every copy of m (Eq. 11), and adds (2^16 yhat_k,m - Y_m)^2 to r_k of each copy's block through
+// LDS slots (owner block, copy) that are flushed with one global atomic per slot.
 template <int CONN>
 __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int par, bool spec) {
     constexpr int H = Sten<CONN>::H;
@@ -769,7 +782,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     const bool skip = spec && ctl_skip(im.ctl);
     const GLOBAL uint8_t *__restrict__ yhat = gp(im.yhat);
     GLOBAL int32_t *__restrict__ Y = gp(im.Y);
-    __shared__ unsigned long long s_res[CONS_NT];
+    __shared__ unsigned long long s_res[CONS_NT * MAXC];   // slot (owner block - kfirst) * MAXC + copy
     __shared__ int s_ovf;
     const int tid = threadIdx.x;
     if (par < 0) par = ctl->t & 1;
@@ -779,15 +792,18 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     const double invM = 1.0 / double(M);
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
     const int kfirst = gp(im.chunk_k0)[chunk];
-    s_res[tid] = 0;
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q) s_res[q * CONS_NT + tid] = 0;
     if (tid == 0) s_ovf = 0;
     __syncthreads();
     const int64_t li = int64_t(chunk) * CONS_NT + tid;
     int ovf = 0;
     int kk = kfirst;
-    int64_t r2 = 0;
+    unsigned long long r2[MAXC];
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q) r2[q] = 0;
     if (li < im.n_blist) {
-        // the copy and its block; its coordinates follow from the closed-form block layout
+        // the owner copy and its block; the coordinates follow from the closed-form block layout
         const GLOBAL int32_t *rec = gp(reinterpret_cast<const int32_t *>(im.blist)) + 2 * li;
         const int32_t c = rec[0];
         kk = rec[1];
@@ -797,8 +813,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         const int ex = axis_ext(AX, kx), ey = axis_ext(AY, ky);
         const int p = int(c - block_offset(g, kx, ky, kz));
         const int3 l = block_local(p, ex, ey, axis_inv_ext(AX, kx), axis_inv_ext(AY, ky));
-        const int lx = l.x, ly = l.y, lz = l.z;
-        const int gx = kx * AX.s + lx, gy = ky * AY.s + ly, gz = kz * AZ.s + lz;
+        const int gx = kx * AX.s + l.x, gy = ky * AY.s + l.y, gz = kz * AZ.s + l.z;
         const int32_t m = int32_t(lin(g, gx, gy, gz));
         // block intervals of the coordinates x-1, x, x+1 along each axis (index 1 = m itself)
         AxCov cx[3], cy[3], cz[3];
@@ -807,11 +822,10 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         if (NDIM == 3) axis_cov3(AZ, gz, cz);
         else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
         const int qm = cx[1].cnt * cy[1].cnt * cz[1].cnt;
-        // Block-major index of pixel (x, y, z) in block (tx, ty, tz), or this copy's own index when that block
-        // does not exist: every gather below is issued unconditionally and masked afterwards.
-        // Indices are below 2^31 (sum of block sizes, pixel count), so 32-bit offsets from a uniform base.  The
-        // index is computed for every candidate block in wrapping 32-bit arithmetic and replaced by this copy's
-        // own index when the block does not exist, so no branch separates the gathers.
+        // Block-major index of pixel (x, y, z) in block (tx, ty, tz).  Indices are below 2^31 (sum of block
+        // sizes), so the index is computed for every candidate block in wrapping 32-bit arithmetic and replaced
+        // by the owner copy's index when that block does not exist: every gather is issued unconditionally and
+        // masked afterwards, with no branch between the gathers.
         const uint32_t s0 = uint32_t(g.span[0]), s1 = uint32_t(g.span[1]);
         auto copy_at = [&](bool valid, int tx, int ty, int tz, int x, int y, int z) -> uint32_t {
             const uint32_t ex_t = uint32_t(axis_ext(AX, tx)), ey_t = uint32_t(axis_ext(AY, ty));
@@ -826,19 +840,18 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             asm volatile("" : "+v"(r));
             return r;
         };
-        // ---- every load of this copy is issued before any of them is used ----
-        const int yk = yhat[uint32_t(c)];
-        const int32_t a_old = Ain[uint32_t(c)];
+        // ---- every load of this pixel is issued before any of them is used ----
         int yv_own[MAXC];
         int32_t a_own[MAXC];
+        uint32_t cc_own[MAXC];
         bool v_own[MAXC];
 #pragma unroll
         for (int q = 0; q < MAXC; ++q) {
             const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
             v_own[q] = e < cx[1].cnt && b < cy[1].cnt && a < cz[1].cnt;
-            const uint32_t cc = copy_at(v_own[q], cx[1].thi - e, cy[1].thi - b, cz[1].thi - a, gx, gy, gz);
-            yv_own[q] = yhat[cc];
-            a_own[q] = Ain[cc];
+            cc_own[q] = copy_at(v_own[q], cx[1].thi - e, cy[1].thi - b, cz[1].thi - a, gx, gy, gz);
+            yv_own[q] = yhat[cc_own[q]];
+            a_own[q] = Ain[cc_own[q]];
         }
         int32_t cwv[ND];
         bool ing[ND];
@@ -907,28 +920,35 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         // floor((M S - 4 Hc) / (M q)) = floor(floor((M S - 4 Hc) / M) / q), q a power of two
         int64_t Yn = floor_div_est(M * S - 4 * HC, M, invM);
         Yn >>= (qm == 1 ? 0 : qm == 2 ? 1 : qm == 4 ? 2 : 3);
-        const int64_t An = int64_t(a_old) + int64_t(yk) * Y_ONE - Yn;
-        if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT || An >= STATE_LIMIT || An <= -STATE_LIMIT) ovf = 1;
+        if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = 1;
         const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
-        const int64_t Ac = An > STATE_LIMIT ? STATE_LIMIT : (An < -STATE_LIMIT ? -STATE_LIMIT : An);
-        if (!skip) {
-            Aout[uint32_t(c)] = int32_t(Ac);
-            if (kx == cx[1].thi && ky == cy[1].thi && kz == cz[1].thi) Y[uint32_t(m)] = int32_t(Yc);
+        if (!skip) Y[uint32_t(m)] = int32_t(Yc);
+        // multipliers (Eq. 11) and residual terms of every copy
+#pragma unroll
+        for (int q = 0; q < MAXC; ++q) {
+            if (!v_own[q]) continue;
+            const int64_t An = int64_t(a_own[q]) + int64_t(yv_own[q]) * Y_ONE - Yn;
+            if (An >= STATE_LIMIT || An <= -STATE_LIMIT) ovf = 1;
+            const int64_t Ac = An > STATE_LIMIT ? STATE_LIMIT : (An < -STATE_LIMIT ? -STATE_LIMIT : An);
+            if (!skip) Aout[cc_own[q]] = int32_t(Ac);
+            const int64_t rr = int64_t(yv_own[q]) * Y_ONE - Yc;
+            r2[q] = (unsigned long long)(rr * rr);
         }
-        const int64_t rr = int64_t(yk) * Y_ONE - Yc;
-        r2 = rr * rr;
     }
-    // per-block residual: one LDS atomic per wavefront when all its lanes share a block
+    // residual slots: one wavefront reduction per copy index when all lanes share an owner, else LDS atomics
     {
         const int k0 = __shfl(kk, 0);
         const bool same = __all(kk == k0);
-        if (same) {
-            unsigned long long v = (unsigned long long)r2;
 #pragma unroll
-            for (int sft = 32; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft);
-            if ((tid & 63) == 0 && v) atomicAdd(&s_res[k0 - kfirst], v);
-        } else if (r2) {
-            atomicAdd(&s_res[kk - kfirst], (unsigned long long)r2);
+        for (int q = 0; q < MAXC; ++q) {
+            if (same) {
+                unsigned long long v = r2[q];
+#pragma unroll
+                for (int sft = 32; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft);
+                if ((tid & 63) == 0 && v) atomicAdd(&s_res[(k0 - kfirst) * MAXC + q], v);
+            } else if (r2[q]) {
+                atomicAdd(&s_res[(kk - kfirst) * MAXC + q], r2[q]);
+            }
         }
     }
     if (ovf) s_ovf = 1;
@@ -936,23 +956,29 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     if (skip) return;   // uniform
     {
         const int klast = (chunk + 1 < im.n_chunks) ? gp(im.chunk_k0)[chunk + 1] : g.K - 1;
-        const int span = min(klast - kfirst + 1, CONS_NT);
-        for (int b = tid; b < span; b += CONS_NT)
-            if (s_res[b]) atomicAdd((unsigned long long *)gp(im.resid + kfirst + b), s_res[b]);
+        const int span = min(klast - kfirst + 1, CONS_NT) * MAXC;
+        const int nbx = AX.nb, nbxy = AX.nb * AY.nb;
+        for (int b = tid; b < span; b += CONS_NT) {
+            if (!s_res[b]) continue;
+            const int q = b % MAXC;
+            const int kq = kfirst + b / MAXC - (q & 1) - ((q >> 1) & 1) * nbx - (q >> 2) * nbxy;
+            atomicAdd((unsigned long long *)gp(im.resid + kq), s_res[b]);
+        }
     }
     if (tid == 0 && s_ovf) atomicOr((int32_t *)gp(&im.ctl->ovf_pending), 1);
 }
 
-// One workgroup per 256-copy chunk of the boundary list.  A one-image launch (one_par >= 0) gets the descriptor
+// One workgroup per 256-pixel chunk of the boundary list.  A one-image launch (one_par >= 0) gets the descriptor
 // and the multiplier parity as kernel arguments.
 template <int CONN>
 __global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ imgs, const Item *__restrict__ items,
                                                        const Img one, int32_t one_par) {
+    const int b = xcd_item(blockIdx.x, gridDim.x);
     if (one_par >= 0) {
-        consensus_chunk<CONN>(one, int(blockIdx.x), one_par, true);
+        consensus_chunk<CONN>(one, b, one_par, true);
         return;
     }
-    const Item wi = items[blockIdx.x];
+    const Item wi = items[b];
     consensus_chunk<CONN>(imgs[wi.img], wi.idx, -1, false);
 }
 
