@@ -32,7 +32,7 @@ struct dope_ctx {
     int32_t *btab = nullptr, *u = nullptr, *w = nullptr, *cw = nullptr, *Y = nullptr, *A0 = nullptr, *A1 = nullptr;
     int32_t *stats = nullptr, *chunk_k0 = nullptr;
     int2 *blist = nullptr;
-    uint8_t *yhat = nullptr, *labels = nullptr;
+    uint8_t *yhat = nullptr, *yslot = nullptr, *labels = nullptr;
     int64_t *resid = nullptr, *epart = nullptr;
     Ctl *hctl = nullptr;       // pinned host mirror of the control block
     std::vector<int32_t> hbtab, hchunk, hblist;
@@ -52,7 +52,8 @@ struct dope_ctx {
 namespace {
 
 struct Layout {
-    size_t ctl, img, bitems, citems, queue, btab, chunk, blist, u, w, cw, Y, A0, A1, yhat, resid, stats, labels, epart, total;
+    size_t ctl, img, bitems, citems, queue, btab, chunk, blist, u, w, cw, Y, A0, A1, yhat, yslot, resid, stats, labels,
+        epart, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -77,6 +78,7 @@ Layout layout_for(const Geom &g) {
     L.A0 = take(size_t(g.tot) * 4);
     L.A1 = take(size_t(g.tot) * 4);
     L.yhat = take(size_t(g.tot));
+    L.yslot = take(size_t(g.n) * dope::slot_count(g));
     L.resid = take(size_t(g.K) * 8);
     L.stats = take(size_t(g.K) * 16);
     L.labels = take(size_t(g.n));
@@ -270,6 +272,7 @@ void assign_pointers(dope_ctx *c) {
     c->A0 = reinterpret_cast<int32_t *>(b + L.A0);
     c->A1 = reinterpret_cast<int32_t *>(b + L.A1);
     c->yhat = reinterpret_cast<uint8_t *>(b + L.yhat);
+    c->yslot = reinterpret_cast<uint8_t *>(b + L.yslot);
     c->resid = reinterpret_cast<int64_t *>(b + L.resid);
     c->stats = reinterpret_cast<int32_t *>(b + L.stats);
     c->labels = reinterpret_cast<uint8_t *>(b + L.labels);
@@ -290,6 +293,7 @@ dope::Img host_img(const dope_ctx *c) {
     im.A1 = c->A1;
     im.stats = c->stats;
     im.yhat = c->yhat;
+    im.yslot = c->yslot;
     im.resid = c->resid;
     im.ctl = c->ctl;
     im.summary = nullptr;

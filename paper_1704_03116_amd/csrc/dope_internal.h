@@ -57,6 +57,9 @@ inline __host__ __device__ int64_t block_offset(const Geom &g, int32_t tx, int32
     return Pz * g.span[1] * g.span[0] + Ez * (Py * g.span[0] + Ey * Px);
 }
 
+// Label slots per pixel (most blocks a pixel can lie in): 4 in 2D, 8 in 3D (6-connected volumes).
+inline __host__ __device__ int slot_count(const Geom &g) { return g.conn == 6 ? 8 : 4; }
+
 inline __host__ __device__ bool is_interior(const Geom &g, int32_t tx, int32_t ty, int32_t tz, int32_t x, int32_t y,
                                             int32_t z) {
     return axis_interior(g.ax[0], tx, x) && axis_interior(g.ax[1], ty, y) && axis_interior(g.ax[2], tz, z);
@@ -109,6 +112,9 @@ struct Img {
     const int32_t *chunk_k0;   // block of the first entry of every CHUNK entries of blist
     int32_t *Y, *A0, *A1, *stats;
     uint8_t *yhat;
+    // Block labels by pixel: slot_count(g) bytes per pixel; byte e + 2b + 4a of pixel (x, y, z) is the label of
+    // its copy in block (tx - e, ty - b, tz - a), (tx, ty, tz) the highest block containing it along each axis.
+    uint8_t *yslot;
     int64_t *resid;
     Ctl *ctl;
     int32_t *summary;   // optional: {t, halted, converged, status} written after every iteration

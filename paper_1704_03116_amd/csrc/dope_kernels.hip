@@ -12,6 +12,8 @@
 // halted, so the host can enqueue several iterations ahead without reading anything back.
 #include "dope_internal.h"
 
+#include <type_traits>
+
 namespace dope {
 
 namespace {
@@ -101,6 +103,15 @@ __device__ __forceinline__ void axis_cov3(const Axis &a, int x, AxCov c[3]) {
         const int two = (th >= 1 && xx < (th - 1) * a.s + a.B) ? 1 : 0;
         c[t] = (xx < 0 || xx >= a.N) ? AxCov{0, 0} : AxCov{th, 1 + two};
     }
+}
+
+// Label slot of the copy at local position (lx, ly, lz) of block (tx, ty, tz): e + 2b + 4a where e = 1 when the
+// pixel also lies in block tx + 1 (local x >= s and a next block exists), i.e. the copy is in block top_x - 1.
+__device__ __forceinline__ int label_slot(const Geom &g, int tx, int ty, int tz, int lx, int ly, int lz) {
+    const int e = (lx >= g.ax[0].s && tx < g.ax[0].nb - 1) ? 1 : 0;
+    const int b = (ly >= g.ax[1].s && ty < g.ax[1].nb - 1) ? 1 : 0;
+    const int a = (lz >= g.ax[2].s && tz < g.ax[2].nb - 1) ? 1 : 0;
+    return e + 2 * b + 4 * a;
 }
 
 __device__ __forceinline__ bool in_axis(const AxCov &c, int t) { return t == c.thi || (c.cnt == 2 && t == c.thi - 1); }
@@ -545,6 +556,8 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     //      Y = 2^16 yhat + A and Eq. 11 to A = 0 there, and no other block reads them) ----
     GLOBAL int32_t *Aout = gp(parity ? im.A0 : im.A1);
     GLOBAL uint8_t *yhat = gp(im.yhat);
+    GLOBAL uint8_t *yslot = gp(im.yslot);
+    const int nslot = CONN == 6 ? 8 : 4;
     GLOBAL int32_t *Yg = gp(im.Y);
     unsigned long long r2 = 0;
     bool ovf = false;
@@ -554,11 +567,13 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         yhat[off + p] = uint8_t(yv);
         const int3 l = block_local(p, ex, ey, inv_ex, inv_ey);
         const int lx = l.x, ly = l.y, lz = l.z;
+        const uint32_t m = uint32_t(x0 + lx) + uint32_t(g.W) * (uint32_t(y0 + ly) + uint32_t(g.H) * uint32_t(z0 + lz));
+        yslot[m * uint32_t(nslot) + uint32_t(label_slot(g, kx, ky, kz, lx, ly, lz))] = uint8_t(yv);
         if (is_interior(g, kx, ky, kz, x0 + lx, y0 + ly, z0 + lz)) {
             const int64_t Yn = int64_t(yv) * Y_ONE + Ain[off + p];
             if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = true;
             const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
-            Yg[lin(g, x0 + lx, y0 + ly, z0 + lz)] = int32_t(Yc);
+            Yg[m] = int32_t(Yc);
             Aout[off + p] = 0;
             const int64_t rr = int64_t(yv) * Y_ONE - Yc;
             r2 += (unsigned long long)(rr * rr);
@@ -733,6 +748,9 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
         const int ex = bt[3], ey = bt[4];
         const int lx = lane % ex, r = lane / ex, ly = r % ey, lz = r / ey;
         const int tx = k % g.ax[0].nb, ty = (k / g.ax[0].nb) % g.ax[1].nb, tz = k / (g.ax[0].nb * g.ax[1].nb);
+        const int nslot = CONN == 6 ? 8 : 4;
+        gp(im.yslot)[lin(g, bt[0] + lx, bt[1] + ly, bt[2] + lz) * nslot + label_slot(g, tx, ty, tz, lx, ly, lz)] =
+            uint8_t(yv);
         if (is_interior(g, tx, ty, tz, bt[0] + lx, bt[1] + ly, bt[2] + lz)) {
             const GLOBAL int32_t *Ain = gp((ctl->t & 1) ? im.A1 : im.A0);
             GLOBAL int32_t *Aout = gp((ctl->t & 1) ? im.A0 : im.A1);
@@ -774,13 +792,11 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     constexpr int ND = 2 * H;
     constexpr int NDIM = CONN == 6 ? 3 : 2;
     constexpr int MAXC = 1 << NDIM;   // most blocks a pixel can lie in
-    static_assert(ND * MAXC <= 64, "neighbour-copy mask is 64 bits");
     const Geom &g = im.g;
     const GLOBAL Ctl *ctl = gp(im.ctl);
     if (!spec && ctl_skip(im.ctl)) return;
     // speculative chunk: the loop control is read here but only the stores wait for it
     const bool skip = spec && ctl_skip(im.ctl);
-    const GLOBAL uint8_t *__restrict__ yhat = gp(im.yhat);
     GLOBAL int32_t *__restrict__ Y = gp(im.Y);
     __shared__ unsigned long long s_res[CONS_NT * MAXC];   // slot (owner block - kfirst) * MAXC + copy
     __shared__ int s_ovf;
@@ -840,8 +856,10 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             asm volatile("" : "+v"(r));
             return r;
         };
-        // ---- every load of this pixel is issued before any of them is used ----
-        int yv_own[MAXC];
+        // ---- every load of this pixel is issued before any of them is used: the multipliers of its copies
+        //      (block-major), its label slots and those of its stencil neighbours, and c_mj ----
+        using SlotWord = typename std::conditional<MAXC == 8, uint64_t, uint32_t>::type;
+        const GLOBAL SlotWord *ysl = reinterpret_cast<const GLOBAL SlotWord *>(gp(im.yslot));
         int32_t a_own[MAXC];
         uint32_t cc_own[MAXC];
         bool v_own[MAXC];
@@ -850,13 +868,12 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
             v_own[q] = e < cx[1].cnt && b < cy[1].cnt && a < cz[1].cnt;
             cc_own[q] = copy_at(v_own[q], cx[1].thi - e, cy[1].thi - b, cz[1].thi - a, gx, gy, gz);
-            yv_own[q] = yhat[cc_own[q]];
             a_own[q] = Ain[cc_own[q]];
         }
+        const SlotWord wm = ysl[uint32_t(m)];
         int32_t cwv[ND];
         bool ing[ND];
-        int yv_nb[ND][MAXC];
-        uint64_t nb_ok = 0;   // bit d * MAXC + q (< 48): copy q of neighbour d exists
+        SlotWord wj[ND];
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
@@ -865,58 +882,49 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             const uint32_t j = ing[d] ? uint32_t(lin(g, jx, jy, jz)) : uint32_t(m);
             const GLOBAL int32_t *cwd = gp(im.cw) + int64_t(d < H ? d : d - H) * g.n;
             cwv[d] = cwd[d < H ? uint32_t(m) : j];
-            const AxCov &ax = cx[v.x + 1], &ay = cy[v.y + 1], &az = cz[v.z + 1];
-#pragma unroll
-            for (int q = 0; q < MAXC; ++q) {
-                const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
-                const bool ok = ing[d] && e < ax.cnt && b < ay.cnt && a < az.cnt;
-                if (ok) nb_ok |= uint64_t(1) << (d * MAXC + q);
-                yv_nb[d][q] = yhat[copy_at(ok, ax.thi - e, ay.thi - b, az.thi - a, jx, jy, jz)];
-            }
+            wj[d] = ysl[j];
         }
-#pragma unroll
-        for (int q = 0; q < MAXC; ++q)
-            if (!v_own[q]) { yv_own[q] = 0; a_own[q] = 0; }
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            if (!ing[d]) cwv[d] = 0;
-#pragma unroll
-            for (int q = 0; q < MAXC; ++q)
-                if (!((nb_ok >> (d * MAXC + q)) & 1u)) yv_nb[d][q] = 0;
-        }
-        // ---- S_m and Hc_m ----
-        int64_t S = 0, HC = 0;
+        int yv_own[MAXC];
 #pragma unroll
         for (int q = 0; q < MAXC; ++q) {
-            if (!v_own[q]) continue;
-            S += int64_t(yv_own[q]) * Y_ONE + a_own[q];
-            if (!yv_own[q]) continue;
-            // first term: sum_j c_mj (q_j - [j in k]) for this copy's block k
-            const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
-            const int tx = cx[1].thi - e, ty = cy[1].thi - b, tz = cz[1].thi - a;
-#pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                const int3 v = full_dir<CONN>(d);
-                const AxCov &ax = cx[v.x + 1], &ay = cy[v.y + 1], &az = cz[v.z + 1];
-                // j lies in block (tx, ty, tz) iff that block is one of j's intervals on every axis
-                const bool inb = in_axis(ax, tx) && in_axis(ay, ty) && in_axis(az, tz);
-                HC += int64_t(cwv[d]) * (ax.cnt * ay.cnt * az.cnt - (inb ? 1 : 0));
-            }
+            yv_own[q] = v_own[q] ? int((wm >> (8 * q)) & 1u) : 0;
+            if (!v_own[q]) a_own[q] = 0;
         }
-        // second term: sum over copies of each neighbour j of (q_m - [m in that block]) c_jm
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+            if (!ing[d]) cwv[d] = 0;
+        // ---- S_m and Hc_m.  With Y1 = sum of this pixel's labels, Hc regroups exactly as
+        //      Hc = Y1 sum_j c_mj q_j - q_m sum_j c_mj (sum of j's labels)
+        //           - sum_j c_mj sum_{blocks b holding m and j} (yhat_b,m - yhat_b,j) ----
+        int64_t S = 0;
+        int Y1 = 0;
+#pragma unroll
+        for (int q = 0; q < MAXC; ++q) {
+            S += int64_t(yv_own[q]) * Y_ONE + a_own[q];
+            Y1 += yv_own[q];
+        }
+        int64_t CQ = 0, YJ = 0, SH = 0;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
             const AxCov &ax = cx[v.x + 1], &ay = cy[v.y + 1], &az = cz[v.z + 1];
+            int yj_sum = 0, shared = 0;
 #pragma unroll
             for (int q = 0; q < MAXC; ++q) {
-                if (!yv_nb[d][q]) continue;
                 const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
-                const int tx = ax.thi - e, ty = ay.thi - b, tz = az.thi - a;
-                const bool m_in = in_axis(cx[1], tx) && in_axis(cy[1], ty) && in_axis(cz[1], tz);
-                HC -= int64_t(qm - (m_in ? 1 : 0)) * int64_t(cwv[d]);
+                if (e < ax.cnt && b < ay.cnt && a < az.cnt) yj_sum += int((wj[d] >> (8 * q)) & 1u);
+                // own copy q in block (tx, ty, tz); when that block also holds j, compare with j's label there
+                const int tx = cx[1].thi - e, ty = cy[1].thi - b, tz = cz[1].thi - a;
+                if (v_own[q] && in_axis(ax, tx) && in_axis(ay, ty) && in_axis(az, tz)) {
+                    const int qj = (ax.thi - tx) + 2 * (ay.thi - ty) + 4 * (az.thi - tz);
+                    shared += yv_own[q] - int((wj[d] >> (8 * qj)) & 1u);
+                }
             }
+            CQ += int64_t(cwv[d]) * (ax.cnt * ay.cnt * az.cnt);
+            YJ += int64_t(cwv[d]) * yj_sum;
+            SH += int64_t(cwv[d]) * shared;
         }
+        const int64_t HC = int64_t(Y1) * CQ - int64_t(qm) * YJ - SH;
         // floor((M S - 4 Hc) / (M q)) = floor(floor((M S - 4 Hc) / M) / q), q a power of two
         int64_t Yn = floor_div_est(M * S - 4 * HC, M, invM);
         Yn >>= (qm == 1 ? 0 : qm == 2 ? 1 : qm == 4 ? 2 : 3);
