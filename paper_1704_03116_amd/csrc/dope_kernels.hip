@@ -260,6 +260,17 @@ struct BlockSync {
         phase = (phase + 1) % 3;
         return r;
     }
+    // OR of the two low bits of f over the workgroup (one barrier; one LDS atomic per wavefront)
+    __device__ __forceinline__ int bits(int f) {
+        int *sl = slots + phase;
+        const int w = (__any(f & 1) ? 1 : 0) | (__any(f & 2) ? 2 : 0);
+        if ((threadIdx.x & 63) == 0 && w) atomicOr(sl, w);
+        __syncthreads();
+        const int r = *sl;
+        if (threadIdx.x == 0) slots[(phase + 2) % 3] = 0;   // the slot of the call after next
+        phase = (phase + 1) % 3;
+        return r;
+    }
 };
 
 struct WaveSync {
@@ -272,6 +283,13 @@ struct WaveSync {
     __device__ __forceinline__ bool any(bool f) {
         sync();
         return __any(f ? 1 : 0) != 0;
+    }
+    __device__ __forceinline__ int bits(int f) {
+        sync();
+        int r = f;
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) r |= __shfl_xor(r, s);
+        return r;
     }
 };
 
@@ -325,8 +343,9 @@ __device__ void flow_on_list(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
     // (1) a node is forced when its unary, with the pairwise terms of its fixed neighbours folded in, exceeds the
     //     total capacity towards its free neighbours.  Forcing only grows as neighbours get fixed, so passes may
     //     see each other's updates in any order and still reach the same fixed point.
+    // bit 0 of the reduction: a node got fixed in this pass; bit 1: a node is still free after its visit
     for (;;) {
-        bool ch = false;
+        int ch = 0;
         for (int i = sy.idx; i < nfree; i += sy.step) {
             const int p = L.lst[i];
             if (L.st[p] & ST_FIXED) continue;
@@ -340,11 +359,17 @@ __device__ void flow_on_list(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
                     if (sv & ST_FIXED) U += (sv & ST_LABEL) ? -c : c;
                     else S += c;
                 }
-            if (U < -S) { L.st[p] = ST_FIXED | ST_LABEL; ch = true; }
-            else if (U > S) { L.st[p] = ST_FIXED; ch = true; }
+            if (U < -S) { L.st[p] = ST_FIXED | ST_LABEL; ch |= 1; }
+            else if (U > S) { L.st[p] = ST_FIXED; ch |= 1; }
+            else ch |= 2;
         }
         ++fs.casc;
-        if (!sy.any(ch)) break;
+        const int r = sy.bits(ch);
+        if (!(r & 1)) {
+            // a pass without changes: a node still free was seen free by this pass, so bit 1 is exact here
+            if (!(r & 2)) return;   // everything is forced: no flow network is left
+            break;
+        }
     }
     // (2) flow network of the remaining free nodes: source excess -U and sink capacity U in one signed value
     for (int i = sy.idx; i < nfree; i += sy.step) {
