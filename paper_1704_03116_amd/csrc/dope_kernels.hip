@@ -343,25 +343,36 @@ __device__ void flow_on_list(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
     // (1) a node is forced when its unary, with the pairwise terms of its fixed neighbours folded in, exceeds the
     //     total capacity towards its free neighbours.  Forcing only grows as neighbours get fixed, so passes may
     //     see each other's updates in any order and still reach the same fixed point.
-    // bit 0 of the reduction: a node got fixed in this pass; bit 1: a node is still free after its visit
+    //     Each wavefront repeats its share of the list until it stops changing before the workgroup-wide
+    //     reduction, so chains of forcings inside a wavefront's share cost no barrier.
+    //     Bit 0 of the reduction: a node got fixed in this pass; bit 1: a node was still free after its visit in
+    //     the wavefront's last sweep.
     for (;;) {
         int ch = 0;
-        for (int i = sy.idx; i < nfree; i += sy.step) {
-            const int p = L.lst[i];
-            if (L.st[p] & ST_FIXED) continue;
-            const unsigned m = L.msk[p];
-            int32_t U = L.dd[p], S = 0;
+        for (;;) {
+            int wch = 0;
+            for (int i = sy.idx; i < nfree; i += sy.step) {
+                const int p = L.lst[i];
+                if (L.st[p] & ST_FIXED) continue;
+                const unsigned m = L.msk[p];
+                int32_t U = L.dd[p], S = 0;
 #pragma unroll
-            for (int d = 0; d < ND; ++d)
-                if ((m >> d) & 1u) {
-                    const uint8_t sv = L.st[L.nbr(p, d)];
-                    const int32_t c = L.capd(p, d);
-                    if (sv & ST_FIXED) U += (sv & ST_LABEL) ? -c : c;
-                    else S += c;
-                }
-            if (U < -S) { L.st[p] = ST_FIXED | ST_LABEL; ch |= 1; }
-            else if (U > S) { L.st[p] = ST_FIXED; ch |= 1; }
-            else ch |= 2;
+                for (int d = 0; d < ND; ++d)
+                    if ((m >> d) & 1u) {
+                        const uint8_t sv = L.st[L.nbr(p, d)];
+                        const int32_t c = L.capd(p, d);
+                        if (sv & ST_FIXED) U += (sv & ST_LABEL) ? -c : c;
+                        else S += c;
+                    }
+                if (U < -S) { L.st[p] = ST_FIXED | ST_LABEL; wch |= 1; }
+                else if (U > S) { L.st[p] = ST_FIXED; wch |= 1; }
+                else wch |= 2;
+            }
+            if (!__any(wch & 1)) {
+                ch |= wch;     // this sweep's still-free bit is exact for the wavefront's share
+                break;
+            }
+            ch |= wch & 1;
         }
         ++fs.casc;
         const int r = sy.bits(ch);
