@@ -174,7 +174,8 @@ dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectiv
  * their block pixels, and one loop-control launch.  Each image keeps its own state, stopping rule, iteration cap
  * and error status, and its results are bit-identical to running it alone (Algorithm 1 applied per image).
  * All contexts must share connectivity and resolved solver and have their energy set; the batch does not own
- * them and they must outlive it.  Work is ordered on the first context's stream. */
+ * them and they must outlive it.  Work is ordered on the first context's stream: a dope_set_energy_async on a
+ * member context must be ordered before the batch call that follows it (the same stream, or synchronised). */
 typedef struct dope_batch dope_batch;
 
 dope_status dope_batch_create(dope_ctx *const *ctxs, int32_t n, dope_batch **out);

@@ -29,6 +29,7 @@ struct dope_ctx {
     bool own_ws = false;
     Ctl *ctl = nullptr;
     dope::Img himg{};          // host copy of the device image descriptor (kernel argument of one-image launches)
+    bool validate_pending = false;   // a setup is enqueued whose validation no control kernel has taken yet
     int32_t *btab = nullptr, *u = nullptr, *w = nullptr, *cw = nullptr, *Y = nullptr, *A0 = nullptr, *A1 = nullptr;
     int32_t *stats = nullptr, *chunk_k0 = nullptr;
     int2 *blist = nullptr;
@@ -351,6 +352,11 @@ dope_status ensure_workspace(dope_ctx *c) {
 }
 
 dope_status sync_ctl(dope_ctx *c) {
+    // a pending energy validation is taken before the loop control is read back
+    if (c->validate_pending) {
+        HIP_TRY(c, dope::launch_validate(c->ctl, c->stream), "validation launch");
+        c->validate_pending = false;
+    }
     HIP_TRY(c, hipMemcpyAsync(c->hctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream), "control readback");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
     return DOPE_OK;
@@ -523,6 +529,7 @@ dope_status enqueue_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int3
                                   c->ctl, c->p.mu0, c->p.mu_fact_num, c->p.mu_fact_den, eps2, allow_negative,
                                   c->stream),
             "setup launch");
+    c->validate_pending = true;
     return DOPE_OK;
 }
 
@@ -603,6 +610,7 @@ dope_status dope_iterate(dope_ctx *c, int32_t n_iter, dope_info *out) {
     if (c->hctl->status != 0) { fill_info(c, out); return dope_status(c->hctl->status); }
     const int32_t t0 = c->hctl->t;
     HIP_TRY(c, dope::launch_ctl_setup(c->ctl, t0 + n_iter, 0, 0, c->stream), "control setup launch");
+    c->validate_pending = false;
     st = enqueue_iterations(c, n_iter);
     if (st != DOPE_OK) return st;
     st = sync_ctl(c);
@@ -620,6 +628,7 @@ dope_status dope_solve(dope_ctx *c, dope_info *out) {
     if (c->hctl->t > 0 && c->hctl->converged) { fill_info(c, out); return DOPE_OK; }
     const int32_t limit = c->p.max_iter;
     HIP_TRY(c, dope::launch_ctl_setup(c->ctl, limit, 1, 0, c->stream), "control setup launch");
+    c->validate_pending = false;
     // Iterations are enqueued in chunks of 2, 2, 4, 8, ... with one readback per chunk.  An iteration enqueued
     // after the stopping rule held is skipped on the device (Ctl::halted), so the result is that of one
     // iteration per readback; only a few empty launches are spent.
@@ -860,6 +869,7 @@ dope_status batch_setup(dope_batch *b) {
     BHIP_TRY(b, hipMemcpyAsync(b->dparams, b->hparams, n * 2 * sizeof(int32_t), hipMemcpyHostToDevice, b->stream),
              "parameter upload");
     BHIP_TRY(b, dope::launch_batch_setup(b->imgs, int32_t(n), b->dparams, b->stream), "batch setup launch");
+    for (dope_ctx *c : b->ctxs) c->validate_pending = false;   // taken by the batch setup kernel
     return DOPE_OK;
 }
 

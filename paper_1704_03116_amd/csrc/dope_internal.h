@@ -84,6 +84,8 @@ struct Ctl {
     int32_t mu_num, mu_den;
     int32_t flags;             // set_energy validation bits being accumulated (see FLAG_*); cleared by validation
     int32_t vflags;            // validation bits of the last set_energy
+    int32_t vpending;          // a set_energy awaits its validation (done by the next control setup kernel)
+    int32_t allow_negative;    // the resolved solver of that set_energy accepts negative weights
 };
 
 enum : int32_t { FLAG_OFFGRID = 1, FLAG_NEGATIVE = 2, FLAG_TOOBIG = 4 };
@@ -158,8 +160,10 @@ hipError_t launch_solve_phase(const Group &grp, hipStream_t s);
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s);
 hipError_t launch_finalize_phase(const Group &grp, hipStream_t s);
 
-// set_energy on the device: workspace copies of u and w (src != ws), c_ij, initial state and loop control, then
-// the validation verdict (status / halted set on the device when the energy is invalid).
+// set_energy on the device: workspace copies of u and w (src != ws), c_ij, initial state and loop control.  The
+// validation verdict (status / halted set on the device when the energy is invalid) is taken by the next
+// launch_validate, launch_ctl_setup or launch_batch_setup.
+hipError_t launch_validate(Ctl *ctl, hipStream_t s);
 hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *w_ws,
                         int32_t *cw, int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
                         int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,

@@ -1088,11 +1088,12 @@ __global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, 
 //   - c_ij = lambda_q8 w_ij 64 / (q_i q_j) for the half-stencil edges of every pixel, with validation bits (nonzero
 //     weight on an off-grid edge, negative weight, per-node sum_j |c_ij| >= 2^29) OR-ed into ctl->flags,
 //   - the initial ADMM state (Y = 1/2, A = 0, yhat = 0, r_k = 0; a grid-stride pass over the block-major arrays),
-//   - the loop control (workgroup (0, 0)); ctl->flags is left alone: k_validate consumes and clears it.
+//   - the loop control (workgroup (0, 0)); ctl->flags is left alone: the validation consumes and clears it.
 struct StateInit {
     int64_t mu0;
     uint64_t eps2;
     int32_t mu_num, mu_den;
+    int32_t allow_negative;
 };
 
 template <int CONN>
@@ -1187,6 +1188,8 @@ __global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict
             c->mu_num = si.mu_num;
             c->mu_den = si.mu_den;
             c->vflags = 0;
+            c->vpending = 1;
+            c->allow_negative = si.allow_negative;
         }
     }
     const int gx = blockIdx.x * 256 + threadIdx.x;
@@ -1196,35 +1199,51 @@ __global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict
         setup_pixel<CONN>(g, gx, row % g.H, row / g.H, u_src, w_src, u_ws, w_ws, cw, lam, Y, ctl);
 }
 
-// Energy validation verdict after k_setup: off-grid or oversized weights -> EINVAL; a negative weight when the
-// resolved solver is max-flow -> ENOTSUBMODULAR.  Stops the loop before any iteration runs.  The accumulated bits
-// move to ctl->vflags (read by the host for the error message) and the accumulator is cleared for the next setup.
-__global__ void k_validate(Ctl *ctl, int32_t allow_negative) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Energy validation verdict of a pending k_setup: off-grid or oversized weights -> EINVAL; a negative weight
+// when the resolved solver is max-flow -> ENOTSUBMODULAR.  Stops the loop before any iteration runs.  The
+// accumulated bits move to ctl->vflags (read by the host for the error message) and the accumulator is cleared
+// for the next setup.  Runs in the single thread of a control kernel.
+__device__ __forceinline__ void validate_pending(Ctl *ctl) {
     GLOBAL Ctl *c = gp(ctl);
+    if (!c->vpending) return;
     const int32_t f = c->flags;
     c->vflags = f;
     c->flags = 0;
+    c->vpending = 0;
     int32_t st = 0;
     if (f & (FLAG_OFFGRID | FLAG_TOOBIG)) st = -1;
-    else if ((f & FLAG_NEGATIVE) && !allow_negative) st = -4;
+    else if ((f & FLAG_NEGATIVE) && !c->allow_negative) st = -4;
     if (st) {
         c->status = st;
         c->halted = 1;
     }
 }
 
+__global__ void k_validate(Ctl *ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) validate_pending(ctl);
+}
+
 __global__ void k_batch_setup(const Img *__restrict__ imgs, int32_t n, const int32_t *__restrict__ params) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    Ctl *ctl = imgs[i].ctl;
+    GLOBAL Ctl *ctl = gp(imgs[i].ctl);
+    validate_pending(imgs[i].ctl);
     ctl->t_limit = params[2 * i];
     ctl->stop_on_converge = params[2 * i + 1];
     if (ctl->status == 0) ctl->halted = 0;
+    // the summary also reports images that will not run (an energy that failed validation)
+    if (imgs[i].summary) {
+        GLOBAL int32_t *sm = gp(imgs[i].summary);
+        sm[0] = ctl->t;
+        sm[1] = ctl->halted;
+        sm[2] = ctl->converged;
+        sm[3] = ctl->status;
+    }
 }
 
 __global__ void k_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        validate_pending(ctl);
         ctl->t_limit = t_limit;
         ctl->stop_on_converge = stop_on_converge;
         if (ctl->status == 0) ctl->halted = 0;
@@ -1344,7 +1363,7 @@ hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_sr
                         int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,
                         int32_t allow_negative, hipStream_t s) {
     const dim3 grid(blocks_for(g.W, 256), row_blocks(g));
-    const StateInit si{mu0, eps2, mu_num, mu_den};
+    const StateInit si{mu0, eps2, mu_num, mu_den, allow_negative};
     switch (g.conn) {
         case 4: hipLaunchKernelGGL(k_setup<4>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, w_ws, cw, lam_q8, Y, A0,
                                    A1, yhat, resid, ctl, si); break;
@@ -1353,7 +1372,11 @@ hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_sr
         default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, w_ws, cw, lam_q8, Y,
                                     A0, A1, yhat, resid, ctl, si); break;
     }
-    hipLaunchKernelGGL(k_validate, dim3(1), dim3(64), 0, s, ctl, allow_negative);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(Ctl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate, dim3(1), dim3(64), 0, s, ctl);
     return hipGetLastError();
 }
 

@@ -236,13 +236,6 @@ class Batch:
         if st != N.DOPE_OK:
             raise N.DopeError(st, N.dope_batch_last_error(self.b).decode())
 
-    def set_energy_async(self, u, w, lambda_q8):
-        pu, ku = _ptr(u)
-        pw, kw = _ptr(w)
-        if ku != kw:
-            raise ValueError("u and w must live in the same memory")
-        N.check(N.dope_set_energy_async(self.ctx, pu, pw, int(lambda_q8), ku), self.ctx)
-
     def iterate(self, n_iter=1):
         self._check(N.dope_batch_iterate(self.b, int(n_iter)))
 

@@ -399,6 +399,42 @@ def test_async_energy_upload_and_deferred_validation():
         assert e.get_state()[4] == 0                     # no iteration ran
 
 
+def test_deferred_validation_through_solve_and_batch():
+    """The verdict of an asynchronous energy is taken by whichever call comes next: a solve, or a batch; a valid
+    energy loaded after an invalid one runs normally."""
+    from paper_1704_03116_amd import _native as N
+    from paper_1704_03116_amd.solver import Batch, Dope
+    announce("deferred validation: solve, batch, reload")
+    q = synth.random_problem(16, (20, 20, 1), 4, (8, 8, 1), (1, 1, 0), neg_frac=0.3)
+    good = synth.random_problem(17, (20, 20, 1), 4, (8, 8, 1), (1, 1, 0))
+    with Dope.from_problem(q, solver="maxflow") as e:
+        e.set_energy_async(q.u, q.w, q.lam_q8)
+        with pytest.raises(N.DopeError) as err:
+            e.solve()
+        assert err.value.status == N.DOPE_ENOTSUBMODULAR
+        e.set_energy_async(good.u, good.w, good.lam_q8)
+        e.iterate(3)
+        st_o, _, _, _ = od.run(good, n_iter=3)
+        Y, A, yh, mu, t = e.get_state()
+        assert t == 3 and np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A)
+    a = Dope.from_problem(good, solver="maxflow")
+    b = Dope.from_problem(q, solver="maxflow")
+    try:
+        a.set_energy_async(good.u, good.w, good.lam_q8)
+        b.set_energy_async(q.u, q.w, q.lam_q8)
+        with Batch([a, b]) as bt:
+            with pytest.raises(N.DopeError) as err:
+                bt.iterate(2)
+            assert err.value.status == N.DOPE_ENOTSUBMODULAR
+            info = bt.info()
+        assert info[0]["iters_done"] == 2 and info[1]["iters_done"] == 0
+        st_o, _, _, _ = od.run(good, n_iter=2)
+        assert np.array_equal(a.get_state()[0], st_o.Y)
+    finally:
+        a.close()
+        b.close()
+
+
 # ------------------------------------------------------------------------------------------------------------
 # serving: continuous batching; every request equals its solve alone; admission within the HBM budget
 # ------------------------------------------------------------------------------------------------------------
