@@ -873,6 +873,20 @@ dope_status batch_setup(dope_batch *b) {
     return DOPE_OK;
 }
 
+// {t, halted, converged, status} of image i: the batch's summary when the batch ran the image last (its context
+// is then marked dirty), otherwise the context's host mirror (the image was reset, set or read back since).
+void image_summary(const dope_batch *b, size_t i, int32_t out[4]) {
+    const dope_ctx *c = b->ctxs[i];
+    if (c->dirty) {
+        for (int f = 0; f < 4; ++f) out[f] = b->hsum[4 * i + f];
+    } else {
+        out[0] = c->hctl->t;
+        out[1] = c->hctl->halted;
+        out[2] = c->hctl->converged;
+        out[3] = c->hctl->status;
+    }
+}
+
 dope_status batch_status(dope_batch *b) {
     for (size_t i = 0; i < b->ctxs.size(); ++i)
         if (b->hsum[4 * i + 3] != 0)
@@ -1014,7 +1028,9 @@ dope_status dope_batch_iterate(dope_batch *b, int32_t n_iter) {
     if (!b || n_iter < 0) return DOPE_EINVAL;
     const size_t n = b->ctxs.size();
     for (size_t i = 0; i < n; ++i) {
-        b->hparams[2 * i] = b->hsum[4 * i] + n_iter;
+        int32_t sm[4];
+        image_summary(b, i, sm);
+        b->hparams[2 * i] = sm[0] + n_iter;
         b->hparams[2 * i + 1] = 0;
     }
     dope_status st = batch_setup(b);
@@ -1034,22 +1050,32 @@ dope_status dope_batch_solve(dope_batch *b) {
     int32_t most = 0;
     for (size_t i = 0; i < n; ++i) {
         const dope_ctx *c = b->ctxs[i];
-        const bool done = b->hsum[4 * i + 3] != 0 || (b->hsum[4 * i] > 0 && b->hsum[4 * i + 2]);
-        b->hparams[2 * i] = done ? b->hsum[4 * i] : c->p.max_iter;   // finished images take no more iterations
+        int32_t sm[4];
+        image_summary(b, i, sm);
+        const bool done = sm[3] != 0 || (sm[0] > 0 && sm[2]);
+        b->hparams[2 * i] = done ? sm[0] : c->p.max_iter;   // finished images take no more iterations
         b->hparams[2 * i + 1] = 1;
         most = std::max(most, c->p.max_iter);
     }
     dope_status st = batch_setup(b);
     if (st != DOPE_OK) return st;
-    for (int32_t it = 0; it < most; ++it) {
-        st = batch_run_iteration(b);
-        if (st != DOPE_OK) return st;
+    // Iterations go out in chunks of 2, 2, 4, 8, ... with one summary readback per chunk; an image whose
+    // stopping rule held, or that reached its limit, skips the rest of the chunk on the device.
+    int32_t issued = 0, chunk = 2, n_chunks = 0;
+    while (issued < most) {
+        const int32_t count = std::min(chunk, most - issued);
+        for (int32_t it = 0; it < count; ++it) {
+            st = batch_run_iteration(b);
+            if (st != DOPE_OK) return st;
+        }
+        issued += count;
         st = batch_sync(b);
         if (st != DOPE_OK) return st;
         bool running = false;
         for (size_t i = 0; i < n && !running; ++i)
             running = !b->hsum[4 * i + 1] && b->hsum[4 * i] < b->hparams[2 * i];
         if (!running) break;
+        if (++n_chunks >= 2) chunk = std::min(2 * chunk, 64);
     }
     return batch_status(b);
 }

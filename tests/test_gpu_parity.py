@@ -350,6 +350,47 @@ def test_batch_solve_per_image_stopping():
         c.close()
 
 
+def test_batch_solve_again_after_new_energies():
+    """A second batch solve after every member got a new energy (asynchronously) starts each image from its own
+    reset state, whatever the first solve left in the batch's summaries: the first energies (no pairwise terms)
+    stop early, the second ones need more iterations."""
+    from paper_1704_03116_amd.solver import Batch
+    import torch
+
+    def problems():
+        out = []
+        for s in range(4):
+            q = synth.config5_image(48 + 16 * s, 40 + 8 * s, lam=1.5, seed=s)
+            q.block, q.overlap = (16, 16, 1), (1, 1, 0)
+            q.max_iter = 12
+            out.append(q)
+        return out
+
+    second = problems()
+    first = problems()
+    for q in first:
+        q.w = np.zeros_like(q.w)
+    announce("batch solve, new energies, batch solve again")
+    ctxs = [make_ctx(p) for p in first]
+    with Batch(ctxs, graph=True) as b:
+        b.solve()
+        first_iters = [i["iters_done"] for i in b.info()]
+        for c, q in zip(ctxs, second):
+            c.set_energy_async(torch.from_numpy(np.ascontiguousarray(q.u)).cuda(),
+                               torch.from_numpy(np.ascontiguousarray(q.w)).cuda(), q.lam_q8)
+        b.solve()
+        infos = b.info()
+    more = 0
+    for q, c, inf, n1 in zip(second, ctxs, infos, first_iters):
+        st_o, infos_o, _, _ = od.run(q)
+        assert inf["iters_done"] == len(infos_o), q.name
+        more += len(infos_o) > n1
+        Y, A, yh, mu, t = c.get_state()
+        assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A)
+        c.close()
+    assert more > 0, "the second energies should need more iterations than the first took"
+
+
 def test_batch_exhaustive_nonsubmodular():
     from paper_1704_03116_amd.solver import Batch
     probs = [synth.config4(seed=s, size=sz) for s, sz in enumerate([24, 37, 16])]
