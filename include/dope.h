@@ -153,7 +153,9 @@ size_t dope_workspace_bytes(const dope_params *p);
 dope_status dope_bind_workspace(dope_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Kernel timing with HIP events on the context stream.  While enabled, every block-solve launch and every
- * consensus launch (not the loop-control launch that follows it) is bracketed by events; dope_profile_read
+ * consensus launch (not the loop-control launch that follows it) records its own dispatch start and end in a pair
+ * of events (hipExtLaunchKernel: no marker packets are added, so the timed stream runs as it would unprofiled);
+ * dope_profile_read
  * returns the summed milliseconds and launch counts since enable. */
 dope_status dope_profile_enable(dope_ctx *ctx, int32_t on);
 dope_status dope_profile_read(dope_ctx *ctx, double *solve_ms, int32_t *solve_launches, double *consensus_ms,

@@ -390,20 +390,14 @@ dope_status enqueue_iterations(dope_ctx *c, int count) {
             continue;
         }
         hipEvent_t e0 = next_event(c->ev_solve, 2 * c->n_solve), e1 = next_event(c->ev_solve, 2 * c->n_solve + 1);
-        if (e0 && e1) (void)hipEventRecord(e0, c->stream);
-        HIP_TRY(c, dope::launch_solve_phase(c->grp, c->stream), "block solve launch");
-        if (e0 && e1) {
-            (void)hipEventRecord(e1, c->stream);
-            ++c->n_solve;
-        }
+        HIP_TRY(c, dope::launch_solve_phase(c->grp, c->stream, e0 && e1 ? e0 : nullptr, e0 && e1 ? e1 : nullptr),
+                "block solve launch");
+        if (e0 && e1) ++c->n_solve;
         e0 = next_event(c->ev_cons, 2 * c->n_cons);
         e1 = next_event(c->ev_cons, 2 * c->n_cons + 1);
-        if (e0 && e1) (void)hipEventRecord(e0, c->stream);
-        HIP_TRY(c, dope::launch_consensus_phase(c->grp, c->stream), "consensus launch");
-        if (e0 && e1) {
-            (void)hipEventRecord(e1, c->stream);
-            ++c->n_cons;
-        }
+        HIP_TRY(c, dope::launch_consensus_phase(c->grp, c->stream, e0 && e1 ? e0 : nullptr, e0 && e1 ? e1 : nullptr),
+                "consensus launch");
+        if (e0 && e1 && c->grp.n_chk_items > 0) ++c->n_cons;
         HIP_TRY(c, dope::launch_finalize_phase(c->grp, c->stream), "finalize launch");
     }
     return DOPE_OK;

@@ -156,8 +156,10 @@ hipError_t launch_iteration(const Group &grp, hipStream_t s);
 // Per-image loop setup of a batch: params[2 i] = t_limit, params[2 i + 1] = stop_on_converge.
 hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params, hipStream_t s);
 // Individual phases (used for per-kernel timing).
-hipError_t launch_solve_phase(const Group &grp, hipStream_t s);
-hipError_t launch_consensus_phase(const Group &grp, hipStream_t s);
+// With events, the launch records its own dispatch start and end in e0 / e1 (hipExtLaunchKernel).
+hipError_t launch_solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0 = nullptr,
+                                  hipEvent_t e1 = nullptr);
 hipError_t launch_finalize_phase(const Group &grp, hipStream_t s);
 
 // set_energy on the device: workspace copies of u and w (src != ws), c_ij, initial state and loop control.  The

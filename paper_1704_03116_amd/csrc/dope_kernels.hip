@@ -12,6 +12,8 @@
 // halted, so the host can enqueue several iterations ahead without reading anything back.
 #include "dope_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 namespace dope {
@@ -1315,7 +1317,7 @@ inline unsigned row_blocks(const Geom &g) {
 }
 
 template <int CONN, int NT>
-hipError_t launch_maxflow(const Group &grp, hipStream_t s) {
+hipError_t launch_maxflow(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     constexpr int H = Sten<CONN>::H;
     const size_t lds = maxflow_lds_bytes(grp.npmax, H);
     static size_t lds_set = 0;
@@ -1331,15 +1333,27 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s) {
     const int32_t direct = workers == grp.n_blk_items ? 1 : 0;
     const Img one = grp.one ? *grp.one : Img{};
     const int32_t one_par = (grp.one && direct) ? grp.par : -1;
-    hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(workers), dim3(NT), lds, s, grp.imgs, grp.blk_items,
-                       grp.n_blk_items, grp.queue, grp.npmax, round_limit, grp.npmax > 2048 ? 8 : 4, direct, one,
-                       one_par);
+    if (e0) {
+        // the events carry the dispatch's own start and end timestamps (no marker packets around the launch)
+        hipExtLaunchKernelGGL(k_block_solve<CONN, NT>, dim3(workers), dim3(NT), uint32_t(lds), s, e0, e1, 0u,
+                              grp.imgs, grp.blk_items, grp.n_blk_items, grp.queue, grp.npmax, round_limit,
+                              int32_t(grp.npmax > 2048 ? 8 : 4), direct, one, one_par);
+    } else {
+        hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(workers), dim3(NT), lds, s, grp.imgs, grp.blk_items,
+                           grp.n_blk_items, grp.queue, grp.npmax, round_limit, grp.npmax > 2048 ? 8 : 4, direct,
+                           one, one_par);
+    }
     return hipGetLastError();
 }
 
 template <int CONN>
-hipError_t solve_phase(const Group &grp, hipStream_t s) {
+hipError_t solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (grp.solver == 2) {
+        if (e0) {
+            hipExtLaunchKernelGGL(k_block_exhaustive<CONN>, dim3(blocks_for(grp.n_blk_items, EX_WAVES)), dim3(256),
+                                  0u, s, e0, e1, 0u, grp.imgs, grp.blk_items, grp.n_blk_items);
+            return hipGetLastError();
+        }
         hipLaunchKernelGGL(k_block_exhaustive<CONN>, dim3(blocks_for(grp.n_blk_items, EX_WAVES)), dim3(256), 0, s,
                            grp.imgs, grp.blk_items, grp.n_blk_items);
         return hipGetLastError();
@@ -1350,10 +1364,10 @@ hipError_t solve_phase(const Group &grp, hipStream_t s) {
     // 32x32 8-connected blocks: 289 and 1089 blocks both favour 512 threads.
     if (grp.npmax > 512) {
         const bool one_per_cu = maxflow_lds_bytes(grp.npmax, Sten<CONN>::H) > LDS_LIMIT / 2;
-        if (one_per_cu || grp.n_blk_items <= NUM_CUS) return launch_maxflow<CONN, 1024>(grp, s);
-        return launch_maxflow<CONN, 512>(grp, s);
+        if (one_per_cu || grp.n_blk_items <= NUM_CUS) return launch_maxflow<CONN, 1024>(grp, s, e0, e1);
+        return launch_maxflow<CONN, 512>(grp, s, e0, e1);
     }
-    return launch_maxflow<CONN, 256>(grp, s);
+    return launch_maxflow<CONN, 256>(grp, s, e0, e1);
 }
 
 }  // namespace
@@ -1386,22 +1400,30 @@ hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge,
     return hipGetLastError();
 }
 
-hipError_t launch_solve_phase(const Group &grp, hipStream_t s) {
+hipError_t launch_solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (grp.conn) {
-        case 4: return solve_phase<4>(grp, s);
-        case 8: return solve_phase<8>(grp, s);
-        default: return solve_phase<6>(grp, s);
+        case 4: return solve_phase<4>(grp, s, e0, e1);
+        case 8: return solve_phase<8>(grp, s, e0, e1);
+        default: return solve_phase<6>(grp, s, e0, e1);
     }
 }
 
-hipError_t launch_consensus_phase(const Group &grp, hipStream_t s) {
+template <int CONN>
+void consensus_launch(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const Img &one,
+                      int32_t one_par) {
     const dim3 grid(unsigned(grp.n_chk_items));
+    if (e0) hipExtLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0u, s, e0, e1, 0u, grp.imgs, grp.chk_items,
+                                  one, one_par);
+    else hipLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items, one, one_par);
+}
+
+hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const Img one = grp.one ? *grp.one : Img{};
     const int32_t one_par = grp.one ? grp.par : -1;
     if (grp.n_chk_items > 0) switch (grp.conn) {
-        case 4: hipLaunchKernelGGL(k_consensus<4>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items, one, one_par); break;
-        case 8: hipLaunchKernelGGL(k_consensus<8>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items, one, one_par); break;
-        default: hipLaunchKernelGGL(k_consensus<6>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items, one, one_par); break;
+        case 4: consensus_launch<4>(grp, s, e0, e1, one, one_par); break;
+        case 8: consensus_launch<8>(grp, s, e0, e1, one, one_par); break;
+        default: consensus_launch<6>(grp, s, e0, e1, one, one_par); break;
     }
     return hipGetLastError();
 }
