@@ -54,13 +54,19 @@ def interior_count(dims, block, overlap):
     return total
 
 
+TRAFFIC_RECORDS = {"config2": "hbm_traffic_config2_512x512.json", "config3": "hbm_traffic_config3_128x128x64.json"}
+
+
 def measured_traffic(workload_name):
-    """HBM bytes per dispatch from the committed rocprofv3 counter summary, only while the kernel source is the
-    one that was measured (FETCH_SIZE and WRITE_SIZE scaled by a 256 MiB copy's readings)."""
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary of this workload, only while the kernel
+    source is the one that was measured (FETCH_SIZE and WRITE_SIZE scaled by a 256 MiB copy's readings)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_config2_512x512.json")
+    rec_name = next((f for k, f in TRAFFIC_RECORDS.items() if workload_name.startswith(k)), None)
+    if rec_name is None:
+        return {}
+    path = os.path.join(ROOT, "profiles", rec_name)
     src = os.path.join(ROOT, "paper_1704_03116_amd", "csrc", "dope_kernels.hip")
-    if not workload_name.startswith("config2") or not os.path.exists(path):
+    if not os.path.exists(path):
         return {}
     rec = json.load(open(path))
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
