@@ -634,28 +634,33 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     }
 }
 
-// Persistent block-solve launch: every workgroup takes (image, block) items from the device work queue until it
-// is empty, so blocks of many images of uneven sizes and uneven max-flow cost share one launch.  With one
-// workgroup per item (direct != 0) workgroup b takes item b and the queue is not touched.  A one-image launch
-// (one_par >= 0) gets the image descriptor and the multiplier parity as kernel arguments: workgroup b solves
-// block b, and no descriptor or loop-control load stands between the launch and the gathers.
+// The image descriptors of a batch are read-only while a launch runs; reading them through the constant address
+// space marks the loads invariant.
+#define CONSTANT __attribute__((address_space(4)))
+__device__ __forceinline__ const Img &const_img(const Img *p) {
+    return *(const Img *)(const CONSTANT Img *)p;
+}
+
+// Batch block solve, one workgroup per (image, block) item: workgroup b takes item b.  Items stay in dispatch
+// order (round-robin over the XCDs): hard blocks cluster in space, and contiguous item ranges per XCD would leave
+// XCDs idle behind the one that got the cluster.
 template <int CONN, int NT>
 __global__ __launch_bounds__(NT) void k_block_solve(const Img *__restrict__ imgs, const Item *__restrict__ items,
-                                                    int32_t n_items, Queue *queue, int32_t npmax,
-                                                    int32_t round_limit, int32_t relabel_period, int32_t direct,
-                                                    const Img one, int32_t one_par) {
+                                                    int32_t npmax, int32_t round_limit, int32_t relabel_period) {
     extern __shared__ __align__(16) unsigned char smem[];
-    if (one_par >= 0) {
-        block_maxflow<CONN, NT>(one, xcd_item(blockIdx.x, gridDim.x), smem, npmax, round_limit, relabel_period,
-                                one_par, true);
-        return;
-    }
-    if (direct) {
-        const Item wi = items[xcd_item(blockIdx.x, gridDim.x)];
-        const Img &im = imgs[wi.img];
-        if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period, -1, false);
-        return;
-    }
+    const Item wi = items[blockIdx.x];
+    const Img &im = const_img(imgs + wi.img);
+    if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period, -1, false);
+}
+
+// Persistent batch block solve: a fixed number of workgroups take (image, block) items from the device work queue
+// until it is empty, so blocks of uneven max-flow cost balance over the workgroups.  A kernel of its own: the
+// loop around the inlined solver raises register pressure, which the one-item-per-workgroup kernel need not pay.
+template <int CONN, int NT>
+__global__ __launch_bounds__(NT) void k_block_solve_queue(const Img *__restrict__ imgs, const Item *__restrict__ items,
+                                                          int32_t n_items, Queue *queue, int32_t npmax,
+                                                          int32_t round_limit, int32_t relabel_period) {
+    extern __shared__ __align__(16) unsigned char smem[];
     int *s_item = reinterpret_cast<int *>(smem) + 15;   // the block solver uses scalar slots 0..14
     for (;;) {
         if (threadIdx.x == 0) *s_item = int(atomicAdd(&queue->next, 1u));
@@ -664,10 +669,20 @@ __global__ __launch_bounds__(NT) void k_block_solve(const Img *__restrict__ imgs
         __syncthreads();
         if (it >= n_items) break;
         const Item wi = items[it];
-        const Img &im = imgs[wi.img];
+        const Img &im = const_img(imgs + wi.img);
         if (!ctl_skip(im.ctl)) block_maxflow<CONN, NT>(im, wi.idx, smem, npmax, round_limit, relabel_period, -1, false);
         __syncthreads();   // the LDS of this item is reused by the next one
     }
+}
+
+// One-image block solve: the image descriptor and the multiplier parity come as kernel arguments, workgroup b
+// solves block b, and no descriptor or loop-control load stands between the launch and the gathers (the loop
+// control is read while they are in flight; a skipped iteration stops before its first global store).
+template <int CONN, int NT>
+__global__ __launch_bounds__(NT) void k_block_solve_one(const Img one, int32_t par, int32_t npmax,
+                                                        int32_t round_limit, int32_t relabel_period) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    block_maxflow<CONN, NT>(one, blockIdx.x, smem, npmax, round_limit, relabel_period, par, true);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -1014,18 +1029,18 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     if (tid == 0 && s_ovf) atomicOr((int32_t *)gp(&im.ctl->ovf_pending), 1);
 }
 
-// One workgroup per 256-pixel chunk of the boundary list.  A one-image launch (one_par >= 0) gets the descriptor
-// and the multiplier parity as kernel arguments.
+// One workgroup per 256-pixel chunk of the boundary list (chunks of all images of a batch).  Chunks have even
+// work, so XCD j takes a contiguous range of them (neighbouring chunks share halo lines in its L2).
 template <int CONN>
-__global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ imgs, const Item *__restrict__ items,
-                                                       const Img one, int32_t one_par) {
-    const int b = xcd_item(blockIdx.x, gridDim.x);
-    if (one_par >= 0) {
-        consensus_chunk<CONN>(one, b, one_par, true);
-        return;
-    }
-    const Item wi = items[b];
+__global__ __launch_bounds__(CONS_NT) void k_consensus(const Img *__restrict__ imgs, const Item *__restrict__ items) {
+    const Item wi = items[xcd_item(blockIdx.x, gridDim.x)];
     consensus_chunk<CONN>(imgs[wi.img], wi.idx, -1, false);
+}
+
+// One-image consensus: descriptor and multiplier parity as kernel arguments.
+template <int CONN>
+__global__ __launch_bounds__(CONS_NT) void k_consensus_one(const Img one, int32_t par) {
+    consensus_chunk<CONN>(one, xcd_item(blockIdx.x, gridDim.x), par, true);
 }
 
 // Loop control after the consensus of one iteration (a single workgroup): max_k r_k, stopping rule, overflow
@@ -1322,8 +1337,12 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s, hipEvent_t e0, hipEve
     const size_t lds = maxflow_lds_bytes(grp.npmax, H);
     static size_t lds_set = 0;
     if (lds > lds_set) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_block_solve<CONN, NT>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        hipError_t e = hipSuccess;
+        const void *fns[3] = {reinterpret_cast<const void *>(&k_block_solve<CONN, NT>),
+                              reinterpret_cast<const void *>(&k_block_solve_queue<CONN, NT>),
+                              reinterpret_cast<const void *>(&k_block_solve_one<CONN, NT>)};
+        for (const void *f : fns)
+            if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
         lds_set = lds;
     }
@@ -1331,17 +1350,24 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s, hipEvent_t e0, hipEve
     const int32_t workers = grp.n_workers > 0 ? (grp.n_workers < grp.n_blk_items ? grp.n_workers : grp.n_blk_items)
                                               : grp.n_blk_items;
     const int32_t direct = workers == grp.n_blk_items ? 1 : 0;
-    const Img one = grp.one ? *grp.one : Img{};
-    const int32_t one_par = (grp.one && direct) ? grp.par : -1;
-    if (e0) {
-        // the events carry the dispatch's own start and end timestamps (no marker packets around the launch)
-        hipExtLaunchKernelGGL(k_block_solve<CONN, NT>, dim3(workers), dim3(NT), uint32_t(lds), s, e0, e1, 0u,
-                              grp.imgs, grp.blk_items, grp.n_blk_items, grp.queue, grp.npmax, round_limit,
-                              int32_t(grp.npmax > 2048 ? 8 : 4), direct, one, one_par);
+    const int32_t relabel_period = grp.npmax > 2048 ? 8 : 4;
+    // the events carry the dispatch's own start and end timestamps (no marker packets around the launch)
+    if (grp.one && direct) {
+        if (e0) hipExtLaunchKernelGGL(k_block_solve_one<CONN, NT>, dim3(workers), dim3(NT), uint32_t(lds), s, e0, e1,
+                                      0u, *grp.one, grp.par, grp.npmax, round_limit, relabel_period);
+        else hipLaunchKernelGGL((k_block_solve_one<CONN, NT>), dim3(workers), dim3(NT), lds, s, *grp.one, grp.par,
+                                grp.npmax, round_limit, relabel_period);
+    } else if (direct) {
+        if (e0) hipExtLaunchKernelGGL(k_block_solve<CONN, NT>, dim3(workers), dim3(NT), uint32_t(lds), s, e0, e1, 0u,
+                                      grp.imgs, grp.blk_items, grp.npmax, round_limit, relabel_period);
+        else hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(workers), dim3(NT), lds, s, grp.imgs, grp.blk_items,
+                                grp.npmax, round_limit, relabel_period);
     } else {
-        hipLaunchKernelGGL((k_block_solve<CONN, NT>), dim3(workers), dim3(NT), lds, s, grp.imgs, grp.blk_items,
-                           grp.n_blk_items, grp.queue, grp.npmax, round_limit, grp.npmax > 2048 ? 8 : 4, direct,
-                           one, one_par);
+        if (e0) hipExtLaunchKernelGGL(k_block_solve_queue<CONN, NT>, dim3(workers), dim3(NT), uint32_t(lds), s, e0, e1,
+                                      0u, grp.imgs, grp.blk_items, grp.n_blk_items, grp.queue, grp.npmax, round_limit,
+                                      relabel_period);
+        else hipLaunchKernelGGL((k_block_solve_queue<CONN, NT>), dim3(workers), dim3(NT), lds, s, grp.imgs,
+                                grp.blk_items, grp.n_blk_items, grp.queue, grp.npmax, round_limit, relabel_period);
     }
     return hipGetLastError();
 }
@@ -1409,21 +1435,23 @@ hipError_t launch_solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hi
 }
 
 template <int CONN>
-void consensus_launch(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const Img &one,
-                      int32_t one_par) {
+void consensus_launch(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid(unsigned(grp.n_chk_items));
-    if (e0) hipExtLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0u, s, e0, e1, 0u, grp.imgs, grp.chk_items,
-                                  one, one_par);
-    else hipLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items, one, one_par);
+    if (grp.one) {
+        if (e0) hipExtLaunchKernelGGL(k_consensus_one<CONN>, grid, dim3(CONS_NT), 0u, s, e0, e1, 0u, *grp.one, grp.par);
+        else hipLaunchKernelGGL(k_consensus_one<CONN>, grid, dim3(CONS_NT), 0, s, *grp.one, grp.par);
+    } else {
+        if (e0) hipExtLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0u, s, e0, e1, 0u, grp.imgs,
+                                      grp.chk_items);
+        else hipLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items);
+    }
 }
 
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const Img one = grp.one ? *grp.one : Img{};
-    const int32_t one_par = grp.one ? grp.par : -1;
     if (grp.n_chk_items > 0) switch (grp.conn) {
-        case 4: consensus_launch<4>(grp, s, e0, e1, one, one_par); break;
-        case 8: consensus_launch<8>(grp, s, e0, e1, one, one_par); break;
-        default: consensus_launch<6>(grp, s, e0, e1, one, one_par); break;
+        case 4: consensus_launch<4>(grp, s, e0, e1); break;
+        case 8: consensus_launch<8>(grp, s, e0, e1); break;
+        default: consensus_launch<6>(grp, s, e0, e1); break;
     }
     return hipGetLastError();
 }
