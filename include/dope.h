@@ -122,7 +122,8 @@ dope_status dope_solve(dope_ctx *ctx, dope_info *out);
 /* Labels l_i = [Y_i > 2^15] (uint8[n]) to host memory (waits) or device memory (stream-ordered, returns at once). */
 dope_status dope_labels(dope_ctx *ctx, uint8_t *labels, int32_t mem_kind);
 
-/* E_q = 256 sum u_i l_i + lambda_q8 sum_edges w_ij |l_i - l_j| of the current labels (exact int64). */
+/* E_q = 256 sum u_i l_i + lambda_q8 sum_edges w_ij |l_i - l_j| of the current labels (exact int64).  EINVAL
+ * when the loaded energy was rejected by validation. */
 dope_status dope_energy(dope_ctx *ctx, int64_t *e_q8);
 
 /* Checkpoint / test access to the whole ADMM state (host memory).  Y: int32[n]; A: int32[sum |block|];

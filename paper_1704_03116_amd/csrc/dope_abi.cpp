@@ -46,6 +46,7 @@ struct dope_ctx {
     bool energy_set = false;
     bool profiling = false;
     std::vector<hipEvent_t> ev_solve, ev_cons;   // start/stop pairs
+    hipEvent_t ev_sync = nullptr;                // completion of the loop-control readback
     size_t n_solve = 0, n_cons = 0;
     std::string err;
 };
@@ -351,6 +352,26 @@ dope_status ensure_workspace(dope_ctx *c) {
     return upload_tables(c);
 }
 
+// Waits for the work enqueued on the context stream.  The loop-control readback sits on the critical path of
+// every solve, so the host polls a completion event for up to ~2 ms before it blocks: a blocking wait adds the
+// wake-up latency of the host thread to every readback.
+dope_status wait_stream(dope_ctx *c) {
+    if (!c->ev_sync && hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
+        c->ev_sync = nullptr;
+        HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+        return DOPE_OK;
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_sync, c->stream), "event record");
+    for (int spin = 0; spin < 200000; ++spin) {
+        const hipError_t q = hipEventQuery(c->ev_sync);
+        if (q == hipSuccess) return DOPE_OK;
+        if (q != hipErrorNotReady) return hip_fail(c, q, "event query");
+        if (spin > 20000) break;
+    }
+    HIP_TRY(c, hipEventSynchronize(c->ev_sync), "event synchronize");
+    return DOPE_OK;
+}
+
 dope_status sync_ctl(dope_ctx *c) {
     // a pending energy validation is taken before the loop control is read back
     if (c->validate_pending) {
@@ -358,8 +379,7 @@ dope_status sync_ctl(dope_ctx *c) {
         c->validate_pending = false;
     }
     HIP_TRY(c, hipMemcpyAsync(c->hctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream), "control readback");
-    HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
-    return DOPE_OK;
+    return wait_stream(c);
 }
 
 void fill_info(const dope_ctx *c, dope_info *out) {
@@ -510,7 +530,8 @@ dope_status enqueue_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int3
     dope_status st = ensure_workspace(c);
     if (st != DOPE_OK) return st;
     const Geom &g = c->g;
-    // host inputs are uploaded into the workspace copies; device inputs are read (and copied) by the setup kernel
+    // host inputs are uploaded into the workspace (w only as staging for the setup kernel); device inputs are read
+    // by the setup kernel directly
     const int32_t *u_src = u, *w_src = w;
     if (mem_kind == DOPE_MEM_HOST) {
         HIP_TRY(c, hipMemcpyAsync(c->u, u, size_t(g.n) * 4, hipMemcpyHostToDevice, c->stream), "unary upload");
@@ -519,7 +540,7 @@ dope_status enqueue_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int3
         w_src = c->w;
     }
     const uint64_t eps2 = uint64_t(c->p.eps_q16) * uint64_t(c->p.eps_q16);
-    HIP_TRY(c, dope::launch_setup(g, u_src, w_src, c->u, c->w, c->cw, lambda_q8, c->Y, c->A0, c->A1, c->yhat, c->resid,
+    HIP_TRY(c, dope::launch_setup(g, u_src, w_src, c->u, c->cw, lambda_q8, c->Y, c->A0, c->A1, c->yhat, c->resid,
                                   c->ctl, c->p.mu0, c->p.mu_fact_num, c->p.mu_fact_den, eps2, allow_negative,
                                   c->stream),
             "setup launch");
@@ -658,9 +679,12 @@ dope_status dope_energy(dope_ctx *c, int64_t *e_q8) {
     dope_status st = check_ready(c);
     if (st != DOPE_OK) return st;
     if (!e_q8) return fail(c, DOPE_EINVAL, "null output");
-    HIP_TRY(c, dope::launch_energy(c->g, c->u, c->w, c->lam_q8, c->Y, c->epart, c->ctl, c->stream), "energy launch");
+    HIP_TRY(c, dope::launch_energy(c->g, c->u, c->cw, c->Y, c->epart, c->ctl, c->stream), "energy launch");
     st = sync_ctl(c);
     if (st != DOPE_OK) return st;
+    // the pairwise term is recovered from c_ij, which a rejected energy does not hold in full
+    if (c->hctl->status == DOPE_EINVAL)
+        return fail(c, DOPE_EINVAL, status_message(c->hctl->status, c->hctl->vflags));
     *e_q8 = c->hctl->energy;
     return DOPE_OK;
 }
@@ -784,6 +808,7 @@ const char *dope_last_error(const dope_ctx *c) { return c ? c->err.c_str() : g_c
 void dope_destroy(dope_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->ev_sync) (void)hipEventDestroy(c->ev_sync);
     for (hipEvent_t e : c->ev_solve) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_cons) (void)hipEventDestroy(e);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
@@ -811,6 +836,7 @@ struct dope_batch {
     bool use_graph = false, graph_ready = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev_sync = nullptr;   // completion of the summary readback
     std::string err;
 };
 
@@ -853,7 +879,18 @@ dope_status batch_sync(dope_batch *b) {
     const size_t n = b->ctxs.size();
     BHIP_TRY(b, hipMemcpyAsync(b->hsum, b->dsum, n * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream),
              "summary readback");
-    BHIP_TRY(b, hipStreamSynchronize(b->stream), "stream synchronize");
+    // poll the completion before blocking (see wait_stream)
+    if (!b->ev_sync && hipEventCreateWithFlags(&b->ev_sync, hipEventDisableTiming) != hipSuccess) b->ev_sync = nullptr;
+    bool done = false;
+    if (b->ev_sync) {
+        BHIP_TRY(b, hipEventRecord(b->ev_sync, b->stream), "event record");
+        for (int spin = 0; spin <= 20000 && !done; ++spin) {
+            const hipError_t q = hipEventQuery(b->ev_sync);
+            if (q == hipSuccess) done = true;
+            else if (q != hipErrorNotReady) return bfail(b, DOPE_EDEVICE, std::string("event query: ") + hipGetErrorString(q));
+        }
+    }
+    if (!done) BHIP_TRY(b, hipStreamSynchronize(b->stream), "stream synchronize");
     for (dope_ctx *c : b->ctxs) c->dirty = true;
     return DOPE_OK;
 }
@@ -1106,6 +1143,7 @@ void dope_batch_destroy(dope_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_sync) (void)hipEventDestroy(b->ev_sync);
     if (b->dbuf) (void)hipFree(b->dbuf);
     if (b->hsum) (void)hipHostFree(b->hsum);
     if (b->hparams) (void)hipHostFree(b->hparams);

@@ -162,20 +162,20 @@ hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0
                                   hipEvent_t e1 = nullptr);
 hipError_t launch_finalize_phase(const Group &grp, hipStream_t s);
 
-// set_energy on the device: workspace copies of u and w (src != ws), c_ij, initial state and loop control.  The
+// set_energy on the device: workspace copy of u (src != ws), c_ij, initial state and loop control.  The
 // validation verdict (status / halted set on the device when the energy is invalid) is taken by the next
 // launch_validate, launch_ctl_setup or launch_batch_setup.
 hipError_t launch_validate(Ctl *ctl, hipStream_t s);
-hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *w_ws,
-                        int32_t *cw, int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
+hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *cw,
+                        int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
                         int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,
                         int32_t allow_negative, hipStream_t s);
 hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy,
                             hipStream_t s);
 hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s);
 // part: ENERGY_PARTS int64 of scratch.
-hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *w, int32_t lam_q8, const int32_t *Y,
-                         int64_t *part, Ctl *ctl, hipStream_t s);
+hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *cw, const int32_t *Y, int64_t *part,
+                         Ctl *ctl, hipStream_t s);
 constexpr int ENERGY_PARTS = 256;
 
 }  // namespace dope

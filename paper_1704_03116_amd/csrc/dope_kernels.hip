@@ -1101,7 +1101,8 @@ __global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, 
 // ------------------------------------------------------------------------------------------------------------
 
 // Everything set_energy puts on the device, in one launch over the pixel grid (grid: (ceil(W/256), H*D)):
-//   - copies of u and w into the workspace (skipped when the source already is the workspace copy),
+//   - a copy of u into the workspace (skipped when the source already is the workspace copy; w is not kept: the
+//     energy kernel recovers lambda_q8 w_ij exactly from c_ij),
 //   - c_ij = lambda_q8 w_ij 64 / (q_i q_j) for the half-stencil edges of every pixel, with validation bits (nonzero
 //     weight on an off-grid edge, negative weight, per-node sum_j |c_ij| >= 2^29) OR-ed into ctl->flags,
 //   - the initial ADMM state (Y = 1/2, A = 0, yhat = 0, r_k = 0; a grid-stride pass over the block-major arrays),
@@ -1116,7 +1117,7 @@ struct StateInit {
 template <int CONN>
 __device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int gz, const int32_t *__restrict__ u_src,
                                             const int32_t *__restrict__ w_src, int32_t *__restrict__ u_ws,
-                                            int32_t *__restrict__ w_ws, int32_t *__restrict__ cw, int32_t lam,
+                                            int32_t *__restrict__ cw, int32_t lam,
                                             int32_t *__restrict__ Y, Ctl *ctl) {
     constexpr int H = Sten<CONN>::H;
     const int64_t i = lin(g, gx, gy, gz);
@@ -1163,10 +1164,6 @@ __device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int g
     }
 #pragma unroll
     for (int d = 0; d < H; ++d) cw[int64_t(d) * g.n + i] = cl[d];
-    if (w_src != w_ws) {
-#pragma unroll
-        for (int d = 0; d < H; ++d) w_ws[int64_t(d) * g.n + i] = wl[d];
-    }
     if (u_src != u_ws) u_ws[i] = ui;
     Y[i] = Y_HALF;
     if (sum >= CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
@@ -1176,7 +1173,7 @@ __device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int g
 template <int CONN>
 __global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict__ u_src,
                                                const int32_t *__restrict__ w_src, int32_t *__restrict__ u_ws,
-                                               int32_t *__restrict__ w_ws, int32_t *__restrict__ cw, int32_t lam,
+                                               int32_t *__restrict__ cw, int32_t lam,
                                                int32_t *__restrict__ Y, int32_t *__restrict__ A0,
                                                int32_t *__restrict__ A1, uint8_t *__restrict__ yhat,
                                                int64_t *__restrict__ resid, Ctl *ctl, StateInit si) {
@@ -1213,7 +1210,7 @@ __global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict
     if (gx >= g.W) return;
     const int rows = g.H * g.D;
     for (int row = blockIdx.y; row < rows; row += gridDim.y)
-        setup_pixel<CONN>(g, gx, row % g.H, row / g.H, u_src, w_src, u_ws, w_ws, cw, lam, Y, ctl);
+        setup_pixel<CONN>(g, gx, row % g.H, row / g.H, u_src, w_src, u_ws, cw, lam, Y, ctl);
 }
 
 // Energy validation verdict of a pending k_setup: off-grid or oversized weights -> EINVAL; a negative weight
@@ -1284,9 +1281,8 @@ constexpr int ENERGY_WGS = 256;
 // Per-workgroup partial sums of E_q = 256 u.l + lambda_q8 sum_edges w |l_i - l_j| (grid-stride over pixels,
 // ENERGY_WGS workgroups, no atomics); k_energy_sum adds the partials into ctl->energy.
 template <int CONN>
-__global__ __launch_bounds__(256) void k_energy(Geom g, const int32_t *__restrict__ u, const int32_t *__restrict__ w,
-                                                int32_t lam, const int32_t *__restrict__ Y,
-                                                int64_t *__restrict__ part) {
+__global__ __launch_bounds__(256) void k_energy(Geom g, const int32_t *__restrict__ u, const int32_t *__restrict__ cw,
+                                                const int32_t *__restrict__ Y, int64_t *__restrict__ part) {
     constexpr int H = Sten<CONN>::H;
     __shared__ long long s_sum[4];
     long long e = 0;
@@ -1297,12 +1293,21 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int32_t *__restric
             const int64_t i = lin(g, gx, gy, gz);
             const int li = Y[i] > Y_HALF;
             if (li) e += 256ll * u[i];
+            AxCov cx[3], cy[3], cz[3];
+            axis_cov3(g.ax[0], gx, cx);
+            axis_cov3(g.ax[1], gy, cy);
+            if (CONN == 6) axis_cov3(g.ax[2], gz, cz);
+            else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
+            const int lqi = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);
 #pragma unroll
             for (int o = 0; o < H; ++o) {
                 const int3 v = half_off<CONN>(o);
                 if (!in_grid(g, gx + v.x, gy + v.y, gz + v.z)) continue;
                 const int lj = Y[lin(g, gx + v.x, gy + v.y, gz + v.z)] > Y_HALF;
-                if (li != lj) e += (long long)lam * w[int64_t(o) * g.n + i];
+                if (li == lj) continue;
+                // lambda_q8 w_ij = c_ij q_i q_j / 64 exactly (c_ij = lambda_q8 w_ij 64 / (q_i q_j), q a power of two)
+                const int lqj = (cx[v.x + 1].cnt - 1) + (cy[v.y + 1].cnt - 1) + (cz[v.z + 1].cnt - 1);
+                e += (static_cast<long long>(cw[int64_t(o) * g.n + i]) << (lqi + lqj)) >> 6;
             }
         }
     }
@@ -1398,18 +1403,18 @@ hipError_t solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_
 
 }  // namespace
 
-hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *w_ws,
-                        int32_t *cw, int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
+hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *cw,
+                        int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
                         int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,
                         int32_t allow_negative, hipStream_t s) {
     const dim3 grid(blocks_for(g.W, 256), row_blocks(g));
     const StateInit si{mu0, eps2, mu_num, mu_den, allow_negative};
     switch (g.conn) {
-        case 4: hipLaunchKernelGGL(k_setup<4>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, w_ws, cw, lam_q8, Y, A0,
+        case 4: hipLaunchKernelGGL(k_setup<4>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
                                    A1, yhat, resid, ctl, si); break;
-        case 8: hipLaunchKernelGGL(k_setup<8>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, w_ws, cw, lam_q8, Y, A0,
+        case 8: hipLaunchKernelGGL(k_setup<8>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
                                    A1, yhat, resid, ctl, si); break;
-        default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, w_ws, cw, lam_q8, Y,
+        default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y,
                                     A0, A1, yhat, resid, ctl, si); break;
     }
     return hipGetLastError();
@@ -1481,14 +1486,14 @@ hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *w, int32_t lam_q8, const int32_t *Y,
-                         int64_t *part, Ctl *ctl, hipStream_t s) {
+hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *cw, const int32_t *Y, int64_t *part,
+                         Ctl *ctl, hipStream_t s) {
     const int64_t rows = int64_t(g.H) * g.D;
     const unsigned wgs = unsigned(rows < ENERGY_WGS ? rows : ENERGY_WGS);
     switch (g.conn) {
-        case 4: hipLaunchKernelGGL(k_energy<4>, dim3(wgs), dim3(256), 0, s, g, u, w, lam_q8, Y, part); break;
-        case 8: hipLaunchKernelGGL(k_energy<8>, dim3(wgs), dim3(256), 0, s, g, u, w, lam_q8, Y, part); break;
-        default: hipLaunchKernelGGL(k_energy<6>, dim3(wgs), dim3(256), 0, s, g, u, w, lam_q8, Y, part); break;
+        case 4: hipLaunchKernelGGL(k_energy<4>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
+        case 8: hipLaunchKernelGGL(k_energy<8>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
+        default: hipLaunchKernelGGL(k_energy<6>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
     }
     hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s, part, int(wgs), ctl);
     return hipGetLastError();
