@@ -116,7 +116,6 @@ __device__ __forceinline__ int label_slot(const Geom &g, int tx, int ty, int tz,
     return e + 2 * b + 4 * a;
 }
 
-__device__ __forceinline__ bool in_axis(const AxCov &c, int t) { return t == c.thi || (c.cnt == 2 && t == c.thi - 1); }
 
 __device__ __forceinline__ bool in_grid(const Geom &g, int x, int y, int z) {
     return x >= 0 && x < g.W && y >= 0 && y < g.H && z >= 0 && z < g.D;
@@ -956,23 +955,45 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             S += int64_t(yv_own[q]) * Y_ONE + a_own[q];
             Y1 += yv_own[q];
         }
+        // The label words hold one byte (0 or 1) per slot q = e + 2b + 4a.  A slot set along one axis is a byte
+        // mask: slot bit e of that axis allowed for e in the 2-bit set.  A neighbour's copy in the block that is
+        // m's slot q sits in the neighbour's slot q + (dx + 2dy + 4dz), d_ the difference of the two pixels'
+        // top blocks, so shifting its word by that many bytes aligns the blocks holding both pixels.
+        auto sel = [](int set, SlotWord lo, SlotWord hi) -> SlotWord {
+            return ((set & 1) ? lo : SlotWord(0)) | ((set & 2) ? hi : SlotWord(0));
+        };
+        auto bytesum = [](SlotWord x) -> int {
+            return MAXC == 8 ? int((uint64_t(x) * 0x0101010101010101ull) >> 56) : int((uint32_t(x) * 0x01010101u) >> 24);
+        };
+        const SlotWord X0 = MAXC == 8 ? SlotWord(0x00FF00FF00FF00FFull) : SlotWord(0x00FF00FFu);
+        const SlotWord Y0 = MAXC == 8 ? SlotWord(0x0000FFFF0000FFFFull) : SlotWord(0x0000FFFFu);
+        const SlotWord Z0 = MAXC == 8 ? SlotWord(0x00000000FFFFFFFFull) : SlotWord(0xFFFFFFFFu);
+        const SlotWord X1 = SlotWord(~X0), Y1m = SlotWord(~Y0), Z1 = MAXC == 8 ? SlotWord(~Z0) : SlotWord(0);
+        // slots e of one axis with e < cnt
+        auto cnt_set = [](int cnt) -> int { return cnt >= 2 ? 3 : cnt; };
+        // slots e of m's axis interval whose block also holds the neighbour (top differs by dt, neighbour count cn)
+        auto shared_set = [](int cm, int dt, int cn) -> int {
+            int set = 0;
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (e < cm && e + dt >= 0 && e + dt < cn) set |= 1 << e;
+            return set;
+        };
         int64_t CQ = 0, YJ = 0, SH = 0;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
             const AxCov &ax = cx[v.x + 1], &ay = cy[v.y + 1], &az = cz[v.z + 1];
-            int yj_sum = 0, shared = 0;
-#pragma unroll
-            for (int q = 0; q < MAXC; ++q) {
-                const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
-                if (e < ax.cnt && b < ay.cnt && a < az.cnt) yj_sum += int((wj[d] >> (8 * q)) & 1u);
-                // own copy q in block (tx, ty, tz); when that block also holds j, compare with j's label there
-                const int tx = cx[1].thi - e, ty = cy[1].thi - b, tz = cz[1].thi - a;
-                if (v_own[q] && in_axis(ax, tx) && in_axis(ay, ty) && in_axis(az, tz)) {
-                    const int qj = (ax.thi - tx) + 2 * (ay.thi - ty) + 4 * (az.thi - tz);
-                    shared += yv_own[q] - int((wj[d] >> (8 * qj)) & 1u);
-                }
-            }
+            const SlotWord vj = sel(cnt_set(ax.cnt), X0, X1) & sel(cnt_set(ay.cnt), Y0, Y1m) &
+                                sel(cnt_set(az.cnt), Z0, Z1);
+            const int yj_sum = bytesum(wj[d] & vj);
+            const int dx = ax.thi - cx[1].thi, dy = ay.thi - cy[1].thi, dz = az.thi - cz[1].thi;
+            const SlotWord sm = sel(shared_set(cx[1].cnt, dx, ax.cnt), X0, X1) &
+                                sel(shared_set(cy[1].cnt, dy, ay.cnt), Y0, Y1m) &
+                                sel(shared_set(cz[1].cnt, dz, az.cnt), Z0, Z1);
+            const int sh = dx + 2 * dy + 4 * dz;
+            const SlotWord wal = sh >= 0 ? SlotWord(wj[d] >> (8 * sh)) : SlotWord(wj[d] << (-8 * sh));
+            const int shared = bytesum(wm & sm) - bytesum(wal & sm);
             CQ += int64_t(cwv[d]) * (ax.cnt * ay.cnt * az.cnt);
             YJ += int64_t(cwv[d]) * yj_sum;
             SH += int64_t(cwv[d]) * shared;
