@@ -1,15 +1,21 @@
 // gfx950 kernels of the DOPE ADMM iteration (Algorithm 1 of the paper).
 //
-//   k_block_solve       one workgroup per block: Eq. (8) unaries from Theorem 1's coupling terms, forced-node
-//                       elimination, push-relabel max preflow in LDS, canonical minimal cut -> yhat_k.
+//   k_setup             energy upload: copy of u, c_ij = lambda w 64 / (q_i q_j) with validation bits, initial
+//                       state (Y = 1/2, A = 0) and loop control.
+//   k_block_solve*      one workgroup per block: Eq. (8) unaries from Theorem 1's coupling terms, strictly forced
+//                       nodes, forced-node elimination, push-relabel max preflow in LDS, canonical minimal cut ->
+//                       yhat_k; Eq. (10)/(11) for the pixels interior to their block.  Variants: one image
+//                       (descriptor as kernel argument), a batch (one workgroup per item), a batch over a
+//                       persistent work queue.
 //   k_block_exhaustive  one wavefront per block of <= 16 pixels: Gray-code enumeration of all labellings,
 //                       smallest-code minimiser (any sign of the pairwise weights).
-//   k_consensus         one thread per block pixel: Eq. (10) consensus Y, Eq. (11) multipliers, per-block
-//                       residual of the stopping rule; the last workgroup updates mu and the loop control.
-//   k_labels_energy     labels [Y > 1/2] and the Eq. (1) energy.
+//   k_consensus*        one thread per boundary pixel: Eq. (10) consensus Y, Eq. (11) multipliers of its copies,
+//                       per-block residual of the stopping rule.
+//   k_finalize          loop control: max_k r_k, stopping rule, errors, mu and t.
+//   k_labels, k_energy  labels [Y > 1/2] and the Eq. (1) energy.
 //
-// All arithmetic is integer; every kernel first checks the device loop control and exits when the loop has
-// halted, so the host can enqueue several iterations ahead without reading anything back.
+// All arithmetic is integer; every kernel checks the device loop control, so the host can enqueue several
+// iterations ahead of the stopping rule without reading anything back.
 #include "dope_internal.h"
 
 #include <hip/hip_ext.h>
@@ -337,9 +343,9 @@ struct FlowStats {
 
 // Everything after the prologue for the nfree nodes of lst: elimination of the nodes that the reduced problem
 // forces, push-relabel to a max preflow, and the canonical cut (ST_MARK = label 1).
+// Forced-node elimination over the nfree nodes of lst; returns whether any node is left free.
 template <int CONN, class Sync>
-__device__ void flow_on_list(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t round_limit, int32_t relabel_period,
-                             FlowStats &fs) {
+__device__ bool eliminate(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs) {
     constexpr int ND = 2 * Sten<CONN>::H;
     // (1) a node is forced when its unary, with the pairwise terms of its fixed neighbours folded in, exceeds the
     //     total capacity towards its free neighbours.  Forcing only grows as neighbours get fixed, so passes may
@@ -379,10 +385,34 @@ __device__ void flow_on_list(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
         const int r = sy.bits(ch);
         if (!(r & 1)) {
             // a pass without changes: a node still free was seen free by this pass, so bit 1 is exact here
-            if (!(r & 2)) return;   // everything is forced: no flow network is left
-            break;
+            return (r & 2) != 0;
         }
     }
+}
+
+// Keeps the list entries that are still free (order not preserved); returns their count.  The height array,
+// not yet in use, holds the survivors by list position in between.  Whole workgroup; ctr is a zeroed LDS slot.
+template <int CONN>
+__device__ int compact_free(BlockLds<CONN> &L, int nfree, int *ctr, int tid, int nt) {
+    for (int i = tid; i < nfree; i += nt) {
+        const int p = L.lst[i];
+        L.hh[i] = (L.st[p] & ST_FIXED) ? int16_t(-1) : int16_t(p);
+    }
+    __syncthreads();
+    for (int i = tid; i < nfree; i += nt) {
+        const int v = L.hh[i];
+        if (v >= 0) L.lst[atomicAdd(ctr, 1)] = int16_t(v);
+    }
+    __syncthreads();
+    return *ctr;
+}
+
+// Everything after the elimination for the nfree nodes of lst: flow network, push-relabel to a max preflow, and
+// the canonical cut (ST_MARK = label 1).
+template <int CONN, class Sync>
+__device__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t round_limit, int32_t relabel_period,
+                             FlowStats &fs) {
+    constexpr int ND = 2 * Sten<CONN>::H;
     // (2) flow network of the remaining free nodes: source excess -U and sink capacity U in one signed value
     for (int i = sy.idx; i < nfree; i += sy.step) {
         const int p = L.lst[i];
@@ -530,7 +560,8 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     const int64_t M = ctl->M;
     const int tid = threadIdx.x;
 
-    int *s_ctr = reinterpret_cast<int *>(smem);    // scalar slots 0..14 (6..7: a 64-bit residual sum)
+    // scalar slots 0..14: 1 free-list length, 2..4 barrier flags, 6..7 a 64-bit residual sum, 8 compaction count
+    int *s_ctr = reinterpret_cast<int *>(smem);
     BlockLds<CONN> L;
     L.npmax = npmax;
     L.cap = reinterpret_cast<int32_t *>(smem + 64);
@@ -581,11 +612,22 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     if (nfree > 0 && nfree <= WAVE_FLOW_MAX) {
         if (tid < 64) {
             WaveSync sy{tid, 64};
-            flow_on_list<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
+            if (eliminate<CONN>(sy, L, nfree, fs)) flow_network<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
         }
     } else if (nfree > 0) {
         BlockSync sy{tid, NT, s_ctr + 2, 0};
-        flow_on_list<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
+        if (eliminate<CONN>(sy, L, nfree, fs)) {
+            // the flow phases only visit the nodes the elimination left free; few enough go to one wavefront
+            const int nleft = compact_free<CONN>(L, nfree, s_ctr + 8, tid, NT);
+            if (nleft <= WAVE_FLOW_MAX) {
+                if (tid < 64) {
+                    WaveSync ws{tid, 64};
+                    flow_network<CONN>(ws, L, nleft, round_limit, relabel_period, fs);
+                }
+            } else {
+                flow_network<CONN>(sy, L, nleft, round_limit, relabel_period, fs);
+            }
+        }
     }
     __syncthreads();
 
