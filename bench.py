@@ -226,9 +226,9 @@ def main():
     kernels = {
         # per block pixel: u 4 + weights 4h + Y 4 + A 4 read, block label 1 written; per interior pixel (finished
         # in this kernel): Y 4 + A 4 written
-        "k_block_solve": (tot * (13 + 4 * h) + n_int * 8, prof["solve_ms"], prof["solve_launches"]),
+        "k_block_solve_one": (tot * (13 + 4 * h) + n_int * 8, prof["solve_ms"], prof["solve_launches"]),
         # per boundary copy: block label 1 + A 4 read, A 4 written; per boundary pixel: weights 4h read, Y 4 written
-        "k_consensus": (n_bl * 9 + (n - n_int) * (4 * h + 4), prof["consensus_ms"], prof["consensus_launches"]),
+        "k_consensus_one": (n_bl * 9 + (n - n_int) * (4 * h + 4), prof["consensus_ms"], prof["consensus_launches"]),
     }
     traffic = measured_traffic(p.name)
 
