@@ -285,12 +285,13 @@ def main():
             c.set_energy(uu, ww, q.lam_q8)
         b = Batch(ctxs, graph=True)
 
+        us, ws, lams = [x[0] for x in ins], [x[1] for x in ins], [q.lam_q8 for q in probs]
+
         def bstep():
-            for c, q, (uu, ww) in zip(ctxs, probs, ins):
-                c.set_energy_async(uu, ww, q.lam_q8)
+            # one launch uploads every image's energy, one launch writes every image's labels
+            b.set_energy_async(us, ws, lams)
             b.solve()
-            for c, lb in zip(ctxs, labs):
-                c.labels(lb)
+            b.labels(labs)
 
         for _ in range(args.warmup):
             bstep()

@@ -182,6 +182,15 @@ dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectiv
 typedef struct dope_batch dope_batch;
 
 dope_status dope_batch_create(dope_ctx *const *ctxs, int32_t n, dope_batch **out);
+/* dope_set_energy_async for every member in one launch: u[i], w[i], lambda_q8[i] as for context i (n entries in
+ * context order, all in mem_kind memory; device inputs must stay valid until the work has run).  The resolved
+ * solver of each member is kept.  Validation errors stop that image on the device and are returned by the next
+ * batch call, as for dope_set_energy_async. */
+dope_status dope_batch_set_energy_async(dope_batch *b, const int32_t *const *u, const int32_t *const *w,
+                                        const int32_t *lambda_q8, int32_t mem_kind);
+/* dope_labels for every member in one launch: labels[i] is uint8[n_i] in mem_kind memory (device memory:
+ * stream-ordered, returns at once; host memory: complete on return). */
+dope_status dope_batch_labels(dope_batch *b, uint8_t *const *labels, int32_t mem_kind);
 /* exactly n_iter iterations for every image whose loop has not stopped on an error */
 dope_status dope_batch_iterate(dope_batch *b, int32_t n_iter);
 /* until every image meets its stopping rule or reaches its max_iter (an image that fails stops alone; the call

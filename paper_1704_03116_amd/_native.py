@@ -72,6 +72,8 @@ SIGNATURES = {
     "dope_profile_read": (ctypes.c_int, [_P, _DP, _I32P, _DP, _I32P]),
     "dope_last_error": (ctypes.c_char_p, [_P]),
     "dope_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "dope_batch_set_energy_async": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _I32P, ctypes.c_int32]),
+    "dope_batch_labels": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.c_int32]),
     "dope_batch_iterate": (ctypes.c_int, [_P, ctypes.c_int32]),
     "dope_batch_solve": (ctypes.c_int, [_P]),
     "dope_batch_set_graph": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -151,6 +153,8 @@ dope_profile_read = _fn("dope_profile_read")
 dope_last_error = _fn("dope_last_error")
 dope_destroy = _fn("dope_destroy")
 dope_batch_create = _fn("dope_batch_create")
+dope_batch_set_energy_async = _fn("dope_batch_set_energy_async")
+dope_batch_labels = _fn("dope_batch_labels")
 dope_batch_iterate = _fn("dope_batch_iterate")
 dope_batch_solve = _fn("dope_batch_solve")
 dope_batch_set_graph = _fn("dope_batch_set_graph")

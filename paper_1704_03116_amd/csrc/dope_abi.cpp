@@ -837,6 +837,12 @@ struct dope_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipEvent_t ev_sync = nullptr;   // completion of the summary readback
+    // batched energy upload and labels: (image, pixel row) items, per-image arguments and label pointers
+    dope::Item *rows = nullptr;
+    int32_t n_rows = 0;
+    dope::SetupArg *dargs = nullptr, *hargs = nullptr;   // device / pinned staging
+    uint8_t **dlabs = nullptr, **hlabs = nullptr;         // device / pinned staging
+    hipEvent_t ev_stage = nullptr;   // the last upload of the pinned staging arrays has run after this
     std::string err;
 };
 
@@ -953,19 +959,23 @@ dope_status batch_bind(dope_batch *b, dope_ctx *const *ctxs, int32_t n) {
         if (c->g.conn != conn || c->solver != solver)
             return bfail(b, DOPE_EINVAL, "batch members must share connectivity and solver");
     }
-    int64_t nblk = 0, nchk = 0;
+    int64_t nblk = 0, nchk = 0, nrow = 0;
     int32_t npmax = 0;
     for (int32_t i = 0; i < n; ++i) {
         nblk += ctxs[i]->g.K;
         nchk += int64_t(ctxs[i]->hchunk.size());
+        nrow += int64_t(ctxs[i]->g.H) * ctxs[i]->g.D;
         npmax = std::max(npmax, ctxs[i]->g.max_np);
     }
-    if (nblk >= (int64_t(1) << 31) || nchk >= (int64_t(1) << 31)) return bfail(b, DOPE_EINVAL, "batch too large");
+    if (nblk >= (int64_t(1) << 31) || nchk >= (int64_t(1) << 31) || nrow >= (int64_t(1) << 31))
+        return bfail(b, DOPE_EINVAL, "batch too large");
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
     const size_t o_img = take(size_t(n) * sizeof(dope::Img)), o_bi = take(size_t(nblk) * sizeof(dope::Item)),
                  o_ci = take(size_t(nchk) * sizeof(dope::Item)), o_q = take(sizeof(dope::Queue)),
-                 o_sum = take(size_t(n) * 16), o_par = take(size_t(n) * 8);
+                 o_sum = take(size_t(n) * 16), o_par = take(size_t(n) * 8),
+                 o_rows = take(size_t(nrow) * sizeof(dope::Item)), o_args = take(size_t(n) * sizeof(dope::SetupArg)),
+                 o_labs = take(size_t(n) * sizeof(uint8_t *));
     if (o > b->dcap) {
         if (b->dbuf) (void)hipFree(b->dbuf);
         b->dbuf = nullptr;
@@ -979,19 +989,30 @@ dope_status batch_bind(dope_batch *b, dope_ctx *const *ctxs, int32_t n) {
         b->dcap = o + o / 2;
     }
     if (size_t(n) > b->hcap) {
+        if (b->ev_stage) (void)hipEventSynchronize(b->ev_stage);   // staging arrays may still be read
         if (b->hsum) (void)hipHostFree(b->hsum);
         if (b->hparams) (void)hipHostFree(b->hparams);
+        if (b->hargs) (void)hipHostFree(b->hargs);
+        if (b->hlabs) (void)hipHostFree(b->hlabs);
         b->hsum = b->hparams = nullptr;
+        b->hargs = nullptr;
+        b->hlabs = nullptr;
         b->hcap = 0;
-        void *hs = nullptr, *hp = nullptr;
+        void *hs = nullptr, *hp = nullptr, *ha = nullptr, *hl = nullptr;
         const size_t cap = size_t(n) + size_t(n) / 2;
         if (hipHostMalloc(&hs, cap * 16, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc(&hp, cap * 8, hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc(&hp, cap * 8, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&ha, cap * sizeof(dope::SetupArg), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&hl, cap * sizeof(uint8_t *), hipHostMallocDefault) != hipSuccess) {
             if (hs) (void)hipHostFree(hs);
+            if (hp) (void)hipHostFree(hp);
+            if (ha) (void)hipHostFree(ha);
             return bfail(b, DOPE_ENOMEM, "pinned host allocation failed");
         }
         b->hsum = static_cast<int32_t *>(hs);
         b->hparams = static_cast<int32_t *>(hp);
+        b->hargs = static_cast<dope::SetupArg *>(ha);
+        b->hlabs = static_cast<uint8_t **>(hl);
         b->hcap = cap;
     }
     b->ctxs.assign(ctxs, ctxs + n);
@@ -1001,16 +1022,22 @@ dope_status batch_bind(dope_batch *b, dope_ctx *const *ctxs, int32_t n) {
     auto *q = reinterpret_cast<dope::Queue *>(b->dbuf + o_q);
     b->dsum = reinterpret_cast<int32_t *>(b->dbuf + o_sum);
     b->dparams = reinterpret_cast<int32_t *>(b->dbuf + o_par);
+    b->rows = reinterpret_cast<dope::Item *>(b->dbuf + o_rows);
+    b->n_rows = int32_t(nrow);
+    b->dargs = reinterpret_cast<dope::SetupArg *>(b->dbuf + o_args);
+    b->dlabs = reinterpret_cast<uint8_t **>(b->dbuf + o_labs);
     std::vector<dope::Img> himg(static_cast<size_t>(n));
-    std::vector<dope::Item> hbi, hci;
+    std::vector<dope::Item> hbi, hci, hrow;
     hbi.reserve(size_t(nblk));
     hci.reserve(size_t(nchk));
+    hrow.reserve(size_t(nrow));
     for (int32_t i = 0; i < n; ++i) {
         dope_ctx *c = ctxs[i];
         himg[size_t(i)] = host_img(c);
         himg[size_t(i)].summary = b->dsum + 4 * i;
         for (int32_t k = 0; k < c->g.K; ++k) hbi.push_back(dope::Item{i, k});
         for (size_t k = 0; k < c->hchunk.size(); ++k) hci.push_back(dope::Item{i, int32_t(k)});
+        for (int32_t r = 0; r < c->g.H * c->g.D; ++r) hrow.push_back(dope::Item{i, r});
         b->hsum[4 * i + 0] = c->hctl->t;
         b->hsum[4 * i + 1] = c->hctl->halted;
         b->hsum[4 * i + 2] = c->hctl->converged;
@@ -1021,6 +1048,8 @@ dope_status batch_bind(dope_batch *b, dope_ctx *const *ctxs, int32_t n) {
              "descriptor upload");
     BHIP_TRY(b, hipMemcpyAsync(bi, hbi.data(), hbi.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream),
              "item upload");
+    BHIP_TRY(b, hipMemcpyAsync(b->rows, hrow.data(), hrow.size() * sizeof(dope::Item), hipMemcpyHostToDevice,
+                               b->stream), "row item upload");
     if (!hci.empty())
         BHIP_TRY(b, hipMemcpyAsync(ci, hci.data(), hci.size() * sizeof(dope::Item), hipMemcpyHostToDevice, b->stream),
                  "item upload");
@@ -1052,6 +1081,77 @@ dope_status dope_batch_create(dope_ctx *const *ctxs, int32_t n, dope_batch **out
         return st;
     }
     *out = b;
+    return DOPE_OK;
+}
+
+dope_status dope_batch_set_energy_async(dope_batch *b, const int32_t *const *u, const int32_t *const *w,
+                                        const int32_t *lambda_q8, int32_t mem_kind) {
+    if (!b || !u || !w || !lambda_q8) return DOPE_EINVAL;
+    if (mem_kind != DOPE_MEM_HOST && mem_kind != DOPE_MEM_DEVICE) return bfail(b, DOPE_EINVAL, "bad mem_kind");
+    const size_t n = b->ctxs.size();
+    for (size_t i = 0; i < n; ++i) {
+        if (!u[i] || !w[i]) return bfail(b, DOPE_EINVAL, "null input of image " + std::to_string(i));
+        if (lambda_q8[i] < 0) return bfail(b, DOPE_EINVAL, "lambda must be >= 0 (image " + std::to_string(i) + ")");
+    }
+    // the pinned argument staging may still be read by the previous upload
+    if (b->ev_stage) BHIP_TRY(b, hipEventSynchronize(b->ev_stage), "event synchronize");
+    for (size_t i = 0; i < n; ++i) {
+        dope_ctx *c = b->ctxs[i];
+        const Geom &g = c->g;
+        const int32_t *u_src = u[i], *w_src = w[i];
+        if (mem_kind == DOPE_MEM_HOST) {
+            BHIP_TRY(b, hipMemcpyAsync(c->u, u[i], size_t(g.n) * 4, hipMemcpyHostToDevice, b->stream), "unary upload");
+            BHIP_TRY(b, hipMemcpyAsync(c->w, w[i], size_t(g.n) * g.hs * 4, hipMemcpyHostToDevice, b->stream),
+                     "weight upload");
+            u_src = c->u;
+            w_src = c->w;
+        }
+        b->hargs[i] = dope::SetupArg{u_src, w_src, c->p.mu0, uint64_t(c->p.eps_q16) * uint64_t(c->p.eps_q16),
+                                     lambda_q8[i], c->p.mu_fact_num, c->p.mu_fact_den,
+                                     int32_t(c->solver == DOPE_SOLVER_EXHAUSTIVE ? 1 : 0)};
+    }
+    BHIP_TRY(b, hipMemcpyAsync(b->dargs, b->hargs, n * sizeof(dope::SetupArg), hipMemcpyHostToDevice, b->stream),
+             "argument upload");
+    if (!b->ev_stage && hipEventCreateWithFlags(&b->ev_stage, hipEventDisableTiming) != hipSuccess) b->ev_stage = nullptr;
+    if (b->ev_stage) BHIP_TRY(b, hipEventRecord(b->ev_stage, b->stream), "event record");
+    BHIP_TRY(b, dope::launch_setup_batch(b->grp.conn, b->imgs, b->dargs, b->rows, b->n_rows, b->stream),
+             "batched setup launch");
+    for (size_t i = 0; i < n; ++i) {
+        dope_ctx *c = b->ctxs[i];
+        // host mirror of the reset state (as dope_set_energy_async); validation is taken by the next batch call
+        Ctl h{};
+        h.M = c->p.mu0;
+        h.eps2 = uint64_t(c->p.eps_q16) * uint64_t(c->p.eps_q16);
+        h.mu_num = c->p.mu_fact_num;
+        h.mu_den = c->p.mu_fact_den;
+        *c->hctl = h;
+        c->dirty = false;
+        c->lam_q8 = lambda_q8[i];
+        c->energy_set = true;
+        c->validate_pending = true;
+        c->err.clear();
+    }
+    return DOPE_OK;
+}
+
+dope_status dope_batch_labels(dope_batch *b, uint8_t *const *labels, int32_t mem_kind) {
+    if (!b || !labels) return DOPE_EINVAL;
+    if (mem_kind != DOPE_MEM_HOST && mem_kind != DOPE_MEM_DEVICE) return bfail(b, DOPE_EINVAL, "bad mem_kind");
+    const size_t n = b->ctxs.size();
+    for (size_t i = 0; i < n; ++i)
+        if (!labels[i]) return bfail(b, DOPE_EINVAL, "null labels of image " + std::to_string(i));
+    if (b->ev_stage) BHIP_TRY(b, hipEventSynchronize(b->ev_stage), "event synchronize");
+    for (size_t i = 0; i < n; ++i) b->hlabs[i] = mem_kind == DOPE_MEM_DEVICE ? labels[i] : b->ctxs[i]->labels;
+    BHIP_TRY(b, hipMemcpyAsync(b->dlabs, b->hlabs, n * sizeof(uint8_t *), hipMemcpyHostToDevice, b->stream),
+             "label pointer upload");
+    if (!b->ev_stage && hipEventCreateWithFlags(&b->ev_stage, hipEventDisableTiming) != hipSuccess) b->ev_stage = nullptr;
+    if (b->ev_stage) BHIP_TRY(b, hipEventRecord(b->ev_stage, b->stream), "event record");
+    BHIP_TRY(b, dope::launch_labels_batch(b->imgs, b->dlabs, b->rows, b->n_rows, b->stream), "batched labels launch");
+    if (mem_kind == DOPE_MEM_DEVICE) return DOPE_OK;   // stream-ordered, no wait
+    for (size_t i = 0; i < n; ++i)
+        BHIP_TRY(b, hipMemcpyAsync(labels[i], b->ctxs[i]->labels, size_t(b->ctxs[i]->g.n), hipMemcpyDeviceToHost,
+                                   b->stream), "labels copy");
+    BHIP_TRY(b, hipStreamSynchronize(b->stream), "stream synchronize");
     return DOPE_OK;
 }
 
@@ -1144,6 +1244,9 @@ void dope_batch_destroy(dope_batch *b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->ev_sync) (void)hipEventDestroy(b->ev_sync);
+    if (b->ev_stage) (void)hipEventDestroy(b->ev_stage);
+    if (b->hargs) (void)hipHostFree(b->hargs);
+    if (b->hlabs) (void)hipHostFree(b->hlabs);
     if (b->dbuf) (void)hipFree(b->dbuf);
     if (b->hsum) (void)hipHostFree(b->hsum);
     if (b->hparams) (void)hipHostFree(b->hparams);

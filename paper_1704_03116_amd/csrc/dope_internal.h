@@ -125,7 +125,15 @@ struct Img {
 };
 
 struct Item {
-    int32_t img, idx;   // image, and block (solve) or 256-copy chunk (consensus)
+    int32_t img, idx;   // image, and block (solve), 256-pixel chunk (consensus) or pixel row (setup, labels)
+};
+
+// Per-image arguments of a batched energy upload.
+struct SetupArg {
+    const int32_t *u_src, *w_src;   // inputs in device memory (the workspace staging copies for host inputs)
+    int64_t mu0;
+    uint64_t eps2;
+    int32_t lam_q8, mu_num, mu_den, allow_negative;
 };
 
 // Device work queue of the persistent block-solve launch; reset by the finalize kernel of each iteration.
@@ -173,6 +181,11 @@ hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_sr
 hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy,
                             hipStream_t s);
 hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s);
+// Batched energy upload and labels: one workgroup per (image, pixel row) item, n_rows items.
+hipError_t launch_setup_batch(int32_t conn, const Img *imgs, const SetupArg *args, const Item *rows, int32_t n_rows,
+                              hipStream_t s);
+hipError_t launch_labels_batch(const Img *imgs, uint8_t *const *labels, const Item *rows, int32_t n_rows,
+                               hipStream_t s);
 // part: ENERGY_PARTS int64 of scratch.
 hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *cw, const int32_t *Y, int64_t *part,
                          Ctl *ctl, hipStream_t s);

@@ -1276,6 +1276,65 @@ __global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict
         setup_pixel<CONN>(g, gx, row % g.H, row / g.H, u_src, w_src, u_ws, cw, lam, Y, ctl);
 }
 
+// Batched energy upload: workgroup b sets up pixel row rows[b].idx of image rows[b].img (row = y + H z) and its
+// share of the image's block-major arrays; the image's row 0 also resets its loop control.
+template <int CONN>
+__global__ __launch_bounds__(256) void k_setup_batch(const Img *__restrict__ imgs, const SetupArg *__restrict__ args,
+                                                     const Item *__restrict__ rows) {
+    const Item wi = rows[blockIdx.x];
+    const Img &im = const_img(imgs + wi.img);
+    const SetupArg &a = args[wi.img];
+    const Geom &g = im.g;
+    const int nrows = g.H * g.D;
+    const int row = wi.idx;
+    {
+        const int64_t lo = g.tot * row / nrows, hi = g.tot * (row + 1) / nrows;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+            gp(im.A0)[i] = 0;
+            gp(im.A1)[i] = 0;
+            gp(im.yhat)[i] = 0;
+        }
+        const int64_t klo = int64_t(g.K) * row / nrows, khi = int64_t(g.K) * (row + 1) / nrows;
+        for (int64_t k = klo + threadIdx.x; k < khi; k += 256) gp(im.resid)[k] = 0;
+        if (row == 0 && threadIdx.x == 0) {
+            GLOBAL Ctl *c = gp(im.ctl);
+            c->M = a.mu0;
+            c->max_resid = 0;
+            c->last_max_resid = 0;
+            c->eps2 = a.eps2;
+            c->energy = 0;
+            c->t = 0;
+            c->t_limit = 0;
+            c->stop_on_converge = 0;
+            c->converged = 0;
+            c->halted = 0;
+            c->status = 0;
+            c->ovf_pending = 0;
+            c->solver_err = 0;
+            c->wg_counter = 0;
+            c->mu_num = a.mu_num;
+            c->mu_den = a.mu_den;
+            c->vflags = 0;
+            c->vpending = 1;
+            c->allow_negative = a.allow_negative;
+        }
+    }
+    for (int gx = threadIdx.x; gx < g.W; gx += 256)
+        setup_pixel<CONN>(g, gx, row % g.H, row / g.H, a.u_src, a.w_src, const_cast<int32_t *>(im.u),
+                          const_cast<int32_t *>(im.cw), a.lam_q8, im.Y, im.ctl);
+}
+
+// Batched labels: workgroup b writes pixel row rows[b].idx of image rows[b].img into labels[img].
+__global__ __launch_bounds__(256) void k_labels_batch(const Img *__restrict__ imgs, uint8_t *const *__restrict__ labels,
+                                                      const Item *__restrict__ rows) {
+    const Item wi = rows[blockIdx.x];
+    const Img &im = const_img(imgs + wi.img);
+    const GLOBAL int32_t *Y = gp(im.Y);
+    GLOBAL uint8_t *out = gp(labels[wi.img]);
+    const int64_t base = int64_t(im.g.W) * wi.idx;
+    for (int gx = threadIdx.x; gx < im.g.W; gx += 256) out[base + gx] = uint8_t(Y[base + gx] > Y_HALF);
+}
+
 // Energy validation verdict of a pending k_setup: off-grid or oversized weights -> EINVAL; a negative weight
 // when the resolved solver is max-flow -> ENOTSUBMODULAR.  Stops the loop before any iteration runs.  The
 // accumulated bits move to ctl->vflags (read by the host for the error message) and the accumulator is cleared
@@ -1480,6 +1539,24 @@ hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_sr
         default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y,
                                     A0, A1, yhat, resid, ctl, si); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_batch(int32_t conn, const Img *imgs, const SetupArg *args, const Item *rows, int32_t n_rows,
+                              hipStream_t s) {
+    if (n_rows <= 0) return hipSuccess;
+    switch (conn) {
+        case 4: hipLaunchKernelGGL(k_setup_batch<4>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
+        case 8: hipLaunchKernelGGL(k_setup_batch<8>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
+        default: hipLaunchKernelGGL(k_setup_batch<6>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_labels_batch(const Img *imgs, uint8_t *const *labels, const Item *rows, int32_t n_rows,
+                               hipStream_t s) {
+    if (n_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_labels_batch, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, labels, rows);
     return hipGetLastError();
 }
 

@@ -236,6 +236,39 @@ class Batch:
         if st != N.DOPE_OK:
             raise N.DopeError(st, N.dope_batch_last_error(self.b).decode())
 
+    def set_energy_async(self, us, ws, lambdas_q8):
+        """Energy upload of every member in one launch (device tensors or host arrays, all in the same memory)."""
+        n = len(self.members)
+        if not (len(us) == len(ws) == len(lambdas_q8) == n):
+            raise ValueError("one u, w and lambda per member")
+        pu, pw, kinds = [], [], set()
+        for u, w in zip(us, ws):
+            a, ka = _ptr(u)
+            c, kc = _ptr(w)
+            pu.append(a)
+            pw.append(c)
+            kinds.update((ka, kc))
+        if len(kinds) != 1:
+            raise ValueError("all inputs must live in the same memory")
+        self._keep = (us, ws)   # device inputs must stay alive until the upload has run
+        arr_u = (ctypes.c_void_p * n)(*[x.value for x in pu])
+        arr_w = (ctypes.c_void_p * n)(*[x.value for x in pw])
+        lam = (ctypes.c_int32 * n)(*[int(x) for x in lambdas_q8])
+        self._check(N.dope_batch_set_energy_async(self.b, arr_u, arr_w, lam, kinds.pop()))
+
+    def labels(self, outs=None):
+        """Labels of every member in one launch: into the given device tensors (stream-ordered), or returned as host
+        arrays."""
+        n = len(self.members)
+        if outs is None:
+            outs = [np.empty(m.n, dtype=np.uint8) for m in self.members]
+            arr = (ctypes.c_void_p * n)(*[o.ctypes.data for o in outs])
+            self._check(N.dope_batch_labels(self.b, arr, N.DOPE_MEM_HOST))
+            return outs
+        arr = (ctypes.c_void_p * n)(*[int(o.data_ptr()) for o in outs])
+        self._check(N.dope_batch_labels(self.b, arr, N.DOPE_MEM_DEVICE))
+        return outs
+
     def iterate(self, n_iter=1):
         self._check(N.dope_batch_iterate(self.b, int(n_iter)))
 

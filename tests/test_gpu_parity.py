@@ -391,6 +391,44 @@ def test_batch_solve_again_after_new_energies():
     assert more > 0, "the second energies should need more iterations than the first took"
 
 
+@pytest.mark.parametrize("device", [True, False])
+def test_batch_energy_upload_and_labels(device):
+    """One-launch energy upload and labels for a whole batch equal the per-context calls and the oracle; a second
+    upload with other energies restarts every image."""
+    from paper_1704_03116_amd.solver import Batch
+    import torch
+    first = _batch_problems()
+    second = [synth.config2(seed=30 + i, W=q.dims[0], H=q.dims[1]) for i, q in enumerate(first)]
+    for q in second:
+        q.mu0 = first[0].mu0
+    announce(f"batched energy upload and labels, device inputs={device}")
+    ctxs = [make_ctx(p) for p in first]
+
+    def inputs(probs):
+        if device:
+            return ([torch.from_numpy(np.ascontiguousarray(q.u)).cuda() for q in probs],
+                    [torch.from_numpy(np.ascontiguousarray(q.w)).cuda() for q in probs])
+        return [np.ascontiguousarray(q.u) for q in probs], [np.ascontiguousarray(q.w) for q in probs]
+
+    with Batch(ctxs, graph=True) as b:
+        for probs in (first, second):
+            us, ws = inputs(probs)
+            b.set_energy_async(us, ws, [q.lam_q8 for q in probs])
+            b.solve()
+            infos = b.info()
+            host = b.labels()
+            dev = b.labels([torch.empty(q.n, dtype=torch.uint8, device="cuda") for q in probs])
+            torch.cuda.synchronize()
+            for q, c, inf, lh, ld in zip(probs, ctxs, infos, host, dev):
+                st_o, infos_o, _, _ = od.run(q)
+                assert inf["iters_done"] == len(infos_o), q.name
+                Y, A, yh, mu, t = c.get_state()
+                assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A), q.name
+                assert np.array_equal(lh, od.labels(st_o.Y)) and np.array_equal(ld.cpu().numpy(), lh), q.name
+    for c in ctxs:
+        c.close()
+
+
 def test_batch_exhaustive_nonsubmodular():
     from paper_1704_03116_amd.solver import Batch
     probs = [synth.config4(seed=s, size=sz) for s, sz in enumerate([24, 37, 16])]
