@@ -91,7 +91,8 @@ typedef struct {
 } dope_info;
 
 /* Validate p and create a context (no device memory is taken until dope_set_energy or a bound workspace).
- * Returns EINVAL for unsupported shapes (block bigger than 160 KiB of LDS, bad overlap, bad stencil). */
+ * Returns EINVAL for unsupported shapes (block bigger than 160 KiB of LDS, bad overlap, bad stencil, more than
+ * 2^30 - 1 pixels in 2D or 2^29 - 1 voxels in 3D, block sizes summing to 2^30 or more). */
 dope_status dope_create(const dope_params *p, dope_ctx **out);
 
 /* Load the energy (Eq. 1) and reset the ADMM state of Algorithm 1's initialisation: Y = 2^15, A = 0,

@@ -109,7 +109,9 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
         if (dims[a] <= 0) return "dims must be positive";
         n *= dims[a];
     }
-    if (n >= (int64_t(1) << 31)) return "grid too large (n must be < 2^31)";
+    // the kernels address per-pixel arrays with 32-bit byte offsets; the label slots take 4 (2D) or 8 (3D)
+    // bytes per pixel
+    if (n * (p->ndim == 3 ? 8 : 4) > (int64_t(1) << 32) - 1) return "grid too large (n must be < 2^30 in 2D, < 2^29 in 3D)";
     int64_t K = 1, max_np = 1;
     for (int a = 0; a < 3; ++a) {
         const int N = dims[a];
@@ -150,7 +152,7 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
                     r[0] = x0; r[1] = y0; r[2] = z0; r[3] = ex; r[4] = ey; r[5] = ez; r[6] = int32_t(tot); r[7] = 0;
                 }
                 tot += int64_t(ex) * ey * ez;
-                if (tot >= (int64_t(1) << 31)) return "sum of block sizes must be < 2^31";
+                if (tot >= (int64_t(1) << 30)) return "sum of block sizes must be < 2^30";
             }
     g.tot = tot;
     for (int a = 0; a < 3; ++a)

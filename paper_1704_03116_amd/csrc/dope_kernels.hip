@@ -33,6 +33,19 @@ namespace {
 template <class T>
 __device__ __forceinline__ GLOBAL T *gp(T *p) { return (GLOBAL T *)p; }
 
+// Element at byte offset off of a global array: a uniform base plus a 32-bit lane offset, which the compiler
+// issues as a load with the base in scalar registers and no 64-bit address arithmetic per lane.  Every array
+// read this way is below 4 GiB: pixel and copy counts are below 2^30, and the label slots of a 3D grid (8 bytes
+// per voxel) below 2^32 bytes.
+template <class T>
+__device__ __forceinline__ T ld_at(const GLOBAL T *base, uint32_t off) {
+    return *reinterpret_cast<const GLOBAL T *>(reinterpret_cast<const GLOBAL char *>(base) + off);
+}
+template <class T>
+__device__ __forceinline__ void st_at(GLOBAL T *base, uint32_t off, T v) {
+    *reinterpret_cast<GLOBAL T *>(reinterpret_cast<GLOBAL char *>(base) + off) = v;
+}
+
 enum : uint8_t { ST_FIXED = 1, ST_LABEL = 2, ST_MARK = 8 };
 constexpr int16_t H_INF = 0x7FFF;
 
@@ -81,8 +94,9 @@ struct AxCov {
 __device__ __forceinline__ int qdiv(int n, int d, double inv, int &rem) {
     int q = int(double(n) * inv);
     int r = n - q * d;
-    if (r < 0) { --q; r += d; }
-    else if (r >= d) { ++q; r -= d; }
+    const bool lo = r < 0, hi = r >= d;   // selects, not branches
+    q += (hi ? 1 : 0) - (lo ? 1 : 0);
+    r += lo ? d : (hi ? -d : 0);
     rem = r;
     return q;
 }
@@ -103,12 +117,18 @@ __device__ __forceinline__ int3 block_local(int p, int ex, int ey, double inv_ex
 __device__ __forceinline__ void axis_cov3(const Axis &a, int x, AxCov c[3]) {
     int rem;
     const int tr = qdiv(x, a.s, a.inv_s, rem);
+    // t_hi of x is tm = min(tr, nb - 1); that of x - 1 is one less when x starts a stride period and tr is not
+    // clamped, that of x + 1 one more when x ends one and tr + 1 is not clamped.  The start of block t_hi - 1,
+    // (t_hi - 1) s, follows from one product.
+    const int tm = tr < a.nb - 1 ? tr : a.nb - 1;
+    const int pm = (tm - 1) * a.s;
+    const bool dn = rem == 0 && tr <= a.nb - 1, up = rem == a.s - 1 && tr < a.nb - 1;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         const int xx = x + t - 1;
-        int th = t == 0 ? tr - (rem == 0 ? 1 : 0) : (t == 2 ? tr + (rem == a.s - 1 ? 1 : 0) : tr);
-        if (th > a.nb - 1) th = a.nb - 1;
-        const int two = (th >= 1 && xx < (th - 1) * a.s + a.B) ? 1 : 0;
+        const int th = t == 0 ? tm - (dn ? 1 : 0) : (t == 2 ? tm + (up ? 1 : 0) : tm);
+        const int ps = t == 0 ? pm - (dn ? a.s : 0) : (t == 2 ? pm + (up ? a.s : 0) : pm);
+        const int two = (th >= 1 && xx < ps + a.B) ? 1 : 0;
         c[t] = (xx < 0 || xx >= a.N) ? AxCov{0, 0} : AxCov{th, 1 + two};
     }
 }
@@ -184,7 +204,7 @@ struct PixLoads {
 };
 
 // Issues every load of PixLoads without waiting for any (an off-grid neighbour reads pixel i itself and is
-// masked when the values are used).  Pixel and copy indices are below 2^31.
+// masked when the values are used).  Pixel and copy indices are below 2^30.
 template <int CONN>
 __device__ __forceinline__ void unary_loads(const Geom &g, const GLOBAL int32_t *__restrict__ u,
                                             const GLOBAL int32_t *__restrict__ cw,
@@ -193,18 +213,20 @@ __device__ __forceinline__ void unary_loads(const Geom &g, const GLOBAL int32_t 
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
     const uint32_t i = uint32_t(gx) + uint32_t(g.W) * (uint32_t(gy) + uint32_t(g.H) * uint32_t(gz));
+    const uint32_t bi = i << 2;
     ld.ing = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
-    ld.u = u[i];
-    ld.Y = Y[i];
-    ld.a = A[ci];
+    ld.u = ld_at(u, bi);
+    ld.Y = ld_at(Y, bi);
+    ld.a = ld_at(A, ci << 2);
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
         const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
-        const uint32_t j = ((ld.ing >> d) & 1u) ? i + uint32_t(dl) : i;
+        uint32_t bj = ((ld.ing >> d) & 1u) ? bi + (uint32_t(dl) << 2) : bi;
+        asm volatile("" : "+v"(bj));   // optimisation barrier only: keeps the loads unconditional
         const GLOBAL int32_t *cwo = cw + int64_t(d < H ? d : d - H) * g.n;
-        ld.cv[d] = cwo[d < H ? i : j];
-        ld.yj[d] = Y[j];
+        ld.cv[d] = ld_at(cwo, d < H ? bi : bj);
+        ld.yj[d] = ld_at(Y, bj);
     }
 }
 
@@ -226,7 +248,7 @@ __device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN
     const int lqi = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);
     const unsigned inb_m = inside_mask<CONN>(lx, ly, lz, ex, ey, ez);   // in the block implies on the grid
     int64_t G = 0;
-    sumc = 0;
+    int32_t sc = 0;   // sum of |c| < 2^29 (checked at upload)
     mask = 0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
@@ -234,14 +256,21 @@ __device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN
         const int32_t c = ((ld.ing >> d) & 1u) ? ld.cv[d] : 0;
         const bool inb = (inb_m >> d) & 1u;
         const int lqj = (cx[v.x + 1].cnt - 1) + (cy[v.y + 1].cnt - 1) + (cz[v.z + 1].cnt - 1);
-        const int64_t t = int64_t(c) * int64_t(ld.Y - ld.yj[d]);
-        G += (t << lqj) - (inb ? t : 0);
-        if (d < H) cap_out[d] = inb ? c : 0;
-        if (inb && c != 0) {
-            sumc += c < 0 ? -int64_t(c) : int64_t(c);
-            mask |= 1u << d;
+        if (CONN != 6) {
+            // q_j <= 4 in 2D, so F = (q_j - [j in k]) c stays below 2^31 in magnitude: one 32 x 32 -> 64-bit
+            // multiply-add per neighbour
+            const int32_t F = c * (1 << lqj) - (inb ? c : 0);
+            G += int64_t(F) * int64_t(ld.Y - ld.yj[d]);
+        } else {
+            const int64_t t = int64_t(c) * int64_t(ld.Y - ld.yj[d]);
+            G += (t << lqj) - (inb ? t : 0);
         }
+        if (d < H) cap_out[d] = inb ? c : 0;
+        const bool on = inb && c != 0;
+        sc += on ? (c < 0 ? -c : c) : 0;
+        mask |= on ? (1u << d) : 0u;
     }
+    sumc = sc;
     const int64_t mu_term = (M << 14) * int64_t(ld.a - ld.Y + Y_HALF);
     return int64_t(ld.u) * int64_t(16384 >> lqi) + ((G + mu_term) >> 16);
 }
@@ -643,17 +672,18 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     for (int p = tid; p < np; p += NT) {
         const uint8_t sb = L.st[p];
         const int yv = (sb & ST_FIXED) ? ((sb & ST_LABEL) ? 1 : 0) : ((sb & ST_MARK) ? 1 : 0);
-        yhat[off + p] = uint8_t(yv);
+        const uint32_t cpy = uint32_t(off + p);
+        st_at(yhat, cpy, uint8_t(yv));
         const int3 l = block_local(p, ex, ey, inv_ex, inv_ey);
         const int lx = l.x, ly = l.y, lz = l.z;
         const uint32_t m = uint32_t(x0 + lx) + uint32_t(g.W) * (uint32_t(y0 + ly) + uint32_t(g.H) * uint32_t(z0 + lz));
-        yslot[m * uint32_t(nslot) + uint32_t(label_slot(g, kx, ky, kz, lx, ly, lz))] = uint8_t(yv);
+        st_at(yslot, m * uint32_t(nslot) + uint32_t(label_slot(g, kx, ky, kz, lx, ly, lz)), uint8_t(yv));
         if (is_interior(g, kx, ky, kz, x0 + lx, y0 + ly, z0 + lz)) {
-            const int64_t Yn = int64_t(yv) * Y_ONE + Ain[off + p];
+            const int64_t Yn = int64_t(yv) * Y_ONE + ld_at(Ain, cpy << 2);
             if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = true;
             const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
-            Yg[m] = int32_t(Yc);
-            Aout[off + p] = 0;
+            st_at(Yg, m << 2, int32_t(Yc));
+            st_at(Aout, cpy << 2, int32_t(0));
             const int64_t rr = int64_t(yv) * Y_ONE - Yc;
             r2 += (unsigned long long)(rr * rr);
         }
@@ -931,8 +961,8 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         axis_cov3(AY, gy, cy);
         if (NDIM == 3) axis_cov3(AZ, gz, cz);
         else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
-        const int qm = cx[1].cnt * cy[1].cnt * cz[1].cnt;
-        // Block-major index of pixel (x, y, z) in block (tx, ty, tz).  Indices are below 2^31 (sum of block
+        const int lqm = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);   // q_m = 2^lqm
+        // Block-major index of pixel (x, y, z) in block (tx, ty, tz).  Indices are below 2^30 (sum of block
         // sizes), so the index is computed for every candidate block in wrapping 32-bit arithmetic and replaced
         // by the owner copy's index when that block does not exist: every gather is issued unconditionally and
         // masked afterwards, with no branch between the gathers.
@@ -962,21 +992,24 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
             v_own[q] = e < cx[1].cnt && b < cy[1].cnt && a < cz[1].cnt;
             cc_own[q] = copy_at(v_own[q], cx[1].thi - e, cy[1].thi - b, cz[1].thi - a, gx, gy, gz);
-            a_own[q] = Ain[cc_own[q]];
+            a_own[q] = ld_at(Ain, cc_own[q] << 2);
         }
-        const SlotWord wm = ysl[uint32_t(m)];
+        constexpr int WSH = MAXC == 8 ? 3 : 2;   // log2 of the label word size
+        const SlotWord wm = ld_at(ysl, uint32_t(m) << WSH);
         int32_t cwv[ND];
         bool ing[ND];
         SlotWord wj[ND];
+        const unsigned ingm = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
-            const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
-            ing[d] = in_grid(g, jx, jy, jz);
-            const uint32_t j = ing[d] ? uint32_t(lin(g, jx, jy, jz)) : uint32_t(m);
+            ing[d] = (ingm >> d) & 1u;
+            const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
+            uint32_t j = ing[d] ? uint32_t(m) + uint32_t(dl) : uint32_t(m);
+            asm volatile("" : "+v"(j));   // optimisation barrier only: keeps the loads unconditional
             const GLOBAL int32_t *cwd = gp(im.cw) + int64_t(d < H ? d : d - H) * g.n;
-            cwv[d] = cwd[d < H ? uint32_t(m) : j];
-            wj[d] = ysl[j];
+            cwv[d] = ld_at(cwd, (d < H ? uint32_t(m) : j) << 2);
+            wj[d] = ld_at(ysl, j << WSH);
         }
         int yv_own[MAXC];
 #pragma unroll
@@ -1004,9 +1037,8 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         auto sel = [](int set, SlotWord lo, SlotWord hi) -> SlotWord {
             return ((set & 1) ? lo : SlotWord(0)) | ((set & 2) ? hi : SlotWord(0));
         };
-        auto bytesum = [](SlotWord x) -> int {
-            return MAXC == 8 ? int((uint64_t(x) * 0x0101010101010101ull) >> 56) : int((uint32_t(x) * 0x01010101u) >> 24);
-        };
+        // every byte of a label word is 0 or 1, so the sum of its bytes is its population count
+        auto bytesum = [](SlotWord x) -> int { return MAXC == 8 ? __popcll(uint64_t(x)) : __popc(uint32_t(x)); };
         const SlotWord X0 = MAXC == 8 ? SlotWord(0x00FF00FF00FF00FFull) : SlotWord(0x00FF00FFu);
         const SlotWord Y0 = MAXC == 8 ? SlotWord(0x0000FFFF0000FFFFull) : SlotWord(0x0000FFFFu);
         const SlotWord Z0 = MAXC == 8 ? SlotWord(0x00000000FFFFFFFFull) : SlotWord(0xFFFFFFFFu);
@@ -1021,7 +1053,8 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
                 if (e < cm && e + dt >= 0 && e + dt < cn) set |= 1 << e;
             return set;
         };
-        int64_t CQ = 0, YJ = 0, SH = 0;
+        // Hc = sum_j c_mj (Y1 q_j - q_m (labels of j) - shared_j): the bracket is a small integer (|.| <= 128)
+        int64_t HC = 0;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
@@ -1034,19 +1067,20 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
                                 sel(shared_set(cy[1].cnt, dy, ay.cnt), Y0, Y1m) &
                                 sel(shared_set(cz[1].cnt, dz, az.cnt), Z0, Z1);
             const int sh = dx + 2 * dy + 4 * dz;
-            const SlotWord wal = sh >= 0 ? SlotWord(wj[d] >> (8 * sh)) : SlotWord(wj[d] << (-8 * sh));
+            // shift right by sh bytes when sh >= 0, left by -sh bytes otherwise (two shifts, no branch)
+            const SlotWord wal = SlotWord(SlotWord(wj[d] >> (8 * (sh > 0 ? sh : 0))) << (8 * (sh < 0 ? -sh : 0)));
             const int shared = bytesum(wm & sm) - bytesum(wal & sm);
-            CQ += int64_t(cwv[d]) * (ax.cnt * ay.cnt * az.cnt);
-            YJ += int64_t(cwv[d]) * yj_sum;
-            SH += int64_t(cwv[d]) * shared;
+            // q_j and q_m are powers of two (an off-grid neighbour has c = 0, so its shift count does not matter)
+            const int lqj = max(ax.cnt - 1, 0) + max(ay.cnt - 1, 0) + max(az.cnt - 1, 0);
+            const int kd = (Y1 << lqj) - (yj_sum << lqm) - shared;
+            HC += int64_t(cwv[d]) * kd;
         }
-        const int64_t HC = int64_t(Y1) * CQ - int64_t(qm) * YJ - SH;
         // floor((M S - 4 Hc) / (M q)) = floor(floor((M S - 4 Hc) / M) / q), q a power of two
         int64_t Yn = floor_div_est(M * S - 4 * HC, M, invM);
-        Yn >>= (qm == 1 ? 0 : qm == 2 ? 1 : qm == 4 ? 2 : 3);
+        Yn >>= lqm;
         if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = 1;
         const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
-        if (!skip) Y[uint32_t(m)] = int32_t(Yc);
+        if (!skip) st_at(Y, uint32_t(m) << 2, int32_t(Yc));
         // multipliers (Eq. 11) and residual terms of every copy
 #pragma unroll
         for (int q = 0; q < MAXC; ++q) {
@@ -1054,7 +1088,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             const int64_t An = int64_t(a_own[q]) + int64_t(yv_own[q]) * Y_ONE - Yn;
             if (An >= STATE_LIMIT || An <= -STATE_LIMIT) ovf = 1;
             const int64_t Ac = An > STATE_LIMIT ? STATE_LIMIT : (An < -STATE_LIMIT ? -STATE_LIMIT : An);
-            if (!skip) Aout[cc_own[q]] = int32_t(Ac);
+            if (!skip) st_at(Aout, cc_own[q] << 2, int32_t(Ac));
             const int64_t rr = int64_t(yv_own[q]) * Y_ONE - Yc;
             r2[q] = (unsigned long long)(rr * rr);
         }
