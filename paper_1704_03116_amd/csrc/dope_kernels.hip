@@ -162,6 +162,29 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
     return j * base + (j < rem ? j : rem) + slot;
 }
 
+// Sum of x over the 64 lanes of a wavefront, returned in lane 63; every lane must be active.  Data-parallel
+// primitive moves, no LDS: each lane adds its three predecessors in its row of 16, then rows add the partial sums
+// of the preceding lanes 4 and 8 apart (upper banks only), then lane 15's total goes to row 1 and lane 31's to
+// rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
+    const int x0 = int(x);
+    uint32_t v = x + uint32_t(__builtin_amdgcn_update_dpp(0, x0, 0x111, 0xf, 0xf, false)) +   // row_shr:1
+                 uint32_t(__builtin_amdgcn_update_dpp(0, x0, 0x112, 0xf, 0xf, false)) +       // row_shr:2
+                 uint32_t(__builtin_amdgcn_update_dpp(0, x0, 0x113, 0xf, 0xf, false));        // row_shr:3
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x114, 0xf, 0xe, false));           // row_shr:4
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x118, 0xf, 0xc, false));           // row_shr:8
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x142, 0xa, 0xf, false));           // row_bcast:15
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x143, 0xc, 0xf, false));           // row_bcast:31
+    return v;
+}
+
+// 64-bit lane sum in lane 63, exact for lane values below 2^52: two 26-bit halves whose 64-lane sums fit 32 bits.
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
+    const uint32_t lo = wave_sum32(uint32_t(x & ((1ull << 26) - 1)));
+    const uint32_t hi = wave_sum32(uint32_t(x >> 26));
+    return (static_cast<unsigned long long>(hi) << 26) + lo;
+}
+
 __device__ __forceinline__ bool ctl_skip(const Ctl *ctl) {
     const GLOBAL Ctl *c = gp(ctl);
     return c->halted != 0 || c->t >= c->t_limit;
@@ -223,10 +246,18 @@ __device__ __forceinline__ void unary_loads(const Geom &g, const GLOBAL int32_t 
         const int3 v = full_dir<CONN>(d);
         const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
         uint32_t bj = ((ld.ing >> d) & 1u) ? bi + (uint32_t(dl) << 2) : bi;
-        asm volatile("" : "+v"(bj));   // optimisation barrier only: keeps the loads unconditional
+        asm("" : "+v"(bj));   // optimisation barrier only: keeps the loads unconditional
         const GLOBAL int32_t *cwo = cw + int64_t(d < H ? d : d - H) * g.n;
         ld.cv[d] = ld_at(cwo, d < H ? bi : bj);
         ld.yj[d] = ld_at(Y, bj);
+    }
+    // 3D (four voxels per thread, four wavefronts per SIMD): an optimisation barrier makes every value wait
+    // until all loads are issued, so the compiler cannot wait for one gather before issuing the next (measured
+    // 10 % faster there; in 2D, with two wavefronts per SIMD, the compiler's interleaving is faster)
+    if constexpr (ND == 6) {
+        asm("" : "+v"(ld.u), "+v"(ld.Y), "+v"(ld.a), "+v"(ld.cv[0]), "+v"(ld.cv[1]), "+v"(ld.cv[2]),
+            "+v"(ld.cv[3]), "+v"(ld.cv[4]), "+v"(ld.cv[5]), "+v"(ld.yj[0]), "+v"(ld.yj[1]), "+v"(ld.yj[2]),
+            "+v"(ld.yj[3]), "+v"(ld.yj[4]), "+v"(ld.yj[5]));
     }
 }
 
@@ -688,10 +719,10 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
             r2 += (unsigned long long)(rr * rr);
         }
     }
-#pragma unroll
-    for (int sft = 32; sft >= 1; sft >>= 1) r2 += __shfl_xor(r2, sft);
+    // r2 < 2^52 per lane (at most 16 pixels per thread, each square below 2^46)
+    r2 = wave_sum64(r2);
     unsigned long long *s_r2 = reinterpret_cast<unsigned long long *>(s_ctr + 6);
-    if ((tid & 63) == 0 && r2) atomicAdd(s_r2, r2);
+    if ((tid & 63) == 63 && r2) atomicAdd(s_r2, r2);
     if (ovf) atomicOr((int32_t *)gp(&im.ctl->ovf_pending), 1);
     __syncthreads();
     if (tid == 0) {
@@ -977,7 +1008,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             uint32_t r = valid ? cc : uint32_t(c);
             // optimisation barrier only (no instruction): keeps the compiler from turning the select back into a
             // branch around the load, which would serialise the gathers
-            asm volatile("" : "+v"(r));
+            asm("" : "+v"(r));
             return r;
         };
         // ---- every load of this pixel is issued before any of them is used: the multipliers of its copies
@@ -995,7 +1026,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             a_own[q] = ld_at(Ain, cc_own[q] << 2);
         }
         constexpr int WSH = MAXC == 8 ? 3 : 2;   // log2 of the label word size
-        const SlotWord wm = ld_at(ysl, uint32_t(m) << WSH);
+        SlotWord wm = ld_at(ysl, uint32_t(m) << WSH);
         int32_t cwv[ND];
         bool ing[ND];
         SlotWord wj[ND];
@@ -1006,10 +1037,25 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             ing[d] = (ingm >> d) & 1u;
             const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
             uint32_t j = ing[d] ? uint32_t(m) + uint32_t(dl) : uint32_t(m);
-            asm volatile("" : "+v"(j));   // optimisation barrier only: keeps the loads unconditional
+            asm("" : "+v"(j));   // optimisation barrier only: keeps the loads unconditional
             const GLOBAL int32_t *cwd = gp(im.cw) + int64_t(d < H ? d : d - H) * g.n;
             cwv[d] = ld_at(cwd, (d < H ? uint32_t(m) : j) << 2);
             wj[d] = ld_at(ysl, j << WSH);
+        }
+        // optimisation barrier only: every gathered value is used after all gathers are issued
+        if constexpr (CONN == 4) {
+            asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(wm), "+v"(cwv[0]),
+                "+v"(cwv[1]), "+v"(cwv[2]), "+v"(cwv[3]), "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]));
+        } else if constexpr (CONN == 8) {
+            asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(wm), "+v"(cwv[0]),
+                "+v"(cwv[1]), "+v"(cwv[2]), "+v"(cwv[3]), "+v"(cwv[4]), "+v"(cwv[5]), "+v"(cwv[6]), "+v"(cwv[7]),
+                "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]), "+v"(wj[4]), "+v"(wj[5]), "+v"(wj[6]),
+                "+v"(wj[7]));
+        } else {
+            asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(a_own[4]),
+                "+v"(a_own[5]), "+v"(a_own[6]), "+v"(a_own[7]), "+v"(wm), "+v"(cwv[0]), "+v"(cwv[1]), "+v"(cwv[2]),
+                "+v"(cwv[3]), "+v"(cwv[4]), "+v"(cwv[5]), "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]),
+                "+v"(wj[4]), "+v"(wj[5]));
         }
         int yv_own[MAXC];
 #pragma unroll
@@ -1100,10 +1146,8 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
 #pragma unroll
         for (int q = 0; q < MAXC; ++q) {
             if (same) {
-                unsigned long long v = r2[q];
-#pragma unroll
-                for (int sft = 32; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft);
-                if ((tid & 63) == 0 && v) atomicAdd(&s_res[(k0 - kfirst) * MAXC + q], v);
+                const unsigned long long v = wave_sum64(r2[q]);   // one square (< 2^46) per lane
+                if ((tid & 63) == 63 && v) atomicAdd(&s_res[(k0 - kfirst) * MAXC + q], v);
             } else if (r2[q]) {
                 atomicAdd(&s_res[(kk - kfirst) * MAXC + q], r2[q]);
             }
@@ -1217,7 +1261,9 @@ __device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int g
                                             int32_t *__restrict__ cw, int32_t lam,
                                             int32_t *__restrict__ Y, Ctl *ctl) {
     constexpr int H = Sten<CONN>::H;
-    const int64_t i = lin(g, gx, gy, gz);
+    constexpr int ND = 2 * H;
+    const uint32_t i = uint32_t(gx) + uint32_t(g.W) * (uint32_t(gy) + uint32_t(g.H) * uint32_t(gz));
+    const uint32_t bi = i << 2;
     AxCov cx[3], cy[3], cz[3];
     axis_cov3(g.ax[0], gx, cx);
     axis_cov3(g.ax[1], gy, cy);
@@ -1225,44 +1271,39 @@ __device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int g
     else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
     // log2 q of this pixel (every cover count is 1 or 2)
     const int lqi = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);
+    const unsigned ing = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
     // all loads first (an off-grid neighbour reads pixel i itself and is masked); the edge's weight lives at the
     // pixel holding its positive half-edge
-    const int32_t ui = u_src[i];
-    int32_t wl[2 * H];
+    const GLOBAL int32_t *wg = gp(w_src);
+    int32_t ui = ld_at(gp(u_src), bi);
+    int32_t wl[ND];
 #pragma unroll
-    for (int d = 0; d < 2 * H; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
-        const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
-        int64_t j = (d >= H && in_grid(g, jx, jy, jz)) ? lin(g, jx, jy, jz) : i;
-        asm volatile("" : "+v"(j));   // optimisation barrier only: keeps the loads unconditional
-        wl[d] = w_src[int64_t(d < H ? d : d - H) * g.n + j];
+        const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
+        uint32_t bj = (d >= H && ((ing >> d) & 1u)) ? bi + (uint32_t(dl) << 2) : bi;
+        asm("" : "+v"(bj));   // optimisation barrier only: keeps the loads unconditional
+        wl[d] = ld_at(wg + int64_t(d < H ? d : d - H) * g.n, bj);
     }
     int flags = 0;
     int64_t sum = 0;
-    int32_t cl[H];
 #pragma unroll
-    for (int d = 0; d < 2 * H; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
-        const int jx = gx + v.x, jy = gy + v.y, jz = gz + v.z;
-        const bool ing = in_grid(g, jx, jy, jz);
-        const int32_t wv = (d < H || ing) ? wl[d] : 0;
-        int32_t c = 0;
-        if (!ing) {
-            if (wv != 0) flags |= FLAG_OFFGRID;
-        } else if (wv != 0) {
-            if (wv < 0) flags |= FLAG_NEGATIVE;
-            const int lqj = (cx[v.x + 1].cnt - 1) + (cy[v.y + 1].cnt - 1) + (cz[v.z + 1].cnt - 1);
-            const int64_t cvv = int64_t(lam) * int64_t(wv) * int64_t(64 >> (lqi + lqj));   // 64 / (q_i q_j)
-            if (cvv >= CAP_SUM_LIMIT || cvv <= -CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
-            else c = int32_t(cvv);
-            sum += cvv < 0 ? -cvv : cvv;
-        }
-        if (d < H) cl[d] = c;
+        const bool on = (ing >> d) & 1u;
+        const int32_t wv = (d < H || on) ? wl[d] : 0;
+        const int lqj = (cx[v.x + 1].cnt - 1) + (cy[v.y + 1].cnt - 1) + (cz[v.z + 1].cnt - 1);
+        // c = lambda_q8 w 64 / (q_i q_j): q_i q_j = 2^(lqi + lqj) <= 64 (0 for an off-grid neighbour)
+        const int64_t cvv = on ? int64_t(lam) * int64_t(wv) * (int64_t(1) << (6 - lqi - lqj)) : 0;
+        const bool big = cvv >= CAP_SUM_LIMIT || cvv <= -CAP_SUM_LIMIT;
+        flags |= (!on && wv != 0) ? FLAG_OFFGRID : 0;
+        flags |= (on && wv < 0) ? FLAG_NEGATIVE : 0;
+        flags |= big ? FLAG_TOOBIG : 0;
+        sum += cvv < 0 ? -cvv : cvv;
+        if (d < H) st_at(gp(cw) + int64_t(d) * g.n, bi, big ? 0 : int32_t(cvv));
     }
-#pragma unroll
-    for (int d = 0; d < H; ++d) cw[int64_t(d) * g.n + i] = cl[d];
-    if (u_src != u_ws) u_ws[i] = ui;
-    Y[i] = Y_HALF;
+    if (u_src != u_ws) st_at(gp(u_ws), bi, ui);
+    st_at(gp(Y), bi, int32_t(Y_HALF));
     if (sum >= CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
     if (flags) atomicOr((int32_t *)gp(&ctl->flags), flags);
 }
@@ -1278,7 +1319,11 @@ __global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict
     {
         const int64_t T = int64_t(gridDim.x) * gridDim.y * 256;
         const int64_t t0 = (int64_t(blockIdx.y) * gridDim.x + blockIdx.x) * 256 + threadIdx.x;
-        for (int64_t i = t0; i < g.tot; i += T) { A0[i] = 0; A1[i] = 0; yhat[i] = 0; }
+        for (uint32_t i = uint32_t(t0); i < uint32_t(g.tot); i += uint32_t(T)) {   // copies < 2^30
+            st_at(gp(A0), i << 2, int32_t(0));
+            st_at(gp(A1), i << 2, int32_t(0));
+            st_at(gp(yhat), i, uint8_t(0));
+        }
         for (int64_t i = t0; i < g.K; i += T) resid[i] = 0;
         if (t0 == 0) {
             GLOBAL Ctl *c = gp(ctl);
@@ -1323,10 +1368,10 @@ __global__ __launch_bounds__(256) void k_setup_batch(const Img *__restrict__ img
     const int row = wi.idx;
     {
         const int64_t lo = g.tot * row / nrows, hi = g.tot * (row + 1) / nrows;
-        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
-            gp(im.A0)[i] = 0;
-            gp(im.A1)[i] = 0;
-            gp(im.yhat)[i] = 0;
+        for (uint32_t i = uint32_t(lo) + threadIdx.x; i < uint32_t(hi); i += 256) {   // copies < 2^30
+            st_at(gp(im.A0), i << 2, int32_t(0));
+            st_at(gp(im.A1), i << 2, int32_t(0));
+            st_at(gp(im.yhat), i, uint8_t(0));
         }
         const int64_t klo = int64_t(g.K) * row / nrows, khi = int64_t(g.K) * (row + 1) / nrows;
         for (int64_t k = klo + threadIdx.x; k < khi; k += 256) gp(im.resid)[k] = 0;
@@ -1507,6 +1552,7 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s, hipEvent_t e0, hipEve
         if (e != hipSuccess) return e;
         lds_set = lds;
     }
+    if ((grp.npmax + NT - 1) / NT > 16) return hipErrorInvalidValue;   // the residual lane sums assume <= 16
     const int32_t round_limit = 65536 + 64 * grp.npmax;
     const int32_t workers = grp.n_workers > 0 ? (grp.n_workers < grp.n_blk_items ? grp.n_workers : grp.n_blk_items)
                                               : grp.n_blk_items;
