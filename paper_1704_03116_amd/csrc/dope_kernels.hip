@@ -1189,15 +1189,26 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus_one(const Img one, int32_
 // inside k_consensus: a device-scope fence per workgroup costs L2 write-backs on every XCD.
 __device__ __forceinline__ void finalize_image(const Img &im) {
     GLOBAL Ctl *ctl = gp(im.ctl);
-    if (ctl_skip(im.ctl)) return;
+    // every load is issued before any is used (one memory round trip): the loop control and the residuals
+    const int32_t halted = ctl->halted, t = ctl->t, t_limit = ctl->t_limit, solver_err = ctl->solver_err,
+                  ovf = ctl->ovf_pending, stop_conv = ctl->stop_on_converge, mu_num = ctl->mu_num,
+                  mu_den = ctl->mu_den, status = ctl->status;
+    const int64_t M = ctl->M;
+    const uint64_t eps2 = ctl->eps2;
     __shared__ unsigned long long s_max[4];
     const int tid = threadIdx.x;
-    unsigned long long mx = 0;
+    const int K = im.g.K;
     const GLOBAL int64_t *resid = gp(im.resid);
-    for (int k = tid; k < im.g.K; k += 256) {
+    // the first two residuals of this thread (clamped indices, masked afterwards), then any others
+    const uint64_t v0 = static_cast<uint64_t>(resid[tid < K ? tid : 0]);
+    const uint64_t v1 = static_cast<uint64_t>(resid[tid + 256 < K ? tid + 256 : 0]);
+    unsigned long long mx = tid < K ? v0 : 0;
+    if (tid + 256 < K && v1 > mx) mx = v1;
+    for (int k = tid + 512; k < K; k += 256) {
         const unsigned long long v = static_cast<unsigned long long>(resid[k]);
         mx = v > mx ? v : mx;
     }
+    if (halted != 0 || t >= t_limit) return;   // uniform
 #pragma unroll
     for (int sft = 32; sft >= 1; sft >>= 1) {
         const unsigned long long o = __shfl_xor(mx, sft);
@@ -1207,24 +1218,26 @@ __device__ __forceinline__ void finalize_image(const Img &im) {
     __syncthreads();
     if (tid == 0) {
         for (int wv = 0; wv < 4; ++wv) mx = s_max[wv] > mx ? s_max[wv] : mx;
-        const int64_t M = ctl->M;
         ctl->last_max_resid = mx;
-        const int conv = mx <= ctl->eps2 ? 1 : 0;
+        const int conv = mx <= eps2 ? 1 : 0;
         ctl->converged = conv;
-        if (ctl->solver_err) { ctl->status = -6; ctl->halted = 1; }
-        if (ctl->ovf_pending) { ctl->status = -5; ctl->halted = 1; }
-        if (ctl->stop_on_converge && conv) ctl->halted = 1;
-        const int64_t Mn = (M * ctl->mu_num) / ctl->mu_den;
+        int st_new = 0, halt_new = 0;
+        if (solver_err) { st_new = -6; halt_new = 1; }
+        if (ovf) { st_new = -5; halt_new = 1; }
+        if (stop_conv && conv) halt_new = 1;
+        if (st_new) ctl->status = st_new;
+        if (halt_new) ctl->halted = 1;
+        const int64_t Mn = (M * mu_num) / mu_den;
         ctl->M = Mn > MU_MAX ? MU_MAX : Mn;
-        ctl->t = ctl->t + 1;
+        ctl->t = t + 1;
         ctl->ovf_pending = 0;
         ctl->solver_err = 0;
         if (im.summary) {
             GLOBAL int32_t *sm = gp(im.summary);
-            sm[0] = ctl->t;
-            sm[1] = ctl->halted;
+            sm[0] = t + 1;
+            sm[1] = halt_new;
             sm[2] = conv;
-            sm[3] = ctl->status;
+            sm[3] = st_new ? st_new : status;
         }
     }
 }
