@@ -125,10 +125,17 @@ def subproblem_objective(un, ea, eb, cap, x) -> int:
 # ----------------------------------------------------------------------------------------------------------
 
 def neighbour_offsets(ndim: int, conn: int):
+    """Half-stencil offsets: each undirected edge i <-> i + offset once (the neighbourhood of Sec. 1's grid
+    graphs; the experiments' square kernels of size 3, 5 and 7 in 2D are conn 8, 24 and 48)."""
     if ndim == 2 and conn == 4:
         return [(1, 0, 0), (0, 1, 0)]
     if ndim == 2 and conn == 8:
         return [(1, 0, 0), (0, 1, 0), (1, 1, 0), (-1, 1, 0)]
+    if ndim == 2 and conn in (24, 48):
+        r = 2 if conn == 24 else 3
+        # every offset of the (2r+1)^2 square whose first nonzero coordinate, taken from y down to x, is positive
+        return [(dx, 0, 0) for dx in range(1, r + 1)] + \
+               [(dx, dy, 0) for dy in range(1, r + 1) for dx in range(-r, r + 1)]
     if ndim == 3 and conn == 6:
         return [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
     raise ValueError("unsupported stencil")

@@ -92,16 +92,20 @@ Layout layout_for(const Geom &g) {
 int half_stencil_size(int ndim, int conn) {
     if (ndim == 2 && conn == 4) return 2;
     if (ndim == 2 && conn == 8) return 4;
+    if (ndim == 2 && conn == 24) return 12;   // 5x5 square neighbourhood
+    if (ndim == 2 && conn == 48) return 24;   // 7x7 square neighbourhood
     if (ndim == 3 && conn == 6) return 3;
     return 0;
 }
+
+int stencil_radius(int conn) { return conn == 24 ? 2 : (conn == 48 ? 3 : 1); }
 
 // Builds the partition; returns an empty string on success or a message.
 std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab) {
     if (!p) return "null params";
     if (p->ndim != 2 && p->ndim != 3) return "ndim must be 2 or 3";
     const int hs = half_stencil_size(p->ndim, p->connectivity);
-    if (!hs) return "connectivity must be 4 or 8 in 2D and 6 in 3D";
+    if (!hs) return "connectivity must be 4, 8, 24 or 48 in 2D and 6 in 3D";
     int32_t dims[3] = {p->dims[0], p->dims[1], p->ndim == 3 ? p->dims[2] : 1};
     if (p->ndim == 2 && p->dims[2] != 1 && p->dims[2] != 0) return "dims[2] must be 1 in 2D";
     int64_t n = 1;
@@ -135,6 +139,11 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
     g.D = dims[2];
     g.conn = p->connectivity;
     g.hs = hs;
+    g.rad = stencil_radius(p->connectivity);
+    // the stencil must not reach past the neighbouring block: every offset changes the top block of a coordinate
+    // by at most one
+    for (int a = 0; a < 3; ++a)
+        if (g.ax[a].nb > 1 && g.rad > g.ax[a].s) return "block stride B - o must be at least the stencil radius";
     g.K = int32_t(K);
     g.max_np = int32_t(max_np);
     g.n = n;
@@ -161,12 +170,8 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
     for (int a = 0; a < 3; ++a) {
         const dope::Axis &ax = g.ax[a];
         int64_t cnt = 0;
-        for (int t = 0; t < ax.nb; ++t) {
-            const int32_t start = t * ax.s, o = ax.B - ax.s;
-            const int32_t lo = t > 0 ? start + o + 1 : 0;
-            const int32_t hi = t < ax.nb - 1 ? start + dope::axis_ext(ax, t) - o - 1 : ax.N;
-            cnt += std::max(0, hi - lo);
-        }
+        for (int t = 0; t < ax.nb; ++t)
+            cnt += std::max(0, dope::axis_interior_hi(ax, t, g.rad) - dope::axis_interior_lo(ax, t, g.rad));
         g.n_interior *= cnt;
     }
     if (btab) {
@@ -490,7 +495,8 @@ dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectiv
         return DOPE_OK;
     }
     const int32_t short_side = std::min(dims[0], dims[1]);
-    const int32_t B = short_side <= 256 ? 16 : 32;
+    // 7x7 neighbourhoods: 32x32 blocks would exceed the LDS (209 bytes per node)
+    const int32_t B = (short_side <= 256 || connectivity == 48) ? 16 : 32;
     block[0] = block[1] = B;
     overlap[0] = overlap[1] = 1;
     block[2] = 1;

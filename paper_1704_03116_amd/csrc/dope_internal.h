@@ -22,8 +22,9 @@ inline Axis make_axis(int32_t N, int32_t B, int32_t s, int32_t nb) {
 struct Geom {
     Axis ax[3];
     int32_t W, H, D;
-    int32_t conn;       // 4, 8 or 6
+    int32_t conn;       // 4, 8, 24 (5x5), 48 (7x7) or 6
     int32_t hs;         // half-stencil size
+    int32_t rad;        // stencil radius: every neighbour offset lies in [-rad, rad] per axis
     int32_t K;          // number of blocks
     int32_t max_np;     // largest block size in pixels
     int64_t n;          // pixels
@@ -37,16 +38,18 @@ inline __host__ __device__ int32_t axis_ext(const Axis &a, int32_t t) {
     return e < a.B ? e : a.B;
 }
 
-// A pixel is interior to block (tx, ty, tz) when it and every pixel of its 3x3(x3) neighbourhood lie in that
-// block only.  Then both Hc terms of Eq. (10) vanish for it, S_m is its single copy, and no other block reads
-// it.  Along one axis: lo <= x < hi with lo = start + o + 1 (0 for the first block), hi = end - o - 1 (N for the
-// last block), o = B - s.
-inline __host__ __device__ bool axis_interior(const Axis &a, int32_t t, int32_t x) {
-    const int32_t start = t * a.s;
-    const int32_t o = a.B - a.s;
-    const int32_t lo = t > 0 ? start + o + 1 : 0;
-    const int32_t hi = t < a.nb - 1 ? start + axis_ext(a, t) - o - 1 : a.N;
-    return x >= lo && x < hi;
+// A pixel is interior to block (tx, ty, tz) when it and every pixel of its stencil box (offsets up to r per axis)
+// lie in that block only.  Then both Hc terms of Eq. (10) vanish for it, S_m is its single copy, and no other
+// block reads it.  Along one axis: lo <= x < hi with lo = start + o + r (0 for the first block),
+// hi = end - o - r (N for the last block), o = B - s.
+inline __host__ __device__ int32_t axis_interior_lo(const Axis &a, int32_t t, int32_t r) {
+    return t > 0 ? t * a.s + (a.B - a.s) + r : 0;
+}
+inline __host__ __device__ int32_t axis_interior_hi(const Axis &a, int32_t t, int32_t r) {
+    return t < a.nb - 1 ? t * a.s + axis_ext(a, t) - (a.B - a.s) - r : a.N;
+}
+inline __host__ __device__ bool axis_interior(const Axis &a, int32_t t, int32_t x, int32_t r) {
+    return x >= axis_interior_lo(a, t, r) && x < axis_interior_hi(a, t, r);
 }
 
 // Start of block (tx, ty, tz) in the block-major vectors.  Blocks are ordered x-fastest and only the last block
@@ -62,7 +65,8 @@ inline __host__ __device__ int slot_count(const Geom &g) { return g.conn == 6 ? 
 
 inline __host__ __device__ bool is_interior(const Geom &g, int32_t tx, int32_t ty, int32_t tz, int32_t x, int32_t y,
                                             int32_t z) {
-    return axis_interior(g.ax[0], tx, x) && axis_interior(g.ax[1], ty, y) && axis_interior(g.ax[2], tz, z);
+    return axis_interior(g.ax[0], tx, x, g.rad) && axis_interior(g.ax[1], ty, y, g.rad) &&
+           axis_interior(g.ax[2], tz, z, g.rad);
 }
 
 // Device-resident loop control.  Written by the host only through k_ctl_* kernels or state uploads.
@@ -97,8 +101,16 @@ constexpr int64_t MU_MAX = (1 << 24) - 1;
 constexpr int64_t CAP_SUM_LIMIT = int64_t(1) << 29;
 constexpr int BTAB_STRIDE = 8;     // x0, y0, z0, ex, ey, ez, offset, pad
 
-// LDS bytes of the max-flow block kernel for a block of np pixels and half-stencil size hs.
-inline size_t maxflow_lds_bytes(int np, int hs) { return 64 + size_t(np) * (8 * hs + 10); }
+// Bytes of the per-node mask of live in-block directions (one bit per full-stencil direction).
+inline __host__ __device__ constexpr int dir_mask_bytes(int hs) { return 2 * hs <= 8 ? 1 : (2 * hs <= 32 ? 4 : 8); }
+
+// LDS bytes of the max-flow block kernel for a block of np pixels and half-stencil size hs: a 64-byte header,
+// capacity and flow per half-edge, unary/excess, height, free list, direction mask (aligned to its size) and
+// state bits per node.
+inline size_t maxflow_lds_bytes(int np, int hs) {
+    const int mb = dir_mask_bytes(hs);
+    return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 1 ? 8 : 0);
+}
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
 constexpr int NUM_CUS = 256;          // MI355X compute units
 

@@ -49,10 +49,21 @@ __device__ __forceinline__ void st_at(GLOBAL T *base, uint32_t off, T v) {
 enum : uint8_t { ST_FIXED = 1, ST_LABEL = 2, ST_MARK = 8 };
 constexpr int16_t H_INF = 0x7FFF;
 
+// Stencils: H half-edges per pixel, radius R (every offset lies in [-R, R] per axis).  CONN 24 and 48 are the
+// square 5x5 and 7x7 neighbourhoods of a 2D grid.
 template <int CONN> struct Sten;
-template <> struct Sten<4> { static constexpr int H = 2; };
-template <> struct Sten<8> { static constexpr int H = 4; };
-template <> struct Sten<6> { static constexpr int H = 3; };
+template <> struct Sten<4> { static constexpr int H = 2, R = 1; };
+template <> struct Sten<8> { static constexpr int H = 4, R = 1; };
+template <> struct Sten<24> { static constexpr int H = 12, R = 2; };
+template <> struct Sten<48> { static constexpr int H = 24, R = 3; };
+template <> struct Sten<6> { static constexpr int H = 3, R = 1; };
+
+// One bit per full-stencil direction.
+template <int CONN>
+using DirMask = typename std::conditional<(2 * Sten<CONN>::H <= 32), uint32_t, uint64_t>::type;
+// The per-node copy of that mask in LDS (see dir_mask_bytes).
+template <int CONN>
+using LdsMask = typename std::conditional<(2 * Sten<CONN>::H <= 8), uint8_t, DirMask<CONN>>::type;
 
 // Half-stencil offsets (must match the weight layout of the public header).
 template <int CONN>
@@ -65,6 +76,13 @@ __device__ __forceinline__ int3 half_off(int o) {
             case 2: return make_int3(1, 1, 0);
             default: return make_int3(-1, 1, 0);
         }
+    }
+    if (CONN == 24 || CONN == 48) {
+        // (dx, 0) for dx = 1..R, then (dx, dy) for dy = 1..R and dx = -R..R (x fastest)
+        constexpr int R = Sten<CONN>::R;
+        if (o < R) return make_int3(o + 1, 0, 0);
+        const int q = o - R;
+        return make_int3(q % (2 * R + 1) - R, 1 + q / (2 * R + 1), 0);
     }
     switch (o) {
         case 0: return make_int3(1, 0, 0);
@@ -112,26 +130,52 @@ __device__ __forceinline__ int3 block_local(int p, int ex, int ey, double inv_ex
     return make_int3(lx, ly, lz);
 }
 
-// Covers of x - 1, x and x + 1 (0 <= x < N) from one division: floor((x -+ 1) / s) differs from floor(x / s)
-// only when x sits on the first / last coordinate of a stride period.
-__device__ __forceinline__ void axis_cov3(const Axis &a, int x, AxCov c[3]) {
+// Covers of x - R .. x + R (0 <= x < N, R at most the stride s when the axis has several blocks) from one
+// division: floor((x + t) / s) differs from floor(x / s) by at most one, downwards when rem + t < 0 and upwards
+// when rem + t >= s.
+template <int R>
+__device__ __forceinline__ void axis_cov(const Axis &a, int x, AxCov c[2 * R + 1]) {
     int rem;
     const int tr = qdiv(x, a.s, a.inv_s, rem);
-    // t_hi of x is tm = min(tr, nb - 1); that of x - 1 is one less when x starts a stride period and tr is not
-    // clamped, that of x + 1 one more when x ends one and tr + 1 is not clamped.  The start of block t_hi - 1,
-    // (t_hi - 1) s, follows from one product.
+    // t_hi of x is tm = min(tr, nb - 1); a neighbour's is one less or one more only when tr is not clamped.  The
+    // start of block t_hi - 1, (t_hi - 1) s, follows from one product.
     const int tm = tr < a.nb - 1 ? tr : a.nb - 1;
     const int pm = (tm - 1) * a.s;
-    const bool dn = rem == 0 && tr <= a.nb - 1, up = rem == a.s - 1 && tr < a.nb - 1;
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        const int xx = x + t - 1;
-        const int th = t == 0 ? tm - (dn ? 1 : 0) : (t == 2 ? tm + (up ? 1 : 0) : tm);
-        const int ps = t == 0 ? pm - (dn ? a.s : 0) : (t == 2 ? pm + (up ? a.s : 0) : pm);
+    for (int t = 0; t <= 2 * R; ++t) {
+        const int xx = x + t - R, d = rem + t - R;
+        const bool dn = d < 0 && tr <= a.nb - 1, up = d >= a.s && tr < a.nb - 1;
+        const int th = tm - (dn ? 1 : 0) + (up ? 1 : 0);
+        const int ps = pm - (dn ? a.s : 0) + (up ? a.s : 0);
         const int two = (th >= 1 && xx < ps + a.B) ? 1 : 0;
         c[t] = (xx < 0 || xx >= a.N) ? AxCov{0, 0} : AxCov{th, 1 + two};
     }
 }
+
+// Covers of one pixel's stencil box along the three axes (the z axis of a 2D grid is a single layer).
+template <int CONN>
+struct BoxCov {
+    static constexpr int R = Sten<CONN>::R;
+    AxCov x[2 * R + 1], y[2 * R + 1], z[2 * R + 1];
+    __device__ __forceinline__ void init(const Geom &g, int gx, int gy, int gz) {
+        axis_cov<R>(g.ax[0], gx, x);
+        axis_cov<R>(g.ax[1], gy, y);
+        if (CONN == 6) {
+            axis_cov<R>(g.ax[2], gz, z);
+        } else {
+#pragma unroll
+            for (int t = 0; t <= 2 * R; ++t) z[t] = AxCov{0, t == R ? 1 : 0};
+        }
+    }
+    // cover of the pixel itself (offset 0) and of neighbour offset v along each axis
+    __device__ __forceinline__ const AxCov &cx(int dx) const { return x[dx + R]; }
+    __device__ __forceinline__ const AxCov &cy(int dy) const { return y[dy + R]; }
+    __device__ __forceinline__ const AxCov &cz(int dz) const { return z[dz + R]; }
+    // log2 q of the pixel at offset v (every cover count is 1 or 2 on the grid; an off-grid offset gives 0)
+    __device__ __forceinline__ int lq(int3 v) const {
+        return max(cx(v.x).cnt - 1, 0) + max(cy(v.y).cnt - 1, 0) + max(cz(v.z).cnt - 1, 0);
+    }
+};
 
 // Label slot of the copy at local position (lx, ly, lz) of block (tx, ty, tz): e + 2b + 4a where e = 1 when the
 // pixel also lies in block tx + 1 (local x >= s and a next block exists), i.e. the copy is in block top_x - 1.
@@ -201,17 +245,23 @@ __device__ __forceinline__ int64_t floor_div_est(int64_t n, int64_t M, double in
 }
 
 // Bit d set when full-stencil neighbour d of (x, y, z) lies inside [0, X) x [0, Y) x [0, Z) (the grid, or a
-// block in local coordinates).  The stencil is a compile-time constant, so this is six comparisons.
+// block in local coordinates).  The stencil is a compile-time constant, so this is 2R comparisons per axis.
 template <int CONN>
-__device__ __forceinline__ unsigned inside_mask(int x, int y, int z, int X, int Y, int Z) {
-    const bool xl = x > 0, xh = x < X - 1, yl = y > 0, yh = y < Y - 1, zl = z > 0, zh = z < Z - 1;
-    unsigned m = 0;
+__device__ __forceinline__ DirMask<CONN> inside_mask(int x, int y, int z, int X, int Y, int Z) {
+    constexpr int R = Sten<CONN>::R;
+    bool okx[2 * R + 1], oky[2 * R + 1], okz[2 * R + 1];
+#pragma unroll
+    for (int t = -R; t <= R; ++t) {
+        okx[t + R] = t < 0 ? x >= -t : (t > 0 ? x < X - t : true);
+        oky[t + R] = t < 0 ? y >= -t : (t > 0 ? y < Y - t : true);
+        okz[t + R] = t < 0 ? z >= -t : (t > 0 ? z < Z - t : true);
+    }
+    DirMask<CONN> m = 0;
 #pragma unroll
     for (int d = 0; d < 2 * Sten<CONN>::H; ++d) {
         const int3 v = full_dir<CONN>(d);
-        const bool ok = (v.x < 0 ? xl : (v.x > 0 ? xh : true)) && (v.y < 0 ? yl : (v.y > 0 ? yh : true)) &&
-                        (v.z < 0 ? zl : (v.z > 0 ? zh : true));
-        m |= ok ? (1u << d) : 0u;
+        const bool ok = okx[v.x + R] && oky[v.y + R] && okz[v.z + R];
+        m |= ok ? (DirMask<CONN>(1) << d) : DirMask<CONN>(0);
     }
     return m;
 }
@@ -223,7 +273,7 @@ struct PixLoads {
     static constexpr int ND = 2 * Sten<CONN>::H;
     int32_t u, Y, a;
     int32_t cv[ND], yj[ND];
-    unsigned ing;
+    DirMask<CONN> ing;
 };
 
 // Issues every load of PixLoads without waiting for any (an off-grid neighbour reads pixel i itself and is
@@ -268,16 +318,13 @@ __device__ __forceinline__ void unary_loads(const Geom &g, const GLOBAL int32_t 
 template <int CONN>
 __device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN> &ld, int64_t M, int gx, int gy,
                                               int gz, int lx, int ly, int lz, int ex, int ey, int ez,
-                                              int32_t *cap_out, unsigned &mask, int64_t &sumc) {
+                                              int32_t *cap_out, DirMask<CONN> &mask, int64_t &sumc) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
-    AxCov cx[3], cy[3], cz[3];
-    axis_cov3(g.ax[0], gx, cx);
-    axis_cov3(g.ax[1], gy, cy);
-    if (CONN == 6) axis_cov3(g.ax[2], gz, cz);
-    else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
-    const int lqi = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);
-    const unsigned inb_m = inside_mask<CONN>(lx, ly, lz, ex, ey, ez);   // in the block implies on the grid
+    BoxCov<CONN> bc;
+    bc.init(g, gx, gy, gz);
+    const int lqi = bc.lq(make_int3(0, 0, 0));
+    const DirMask<CONN> inb_m = inside_mask<CONN>(lx, ly, lz, ex, ey, ez);   // in the block implies on the grid
     int64_t G = 0;
     int32_t sc = 0;   // sum of |c| < 2^29 (checked at upload)
     mask = 0;
@@ -286,7 +333,7 @@ __device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN
         const int3 v = full_dir<CONN>(d);
         const int32_t c = ((ld.ing >> d) & 1u) ? ld.cv[d] : 0;
         const bool inb = (inb_m >> d) & 1u;
-        const int lqj = (cx[v.x + 1].cnt - 1) + (cy[v.y + 1].cnt - 1) + (cz[v.z + 1].cnt - 1);
+        const int lqj = bc.lq(v);
         if (CONN != 6) {
             // q_j <= 4 in 2D, so F = (q_j - [j in k]) c stays below 2^31 in magnitude: one 32 x 32 -> 64-bit
             // multiply-add per neighbour
@@ -299,7 +346,7 @@ __device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN
         if (d < H) cap_out[d] = inb ? c : 0;
         const bool on = inb && c != 0;
         sc += on ? (c < 0 ? -c : c) : 0;
-        mask |= on ? (1u << d) : 0u;
+        mask |= on ? (DirMask<CONN>(1) << d) : DirMask<CONN>(0);
     }
     sumc = sc;
     const int64_t mu_term = (M << 14) * int64_t(ld.a - ld.Y + Y_HALF);
@@ -369,7 +416,7 @@ struct BlockLds {
     int32_t *dd;       // unary during elimination, then excess minus sink residual
     int16_t *hh;       // heights
     int16_t *lst;      // free nodes after the prologue's forcing test
-    uint8_t *msk;      // live in-block directions
+    LdsMask<CONN> *msk;   // live in-block directions
     uint8_t *st;       // ST_* bits
     int npmax;
     int loff[H];
@@ -421,7 +468,7 @@ __device__ bool eliminate(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs)
             for (int i = sy.idx; i < nfree; i += sy.step) {
                 const int p = L.lst[i];
                 if (L.st[p] & ST_FIXED) continue;
-                const unsigned m = L.msk[p];
+                const DirMask<CONN> m = L.msk[p];
                 int32_t U = L.dd[p], S = 0;
 #pragma unroll
                 for (int d = 0; d < ND; ++d)
@@ -477,17 +524,17 @@ __device__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
     for (int i = sy.idx; i < nfree; i += sy.step) {
         const int p = L.lst[i];
         if (L.st[p] & ST_FIXED) continue;
-        const unsigned m = L.msk[p];
-        unsigned live = 0;
+        const DirMask<CONN> m = L.msk[p];
+        DirMask<CONN> live = 0;
         int32_t U = L.dd[p];
 #pragma unroll
         for (int d = 0; d < ND; ++d)
             if ((m >> d) & 1u) {
                 const uint8_t sv = L.st[L.nbr(p, d)];
                 if (sv & ST_FIXED) U += (sv & ST_LABEL) ? -L.capd(p, d) : L.capd(p, d);
-                else live |= 1u << d;
+                else live |= DirMask<CONN>(1) << d;
             }
-        L.msk[p] = uint8_t(live);
+        L.msk[p] = LdsMask<CONN>(live);
         L.dd[p] = -U;
     }
     sy.sync();
@@ -503,7 +550,7 @@ __device__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
             for (int i = sy.idx; i < nfree; i += sy.step) {
                 const int p = L.lst[i];
                 if (L.st[p] & ST_FIXED) continue;
-                const unsigned m = L.msk[p];
+                const DirMask<CONN> m = L.msk[p];
                 const int h = L.hh[p];
                 if (!m || h == 1) continue;
                 int best = h;
@@ -533,7 +580,7 @@ __device__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
                 const int32_t e = L.dd[p];
                 const int h = L.hh[p];
                 if (e <= 0 || h >= H_INF) continue;
-                const unsigned m = L.msk[p];
+                const DirMask<CONN> m = L.msk[p];
                 int32_t rem = e;
 #pragma unroll
                 for (int d = 0; d < ND; ++d) {
@@ -556,7 +603,7 @@ __device__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
                 if (L.st[p] & ST_FIXED) continue;
                 const int h = L.hh[p];
                 if (L.dd[p] <= 0 || h >= H_INF) continue;
-                const unsigned m = L.msk[p];
+                const DirMask<CONN> m = L.msk[p];
                 int best = 1 << 30;
                 bool adm = false;
 #pragma unroll
@@ -584,7 +631,7 @@ __device__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t rou
         for (int i = sy.idx; i < nfree; i += sy.step) {
             const int p = L.lst[i];
             if (L.st[p] & (ST_FIXED | ST_MARK)) continue;
-            const unsigned m = L.msk[p];
+            const DirMask<CONN> m = L.msk[p];
 #pragma unroll
             for (int d = 0; d < ND; ++d)
                 if (((m >> d) & 1u) && (L.st[L.nbr(p, d)] & ST_MARK) && L.res_in(p, d) > 0) {
@@ -629,8 +676,13 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     L.dd = L.flw + H * npmax;
     L.hh = reinterpret_cast<int16_t *>(L.dd + npmax);
     L.lst = L.hh + npmax;
-    L.msk = reinterpret_cast<uint8_t *>(L.lst + npmax);
-    L.st = L.msk + npmax;
+    {
+        // the mask array follows the free list, aligned to its element size (maxflow_lds_bytes counts the slack)
+        constexpr size_t MB = sizeof(LdsMask<CONN>);
+        const size_t mo = 64 + size_t(npmax) * (8 * H + 8);
+        L.msk = reinterpret_cast<LdsMask<CONN> *>(smem + ((mo + MB - 1) & ~(MB - 1)));
+    }
+    L.st = reinterpret_cast<uint8_t *>(L.msk + npmax);
 #pragma unroll
     for (int o = 0; o < H; ++o) {
         const int3 v = half_off<CONN>(o);
@@ -647,7 +699,7 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         PixLoads<CONN> ld;
         unary_loads<CONN>(g, gu, gcw, gY, Ain, uint32_t(off + p), x0 + l.x, y0 + l.y, z0 + l.z, ld);
         int32_t cp[H];
-        unsigned m;
+        DirMask<CONN> m;
         int64_t sumc;
         const int64_t Ut = unary_from<CONN>(g, ld, M, x0 + l.x, y0 + l.y, z0 + l.z, l.x, l.y, l.z, ex, ey, ez, cp, m,
                                             sumc);
@@ -660,7 +712,7 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         if (Ut < -sumc) sbits = ST_FIXED | ST_LABEL;       // label 1 in every minimiser
         else if (Ut > sumc) sbits = ST_FIXED;              // label 0 in every minimiser
         L.st[p] = sbits;
-        L.msk[p] = uint8_t(m);
+        L.msk[p] = LdsMask<CONN>(m);
         L.dd[p] = sbits ? 0 : int32_t(Ut);                 // |Ut| <= sumc < 2^29 for free nodes
         if (!sbits) L.lst[atomicAdd(&s_ctr[1], 1)] = int16_t(p);
     }
@@ -801,7 +853,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
     __shared__ int32_t s_U[EX_WAVES][16];
     __shared__ int32_t s_nc[EX_WAVES][16][ND];   // capacity towards full-stencil neighbour d (0 = none)
     __shared__ int8_t s_nj[EX_WAVES][16][ND];    // local index of that neighbour
-    __shared__ uint8_t s_m[EX_WAVES][16];        // in-block neighbour mask
+    __shared__ DirMask<CONN> s_m[EX_WAVES][16];  // in-block neighbour mask
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int it = blockIdx.x * EX_WAVES + wave;
     const Item wi = it < n_items ? items[it] : Item{0, 0};
@@ -822,7 +874,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
             const int p = lane;
             const int lx = p % ex, r = p / ex, ly = r % ey, lz = r / ey;
             int32_t cp[H];
-            unsigned m;
+            DirMask<CONN> m;
             int64_t sumc;
             PixLoads<CONN> ld;
             unary_loads<CONN>(g, gp(im.u), gp(im.cw), gp(im.Y), Ain, uint32_t(off + p), x0 + lx, y0 + ly, z0 + lz,
@@ -833,7 +885,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
             if (Ut > sumc + 1) Ut = sumc + 1;
             if (Ut < -sumc - 1) Ut = -sumc - 1;
             s_U[wave][p] = int32_t(Ut);
-            s_m[wave][p] = uint8_t(m);
+            s_m[wave][p] = m;
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
                 const int3 v = full_dir<CONN>(d);
@@ -846,7 +898,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
     // the capacity towards a negative direction is the neighbour's positive half-edge
     if (live && lane < np) {
         const int p = lane;
-        const unsigned m = s_m[wave][p];
+        const DirMask<CONN> m = s_m[wave][p];
 #pragma unroll
         for (int d = H; d < ND; ++d)
             if ((m >> d) & 1u) s_nc[wave][p][d] = s_nc[wave][s_nj[wave][p][d]][d - H];
@@ -986,13 +1038,11 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         const int3 l = block_local(p, ex, ey, axis_inv_ext(AX, kx), axis_inv_ext(AY, ky));
         const int gx = kx * AX.s + l.x, gy = ky * AY.s + l.y, gz = kz * AZ.s + l.z;
         const int32_t m = int32_t(lin(g, gx, gy, gz));
-        // block intervals of the coordinates x-1, x, x+1 along each axis (index 1 = m itself)
-        AxCov cx[3], cy[3], cz[3];
-        axis_cov3(AX, gx, cx);
-        axis_cov3(AY, gy, cy);
-        if (NDIM == 3) axis_cov3(AZ, gz, cz);
-        else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
-        const int lqm = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);   // q_m = 2^lqm
+        // block intervals of the coordinates x - R .. x + R along each axis
+        BoxCov<CONN> bc;
+        bc.init(g, gx, gy, gz);
+        const AxCov mx = bc.cx(0), my = bc.cy(0), mz = bc.cz(0);   // m itself
+        const int lqm = bc.lq(make_int3(0, 0, 0));   // q_m = 2^lqm
         // Block-major index of pixel (x, y, z) in block (tx, ty, tz).  Indices are below 2^30 (sum of block
         // sizes), so the index is computed for every candidate block in wrapping 32-bit arithmetic and replaced
         // by the owner copy's index when that block does not exist: every gather is issued unconditionally and
@@ -1021,8 +1071,8 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
 #pragma unroll
         for (int q = 0; q < MAXC; ++q) {
             const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
-            v_own[q] = e < cx[1].cnt && b < cy[1].cnt && a < cz[1].cnt;
-            cc_own[q] = copy_at(v_own[q], cx[1].thi - e, cy[1].thi - b, cz[1].thi - a, gx, gy, gz);
+            v_own[q] = e < mx.cnt && b < my.cnt && a < mz.cnt;
+            cc_own[q] = copy_at(v_own[q], mx.thi - e, my.thi - b, mz.thi - a, gx, gy, gz);
             a_own[q] = ld_at(Ain, cc_own[q] << 2);
         }
         constexpr int WSH = MAXC == 8 ? 3 : 2;   // log2 of the label word size
@@ -1030,7 +1080,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         int32_t cwv[ND];
         bool ing[ND];
         SlotWord wj[ND];
-        const unsigned ingm = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
+        const DirMask<CONN> ingm = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
@@ -1051,7 +1101,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
                 "+v"(cwv[1]), "+v"(cwv[2]), "+v"(cwv[3]), "+v"(cwv[4]), "+v"(cwv[5]), "+v"(cwv[6]), "+v"(cwv[7]),
                 "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]), "+v"(wj[4]), "+v"(wj[5]), "+v"(wj[6]),
                 "+v"(wj[7]));
-        } else {
+        } else if constexpr (CONN == 6) {
             asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(a_own[4]),
                 "+v"(a_own[5]), "+v"(a_own[6]), "+v"(a_own[7]), "+v"(wm), "+v"(cwv[0]), "+v"(cwv[1]), "+v"(cwv[2]),
                 "+v"(cwv[3]), "+v"(cwv[4]), "+v"(cwv[5]), "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]),
@@ -1104,20 +1154,20 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
-            const AxCov &ax = cx[v.x + 1], &ay = cy[v.y + 1], &az = cz[v.z + 1];
+            const AxCov &ax = bc.cx(v.x), &ay = bc.cy(v.y), &az = bc.cz(v.z);
             const SlotWord vj = sel(cnt_set(ax.cnt), X0, X1) & sel(cnt_set(ay.cnt), Y0, Y1m) &
                                 sel(cnt_set(az.cnt), Z0, Z1);
             const int yj_sum = bytesum(wj[d] & vj);
-            const int dx = ax.thi - cx[1].thi, dy = ay.thi - cy[1].thi, dz = az.thi - cz[1].thi;
-            const SlotWord sm = sel(shared_set(cx[1].cnt, dx, ax.cnt), X0, X1) &
-                                sel(shared_set(cy[1].cnt, dy, ay.cnt), Y0, Y1m) &
-                                sel(shared_set(cz[1].cnt, dz, az.cnt), Z0, Z1);
+            const int dx = ax.thi - mx.thi, dy = ay.thi - my.thi, dz = az.thi - mz.thi;
+            const SlotWord sm = sel(shared_set(mx.cnt, dx, ax.cnt), X0, X1) &
+                                sel(shared_set(my.cnt, dy, ay.cnt), Y0, Y1m) &
+                                sel(shared_set(mz.cnt, dz, az.cnt), Z0, Z1);
             const int sh = dx + 2 * dy + 4 * dz;
             // shift right by sh bytes when sh >= 0, left by -sh bytes otherwise (two shifts, no branch)
             const SlotWord wal = SlotWord(SlotWord(wj[d] >> (8 * (sh > 0 ? sh : 0))) << (8 * (sh < 0 ? -sh : 0)));
             const int shared = bytesum(wm & sm) - bytesum(wal & sm);
             // q_j and q_m are powers of two (an off-grid neighbour has c = 0, so its shift count does not matter)
-            const int lqj = max(ax.cnt - 1, 0) + max(ay.cnt - 1, 0) + max(az.cnt - 1, 0);
+            const int lqj = bc.lq(v);
             const int kd = (Y1 << lqj) - (yj_sum << lqm) - shared;
             HC += int64_t(cwv[d]) * kd;
         }
@@ -1277,14 +1327,10 @@ __device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int g
     constexpr int ND = 2 * H;
     const uint32_t i = uint32_t(gx) + uint32_t(g.W) * (uint32_t(gy) + uint32_t(g.H) * uint32_t(gz));
     const uint32_t bi = i << 2;
-    AxCov cx[3], cy[3], cz[3];
-    axis_cov3(g.ax[0], gx, cx);
-    axis_cov3(g.ax[1], gy, cy);
-    if (CONN == 6) axis_cov3(g.ax[2], gz, cz);
-    else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
-    // log2 q of this pixel (every cover count is 1 or 2)
-    const int lqi = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);
-    const unsigned ing = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
+    BoxCov<CONN> bc;
+    bc.init(g, gx, gy, gz);
+    const int lqi = bc.lq(make_int3(0, 0, 0));   // log2 q of this pixel
+    const DirMask<CONN> ing = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
     // all loads first (an off-grid neighbour reads pixel i itself and is masked); the edge's weight lives at the
     // pixel holding its positive half-edge
     const GLOBAL int32_t *wg = gp(w_src);
@@ -1305,7 +1351,7 @@ __device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int g
         const int3 v = full_dir<CONN>(d);
         const bool on = (ing >> d) & 1u;
         const int32_t wv = (d < H || on) ? wl[d] : 0;
-        const int lqj = (cx[v.x + 1].cnt - 1) + (cy[v.y + 1].cnt - 1) + (cz[v.z + 1].cnt - 1);
+        const int lqj = bc.lq(v);
         // c = lambda_q8 w 64 / (q_i q_j): q_i q_j = 2^(lqi + lqj) <= 64 (0 for an off-grid neighbour)
         const int64_t cvv = on ? int64_t(lam) * int64_t(wv) * (int64_t(1) << (6 - lqi - lqj)) : 0;
         const bool big = cvv >= CAP_SUM_LIMIT || cvv <= -CAP_SUM_LIMIT;
@@ -1469,13 +1515,26 @@ __global__ void k_batch_setup(const Img *__restrict__ imgs, int32_t n, const int
     }
 }
 
+// Same effect as validate_pending followed by the loop-limit update, with every field loaded in one round trip.
 __global__ void k_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        validate_pending(ctl);
-        ctl->t_limit = t_limit;
-        ctl->stop_on_converge = stop_on_converge;
-        if (ctl->status == 0) ctl->halted = 0;
-        if (clear_energy) ctl->energy = 0;
+        GLOBAL Ctl *c = gp(ctl);
+        const int32_t vpending = c->vpending, f = c->flags, allow_negative = c->allow_negative,
+                      status = c->status;
+        int32_t st = 0;
+        if (vpending) {
+            c->vflags = f;
+            c->flags = 0;
+            c->vpending = 0;
+            if (f & (FLAG_OFFGRID | FLAG_TOOBIG)) st = -1;
+            else if ((f & FLAG_NEGATIVE) && !allow_negative) st = -4;
+            if (st) c->status = st;
+        }
+        c->t_limit = t_limit;
+        c->stop_on_converge = stop_on_converge;
+        if (st) c->halted = 1;
+        else if (status == 0) c->halted = 0;
+        if (clear_energy) c->energy = 0;
     }
 }
 
@@ -1507,12 +1566,9 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int32_t *__restric
             const int64_t i = lin(g, gx, gy, gz);
             const int li = Y[i] > Y_HALF;
             if (li) e += 256ll * u[i];
-            AxCov cx[3], cy[3], cz[3];
-            axis_cov3(g.ax[0], gx, cx);
-            axis_cov3(g.ax[1], gy, cy);
-            if (CONN == 6) axis_cov3(g.ax[2], gz, cz);
-            else cz[0] = cz[1] = cz[2] = AxCov{0, 1};
-            const int lqi = (cx[1].cnt - 1) + (cy[1].cnt - 1) + (cz[1].cnt - 1);
+            BoxCov<CONN> bc;
+            bc.init(g, gx, gy, gz);
+            const int lqi = bc.lq(make_int3(0, 0, 0));
 #pragma unroll
             for (int o = 0; o < H; ++o) {
                 const int3 v = half_off<CONN>(o);
@@ -1520,7 +1576,7 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int32_t *__restric
                 const int lj = Y[lin(g, gx + v.x, gy + v.y, gz + v.z)] > Y_HALF;
                 if (li == lj) continue;
                 // lambda_q8 w_ij = c_ij q_i q_j / 64 exactly (c_ij = lambda_q8 w_ij 64 / (q_i q_j), q a power of two)
-                const int lqj = (cx[v.x + 1].cnt - 1) + (cy[v.y + 1].cnt - 1) + (cz[v.z + 1].cnt - 1);
+                const int lqj = bc.lq(v);
                 e += (static_cast<long long>(cw[int64_t(o) * g.n + i]) << (lqi + lqj)) >> 6;
             }
         }
@@ -1629,6 +1685,10 @@ hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_sr
                                    A1, yhat, resid, ctl, si); break;
         case 8: hipLaunchKernelGGL(k_setup<8>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
                                    A1, yhat, resid, ctl, si); break;
+        case 24: hipLaunchKernelGGL(k_setup<24>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
+                                    A1, yhat, resid, ctl, si); break;
+        case 48: hipLaunchKernelGGL(k_setup<48>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
+                                    A1, yhat, resid, ctl, si); break;
         default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y,
                                     A0, A1, yhat, resid, ctl, si); break;
     }
@@ -1641,6 +1701,8 @@ hipError_t launch_setup_batch(int32_t conn, const Img *imgs, const SetupArg *arg
     switch (conn) {
         case 4: hipLaunchKernelGGL(k_setup_batch<4>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
         case 8: hipLaunchKernelGGL(k_setup_batch<8>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
+        case 24: hipLaunchKernelGGL(k_setup_batch<24>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
+        case 48: hipLaunchKernelGGL(k_setup_batch<48>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
         default: hipLaunchKernelGGL(k_setup_batch<6>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
     }
     return hipGetLastError();
@@ -1668,6 +1730,8 @@ hipError_t launch_solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hi
     switch (grp.conn) {
         case 4: return solve_phase<4>(grp, s, e0, e1);
         case 8: return solve_phase<8>(grp, s, e0, e1);
+        case 24: return solve_phase<24>(grp, s, e0, e1);
+        case 48: return solve_phase<48>(grp, s, e0, e1);
         default: return solve_phase<6>(grp, s, e0, e1);
     }
 }
@@ -1689,6 +1753,8 @@ hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0
     if (grp.n_chk_items > 0) switch (grp.conn) {
         case 4: consensus_launch<4>(grp, s, e0, e1); break;
         case 8: consensus_launch<8>(grp, s, e0, e1); break;
+        case 24: consensus_launch<24>(grp, s, e0, e1); break;
+        case 48: consensus_launch<48>(grp, s, e0, e1); break;
         default: consensus_launch<6>(grp, s, e0, e1); break;
     }
     return hipGetLastError();
@@ -1726,6 +1792,8 @@ hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *cw, con
     switch (g.conn) {
         case 4: hipLaunchKernelGGL(k_energy<4>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
         case 8: hipLaunchKernelGGL(k_energy<8>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
+        case 24: hipLaunchKernelGGL(k_energy<24>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
+        case 48: hipLaunchKernelGGL(k_energy<48>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
         default: hipLaunchKernelGGL(k_energy<6>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
     }
     hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s, part, int(wgs), ctl);

@@ -23,6 +23,7 @@ from .configs import (  # noqa: F401
     config5_request,
     config5_image,
     config5_trace,
+    config_kernel,
     random_problem,
     lambda_q8,
     DEFAULT_MU0_2D,

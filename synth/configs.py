@@ -29,6 +29,13 @@ def half_stencil(ndim: int, conn: int) -> List[Tuple[int, int, int]]:
         return [(1, 0, 0), (0, 1, 0)]
     if ndim == 2 and conn == 8:
         return [(1, 0, 0), (0, 1, 0), (1, 1, 0), (-1, 1, 0)]
+    if ndim == 2 and conn in (24, 48):   # 5x5 and 7x7 squares: (dx, 0) for dx = 1..r, then rows dy = 1..r
+        r = 2 if conn == 24 else 3
+        out = [(dx, 0, 0) for dx in range(1, r + 1)]
+        for dy in range(1, r + 1):
+            for dx in range(-r, r + 1):
+                out.append((dx, dy, 0))
+        return out
     if ndim == 3 and conn == 6:
         return [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
     raise ValueError(f"unsupported stencil ndim={ndim} conn={conn}")
@@ -76,7 +83,7 @@ def _weights_from_features(feat: np.ndarray, ndim: int, conn: int, sigma_w: floa
                            scale: float = 1000.0) -> np.ndarray:
     """Contrast-sensitive weights w = round(scale * exp(-|dx|^2 / (2 sigma^2)) / d) on the half-stencil.
 
-    feat has shape (D, H, W, C).  d is the Euclidean length of the offset (1 or sqrt 2)."""
+    feat has shape (D, H, W, C).  d is the Euclidean length of the offset."""
     D, H, W, _ = feat.shape
     offs = half_stencil(ndim, conn)
     n = W * H * D
@@ -231,6 +238,26 @@ def config5_trace(n_requests: int = 2000, mean_gap_s: float = 0.005, seed: int =
     """Poisson arrival times (seconds) for the serving workload: exponential gaps, mean 5 ms (200 req/s)."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(mean_gap_s, size=n_requests))
+
+
+def config_kernel(k: int, seed: int = 0, W: int = 512, H: int = 512, mu0: int = DEFAULT_MU0_2D) -> Problem:
+    """The image of config2 with the k x k square neighbourhood (k = 5 or 7) of the paper's larger-kernel
+    experiments: contrast weights on every offset of the square (scale 1000, divided by the offset's length);
+    lambda = 1 (k = 5) or 0.6 (k = 7), so that the total smoothing per pixel stays near config2's; 32x32 blocks
+    with o = 2 for k = 5 and 16x16 blocks with o = 2 for k = 7 (LDS per block node grows with the stencil)."""
+    if k not in (5, 7):
+        raise ValueError("k must be 5 or 7")
+    conn = 24 if k == 5 else 48
+    rng = np.random.default_rng(seed)
+    fg = _ellipse_mask(rng, W, H, 5)
+    base = np.where(fg, 0.7, 0.3)[:, :, None]
+    img = base + rng.normal(0.0, 0.1, size=(H, W, 3))
+    u = _gauss_llr(img, 0.7, 0.3, 0.1, channels=True)
+    w = _weights_from_features(img[None], 2, conn, 0.1)
+    B = 32 if k == 5 else 16
+    return Problem(f"kernel{k}_ellipses{W}x{H}_{conn}conn", (W, H, 1), 2, conn, u.astype(np.int32), w,
+                   lambda_q8(1.0 if k == 5 else 0.6), (B, B, 1), (2, 2, 0), mu0,
+                   truth=fg.reshape(-1).astype(np.uint8))
 
 
 def random_problem(seed: int, dims, conn: int, block, overlap, lam_q8: int = 256,

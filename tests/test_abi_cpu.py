@@ -59,8 +59,8 @@ def _params(native, dims=(512, 512, 1), conn=8, block=(32, 32, 1), overlap=(2, 2
     return p
 
 
-def _interior_count(dims, block, overlap):
-    """Pixels whose 3x3(x3) neighbourhood lies in their own block only (the block-solve kernel finishes them)."""
+def _interior_count(dims, block, overlap, r=1):
+    """Pixels whose stencil box (radius r) lies in their own block only (the block-solve kernel finishes them)."""
     from oracle import dope as od
     total = 1
     for N, B, o in zip(dims, block, overlap):
@@ -68,8 +68,8 @@ def _interior_count(dims, block, overlap):
         oo = 0 if len(iv) == 1 else o
         cnt = 0
         for t, (a, b) in enumerate(iv):
-            lo = a + oo + 1 if t > 0 else 0
-            hi = b - oo - 1 if t < len(iv) - 1 else N
+            lo = a + oo + r if t > 0 else 0
+            hi = b - oo - r if t < len(iv) - 1 else N
             cnt += max(0, hi - lo)
         total *= cnt
     return total
@@ -90,16 +90,19 @@ def _workspace_model(dims, h, K, tot, n_int):
     ((64, 64, 1), 4, (16, 16, 1), (1, 1, 0), 2),
     ((128, 128, 64), 6, (16, 16, 16), (1, 1, 1), 3),
     ((257, 131, 1), 8, (32, 16, 1), (3, 1, 0), 2),
+    ((512, 512, 1), 24, (32, 32, 1), (2, 2, 0), 2),
+    ((200, 150, 1), 48, (16, 16, 1), (2, 2, 0), 2),
 ])
 def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, ndim):
     from oracle import dope as od
     p = _params(native, dims, conn, block, overlap, ndim=ndim)
     blocks = od.make_blocks(dims, block, overlap)
     n = dims[0] * dims[1] * dims[2]
-    h = {4: 2, 8: 4, 6: 3}[conn]
+    h = {4: 2, 8: 4, 6: 3, 24: 12, 48: 24}[conn]
+    r = {24: 2, 48: 3}.get(conn, 1)
     tot = sum(len(b.idx) for b in blocks)
     assert native.dope_workspace_bytes(ctypes.byref(p)) == _workspace_model(dims, h, len(blocks), tot,
-                                                                     _interior_count(dims, block, overlap))
+                                                                     _interior_count(dims, block, overlap, r))
 
 
 @pytest.mark.parametrize("kw,msg", [
@@ -109,6 +112,9 @@ def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, n
     (dict(block=(64, 64, 1)), "LDS"),                     # 64x64 8-connected exceeds 160 KiB of LDS
     (dict(block=(32, 32, 1), solver=2), "exhaustive"),    # enumeration needs <= 16 pixels
     (dict(dims=(0, 5, 1)), "dims"),
+    (dict(conn=48), "LDS"),                               # 32x32 blocks with 7x7 neighbourhoods: 209 B per node
+    (dict(conn=48, block=(4, 4, 1), overlap=(2, 2, 0)), "stencil radius"),   # stride 2 < radius 3
+    (dict(conn=24, ndim=3, dims=(16, 16, 16), block=(8, 8, 8), overlap=(1, 1, 1)), "connectivity"),
 ])
 def test_create_rejects_bad_params(native, kw, msg):
     p = _params(native, **kw)
@@ -128,6 +134,8 @@ def test_autotune_is_a_pure_function_of_shape(native):
     assert autotune(2, (4096, 256), 8) == ((16, 16, 1), (1, 1, 0))
     assert autotune(2, (512, 300), 8) == ((32, 32, 1), (1, 1, 0))
     assert autotune(3, (128, 128, 64), 6) == ((16, 16, 16), (1, 1, 1))
+    assert autotune(2, (512, 512), 24) == ((32, 32, 1), (1, 1, 0))
+    assert autotune(2, (512, 512), 48) == ((16, 16, 1), (1, 1, 0))
     assert autotune(2, (512, 512), 8) == autotune(2, (512, 512), 8)
     with pytest.raises(Exception):
         autotune(2, (64, 64), 6)

@@ -294,6 +294,72 @@ def test_config4_full_size_sampled():
 
 
 # ------------------------------------------------------------------------------------------------------------
+# larger neighbourhoods: 5x5 (connectivity 24) and 7x7 (48) squares
+# ------------------------------------------------------------------------------------------------------------
+
+WIDE_CASES = [
+    # dims, conn, block, overlap, lam_q8, mu0
+    ((37, 29, 1), 24, (8, 8, 1), (2, 2, 0), 300, 1000),
+    ((23, 19, 1), 24, (4, 4, 1), (2, 2, 0), 256, 500),      # stride 2 = radius: q up to 4 everywhere
+    ((20, 17, 1), 24, (0, 0, 0), (0, 0, 0), 256, 1000),     # one block: global cut
+    ((40, 33, 1), 48, (10, 10, 1), (3, 3, 0), 150, 1000),
+    ((31, 26, 1), 48, (6, 6, 1), (3, 3, 0), 120, 800),      # stride 3 = radius
+    ((3, 30, 1), 48, (3, 8, 1), (0, 3, 0), 150, 1000),      # grid narrower than the stencil
+]
+
+
+@pytest.mark.parametrize("case", WIDE_CASES)
+def test_wide_stencils_every_iteration(case):
+    dims, conn, block, overlap, lam, mu0 = case
+    p = synth.random_problem(21, dims, conn, block, overlap, lam_q8=lam, u_range=(-4000, 4000),
+                             w_range=(0, 900), mu0=mu0)
+    d, _, _ = run_parity(p, 5, f"wide {case}")
+    d.close()
+
+
+@pytest.mark.parametrize("k,W,H", [(5, 100, 90), (7, 90, 70)])
+def test_kernel_workloads_small_every_iteration(k, W, H):
+    """The larger-kernel workloads (contrast weights on the 5x5 / 7x7 square) on small grids."""
+    p = synth.config_kernel(k, W=W, H=H)
+    p.mu0 = 300
+    d, st_o, dec = run_parity(p, 8, f"kernel{k} {W}x{H}")
+    assert np.array_equal(d.labels(), od.labels(st_o.Y))
+    assert d.energy() == od.energy_q(dec, od.labels(st_o.Y))
+    d.close()
+
+
+def test_wide_exhaustive_nonsubmodular():
+    p = synth.random_problem(14, (16, 15, 1), 24, (4, 4, 1), (1, 1, 0), lam_q8=200, u_range=(-2000, 2000),
+                             w_range=(0, 500), neg_frac=0.3, mu0=1000, solver="exhaustive")
+    d, _, _ = run_parity(p, 4, "5x5 neighbourhood, 4x4 blocks, exhaustive")
+    d.close()
+
+
+def test_kernel5_full_size_sampled():
+    sampled_parity(synth.config_kernel(5), 3, 20, "kernel5 512x512")
+
+
+def test_kernel7_full_size_sampled():
+    sampled_parity(synth.config_kernel(7), 2, 40, "kernel7 512x512")
+
+
+def test_batch_wide_stencil_matches_alone():
+    from paper_1704_03116_amd.solver import Batch
+    probs = [synth.config_kernel(5, seed=s, W=W, H=H) for s, (W, H) in enumerate([(90, 70), (64, 99), (120, 41)])]
+    for p in probs:
+        p.mu0 = 300
+    announce("batch of 5x5-neighbourhood images")
+    ctxs = [make_ctx(p) for p in probs]
+    with Batch(ctxs, graph=True) as b:
+        b.iterate(4)
+    for p, c in zip(probs, ctxs):
+        st_o, _, _, _ = od.run(p, n_iter=4)
+        Y, A, yh, mu, t = c.get_state()
+        assert t == 4 and np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+        c.close()
+
+
+# ------------------------------------------------------------------------------------------------------------
 # batched launches: many images, one launch per phase; each image bit-identical to running alone
 # ------------------------------------------------------------------------------------------------------------
 

@@ -62,7 +62,20 @@ TINY = [
     ((9, 7, 1), 8, (5, 5, 1), (2, 2, 0)),
     ((4, 4, 4), 6, (3, 3, 3), (1, 1, 1)),
     ((5, 4, 3), 6, (3, 2, 2), (1, 0, 0)),
+    ((7, 7, 1), 24, (4, 4, 1), (1, 1, 0)),     # 5x5 neighbourhood, stride 3 >= radius 2
+    ((8, 7, 1), 48, (5, 5, 1), (2, 2, 0)),     # 7x7 neighbourhood, stride 3 = radius 3
 ]
+
+
+@pytest.mark.parametrize("conn,r", [(24, 2), (48, 3)])
+def test_square_neighbourhood_offsets(conn, r):
+    """The larger neighbourhoods of the experiments (square kernels of size 5 and 7): the half-stencil and its
+    negation partition the (2r+1)^2 square without its centre, so every undirected edge appears exactly once."""
+    half = dope.neighbour_offsets(2, conn)
+    full = half + [(-dx, -dy, -dz) for dx, dy, dz in half]
+    square = [(dx, dy, 0) for dy in range(-r, r + 1) for dx in range(-r, r + 1) if (dx, dy) != (0, 0)]
+    assert len(half) == len(set(half)) == (len(square)) // 2
+    assert sorted(full) == sorted(square)
 
 
 # --------------------------------------------------------------------------------------------------------
@@ -337,9 +350,9 @@ def test_energy_definition_eq1():
         assert dope.energy_q(p, l) == exp
 
 
-@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("seed", range(8))
 def test_global_mincut_vs_bruteforce(seed):
-    p = tiny_problem(20 + seed, (4, 3, 1), 8 if seed % 2 else 4, (2, 2, 1), (0, 0, 0))
+    p = tiny_problem(20 + seed, (4, 3, 1), [4, 8, 24, 48][seed % 4], (2, 2, 1), (0, 0, 0))
     x, e = dope.global_mincut(p)
     best, sols = None, []
     for code in range(1 << p.n):
@@ -357,7 +370,8 @@ def test_global_mincut_vs_bruteforce(seed):
 # special cases of Algorithm 1
 # --------------------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("conn,dims", [(4, (7, 6, 1)), (8, (6, 6, 1)), (6, (4, 3, 3))])
+@pytest.mark.parametrize("conn,dims", [(4, (7, 6, 1)), (8, (6, 6, 1)), (6, (4, 3, 3)), (24, (6, 5, 1)),
+                                       (48, (6, 6, 1))])
 def test_single_block_is_global_cut(conn, dims):
     """K = 1: C = R = 0, so iteration 1 solves Eq. (3) exactly; y = y^ and the residual is 0 (stop at t = 1)."""
     p = tiny_problem(30, dims, conn, (0, 0, 0), (0, 0, 0))
