@@ -31,12 +31,14 @@ def workload(name, seed=0):
         return synth.config1(seed=seed)
     if name == "config4":
         return synth.config4(seed=seed)
+    if name in ("kernel5", "kernel7"):   # the config2 image with 5x5 / 7x7 square neighbourhoods
+        return synth.config_kernel(int(name[-1]), seed=seed)
     raise SystemExit(f"unknown workload {name}")
 
 
-def interior_count(dims, block, overlap):
-    """Block pixels whose 3x3(x3) neighbourhood lies in their own block only (finished by the block-solve
-    kernel): per axis, block t contributes [start + o + 1 (0 for t = 0), end - o - 1 (N for the last block))."""
+def interior_count(dims, block, overlap, r=1):
+    """Block pixels whose stencil box (radius r) lies in their own block only (finished by the block-solve
+    kernel): per axis, block t contributes [start + o + r (0 for t = 0), end - o - r (N for the last block))."""
     total = 1
     for N, B, o in zip(dims, block, overlap):
         if B <= 0 or B >= N:
@@ -47,8 +49,8 @@ def interior_count(dims, block, overlap):
         c = 0
         for t in range(count):
             a, b = t * s, min(t * s + B, N)
-            lo = a + o + 1 if t > 0 else 0
-            hi = b - o - 1 if t < count - 1 else N
+            lo = a + o + r if t > 0 else 0
+            hi = b - o - r if t < count - 1 else N
             c += max(0, hi - lo)
         total *= c
     return total
@@ -221,7 +223,7 @@ def main():
     value = p.n * args.steps / elapsed / 1e6
 
     K, tot, h, n = d.K, d.tot, d.h, p.n
-    n_int = interior_count(p.dims, p.block, p.overlap)
+    n_int = interior_count(p.dims, p.block, p.overlap, {24: 2, 48: 3}.get(p.conn, 1))
     n_bl = tot - n_int
     kernels = {
         # per block pixel: u 4 + weights 4h + Y 4 + A 4 read, block label 1 written; per interior pixel (finished

@@ -452,7 +452,7 @@ struct FlowStats {
 // forces, push-relabel to a max preflow, and the canonical cut (ST_MARK = label 1).
 // Forced-node elimination over the nfree nodes of lst; returns whether any node is left free.
 template <int CONN, class Sync>
-__device__ bool eliminate(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs) {
+__device__ __forceinline__ bool eliminate(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs) {
     constexpr int ND = 2 * Sten<CONN>::H;
     // (1) a node is forced when its unary, with the pairwise terms of its fixed neighbours folded in, exceeds the
     //     total capacity towards its free neighbours.  Forcing only grows as neighbours get fixed, so passes may
@@ -500,7 +500,7 @@ __device__ bool eliminate(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs)
 // Keeps the list entries that are still free (order not preserved); returns their count.  The height array,
 // not yet in use, holds the survivors by list position in between.  Whole workgroup; ctr is a zeroed LDS slot.
 template <int CONN>
-__device__ int compact_free(BlockLds<CONN> &L, int nfree, int *ctr, int tid, int nt) {
+__device__ __forceinline__ int compact_free(BlockLds<CONN> &L, int nfree, int *ctr, int tid, int nt) {
     for (int i = tid; i < nfree; i += nt) {
         const int p = L.lst[i];
         L.hh[i] = (L.st[p] & ST_FIXED) ? int16_t(-1) : int16_t(p);
@@ -517,8 +517,8 @@ __device__ int compact_free(BlockLds<CONN> &L, int nfree, int *ctr, int tid, int
 // Everything after the elimination for the nfree nodes of lst: flow network, push-relabel to a max preflow, and
 // the canonical cut (ST_MARK = label 1).
 template <int CONN, class Sync>
-__device__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t round_limit, int32_t relabel_period,
-                             FlowStats &fs) {
+__device__ __forceinline__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t round_limit,
+                                             int32_t relabel_period, FlowStats &fs) {
     constexpr int ND = 2 * Sten<CONN>::H;
     // (2) flow network of the remaining free nodes: source excess -U and sink capacity U in one signed value
     for (int i = sy.idx; i < nfree; i += sy.step) {
@@ -795,11 +795,14 @@ __device__ __forceinline__ const Img &const_img(const Img *p) {
     return *(const Img *)(const CONSTANT Img *)p;
 }
 
+// The block-solve kernels ask for at least two wavefronts per SIMD (at most 256 VGPRs): with the 7x7 stencil's
+// 256-thread workgroups that lets two blocks share a CU, as their LDS allows.
+//
 // Batch block solve, one workgroup per (image, block) item: workgroup b takes item b.  Items stay in dispatch
 // order (round-robin over the XCDs): hard blocks cluster in space, and contiguous item ranges per XCD would leave
 // XCDs idle behind the one that got the cluster.
 template <int CONN, int NT>
-__global__ __launch_bounds__(NT) void k_block_solve(const Img *__restrict__ imgs, const Item *__restrict__ items,
+__global__ __launch_bounds__(NT, 2) void k_block_solve(const Img *__restrict__ imgs, const Item *__restrict__ items,
                                                     int32_t npmax, int32_t round_limit, int32_t relabel_period) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Item wi = items[blockIdx.x];
@@ -811,7 +814,8 @@ __global__ __launch_bounds__(NT) void k_block_solve(const Img *__restrict__ imgs
 // until it is empty, so blocks of uneven max-flow cost balance over the workgroups.  A kernel of its own: the
 // loop around the inlined solver raises register pressure, which the one-item-per-workgroup kernel need not pay.
 template <int CONN, int NT>
-__global__ __launch_bounds__(NT) void k_block_solve_queue(const Img *__restrict__ imgs, const Item *__restrict__ items,
+__global__ __launch_bounds__(NT, 2) void k_block_solve_queue(const Img *__restrict__ imgs,
+                                                             const Item *__restrict__ items,
                                                           int32_t n_items, Queue *queue, int32_t npmax,
                                                           int32_t round_limit, int32_t relabel_period) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -833,7 +837,7 @@ __global__ __launch_bounds__(NT) void k_block_solve_queue(const Img *__restrict_
 // solves block b, and no descriptor or loop-control load stands between the launch and the gathers (the loop
 // control is read while they are in flight; a skipped iteration stops before its first global store).
 template <int CONN, int NT>
-__global__ __launch_bounds__(NT) void k_block_solve_one(const Img one, int32_t par, int32_t npmax,
+__global__ __launch_bounds__(NT, 2) void k_block_solve_one(const Img one, int32_t par, int32_t npmax,
                                                         int32_t round_limit, int32_t relabel_period) {
     extern __shared__ __align__(16) unsigned char smem[];
     block_maxflow<CONN, NT>(one, blockIdx.x, smem, npmax, round_limit, relabel_period, par, true);
