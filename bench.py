@@ -56,7 +56,8 @@ def interior_count(dims, block, overlap, r=1):
     return total
 
 
-TRAFFIC_RECORDS = {"config2": "hbm_traffic_config2_512x512.json", "config3": "hbm_traffic_config3_128x128x64.json"}
+TRAFFIC_RECORDS = {"config2": "hbm_traffic_config2_512x512.json", "config3": "hbm_traffic_config3_128x128x64.json",
+                   "kernel5": "hbm_traffic_kernel5_512x512.json", "kernel7": "hbm_traffic_kernel7_512x512.json"}
 
 
 def measured_traffic(workload_name):
