@@ -833,14 +833,19 @@ __global__ __launch_bounds__(NT, 2) void k_block_solve_queue(const Img *__restri
     }
 }
 
-// One-image block solve: the image descriptor and the multiplier parity come as kernel arguments, workgroup b
-// solves block b, and no descriptor or loop-control load stands between the launch and the gathers (the loop
-// control is read while they are in flight; a skipped iteration stops before its first global store).
+// One-image block solve: the image descriptor and the multiplier parity come as kernel arguments, and no
+// descriptor or loop-control load stands between the launch and the gathers (the loop control is read while they
+// are in flight; a skipped iteration stops before its first global store).  Workgroup b solves block
+// xcd_item(b, K): each XCD gets a contiguous range of blocks, so the halo lines that neighbouring blocks share are
+// fetched into one L2 (measured on MI355X: 7x7 neighbourhood 55 -> 41 us per launch, 5x5 30 -> 28 us, 512x512
+// 8-connected solve 2 % faster).  The batch kernels keep dispatch order, where whole images of hard blocks
+// would otherwise land on one XCD.
 template <int CONN, int NT>
 __global__ __launch_bounds__(NT, 2) void k_block_solve_one(const Img one, int32_t par, int32_t npmax,
                                                         int32_t round_limit, int32_t relabel_period) {
     extern __shared__ __align__(16) unsigned char smem[];
-    block_maxflow<CONN, NT>(one, blockIdx.x, smem, npmax, round_limit, relabel_period, par, true);
+    block_maxflow<CONN, NT>(one, xcd_item(blockIdx.x, gridDim.x), smem, npmax, round_limit, relabel_period, par,
+                            true);
 }
 
 // ------------------------------------------------------------------------------------------------------------
