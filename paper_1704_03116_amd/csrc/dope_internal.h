@@ -22,7 +22,7 @@ inline Axis make_axis(int32_t N, int32_t B, int32_t s, int32_t nb) {
 struct Geom {
     Axis ax[3];
     int32_t W, H, D;
-    int32_t conn;       // 4, 8, 24 (5x5), 48 (7x7) or 6
+    int32_t conn;       // 2D: 4, 8, 24 (5x5), 48 (7x7); 3D: 6, 32 (radius-2 ball)
     int32_t hs;         // half-stencil size
     int32_t rad;        // stencil radius: every neighbour offset lies in [-rad, rad] per axis
     int32_t K;          // number of blocks
@@ -60,8 +60,9 @@ inline __host__ __device__ int64_t block_offset(const Geom &g, int32_t tx, int32
     return Pz * g.span[1] * g.span[0] + Ez * (Py * g.span[0] + Ey * Px);
 }
 
-// Label slots per pixel (most blocks a pixel can lie in): 4 in 2D, 8 in 3D (6-connected volumes).
-inline __host__ __device__ int slot_count(const Geom &g) { return g.conn == 6 ? 8 : 4; }
+// Label slots per pixel (most blocks a pixel can lie in): 4 in 2D, 8 in 3D.
+inline __host__ __device__ bool conn_is_3d(int32_t conn) { return conn == 6 || conn == 32; }
+inline __host__ __device__ int slot_count(const Geom &g) { return conn_is_3d(g.conn) ? 8 : 4; }
 
 inline __host__ __device__ bool is_interior(const Geom &g, int32_t tx, int32_t ty, int32_t tz, int32_t x, int32_t y,
                                             int32_t z) {

@@ -49,14 +49,16 @@ __device__ __forceinline__ void st_at(GLOBAL T *base, uint32_t off, T v) {
 enum : uint8_t { ST_FIXED = 1, ST_LABEL = 2, ST_MARK = 8 };
 constexpr int16_t H_INF = 0x7FFF;
 
-// Stencils: H half-edges per pixel, radius R (every offset lies in [-R, R] per axis).  CONN 24 and 48 are the
-// square 5x5 and 7x7 neighbourhoods of a 2D grid.
+// Stencils: H half-edges per pixel, radius R (every offset lies in [-R, R] per axis), grid dimension NDIM.
+// CONN 24 and 48 are the square 5x5 and 7x7 neighbourhoods of a 2D grid, CONN 32 the radius-2 ball of a 3D grid
+// (the spherical kernel of size 5).
 template <int CONN> struct Sten;
-template <> struct Sten<4> { static constexpr int H = 2, R = 1; };
-template <> struct Sten<8> { static constexpr int H = 4, R = 1; };
-template <> struct Sten<24> { static constexpr int H = 12, R = 2; };
-template <> struct Sten<48> { static constexpr int H = 24, R = 3; };
-template <> struct Sten<6> { static constexpr int H = 3, R = 1; };
+template <> struct Sten<4> { static constexpr int H = 2, R = 1, NDIM = 2; };
+template <> struct Sten<8> { static constexpr int H = 4, R = 1, NDIM = 2; };
+template <> struct Sten<24> { static constexpr int H = 12, R = 2, NDIM = 2; };
+template <> struct Sten<48> { static constexpr int H = 24, R = 3, NDIM = 2; };
+template <> struct Sten<6> { static constexpr int H = 3, R = 1, NDIM = 3; };
+template <> struct Sten<32> { static constexpr int H = 16, R = 2, NDIM = 3; };
 
 // One bit per full-stencil direction.
 template <int CONN>
@@ -83,6 +85,28 @@ __device__ __forceinline__ int3 half_off(int o) {
         if (o < R) return make_int3(o + 1, 0, 0);
         const int q = o - R;
         return make_int3(q % (2 * R + 1) - R, 1 + q / (2 * R + 1), 0);
+    }
+    if (CONN == 32) {
+        // offsets of length at most 2 whose first nonzero coordinate, from z down to x, is positive; ordered by
+        // z, then y, then x
+        switch (o) {
+            case 0: return make_int3(1, 0, 0);
+            case 1: return make_int3(2, 0, 0);
+            case 2: return make_int3(-1, 1, 0);
+            case 3: return make_int3(0, 1, 0);
+            case 4: return make_int3(1, 1, 0);
+            case 5: return make_int3(0, 2, 0);
+            case 6: return make_int3(-1, -1, 1);
+            case 7: return make_int3(0, -1, 1);
+            case 8: return make_int3(1, -1, 1);
+            case 9: return make_int3(-1, 0, 1);
+            case 10: return make_int3(0, 0, 1);
+            case 11: return make_int3(1, 0, 1);
+            case 12: return make_int3(-1, 1, 1);
+            case 13: return make_int3(0, 1, 1);
+            case 14: return make_int3(1, 1, 1);
+            default: return make_int3(0, 0, 2);
+        }
     }
     switch (o) {
         case 0: return make_int3(1, 0, 0);
@@ -160,7 +184,7 @@ struct BoxCov {
     __device__ __forceinline__ void init(const Geom &g, int gx, int gy, int gz) {
         axis_cov<R>(g.ax[0], gx, x);
         axis_cov<R>(g.ax[1], gy, y);
-        if (CONN == 6) {
+        if (Sten<CONN>::NDIM == 3) {
             axis_cov<R>(g.ax[2], gz, z);
         } else {
 #pragma unroll
@@ -334,7 +358,7 @@ __device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN
         const int32_t c = ((ld.ing >> d) & 1u) ? ld.cv[d] : 0;
         const bool inb = (inb_m >> d) & 1u;
         const int lqj = bc.lq(v);
-        if (CONN != 6) {
+        if (Sten<CONN>::NDIM == 2) {
             // q_j <= 4 in 2D, so F = (q_j - [j in k]) c stays below 2^31 in magnitude: one 32 x 32 -> 64-bit
             // multiply-add per neighbour
             const int32_t F = c * (1 << lqj) - (inb ? c : 0);
@@ -748,7 +772,7 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     GLOBAL int32_t *Aout = gp(parity ? im.A0 : im.A1);
     GLOBAL uint8_t *yhat = gp(im.yhat);
     GLOBAL uint8_t *yslot = gp(im.yslot);
-    const int nslot = CONN == 6 ? 8 : 4;
+    const int nslot = Sten<CONN>::NDIM == 3 ? 8 : 4;
     GLOBAL int32_t *Yg = gp(im.Y);
     unsigned long long r2 = 0;
     bool ovf = false;
@@ -964,7 +988,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
         const int ex = bt[3], ey = bt[4];
         const int lx = lane % ex, r = lane / ex, ly = r % ey, lz = r / ey;
         const int tx = k % g.ax[0].nb, ty = (k / g.ax[0].nb) % g.ax[1].nb, tz = k / (g.ax[0].nb * g.ax[1].nb);
-        const int nslot = CONN == 6 ? 8 : 4;
+        const int nslot = Sten<CONN>::NDIM == 3 ? 8 : 4;
         gp(im.yslot)[lin(g, bt[0] + lx, bt[1] + ly, bt[2] + lz) * nslot + label_slot(g, tx, ty, tz, lx, ly, lz)] =
             uint8_t(yv);
         if (is_interior(g, tx, ty, tz, bt[0] + lx, bt[1] + ly, bt[2] + lz)) {
@@ -1006,7 +1030,7 @@ template <int CONN>
 __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int par, bool spec) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
-    constexpr int NDIM = CONN == 6 ? 3 : 2;
+    constexpr int NDIM = Sten<CONN>::NDIM;
     constexpr int MAXC = 1 << NDIM;   // most blocks a pixel can lie in
     const Geom &g = im.g;
     const GLOBAL Ctl *ctl = gp(im.ctl);
@@ -1698,6 +1722,8 @@ hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_sr
                                     A1, yhat, resid, ctl, si); break;
         case 48: hipLaunchKernelGGL(k_setup<48>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
                                     A1, yhat, resid, ctl, si); break;
+        case 32: hipLaunchKernelGGL(k_setup<32>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
+                                    A1, yhat, resid, ctl, si); break;
         default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y,
                                     A0, A1, yhat, resid, ctl, si); break;
     }
@@ -1712,6 +1738,7 @@ hipError_t launch_setup_batch(int32_t conn, const Img *imgs, const SetupArg *arg
         case 8: hipLaunchKernelGGL(k_setup_batch<8>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
         case 24: hipLaunchKernelGGL(k_setup_batch<24>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
         case 48: hipLaunchKernelGGL(k_setup_batch<48>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
+        case 32: hipLaunchKernelGGL(k_setup_batch<32>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
         default: hipLaunchKernelGGL(k_setup_batch<6>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
     }
     return hipGetLastError();
@@ -1741,6 +1768,7 @@ hipError_t launch_solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hi
         case 8: return solve_phase<8>(grp, s, e0, e1);
         case 24: return solve_phase<24>(grp, s, e0, e1);
         case 48: return solve_phase<48>(grp, s, e0, e1);
+        case 32: return solve_phase<32>(grp, s, e0, e1);
         default: return solve_phase<6>(grp, s, e0, e1);
     }
 }
@@ -1764,6 +1792,7 @@ hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0
         case 8: consensus_launch<8>(grp, s, e0, e1); break;
         case 24: consensus_launch<24>(grp, s, e0, e1); break;
         case 48: consensus_launch<48>(grp, s, e0, e1); break;
+        case 32: consensus_launch<32>(grp, s, e0, e1); break;
         default: consensus_launch<6>(grp, s, e0, e1); break;
     }
     return hipGetLastError();
@@ -1803,6 +1832,7 @@ hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *cw, con
         case 8: hipLaunchKernelGGL(k_energy<8>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
         case 24: hipLaunchKernelGGL(k_energy<24>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
         case 48: hipLaunchKernelGGL(k_energy<48>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
+        case 32: hipLaunchKernelGGL(k_energy<32>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
         default: hipLaunchKernelGGL(k_energy<6>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
     }
     hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s, part, int(wgs), ctl);

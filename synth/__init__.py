@@ -24,6 +24,7 @@ from .configs import (  # noqa: F401
     config5_image,
     config5_trace,
     config_kernel,
+    config3_kernel5,
     random_problem,
     lambda_q8,
     DEFAULT_MU0_2D,

@@ -81,7 +81,7 @@ def _workspace_model(dims, h, K, tot, n_int):
     nbl = n - n_int   # boundary pixels (each listed once, through its owner copy)
     chunks = (nbl + 255) // 256
     return (a(128) + a(512) + a(8 * K) + a(8 * chunks) + a(256) + a(K * 32) + a(4 * chunks) + a(8 * nbl)
-            + a(4 * n) + 2 * a(4 * h * n) + a(4 * n) + 2 * a(4 * tot) + a(tot) + a(n * (8 if h == 3 else 4))
+            + a(4 * n) + 2 * a(4 * h * n) + a(4 * n) + 2 * a(4 * tot) + a(tot) + a(n * (8 if dims[2] > 1 else 4))
             + a(8 * K) + a(16 * K) + a(n) + a(8 * 256))
 
 
@@ -92,14 +92,15 @@ def _workspace_model(dims, h, K, tot, n_int):
     ((257, 131, 1), 8, (32, 16, 1), (3, 1, 0), 2),
     ((512, 512, 1), 24, (32, 32, 1), (2, 2, 0), 2),
     ((200, 150, 1), 48, (16, 16, 1), (2, 2, 0), 2),
+    ((64, 48, 40), 32, (8, 8, 8), (1, 1, 1), 3),
 ])
 def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, ndim):
     from oracle import dope as od
     p = _params(native, dims, conn, block, overlap, ndim=ndim)
     blocks = od.make_blocks(dims, block, overlap)
     n = dims[0] * dims[1] * dims[2]
-    h = {4: 2, 8: 4, 6: 3, 24: 12, 48: 24}[conn]
-    r = {24: 2, 48: 3}.get(conn, 1)
+    h = {4: 2, 8: 4, 6: 3, 24: 12, 48: 24, 32: 16}[conn]
+    r = {24: 2, 48: 3, 32: 2}.get(conn, 1)
     tot = sum(len(b.idx) for b in blocks)
     assert native.dope_workspace_bytes(ctypes.byref(p)) == _workspace_model(dims, h, len(blocks), tot,
                                                                      _interior_count(dims, block, overlap, r))
@@ -115,6 +116,7 @@ def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, n
     (dict(conn=48), "LDS"),                               # 32x32 blocks with 7x7 neighbourhoods: 209 B per node
     (dict(conn=48, block=(4, 4, 1), overlap=(2, 2, 0)), "stencil radius"),   # stride 2 < radius 3
     (dict(conn=24, ndim=3, dims=(16, 16, 16), block=(8, 8, 8), overlap=(1, 1, 1)), "connectivity"),
+    (dict(conn=32, ndim=3, dims=(64, 64, 64), block=(16, 16, 16), overlap=(1, 1, 1)), "LDS"),   # 141 B per node
 ])
 def test_create_rejects_bad_params(native, kw, msg):
     p = _params(native, **kw)
@@ -136,6 +138,7 @@ def test_autotune_is_a_pure_function_of_shape(native):
     assert autotune(3, (128, 128, 64), 6) == ((16, 16, 16), (1, 1, 1))
     assert autotune(2, (512, 512), 24) == ((32, 32, 1), (1, 1, 0))
     assert autotune(2, (512, 512), 48) == ((16, 16, 1), (1, 1, 0))
+    assert autotune(3, (128, 128, 64), 32) == ((8, 8, 8), (1, 1, 1))
     assert autotune(2, (512, 512), 8) == autotune(2, (512, 512), 8)
     with pytest.raises(Exception):
         autotune(2, (64, 64), 6)

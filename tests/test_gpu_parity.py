@@ -305,6 +305,8 @@ WIDE_CASES = [
     ((40, 33, 1), 48, (10, 10, 1), (3, 3, 0), 150, 1000),
     ((31, 26, 1), 48, (6, 6, 1), (3, 3, 0), 120, 800),      # stride 3 = radius
     ((3, 30, 1), 48, (3, 8, 1), (0, 3, 0), 150, 1000),      # grid narrower than the stencil
+    ((13, 11, 9), 32, (5, 5, 4), (1, 1, 1), 200, 5000),     # 3D ball of radius 2
+    ((9, 9, 8), 32, (4, 4, 4), (2, 2, 2), 150, 3000),       # stride 2 = radius: 8 copies at every corner
 ]
 
 
@@ -332,6 +334,15 @@ def test_wide_exhaustive_nonsubmodular():
     p = synth.random_problem(14, (16, 15, 1), 24, (4, 4, 1), (1, 1, 0), lam_q8=200, u_range=(-2000, 2000),
                              w_range=(0, 500), neg_frac=0.3, mu0=1000, solver="exhaustive")
     d, _, _ = run_parity(p, 4, "5x5 neighbourhood, 4x4 blocks, exhaustive")
+    d.close()
+
+
+def test_ball_kernel_volume_small_every_iteration():
+    """The spherical kernel of size 5 on a small version of the config3 volume."""
+    p = synth.config3_kernel5(dims=(40, 36, 20))
+    d, st_o, dec = run_parity(p, 5, "ball kernel 40x36x20")
+    assert np.array_equal(d.labels(), od.labels(st_o.Y))
+    assert d.energy() == od.energy_q(dec, od.labels(st_o.Y))
     d.close()
 
 

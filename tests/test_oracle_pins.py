@@ -64,6 +64,7 @@ TINY = [
     ((5, 4, 3), 6, (3, 2, 2), (1, 0, 0)),
     ((7, 7, 1), 24, (4, 4, 1), (1, 1, 0)),     # 5x5 neighbourhood, stride 3 >= radius 2
     ((8, 7, 1), 48, (5, 5, 1), (2, 2, 0)),     # 7x7 neighbourhood, stride 3 = radius 3
+    ((5, 4, 4), 32, (3, 3, 3), (1, 1, 1)),     # 3D ball of radius 2, stride 2 = radius
 ]
 
 
@@ -76,6 +77,17 @@ def test_square_neighbourhood_offsets(conn, r):
     square = [(dx, dy, 0) for dy in range(-r, r + 1) for dx in range(-r, r + 1) if (dx, dy) != (0, 0)]
     assert len(half) == len(set(half)) == (len(square)) // 2
     assert sorted(full) == sorted(square)
+
+
+def test_ball_neighbourhood_offsets():
+    """The spherical kernel of size 5 in 3D: the half-stencil and its negation partition the lattice points of
+    the radius-2 ball without its centre (32 neighbours)."""
+    half = dope.neighbour_offsets(3, 32)
+    full = half + [(-dx, -dy, -dz) for dx, dy, dz in half]
+    ball = [(x, y, z) for x in range(-2, 3) for y in range(-2, 3) for z in range(-2, 3)
+            if 0 < x * x + y * y + z * z <= 4]
+    assert len(ball) == 32 and len(half) == len(set(half)) == 16
+    assert sorted(full) == sorted(ball)
 
 
 # --------------------------------------------------------------------------------------------------------
@@ -371,7 +383,7 @@ def test_global_mincut_vs_bruteforce(seed):
 # --------------------------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("conn,dims", [(4, (7, 6, 1)), (8, (6, 6, 1)), (6, (4, 3, 3)), (24, (6, 5, 1)),
-                                       (48, (6, 6, 1))])
+                                       (48, (6, 6, 1)), (32, (4, 4, 3))])
 def test_single_block_is_global_cut(conn, dims):
     """K = 1: C = R = 0, so iteration 1 solves Eq. (3) exactly; y = y^ and the residual is 0 (stop at t = 1)."""
     p = tiny_problem(30, dims, conn, (0, 0, 0), (0, 0, 0))
