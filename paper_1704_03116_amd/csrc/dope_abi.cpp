@@ -36,7 +36,8 @@ struct dope_ctx {
     uint8_t *yhat = nullptr, *yslot = nullptr, *labels = nullptr;
     int64_t *resid = nullptr, *epart = nullptr;
     Ctl *hctl = nullptr;       // pinned host mirror of the control block
-    std::vector<int32_t> hbtab, hchunk, hblist;
+    std::vector<int32_t> hbtab, hchunk;
+    int64_t nbl = 0;   // boundary list entries
     dope::Img *dimg = nullptr;          // this context's descriptor (device)
     dope::Item *blk_items = nullptr, *chk_items = nullptr;
     dope::Queue *queue = nullptr;
@@ -208,45 +209,39 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
 
 thread_local std::string g_create_error;
 
-// blist = block-major indices of the copies that are not interior to their block (the consensus kernel's work;
-// interior copies are finished by the block-solve kernel); chunk[c] = block of blist entry c * CHUNK.
-// Highest block index along an axis whose interval contains coordinate x.
-int top_block(const dope::Axis &a, int x) { return std::min(x / a.s, a.nb - 1); }
-
-// blist: (block-major index, block) of the owner copy of every pixel that is not interior to its block, in
-// block-major order; the owner copy is the one in the block with the highest index along every axis.  chunk:
-// block of the first entry of every CHUNK entries.  Every block owns at least one such pixel when there are two
-// or more blocks, so the owners within a chunk are consecutive block indices (checked).
-bool build_tables(const Geom &g, const std::vector<int32_t> &btab, std::vector<int32_t> &blist,
-                  std::vector<int32_t> &chunk) {
-    blist.clear();
-    blist.reserve(2 * size_t(g.n - g.n_interior));
+// The boundary list (the consensus kernel's work; interior copies are finished by the block-solve kernel) holds
+// (block-major index, block) of the owner copy of every pixel that is not interior to its block, block by block
+// and in each block's local raster order; the owner copy is the one in the block with the highest index along
+// every axis.  The host computes, per block, how many such pixels it owns (a closed form: the owned box minus the
+// interior box) and where its entries start (btab[k][7]); the device writes the entries (launch_build_blist).
+// chunk: block of the first entry of every CHUNK entries.  Every block owns at least one such pixel when there
+// are two or more blocks, so the owners within a chunk are consecutive block indices (checked).
+bool build_tables(const Geom &g, std::vector<int32_t> &btab, int64_t &nbl, std::vector<int32_t> &chunk) {
+    nbl = 0;
+    chunk.clear();
     int64_t k = 0;
     for (int tz = 0; tz < g.ax[2].nb; ++tz)
         for (int ty = 0; ty < g.ax[1].nb; ++ty)
             for (int tx = 0; tx < g.ax[0].nb; ++tx, ++k) {
-                const int32_t *r = btab.data() + size_t(k) * dope::BTAB_STRIDE;
-                int32_t c = r[6];
-                for (int lz = 0; lz < r[5]; ++lz)
-                    for (int ly = 0; ly < r[4]; ++ly)
-                        for (int lx = 0; lx < r[3]; ++lx, ++c) {
-                            const int x = r[0] + lx, y = r[1] + ly, z = r[2] + lz;
-                            if (dope::is_interior(g, tx, ty, tz, x, y, z)) continue;
-                            if (top_block(g.ax[0], x) != tx || top_block(g.ax[1], y) != ty ||
-                                top_block(g.ax[2], z) != tz)
-                                continue;
-                            blist.push_back(c);
-                            blist.push_back(int32_t(k));
-                        }
+                const int t[3] = {tx, ty, tz};
+                int64_t owned = 1, inner = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const dope::Axis &ax = g.ax[a];
+                    const int32_t start = t[a] * ax.s;
+                    const int32_t olen = t[a] < ax.nb - 1 ? ax.s : ax.N - start;
+                    const int32_t ilen = std::max(0, dope::axis_interior_hi(ax, t[a], g.rad) -
+                                                         dope::axis_interior_lo(ax, t[a], g.rad));
+                    owned *= olen;
+                    inner *= ilen;
+                }
+                const int64_t cnt = owned - inner;
+                if (g.K > 1 && cnt < 1) return false;
+                btab[size_t(k) * dope::BTAB_STRIDE + 7] = int32_t(nbl);
+                for (int64_t e = (nbl + dope::CHUNK - 1) / dope::CHUNK * dope::CHUNK; e < nbl + cnt; e += dope::CHUNK)
+                    chunk.push_back(int32_t(k));
+                nbl += cnt;
             }
-    const size_t nbl = blist.size() / 2;
-    if (int64_t(nbl) != g.n - g.n_interior) return false;
-    for (size_t e = 1; e < nbl; ++e)
-        if (blist[2 * e + 1] - blist[2 * e - 1] > 1) return false;
-    const size_t nch = (nbl + dope::CHUNK - 1) / dope::CHUNK;
-    chunk.assign(nch, 0);
-    for (size_t ch = 0; ch < nch; ++ch) chunk[ch] = blist[2 * ch * dope::CHUNK + 1];
-    return true;
+    return nbl == g.n - g.n_interior;
 }
 
 dope_status fail(dope_ctx *c, dope_status s, const std::string &msg) {
@@ -308,7 +303,7 @@ dope::Img host_img(const dope_ctx *c) {
     im.ctl = c->ctl;
     im.summary = nullptr;
     im.n_chunks = int32_t(c->hchunk.size());
-    im.n_blist = int32_t(c->hblist.size() / 2);
+    im.n_blist = int32_t(c->nbl);
     return im;
 }
 
@@ -318,9 +313,7 @@ dope_status upload_tables(dope_ctx *c) {
     if (!c->hchunk.empty())
         HIP_TRY(c, hipMemcpyAsync(c->chunk_k0, c->hchunk.data(), c->hchunk.size() * 4, hipMemcpyHostToDevice,
                                   c->stream), "chunk table upload");
-    if (!c->hblist.empty())
-        HIP_TRY(c, hipMemcpyAsync(c->blist, c->hblist.data(), c->hblist.size() * 4, hipMemcpyHostToDevice,
-                                  c->stream), "boundary list upload");
+    if (c->nbl > 0) HIP_TRY(c, dope::launch_build_blist(c->g, c->btab, c->blist, c->stream), "boundary list");
     // one-image launch group: descriptor, work items, zeroed queue (staged in host memory that stays alive
     // until the synchronisation at the end of this function)
     const dope::Img im = host_img(c);
@@ -460,7 +453,7 @@ dope_status dope_create(const dope_params *p, dope_ctx **out) {
     c->p = q;
     c->g = g;
     c->hbtab.swap(bt);
-    if (!build_tables(c->g, c->hbtab, c->hblist, c->hchunk)) {
+    if (!build_tables(c->g, c->hbtab, c->nbl, c->hchunk)) {
         g_create_error = "internal: boundary pixel table inconsistent with the partition";
         delete c;
         return DOPE_EINVAL;

@@ -187,6 +187,9 @@ hipError_t launch_finalize_phase(const Group &grp, hipStream_t s);
 // validation verdict (status / halted set on the device when the energy is invalid) is taken by the next
 // launch_validate, launch_ctl_setup or launch_batch_setup.
 hipError_t launch_validate(Ctl *ctl, hipStream_t s);
+// Boundary list of one image (see the workspace layout): one workgroup per block writes the owner copies of the
+// block's non-interior pixels from the block's base entry btab[k][7].
+hipError_t launch_build_blist(const Geom &g, const int32_t *btab, int2 *blist, hipStream_t s);
 hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *cw,
                         int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
                         int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,

@@ -1039,6 +1039,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     const bool skip = spec && ctl_skip(im.ctl);
     GLOBAL int32_t *__restrict__ Y = gp(im.Y);
     __shared__ unsigned long long s_res[CONS_NT * MAXC];   // slot (owner block - kfirst) * MAXC + copy
+    __shared__ unsigned long long s_tr[CONS_NT / 64][MAXC][64];   // per wavefront: residual of copy q by lane
     __shared__ int s_ovf;
     const int tid = threadIdx.x;
     if (par < 0) par = ctl->t & 1;
@@ -1222,18 +1223,30 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
             r2[q] = (unsigned long long)(rr * rr);
         }
     }
-    // residual slots: one wavefront reduction per copy index when all lanes share an owner, else LDS atomics
+    // residual slots.  When all lanes of a wavefront share an owner block, the MAXC sums over the wavefront are
+    // taken through LDS: lanes write their MAXC residuals by copy index, then each group of G = 64 / MAXC lanes
+    // sums one copy index (MAXC values per lane, then log2 G shuffle steps).  Otherwise every lane adds its
+    // residuals to the slots with LDS atomics.
     {
         const int k0 = __shfl(kk, 0);
         const bool same = __all(kk == k0);
+        const int lane = tid & 63, wv = tid >> 6;
+        if (same) {
+            constexpr int G = 64 / MAXC;
 #pragma unroll
-        for (int q = 0; q < MAXC; ++q) {
-            if (same) {
-                const unsigned long long v = wave_sum64(r2[q]);   // one square (< 2^46) per lane
-                if ((tid & 63) == 63 && v) atomicAdd(&s_res[(k0 - kfirst) * MAXC + q], v);
-            } else if (r2[q]) {
-                atomicAdd(&s_res[(kk - kfirst) * MAXC + q], r2[q]);
-            }
+            for (int q = 0; q < MAXC; ++q) s_tr[wv][q][lane] = r2[q];
+            __builtin_amdgcn_wave_barrier();
+            const int q = lane / G, part = lane % G;
+            unsigned long long v = 0;
+#pragma unroll
+            for (int i = 0; i < MAXC; ++i) v += s_tr[wv][q][part * MAXC + i];
+#pragma unroll
+            for (int sft = G / 2; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft);
+            if (part == 0 && v) atomicAdd(&s_res[(k0 - kfirst) * MAXC + q], v);
+        } else {
+#pragma unroll
+            for (int q = 0; q < MAXC; ++q)
+                if (r2[q]) atomicAdd(&s_res[(kk - kfirst) * MAXC + q], r2[q]);
         }
     }
     if (ovf) s_ovf = 1;
@@ -1727,6 +1740,54 @@ hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_sr
         default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y,
                                     A0, A1, yhat, resid, ctl, si); break;
     }
+    return hipGetLastError();
+}
+
+// One workgroup per block: the owner copies of the block's pixels that are not interior to it, in the block's
+// local raster order (the owned box is a prefix of the block along every axis), from entry btab[k][7].  Ranks come
+// from wavefront ballots and a prefix over the four wavefronts of each 256-position pass.
+__global__ __launch_bounds__(256) void k_build_blist(Geom g, const int32_t *__restrict__ btab,
+                                                     int32_t *__restrict__ blist) {
+    __shared__ int s_wc[4];
+    const int k = blockIdx.x;
+    const int32_t *r = btab + int64_t(BTAB_STRIDE) * k;
+    const int t[3] = {k % g.ax[0].nb, (k / g.ax[0].nb) % g.ax[1].nb, k / (g.ax[0].nb * g.ax[1].nb)};
+    int ol[3], lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const Axis &ax = g.ax[a];
+        const int start = t[a] * ax.s;
+        ol[a] = t[a] < ax.nb - 1 ? ax.s : ax.N - start;
+        lo[a] = axis_interior_lo(ax, t[a], g.rad) - start;
+        hi[a] = axis_interior_hi(ax, t[a], g.rad) - start;
+    }
+    const int total = ol[0] * ol[1] * ol[2];
+    const int ex = r[3], ey = r[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int run = r[7];
+    for (int b = 0; b < total; b += 256) {
+        const int i = b + tid;
+        const int lx = i % ol[0], rr = i / ol[0], ly = rr % ol[1], lz = rr / ol[1];
+        const bool inner = lx >= lo[0] && lx < hi[0] && ly >= lo[1] && ly < hi[1] && lz >= lo[2] && lz < hi[2];
+        const bool flag = i < total && !inner;
+        const unsigned long long m = __ballot(flag);
+        if (lane == 0) s_wc[wv] = __popcll(m);
+        __syncthreads();
+        int off = run;
+        for (int w = 0; w < wv; ++w) off += s_wc[w];
+        if (flag) {
+            const int e = off + __popcll(m & ((1ull << lane) - 1));
+            blist[2 * int64_t(e)] = r[6] + lx + ex * (ly + ey * lz);
+            blist[2 * int64_t(e) + 1] = k;
+        }
+        run += s_wc[0] + s_wc[1] + s_wc[2] + s_wc[3];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_build_blist(const Geom &g, const int32_t *btab, int2 *blist, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_blist, dim3(unsigned(g.K)), dim3(256), 0, s, g, btab,
+                       reinterpret_cast<int32_t *>(blist));
     return hipGetLastError();
 }
 
