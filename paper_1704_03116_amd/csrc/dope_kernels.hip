@@ -13,9 +13,12 @@
 //                       per-block residual of the stopping rule.
 //   k_finalize          loop control: max_k r_k, stopping rule, errors, mu and t.
 //   k_labels, k_energy  labels [Y > 1/2] and the Eq. (1) energy.
+//   k_build_blist       the consensus work list (owner copies of the pixels not interior to their block).
+//   k_setup_batch, k_labels_batch, k_batch_setup, k_ctl_setup: the same set-up and outputs over a batch.
 //
-// All arithmetic is integer; every kernel checks the device loop control, so the host can enqueue several
-// iterations ahead of the stopping rule without reading anything back.
+// Every kernel is a template over the stencil (CONN): 4- and 8-connected, 5x5 and 7x7 squares in 2D; 6-connected
+// and the radius-2 ball in 3D.  All arithmetic is integer; every kernel checks the device loop control, so the
+// host can enqueue several iterations ahead of the stopping rule without reading anything back.
 #include "dope_internal.h"
 
 #include <hip/hip_ext.h>

@@ -117,6 +117,8 @@ def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, n
     (dict(conn=48, block=(4, 4, 1), overlap=(2, 2, 0)), "stencil radius"),   # stride 2 < radius 3
     (dict(conn=24, ndim=3, dims=(16, 16, 16), block=(8, 8, 8), overlap=(1, 1, 1)), "connectivity"),
     (dict(conn=32, ndim=3, dims=(64, 64, 64), block=(16, 16, 16), overlap=(1, 1, 1)), "LDS"),   # 141 B per node
+    (dict(dims=(32768, 32768, 1)), "grid too large"),      # 2^30 pixels: 32-bit byte offsets no longer suffice
+    (dict(conn=6, ndim=3, dims=(1024, 1024, 512), block=(16, 16, 16), overlap=(1, 1, 1)), "grid too large"),
 ])
 def test_create_rejects_bad_params(native, kw, msg):
     p = _params(native, **kw)
