@@ -19,6 +19,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# int32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane and clock
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+EXH_OPS_PER_CODE = 15
+
+
+def exhaustive_codes(dims, block, overlap):
+    """Labellings enumerated per iteration: sum over blocks of 2^|block| (partition rule of the block layout)."""
+    ext = []
+    for N, B, o in zip(dims, block, overlap):
+        if B <= 0 or B >= N:
+            ext.append([N])
+            continue
+        s = B - o
+        count = 1 + -(-(N - B) // s)
+        ext.append([min(B, N - t * s) for t in range(count)])
+    return sum(2 ** (a * b * c) for c in ext[2] for b in ext[1] for a in ext[0])
 
 
 def workload(name, seed=0):
@@ -235,6 +251,12 @@ def main():
         # per boundary copy: block label 1 + A 4 read, A 4 written; per boundary pixel: weights 4h read, Y 4 written
         "k_consensus_one": (n_bl * 9 + (n - n_int) * (4 * h + 4), prof["consensus_ms"], prof["consensus_launches"]),
     }
+    if p.solver == "exhaustive":
+        # enumeration of every labelling of every block: 2^|block| codes, about 15 integer operations per Gray-code
+        # step (bit flip, unary, the in-block edge deltas, energy update, compare-and-select); VALU-bound
+        del kernels["k_block_solve_one"]
+        kernels["k_block_exhaustive"] = (exhaustive_codes(p.dims, p.block, p.overlap) * EXH_OPS_PER_CODE,
+                                         prof["solve_ms"], prof["solve_launches"])
     traffic = measured_traffic(p.name)
 
     # Every step runs the same number of iterations (same input); launches beyond that were enqueued after the
@@ -242,14 +264,17 @@ def main():
     working = info["iters_done"] * args.steps
 
     def roof(name):
-        nbytes, ms, launches = kernels[name]
+        amount, ms, launches = kernels[name]
         avg_ms = ms / max(launches, 1)
-        achieved = nbytes * min(working, launches) / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic.get(name),
-                "avg_launch_ms": round(avg_ms, 5), "launches": launches, "working_launches": min(working, launches),
-                "bytes_per_launch": int(nbytes), "total_ms": round(ms, 4),
-                "event_pass_ms_per_step": round(prof_elapsed * 1e3 / args.steps, 4)}
+        alu = name == "k_block_exhaustive"
+        scale, peak, unit = (1e12, ALU_PEAK_TOPS, "TOP/s") if alu else (1e9, HBM_PEAK_GBS, "GB/s")
+        achieved = amount * min(working, launches) / (ms * 1e-3) / scale if ms > 0 else 0.0
+        r = {"bound": "alu" if alu else "hbm", "kernel": name, "achieved": round(achieved, 3 if alu else 2),
+             "peak": peak, "unit": unit, "frac": round(achieved / peak, 5), "traffic": traffic.get(name),
+             "avg_launch_ms": round(avg_ms, 5), "launches": launches, "working_launches": min(working, launches)}
+        r["ops_per_launch" if alu else "bytes_per_launch"] = int(amount)
+        r.update({"total_ms": round(ms, 4), "event_pass_ms_per_step": round(prof_elapsed * 1e3 / args.steps, 4)})
+        return r
 
     names = sorted(kernels, key=lambda k: -kernels[k][1])
     out = {

@@ -925,8 +925,11 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
                 const int3 v = full_dir<CONN>(d);
-                s_nj[wave][p][d] = int8_t(p + v.x + ex * (v.y + ey * v.z));
-                s_nc[wave][p][d] = (d < H && ((m >> d) & 1u)) ? cp[d] : 0;
+                // an absent neighbour points at the pixel itself with capacity 0, so the enumeration can use
+                // every direction without a test
+                const bool inb = (m >> d) & 1u;
+                s_nj[wave][p][d] = int8_t(inb ? p + v.x + ex * (v.y + ey * v.z) : p);
+                s_nc[wave][p][d] = (d < H && inb) ? cp[d] : 0;
             }
         }
     }
@@ -943,8 +946,9 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
     if (!live) return;
     const int L = np > 6 ? np - 6 : 0;               // enumerated low bits per lane
     const int lanes_used = 1 << (np - L);
+    // The minimiser with the smallest code is the smallest key E * 2^16 + code (codes are below 2^16 and
+    // |E| < 2^35), so one 64-bit minimum keeps both the energy order and the tie rule.
     int64_t best = INT64_MAX;
-    uint32_t bestc = 0xFFFFFFFFu;
     if (lane < lanes_used) {
         uint32_t x = uint32_t(lane) << L;
         int64_t E = 0;
@@ -960,29 +964,67 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
                 }
             }
         }
-        best = E;
-        bestc = x;
+        int64_t key = E * 65536 + int64_t(x);
+        best = key;
         const uint32_t cnt = 1u << L;
-        for (uint32_t gi = 1; gi < cnt; ++gi) {
-            const int b = __builtin_ctz(gi);
-            const int xb = (x >> b) & 1;
+        // Gray-code step gi flips bit b = ctz(gi); E changes by +-t with t = U_b + sum_j (x_j ? -c_bj : c_bj)
+        // = S_b - 2 sum_j (x_j ? c_bj : 0), S_b = U_b + sum_j c_bj, all below 2^31 in magnitude (|U_b| <= sum |c|
+        // + 1 after the clamp above, sum |c| < 2^29); the key changes by +-(t 2^16 + 2^b)
+        auto flip = [&](int b, int32_t sb, const int32_t *cb, const int *jb) {
+            int32_t acc = 0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) acc += cb[d] & -int32_t((x >> jb[d]) & 1u);
+            const int64_t dk = int64_t(sb - 2 * acc) * 65536 + (int64_t(1) << b);
+            key += ((x >> b) & 1u) ? -dk : dk;
             x ^= 1u << b;
-            int64_t t = s_U[wave][b];
+            best = key < best ? key : best;
+        };
+        auto flip_lds = [&](int b) {
+            int32_t cb[ND];
+            int jb[ND];
+            int32_t sb = s_U[wave][b];
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
-                const int32_t c = s_nc[wave][b][d];
-                if (c != 0) t += ((x >> s_nj[wave][b][d]) & 1u) ? -int64_t(c) : int64_t(c);
+                cb[d] = s_nc[wave][b][d];
+                jb[d] = s_nj[wave][b][d];
+                sb += cb[d];
             }
-            E += xb ? -t : t;
-            if (E < best || (E == best && x < bestc)) { best = E; bestc = x; }
+            flip(b, sb, cb, jb);
+        };
+        constexpr int RB = 4;   // low bits whose data stays in registers
+        if (ND <= 8 && L >= RB) {
+            // fifteen of every sixteen steps flip one of bits 0..3 (ruler sequence 0 1 0 2 0 1 0 3 0 1 0 2 0 1 0,
+            // then ctz >= 4): their data stays in registers, so one step in sixteen reads the block's LDS tables
+            int32_t sr[RB], cr[RB][ND];
+            int jr[RB][ND];
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                sr[b] = s_U[wave][b];
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    cr[b][d] = s_nc[wave][b][d];
+                    jr[b][d] = s_nj[wave][b][d];
+                    sr[b] += cr[b][d];
+                }
+            }
+            for (uint32_t gb = 0; gb < cnt; gb += 16) {
+#pragma unroll
+                for (int i = 1; i < 16; ++i) {
+                    const int b = __builtin_ctz(i);
+                    flip(b, sr[b], cr[b], jr[b]);
+                }
+                if (gb + 16 < cnt) flip_lds(__builtin_ctz(gb + 16));
+            }
+        } else {
+            for (uint32_t gi = 1; gi < cnt; ++gi) flip_lds(__builtin_ctz(gi));
         }
     }
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) {
-        const int64_t oE = __shfl_xor(best, s);
-        const uint32_t oc = __shfl_xor(bestc, s);
-        if (oE < best || (oE == best && oc < bestc)) { best = oE; bestc = oc; }
+        const int64_t o = __shfl_xor(best, s);
+        best = o < best ? o : best;
     }
+    const uint32_t bestc = uint32_t(best & 0xFFFF);
     unsigned long long r2 = 0;
     if (lane < np) {
         const int yv = int((bestc >> lane) & 1u);
