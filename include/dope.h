@@ -71,11 +71,11 @@ enum { DOPE_MEM_HOST = 0, DOPE_MEM_DEVICE = 1 };
 typedef struct {
     int32_t ndim;              /* 2 or 3                                                                  */
     int32_t dims[3];           /* W, H, D (D = 1 in 2D)                                                  */
-    int32_t connectivity;      /* 4, 8, 24 (5x5 square) or 48 (7x7 square) in 2D; 6 or 32 (ball of     */
-                               /* radius 2) in 3D                                                        */
+    int32_t connectivity;      /* 4, 8, 24 (5x5 square), 48 (7x7 square) or 80 (9x9 square) in 2D;    */
+                               /* 6 or 32 (ball of radius 2) in 3D                                       */
     int32_t block[3];          /* block edge B per axis                                                  */
     int32_t overlap[3];        /* overlap o per axis; B - o must be at least the stencil radius (2 for  */
-                               /* connectivity 24 and 32, 3 for 48) on every axis with more than one   */
+                               /* connectivity 24 and 32, 3 for 48, 4 for 80) on every axis with more  */
                                /* block                                                                  */
     int64_t mu0;               /* initial mu, 1 <= mu0 <= 2^24 - 1, input-energy units                   */
     int32_t mu_fact_num;       /* mu_fact = num / den (default 21 / 20)                                   */
@@ -102,8 +102,8 @@ dope_status dope_create(const dope_params *p, dope_ctx **out);
  * M = mu0, t = 0.
  *   u: int32[n]; w: int32[h * n], offset-major over the half-stencil
  *      2D: (+1,0), (0,+1), then for 8-connectivity (+1,+1), (-1,+1); 3D: (+1,0,0), (0,+1,0), (0,0,+1);
- *      2D squares of radius r (connectivity 24: r = 2, 48: r = 3, the larger neighbourhoods of the paper's
- *      experiments): (dx,0) for dx = 1..r, then (dx,dy) for dy = 1..r and dx = -r..r, x fastest;
+ *      2D squares of radius r (connectivity 24: r = 2, 48: r = 3, 80: r = 4, the larger neighbourhoods of the
+ *      paper's experiments): (dx,0) for dx = 1..r, then (dx,dy) for dy = 1..r and dx = -r..r, x fastest;
  *      3D ball of radius 2 (connectivity 32, the spherical kernel of size 5): the offsets of length <= 2 whose
  *      first nonzero coordinate, from z down to x, is positive, ordered by z, then y, then x.
  *      w[o*n + i] weights the edge i <-> i + offset[o] and must be 0 where that neighbour is off-grid.
@@ -173,9 +173,10 @@ dope_status dope_profile_read(dope_ctx *ctx, double *solve_ms, int32_t *solve_la
 /* Block partition for an image: a pure function of (ndim, dims, connectivity), never of load, so that a
  * request's result does not depend on what else is running.  Chosen from measured MI355X throughput of the
  * max-flow path: 8- and 4-connected 2D images use 16x16 blocks with 1-pixel overlap when the shorter side is
- * at most 256 pixels and 32x32 blocks with 1-pixel overlap otherwise (the same for 5x5 neighbourhoods; 7x7
- * neighbourhoods always use 16x16 blocks, since larger ones exceed the LDS); 6-connected 3D volumes use 16^3
- * blocks with 1-voxel overlap, radius-2 balls 8^3 blocks with 1-voxel overlap.  Writes block[3] and overlap[3]; EINVAL for an unsupported stencil. */
+ * at most 256 pixels and 32x32 blocks with 1-pixel overlap otherwise (the same for 5x5 neighbourhoods; 7x7 and
+ * 9x9 neighbourhoods always use 16x16 blocks, since larger ones exceed the LDS); 6-connected 3D volumes use
+ * 16^3 blocks with 1-voxel overlap, radius-2 balls 8^3 blocks with 1-voxel overlap.  Writes block[3] and
+ * overlap[3]; EINVAL for an unsupported stencil. */
 dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectivity, int32_t block[3],
                           int32_t overlap[3]);
 

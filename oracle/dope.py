@@ -126,13 +126,13 @@ def subproblem_objective(un, ea, eb, cap, x) -> int:
 
 def neighbour_offsets(ndim: int, conn: int):
     """Half-stencil offsets: each undirected edge i <-> i + offset once (the neighbourhood of Sec. 1's grid
-    graphs; the experiments' square kernels of size 3, 5 and 7 in 2D are conn 8, 24 and 48)."""
+    graphs; the experiments' square kernels of size 3, 5, 7 and 9 in 2D are conn 8, 24, 48 and 80)."""
     if ndim == 2 and conn == 4:
         return [(1, 0, 0), (0, 1, 0)]
     if ndim == 2 and conn == 8:
         return [(1, 0, 0), (0, 1, 0), (1, 1, 0), (-1, 1, 0)]
-    if ndim == 2 and conn in (24, 48):
-        r = 2 if conn == 24 else 3
+    if ndim == 2 and conn in (24, 48, 80):
+        r = {24: 2, 48: 3, 80: 4}[conn]
         # every offset of the (2r+1)^2 square whose first nonzero coordinate, taken from y down to x, is positive
         return [(dx, 0, 0) for dx in range(1, r + 1)] + \
                [(dx, dy, 0) for dy in range(1, r + 1) for dx in range(-r, r + 1)]

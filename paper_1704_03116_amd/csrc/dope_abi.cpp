@@ -95,19 +95,20 @@ int half_stencil_size(int ndim, int conn) {
     if (ndim == 2 && conn == 8) return 4;
     if (ndim == 2 && conn == 24) return 12;   // 5x5 square neighbourhood
     if (ndim == 2 && conn == 48) return 24;   // 7x7 square neighbourhood
+    if (ndim == 2 && conn == 80) return 40;   // 9x9 square neighbourhood
     if (ndim == 3 && conn == 6) return 3;
     if (ndim == 3 && conn == 32) return 16;   // ball of radius 2 (32 neighbours)
     return 0;
 }
 
-int stencil_radius(int conn) { return (conn == 24 || conn == 32) ? 2 : (conn == 48 ? 3 : 1); }
+int stencil_radius(int conn) { return (conn == 24 || conn == 32) ? 2 : (conn == 48 ? 3 : (conn == 80 ? 4 : 1)); }
 
 // Builds the partition; returns an empty string on success or a message.
 std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab) {
     if (!p) return "null params";
     if (p->ndim != 2 && p->ndim != 3) return "ndim must be 2 or 3";
     const int hs = half_stencil_size(p->ndim, p->connectivity);
-    if (!hs) return "connectivity must be 4, 8, 24 or 48 in 2D and 6 or 32 in 3D";
+    if (!hs) return "connectivity must be 4, 8, 24, 48 or 80 in 2D and 6 or 32 in 3D";
     int32_t dims[3] = {p->dims[0], p->dims[1], p->ndim == 3 ? p->dims[2] : 1};
     if (p->ndim == 2 && p->dims[2] != 1 && p->dims[2] != 0) return "dims[2] must be 1 in 2D";
     int64_t n = 1;
@@ -491,8 +492,8 @@ dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectiv
         return DOPE_OK;
     }
     const int32_t short_side = std::min(dims[0], dims[1]);
-    // 7x7 neighbourhoods: 32x32 blocks would exceed the LDS (209 bytes per node)
-    const int32_t B = (short_side <= 256 || connectivity == 48) ? 16 : 32;
+    // 7x7 and 9x9 neighbourhoods: 32x32 blocks would exceed the LDS (209 and 345 bytes per node)
+    const int32_t B = (short_side <= 256 || connectivity == 48 || connectivity == 80) ? 16 : 32;
     block[0] = block[1] = B;
     overlap[0] = overlap[1] = 1;
     block[2] = 1;

@@ -22,7 +22,7 @@ inline Axis make_axis(int32_t N, int32_t B, int32_t s, int32_t nb) {
 struct Geom {
     Axis ax[3];
     int32_t W, H, D;
-    int32_t conn;       // 2D: 4, 8, 24 (5x5), 48 (7x7); 3D: 6, 32 (radius-2 ball)
+    int32_t conn;       // 2D: 4, 8, 24 (5x5), 48 (7x7), 80 (9x9); 3D: 6, 32 (radius-2 ball)
     int32_t hs;         // half-stencil size
     int32_t rad;        // stencil radius: every neighbour offset lies in [-rad, rad] per axis
     int32_t K;          // number of blocks
@@ -103,14 +103,16 @@ constexpr int64_t CAP_SUM_LIMIT = int64_t(1) << 29;
 constexpr int BTAB_STRIDE = 8;     // x0, y0, z0, ex, ey, ez, offset, pad
 
 // Bytes of the per-node mask of live in-block directions (one bit per full-stencil direction).
-inline __host__ __device__ constexpr int dir_mask_bytes(int hs) { return 2 * hs <= 8 ? 1 : (2 * hs <= 32 ? 4 : 8); }
+inline __host__ __device__ constexpr int dir_mask_bytes(int hs) {
+    return 2 * hs <= 8 ? 1 : (2 * hs <= 32 ? 4 : (2 * hs <= 64 ? 8 : 16));
+}
 
 // LDS bytes of the max-flow block kernel for a block of np pixels and half-stencil size hs: a 64-byte header,
 // capacity and flow per half-edge, unary/excess, height, free list, direction mask (aligned to its size) and
 // state bits per node.
 inline size_t maxflow_lds_bytes(int np, int hs) {
     const int mb = dir_mask_bytes(hs);
-    return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 1 ? 8 : 0);
+    return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 8 ? 16 : (mb > 1 ? 8 : 0));
 }
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
 constexpr int NUM_CUS = 256;          // MI355X compute units

@@ -53,19 +53,22 @@ enum : uint8_t { ST_FIXED = 1, ST_LABEL = 2, ST_MARK = 8 };
 constexpr int16_t H_INF = 0x7FFF;
 
 // Stencils: H half-edges per pixel, radius R (every offset lies in [-R, R] per axis), grid dimension NDIM.
-// CONN 24 and 48 are the square 5x5 and 7x7 neighbourhoods of a 2D grid, CONN 32 the radius-2 ball of a 3D grid
-// (the spherical kernel of size 5).
+// CONN 24, 48 and 80 are the square 5x5, 7x7 and 9x9 neighbourhoods of a 2D grid, CONN 32 the radius-2 ball of a
+// 3D grid (the spherical kernel of size 5).
 template <int CONN> struct Sten;
 template <> struct Sten<4> { static constexpr int H = 2, R = 1, NDIM = 2; };
 template <> struct Sten<8> { static constexpr int H = 4, R = 1, NDIM = 2; };
 template <> struct Sten<24> { static constexpr int H = 12, R = 2, NDIM = 2; };
 template <> struct Sten<48> { static constexpr int H = 24, R = 3, NDIM = 2; };
+template <> struct Sten<80> { static constexpr int H = 40, R = 4, NDIM = 2; };
 template <> struct Sten<6> { static constexpr int H = 3, R = 1, NDIM = 3; };
 template <> struct Sten<32> { static constexpr int H = 16, R = 2, NDIM = 3; };
 
 // One bit per full-stencil direction.
 template <int CONN>
-using DirMask = typename std::conditional<(2 * Sten<CONN>::H <= 32), uint32_t, uint64_t>::type;
+using DirMask = typename std::conditional<
+    (2 * Sten<CONN>::H <= 32), uint32_t,
+    typename std::conditional<(2 * Sten<CONN>::H <= 64), uint64_t, unsigned __int128>::type>::type;
 // The per-node copy of that mask in LDS (see dir_mask_bytes).
 template <int CONN>
 using LdsMask = typename std::conditional<(2 * Sten<CONN>::H <= 8), uint8_t, DirMask<CONN>>::type;
@@ -82,7 +85,7 @@ __device__ __forceinline__ int3 half_off(int o) {
             default: return make_int3(-1, 1, 0);
         }
     }
-    if (CONN == 24 || CONN == 48) {
+    if (CONN == 24 || CONN == 48 || CONN == 80) {
         // (dx, 0) for dx = 1..R, then (dx, dy) for dy = 1..R and dx = -R..R (x fastest)
         constexpr int R = Sten<CONN>::R;
         if (o < R) return make_int3(o + 1, 0, 0);
@@ -1782,6 +1785,8 @@ hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_sr
                                     A1, yhat, resid, ctl, si); break;
         case 32: hipLaunchKernelGGL(k_setup<32>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
                                     A1, yhat, resid, ctl, si); break;
+        case 80: hipLaunchKernelGGL(k_setup<80>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
+                                    A1, yhat, resid, ctl, si); break;
         default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y,
                                     A0, A1, yhat, resid, ctl, si); break;
     }
@@ -1845,6 +1850,7 @@ hipError_t launch_setup_batch(int32_t conn, const Img *imgs, const SetupArg *arg
         case 24: hipLaunchKernelGGL(k_setup_batch<24>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
         case 48: hipLaunchKernelGGL(k_setup_batch<48>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
         case 32: hipLaunchKernelGGL(k_setup_batch<32>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
+        case 80: hipLaunchKernelGGL(k_setup_batch<80>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
         default: hipLaunchKernelGGL(k_setup_batch<6>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
     }
     return hipGetLastError();
@@ -1875,6 +1881,7 @@ hipError_t launch_solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hi
         case 24: return solve_phase<24>(grp, s, e0, e1);
         case 48: return solve_phase<48>(grp, s, e0, e1);
         case 32: return solve_phase<32>(grp, s, e0, e1);
+        case 80: return solve_phase<80>(grp, s, e0, e1);
         default: return solve_phase<6>(grp, s, e0, e1);
     }
 }
@@ -1899,6 +1906,7 @@ hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0
         case 24: consensus_launch<24>(grp, s, e0, e1); break;
         case 48: consensus_launch<48>(grp, s, e0, e1); break;
         case 32: consensus_launch<32>(grp, s, e0, e1); break;
+        case 80: consensus_launch<80>(grp, s, e0, e1); break;
         default: consensus_launch<6>(grp, s, e0, e1); break;
     }
     return hipGetLastError();
@@ -1939,6 +1947,7 @@ hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *cw, con
         case 24: hipLaunchKernelGGL(k_energy<24>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
         case 48: hipLaunchKernelGGL(k_energy<48>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
         case 32: hipLaunchKernelGGL(k_energy<32>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
+        case 80: hipLaunchKernelGGL(k_energy<80>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
         default: hipLaunchKernelGGL(k_energy<6>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
     }
     hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s, part, int(wgs), ctl);

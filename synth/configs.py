@@ -29,8 +29,8 @@ def half_stencil(ndim: int, conn: int) -> List[Tuple[int, int, int]]:
         return [(1, 0, 0), (0, 1, 0)]
     if ndim == 2 and conn == 8:
         return [(1, 0, 0), (0, 1, 0), (1, 1, 0), (-1, 1, 0)]
-    if ndim == 2 and conn in (24, 48):   # 5x5 and 7x7 squares: (dx, 0) for dx = 1..r, then rows dy = 1..r
-        r = 2 if conn == 24 else 3
+    if ndim == 2 and conn in (24, 48, 80):   # 5x5, 7x7, 9x9 squares: (dx, 0) for dx = 1..r, then rows dy = 1..r
+        r = {24: 2, 48: 3, 80: 4}[conn]
         out = [(dx, 0, 0) for dx in range(1, r + 1)]
         for dy in range(1, r + 1):
             for dx in range(-r, r + 1):
@@ -251,15 +251,15 @@ def config5_trace(n_requests: int = 2000, mean_gap_s: float = 0.005, seed: int =
 
 
 def config_kernel(k: int, seed: int = 0, W: int = 512, H: int = 512, mu0: int = DEFAULT_MU0_2D) -> Problem:
-    """The image of config2 with the k x k square neighbourhood (k = 5 or 7) of the paper's larger-kernel
+    """The image of config2 with the k x k square neighbourhood (k = 5, 7 or 9) of the paper's larger-kernel
     experiments: contrast weights on every offset of the square (scale 1000, divided by the offset's length);
-    lambda = 0.5 (k = 5) or 0.6 (k = 7), which keep the total smoothing per pixel at or below config2's and
-    converge within a few iterations (with k = 5 and lambda = 1 a pixel keeps oscillating between its blocks
-    and the stopping rule never holds in 50 iterations); 32x32 blocks with o = 2 for k = 5 and 16x16 blocks with
-    o = 2 for k = 7 (LDS per block node grows with the stencil)."""
-    if k not in (5, 7):
-        raise ValueError("k must be 5 or 7")
-    conn = 24 if k == 5 else 48
+    lambda = 0.5 (k = 5), 0.6 (k = 7) or 0.4 (k = 9), which keep the total smoothing per pixel at or below
+    config2's and converge within a few iterations (with k = 5 and lambda = 1 a pixel keeps oscillating between its
+    blocks and the stopping rule never holds in 50 iterations); 32x32 blocks with o = 2 for k = 5, 16x16 blocks
+    with o = 2 for k = 7 and 9 (LDS per block node grows with the stencil)."""
+    if k not in (5, 7, 9):
+        raise ValueError("k must be 5, 7 or 9")
+    conn = {5: 24, 7: 48, 9: 80}[k]
     rng = np.random.default_rng(seed)
     fg = _ellipse_mask(rng, W, H, 5)
     base = np.where(fg, 0.7, 0.3)[:, :, None]
@@ -268,7 +268,7 @@ def config_kernel(k: int, seed: int = 0, W: int = 512, H: int = 512, mu0: int = 
     w = _weights_from_features(img[None], 2, conn, 0.1)
     B = 32 if k == 5 else 16
     return Problem(f"kernel{k}_ellipses{W}x{H}_{conn}conn", (W, H, 1), 2, conn, u.astype(np.int32), w,
-                   lambda_q8(0.5 if k == 5 else 0.6), (B, B, 1), (2, 2, 0), mu0,
+                   lambda_q8({5: 0.5, 7: 0.6, 9: 0.4}[k]), (B, B, 1), (2, 2, 0), mu0,
                    truth=fg.reshape(-1).astype(np.uint8))
 
 

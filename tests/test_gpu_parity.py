@@ -307,6 +307,8 @@ WIDE_CASES = [
     ((3, 30, 1), 48, (3, 8, 1), (0, 3, 0), 150, 1000),      # grid narrower than the stencil
     ((13, 11, 9), 32, (5, 5, 4), (1, 1, 1), 200, 5000),     # 3D ball of radius 2
     ((9, 9, 8), 32, (4, 4, 4), (2, 2, 2), 150, 3000),       # stride 2 = radius: 8 copies at every corner
+    ((41, 35, 1), 80, (12, 12, 1), (2, 2, 0), 100, 1000),   # 9x9 neighbourhood
+    ((29, 23, 1), 80, (6, 6, 1), (2, 2, 0), 80, 800),       # 9x9, stride 4 = radius
 ]
 
 
@@ -319,7 +321,7 @@ def test_wide_stencils_every_iteration(case):
     d.close()
 
 
-@pytest.mark.parametrize("k,W,H", [(5, 100, 90), (7, 90, 70)])
+@pytest.mark.parametrize("k,W,H", [(5, 100, 90), (7, 90, 70), (9, 80, 75)])
 def test_kernel_workloads_small_every_iteration(k, W, H):
     """The larger-kernel workloads (contrast weights on the 5x5 / 7x7 square) on small grids."""
     p = synth.config_kernel(k, W=W, H=H)
@@ -352,6 +354,10 @@ def test_kernel5_full_size_sampled():
 
 def test_kernel7_full_size_sampled():
     sampled_parity(synth.config_kernel(7), 2, 40, "kernel7 512x512")
+
+
+def test_kernel9_full_size_sampled():
+    sampled_parity(synth.config_kernel(9), 2, 40, "kernel9 512x512")
 
 
 def test_batch_wide_stencil_matches_alone():

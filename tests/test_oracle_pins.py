@@ -65,10 +65,11 @@ TINY = [
     ((7, 7, 1), 24, (4, 4, 1), (1, 1, 0)),     # 5x5 neighbourhood, stride 3 >= radius 2
     ((8, 7, 1), 48, (5, 5, 1), (2, 2, 0)),     # 7x7 neighbourhood, stride 3 = radius 3
     ((5, 4, 4), 32, (3, 3, 3), (1, 1, 1)),     # 3D ball of radius 2, stride 2 = radius
+    ((9, 8, 1), 80, (6, 6, 1), (2, 2, 0)),     # 9x9 neighbourhood, stride 4 = radius 4
 ]
 
 
-@pytest.mark.parametrize("conn,r", [(24, 2), (48, 3)])
+@pytest.mark.parametrize("conn,r", [(24, 2), (48, 3), (80, 4)])
 def test_square_neighbourhood_offsets(conn, r):
     """The larger neighbourhoods of the experiments (square kernels of size 5 and 7): the half-stencil and its
     negation partition the (2r+1)^2 square without its centre, so every undirected edge appears exactly once."""
@@ -383,7 +384,7 @@ def test_global_mincut_vs_bruteforce(seed):
 # --------------------------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("conn,dims", [(4, (7, 6, 1)), (8, (6, 6, 1)), (6, (4, 3, 3)), (24, (6, 5, 1)),
-                                       (48, (6, 6, 1)), (32, (4, 4, 3))])
+                                       (48, (6, 6, 1)), (32, (4, 4, 3)), (80, (6, 5, 1))])
 def test_single_block_is_global_cut(conn, dims):
     """K = 1: C = R = 0, so iteration 1 solves Eq. (3) exactly; y = y^ and the residual is 0 (stop at t = 1)."""
     p = tiny_problem(30, dims, conn, (0, 0, 0), (0, 0, 0))
