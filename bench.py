@@ -49,8 +49,8 @@ def workload(name, seed=0):
         return synth.config4(seed=seed)
     if name in ("kernel5", "kernel7", "kernel9"):   # the config2 image with 5x5 / 7x7 / 9x9 neighbourhoods
         return synth.config_kernel(int(name[-1]), seed=seed)
-    if name == "kernel5_3d":              # the config3 volume with the radius-2 ball
-        return synth.config3_kernel5(seed=seed)
+    if name in ("kernel5_3d", "kernel7_3d"):   # the config3 volume with the radius-2 / radius-3 ball
+        return synth.config3_kernel5(seed=seed, k=int(name[6]))
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -242,7 +242,7 @@ def main():
     value = p.n * args.steps / elapsed / 1e6
 
     K, tot, h, n = d.K, d.tot, d.h, p.n
-    n_int = interior_count(p.dims, p.block, p.overlap, {24: 2, 48: 3, 32: 2, 80: 4}.get(p.conn, 1))
+    n_int = interior_count(p.dims, p.block, p.overlap, {24: 2, 48: 3, 32: 2, 80: 4, 122: 3}.get(p.conn, 1))
     n_bl = tot - n_int
     kernels = {
         # per block pixel: u 4 + weights 4h + Y 4 + A 4 read, block label 1 written; per interior pixel (finished

@@ -7,7 +7,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdope.so")
-SOURCES = ["dope_kernels.hip", "dope_abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code (no float arithmetic is on this path anyway).
@@ -16,10 +15,34 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wal
          "-I", os.path.join(ROOT, "include")]
 
 
+# Stencils whose kernels are compiled in a translation unit of their own (dope_kernels.hip with DOPE_CONN set),
+# so that the build runs in parallel; the unit without DOPE_CONN holds the launchers and the stencil-free kernels.
+STENCILS = [4, 8, 24, 48, 80, 6, 32, 122]
+
+
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    kern = os.path.join(CSRC, "dope_kernels.hip")
+    units = [([kern], "dope_kernels_main.o", [])] + \
+            [([kern], f"dope_kernels_{c}.o", [f"-DDOPE_CONN={c}"]) for c in STENCILS] + \
+            [([os.path.join(CSRC, "dope_abi.cpp")], "dope_abi.o", [])]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+
+    def compile_one(unit):
+        srcs, obj, extra = unit
+        cmd = [HIPCC] + compile_flags + extra + ["-c", "-o", os.path.join(objdir, obj)] + srcs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return os.path.join(objdir, obj)
+
+    workers = max(1, min(len(units), os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(compile_one, units))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -53,8 +53,8 @@ enum : uint8_t { ST_FIXED = 1, ST_LABEL = 2, ST_MARK = 8 };
 constexpr int16_t H_INF = 0x7FFF;
 
 // Stencils: H half-edges per pixel, radius R (every offset lies in [-R, R] per axis), grid dimension NDIM.
-// CONN 24, 48 and 80 are the square 5x5, 7x7 and 9x9 neighbourhoods of a 2D grid, CONN 32 the radius-2 ball of a
-// 3D grid (the spherical kernel of size 5).
+// CONN 24, 48 and 80 are the square 5x5, 7x7 and 9x9 neighbourhoods of a 2D grid, CONN 32 and 122 the radius-2
+// and radius-3 balls of a 3D grid (the spherical kernels of size 5 and 7).
 template <int CONN> struct Sten;
 template <> struct Sten<4> { static constexpr int H = 2, R = 1, NDIM = 2; };
 template <> struct Sten<8> { static constexpr int H = 4, R = 1, NDIM = 2; };
@@ -63,6 +63,19 @@ template <> struct Sten<48> { static constexpr int H = 24, R = 3, NDIM = 2; };
 template <> struct Sten<80> { static constexpr int H = 40, R = 4, NDIM = 2; };
 template <> struct Sten<6> { static constexpr int H = 3, R = 1, NDIM = 3; };
 template <> struct Sten<32> { static constexpr int H = 16, R = 2, NDIM = 3; };
+template <> struct Sten<122> { static constexpr int H = 61, R = 3, NDIM = 3; };
+
+// Half-stencil of the radius-3 ball (the spherical kernel of size 7): offsets of length at most 3 whose first
+// nonzero coordinate, from z down to x, is positive, ordered by z, then y, then x.
+constexpr int8_t kBall3[61][3] = {
+    {1, 0, 0}, {2, 0, 0}, {3, 0, 0}, {-2, 1, 0}, {-1, 1, 0}, {0, 1, 0}, {1, 1, 0}, {2, 1, 0}, {-2, 2, 0},
+    {-1, 2, 0}, {0, 2, 0}, {1, 2, 0}, {2, 2, 0}, {0, 3, 0}, {-2, -2, 1}, {-1, -2, 1}, {0, -2, 1}, {1, -2, 1},
+    {2, -2, 1}, {-2, -1, 1}, {-1, -1, 1}, {0, -1, 1}, {1, -1, 1}, {2, -1, 1}, {-2, 0, 1}, {-1, 0, 1}, {0, 0, 1},
+    {1, 0, 1}, {2, 0, 1}, {-2, 1, 1}, {-1, 1, 1}, {0, 1, 1}, {1, 1, 1}, {2, 1, 1}, {-2, 2, 1}, {-1, 2, 1},
+    {0, 2, 1}, {1, 2, 1}, {2, 2, 1}, {-1, -2, 2}, {0, -2, 2}, {1, -2, 2}, {-2, -1, 2}, {-1, -1, 2}, {0, -1, 2},
+    {1, -1, 2}, {2, -1, 2}, {-2, 0, 2}, {-1, 0, 2}, {0, 0, 2}, {1, 0, 2}, {2, 0, 2}, {-2, 1, 2}, {-1, 1, 2},
+    {0, 1, 2}, {1, 1, 2}, {2, 1, 2}, {-1, 2, 2}, {0, 2, 2}, {1, 2, 2}, {0, 0, 3}
+};
 
 // One bit per full-stencil direction.
 template <int CONN>
@@ -92,6 +105,7 @@ __device__ __forceinline__ int3 half_off(int o) {
         const int q = o - R;
         return make_int3(q % (2 * R + 1) - R, 1 + q / (2 * R + 1), 0);
     }
+    if (CONN == 122) return make_int3(kBall3[o][0], kBall3[o][1], kBall3[o][2]);
     if (CONN == 32) {
         // offsets of length at most 2 whose first nonzero coordinate, from z down to x, is positive; ordered by
         // z, then y, then x
@@ -1758,39 +1772,119 @@ hipError_t solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_
     // (or when the LDS footprint allows only one block per CU), otherwise 512 threads so that all blocks are
     // resident at once and neighbours on a CU hide each other's barrier and LDS latency.  Measured on MI355X with
     // 32x32 8-connected blocks: 289 and 1089 blocks both favour 512 threads.
-    if (grp.npmax > 512) {
-        const bool one_per_cu = maxflow_lds_bytes(grp.npmax, Sten<CONN>::H) > LDS_LIMIT / 2;
-        if (one_per_cu || grp.n_blk_items <= NUM_CUS) return launch_maxflow<CONN, 1024>(grp, s, e0, e1);
-        return launch_maxflow<CONN, 512>(grp, s, e0, e1);
+    // stencils so wide that no block of more than 512 pixels fits the LDS get the 256-thread kernels only
+    if constexpr (maxflow_lds_bytes(513, Sten<CONN>::H) > LDS_LIMIT) {
+        return launch_maxflow<CONN, 256>(grp, s, e0, e1);
+    } else {
+        if (grp.npmax > 512) {
+            const bool one_per_cu = maxflow_lds_bytes(grp.npmax, Sten<CONN>::H) > LDS_LIMIT / 2;
+            if (one_per_cu || grp.n_blk_items <= NUM_CUS) return launch_maxflow<CONN, 1024>(grp, s, e0, e1);
+            return launch_maxflow<CONN, 512>(grp, s, e0, e1);
+        }
+        return launch_maxflow<CONN, 256>(grp, s, e0, e1);
     }
-    return launch_maxflow<CONN, 256>(grp, s, e0, e1);
+}
+
+template <int CONN>
+void consensus_launch(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 grid(unsigned(grp.n_chk_items));
+    if (grp.one) {
+        if (e0) hipExtLaunchKernelGGL(k_consensus_one<CONN>, grid, dim3(CONS_NT), 0u, s, e0, e1, 0u, *grp.one, grp.par);
+        else hipLaunchKernelGGL(k_consensus_one<CONN>, grid, dim3(CONS_NT), 0, s, *grp.one, grp.par);
+    } else {
+        if (e0) hipExtLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0u, s, e0, e1, 0u, grp.imgs,
+                                      grp.chk_items);
+        else hipLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items);
+    }
 }
 
 }  // namespace
+
+// Per-stencil entry points.  Each stencil's kernels are compiled in a translation unit of their own (this file
+// with DOPE_CONN defined, see the build script), which instantiates these; the launchers below dispatch on the
+// stencil at run time.
+template <int CONN>
+hipError_t conn_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *cw,
+                      int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid, Ctl *ctl,
+                      int64_t mu0, uint64_t eps2, int32_t mu_num, int32_t mu_den, int32_t allow_negative,
+                      hipStream_t s) {
+    const StateInit si{mu0, eps2, mu_num, mu_den, allow_negative};
+    hipLaunchKernelGGL(k_setup<CONN>, dim3(blocks_for(g.W, 256), row_blocks(g)), dim3(256), 0, s, g, u_src, w_src,
+                       u_ws, cw, lam_q8, Y, A0, A1, yhat, resid, ctl, si);
+    return hipGetLastError();
+}
+
+template <int CONN>
+hipError_t conn_setup_batch(const Img *imgs, const SetupArg *args, const Item *rows, int32_t n_rows, hipStream_t s) {
+    hipLaunchKernelGGL(k_setup_batch<CONN>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows);
+    return hipGetLastError();
+}
+
+template <int CONN>
+hipError_t conn_solve(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    return solve_phase<CONN>(grp, s, e0, e1);
+}
+
+template <int CONN>
+hipError_t conn_consensus(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    consensus_launch<CONN>(grp, s, e0, e1);
+    return hipGetLastError();
+}
+
+template <int CONN>
+hipError_t conn_energy(const Geom &g, const int32_t *u, const int32_t *cw, const int32_t *Y, int64_t *part,
+                       unsigned wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy<CONN>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part);
+    return hipGetLastError();
+}
+
+#define DOPE_CONN_ENTRIES(SPEC, C)                                                                                 \
+    SPEC template hipError_t conn_setup<C>(const Geom &, const int32_t *, const int32_t *, int32_t *, int32_t *,    \
+                                           int32_t, int32_t *, int32_t *, int32_t *, uint8_t *, int64_t *, Ctl *,   \
+                                           int64_t, uint64_t, int32_t, int32_t, int32_t, hipStream_t);              \
+    SPEC template hipError_t conn_setup_batch<C>(const Img *, const SetupArg *, const Item *, int32_t, hipStream_t); \
+    SPEC template hipError_t conn_solve<C>(const Group &, hipStream_t, hipEvent_t, hipEvent_t);                      \
+    SPEC template hipError_t conn_consensus<C>(const Group &, hipStream_t, hipEvent_t, hipEvent_t);                  \
+    SPEC template hipError_t conn_energy<C>(const Geom &, const int32_t *, const int32_t *, const int32_t *,         \
+                                            int64_t *, unsigned, hipStream_t);
+
+#ifdef DOPE_CONN
+DOPE_CONN_ENTRIES(, DOPE_CONN)
+#else
+// instantiated by the per-stencil translation units
+DOPE_CONN_ENTRIES(extern, 4)
+DOPE_CONN_ENTRIES(extern, 8)
+DOPE_CONN_ENTRIES(extern, 24)
+DOPE_CONN_ENTRIES(extern, 48)
+DOPE_CONN_ENTRIES(extern, 80)
+DOPE_CONN_ENTRIES(extern, 6)
+DOPE_CONN_ENTRIES(extern, 32)
+DOPE_CONN_ENTRIES(extern, 122)
+
+// Run-time dispatch on the stencil; f is called as f(std::integral_constant<int, CONN>()).
+template <class F>
+hipError_t by_conn(int32_t conn, F &&f) {
+    switch (conn) {
+        case 4: return f(std::integral_constant<int, 4>());
+        case 8: return f(std::integral_constant<int, 8>());
+        case 24: return f(std::integral_constant<int, 24>());
+        case 48: return f(std::integral_constant<int, 48>());
+        case 80: return f(std::integral_constant<int, 80>());
+        case 6: return f(std::integral_constant<int, 6>());
+        case 32: return f(std::integral_constant<int, 32>());
+        case 122: return f(std::integral_constant<int, 122>());
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *cw,
                         int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
                         int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,
                         int32_t allow_negative, hipStream_t s) {
-    const dim3 grid(blocks_for(g.W, 256), row_blocks(g));
-    const StateInit si{mu0, eps2, mu_num, mu_den, allow_negative};
-    switch (g.conn) {
-        case 4: hipLaunchKernelGGL(k_setup<4>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
-                                   A1, yhat, resid, ctl, si); break;
-        case 8: hipLaunchKernelGGL(k_setup<8>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
-                                   A1, yhat, resid, ctl, si); break;
-        case 24: hipLaunchKernelGGL(k_setup<24>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
-                                    A1, yhat, resid, ctl, si); break;
-        case 48: hipLaunchKernelGGL(k_setup<48>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
-                                    A1, yhat, resid, ctl, si); break;
-        case 32: hipLaunchKernelGGL(k_setup<32>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
-                                    A1, yhat, resid, ctl, si); break;
-        case 80: hipLaunchKernelGGL(k_setup<80>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y, A0,
-                                    A1, yhat, resid, ctl, si); break;
-        default: hipLaunchKernelGGL(k_setup<6>, grid, dim3(256), 0, s, g, u_src, w_src, u_ws, cw, lam_q8, Y,
-                                    A0, A1, yhat, resid, ctl, si); break;
-    }
-    return hipGetLastError();
+    return by_conn(g.conn, [&](auto c) {
+        return conn_setup<decltype(c)::value>(g, u_src, w_src, u_ws, cw, lam_q8, Y, A0, A1, yhat, resid, ctl, mu0,
+                                              eps2, mu_num, mu_den, allow_negative, s);
+    });
 }
 
 // One workgroup per block: the owner copies of the block's pixels that are not interior to it, in the block's
@@ -1844,16 +1938,7 @@ hipError_t launch_build_blist(const Geom &g, const int32_t *btab, int2 *blist, h
 hipError_t launch_setup_batch(int32_t conn, const Img *imgs, const SetupArg *args, const Item *rows, int32_t n_rows,
                               hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
-    switch (conn) {
-        case 4: hipLaunchKernelGGL(k_setup_batch<4>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
-        case 8: hipLaunchKernelGGL(k_setup_batch<8>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
-        case 24: hipLaunchKernelGGL(k_setup_batch<24>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
-        case 48: hipLaunchKernelGGL(k_setup_batch<48>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
-        case 32: hipLaunchKernelGGL(k_setup_batch<32>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
-        case 80: hipLaunchKernelGGL(k_setup_batch<80>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
-        default: hipLaunchKernelGGL(k_setup_batch<6>, dim3(unsigned(n_rows)), dim3(256), 0, s, imgs, args, rows); break;
-    }
-    return hipGetLastError();
+    return by_conn(conn, [&](auto c) { return conn_setup_batch<decltype(c)::value>(imgs, args, rows, n_rows, s); });
 }
 
 hipError_t launch_labels_batch(const Img *imgs, uint8_t *const *labels, const Item *rows, int32_t n_rows,
@@ -1875,41 +1960,12 @@ hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge,
 }
 
 hipError_t launch_solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    switch (grp.conn) {
-        case 4: return solve_phase<4>(grp, s, e0, e1);
-        case 8: return solve_phase<8>(grp, s, e0, e1);
-        case 24: return solve_phase<24>(grp, s, e0, e1);
-        case 48: return solve_phase<48>(grp, s, e0, e1);
-        case 32: return solve_phase<32>(grp, s, e0, e1);
-        case 80: return solve_phase<80>(grp, s, e0, e1);
-        default: return solve_phase<6>(grp, s, e0, e1);
-    }
-}
-
-template <int CONN>
-void consensus_launch(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const dim3 grid(unsigned(grp.n_chk_items));
-    if (grp.one) {
-        if (e0) hipExtLaunchKernelGGL(k_consensus_one<CONN>, grid, dim3(CONS_NT), 0u, s, e0, e1, 0u, *grp.one, grp.par);
-        else hipLaunchKernelGGL(k_consensus_one<CONN>, grid, dim3(CONS_NT), 0, s, *grp.one, grp.par);
-    } else {
-        if (e0) hipExtLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0u, s, e0, e1, 0u, grp.imgs,
-                                      grp.chk_items);
-        else hipLaunchKernelGGL(k_consensus<CONN>, grid, dim3(CONS_NT), 0, s, grp.imgs, grp.chk_items);
-    }
+    return by_conn(grp.conn, [&](auto c) { return conn_solve<decltype(c)::value>(grp, s, e0, e1); });
 }
 
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (grp.n_chk_items > 0) switch (grp.conn) {
-        case 4: consensus_launch<4>(grp, s, e0, e1); break;
-        case 8: consensus_launch<8>(grp, s, e0, e1); break;
-        case 24: consensus_launch<24>(grp, s, e0, e1); break;
-        case 48: consensus_launch<48>(grp, s, e0, e1); break;
-        case 32: consensus_launch<32>(grp, s, e0, e1); break;
-        case 80: consensus_launch<80>(grp, s, e0, e1); break;
-        default: consensus_launch<6>(grp, s, e0, e1); break;
-    }
-    return hipGetLastError();
+    if (grp.n_chk_items <= 0) return hipSuccess;
+    return by_conn(grp.conn, [&](auto c) { return conn_consensus<decltype(c)::value>(grp, s, e0, e1); });
 }
 
 hipError_t launch_finalize_phase(const Group &grp, hipStream_t s) {
@@ -1941,17 +1997,13 @@ hipError_t launch_energy(const Geom &g, const int32_t *u, const int32_t *cw, con
                          Ctl *ctl, hipStream_t s) {
     const int64_t rows = int64_t(g.H) * g.D;
     const unsigned wgs = unsigned(rows < ENERGY_WGS ? rows : ENERGY_WGS);
-    switch (g.conn) {
-        case 4: hipLaunchKernelGGL(k_energy<4>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
-        case 8: hipLaunchKernelGGL(k_energy<8>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
-        case 24: hipLaunchKernelGGL(k_energy<24>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
-        case 48: hipLaunchKernelGGL(k_energy<48>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
-        case 32: hipLaunchKernelGGL(k_energy<32>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
-        case 80: hipLaunchKernelGGL(k_energy<80>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
-        default: hipLaunchKernelGGL(k_energy<6>, dim3(wgs), dim3(256), 0, s, g, u, cw, Y, part); break;
-    }
+    const hipError_t e =
+        by_conn(g.conn, [&](auto c) { return conn_energy<decltype(c)::value>(g, u, cw, Y, part, wgs, s); });
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s, part, int(wgs), ctl);
     return hipGetLastError();
 }
+
+#endif  // DOPE_CONN
 
 }  // namespace dope

@@ -38,12 +38,13 @@ def half_stencil(ndim: int, conn: int) -> List[Tuple[int, int, int]]:
         return out
     if ndim == 3 and conn == 6:
         return [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
-    if ndim == 3 and conn == 32:   # ball of radius 2; first nonzero coordinate (z, then y, then x) positive
+    if ndim == 3 and conn in (32, 122):   # balls of radius 2 / 3; first nonzero coordinate (z, y, x) positive
+        r = 2 if conn == 32 else 3
         out = []
-        for dz in range(0, 3):
-            for dy in range(-2, 3):
-                for dx in range(-2, 3):
-                    if dx * dx + dy * dy + dz * dz > 4 or (dx, dy, dz) == (0, 0, 0):
+        for dz in range(0, r + 1):
+            for dy in range(-r, r + 1):
+                for dx in range(-r, r + 1):
+                    if dx * dx + dy * dy + dz * dz > r * r or (dx, dy, dz) == (0, 0, 0):
                         continue
                     if dz > 0 or (dz == 0 and dy > 0) or (dz == 0 and dy == 0 and dx > 0):
                         out.append((dx, dy, dz))
@@ -272,21 +273,26 @@ def config_kernel(k: int, seed: int = 0, W: int = 512, H: int = 512, mu0: int = 
                    truth=fg.reshape(-1).astype(np.uint8))
 
 
-def config3_kernel5(seed: int = 0, dims=(128, 128, 64), mu0: int = DEFAULT_MU0_3D) -> Problem:
-    """The volume of config3 with the spherical kernel of size 5 (the radius-2 ball, 32 neighbours): distance-
-    weighted Potts w = round(1000 / |offset|), lambda = 0.4 (total smoothing per voxel near config3's
-    1.5 x 6 x 1000), 8^3 blocks with o = 1 (141 LDS bytes per block node)."""
+def config3_kernel5(seed: int = 0, dims=(128, 128, 64), mu0: int = DEFAULT_MU0_3D, k: int = 5) -> Problem:
+    """The volume of config3 with the spherical kernel of size k: the radius-2 ball (k = 5, 32 neighbours) or the
+    radius-3 ball (k = 7, 122 neighbours), distance-weighted Potts w = round(1000 / |offset|), lambda = 0.4 or
+    0.16 (total smoothing per voxel near config3's 1.5 x 6 x 1000); 8^3 or 6^3 blocks with o = 1 (141 or 513 LDS
+    bytes per block node)."""
+    if k not in (5, 7):
+        raise ValueError("k must be 5 or 7")
+    conn = 32 if k == 5 else 122
     base = config3(seed=seed, dims=dims, mu0=mu0)
     W, H, D = dims
     zz, yy, xx = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
-    offs = half_stencil(3, 32)
+    offs = half_stencil(3, conn)
     w = np.zeros((len(offs), W * H * D), dtype=np.int32)
     for o, (dx, dy, dz) in enumerate(offs):
         ok = ((xx + dx >= 0) & (xx + dx < W) & (yy + dy >= 0) & (yy + dy < H)
               & (zz + dz >= 0) & (zz + dz < D))
         w[o] = np.where(ok.reshape(-1), int(_round(1000.0 / math.sqrt(dx * dx + dy * dy + dz * dz))), 0)
-    return Problem(f"kernel5_spheres{W}x{H}x{D}_32conn", (W, H, D), 3, 32, base.u, w, lambda_q8(0.4),
-                   (8, 8, 8), (1, 1, 1), mu0, truth=base.truth)
+    B = 8 if k == 5 else 6
+    return Problem(f"kernel{k}_spheres{W}x{H}x{D}_{conn}conn", (W, H, D), 3, conn, base.u, w,
+                   lambda_q8(0.4 if k == 5 else 0.16), (B, B, B), (1, 1, 1), mu0, truth=base.truth)
 
 
 def random_problem(seed: int, dims, conn: int, block, overlap, lam_q8: int = 256,
@@ -295,7 +301,7 @@ def random_problem(seed: int, dims, conn: int, block, overlap, lam_q8: int = 256
     """Uniform random integer unaries and weights (a fraction neg_frac of edges negated) on any grid."""
     rng = np.random.default_rng(seed)
     W, H, D = dims
-    ndim = 3 if conn in (6, 32) else 2
+    ndim = 3 if conn in (6, 32, 122) else 2
     n = W * H * D
     u = rng.integers(u_range[0], u_range[1] + 1, size=n).astype(np.int32)
     offs = half_stencil(ndim, conn)

@@ -94,14 +94,15 @@ def _workspace_model(dims, h, K, tot, n_int):
     ((200, 150, 1), 48, (16, 16, 1), (2, 2, 0), 2),
     ((64, 48, 40), 32, (8, 8, 8), (1, 1, 1), 3),
     ((131, 97, 1), 80, (16, 16, 1), (2, 2, 0), 2),
+    ((40, 30, 20), 122, (6, 6, 6), (1, 1, 1), 3),
 ])
 def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, ndim):
     from oracle import dope as od
     p = _params(native, dims, conn, block, overlap, ndim=ndim)
     blocks = od.make_blocks(dims, block, overlap)
     n = dims[0] * dims[1] * dims[2]
-    h = {4: 2, 8: 4, 6: 3, 24: 12, 48: 24, 32: 16, 80: 40}[conn]
-    r = {24: 2, 48: 3, 32: 2, 80: 4}.get(conn, 1)
+    h = {4: 2, 8: 4, 6: 3, 24: 12, 48: 24, 32: 16, 80: 40, 122: 61}[conn]
+    r = {24: 2, 48: 3, 32: 2, 80: 4, 122: 3}.get(conn, 1)
     tot = sum(len(b.idx) for b in blocks)
     assert native.dope_workspace_bytes(ctypes.byref(p)) == _workspace_model(dims, h, len(blocks), tot,
                                                                      _interior_count(dims, block, overlap, r))
@@ -143,6 +144,7 @@ def test_autotune_is_a_pure_function_of_shape(native):
     assert autotune(2, (512, 512), 48) == ((16, 16, 1), (1, 1, 0))
     assert autotune(3, (128, 128, 64), 32) == ((8, 8, 8), (1, 1, 1))
     assert autotune(2, (512, 512), 80) == ((16, 16, 1), (1, 1, 0))
+    assert autotune(3, (128, 128, 64), 122) == ((6, 6, 6), (1, 1, 1))
     assert autotune(2, (512, 512), 8) == autotune(2, (512, 512), 8)
     with pytest.raises(Exception):
         autotune(2, (64, 64), 6)

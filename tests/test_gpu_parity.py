@@ -309,6 +309,7 @@ WIDE_CASES = [
     ((9, 9, 8), 32, (4, 4, 4), (2, 2, 2), 150, 3000),       # stride 2 = radius: 8 copies at every corner
     ((41, 35, 1), 80, (12, 12, 1), (2, 2, 0), 100, 1000),   # 9x9 neighbourhood
     ((29, 23, 1), 80, (6, 6, 1), (2, 2, 0), 80, 800),       # 9x9, stride 4 = radius
+    ((14, 12, 10), 122, (6, 6, 5), (1, 1, 1), 40, 4000),    # 3D ball of radius 3
 ]
 
 
@@ -339,10 +340,11 @@ def test_wide_exhaustive_nonsubmodular():
     d.close()
 
 
-def test_ball_kernel_volume_small_every_iteration():
-    """The spherical kernel of size 5 on a small version of the config3 volume."""
-    p = synth.config3_kernel5(dims=(40, 36, 20))
-    d, st_o, dec = run_parity(p, 5, "ball kernel 40x36x20")
+@pytest.mark.parametrize("k,dims", [(5, (40, 36, 20)), (7, (30, 26, 14))])
+def test_ball_kernel_volume_small_every_iteration(k, dims):
+    """The spherical kernels of size 5 and 7 on small versions of the config3 volume."""
+    p = synth.config3_kernel5(dims=dims, k=k)
+    d, st_o, dec = run_parity(p, 5, f"ball kernel {k} {dims}")
     assert np.array_equal(d.labels(), od.labels(st_o.Y))
     assert d.energy() == od.energy_q(dec, od.labels(st_o.Y))
     d.close()
