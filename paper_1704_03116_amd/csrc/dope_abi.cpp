@@ -405,13 +405,16 @@ hipEvent_t next_event(std::vector<hipEvent_t> &pool, size_t idx) {
 }
 
 // Enqueues count iterations after the c->hctl->t completed ones (the host mirror is current whenever this runs).
+// The last iteration's loop-control kernel also refreshes the pinned host mirror, so the readback that follows is
+// a wait on the stream instead of a copy launch (see read_back).
 dope_status enqueue_iterations(dope_ctx *c, int count) {
     c->grp.solver = c->solver;
     c->grp.one = &c->himg;
     for (int it = 0; it < count; ++it) {
         c->grp.par = (c->hctl->t + it) & 1;
+        Ctl *mirror = it == count - 1 ? c->hctl : nullptr;
         if (!c->profiling) {
-            HIP_TRY(c, dope::launch_iteration(c->grp, c->stream), "iteration launch");
+            HIP_TRY(c, dope::launch_iteration(c->grp, c->stream, mirror), "iteration launch");
             continue;
         }
         hipEvent_t e0 = next_event(c->ev_solve, 2 * c->n_solve), e1 = next_event(c->ev_solve, 2 * c->n_solve + 1);
@@ -423,10 +426,14 @@ dope_status enqueue_iterations(dope_ctx *c, int count) {
         HIP_TRY(c, dope::launch_consensus_phase(c->grp, c->stream, e0 && e1 ? e0 : nullptr, e0 && e1 ? e1 : nullptr),
                 "consensus launch");
         if (e0 && e1 && c->grp.n_chk_items > 0) ++c->n_cons;
-        HIP_TRY(c, dope::launch_finalize_phase(c->grp, c->stream), "finalize launch");
+        HIP_TRY(c, dope::launch_finalize_phase(c->grp, c->stream, mirror), "finalize launch");
     }
     return DOPE_OK;
 }
+
+// The loop control after enqueue_iterations(c, count): the mirror is written by the last loop-control kernel when
+// count > 0, otherwise it is copied back.
+dope_status read_back(dope_ctx *c, int count) { return count > 0 ? wait_stream(c) : sync_ctl(c); }
 
 dope_status check_ready(dope_ctx *c) {
     if (!c) return DOPE_EINVAL;
@@ -636,7 +643,7 @@ dope_status dope_iterate(dope_ctx *c, int32_t n_iter, dope_info *out) {
     c->validate_pending = false;
     st = enqueue_iterations(c, n_iter);
     if (st != DOPE_OK) return st;
-    st = sync_ctl(c);
+    st = read_back(c, n_iter);
     if (st != DOPE_OK) return st;
     fill_info(c, out);
     if (c->hctl->status != 0)
@@ -660,7 +667,7 @@ dope_status dope_solve(dope_ctx *c, dope_info *out) {
         const int count = std::min(chunk, limit - c->hctl->t);
         st = enqueue_iterations(c, count);
         if (st != DOPE_OK) return st;
-        st = sync_ctl(c);
+        st = read_back(c, count);
         if (st != DOPE_OK) return st;
         if (c->hctl->halted) break;
         if (++n_chunks >= 2) chunk = std::min(2 * chunk, 64);

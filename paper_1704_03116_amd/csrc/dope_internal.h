@@ -175,7 +175,8 @@ struct Group {
 };
 
 // One ADMM iteration (block solves, consensus and multipliers, loop control) for every image of the group.
-hipError_t launch_iteration(const Group &grp, hipStream_t s);
+// mirror: host-visible copy of the one-image loop control that the finalize kernel refreshes (or nullptr)
+hipError_t launch_iteration(const Group &grp, hipStream_t s, Ctl *mirror = nullptr);
 // Per-image loop setup of a batch: params[2 i] = t_limit, params[2 i + 1] = stop_on_converge.
 hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params, hipStream_t s);
 // Individual phases (used for per-kernel timing).
@@ -183,7 +184,7 @@ hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params,
 hipError_t launch_solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0 = nullptr,
                                   hipEvent_t e1 = nullptr);
-hipError_t launch_finalize_phase(const Group &grp, hipStream_t s);
+hipError_t launch_finalize_phase(const Group &grp, hipStream_t s, Ctl *mirror = nullptr);
 
 // set_energy on the device: workspace copy of u (src != ws), c_ij, initial state and loop control.  The
 // validation verdict (status / halted set on the device when the energy is invalid) is taken by the next

@@ -1345,7 +1345,17 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus_one(const Img one, int32_
 // Loop control after the consensus of one iteration (a single workgroup): max_k r_k, stopping rule, overflow
 // and solver errors, mu <- mu * mu_fact, t <- t + 1.  A separate launch instead of a last-workgroup handshake
 // inside k_consensus: a device-scope fence per workgroup costs L2 write-backs on every XCD.
-__device__ __forceinline__ void finalize_image(const Img &im) {
+// Copies the loop control into the host-visible mirror (thread 0 after its own updates, so it reads them back).
+__device__ __forceinline__ void mirror_ctl(const GLOBAL Ctl *ctl, Ctl *mirror) {
+    static_assert(sizeof(Ctl) % 8 == 0, "the loop control is copied in 8-byte words");
+    const GLOBAL unsigned long long *src = reinterpret_cast<const GLOBAL unsigned long long *>(ctl);
+    unsigned long long *dst = reinterpret_cast<unsigned long long *>(mirror);
+#pragma unroll
+    for (int i = 0; i < int(sizeof(Ctl) / 8); ++i) dst[i] = src[i];
+}
+
+// mirror (single-image launches only): host-visible copy of the loop control to refresh after the update.
+__device__ __forceinline__ void finalize_image(const Img &im, Ctl *mirror = nullptr) {
     GLOBAL Ctl *ctl = gp(im.ctl);
     // every load is issued before any is used (one memory round trip): the loop control and the residuals
     const int32_t halted = ctl->halted, t = ctl->t, t_limit = ctl->t_limit, solver_err = ctl->solver_err,
@@ -1366,7 +1376,10 @@ __device__ __forceinline__ void finalize_image(const Img &im) {
         const unsigned long long v = static_cast<unsigned long long>(resid[k]);
         mx = v > mx ? v : mx;
     }
-    if (halted != 0 || t >= t_limit) return;   // uniform
+    if (halted != 0 || t >= t_limit) {   // uniform
+        if (mirror && tid == 0) mirror_ctl(ctl, mirror);
+        return;
+    }
 #pragma unroll
     for (int sft = 32; sft >= 1; sft >>= 1) {
         const unsigned long long o = __shfl_xor(mx, sft);
@@ -1397,14 +1410,15 @@ __device__ __forceinline__ void finalize_image(const Img &im) {
             sm[2] = conv;
             sm[3] = st_new ? st_new : status;
         }
+        if (mirror) mirror_ctl(ctl, mirror);
     }
 }
 
 // One workgroup per image (one = the only image's descriptor when single != 0).
 __global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, Queue *queue, const Img one,
-                                                  int32_t single) {
+                                                  int32_t single, Ctl *mirror) {
     if (blockIdx.x == 0 && threadIdx.x == 0) queue->next = 0;   // next iteration's block-solve queue
-    if (single) finalize_image(one);
+    if (single) finalize_image(one, mirror);
     else finalize_image(imgs[blockIdx.x]);
 }
 
@@ -1968,10 +1982,10 @@ hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0
     return by_conn(grp.conn, [&](auto c) { return conn_consensus<decltype(c)::value>(grp, s, e0, e1); });
 }
 
-hipError_t launch_finalize_phase(const Group &grp, hipStream_t s) {
+hipError_t launch_finalize_phase(const Group &grp, hipStream_t s, Ctl *mirror) {
     const Img one = grp.one ? *grp.one : Img{};
     hipLaunchKernelGGL(k_finalize, dim3(unsigned(grp.n_imgs)), dim3(256), 0, s, grp.imgs, grp.queue, one,
-                       int32_t(grp.one ? 1 : 0));
+                       int32_t(grp.one ? 1 : 0), grp.one ? mirror : nullptr);
     return hipGetLastError();
 }
 
@@ -1980,10 +1994,10 @@ hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params,
     return hipGetLastError();
 }
 
-hipError_t launch_iteration(const Group &grp, hipStream_t s) {
+hipError_t launch_iteration(const Group &grp, hipStream_t s, Ctl *mirror) {
     hipError_t e = launch_solve_phase(grp, s);
     if (e == hipSuccess) e = launch_consensus_phase(grp, s);
-    if (e == hipSuccess) e = launch_finalize_phase(grp, s);
+    if (e == hipSuccess) e = launch_finalize_phase(grp, s, mirror);
     return e;
 }
 
