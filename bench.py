@@ -74,15 +74,18 @@ def interior_count(dims, block, overlap, r=1):
     return total
 
 
-TRAFFIC_RECORDS = {"config2": "hbm_traffic_config2_512x512.json", "config3": "hbm_traffic_config3_128x128x64.json",
-                   "kernel5": "hbm_traffic_kernel5_512x512.json", "kernel7": "hbm_traffic_kernel7_512x512.json"}
+TRAFFIC_RECORDS = {"config2_ellipses512x512_8conn": "hbm_traffic_config2_512x512.json",
+                   "config3_spheres128x128x64_6conn": "hbm_traffic_config3_128x128x64.json",
+                   "kernel5_ellipses512x512_24conn": "hbm_traffic_kernel5_512x512.json",
+                   "kernel7_ellipses512x512_48conn": "hbm_traffic_kernel7_512x512.json",
+                   "kernel9_ellipses512x512_80conn": "hbm_traffic_kernel9_512x512.json"}
 
 
 def measured_traffic(workload_name):
     """HBM bytes per dispatch from the committed rocprofv3 counter summary of this workload, only while the kernel
     source is the one that was measured (FETCH_SIZE and WRITE_SIZE scaled by a 256 MiB copy's readings)."""
     import hashlib
-    rec_name = next((f for k, f in TRAFFIC_RECORDS.items() if workload_name.startswith(k)), None)
+    rec_name = TRAFFIC_RECORDS.get(workload_name)   # exact workload: name carries the sizes and stencil
     if rec_name is None:
         return {}
     path = os.path.join(ROOT, "profiles", rec_name)
