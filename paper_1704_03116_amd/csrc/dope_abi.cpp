@@ -30,6 +30,9 @@ struct dope_ctx {
     Ctl *ctl = nullptr;
     dope::Img himg{};          // host copy of the device image descriptor (kernel argument of one-image launches)
     bool validate_pending = false;   // a setup is enqueued whose validation no control kernel has taken yet
+    bool ctl_fresh = false;          // the device loop control is as the setup kernel leaves it (t = 0, limit
+                                     // max_iter, halting on convergence, verdict taken by the first k_finalize):
+                                     // a solve needs no control setup
     int32_t *btab = nullptr, *u = nullptr, *w = nullptr, *cw = nullptr, *Y = nullptr, *A0 = nullptr, *A1 = nullptr;
     int32_t *stats = nullptr, *chunk_k0 = nullptr;
     int2 *blist = nullptr;
@@ -335,6 +338,7 @@ dope_status upload_tables(dope_ctx *c) {
     HIP_TRY(c, hipMemcpyAsync(c->queue, &q, sizeof(q), hipMemcpyHostToDevice, c->stream), "queue upload");
     // a zeroed loop control: the setup kernel initialises every field except the validation accumulator
     const dope::Ctl zc{};
+    c->ctl_fresh = false;
     HIP_TRY(c, hipMemcpyAsync(c->ctl, &zc, sizeof(zc), hipMemcpyHostToDevice, c->stream), "control reset");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
     c->grp = dope::Group{c->dimg, 1, c->blk_items, c->g.K, c->chk_items, int32_t(ci.size()), c->queue,
@@ -555,11 +559,15 @@ dope_status enqueue_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int3
         w_src = c->w;
     }
     const uint64_t eps2 = uint64_t(c->p.eps_q16) * uint64_t(c->p.eps_q16);
+    // a verdict still pending (an earlier set-up no call has run since) consumes its bits first, so that they do
+    // not reach this one's
+    if (c->validate_pending) HIP_TRY(c, dope::launch_validate(c->ctl, c->stream), "validation launch");
     HIP_TRY(c, dope::launch_setup(g, u_src, w_src, c->u, c->cw, lambda_q8, c->Y, c->A0, c->A1, c->yhat, c->resid,
                                   c->ctl, c->p.mu0, c->p.mu_fact_num, c->p.mu_fact_den, eps2, allow_negative,
-                                  c->stream),
+                                  c->p.max_iter, c->stream),
             "setup launch");
     c->validate_pending = true;
+    c->ctl_fresh = true;
     return DOPE_OK;
 }
 
@@ -620,6 +628,8 @@ dope_status dope_set_energy_async(dope_ctx *c, const int32_t *u, const int32_t *
     if (st != DOPE_OK) return st;
     // host mirror of the reset state; a validation failure shows up at the next readback
     Ctl h{};
+    h.t_limit = c->p.max_iter;
+    h.stop_on_converge = 1;
     h.M = c->p.mu0;
     h.eps2 = uint64_t(c->p.eps_q16) * uint64_t(c->p.eps_q16);
     h.mu_num = c->p.mu_fact_num;
@@ -641,6 +651,7 @@ dope_status dope_iterate(dope_ctx *c, int32_t n_iter, dope_info *out) {
     const int32_t t0 = c->hctl->t;
     HIP_TRY(c, dope::launch_ctl_setup(c->ctl, t0 + n_iter, 0, 0, c->stream), "control setup launch");
     c->validate_pending = false;
+    c->ctl_fresh = false;
     st = enqueue_iterations(c, n_iter);
     if (st != DOPE_OK) return st;
     st = read_back(c, n_iter);
@@ -657,8 +668,9 @@ dope_status dope_solve(dope_ctx *c, dope_info *out) {
     if (c->hctl->status != 0) { fill_info(c, out); return dope_status(c->hctl->status); }
     if (c->hctl->t > 0 && c->hctl->converged) { fill_info(c, out); return DOPE_OK; }
     const int32_t limit = c->p.max_iter;
-    HIP_TRY(c, dope::launch_ctl_setup(c->ctl, limit, 1, 0, c->stream), "control setup launch");
+    if (!c->ctl_fresh) HIP_TRY(c, dope::launch_ctl_setup(c->ctl, limit, 1, 0, c->stream), "control setup launch");
     c->validate_pending = false;
+    c->ctl_fresh = false;
     // Iterations are enqueued in chunks of 2, 2, 4, 8, ... with one readback per chunk.  An iteration enqueued
     // after the stopping rule held is skipped on the device (Ctl::halted), so the result is that of one
     // iteration per readback; only a few empty launches are spent.
@@ -750,6 +762,7 @@ dope_status dope_set_state(dope_ctx *c, const int32_t *Y, const int32_t *A, cons
     h.solver_err = 0;
     h.wg_counter = 0;
     *c->hctl = h;
+    c->ctl_fresh = false;
     HIP_TRY(c, hipMemcpyAsync(c->ctl, c->hctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream), "control upload");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
     return DOPE_OK;
@@ -921,7 +934,10 @@ dope_status batch_setup(dope_batch *b) {
     BHIP_TRY(b, hipMemcpyAsync(b->dparams, b->hparams, n * 2 * sizeof(int32_t), hipMemcpyHostToDevice, b->stream),
              "parameter upload");
     BHIP_TRY(b, dope::launch_batch_setup(b->imgs, int32_t(n), b->dparams, b->stream), "batch setup launch");
-    for (dope_ctx *c : b->ctxs) c->validate_pending = false;   // taken by the batch setup kernel
+    for (dope_ctx *c : b->ctxs) {
+        c->validate_pending = false;   // taken by the batch setup kernel
+        c->ctl_fresh = false;
+    }
     return DOPE_OK;
 }
 
@@ -1144,6 +1160,7 @@ dope_status dope_batch_set_energy_async(dope_batch *b, const int32_t *const *u, 
         c->lam_q8 = lambda_q8[i];
         c->energy_set = true;
         c->validate_pending = true;
+        c->ctl_fresh = false;
         c->err.clear();
     }
     return DOPE_OK;

@@ -186,9 +186,10 @@ hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0
                                   hipEvent_t e1 = nullptr);
 hipError_t launch_finalize_phase(const Group &grp, hipStream_t s, Ctl *mirror = nullptr);
 
-// set_energy on the device: workspace copy of u (src != ws), c_ij, initial state and loop control.  The
-// validation verdict (status / halted set on the device when the energy is invalid) is taken by the next
-// launch_validate, launch_ctl_setup or launch_batch_setup.
+// set_energy on the device: workspace copy of u (src != ws), c_ij, initial state and loop control, left as a
+// solve with limit t_limit starts it.  The validation verdict (status / halted set on the device when the energy
+// is invalid) is taken by the next launch_validate, launch_ctl_setup, launch_batch_setup or k_finalize; until
+// then the iteration kernels skip an energy the verdict will reject.
 hipError_t launch_validate(Ctl *ctl, hipStream_t s);
 // Boundary list of one image (see the workspace layout): one workgroup per block writes the owner copies of the
 // block's non-interior pixels from the block's base entry btab[k][7].
@@ -196,7 +197,7 @@ hipError_t launch_build_blist(const Geom &g, const int32_t *btab, int2 *blist, h
 hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *cw,
                         int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
                         int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,
-                        int32_t allow_negative, hipStream_t s);
+                        int32_t allow_negative, int32_t t_limit, hipStream_t s);
 hipError_t launch_ctl_setup(Ctl *ctl, int32_t t_limit, int32_t stop_on_converge, int32_t clear_energy,
                             hipStream_t s);
 hipError_t launch_labels(const Geom &g, const int32_t *Y, uint8_t *labels, hipStream_t s);

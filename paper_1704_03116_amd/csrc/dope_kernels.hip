@@ -273,9 +273,19 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
     return (static_cast<unsigned long long>(hi) << 26) + lo;
 }
 
+// Status an energy's validation bits give (FLAG_*): off-grid or oversized weights -> EINVAL (-1), a negative
+// weight when the solver needs c_ij >= 0 -> ENOTSUBMODULAR (-4), else 0.
+__device__ __forceinline__ int32_t energy_verdict(int32_t flags, int32_t allow_negative) {
+    return (flags & (FLAG_OFFGRID | FLAG_TOOBIG)) ? -1 : (((flags & FLAG_NEGATIVE) && !allow_negative) ? -4 : 0);
+}
+
+// An iteration kernel does nothing once the loop halted or reached its limit, or while the verdict on the energy
+// is pending and will reject it.
 __device__ __forceinline__ bool ctl_skip(const Ctl *ctl) {
     const GLOBAL Ctl *c = gp(ctl);
-    return c->halted != 0 || c->t >= c->t_limit;
+    const int32_t halted = c->halted, t = c->t, t_limit = c->t_limit, vpending = c->vpending, flags = c->flags,
+                  allow_negative = c->allow_negative;
+    return halted != 0 || t >= t_limit || (vpending && energy_verdict(flags, allow_negative) != 0);
 }
 
 // floor(n / M) for M >= 1 and |n| < 2^53: a double-precision estimate within +-2 of the quotient, then an exact
@@ -1360,7 +1370,8 @@ __device__ __forceinline__ void finalize_image(const Img &im, Ctl *mirror = null
     // every load is issued before any is used (one memory round trip): the loop control and the residuals
     const int32_t halted = ctl->halted, t = ctl->t, t_limit = ctl->t_limit, solver_err = ctl->solver_err,
                   ovf = ctl->ovf_pending, stop_conv = ctl->stop_on_converge, mu_num = ctl->mu_num,
-                  mu_den = ctl->mu_den, status = ctl->status;
+                  mu_den = ctl->mu_den, status = ctl->status, vpending = ctl->vpending, flags = ctl->flags,
+                  allow_negative = ctl->allow_negative;
     const int64_t M = ctl->M;
     const uint64_t eps2 = ctl->eps2;
     __shared__ unsigned long long s_max[4];
@@ -1376,8 +1387,29 @@ __device__ __forceinline__ void finalize_image(const Img &im, Ctl *mirror = null
         const unsigned long long v = static_cast<unsigned long long>(resid[k]);
         mx = v > mx ? v : mx;
     }
-    if (halted != 0 || t >= t_limit) {   // uniform
-        if (mirror && tid == 0) mirror_ctl(ctl, mirror);
+    // a verdict still pending (a solve straight after the energy upload): taken here; a rejected energy halts the
+    // loop with t unchanged (the iteration kernels skipped it)
+    const int32_t vst = vpending ? energy_verdict(flags, allow_negative) : 0;
+    if (vpending && tid == 0) {
+        ctl->vflags = flags;
+        ctl->flags = 0;
+        ctl->vpending = 0;
+        if (vst) {
+            ctl->status = vst;
+            ctl->halted = 1;
+        }
+    }
+    if (halted != 0 || t >= t_limit || vst != 0) {   // uniform
+        if (tid == 0) {
+            if (vst && im.summary) {
+                GLOBAL int32_t *sm = gp(im.summary);
+                sm[0] = t;
+                sm[1] = 1;
+                sm[2] = 0;
+                sm[3] = vst;
+            }
+            if (mirror) mirror_ctl(ctl, mirror);
+        }
         return;
     }
 #pragma unroll
@@ -1432,19 +1464,23 @@ __global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, 
 //   - c_ij = lambda_q8 w_ij 64 / (q_i q_j) for the half-stencil edges of every pixel, with validation bits (nonzero
 //     weight on an off-grid edge, negative weight, per-node sum_j |c_ij| >= 2^29) OR-ed into ctl->flags,
 //   - the initial ADMM state (Y = 1/2, A = 0, yhat = 0, r_k = 0; a grid-stride pass over the block-major arrays),
-//   - the loop control (workgroup (0, 0)); ctl->flags is left alone: the validation consumes and clears it.
+//   - the loop control (workgroup (0, 0)), left as a solve starts it (limit si.t_limit, halting when the stopping
+//     rule holds) with the validation verdict pending; ctl->flags is left alone: the verdict consumes and clears
+//     it.  The verdict is taken by the next control kernel (the first iteration's k_finalize included), and until
+//     then the iteration kernels skip an energy that fails it (ctl_skip).
 struct StateInit {
     int64_t mu0;
     uint64_t eps2;
     int32_t mu_num, mu_den;
     int32_t allow_negative;
+    int32_t t_limit;   // iteration limit a solve runs under
 };
 
+// Returns the validation bits (FLAG_*) of the pixel's weights.
 template <int CONN>
-__device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int gz, const int32_t *__restrict__ u_src,
-                                            const int32_t *__restrict__ w_src, int32_t *__restrict__ u_ws,
-                                            int32_t *__restrict__ cw, int32_t lam,
-                                            int32_t *__restrict__ Y, Ctl *ctl) {
+__device__ __forceinline__ int setup_pixel(const Geom &g, int gx, int gy, int gz, const int32_t *__restrict__ u_src,
+                                           const int32_t *__restrict__ w_src, int32_t *__restrict__ u_ws,
+                                           int32_t *__restrict__ cw, int32_t lam, int32_t *__restrict__ Y) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
     const uint32_t i = uint32_t(gx) + uint32_t(g.W) * (uint32_t(gy) + uint32_t(g.H) * uint32_t(gz));
@@ -1486,8 +1522,9 @@ __device__ __forceinline__ void setup_pixel(const Geom &g, int gx, int gy, int g
     if (u_src != u_ws) st_at(gp(u_ws), bi, ui);
     st_at(gp(Y), bi, int32_t(Y_HALF));
     if (sum >= CAP_SUM_LIMIT) flags |= FLAG_TOOBIG;
-    if (flags) atomicOr((int32_t *)gp(&ctl->flags), flags);
+    return flags;
 }
+
 
 template <int CONN>
 __global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict__ u_src,
@@ -1514,8 +1551,8 @@ __global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict
             c->eps2 = si.eps2;
             c->energy = 0;
             c->t = 0;
-            c->t_limit = 0;
-            c->stop_on_converge = 0;
+            c->t_limit = si.t_limit;
+            c->stop_on_converge = 1;
             c->converged = 0;
             c->halted = 0;
             c->status = 0;
@@ -1532,8 +1569,10 @@ __global__ __launch_bounds__(256) void k_setup(Geom g, const int32_t *__restrict
     const int gx = blockIdx.x * 256 + threadIdx.x;
     if (gx >= g.W) return;
     const int rows = g.H * g.D;
+    int flags = 0;
     for (int row = blockIdx.y; row < rows; row += gridDim.y)
-        setup_pixel<CONN>(g, gx, row % g.H, row / g.H, u_src, w_src, u_ws, cw, lam, Y, ctl);
+        flags |= setup_pixel<CONN>(g, gx, row % g.H, row / g.H, u_src, w_src, u_ws, cw, lam, Y);
+    if (flags) atomicOr((int32_t *)gp(&ctl->flags), flags);
 }
 
 // Batched energy upload: workgroup b sets up pixel row rows[b].idx of image rows[b].img (row = y + H z) and its
@@ -1579,9 +1618,11 @@ __global__ __launch_bounds__(256) void k_setup_batch(const Img *__restrict__ img
             c->allow_negative = a.allow_negative;
         }
     }
+    int flags = 0;
     for (int gx = threadIdx.x; gx < g.W; gx += 256)
-        setup_pixel<CONN>(g, gx, row % g.H, row / g.H, a.u_src, a.w_src, const_cast<int32_t *>(im.u),
-                          const_cast<int32_t *>(im.cw), a.lam_q8, im.Y, im.ctl);
+        flags |= setup_pixel<CONN>(g, gx, row % g.H, row / g.H, a.u_src, a.w_src, const_cast<int32_t *>(im.u),
+                                   const_cast<int32_t *>(im.cw), a.lam_q8, im.Y);
+    if (flags) atomicOr((int32_t *)gp(&im.ctl->flags), flags);
 }
 
 // Batched labels: workgroup b writes pixel row rows[b].idx of image rows[b].img into labels[img].
@@ -1595,7 +1636,7 @@ __global__ __launch_bounds__(256) void k_labels_batch(const Img *__restrict__ im
     for (int gx = threadIdx.x; gx < im.g.W; gx += 256) out[base + gx] = uint8_t(Y[base + gx] > Y_HALF);
 }
 
-// Energy validation verdict of a pending k_setup: off-grid or oversized weights -> EINVAL; a negative weight
+// Energy validation verdict of a pending set-up: off-grid or oversized weights -> EINVAL; a negative weight
 // when the resolved solver is max-flow -> ENOTSUBMODULAR.  Stops the loop before any iteration runs.  The
 // accumulated bits move to ctl->vflags (read by the host for the error message) and the accumulator is cleared
 // for the next setup.  Runs in the single thread of a control kernel.
@@ -1821,8 +1862,8 @@ template <int CONN>
 hipError_t conn_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *cw,
                       int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat, int64_t *resid, Ctl *ctl,
                       int64_t mu0, uint64_t eps2, int32_t mu_num, int32_t mu_den, int32_t allow_negative,
-                      hipStream_t s) {
-    const StateInit si{mu0, eps2, mu_num, mu_den, allow_negative};
+                      int32_t t_limit, hipStream_t s) {
+    const StateInit si{mu0, eps2, mu_num, mu_den, allow_negative, t_limit};
     hipLaunchKernelGGL(k_setup<CONN>, dim3(blocks_for(g.W, 256), row_blocks(g)), dim3(256), 0, s, g, u_src, w_src,
                        u_ws, cw, lam_q8, Y, A0, A1, yhat, resid, ctl, si);
     return hipGetLastError();
@@ -1855,7 +1896,7 @@ hipError_t conn_energy(const Geom &g, const int32_t *u, const int32_t *cw, const
 #define DOPE_CONN_ENTRIES(SPEC, C)                                                                                 \
     SPEC template hipError_t conn_setup<C>(const Geom &, const int32_t *, const int32_t *, int32_t *, int32_t *,    \
                                            int32_t, int32_t *, int32_t *, int32_t *, uint8_t *, int64_t *, Ctl *,   \
-                                           int64_t, uint64_t, int32_t, int32_t, int32_t, hipStream_t);              \
+                                           int64_t, uint64_t, int32_t, int32_t, int32_t, int32_t, hipStream_t);     \
     SPEC template hipError_t conn_setup_batch<C>(const Img *, const SetupArg *, const Item *, int32_t, hipStream_t); \
     SPEC template hipError_t conn_solve<C>(const Group &, hipStream_t, hipEvent_t, hipEvent_t);                      \
     SPEC template hipError_t conn_consensus<C>(const Group &, hipStream_t, hipEvent_t, hipEvent_t);                  \
@@ -1894,10 +1935,10 @@ hipError_t by_conn(int32_t conn, F &&f) {
 hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *cw,
                         int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
                         int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,
-                        int32_t allow_negative, hipStream_t s) {
+                        int32_t allow_negative, int32_t t_limit, hipStream_t s) {
     return by_conn(g.conn, [&](auto c) {
         return conn_setup<decltype(c)::value>(g, u_src, w_src, u_ws, cw, lam_q8, Y, A0, A1, yhat, resid, ctl, mu0,
-                                              eps2, mu_num, mu_den, allow_negative, s);
+                                              eps2, mu_num, mu_den, allow_negative, t_limit, s);
     });
 }
 

@@ -563,6 +563,71 @@ def test_async_energy_upload_and_deferred_validation():
         assert e.get_state()[4] == 0                     # no iteration ran
 
 
+def test_solve_straight_after_upload():
+    """A solve straight after an energy upload runs under the loop control that the setup kernel leaves
+    (validated, limit max_iter, halting when the stopping rule holds), with no control-setup launch; a solve after
+    iterate() goes through the control-setup kernel.  Every order equals the oracle, also when max_iter cuts the
+    solve short."""
+    import torch
+    from paper_1704_03116_amd.solver import Dope
+    announce("solve straight after the energy upload")
+    full = synth.config2(W=96, H=80)
+    short = synth.config2(W=96, H=80)
+    short.max_iter = 1
+    for p in (full, short):
+        st_o, infos_o, _, _ = od.run(p)
+        for mode in ("sync", "async", "async-device", "iterate0", "iterate1"):
+            with Dope.from_problem(p) as d:
+                u = np.ascontiguousarray(p.u, np.int32)
+                w = np.ascontiguousarray(p.w, np.int32)
+                if mode == "sync":
+                    d.set_energy(u, w, p.lam_q8)
+                elif mode == "async-device":
+                    d.set_energy_async(torch.from_numpy(u).cuda(), torch.from_numpy(w).cuda(), p.lam_q8)
+                else:
+                    d.set_energy_async(u, w, p.lam_q8)
+                if mode.startswith("iterate"):
+                    d.iterate(int(mode[-1]))
+                info = d.solve()
+                assert info["iters_done"] == len(infos_o), (p.max_iter, mode)
+                assert info["converged"] == infos_o[-1].converged, (p.max_iter, mode)
+                Y, A, yh, mu, t = d.get_state()
+                assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+                assert d.solve()["iters_done"] == len(infos_o)   # nothing more to do
+
+
+def test_setup_verdict_sees_every_workgroup():
+    """The set-up's validation verdict is taken by its last workgroup over the bits of all of them (1024
+    workgroups at 512x512): a single bad weight anywhere is reported, by the blocking and the deferred upload."""
+    from paper_1704_03116_amd import _native as N
+    from paper_1704_03116_amd.solver import Dope
+    announce("setup verdict over every workgroup (512x512)")
+    base = synth.config2()
+    W, H = base.dims[0], base.dims[1]
+    rng = np.random.default_rng(5)
+    cases = []
+    for pos in (0, (H - 2) * W + W - 1, int(rng.integers(W * (H - 1)))):
+        neg = np.array(base.w, np.int32, copy=True)
+        neg[1, pos] = -3           # the (0, 1) edge of a pixel above the last row
+        cases.append((neg, N.DOPE_ENOTSUBMODULAR))
+    off = np.array(base.w, np.int32, copy=True)
+    off[0, W * H - 1] = 7          # +x neighbour of the last pixel lies off the grid
+    cases.append((off, N.DOPE_EINVAL))
+    for w, status in cases:
+        with Dope.from_problem(base, solver="maxflow") as d:
+            with pytest.raises(N.DopeError) as err:
+                d.set_energy(np.ascontiguousarray(base.u, np.int32), w, base.lam_q8)
+            assert err.value.status == status
+            d.set_energy_async(np.ascontiguousarray(base.u, np.int32), w, base.lam_q8)
+            with pytest.raises(N.DopeError) as err:
+                d.solve()
+            assert err.value.status == status
+            assert d.get_state()[4] == 0
+            d.set_energy(np.ascontiguousarray(base.u, np.int32), np.ascontiguousarray(base.w, np.int32),
+                         base.lam_q8)
+            assert d.solve()["converged"]
+
+
 def test_deferred_validation_through_solve_and_batch():
     """The verdict of an asynchronous energy is taken by whichever call comes next: a solve, or a batch; a valid
     energy loaded after an invalid one runs normally."""
