@@ -49,6 +49,8 @@ def workload(name, seed=0):
         return synth.config4(seed=seed)
     if name in ("kernel5", "kernel7", "kernel9"):   # the config2 image with 5x5 / 7x7 / 9x9 neighbourhoods
         return synth.config_kernel(int(name[-1]), seed=seed)
+    if name in ("even32", "even64", "even128"):   # the config2 image in 32 / 64 / 128 even blocks (o = 2)
+        return synth.config2_even(int(name[4:]), seed=seed)
     if name in ("kernel5_3d", "kernel7_3d"):   # the config3 volume with the radius-2 / radius-3 ball
         return synth.config3_kernel5(seed=seed, k=int(name[6]))
     raise SystemExit(f"unknown workload {name}")
@@ -254,6 +256,12 @@ def main():
         # per boundary copy: block label 1 + A 4 read, A 4 written; per boundary pixel: weights 4h read, Y 4 written
         "k_consensus_one": (n_bl * 9 + (n - n_int) * (4 * h + 4), prof["consensus_ms"], prof["consensus_launches"]),
     }
+    np_max = 1
+    for N, B in zip(p.dims, p.block):
+        np_max *= min(N, B) if B > 0 else N
+    if p.solver != "exhaustive" and p.conn in (4, 8, 6) and 64 + np_max * (8 * h + 10) > 160 * 1024:
+        # blocks beyond the LDS: the same block solver with its max-flow state in global memory
+        kernels["k_block_solve_gmem"] = kernels.pop("k_block_solve_one")
     if p.solver == "exhaustive":
         # enumeration of every labelling of every block: 2^|block| codes, about 15 integer operations per Gray-code
         # step (bit flip, unary, the in-block edge deltas, energy update, compare-and-select); VALU-bound

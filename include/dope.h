@@ -94,8 +94,11 @@ typedef struct {
 } dope_info;
 
 /* Validate p and create a context (no device memory is taken until dope_set_energy or a bound workspace).
- * Returns EINVAL for unsupported shapes (block bigger than 160 KiB of LDS, bad overlap, bad stencil, more than
- * 2^30 - 1 pixels in 2D or 2^29 - 1 voxels in 3D, block sizes summing to 2^30 or more). */
+ * Blocks whose max-flow state exceeds the 160 KiB of LDS (the even partitions into 32 to 128 blocks of the 2D experiments, Sec. 3.1) are solved
+ * with that state in the workspace (the block-solve kernel is the same; one workgroup of 1024 threads per block):
+ * 4-, 8- and 6-connected stencils, at most 16384 pixels per block, one image at a time (a batch or a server
+ * rejects them).  Returns EINVAL for unsupported shapes (a block beyond the LDS otherwise, bad overlap, bad
+ * stencil, more than 2^30 - 1 pixels in 2D or 2^29 - 1 voxels in 3D, block sizes summing to 2^30 or more). */
 dope_status dope_create(const dope_params *p, dope_ctx **out);
 
 /* Load the energy (Eq. 1) and reset the ADMM state of Algorithm 1's initialisation: Y = 2^15, A = 0,
@@ -116,7 +119,7 @@ dope_status dope_set_energy(dope_ctx *ctx, const int32_t *u, const int32_t *w, i
 
 /* Same as dope_set_energy but without waiting: the copies, state reset and weight preparation are only
  * enqueued on the context stream (device inputs must stay valid until that work has run).  DOPE_SOLVER_AUTO
- * resolves to max-flow when the block fits the LDS budget, else to the exhaustive solver.  Validation errors
+ * resolves to max-flow when the blocks can take it (see dope_create), else to the exhaustive solver.  Validation errors
  * (EINVAL, ENOTSUBMODULAR) stop the loop on the device and are returned by the next call that reads the state
  * back (dope_iterate, dope_solve, dope_get_state, a batch call, ...). */
 dope_status dope_set_energy_async(dope_ctx *ctx, const int32_t *u, const int32_t *w, int32_t lambda_q8,

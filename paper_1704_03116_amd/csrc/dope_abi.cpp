@@ -38,6 +38,7 @@ struct dope_ctx {
     int2 *blist = nullptr;
     uint8_t *yhat = nullptr, *yslot = nullptr, *labels = nullptr;
     int64_t *resid = nullptr, *epart = nullptr;
+    unsigned char *gscr = nullptr;   // per-block max-flow state of blocks beyond the LDS
     Ctl *hctl = nullptr;       // pinned host mirror of the control block
     std::vector<int32_t> hbtab, hchunk;
     int64_t nbl = 0;   // boundary list entries
@@ -59,10 +60,24 @@ namespace {
 
 struct Layout {
     size_t ctl, img, bitems, citems, queue, btab, chunk, blist, u, w, cw, Y, A0, A1, yhat, yslot, resid, stats, labels,
-        epart, total;
+        epart, gscr, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// The max-flow solver takes the partition's blocks: in LDS, or in global memory for the stencils that have that
+// solver.
+bool maxflow_possible(const Geom &g) {
+    return dope::maxflow_lds_bytes(g.max_np, g.hs) <= dope::LDS_LIMIT ||
+           (dope::conn_has_gmem_solver(g.conn) && g.max_np <= dope::GMEM_MAX_NP);
+}
+
+// Per-block max-flow state in global memory when a block exceeds the LDS (0 otherwise).
+size_t gmem_stride(const Geom &g) {
+    const size_t b = dope::maxflow_lds_bytes(g.max_np, g.hs);
+    return b > dope::LDS_LIMIT ? align256(b) : 0;
+}
+
 
 Layout layout_for(const Geom &g) {
     Layout L{};
@@ -89,6 +104,7 @@ Layout layout_for(const Geom &g) {
     L.stats = take(size_t(g.K) * 16);
     L.labels = take(size_t(g.n));
     L.epart = take(size_t(dope::ENERGY_PARTS) * 8);
+    L.gscr = take(size_t(g.K) * gmem_stride(g));
     L.total = o;
     return L;
 }
@@ -197,16 +213,21 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
     if ((p->mu_fact_num == 0) != (p->mu_fact_den == 0)) return "mu_fact numerator and denominator must both be set";
     if (p->eps_q16 < 0) return "eps_q16 must be >= 0";
     if (p->max_iter < 0) return "max_iter must be >= 0";
+    // blocks beyond the LDS take the global-memory solver (4-, 8- and 6-connected, at most 16384 pixels)
     const bool fits_lds = dope::maxflow_lds_bytes(g.max_np, hs) <= dope::LDS_LIMIT;
+    const bool maxflow_ok = fits_lds || (dope::conn_has_gmem_solver(p->connectivity) && g.max_np <= dope::GMEM_MAX_NP);
+    const char *too_big = fits_lds || !dope::conn_has_gmem_solver(p->connectivity)
+                              ? "block too large for the LDS-resident max-flow solver"
+                              : "block too large: more than 16384 pixels beyond the LDS";
     switch (p->solver) {
         case DOPE_SOLVER_MAXFLOW:
-            if (!fits_lds) return "block too large for the LDS-resident max-flow solver";
+            if (!maxflow_ok) return too_big;
             break;
         case DOPE_SOLVER_EXHAUSTIVE:
             if (g.max_np > 16) return "the exhaustive solver needs blocks of at most 16 pixels";
             break;
         case DOPE_SOLVER_AUTO:
-            if (!fits_lds && g.max_np > 16) return "block too large for the LDS-resident max-flow solver";
+            if (!maxflow_ok && g.max_np > 16) return too_big;
             break;
         default:
             return "unknown solver";
@@ -289,6 +310,7 @@ void assign_pointers(dope_ctx *c) {
     c->stats = reinterpret_cast<int32_t *>(b + L.stats);
     c->labels = reinterpret_cast<uint8_t *>(b + L.labels);
     c->epart = reinterpret_cast<int64_t *>(b + L.epart);
+    c->gscr = gmem_stride(c->g) ? reinterpret_cast<unsigned char *>(b + L.gscr) : nullptr;
 }
 
 dope::Img host_img(const dope_ctx *c) {
@@ -343,6 +365,8 @@ dope_status upload_tables(dope_ctx *c) {
     HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
     c->grp = dope::Group{c->dimg, 1, c->blk_items, c->g.K, c->chk_items, int32_t(ci.size()), c->queue,
                          c->g.conn, 0, c->g.max_np, 0};
+    c->grp.gscratch = c->gscr;
+    c->grp.gstride = gmem_stride(c->g);
     return DOPE_OK;
 }
 
@@ -607,7 +631,7 @@ dope_status dope_set_energy(dope_ctx *c, const int32_t *u, const int32_t *w, int
             solver = DOPE_SOLVER_EXHAUSTIVE;
         }
     } else if (solver == DOPE_SOLVER_AUTO) {
-        solver = dope::maxflow_lds_bytes(g.max_np, g.hs) <= dope::LDS_LIMIT ? DOPE_SOLVER_MAXFLOW : DOPE_SOLVER_EXHAUSTIVE;
+        solver = maxflow_possible(g) ? DOPE_SOLVER_MAXFLOW : DOPE_SOLVER_EXHAUSTIVE;
     }
     c->solver = solver;
     c->lam_q8 = lambda_q8;
@@ -621,8 +645,7 @@ dope_status dope_set_energy_async(dope_ctx *c, const int32_t *u, const int32_t *
     if (!c) return DOPE_EINVAL;
     int solver = c->p.solver;
     if (solver == DOPE_SOLVER_AUTO)
-        solver = dope::maxflow_lds_bytes(c->g.max_np, c->g.hs) <= dope::LDS_LIMIT ? DOPE_SOLVER_MAXFLOW
-                                                                                  : DOPE_SOLVER_EXHAUSTIVE;
+        solver = maxflow_possible(c->g) ? DOPE_SOLVER_MAXFLOW : DOPE_SOLVER_EXHAUSTIVE;
     c->energy_set = false;
     dope_status st = enqueue_energy(c, u, w, lambda_q8, mem_kind, solver == DOPE_SOLVER_EXHAUSTIVE);
     if (st != DOPE_OK) return st;
@@ -989,6 +1012,7 @@ dope_status batch_bind(dope_batch *b, dope_ctx *const *ctxs, int32_t n) {
         if (i == 0) { conn = c->g.conn; solver = c->solver; }
         if (c->g.conn != conn || c->solver != solver)
             return bfail(b, DOPE_EINVAL, "batch members must share connectivity and solver");
+        if (c->gscr) return bfail(b, DOPE_EINVAL, "blocks beyond the LDS are solved one image at a time");
     }
     int64_t nblk = 0, nchk = 0, nrow = 0;
     int32_t npmax = 0;
@@ -1419,6 +1443,11 @@ dope_status dope_server_submit(dope_server *s, const dope_params *p, const int32
     q.stream = s->stream;
     const size_t bytes = dope_workspace_bytes(&q);
     if (bytes == 0) return sfail(s, DOPE_EINVAL, "invalid request parameters");
+    {
+        Geom g;
+        if (!make_geom(&q, g, nullptr).empty() || gmem_stride(g))
+            return sfail(s, DOPE_EINVAL, "blocks beyond the LDS are solved one image at a time");
+    }
     if (s->conn == 0) s->conn = q.connectivity;
     if (q.connectivity != s->conn) return sfail(s, DOPE_EINVAL, "requests of a server must share connectivity");
     const size_t need = align256(bytes);

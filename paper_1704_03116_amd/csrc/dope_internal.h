@@ -115,6 +115,10 @@ inline __host__ __device__ constexpr size_t maxflow_lds_bytes(int np, int hs) {
     return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 8 ? 16 : (mb > 1 ? 8 : 0));
 }
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
+// Blocks beyond the LDS: stencils with a global-memory block solver, and its largest block (1024 threads with at
+// most 16 pixels each).
+constexpr bool conn_has_gmem_solver(int conn) { return conn == 4 || conn == 8 || conn == 6; }
+constexpr int GMEM_MAX_NP = 16384;
 constexpr int NUM_CUS = 256;          // MI355X compute units
 
 
@@ -172,6 +176,10 @@ struct Group {
     // buffer parity (t & 1) of the iteration being enqueued.  Null for batches (read from device memory).
     const Img *one = nullptr;
     int32_t par = 0;
+    // One-image groups whose blocks exceed the LDS: the max-flow state of workgroup b lives at
+    // gscratch + b * gstride (gstride >= maxflow_lds_bytes(npmax, h)); null otherwise.
+    unsigned char *gscratch = nullptr;
+    uint64_t gstride = 0;
 };
 
 // One ADMM iteration (block solves, consensus and multipliers, loop control) for every image of the group.

@@ -902,6 +902,19 @@ __global__ __launch_bounds__(NT, 2) void k_block_solve_one(const Img one, int32_
                             true);
 }
 
+// One-image block solve for blocks whose max-flow state exceeds the LDS (large blocks of the paper's even
+// partitions): the same solver with its node arrays in a global-memory region of the workgroup's own,
+// scratch + b * stride (stride >= maxflow_lds_bytes(npmax, h)), which stays mostly in the L2.  Barriers order
+// these accesses as they do LDS ones (workgroup-scope fences; the waves of a workgroup share one CU).
+template <int CONN, int NT>
+__global__ __launch_bounds__(NT, 2) void k_block_solve_gmem(const Img one, int32_t par, int32_t npmax,
+                                                         int32_t round_limit, int32_t relabel_period,
+                                                         unsigned char *scratch, uint64_t stride) {
+    unsigned char *mem = scratch + uint64_t(blockIdx.x) * stride;
+    block_maxflow<CONN, NT>(one, xcd_item(blockIdx.x, gridDim.x), mem, npmax, round_limit, relabel_period, par,
+                            true);
+}
+
 // ------------------------------------------------------------------------------------------------------------
 // Exhaustive block solve (blocks of at most 16 pixels, any sign of the weights)
 // ------------------------------------------------------------------------------------------------------------
@@ -1812,6 +1825,21 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s, hipEvent_t e0, hipEve
 }
 
 template <int CONN>
+hipError_t launch_maxflow_gmem(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    constexpr int NT = 1024;
+    if (!grp.one || grp.npmax > GMEM_MAX_NP || grp.gstride < maxflow_lds_bytes(grp.npmax, Sten<CONN>::H))
+        return hipErrorInvalidValue;
+    const int32_t round_limit = 65536 + 64 * grp.npmax;
+    const int32_t relabel_period = 8;
+    const dim3 grid(unsigned(grp.n_blk_items));
+    if (e0) hipExtLaunchKernelGGL(k_block_solve_gmem<CONN, NT>, grid, dim3(NT), 0u, s, e0, e1, 0u, *grp.one, grp.par,
+                                  grp.npmax, round_limit, relabel_period, grp.gscratch, grp.gstride);
+    else hipLaunchKernelGGL((k_block_solve_gmem<CONN, NT>), grid, dim3(NT), 0, s, *grp.one, grp.par, grp.npmax,
+                            round_limit, relabel_period, grp.gscratch, grp.gstride);
+    return hipGetLastError();
+}
+
+template <int CONN>
 hipError_t solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (grp.solver == 2) {
         if (e0) {
@@ -1822,6 +1850,10 @@ hipError_t solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_
         hipLaunchKernelGGL(k_block_exhaustive<CONN>, dim3(blocks_for(grp.n_blk_items, EX_WAVES)), dim3(256), 0, s,
                            grp.imgs, grp.blk_items, grp.n_blk_items);
         return hipGetLastError();
+    }
+    if (grp.gscratch) {   // blocks beyond the LDS
+        if constexpr (conn_has_gmem_solver(CONN)) return launch_maxflow_gmem<CONN>(grp, s, e0, e1);
+        else return hipErrorInvalidValue;
     }
     // Workgroup size: blocks of more than 512 pixels use 1024 threads when every block gets a CU of its own
     // (or when the LDS footprint allows only one block per CU), otherwise 512 threads so that all blocks are

@@ -18,6 +18,7 @@ from .configs import (  # noqa: F401
     Problem,
     config1,
     config2,
+    config2_even,
     config3,
     config4,
     config5_request,

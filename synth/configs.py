@@ -176,6 +176,19 @@ def config2(seed: int = 0, W: int = 512, H: int = 512, mu0: int = DEFAULT_MU0_2D
                    truth=fg.reshape(-1).astype(np.uint8))
 
 
+def config2_even(K: int, seed: int = 0, W: int = 512, H: int = 512, mu0: int = DEFAULT_MU0_2D) -> Problem:
+    """The config2 image split into K even blocks (the 2D experiments' partitions into 32, 64 or 128 blocks):
+    8 x 4, 8 x 8 or 16 x 8 blocks with o = 2, each the smallest size whose partition has that many blocks per
+    axis (66 x 130, 66 x 66 or 34 x 66 at 512 x 512).  With 32 and 64 blocks the max-flow state of a block
+    exceeds the LDS."""
+    nbx, nby = {32: (8, 4), 64: (8, 8), 128: (16, 8)}[K]
+    o = 2
+    base = config2(seed=seed, W=W, H=H, mu0=mu0)
+    size = lambda N, nb: -(-(N + (nb - 1) * o) // nb)   # noqa: E731
+    return dataclasses.replace(base, name=f"config2_even{K}_ellipses{W}x{H}_8conn",
+                               block=(size(W, nbx), size(H, nby), 1), overlap=(o, o, 0))
+
+
 def config3(seed: int = 0, dims=(128, 128, 64), mu0: int = DEFAULT_MU0_3D) -> Problem:
     """128x128x64 volume with 3 random spheres (r in U[8, 24]) + N(0, 0.2^2); 6-connected constant Potts
     w = 1000; lambda = 1.5; 16^3 blocks, o = 1."""

@@ -112,7 +112,7 @@ def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, n
     (dict(overlap=(17, 2, 0)), "overlap"),
     (dict(conn=6), "connectivity"),
     (dict(mu0=0), "mu0"),
-    (dict(block=(64, 64, 1)), "LDS"),                     # 64x64 8-connected exceeds 160 KiB of LDS
+    (dict(block=(160, 160, 1)), "16384 pixels"),          # beyond the LDS and beyond the global-memory solver
     (dict(block=(32, 32, 1), solver=2), "exhaustive"),    # enumeration needs <= 16 pixels
     (dict(dims=(0, 5, 1)), "dims"),
     (dict(conn=48), "LDS"),                               # 32x32 blocks with 7x7 neighbourhoods: 209 B per node
@@ -128,6 +128,27 @@ def test_create_rejects_bad_params(native, kw, msg):
     assert native.dope_create(ctypes.byref(p), ctypes.byref(ctx)) == native.DOPE_EINVAL
     assert msg in native.dope_last_error(None).decode()
     assert native.dope_workspace_bytes(ctypes.byref(p)) == 0
+
+
+@pytest.mark.parametrize("dims,conn,block,overlap,ndim", [
+    ((512, 512, 1), 8, (64, 64, 1), (2, 2, 0), 2),       # 4356-node blocks: 183 KB of max-flow state each
+    ((300, 200, 1), 4, (100, 100, 1), (1, 1, 0), 2),
+    ((64, 64, 48), 6, (24, 24, 24), (1, 1, 1), 3),
+])
+def test_blocks_beyond_lds_take_workspace_state(native, dims, conn, block, overlap, ndim):
+    """Blocks whose max-flow state exceeds the LDS are accepted for the 4-, 8- and 6-connected stencils, with each
+    block's state (64 + np (8h + 9 + 1) bytes for the largest block, 256-aligned) after the workspace layout of
+    the LDS path."""
+    from oracle import dope as od
+    p = _params(native, dims, conn, block, overlap, ndim=ndim)     # accepted: a nonzero workspace size
+    blocks = od.make_blocks(dims, block, overlap)
+    h = {4: 2, 8: 4, 6: 3}[conn]
+    np_max = max(len(b.idx) for b in blocks)
+    per_block = (64 + np_max * (8 * h + 9 + 1) + 255) // 256 * 256
+    assert per_block > 160 * 1024
+    tot = sum(len(b.idx) for b in blocks)
+    base = _workspace_model(dims, h, len(blocks), tot, _interior_count(dims, block, overlap))
+    assert native.dope_workspace_bytes(ctypes.byref(p)) == base + len(blocks) * per_block
 
 
 def test_last_error_null_safe(native):

@@ -3,6 +3,8 @@
 Small problems are compared on the whole state (Y, A, block labels, mu, t, per-block residuals) after every
 iteration.  Full-size workloads are compared on sampled block solves and on the complete consensus /
 multiplier update, both recomputed by the oracle from the GPU's own state of the previous iteration."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -561,6 +563,50 @@ def test_async_energy_upload_and_deferred_validation():
             e.iterate(1)
         assert err.value.status == N.DOPE_ENOTSUBMODULAR
         assert e.get_state()[4] == 0                     # no iteration ran
+
+
+BEYOND_LDS_CASES = [
+    ("8-connected 2x2 blocks of 98x82", lambda: dataclasses.replace(synth.config2(W=192, H=160), block=(98, 82, 1))),
+    ("4-connected 3x2 blocks of 112x100", lambda: synth.random_problem(21, (230, 150, 1), 4, (112, 100, 1),
+                                                                         (1, 1, 0))),
+    ("6-connected 2x2x2 blocks of 22x20x16", lambda: synth.random_problem(22, (40, 36, 30), 6, (22, 20, 16),
+                                                                            (1, 1, 1))),
+]
+
+
+@pytest.mark.parametrize("label,make", BEYOND_LDS_CASES, ids=[c[0] for c in BEYOND_LDS_CASES])
+def test_blocks_beyond_lds_every_iteration(label, make):
+    """Blocks whose max-flow state exceeds the LDS (7040 to 11200 nodes) run the same solver with that state in
+    the workspace: Y, A, yhat, mu, t and the block residuals equal the oracle's after every iteration."""
+    p = make()
+    d, st_o, dec = run_parity(p, 6, f"beyond LDS, {label}")
+    d.close()
+
+
+@pytest.mark.parametrize("K", [32, 64])
+def test_even_partition_full_solve(K):
+    """The 512x512 image split into 32 or 64 even blocks (66x130 / 66x66 pixels, beyond the LDS): the solve
+    equals the oracle's (iterations, state, labels, energy); a batch refuses such blocks."""
+    from paper_1704_03116_amd import _native as N
+    from paper_1704_03116_amd.solver import Batch
+    p = synth.config2_even(K)
+    announce(f"even partition K={K}: block={p.block}")
+    st_o, infos, _, dec = od.run(p)
+    d = make_ctx(p)
+    try:
+        info = d.solve()
+        assert info["iters_done"] == len(infos)
+        assert info["converged"] == infos[-1].converged
+        Y, A, yh, mu, t = d.get_state()
+        assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+        l = d.labels()
+        assert np.array_equal(l, od.labels(st_o.Y))
+        assert d.energy() == od.energy_q(dec, l)
+        with pytest.raises(N.DopeError) as err:
+            Batch([d])
+        assert err.value.status == N.DOPE_EINVAL
+    finally:
+        d.close()
 
 
 def test_solve_straight_after_upload():
