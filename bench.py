@@ -10,6 +10,7 @@ HBM bytes of one launch (per block pixel: u 4 + weights 4h + Y 4 + A 4 + block l
 duration, timed with HIP events on the launch stream inside the timed region.  cpu_baseline times the CPU
 oracle on the same workload."""
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -53,6 +54,11 @@ def workload(name, seed=0):
         return synth.config2_even(int(name[4:]), seed=seed)
     if name in ("kernel5_3d", "kernel7_3d"):   # the config3 volume with the radius-2 / radius-3 ball
         return synth.config3_kernel5(seed=seed, k=int(name[6]))
+    if name in ("kernel5_3d_big", "kernel7_3d_big"):   # the same with 16^3 / 12^3 blocks (beyond the LDS)
+        k = int(name[6])
+        b = 16 if k == 5 else 12
+        p = synth.config3_kernel5(seed=seed, k=k)
+        return dataclasses.replace(p, name=p.name.replace("_spheres", f"_blocks{b}_spheres"), block=(b, b, b))
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -259,7 +265,9 @@ def main():
     np_max = 1
     for N, B in zip(p.dims, p.block):
         np_max *= min(N, B) if B > 0 else N
-    if p.solver != "exhaustive" and p.conn in (4, 8, 6) and 64 + np_max * (8 * h + 10) > 160 * 1024:
+    mb = 1 if 2 * h <= 8 else (4 if 2 * h <= 32 else (8 if 2 * h <= 64 else 16))   # direction-mask bytes per node
+    state = 64 + np_max * (8 * h + 9 + mb) + (16 if mb > 8 else (8 if mb > 1 else 0))
+    if p.solver != "exhaustive" and state > 160 * 1024:
         # blocks beyond the LDS: the same block solver with its max-flow state in global memory
         kernels["k_block_solve_gmem"] = kernels.pop("k_block_solve_one")
     if p.solver == "exhaustive":

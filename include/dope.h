@@ -95,9 +95,9 @@ typedef struct {
 
 /* Validate p and create a context (no device memory is taken until dope_set_energy or a bound workspace).
  * Blocks whose max-flow state exceeds the 160 KiB of LDS (the even partitions into 32 to 128 blocks of the 2D experiments, Sec. 3.1) are solved
- * with that state in the workspace (the block-solve kernel is the same; one workgroup of 1024 threads per block):
- * 4-, 8- and 6-connected stencils, at most 16384 pixels per block, one image at a time (a batch or a server
- * rejects them).  Returns EINVAL for unsupported shapes (a block beyond the LDS otherwise, bad overlap, bad
+ * with that state in the workspace (the block-solve kernel is the same; one workgroup per block of 1024 threads
+ * for the 4-, 8- and 6-connected stencils, 256 for the wider ones), at most 16 pixels per thread (16384 or 4096
+ * per block), one image at a time (a batch or a server rejects them).  Returns EINVAL for unsupported shapes (a block beyond the LDS otherwise, bad overlap, bad
  * stencil, more than 2^30 - 1 pixels in 2D or 2^29 - 1 voxels in 3D, block sizes summing to 2^30 or more). */
 dope_status dope_create(const dope_params *p, dope_ctx **out);
 

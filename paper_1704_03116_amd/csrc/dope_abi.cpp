@@ -68,8 +68,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // The max-flow solver takes the partition's blocks: in LDS, or in global memory for the stencils that have that
 // solver.
 bool maxflow_possible(const Geom &g) {
-    return dope::maxflow_lds_bytes(g.max_np, g.hs) <= dope::LDS_LIMIT ||
-           (dope::conn_has_gmem_solver(g.conn) && g.max_np <= dope::GMEM_MAX_NP);
+    return dope::maxflow_lds_bytes(g.max_np, g.hs) <= dope::LDS_LIMIT || g.max_np <= dope::gmem_max_np(g.conn);
 }
 
 // Per-block max-flow state in global memory when a block exceeds the LDS (0 otherwise).
@@ -213,12 +212,13 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
     if ((p->mu_fact_num == 0) != (p->mu_fact_den == 0)) return "mu_fact numerator and denominator must both be set";
     if (p->eps_q16 < 0) return "eps_q16 must be >= 0";
     if (p->max_iter < 0) return "max_iter must be >= 0";
-    // blocks beyond the LDS take the global-memory solver (4-, 8- and 6-connected, at most 16384 pixels)
-    const bool fits_lds = dope::maxflow_lds_bytes(g.max_np, hs) <= dope::LDS_LIMIT;
-    const bool maxflow_ok = fits_lds || (dope::conn_has_gmem_solver(p->connectivity) && g.max_np <= dope::GMEM_MAX_NP);
-    const char *too_big = fits_lds || !dope::conn_has_gmem_solver(p->connectivity)
-                              ? "block too large for the LDS-resident max-flow solver"
-                              : "block too large: more than 16384 pixels beyond the LDS";
+    // blocks beyond the LDS take the global-memory solver (at most 16384 pixels with the 3x3 stencils, 4096 with
+    // the wide ones)
+    const bool maxflow_ok = dope::maxflow_lds_bytes(g.max_np, hs) <= dope::LDS_LIMIT ||
+                            g.max_np <= dope::gmem_max_np(p->connectivity);
+    const std::string too_big_msg = "block too large for the max-flow solver: more than " +
+                                    std::to_string(dope::gmem_max_np(p->connectivity)) + " pixels beyond the LDS";
+    const char *too_big = too_big_msg.c_str();
     switch (p->solver) {
         case DOPE_SOLVER_MAXFLOW:
             if (!maxflow_ok) return too_big;

@@ -115,10 +115,10 @@ inline __host__ __device__ constexpr size_t maxflow_lds_bytes(int np, int hs) {
     return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 8 ? 16 : (mb > 1 ? 8 : 0));
 }
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
-// Blocks beyond the LDS: stencils with a global-memory block solver, and its largest block (1024 threads with at
-// most 16 pixels each).
-constexpr bool conn_has_gmem_solver(int conn) { return conn == 4 || conn == 8 || conn == 6; }
-constexpr int GMEM_MAX_NP = 16384;
+// Blocks beyond the LDS: workgroup size of the global-memory block solver (1024 threads for the 3x3 stencils, 256
+// for the wide ones, whose solver needs more registers) and its largest block (at most 16 pixels per thread).
+constexpr int gmem_threads(int conn) { return (conn == 4 || conn == 8 || conn == 6) ? 1024 : 256; }
+constexpr int gmem_max_np(int conn) { return 16 * gmem_threads(conn); }
 constexpr int NUM_CUS = 256;          // MI355X compute units
 
 

@@ -903,7 +903,8 @@ __global__ __launch_bounds__(NT, 2) void k_block_solve_one(const Img one, int32_
 }
 
 // One-image block solve for blocks whose max-flow state exceeds the LDS (large blocks of the paper's even
-// partitions): the same solver with its node arrays in a global-memory region of the workgroup's own,
+// partitions, or blocks of the wide stencils larger than a few hundred pixels): the same solver with its node
+// arrays in a global-memory region of the workgroup's own,
 // scratch + b * stride (stride >= maxflow_lds_bytes(npmax, h)), which stays mostly in the L2.  Barriers order
 // these accesses as they do LDS ones (workgroup-scope fences; the waves of a workgroup share one CU).
 template <int CONN, int NT>
@@ -1826,8 +1827,8 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s, hipEvent_t e0, hipEve
 
 template <int CONN>
 hipError_t launch_maxflow_gmem(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    constexpr int NT = 1024;
-    if (!grp.one || grp.npmax > GMEM_MAX_NP || grp.gstride < maxflow_lds_bytes(grp.npmax, Sten<CONN>::H))
+    constexpr int NT = gmem_threads(CONN);
+    if (!grp.one || grp.npmax > gmem_max_np(CONN) || grp.gstride < maxflow_lds_bytes(grp.npmax, Sten<CONN>::H))
         return hipErrorInvalidValue;
     const int32_t round_limit = 65536 + 64 * grp.npmax;
     const int32_t relabel_period = 8;
@@ -1851,10 +1852,7 @@ hipError_t solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_
                            grp.imgs, grp.blk_items, grp.n_blk_items);
         return hipGetLastError();
     }
-    if (grp.gscratch) {   // blocks beyond the LDS
-        if constexpr (conn_has_gmem_solver(CONN)) return launch_maxflow_gmem<CONN>(grp, s, e0, e1);
-        else return hipErrorInvalidValue;
-    }
+    if (grp.gscratch) return launch_maxflow_gmem<CONN>(grp, s, e0, e1);   // blocks beyond the LDS
     // Workgroup size: blocks of more than 512 pixels use 1024 threads when every block gets a CU of its own
     // (or when the LDS footprint allows only one block per CU), otherwise 512 threads so that all blocks are
     // resident at once and neighbours on a CU hide each other's barrier and LDS latency.  Measured on MI355X with

@@ -115,10 +115,10 @@ def test_workspace_bytes_matches_partition(native, dims, conn, block, overlap, n
     (dict(block=(160, 160, 1)), "16384 pixels"),          # beyond the LDS and beyond the global-memory solver
     (dict(block=(32, 32, 1), solver=2), "exhaustive"),    # enumeration needs <= 16 pixels
     (dict(dims=(0, 5, 1)), "dims"),
-    (dict(conn=48), "LDS"),                               # 32x32 blocks with 7x7 neighbourhoods: 209 B per node
+    (dict(conn=48, block=(80, 80, 1)), "4096 pixels"),    # 7x7 neighbourhoods beyond the LDS: 256 threads x 16 px
     (dict(conn=48, block=(4, 4, 1), overlap=(2, 2, 0)), "stencil radius"),   # stride 2 < radius 3
     (dict(conn=24, ndim=3, dims=(16, 16, 16), block=(8, 8, 8), overlap=(1, 1, 1)), "connectivity"),
-    (dict(conn=32, ndim=3, dims=(64, 64, 64), block=(16, 16, 16), overlap=(1, 1, 1)), "LDS"),   # 141 B per node
+    (dict(conn=32, ndim=3, dims=(64, 64, 64), block=(20, 20, 20), overlap=(1, 1, 1)), "4096 pixels"),
     (dict(dims=(32768, 32768, 1)), "grid too large"),      # 2^30 pixels: 32-bit byte offsets no longer suffice
     (dict(conn=6, ndim=3, dims=(1024, 1024, 512), block=(16, 16, 16), overlap=(1, 1, 1)), "grid too large"),
 ])
@@ -134,20 +134,25 @@ def test_create_rejects_bad_params(native, kw, msg):
     ((512, 512, 1), 8, (64, 64, 1), (2, 2, 0), 2),       # 4356-node blocks: 183 KB of max-flow state each
     ((300, 200, 1), 4, (100, 100, 1), (1, 1, 0), 2),
     ((64, 64, 48), 6, (24, 24, 24), (1, 1, 1), 3),
+    ((200, 150, 1), 48, (48, 48, 1), (3, 3, 0), 2),      # 7x7: 209 B per node
+    ((40, 36, 30), 122, (12, 12, 12), (1, 1, 1), 3),     # radius-3 ball: 513 B per node
 ])
 def test_blocks_beyond_lds_take_workspace_state(native, dims, conn, block, overlap, ndim):
-    """Blocks whose max-flow state exceeds the LDS are accepted for the 4-, 8- and 6-connected stencils, with each
-    block's state (64 + np (8h + 9 + 1) bytes for the largest block, 256-aligned) after the workspace layout of
-    the LDS path."""
+    """Blocks whose max-flow state exceeds the LDS are accepted, with each block's state (64 + np (8h + 9 + m)
+    bytes, m the direction-mask bytes, plus alignment, for the largest block, 256-aligned) after the workspace
+    layout of the LDS path."""
     from oracle import dope as od
     p = _params(native, dims, conn, block, overlap, ndim=ndim)     # accepted: a nonzero workspace size
     blocks = od.make_blocks(dims, block, overlap)
-    h = {4: 2, 8: 4, 6: 3}[conn]
+    h = {4: 2, 8: 4, 6: 3, 48: 24, 122: 61}[conn]
+    r = {48: 3, 122: 3}.get(conn, 1)
+    mb = 1 if 2 * h <= 8 else (4 if 2 * h <= 32 else (8 if 2 * h <= 64 else 16))   # direction-mask bytes
+    slack = 16 if mb > 8 else (8 if mb > 1 else 0)
     np_max = max(len(b.idx) for b in blocks)
-    per_block = (64 + np_max * (8 * h + 9 + 1) + 255) // 256 * 256
+    per_block = (64 + np_max * (8 * h + 9 + mb) + slack + 255) // 256 * 256
     assert per_block > 160 * 1024
     tot = sum(len(b.idx) for b in blocks)
-    base = _workspace_model(dims, h, len(blocks), tot, _interior_count(dims, block, overlap))
+    base = _workspace_model(dims, h, len(blocks), tot, _interior_count(dims, block, overlap, r))
     assert native.dope_workspace_bytes(ctypes.byref(p)) == base + len(blocks) * per_block
 
 

@@ -571,13 +571,22 @@ BEYOND_LDS_CASES = [
                                                                          (1, 1, 0))),
     ("6-connected 2x2x2 blocks of 22x20x16", lambda: synth.random_problem(22, (40, 36, 30), 6, (22, 20, 16),
                                                                             (1, 1, 1))),
+    ("5x5 2x2 blocks of 60x60", lambda: synth.random_problem(26, (118, 100, 1), 24, (60, 60, 1), (2, 2, 0))),
+    ("7x7 2x2 blocks of 48x48", lambda: synth.random_problem(23, (90, 88, 1), 48, (48, 48, 1), (3, 3, 0))),
+    ("9x9 2x2 blocks of 40x40", lambda: synth.random_problem(24, (70, 66, 1), 80, (40, 40, 1), (4, 4, 0),
+                                                             w_range=(0, 400))),   # 80 edges: sum |c| < 2^29
+    ("radius-2 ball 2x2x2 blocks of 14^3", lambda: synth.random_problem(25, (26, 24, 22), 32, (14, 14, 14),
+                                                                          (2, 2, 2))),
+    ("radius-3 ball 2x2x2 blocks of 12^3", lambda: dataclasses.replace(
+        synth.config3_kernel5(dims=(22, 22, 20), k=7), block=(12, 12, 12), overlap=(1, 1, 1))),
 ]
 
 
 @pytest.mark.parametrize("label,make", BEYOND_LDS_CASES, ids=[c[0] for c in BEYOND_LDS_CASES])
 def test_blocks_beyond_lds_every_iteration(label, make):
-    """Blocks whose max-flow state exceeds the LDS (7040 to 11200 nodes) run the same solver with that state in
-    the workspace: Y, A, yhat, mu, t and the block residuals equal the oracle's after every iteration."""
+    """Blocks whose max-flow state exceeds the LDS (7040 to 11200 nodes with the 3x3 stencils, 1600 to 3600 with
+    the wide ones) run the same solver with that state in the workspace: Y, A, yhat, mu, t and the block
+    residuals equal the oracle's after every iteration."""
     p = make()
     d, st_o, dec = run_parity(p, 6, f"beyond LDS, {label}")
     d.close()
