@@ -911,9 +911,11 @@ template <int CONN, int NT>
 __global__ __launch_bounds__(NT, 2) void k_block_solve_gmem(const Img one, int32_t par, int32_t npmax,
                                                          int32_t round_limit, int32_t relabel_period,
                                                          unsigned char *scratch, uint64_t stride) {
+    // a skipped iteration returns before the prologue, whose state would go to global memory
+    if (ctl_skip(one.ctl)) return;
     unsigned char *mem = scratch + uint64_t(blockIdx.x) * stride;
     block_maxflow<CONN, NT>(one, xcd_item(blockIdx.x, gridDim.x), mem, npmax, round_limit, relabel_period, par,
-                            true);
+                            false);
 }
 
 // ------------------------------------------------------------------------------------------------------------
