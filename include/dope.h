@@ -94,11 +94,12 @@ typedef struct {
 } dope_info;
 
 /* Validate p and create a context (no device memory is taken until dope_set_energy or a bound workspace).
- * Blocks whose max-flow state exceeds the 160 KiB of LDS (the even partitions into 32 to 128 blocks of the 2D experiments, Sec. 3.1) are solved
- * with that state in the workspace (the block-solve kernel is the same; one workgroup per block of 1024 threads
- * for the 4-, 8- and 6-connected stencils, 256 for the wider ones), at most 16 pixels per thread (16384 or 4096
- * per block), one image at a time (a batch or a server rejects them).  Returns EINVAL for unsupported shapes (a block beyond the LDS otherwise, bad overlap, bad
- * stencil, more than 2^30 - 1 pixels in 2D or 2^29 - 1 voxels in 3D, block sizes summing to 2^30 or more). */
+ * Blocks whose max-flow state exceeds the 160 KiB of LDS (such as the even partitions into 32 to 128 blocks of
+ * the 2D experiments, Sec. 3.1) are solved with that state in the workspace (the block-solve kernel is the same;
+ * one workgroup per block, of 1024 threads for the 4-, 8- and 6-connected stencils and 256 for the wider ones,
+ * with at most 16 pixels per thread: 16384 or 4096 per block), one image at a time (a batch or a server rejects
+ * them).  Returns EINVAL for unsupported shapes (a larger block, bad overlap, bad stencil, more than 2^30 - 1
+ * pixels in 2D or 2^29 - 1 voxels in 3D, block sizes summing to 2^30 or more). */
 dope_status dope_create(const dope_params *p, dope_ctx **out);
 
 /* Load the energy (Eq. 1) and reset the ADMM state of Algorithm 1's initialisation: Y = 2^15, A = 0,
