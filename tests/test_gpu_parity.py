@@ -683,6 +683,24 @@ def test_setup_verdict_sees_every_workgroup():
             assert d.solve()["converged"]
 
 
+def test_upload_after_an_unvalidated_rejected_one():
+    """Two uploads in a row with no readback between them: the first (negative weights, max-flow solver) is
+    rejected by its verdict, taken before the second set-up runs, so its bits do not reach the second's; the
+    second solves like the oracle."""
+    from paper_1704_03116_amd.solver import Dope
+    announce("upload after an unvalidated rejected upload")
+    q = synth.random_problem(16, (20, 20, 1), 4, (8, 8, 1), (1, 1, 0), neg_frac=0.3)
+    good = synth.random_problem(17, (20, 20, 1), 4, (8, 8, 1), (1, 1, 0))
+    st_o, infos, _, _ = od.run(good)
+    with Dope.from_problem(good, solver="maxflow") as e:
+        e.set_energy_async(q.u, q.w, q.lam_q8)
+        e.set_energy_async(good.u, good.w, good.lam_q8)
+        info = e.solve()
+        assert info["iters_done"] == len(infos)
+        Y, A, yh, mu, t = e.get_state()
+        assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+
+
 def test_deferred_validation_through_solve_and_batch():
     """The verdict of an asynchronous energy is taken by whichever call comes next: a solve, or a batch; a valid
     energy loaded after an invalid one runs normally."""
