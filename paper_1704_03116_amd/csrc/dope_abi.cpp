@@ -5,6 +5,7 @@
 #include "dope_internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <deque>
@@ -42,6 +43,7 @@ struct dope_ctx {
     Ctl *hctl = nullptr;       // pinned host mirror of the control block
     std::vector<int32_t> hbtab, hchunk;
     int64_t nbl = 0;   // boundary list entries
+    int64_t seq = 0;   // number of the last chunk readback enqueued (the mirror's last word once it has landed)
     dope::Img *dimg = nullptr;          // this context's descriptor (device)
     dope::Item *blk_items = nullptr, *chk_items = nullptr;
     dope::Queue *queue = nullptr;
@@ -405,6 +407,24 @@ dope_status wait_stream(dope_ctx *c) {
     return DOPE_OK;
 }
 
+// Waits for the mirror of the chunk enqueued last: its loop-control kernel writes the mirror and then, with
+// system-scope release, the chunk's readback number; polling that word returns as soon as it lands, ahead of the
+// kernel's completion signal.  A chunk still running after a few milliseconds falls back to the stream event,
+// which also reports a failed kernel.
+dope_status wait_mirror(dope_ctx *c) {
+    const int64_t want = c->seq;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int spin = 0;; ++spin) {
+        if (__atomic_load_n(&c->hctl->seq, __ATOMIC_ACQUIRE) == want) return DOPE_OK;
+        if ((spin & 255) == 255 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) break;
+    }
+    dope_status st = wait_stream(c);
+    if (st != DOPE_OK) return st;
+    if (__atomic_load_n(&c->hctl->seq, __ATOMIC_ACQUIRE) != want)
+        return fail(c, DOPE_EDEVICE, "loop-control readback: the mirror was not written");
+    return DOPE_OK;
+}
+
 dope_status sync_ctl(dope_ctx *c) {
     // a pending energy validation is taken before the loop control is read back
     if (c->validate_pending) {
@@ -441,8 +461,9 @@ dope_status enqueue_iterations(dope_ctx *c, int count) {
     for (int it = 0; it < count; ++it) {
         c->grp.par = (c->hctl->t + it) & 1;
         Ctl *mirror = it == count - 1 ? c->hctl : nullptr;
+        const int64_t seq = mirror ? ++c->seq : 0;
         if (!c->profiling) {
-            HIP_TRY(c, dope::launch_iteration(c->grp, c->stream, mirror), "iteration launch");
+            HIP_TRY(c, dope::launch_iteration(c->grp, c->stream, mirror, seq), "iteration launch");
             continue;
         }
         hipEvent_t e0 = next_event(c->ev_solve, 2 * c->n_solve), e1 = next_event(c->ev_solve, 2 * c->n_solve + 1);
@@ -454,14 +475,14 @@ dope_status enqueue_iterations(dope_ctx *c, int count) {
         HIP_TRY(c, dope::launch_consensus_phase(c->grp, c->stream, e0 && e1 ? e0 : nullptr, e0 && e1 ? e1 : nullptr),
                 "consensus launch");
         if (e0 && e1 && c->grp.n_chk_items > 0) ++c->n_cons;
-        HIP_TRY(c, dope::launch_finalize_phase(c->grp, c->stream, mirror), "finalize launch");
+        HIP_TRY(c, dope::launch_finalize_phase(c->grp, c->stream, mirror, seq), "finalize launch");
     }
     return DOPE_OK;
 }
 
 // The loop control after enqueue_iterations(c, count): the mirror is written by the last loop-control kernel when
 // count > 0, otherwise it is copied back.
-dope_status read_back(dope_ctx *c, int count) { return count > 0 ? wait_stream(c) : sync_ctl(c); }
+dope_status read_back(dope_ctx *c, int count) { return count > 0 ? wait_mirror(c) : sync_ctl(c); }
 
 dope_status check_ready(dope_ctx *c) {
     if (!c) return DOPE_EINVAL;

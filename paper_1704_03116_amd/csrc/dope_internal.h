@@ -91,6 +91,8 @@ struct Ctl {
     int32_t vflags;            // validation bits of the last set_energy
     int32_t vpending;          // a set_energy awaits its validation (done by the next control setup kernel)
     int32_t allow_negative;    // the resolved solver of that set_energy accepts negative weights
+    int32_t spare;
+    int64_t seq;               // host mirror only: number of the readback whose loop-control kernel wrote it last
 };
 
 enum : int32_t { FLAG_OFFGRID = 1, FLAG_NEGATIVE = 2, FLAG_TOOBIG = 4 };
@@ -184,7 +186,8 @@ struct Group {
 
 // One ADMM iteration (block solves, consensus and multipliers, loop control) for every image of the group.
 // mirror: host-visible copy of the one-image loop control that the finalize kernel refreshes (or nullptr)
-hipError_t launch_iteration(const Group &grp, hipStream_t s, Ctl *mirror = nullptr);
+// seq: written into the mirror after the rest of it (system-scope fence between), so that the host can poll it
+hipError_t launch_iteration(const Group &grp, hipStream_t s, Ctl *mirror = nullptr, int64_t seq = 0);
 // Per-image loop setup of a batch: params[2 i] = t_limit, params[2 i + 1] = stop_on_converge.
 hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params, hipStream_t s);
 // Individual phases (used for per-kernel timing).
@@ -192,7 +195,7 @@ hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params,
 hipError_t launch_solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0 = nullptr,
                                   hipEvent_t e1 = nullptr);
-hipError_t launch_finalize_phase(const Group &grp, hipStream_t s, Ctl *mirror = nullptr);
+hipError_t launch_finalize_phase(const Group &grp, hipStream_t s, Ctl *mirror = nullptr, int64_t seq = 0);
 
 // set_energy on the device: workspace copy of u (src != ws), c_ij, initial state and loop control, left as a
 // solve with limit t_limit starts it.  The validation verdict (status / halted set on the device when the energy

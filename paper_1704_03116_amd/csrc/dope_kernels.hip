@@ -1371,17 +1371,23 @@ __global__ __launch_bounds__(CONS_NT) void k_consensus_one(const Img one, int32_
 // Loop control after the consensus of one iteration (a single workgroup): max_k r_k, stopping rule, overflow
 // and solver errors, mu <- mu * mu_fact, t <- t + 1.  A separate launch instead of a last-workgroup handshake
 // inside k_consensus: a device-scope fence per workgroup costs L2 write-backs on every XCD.
-// Copies the loop control into the host-visible mirror (thread 0 after its own updates, so it reads them back).
-__device__ __forceinline__ void mirror_ctl(const GLOBAL Ctl *ctl, Ctl *mirror) {
-    static_assert(sizeof(Ctl) % 8 == 0, "the loop control is copied in 8-byte words");
+// Copies the loop control into the host-visible mirror (thread 0 after its own updates, so it reads them back),
+// then, with system-scope release, the readback number seq into its last word: the host polls that word and
+// finds the rest complete once it matches.
+__device__ __forceinline__ void mirror_ctl(const GLOBAL Ctl *ctl, Ctl *mirror, int64_t seq) {
+    static_assert(sizeof(Ctl) % 8 == 0 && offsetof(Ctl, seq) == sizeof(Ctl) - 8,
+                  "the loop control is copied in 8-byte words, the readback number last");
     const GLOBAL unsigned long long *src = reinterpret_cast<const GLOBAL unsigned long long *>(ctl);
     unsigned long long *dst = reinterpret_cast<unsigned long long *>(mirror);
 #pragma unroll
-    for (int i = 0; i < int(sizeof(Ctl) / 8); ++i) dst[i] = src[i];
+    for (int i = 0; i < int(sizeof(Ctl) / 8) - 1; ++i) dst[i] = src[i];
+    // release at system scope: the words above reach host memory first (written back from the L2 if the mirror
+    // is cached there), then this store, which goes through at system scope
+    __hip_atomic_store(&mirror->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // mirror (single-image launches only): host-visible copy of the loop control to refresh after the update.
-__device__ __forceinline__ void finalize_image(const Img &im, Ctl *mirror = nullptr) {
+__device__ __forceinline__ void finalize_image(const Img &im, Ctl *mirror = nullptr, int64_t seq = 0) {
     GLOBAL Ctl *ctl = gp(im.ctl);
     // every load is issued before any is used (one memory round trip): the loop control and the residuals
     const int32_t halted = ctl->halted, t = ctl->t, t_limit = ctl->t_limit, solver_err = ctl->solver_err,
@@ -1424,7 +1430,7 @@ __device__ __forceinline__ void finalize_image(const Img &im, Ctl *mirror = null
                 sm[2] = 0;
                 sm[3] = vst;
             }
-            if (mirror) mirror_ctl(ctl, mirror);
+            if (mirror) mirror_ctl(ctl, mirror, seq);
         }
         return;
     }
@@ -1458,15 +1464,15 @@ __device__ __forceinline__ void finalize_image(const Img &im, Ctl *mirror = null
             sm[2] = conv;
             sm[3] = st_new ? st_new : status;
         }
-        if (mirror) mirror_ctl(ctl, mirror);
+        if (mirror) mirror_ctl(ctl, mirror, seq);
     }
 }
 
 // One workgroup per image (one = the only image's descriptor when single != 0).
 __global__ __launch_bounds__(256) void k_finalize(const Img *__restrict__ imgs, Queue *queue, const Img one,
-                                                  int32_t single, Ctl *mirror) {
+                                                  int32_t single, Ctl *mirror, int64_t seq) {
     if (blockIdx.x == 0 && threadIdx.x == 0) queue->next = 0;   // next iteration's block-solve queue
-    if (single) finalize_image(one, mirror);
+    if (single) finalize_image(one, mirror, seq);
     else finalize_image(imgs[blockIdx.x]);
 }
 
@@ -2055,10 +2061,10 @@ hipError_t launch_consensus_phase(const Group &grp, hipStream_t s, hipEvent_t e0
     return by_conn(grp.conn, [&](auto c) { return conn_consensus<decltype(c)::value>(grp, s, e0, e1); });
 }
 
-hipError_t launch_finalize_phase(const Group &grp, hipStream_t s, Ctl *mirror) {
+hipError_t launch_finalize_phase(const Group &grp, hipStream_t s, Ctl *mirror, int64_t seq) {
     const Img one = grp.one ? *grp.one : Img{};
     hipLaunchKernelGGL(k_finalize, dim3(unsigned(grp.n_imgs)), dim3(256), 0, s, grp.imgs, grp.queue, one,
-                       int32_t(grp.one ? 1 : 0), grp.one ? mirror : nullptr);
+                       int32_t(grp.one ? 1 : 0), grp.one ? mirror : nullptr, seq);
     return hipGetLastError();
 }
 
@@ -2067,10 +2073,10 @@ hipError_t launch_batch_setup(const Img *imgs, int32_t n, const int32_t *params,
     return hipGetLastError();
 }
 
-hipError_t launch_iteration(const Group &grp, hipStream_t s, Ctl *mirror) {
+hipError_t launch_iteration(const Group &grp, hipStream_t s, Ctl *mirror, int64_t seq) {
     hipError_t e = launch_solve_phase(grp, s);
     if (e == hipSuccess) e = launch_consensus_phase(grp, s);
-    if (e == hipSuccess) e = launch_finalize_phase(grp, s, mirror);
+    if (e == hipSuccess) e = launch_finalize_phase(grp, s, mirror, seq);
     return e;
 }
 
