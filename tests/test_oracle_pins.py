@@ -521,3 +521,163 @@ def test_energy_gap_invariant_and_quality():
     assert e >= egc
     assert (e - egc) / abs(egc) < 0.01
     assert 2 * np.sum(l & x) / (np.sum(l) + np.sum(x)) > 0.99
+
+
+# --------------------------------------------------------------------------------------------------------
+# the stopping rule of Algorithm 1 (its while-condition on the per-block residuals)
+# --------------------------------------------------------------------------------------------------------
+
+def _no_pairwise_problem():
+    """8x8 grid, 4-connected, w = 0, 4x4 blocks with 1-pixel overlap (2 x 2 blocks); with w = 0 Eq. (10) is the
+    plain average of the copies: Y_m = floor(sum_k (2^16 yhat_k,m + A_k,m) / q_m)."""
+    p = tiny_problem(41, (8, 8, 1), 4, (5, 5, 1), (2, 2, 0))
+    p.w[:] = 0
+    return p
+
+
+def _copy_index(dec, k, pixel):
+    return int(dec.offsets[k] + list(dec.blocks[k].idx).index(pixel))
+
+
+@pytest.mark.parametrize("vals", [(5,), (3, 4), (6, 0, 8)])
+def test_stopping_threshold_is_eps_squared(vals):
+    """Block 0 gets multipliers v on pixels that lie in it alone (q = 1); with yhat = 0 and w = 0 the new Y of
+    those pixels is v (Eq. 10), every other copy is consistent, so r_0 = sum v^2 and r_k = 0 elsewhere.  The loop
+    stops iff max_k r_k <= eps^2: eps = sqrt(sum v^2) stops (equality included), one less does not."""
+    p = _no_pairwise_problem()
+    dec = dope.decompose(p)
+    st = dope.initial_state(dec, 1000)
+    st.Y[:] = 0
+    interior = [i for i in dec.blocks[0].idx if dec.q[i] == 1]
+    for v, pix in zip(vals, interior):
+        st.A[_copy_index(dec, 0, int(pix))] = v
+    yz = np.zeros_like(st.yhat)
+    R = sum(v * v for v in vals)
+    eps = int(round(R ** 0.5))
+    assert eps * eps == R
+    new, info = dope.iterate(dec, st, yhat_override=yz, eps_q16=eps)
+    assert info.resid2[0] == R and np.all(info.resid2[1:] == 0)
+    assert info.converged
+    _, info = dope.iterate(dec, st, yhat_override=yz, eps_q16=eps - 1)
+    assert not info.converged
+    if R > 1:
+        # a threshold of eps instead of eps^2 would not stop here
+        assert R > eps
+
+
+def test_residual_of_shared_pixel_counts_in_every_block():
+    """A pixel in two blocks (q = 2) with multipliers 6 and 10 gets Y = floor(16 / 2) = 8 (Eq. 10 with w = 0); both
+    blocks' residuals hold (0 - 8)^2 = 64 and the multipliers become 6 - 8 and 10 - 8 (Eq. 11)."""
+    p = _no_pairwise_problem()
+    dec = dope.decompose(p)
+    st = dope.initial_state(dec, 1000)
+    st.Y[:] = 0
+    shared = [i for i in dec.blocks[0].idx if dec.q[i] == 2 and i in set(dec.blocks[1].idx)][0]
+    c0, c1 = _copy_index(dec, 0, int(shared)), _copy_index(dec, 1, int(shared))
+    st.A[c0], st.A[c1] = 6, 10
+    new, info = dope.iterate(dec, st, yhat_override=np.zeros_like(st.yhat), eps_q16=7)
+    assert new.Y[shared] == 8
+    assert info.resid2[0] == 64 and info.resid2[1] == 64 and np.all(info.resid2[2:] == 0)
+    assert new.A[c0] == -2 and new.A[c1] == 2
+    assert not info.converged          # 64 > 7^2
+    _, info = dope.iterate(dec, st, yhat_override=np.zeros_like(st.yhat), eps_q16=8)
+    assert info.converged              # 64 <= 8^2
+
+
+@pytest.mark.parametrize("case", TINY[:6])
+def test_block_residuals_by_hand(case):
+    """After two iterations of a random problem, r_k = sum over the pixels of block k of (2^16 yhat_k,i - Y_i)^2,
+    summed here by plain loops over the block's pixel list."""
+    dims, conn, block, overlap = case
+    p = tiny_problem(43, dims, conn, block, overlap)
+    dec = dope.decompose(p)
+    st = dope.initial_state(dec, 900)
+    st, _ = dope.iterate(dec, st, threads=1)
+    new, info = dope.iterate(dec, st, threads=1, eps_q16=6554)
+    for k, idx in enumerate(block_sets(p)):
+        a = int(dec.offsets[k])
+        r = 0
+        for t, i in enumerate(idx):
+            d = 65536 * int(new.yhat[a + t]) - int(new.Y[i])
+            r += d * d
+        assert info.resid2[k] == r
+    assert info.converged == (max(int(x) for x in info.resid2) <= 6554 * 6554)
+
+
+# --------------------------------------------------------------------------------------------------------
+# non-convergence on the 64x64 disk is the method's: a real-valued Algorithm 1 settles in the same 2-cycle
+# --------------------------------------------------------------------------------------------------------
+
+def float_dope_vectorised(p, iters):
+    """Real-valued (float64) Algorithm 1 on sparse matrices built from the hand closed forms of Theorem 1's
+    coupling term: g_k(y) = G_k y with G_k[i, i] += c, G_k[i, j] -= c, c = w_ij (q_j - [j in k]) / (q_i q_j);
+    Eq. (10) uses G_k^T yhat_k.  Block problems are solved with real unaries and capacities scaled by 2^20 and
+    rounded (labels only).  Returns per iteration (block labels, y, per-block residuals ||yhat_k - S_k y||^2)."""
+    import scipy.sparse as sps
+    nb = neighbours(p)
+    bsets = block_sets(p)
+    q = np.array(multiplicities(p, bsets), float)
+    lam = p.lam_q8 / 256.0
+    G, S, edges = [], [], []
+    for idx in bsets:
+        ink = set(idx)
+        pos = {i: t for t, i in enumerate(idx)}
+        rows, cols, vals = [], [], []
+        ea, eb, cap = [], [], []
+        for t, i in enumerate(idx):
+            for j, wv in nb[i]:
+                c = wv * (q[j] - (j in ink)) / (q[i] * q[j])
+                rows += [t, t]
+                cols += [i, j]
+                vals += [c, -c]
+                if i < j and j in pos:
+                    ea.append(t); eb.append(pos[j]); cap.append(lam * wv / (q[i] * q[j]))
+        G.append(sps.csr_matrix((vals, (rows, cols)), shape=(len(idx), p.n)))
+        S.append(sps.csr_matrix((np.ones(len(idx)), (np.arange(len(idx)), idx)), shape=(len(idx), p.n)))
+        edges.append((np.array(ea, np.int32), np.array(eb, np.int32),
+                      np.round(np.array(cap) * 2 ** 20).astype(np.int64)))
+    u = np.asarray(p.u, float)
+    mu = float(p.mu0)
+    y = np.full(p.n, 0.5)
+    a = [np.zeros(len(b)) for b in bsets]
+    hist = []
+    for _ in range(iters):
+        yh = []
+        for k, idx in enumerate(bsets):
+            un = u[idx] / q[idx] + lam * (G[k] @ y) + mu * (a[k] - y[idx] + 0.5)
+            x, _ = dope.solve_subproblem(np.round(un * 2 ** 20).astype(np.int64), *edges[k])
+            yh.append(x.astype(float))
+        num = np.zeros(p.n)
+        for k in range(len(bsets)):
+            num += S[k].T @ (mu * (yh[k] + a[k])) - lam * (G[k].T @ yh[k])
+        y = num / (mu * q)
+        r = []
+        for k, idx in enumerate(bsets):
+            a[k] = a[k] + yh[k] - y[idx]
+            r.append(float(np.sum((yh[k] - y[idx]) ** 2)))
+        mu *= 1.05
+        hist.append((np.concatenate(yh).astype(np.uint8), y.copy(), np.array(r)))
+    return hist
+
+
+def test_disk_two_cycle_is_the_methods():
+    """On the 64x64 disk (16x16 blocks, o = 1, mu0 = 1000) the fixed-point loop never meets eps = 0.1: from
+    iteration 7 the same few overlap copies flip every iteration (block labels repeat with period 2) and
+    sqrt(max_k r_k) stays near 0.71.  A real-valued float64 Algorithm 1 settles into the same 2-cycle with the
+    same residual, so the stall belongs to Algorithm 1 on this input, not to the Q16.16 reading."""
+    p = synth.config1()
+    n_it = 40
+    _, infos, states, _ = dope.run(p, n_iter=n_it, record=True)
+    hist = float_dope_vectorised(p, n_it)
+    for t in range(20, n_it):
+        fx_res = np.sqrt(np.max(infos[t].resid2)) / 65536.0
+        fl_res = np.sqrt(np.max(hist[t][2]))
+        assert 0.6 < fx_res < 0.8 and 0.6 < fl_res < 0.8, (t, fx_res, fl_res)
+        assert abs(fx_res - fl_res) < 0.01
+        # period 2, and a real flip each iteration
+        assert np.array_equal(states[t].yhat, states[t - 2].yhat)
+        assert not np.array_equal(states[t].yhat, states[t - 1].yhat)
+        assert np.array_equal(hist[t][0], hist[t - 2][0])
+        assert not np.array_equal(hist[t][0], hist[t - 1][0])
+    # the two loops flip the same copies
+    assert np.array_equal(states[n_it - 1].yhat, hist[n_it - 1][0])
