@@ -38,8 +38,12 @@
  *
  * Conventions: every call returns a dope_status; no exception crosses the ABI.  A failed call leaves the
  * state unchanged, except DOPE_EOVERFLOW and DOPE_ESOLVER, which stop the loop with the state of the failing
- * iteration.  A context is not thread-safe; separate contexts are independent.  Work is ordered on the
- * context's HIP stream; calls that return results to the host synchronise that stream before returning.
+ * iteration.  A context is not thread-safe; separate contexts (also used from different threads) are
+ * independent.  Work is ordered on the context's HIP stream.  A call that returns results to the host returns
+ * once those results are complete; it does not always leave the stream idle: dope_iterate and dope_solve return
+ * as soon as the loop-control kernel of their last iteration has published the loop state to the host, while
+ * that kernel may still be finishing on the stream.  Work on other streams that needs the results must wait on
+ * the context's stream (an event recorded on it after the call), as for any stream-ordered producer.
  */
 #ifndef DOPE_H
 #define DOPE_H
@@ -132,11 +136,13 @@ dope_status dope_iterate(dope_ctx *ctx, int32_t n_iter, dope_info *out);
 /* Run until the stopping rule holds or t reaches max_iter.  out may be NULL. */
 dope_status dope_solve(dope_ctx *ctx, dope_info *out);
 
-/* Labels l_i = [Y_i > 2^15] (uint8[n]) to host memory (waits) or device memory (stream-ordered, returns at once). */
+/* The segmentation Algorithm 1 returns, made binary: labels l_i = [Y_i > 2^15] (y_i > 1/2 strictly) as uint8[n],
+ * to host memory (complete on return) or device memory (stream-ordered, returns at once). */
 dope_status dope_labels(dope_ctx *ctx, uint8_t *labels, int32_t mem_kind);
 
-/* E_q = 256 sum u_i l_i + lambda_q8 sum_edges w_ij |l_i - l_j| of the current labels (exact int64).  EINVAL
- * when the loaded energy was rejected by validation. */
+/* The pairwise energy of Eq. (1) (each undirected edge once, as in Eq. (3)) of the current labels, scaled by 256:
+ * E_q = 256 sum u_i l_i + lambda_q8 sum_edges w_ij |l_i - l_j| (exact int64).  EINVAL when the loaded energy
+ * was rejected by validation. */
 dope_status dope_energy(dope_ctx *ctx, int64_t *e_q8);
 
 /* Checkpoint / test access to the whole ADMM state (host memory).  Y: int32[n]; A: int32[sum |block|];

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -431,7 +432,9 @@ dope_status sync_ctl(dope_ctx *c) {
         HIP_TRY(c, dope::launch_validate(c->ctl, c->stream), "validation launch");
         c->validate_pending = false;
     }
-    HIP_TRY(c, hipMemcpyAsync(c->hctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream), "control readback");
+    // the readback number is the host's own (the device never writes it in the control block): not copied
+    HIP_TRY(c, hipMemcpyAsync(c->hctl, c->ctl, offsetof(Ctl, seq), hipMemcpyDeviceToHost, c->stream),
+            "control readback");
     return wait_stream(c);
 }
 
@@ -712,6 +715,17 @@ dope_status dope_solve(dope_ctx *c, dope_info *out) {
     if (c->hctl->status != 0) { fill_info(c, out); return dope_status(c->hctl->status); }
     if (c->hctl->t > 0 && c->hctl->converged) { fill_info(c, out); return DOPE_OK; }
     const int32_t limit = c->p.max_iter;
+    if (c->hctl->t >= limit) {
+        // no iteration to run (max_iter = 0, or t already at the cap): a pending verdict is taken and the loop
+        // control read back, so a rejected energy is reported here and its bits do not reach the next upload
+        c->ctl_fresh = false;
+        st = sync_ctl(c);
+        if (st != DOPE_OK) return st;
+        fill_info(c, out);
+        if (c->hctl->status != 0)
+            return fail(c, dope_status(c->hctl->status), status_message(c->hctl->status, c->hctl->vflags));
+        return DOPE_OK;
+    }
     if (!c->ctl_fresh) HIP_TRY(c, dope::launch_ctl_setup(c->ctl, limit, 1, 0, c->stream), "control setup launch");
     c->validate_pending = false;
     c->ctl_fresh = false;
@@ -807,7 +821,8 @@ dope_status dope_set_state(dope_ctx *c, const int32_t *Y, const int32_t *A, cons
     h.wg_counter = 0;
     *c->hctl = h;
     c->ctl_fresh = false;
-    HIP_TRY(c, hipMemcpyAsync(c->ctl, c->hctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream), "control upload");
+    HIP_TRY(c, hipMemcpyAsync(c->ctl, c->hctl, offsetof(Ctl, seq), hipMemcpyHostToDevice, c->stream),
+            "control upload");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
     return DOPE_OK;
 }
@@ -1005,14 +1020,6 @@ dope_status batch_status(dope_batch *b) {
             return bfail(b, dope_status(b->hsum[4 * i + 3]), "image " + std::to_string(i) + " stopped with an error");
     return DOPE_OK;
 }
-
-}  // namespace
-
-extern "C" {
-
-}  // extern "C"
-
-namespace {
 
 void batch_drop_graph(dope_batch *b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);

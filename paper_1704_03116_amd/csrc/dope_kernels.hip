@@ -23,6 +23,7 @@
 
 #include <hip/hip_ext.h>
 
+#include <mutex>
 #include <type_traits>
 
 namespace dope {
@@ -1795,17 +1796,20 @@ template <int CONN, int NT>
 hipError_t launch_maxflow(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     constexpr int H = Sten<CONN>::H;
     const size_t lds = maxflow_lds_bytes(grp.npmax, H);
-    static size_t lds_set = 0;
-    if (lds > lds_set) {
-        hipError_t e = hipSuccess;
+    // The dynamic-LDS limit of these kernels is raised once per process to the whole 160 KiB (every block the
+    // host admits fits it), so launches from contexts on several threads never race on the attribute.
+    static std::once_flag lds_once;
+    static hipError_t lds_err = hipSuccess;
+    std::call_once(lds_once, [] {
         const void *fns[3] = {reinterpret_cast<const void *>(&k_block_solve<CONN, NT>),
                               reinterpret_cast<const void *>(&k_block_solve_queue<CONN, NT>),
                               reinterpret_cast<const void *>(&k_block_solve_one<CONN, NT>)};
         for (const void *f : fns)
-            if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-        lds_set = lds;
-    }
+            if (lds_err == hipSuccess)
+                lds_err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(LDS_LIMIT));
+    });
+    if (lds_err != hipSuccess) return lds_err;
+    if (lds > LDS_LIMIT) return hipErrorInvalidValue;
     if ((grp.npmax + NT - 1) / NT > 16) return hipErrorInvalidValue;   // the residual lane sums assume <= 16
     const int32_t round_limit = 65536 + 64 * grp.npmax;
     const int32_t workers = grp.n_workers > 0 ? (grp.n_workers < grp.n_blk_items ? grp.n_workers : grp.n_blk_items)

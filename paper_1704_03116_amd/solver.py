@@ -58,19 +58,8 @@ class Dope:
 
     def __init__(self, dims, connectivity, block, overlap, mu0, *, ndim=None, mu_fact=(21, 20), eps_q16=6554,
                  max_iter=50, solver="auto", stream=None, torch_workspace=True):
-        p = N.dope_params()
-        dims = tuple(int(d) for d in dims) + (1,) * (3 - len(dims))
-        p.ndim = ndim if ndim is not None else (3 if connectivity in (6, 32, 122) else 2)
-        p.dims[:] = dims
-        p.connectivity = int(connectivity)
-        p.block[:] = tuple(int(b) for b in block) + (1,) * (3 - len(block))
-        p.overlap[:] = tuple(int(o) for o in overlap) + (0,) * (3 - len(overlap))
-        p.mu0 = int(mu0)
-        p.mu_fact_num, p.mu_fact_den = int(mu_fact[0]), int(mu_fact[1])
-        p.eps_q16 = int(eps_q16)
-        p.max_iter = int(max_iter)
-        p.solver = {"auto": N.DOPE_SOLVER_AUTO, "maxflow": N.DOPE_SOLVER_MAXFLOW,
-                    "exhaustive": N.DOPE_SOLVER_EXHAUSTIVE}[solver]
+        p = make_params(dims, connectivity, block, overlap, mu0, ndim=ndim, mu_fact=mu_fact, eps_q16=eps_q16,
+                        max_iter=max_iter, solver=solver)
         self._workspace = None
         if stream is None and torch_workspace:
             import torch

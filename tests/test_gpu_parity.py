@@ -1,9 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle, bit-exact at every ADMM iteration.
 
-Small problems are compared on the whole state (Y, A, block labels, mu, t, per-block residuals) after every
-iteration.  Full-size workloads are compared on sampled block solves and on the complete consensus /
-multiplier update, both recomputed by the oracle from the GPU's own state of the previous iteration."""
+Every problem, the full-size workloads included, is compared on the whole state (Y, A, block labels, mu, t,
+per-block residuals and the stopping flag) after every iteration."""
 import dataclasses
+import os
 
 import numpy as np
 import pytest
@@ -52,22 +52,35 @@ def assert_state_equal(d, S, info_o, t, dec):
     assert np.array_equal(d.block_resid(), info_o.resid2), f"iteration {t}: residuals differ"
 
 
-def run_parity(p, n_iter, label):
+# host threads for the oracle's block solves (the GPU machine's CPU share is 16 cores)
+ORACLE_THREADS = min(16, os.cpu_count() or 1)
+
+
+def run_parity(p, n_iter, label, stats=None, dec=None):
+    """Runs the oracle and the GPU side by side for n_iter iterations (stopping early only on overflow) and
+    compares the whole state (Y, A, block labels, mu, t, per-block residuals, the stopping flag) after every
+    iteration.  stats: optional list that receives each iteration's per-block solver statistics."""
     announce(f"{label}: dims={p.dims} conn={p.conn} block={p.block} overlap={p.overlap} mu0={p.mu0} "
              f"solver={p.solver} iters={n_iter}")
-    st_o, infos, states, dec = od.run(p, n_iter=n_iter, record=True)
+    if dec is None:
+        dec = od.decompose(p)
+    st = od.initial_state(dec, p.mu0)
     d = make_ctx(p)
     try:
-        for t, (S, inf) in enumerate(zip(states, infos), start=1):
+        for t in range(1, n_iter + 1):
+            st, inf = od.iterate(dec, st, threads=ORACLE_THREADS, mu_num=p.mu_num, mu_den=p.mu_den,
+                                 eps_q16=p.eps_q16)
             status, info = d.iterate_status(1)
+            if stats is not None:
+                stats.append(d.block_stats())
             if inf.overflow:
                 assert status == -5, f"oracle overflowed at iteration {t}, GPU status {status}"
-                assert_state_equal(d, S, inf, t, dec)
-                return d, st_o, dec
+                assert_state_equal(d, st, inf, t, dec)
+                return d, st, dec
             assert status == 0, f"iteration {t}: status {status}"
-            assert info["converged"] == (int(np.max(inf.resid2)) <= p.eps_q16 ** 2)
-            assert_state_equal(d, S, inf, t, dec)
-        return d, st_o, dec
+            assert info["converged"] == inf.converged == (int(np.max(inf.resid2)) <= p.eps_q16 ** 2)
+            assert_state_equal(d, st, inf, t, dec)
+        return d, st, dec
     except Exception:
         d.close()
         raise
@@ -251,48 +264,50 @@ def test_device_inputs_and_labels():
 
 
 # ------------------------------------------------------------------------------------------------------------
-# full-size workloads: sampled block solves + complete consensus, from the GPU's own previous state
+# full-size workloads: the whole state after every iteration, in the launch configuration the benchmark times
 # ------------------------------------------------------------------------------------------------------------
 
-def sampled_parity(p, n_iter, n_sample, label, seed=0):
-    announce(f"{label}: full size {p.dims}, {n_iter} iterations, {n_sample} sampled blocks per iteration")
-    dec = od.decompose(p)
-    d = make_ctx(p)
-    rng = np.random.default_rng(seed)
-    K = len(dec.blocks)
-    prev = d.get_state()
-    for t in range(1, n_iter + 1):
-        status, info = d.iterate_status(1)
-        assert status == 0
-        cur = d.get_state()
-        Y0, A0, _, M0, _ = prev
-        Y1, A1, yh1, M1, t1 = cur
-        assert t1 == t and M1 == od.next_mu(M0, p.mu_num, p.mu_den)
-        sample = rng.choice(K, size=min(n_sample, K), replace=False)
-        for k in sample:
-            a, b = dec.offsets[k], dec.offsets[k + 1]
-            Ut, ea, eb, cap = od.block_subproblem(dec, int(k), Y0.astype(np.int64), A0[a:b].astype(np.int64), M0)
-            x, _ = od.solve_subproblem(Ut, ea, eb, cap, "maxflow" if p.solver == "maxflow" else "exhaustive")
-            assert np.array_equal(yh1[a:b], x), f"iteration {t}: block {k} labels differ"
-        st = od.State(Y0.astype(np.int64), A0.astype(np.int64), yh1.copy(), M0, t - 1)
-        new, inf = od.iterate(dec, st, yhat_override=yh1, mu_num=p.mu_num, mu_den=p.mu_den, eps_q16=p.eps_q16)
-        assert np.array_equal(Y1, new.Y), f"iteration {t}: consensus differs"
-        assert np.array_equal(A1, new.A), f"iteration {t}: multipliers differ"
-        assert np.array_equal(d.block_resid(), inf.resid2)
-        prev = cur
+@pytest.mark.timeout(600)
+def test_config2_full_size_every_iteration():
+    """512x512, 8-connected, 32x32 blocks with o = 2 (289 blocks, the 512-thread block solver): the solve stops
+    after 2 iterations; 4 are compared."""
+    d, st, dec = run_parity(synth.config2(), 4, "config2 512x512 full size")
+    assert np.array_equal(d.labels(), od.labels(st.Y))
     d.close()
 
 
-def test_config2_full_size_sampled():
-    sampled_parity(synth.config2(), 4, 40, "config2 512x512")
+@pytest.mark.timeout(900)
+def test_config3_full_size_every_iteration():
+    """128x128x64, 6-connected, 16^3 blocks with o = 1 (405 blocks, one 1024-thread workgroup per CU): all 50
+    iterations of the solve, whole state after each, then labels and energy."""
+    p = synth.config3()
+    d, st, dec = run_parity(p, p.max_iter, "config3 128x128x64 full size")
+    assert np.array_equal(d.labels(), od.labels(st.Y))
+    assert d.energy() == od.energy_q(dec, od.labels(st.Y))
+    d.close()
 
 
-def test_config3_full_size_sampled():
-    sampled_parity(synth.config3(), 3, 12, "config3 128x128x64")
+@pytest.mark.timeout(600)
+def test_config4_full_size_every_iteration():
+    """256x256 non-submodular grid, 7225 exhaustive 4x4 blocks: 3 iterations."""
+    d, _, _ = run_parity(synth.config4(), 3, "config4 256x256 exhaustive full size")
+    d.close()
 
 
-def test_config4_full_size_sampled():
-    sampled_parity(synth.config4(), 2, 150, "config4 256x256 exhaustive")
+@pytest.mark.timeout(600)
+def test_config2_full_size_solve():
+    """dope_solve (speculative iteration chunks, polled readback) on the full 512x512 image: iterations, stopping
+    flag, state and labels equal the oracle's solve."""
+    p = synth.config2()
+    announce("config2 512x512 full-size solve")
+    st_o, infos, _, dec = od.run(p, threads=ORACLE_THREADS)
+    d = make_ctx(p)
+    info = d.solve()
+    assert info["iters_done"] == len(infos) and info["converged"] == infos[-1].converged
+    Y, A, yh, mu, t = d.get_state()
+    assert np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+    assert np.array_equal(d.labels(), od.labels(st_o.Y))
+    d.close()
 
 
 # ------------------------------------------------------------------------------------------------------------
@@ -352,16 +367,14 @@ def test_ball_kernel_volume_small_every_iteration(k, dims):
     d.close()
 
 
-def test_kernel5_full_size_sampled():
-    sampled_parity(synth.config_kernel(5), 3, 20, "kernel5 512x512")
-
-
-def test_kernel7_full_size_sampled():
-    sampled_parity(synth.config_kernel(7), 2, 40, "kernel7 512x512")
-
-
-def test_kernel9_full_size_sampled():
-    sampled_parity(synth.config_kernel(9), 2, 40, "kernel9 512x512")
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("k,n_iter", [(5, 4), (7, 3), (9, 2)])
+def test_kernel_full_size_every_iteration(k, n_iter):
+    """The 512x512 image with the 5x5 / 7x7 / 9x9 neighbourhood (its solve stops after 3 / 2 / 1 iterations): the
+    whole state after every iteration, one past the stop."""
+    d, st, dec = run_parity(synth.config_kernel(k), n_iter, f"kernel{k} 512x512 full size")
+    assert np.array_equal(d.labels(), od.labels(st.Y))
+    d.close()
 
 
 def test_batch_wide_stencil_matches_alone():
@@ -821,3 +834,87 @@ def test_serving_admission_budget_and_busy():
             if finished == len(reqs):
                 break
         assert finished == len(reqs)
+
+
+# ------------------------------------------------------------------------------------------------------------
+# ties: energies with many minimisers, where only the canonical choice of the block labelling decides the result
+# ------------------------------------------------------------------------------------------------------------
+
+TIE_CASES = [
+    # label, dims, conn, block, overlap, solver, unary range, weight range
+    ("4-connected LDS", (40, 36, 1), 4, (8, 8, 1), (1, 1, 0), "maxflow", (-2, 2), (0, 2)),
+    ("8-connected LDS", (48, 40, 1), 8, (16, 16, 1), (2, 2, 0), "maxflow", (-2, 2), (0, 2)),
+    ("6-connected LDS", (20, 18, 16), 6, (8, 8, 8), (1, 1, 1), "maxflow", (-2, 2), (0, 2)),
+    ("5x5 LDS", (30, 28, 1), 24, (10, 10, 1), (2, 2, 0), "maxflow", (-6, 6), (0, 1)),
+    ("8-connected beyond the LDS", (150, 120, 1), 8, (100, 90, 1), (2, 2, 0), "maxflow", (-2, 2), (0, 2)),
+    ("4-connected exhaustive", (23, 19, 1), 4, (4, 4, 1), (1, 1, 0), "exhaustive", (-2, 2), (0, 2)),
+]
+
+
+def tie_counts(p, dec):
+    """Iteration-1 block problems with more than one minimiser.  Max-flow blocks: the minimal minimiser differs
+    from the maximal one, which is 1 - (minimal minimiser of the problem with negated unaries).  Enumerated
+    blocks: brute force over all 2^|block| labellings counts the minimisers."""
+    st = od.initial_state(dec, p.mu0)
+    n_multi = 0
+    for k in range(len(dec.blocks)):
+        a, b = dec.offsets[k], dec.offsets[k + 1]
+        Ut, ea, eb, cap = od.block_subproblem(dec, k, st.Y, st.A[a:b], st.M)
+        if p.solver == "maxflow":
+            lo, _ = od.solve_subproblem(Ut, ea, eb, cap, "maxflow")
+            neg, _ = od.solve_subproblem(-Ut, ea, eb, cap, "maxflow")
+            n_multi += int(not np.array_equal(lo, 1 - neg))
+        else:
+            m = len(Ut)
+            codes = np.arange(1 << m, dtype=np.int64)
+            bits = (codes[:, None] >> np.arange(m)) & 1
+            e = bits @ np.asarray(Ut, np.int64)
+            for i, j, c in zip(ea, eb, cap):
+                e += int(c) * (bits[:, i] != bits[:, j])
+            n_multi += int(np.sum(e == e.min()) > 1)
+    return n_multi, len(dec.blocks)
+
+
+@pytest.mark.parametrize("case", TIE_CASES, ids=[c[0] for c in TIE_CASES])
+def test_tie_prone_energies_every_iteration(case):
+    """Unaries in {-2..2} (zeros included) and weights in {0, 1, 2} at lambda = 1 (the 5x5 stencil: {-6..6} and
+    {0, 1}): at iteration 1 the block unary
+    is u 2^14 / q and an edge's capacity w 2^14 / (q_i q_j), so zero unaries, |U~| equal to the sum of the node's
+    capacities and blocks with several minimisers are common (asserted first, through the oracle: at least 20 % of
+    the iteration-1 block solves).  The whole state is then compared bit for bit after every iteration."""
+    label, dims, conn, block, overlap, solver, u_range, w_range = case
+    p = synth.random_problem(51, dims, conn, block, overlap, lam_q8=256, u_range=u_range, w_range=w_range,
+                             neg_frac=0.3 if solver == "exhaustive" else 0.0, mu0=3, solver=solver)
+    dec = od.decompose(p)
+    n_multi, K = tie_counts(p, dec)
+    announce(f"ties, {label}: {n_multi} of {K} iteration-1 block solves have several minimisers")
+    assert n_multi >= 0.2 * K
+    stats = []
+    d, _, _ = run_parity(p, 6, f"ties, {label}", stats=stats, dec=dec)
+    if solver == "maxflow":
+        # the flow phase ran (free nodes after forcing, push-relabel rounds)
+        assert sum(int(s[:, 0].sum()) for s in stats) > 0
+    d.close()
+
+
+def test_solve_with_no_iteration_reports_a_rejected_upload():
+    """max_iter = 0: a solve straight after an asynchronous upload runs no iteration, yet takes the pending
+    verdict: a rejected energy (negative weights, max-flow solver) is reported by the solve, and a valid energy
+    uploaded next is accepted (the rejected one's validation bits do not reach it) and solves like the oracle."""
+    from paper_1704_03116_amd import _native as N
+    from paper_1704_03116_amd.solver import Dope
+    announce("max_iter = 0 after a rejected asynchronous upload")
+    bad = synth.random_problem(16, (20, 20, 1), 4, (8, 8, 1), (1, 1, 0), neg_frac=0.3)
+    good = synth.random_problem(17, (20, 20, 1), 4, (8, 8, 1), (1, 1, 0))
+    with Dope.from_problem(good, solver="maxflow", max_iter=0) as e:
+        e.set_energy_async(bad.u, bad.w, bad.lam_q8)
+        with pytest.raises(N.DopeError) as err:
+            e.solve()
+        assert err.value.status == N.DOPE_ENOTSUBMODULAR
+        e.set_energy_async(good.u, good.w, good.lam_q8)
+        info = e.solve()
+        assert info["iters_done"] == 0
+        e.iterate(3)
+        st_o, _, _, _ = od.run(good, n_iter=3)
+        Y, A, yh, mu, t = e.get_state()
+        assert t == 3 and np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
