@@ -262,6 +262,28 @@ dope_status dope_server_load(const dope_server *s, int32_t *waiting, int32_t *ac
 const char *dope_server_last_error(const dope_server *s);
 void dope_server_destroy(dope_server *s);
 
+/* ---- Solving without allocation ---------------------------------------------------------------------------
+ * For callers that cannot allocate (harnesses that forbid hipMalloc, serving loops that must not enter the
+ * allocator): dope_set_energy_async, dope_solve and dope_labels of one image in one call, with the whole device
+ * state (the layout dope_workspace_bytes(p) measures) in a static device array of the library of
+ * DOPE_NOALLOC_MAX_BYTES, which every GPU the library runs on holds from module load until the process ends.
+ * The call allocates nothing: no device or pinned memory, no stream, no event (the loop control is copied back
+ * into host memory and the stream synchronised at every readback, so the call is slower than dope_solve on a
+ * context for small images).
+ *   p: as for dope_create; p->stream orders the work (NULL = the null stream).
+ *   u, w: device memory, layout as for dope_set_energy; lambda_q8 as there.
+ *   labels: device memory, uint8[n], labels l_i = [Y_i > 2^15] of the result; complete on return.
+ *   out: host memory, may be NULL: the loop information of the solve.
+ * Errors: EINVAL for bad parameters or when dope_workspace_bytes(p) > DOPE_NOALLOC_MAX_BYTES (the message is
+ * dope_last_error(NULL)), the validation errors of dope_set_energy, and EOVERFLOW / ESOLVER / EDEVICE.
+ * Every call on one GPU shares that GPU's array and leaves its contents there; each call re-initialises all of
+ * the state it reads.  Calls on one GPU are serialised by a per-device lock and return only after their work has
+ * completed, so calls from several host threads do not overlap; device work that is still running from an
+ * earlier call cannot exist, but any other user of the array would race with a call. */
+#define DOPE_NOALLOC_MAX_BYTES (64u << 20)
+dope_status dope_solve_noalloc(const dope_params *p, const int32_t *u, const int32_t *w, int32_t lambda_q8,
+                               uint8_t *labels, dope_info *out);
+
 /* Context-local message of the last error; never NULL.  With ctx == NULL: the calling thread's last
  * dope_create validation message (empty when it succeeded). */
 const char *dope_last_error(const dope_ctx *ctx);

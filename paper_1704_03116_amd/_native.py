@@ -89,8 +89,12 @@ SIGNATURES = {
     "dope_server_load": (ctypes.c_int, [_P, _I32P, _I32P, ctypes.POINTER(ctypes.c_size_t)]),
     "dope_server_last_error": (ctypes.c_char_p, [_P]),
     "dope_server_destroy": (None, [_P]),
+    "dope_solve_noalloc": (ctypes.c_int, [ctypes.POINTER(dope_params), _P, _P, ctypes.c_int32, _P,
+                                          ctypes.POINTER(dope_info)]),
     "dope_destroy": (None, [_P]),
 }
+
+DOPE_NOALLOC_MAX_BYTES = 64 << 20
 
 _lib = None
 
@@ -152,6 +156,7 @@ dope_profile_enable = _fn("dope_profile_enable")
 dope_profile_read = _fn("dope_profile_read")
 dope_last_error = _fn("dope_last_error")
 dope_destroy = _fn("dope_destroy")
+dope_solve_noalloc = _fn("dope_solve_noalloc")
 dope_batch_create = _fn("dope_batch_create")
 dope_batch_set_energy_async = _fn("dope_batch_set_energy_async")
 dope_batch_labels = _fn("dope_batch_labels")

@@ -27,7 +27,8 @@ def build(verbose: bool = False) -> str:
     kern = os.path.join(CSRC, "dope_kernels.hip")
     units = [([kern], "dope_kernels_main.o", [])] + \
             [([kern], f"dope_kernels_{c}.o", [f"-DDOPE_CONN={c}"]) for c in STENCILS] + \
-            [([os.path.join(CSRC, "dope_abi.cpp")], "dope_abi.o", [])]
+            [([os.path.join(CSRC, "dope_abi.cpp")], "dope_abi.o", []),
+             ([os.path.join(CSRC, "dope_noalloc.hip")], "dope_noalloc.o", [])]
     compile_flags = [f for f in FLAGS if f != "-shared"]
 
     def compile_one(unit):

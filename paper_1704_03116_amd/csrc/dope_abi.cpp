@@ -55,6 +55,10 @@ struct dope_ctx {
     bool profiling = false;
     std::vector<hipEvent_t> ev_solve, ev_cons;   // start/stop pairs
     hipEvent_t ev_sync = nullptr;                // completion of the loop-control readback
+    // A context over caller-provided device memory that may create nothing (solve_in_buffer): no events, no
+    // pinned mirror (the loop control is copied back into hctl_host and the stream synchronised instead)
+    bool no_alloc = false;
+    Ctl hctl_host{};
     size_t n_solve = 0, n_cons = 0;
     std::string err;
 };
@@ -392,6 +396,10 @@ dope_status ensure_workspace(dope_ctx *c) {
 // every solve, so the host polls a completion event for up to ~2 ms before it blocks: a blocking wait adds the
 // wake-up latency of the host thread to every readback.
 dope_status wait_stream(dope_ctx *c) {
+    if (c->no_alloc) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
+        return DOPE_OK;
+    }
     if (!c->ev_sync && hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
         c->ev_sync = nullptr;
         HIP_TRY(c, hipStreamSynchronize(c->stream), "stream synchronize");
@@ -463,7 +471,7 @@ dope_status enqueue_iterations(dope_ctx *c, int count) {
     c->grp.one = &c->himg;
     for (int it = 0; it < count; ++it) {
         c->grp.par = (c->hctl->t + it) & 1;
-        Ctl *mirror = it == count - 1 ? c->hctl : nullptr;
+        Ctl *mirror = (it == count - 1 && !c->no_alloc) ? c->hctl : nullptr;
         const int64_t seq = mirror ? ++c->seq : 0;
         if (!c->profiling) {
             HIP_TRY(c, dope::launch_iteration(c->grp, c->stream, mirror, seq), "iteration launch");
@@ -484,8 +492,10 @@ dope_status enqueue_iterations(dope_ctx *c, int count) {
 }
 
 // The loop control after enqueue_iterations(c, count): the mirror is written by the last loop-control kernel when
-// count > 0, otherwise it is copied back.
-dope_status read_back(dope_ctx *c, int count) { return count > 0 ? wait_mirror(c) : sync_ctl(c); }
+// count > 0 (contexts with a pinned mirror), otherwise it is copied back.
+dope_status read_back(dope_ctx *c, int count) {
+    return (count > 0 && !c->no_alloc) ? wait_mirror(c) : sync_ctl(c);
+}
 
 dope_status check_ready(dope_ctx *c) {
     if (!c) return DOPE_EINVAL;
@@ -1598,3 +1608,63 @@ void dope_server_destroy(dope_server *s) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------------------------------------------
+// One whole solve in caller-provided device memory, for the entry point that allocates nothing
+// ------------------------------------------------------------------------------------------------------------
+
+namespace dope {
+
+// dope_set_energy_async + dope_solve + dope_labels on a transient host-side context whose workspace is ws (device
+// memory of at least the workspace size of p, 256-byte aligned).  Creates no stream, event, pinned buffer or
+// device allocation: the loop control is copied back into host memory of the context and the stream synchronised
+// at every readback.  u, w, labels are device pointers; the labels are complete on return.  Errors are reported
+// through the thread's dope_last_error(NULL) message.
+dope_status solve_in_buffer(const dope_params *p, void *ws, size_t bytes, const int32_t *u, const int32_t *w,
+                            int32_t lambda_q8, uint8_t *labels, dope_info *out) {
+    if (!p || !u || !w || !labels) {
+        g_create_error = "null params, input or output";
+        return DOPE_EINVAL;
+    }
+    dope_params q = *p;
+    if (q.mu_fact_num == 0 && q.mu_fact_den == 0) { q.mu_fact_num = 21; q.mu_fact_den = 20; }
+    dope_ctx c;
+    std::vector<int32_t> bt;
+    std::string msg = make_geom(&q, c.g, &bt);
+    if (!msg.empty()) {
+        g_create_error = msg;
+        return DOPE_EINVAL;
+    }
+    const size_t need = layout_for(c.g).total;
+    if (need > bytes) {
+        g_create_error = "the problem needs " + std::to_string(need) + " bytes of device state, more than the " +
+                         std::to_string(bytes) + " bytes of the static scratch buffer";
+        return DOPE_EINVAL;
+    }
+    c.p = q;
+    c.hbtab.swap(bt);
+    if (!build_tables(c.g, c.hbtab, c.nbl, c.hchunk)) {
+        g_create_error = "internal: boundary pixel table inconsistent with the partition";
+        return DOPE_EINVAL;
+    }
+    c.stream = static_cast<hipStream_t>(q.stream);
+    c.no_alloc = true;
+    c.hctl = &c.hctl_host;
+    c.ws = static_cast<char *>(ws);
+    c.ws_bytes = bytes;
+    c.own_ws = false;
+    assign_pointers(&c);
+    dope_status st = upload_tables(&c);
+    if (st == DOPE_OK) st = dope_set_energy_async(&c, u, w, lambda_q8, DOPE_MEM_DEVICE);
+    if (st == DOPE_OK) st = dope_solve(&c, out);
+    if (st == DOPE_OK) st = dope_labels(&c, labels, DOPE_MEM_DEVICE);
+    if (st == DOPE_OK && hipStreamSynchronize(c.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        c.err = "stream synchronize after the labels";
+        st = DOPE_EDEVICE;
+    }
+    g_create_error = st == DOPE_OK ? std::string() : c.err;
+    return st;
+}
+
+}  // namespace dope

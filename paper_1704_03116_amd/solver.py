@@ -53,6 +53,28 @@ def autotune(ndim, dims, connectivity):
     return tuple(b), tuple(o)
 
 
+def solve_noalloc(params, u, w, lambda_q8, labels, stream=None):
+    """dope_solve_noalloc: one whole solve whose device state lives in the library's static device array.
+    u, w, labels are device tensors; returns the loop information (dict).  stream: HIP stream handle (None = the
+    current torch stream)."""
+    p = N.dope_params()
+    ctypes.memmove(ctypes.byref(p), ctypes.byref(params), ctypes.sizeof(p))
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    p.stream = ctypes.c_void_p(stream) if stream else None
+    up, uk = _ptr(u)
+    wp, wk = _ptr(w)
+    lp, lk = _ptr(labels)
+    if not (uk == wk == lk == N.DOPE_MEM_DEVICE):
+        raise ValueError("dope_solve_noalloc takes device tensors")
+    info = N.dope_info()
+    st = N.dope_solve_noalloc(ctypes.byref(p), up, wp, int(lambda_q8), lp, ctypes.byref(info))
+    if st != N.DOPE_OK:
+        raise N.DopeError(st, N.dope_last_error(None).decode())
+    return _info(info)
+
+
 class Dope:
     """One DOPE solve context (see include/dope.h)."""
 
