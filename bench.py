@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the DOPE hot path on one MI355X: Mpixel/s to the converged, bit-exact labelling.
 
-One step = one whole solve of one image whose integer energy is already resident in HBM: dope_set_energy
+One step = one whole solve of one image whose integer energy is already resident in HBM: dope_set_energy_async
 (device-to-device copy, weight preparation, state reset), dope_solve (ADMM iterations of Algorithm 1 until the
-stopping rule or the iteration cap) and dope_labels into a device tensor.
+stopping rule or the iteration cap) and dope_labels into a device tensor.  The headline workload is the
+128x128x64 volume (6-connected Potts, 16^3 blocks with 1-voxel overlap), the largest of the single-GPU
+workloads; the 512x512 ellipse image and the 256x256 non-submodular grid follow as secondary lines.
 
-Prints one JSON line.  Roofline: the dominant kernel is the block solve; its achieved rate is the algorithmic
-HBM bytes of one launch (per block pixel: u 4 + weights 4h + Y 4 + A 4 + block label 1) over its average launch
-duration, timed with HIP events on the launch stream inside the timed region.  cpu_baseline times the CPU
-oracle on the same workload."""
+Prints one JSON line.  Roofline: the dominant kernel of the headline workload is the block solve; its achieved
+rate is the algorithmic HBM bytes of one launch (per block pixel: u 4 + weights 4h + Y 4 + A 4 + block label 1;
+per interior pixel Y 4 + A 4 written) over its average launch duration, timed with HIP events on the launch
+stream.  roofline_lds puts the same launches against the LDS bandwidth measured by the library's own probe
+kernel.  cpu_baseline times the CPU oracle on a bounded sample of the same workload; energy_gap compares the
+labels with a serial global min cut (Eq. 12)."""
 import argparse
 import dataclasses
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -23,6 +28,16 @@ HBM_PEAK_GBS = 8000.0
 # int32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane and clock
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 EXH_OPS_PER_CODE = 15
+# host threads for the oracle: the CPU share of a one-GPU machine is 16 cores
+HOST_THREAD_CAP = 16
+
+
+def host_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(HOST_THREAD_CAP, n))
 
 
 def exhaustive_codes(dims, block, overlap):
@@ -82,6 +97,40 @@ def interior_count(dims, block, overlap, r=1):
     return total
 
 
+def block_sizes(dims, block, overlap):
+    """Pixels of every block of the partition (x-fastest block order)."""
+    ext = []
+    for N, B, o in zip(dims, block, overlap):
+        if B <= 0 or B >= N:
+            ext.append([N])
+            continue
+        s = B - o
+        count = 1 + -(-(N - B) // s)
+        ext.append([min(B, N - t * s) for t in range(count)])
+    return [a * b * c for c in ext[2] for b in ext[1] for a in ext[0]]
+
+
+def dir_mask_bytes(h):
+    return 1 if 2 * h <= 8 else (4 if 2 * h <= 32 else (8 if 2 * h <= 64 else 16))
+
+
+def lds_bytes_per_iteration(stats, sizes, h):
+    """Algorithmic LDS bytes of one block-solve launch from the per-block solver statistics {free nodes after
+    elimination, push/relabel rounds, global relabels, elimination passes}: every block stages its graph once
+    (per node: capacity and flow per half-edge 8h, unary/excess 4, height 2, list 2, state 1, direction mask)
+    and reads each node's label once; every sweep over the free nodes reads per node its excess and height
+    (8 bytes) and, per incident arc (2h of them), a residual and a neighbour height (8 bytes).  Sweeps counted:
+    elimination passes, a push and a relabel sweep per round, and one relaxation plus one activity sweep per
+    global relabel (a lower bound: repeated relaxation sweeps and the cut's reachability sweeps are not counted)."""
+    stage = 8 * h + 9 + dir_mask_bytes(h) + 1
+    per_sweep = 8 + 8 * 2 * h
+    total = 0
+    for k, npx in enumerate(sizes):
+        nfree, rounds, grel, casc = (int(x) for x in stats[k])
+        total += npx * stage + nfree * per_sweep * (casc + 2 * rounds + 2 * grel)
+    return total
+
+
 TRAFFIC_RECORDS = {"config2_ellipses512x512_8conn": "hbm_traffic_config2_512x512.json",
                    "config3_spheres128x128x64_6conn": "hbm_traffic_config3_128x128x64.json",
                    "kernel5_ellipses512x512_24conn": "hbm_traffic_kernel5_512x512.json",
@@ -110,49 +159,241 @@ def measured_traffic(workload_name):
     return out
 
 
-def cpu_baseline(p, threads):
-    from oracle import dope as od
+# ------------------------------------------------------------------------------------------------------------
+# plain path: one image per launch sequence
+# ------------------------------------------------------------------------------------------------------------
+
+def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
+    """Times `steps` whole solves of p (energy upload, solve, labels into a device tensor) after `warmup` untimed
+    ones, then the same steps again with per-launch HIP events for the kernel rooflines.  Returns (summary dict,
+    labels tensor, context); the caller closes the context."""
+    import numpy as np
+    import torch
+    from paper_1704_03116_amd.solver import Dope
+
+    print(f"[bench] plain {p.name} n={p.n} steps={steps} warmup={warmup}", file=sys.stderr, flush=True)
+    d = Dope.from_problem(p)
+    u = torch.from_numpy(np.ascontiguousarray(p.u, np.int32)).cuda()
+    w = torch.from_numpy(np.ascontiguousarray(p.w, np.int32)).cuda()
+    lab = torch.empty(p.n, dtype=torch.uint8, device="cuda")
+
+    def step():
+        d.set_energy_async(u, w, p.lam_q8)
+        info = d.solve()
+        d.labels(lab)
+        return info
+
+    for _ in range(warmup):
+        info = step()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st, infos, _, dec = od.run(p, threads=threads)
-    el = time.perf_counter() - t0
-    return el, st, infos, dec
+    for _ in range(steps):
+        info = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # Per-kernel durations come from HIP events recorded around every block-solve and consensus launch on the
+    # solver's stream, over a second pass of the same steps: the event markers leave the GPU idle between
+    # kernels, so the throughput pass above carries none.
+    d.profile_enable(True)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    prof_elapsed = time.perf_counter() - t1
+    prof = d.profile_read()
+    d.profile_enable(False)
+    stats = d.block_stats()
+    ms_per_step = elapsed * 1e3 / steps
+    value = p.n * steps / elapsed / 1e6
+
+    K, tot, h, n = d.K, d.tot, d.h, p.n
+    n_int = interior_count(p.dims, p.block, p.overlap, {24: 2, 48: 3, 32: 2, 80: 4, 122: 3}.get(p.conn, 1))
+    n_bl = tot - n_int
+    kernels = {
+        # per block pixel: u 4 + weights 4h + Y 4 + A 4 read, block label 1 written; per interior pixel (finished
+        # in this kernel): Y 4 + A 4 written
+        "k_block_solve_one": (tot * (13 + 4 * h) + n_int * 8, prof["solve_ms"], prof["solve_launches"]),
+        # per boundary copy: block label 1 + A 4 read, A 4 written; per boundary pixel: weights 4h read, Y 4 written
+        "k_consensus_one": (n_bl * 9 + (n - n_int) * (4 * h + 4), prof["consensus_ms"], prof["consensus_launches"]),
+    }
+    sizes = block_sizes(p.dims, p.block, p.overlap)
+    np_max = max(sizes)
+    mb = dir_mask_bytes(h)
+    state = 64 + np_max * (8 * h + 9 + mb) + (16 if mb > 8 else (8 if mb > 1 else 0))
+    if p.solver != "exhaustive" and state > 160 * 1024:
+        # blocks beyond the LDS: the same block solver with its max-flow state in global memory
+        kernels["k_block_solve_gmem"] = kernels.pop("k_block_solve_one")
+    if p.solver == "exhaustive":
+        # enumeration of every labelling of every block: 2^|block| codes, about 15 integer operations per Gray-code
+        # step (bit flip, unary, the in-block edge deltas, energy update, compare-and-select); VALU-bound
+        del kernels["k_block_solve_one"]
+        kernels["k_block_exhaustive"] = (exhaustive_codes(p.dims, p.block, p.overlap) * EXH_OPS_PER_CODE,
+                                         prof["solve_ms"], prof["solve_launches"])
+    traffic = measured_traffic(p.name)
+
+    # Every step runs the same number of iterations (same input); launches beyond that were enqueued after the
+    # stopping rule held and skipped on the device, so they count for time but not for bytes.
+    working = info["iters_done"] * steps
+
+    def roof(name):
+        amount, ms, launches = kernels[name]
+        avg_ms = ms / max(launches, 1)
+        alu = name == "k_block_exhaustive"
+        scale, peak, unit = (1e12, ALU_PEAK_TOPS, "TOP/s") if alu else (1e9, HBM_PEAK_GBS, "GB/s")
+        achieved = amount * min(working, launches) / (ms * 1e-3) / scale if ms > 0 else 0.0
+        r = {"bound": "alu" if alu else "hbm", "kernel": name, "achieved": round(achieved, 3 if alu else 2),
+             "peak": peak, "unit": unit, "frac": round(achieved / peak, 5), "traffic": traffic.get(name),
+             "avg_launch_ms": round(avg_ms, 5), "launches": launches, "working_launches": min(working, launches)}
+        r["ops_per_launch" if alu else "bytes_per_launch"] = int(amount)
+        r.update({"total_ms": round(ms, 4), "event_pass_ms_per_step": round(prof_elapsed * 1e3 / steps, 4)})
+        return r
+
+    names = sorted(kernels, key=lambda k: -kernels[k][1])
+    out = {
+        "workload": p.name, "value": round(value, 3), "ms_per_step": round(ms_per_step, 4),
+        "grid": list(p.dims[:p.ndim]), "connectivity": p.conn, "block": list(p.block[:p.ndim]),
+        "overlap": list(p.overlap[:p.ndim]), "lambda_q8": p.lam_q8, "mu0": p.mu0, "eps_q16": p.eps_q16,
+        "max_iter": p.max_iter, "blocks": K, "iterations": info["iters_done"], "converged": info["converged"],
+        "solver": p.solver,
+        "roofline": roof(names[0]),
+        "roofline_next": roof(names[1]) if len(names) > 1 else None,
+        "workload_stats": {
+            "free_nodes_frac_last_iter": round(float(stats[:, 0].sum()) / tot, 5),
+            "pushrelabel_rounds_max": int(stats[:, 1].max()), "global_relabels_max": int(stats[:, 2].max()),
+        },
+    }
+    if lds_pass and p.solver != "exhaustive":
+        # per-iteration solver statistics of one solve (iteration by iteration) for the algorithmic LDS bytes
+        d.set_energy_async(u, w, p.lam_q8)
+        lds_total, rounds_total, free_total = 0, 0, 0
+        for _ in range(info["iters_done"]):
+            d.iterate(1)
+            st = d.block_stats()
+            lds_total += lds_bytes_per_iteration(st, sizes, h)
+            rounds_total += int(st[:, 1].sum())
+            free_total += int(st[:, 0].sum())
+        amount, ms, launches = kernels[names[0]] if names[0].startswith("k_block_solve") else (0, 0.0, 0)
+        avg_bytes = lds_total / max(info["iters_done"], 1)
+        avg_ms = ms / max(min(working, launches), 1)
+        ach = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+        out["roofline_lds"] = {
+            "bound": "lds", "kernel": names[0], "achieved": round(ach, 2), "peak": lds_peak_gbs, "unit": "GB/s",
+            "frac": round(ach / lds_peak_gbs, 5) if lds_peak_gbs else None,
+            "bytes_per_launch": int(avg_bytes), "avg_working_launch_ms": round(avg_ms, 5),
+            "free_nodes_per_solve": free_total, "pushrelabel_rounds_per_solve": rounds_total,
+            "peak_source": "measured by dope_measure_lds_bandwidth in this run",
+        }
+    return out, lab, d, info
+
+
+def measure_batch(name, n_images, steps, warmup, plain_value):
+    """n_images images (seeds 0..n-1) as one batch with hipGraph replay: one launch uploads every energy, the
+    batched solve, one launch writes every image's labels."""
+    import numpy as np
+    import torch
+    from paper_1704_03116_amd.solver import Batch, Dope
+    probs = [workload(name, seed=s) for s in range(n_images)]
+    print(f"[bench] batch of {n_images} {probs[0].name}", file=sys.stderr, flush=True)
+    ctxs = [Dope.from_problem(q) for q in probs]
+    ins = [(torch.from_numpy(np.ascontiguousarray(q.u, np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(q.w, np.int32)).cuda()) for q in probs]
+    labs = [torch.empty(q.n, dtype=torch.uint8, device="cuda") for q in probs]
+    for c, q, (uu, ww) in zip(ctxs, probs, ins):
+        c.set_energy(uu, ww, q.lam_q8)
+    b = Batch(ctxs, graph=True)
+    us, ws, lams = [x[0] for x in ins], [x[1] for x in ins], [q.lam_q8 for q in probs]
+
+    def bstep():
+        b.set_energy_async(us, ws, lams)
+        b.solve()
+        b.labels(labs)
+
+    for _ in range(warmup):
+        bstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bstep()
+    torch.cuda.synchronize()
+    bel = time.perf_counter() - t0
+    binfo = b.info()
+    bval = sum(q.n for q in probs) * steps / bel / 1e6
+    out = {"workload": probs[0].name, "images": n_images, "value": round(bval, 3), "unit": "Mpixel/s",
+           "ms_per_step": round(bel * 1e3 / steps, 4), "vs_plain": round(bval / plain_value, 3) if plain_value else None,
+           "graph": True, "seeds": f"0..{n_images - 1}", "iterations": [i["iters_done"] for i in binfo]}
+    b.close()
+    for c in ctxs:
+        c.close()
+    return out
+
+
+# ------------------------------------------------------------------------------------------------------------
+# serving replay
+# ------------------------------------------------------------------------------------------------------------
+
+def _gen_request(r):
+    """Serving request r as (dims, u, w, lambda_q8) (runs in a worker process; numpy only)."""
+    import numpy as np
+    import synth
+    p = synth.config5_request(r)
+    return r, p.dims, np.ascontiguousarray(p.u, np.int32), np.ascontiguousarray(p.w, np.int32), p.lam_q8, p.mu0
 
 
 def serve_replay(n_req, slots):
     """Replay the first n_req requests of the serving trace (Poisson arrivals, 200 req/s) twice: continuous
     batching (up to `slots` requests admitted, one batched ADMM iteration per tick) and the plain path (one request
     at a time, FIFO).  Also runs both closed-loop (every request queued at t = 0) for capacity.  Request inputs are
-    staged in HBM before the replay; block partitions come from dope_autotune."""
+    generated in worker processes (host memory holds a few requests at a time) and staged in HBM before the
+    replay; block partitions come from dope_autotune."""
+    import multiprocessing as mp
     import numpy as np
     import torch
     import synth
-    from concurrent.futures import ThreadPoolExecutor
-    from paper_1704_03116_amd.solver import Server, autotune, params_from_problem
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1704_03116_amd.solver import Server, autotune, make_params
 
     arrivals = synth.config5_trace()[:n_req]
-    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-        probs = list(ex.map(synth.config5_request, range(n_req)))
-    staged = []
-    for p in probs:
-        p.block, p.overlap = autotune(2, p.dims, p.conn)
-        staged.append((params_from_problem(p), torch.from_numpy(np.ascontiguousarray(p.u)).cuda(),
-                       torch.from_numpy(np.ascontiguousarray(p.w)).cuda(),
-                       torch.empty(p.n, dtype=torch.uint8, device="cuda")))
+    staged = [None] * n_req
+    lams = [0] * n_req
+    sizes = [0] * n_req
+    t_gen = time.perf_counter()
+    workers = host_threads()
+    ctx = mp.get_context("spawn")   # the workers never touch the GPU
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        window = 2 * workers
+        pending = {}
+        nxt = 0
+        while nxt < n_req or pending:
+            while nxt < n_req and len(pending) < window:
+                pending[nxt] = ex.submit(_gen_request, nxt)
+                nxt += 1
+            first = min(pending)
+            r, dims, u, w, lam_q8, mu0 = pending.pop(first).result()
+            block, overlap = autotune(2, dims, 8)
+            prm = make_params(dims, 8, block, overlap, mu0, ndim=2)
+            staged[r] = (prm, torch.from_numpy(u).cuda(), torch.from_numpy(w).cuda(),
+                         torch.empty(u.size, dtype=torch.uint8, device="cuda"))
+            lams[r] = lam_q8
+            sizes[r] = u.size
+            if (r + 1) % 250 == 0:
+                print(f"[bench] serving trace: {r + 1} of {n_req} requests staged", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    total_px = sum(p.n for p in probs)
+    gen_s = time.perf_counter() - t_gen
+    total_px = sum(sizes)
 
-    def run(max_active, closed):
+    def run(n, max_active, closed, label):
+        """The first n requests of the trace; closed: every request queued at t = 0."""
         budget = 96 << 30
         srv = Server(budget, max_active)
-        lat = [None] * n_req
+        lat = [None] * n
         owner = {}
         t0 = time.perf_counter()
         nxt, done, last = 0, 0, 0.0
-        while done < n_req:
+        while done < n:
             now = time.perf_counter() - t0
-            while nxt < n_req and (closed or arrivals[nxt] <= now):
+            while nxt < n and (closed or arrivals[nxt] <= now):
                 prm, u, w, lab = staged[nxt]
-                owner[srv.submit(prm, u, w, probs[nxt].lam_q8, lab)] = nxt
+                owner[srv.submit(prm, u, w, lams[nxt], lab)] = nxt
                 nxt += 1
             waiting, active, _ = srv.load()
             if waiting == 0 and active == 0:
@@ -168,17 +409,19 @@ def serve_replay(n_req, slots):
         srv.close()
         first = 0.0 if closed else float(arrivals[0])
         lat_ms = np.array(lat) * 1e3
+        px = sum(sizes[:n])
+        print(f"[bench] serving {label}: {n} requests in {last:.2f} s", file=sys.stderr, flush=True)
         return {"p50_ms": round(float(np.percentile(lat_ms, 50)), 2), "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
-                "mpx_s": round(total_px / (last - first) / 1e6, 2), "makespan_s": round(last - first, 3)}
+                "mpx_s": round(px / (last - first) / 1e6, 2), "makespan_s": round(last - first, 3)}
 
-    run(slots, True)   # warm-up (kernels, allocator)
-    served = run(slots, False)
-    plain = run(1, False)
-    served_cap = run(slots, True)
-    plain_cap = run(1, True)
+    run(min(n_req, 100), slots, True, "warm-up")   # kernels, allocator
+    served = run(n_req, slots, False, "served, open loop")
+    plain = run(n_req, 1, False, "plain, open loop")
+    served_cap = run(n_req, slots, True, "served, closed loop")
+    plain_cap = run(n_req, 1, True, "plain, closed loop")
     return {
         "requests": n_req, "trace": "Poisson 200 req/s, sides {128..2048}, aspect U[0.5, 2], 8-connected, lambda U[0.5, 3]",
-        "mpx_total": round(total_px / 1e6, 1), "slots": slots,
+        "mpx_total": round(total_px / 1e6, 1), "slots": slots, "staging_s": round(gen_s, 1),
         "served_p50_ms": served["p50_ms"], "served_p99_ms": served["p99_ms"], "served_mpx_s": served["mpx_s"],
         "plain_p50_ms": plain["p50_ms"], "plain_p99_ms": plain["p99_ms"], "plain_mpx_s": plain["mpx_s"],
         "served_capacity_mpx_s": served_cap["mpx_s"], "plain_capacity_mpx_s": plain_cap["mpx_s"],
@@ -186,15 +429,72 @@ def serve_replay(n_req, slots):
     }
 
 
+# ------------------------------------------------------------------------------------------------------------
+# CPU baseline and energy gap
+# ------------------------------------------------------------------------------------------------------------
+
+def cpu_baseline(p, sample_iters, full_iters, runs=3):
+    """The oracle as it stands on a bounded sample of the workload: the first sample_iters ADMM iterations (block
+    solves on a thread pool, consensus, multipliers), median of `runs` runs; the Theorem 1 block parameters are
+    built once beforehand, untimed.  The rate is scaled to the iteration count of the GPU's solve."""
+    from oracle import dope as od
+    threads = host_threads()
+    t0 = time.perf_counter()
+    dec = od.decompose(p)
+    setup_s = time.perf_counter() - t0
+    times, st = [], None
+    for _ in range(runs):
+        st = od.initial_state(dec, p.mu0)
+        t1 = time.perf_counter()
+        for _ in range(sample_iters):
+            st, _ = od.iterate(dec, st, threads=threads, mu_num=p.mu_num, mu_den=p.mu_den, eps_q16=p.eps_q16)
+        times.append(time.perf_counter() - t1)
+    med = statistics.median(times)
+    per_iter = med / sample_iters
+    value = p.n / (per_iter * max(full_iters, 1)) / 1e6
+    return {"value": round(value, 5), "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+            "sample": (f"first {sample_iters} ADMM iterations of the same {'x'.join(map(str, p.dims[:p.ndim]))} "
+                       f"workload, median of {runs} runs ({', '.join(f'{t:.2f}' for t in times)} s; block max-flows "
+                       f"on a {threads}-thread pool; Theorem 1 block parameters built beforehand in {setup_s:.1f} s, "
+                       f"untimed), scaled to the {full_iters} iterations of the GPU solve"),
+            "seconds_per_iteration": round(per_iter, 4)}, st, dec
+
+
+def energy_gap(p, gpu_labels, gpu_energy_q8):
+    """Eq. 12 against a serial global min cut of the whole energy (the oracle's Dinic max-flow on one core, the
+    sGC comparator), with the Dice coefficient of the two labellings."""
+    import numpy as np
+    from oracle import dope as od
+    t0 = time.perf_counter()
+    x_gc, e_gc = od.global_mincut(p)
+    gc_s = time.perf_counter() - t0
+    a = np.asarray(gpu_labels, dtype=bool)
+    b = np.asarray(x_gc, dtype=bool)
+    denom = int(a.sum()) + int(b.sum())
+    dice = 2.0 * int((a & b).sum()) / denom if denom else 1.0
+    out = {"E_dope_q8": int(gpu_energy_q8), "E_gc_q8": int(e_gc),
+           "eq12_pct": round((e_gc - gpu_energy_q8) / e_gc * 100.0, 5) if e_gc else None,
+           "gap_pct": round((gpu_energy_q8 - e_gc) / abs(e_gc) * 100.0, 5) if e_gc else None,
+           "dice": round(dice, 6), "serial_gc_s": round(gc_s, 3),
+           "serial_gc_mpx_s": round(p.n / gc_s / 1e6, 4),
+           "serial_gc": "oracle Dinic max-flow over the whole grid on one core (graph build included)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="config3")
+    ap.add_argument("--secondary", default="config2,config4",
+                    help="comma-separated workloads measured after the headline one (plain path; '' = none)")
+    ap.add_argument("--secondary-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=4, help="ADMM iterations of the oracle's timed sample")
     ap.add_argument("--batch", type=int, default=16, help="images of the batched measurement (0 = skip)")
-    ap.add_argument("--serve", type=int, default=200,
+    ap.add_argument("--batch-workload", default="config2")
+    ap.add_argument("--serve", type=int, default=2000,
                     help="requests of the serving replay (first requests of the 2000-request trace; 0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=64, help="max admitted requests when serving")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -207,7 +507,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_1704_03116_amd.solver import Batch, Dope
+    from paper_1704_03116_amd.solver import measure_lds_bandwidth
 
     torch.cuda.set_device(0)
     if args.calibrate_copy:
@@ -217,165 +517,72 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    lds_peak = measure_lds_bandwidth()
     p = workload(args.workload)
-    print(f"[bench] workload {p.name} n={p.n} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-    d = Dope.from_problem(p)
-    u = torch.from_numpy(np.ascontiguousarray(p.u, np.int32)).cuda()
-    w = torch.from_numpy(np.ascontiguousarray(p.w, np.int32)).cuda()
-    lab = torch.empty(p.n, dtype=torch.uint8, device="cuda")
-
-    def step():
-        d.set_energy_async(u, w, p.lam_q8)
-        info = d.solve()
-        d.labels(lab)
-        return info
-
-    for _ in range(args.warmup):
-        info = step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # Per-kernel durations come from HIP events recorded around every block-solve and consensus launch on the
-    # solver's stream, over a second pass of the same steps: the event markers leave the GPU idle between
-    # kernels, so the throughput pass above carries none.
-    d.profile_enable(True)
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    prof_elapsed = time.perf_counter() - t1
-    prof = d.profile_read()
-    d.profile_enable(False)
-    stats = d.block_stats()
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = p.n * args.steps / elapsed / 1e6
-
-    K, tot, h, n = d.K, d.tot, d.h, p.n
-    n_int = interior_count(p.dims, p.block, p.overlap, {24: 2, 48: 3, 32: 2, 80: 4, 122: 3}.get(p.conn, 1))
-    n_bl = tot - n_int
-    kernels = {
-        # per block pixel: u 4 + weights 4h + Y 4 + A 4 read, block label 1 written; per interior pixel (finished
-        # in this kernel): Y 4 + A 4 written
-        "k_block_solve_one": (tot * (13 + 4 * h) + n_int * 8, prof["solve_ms"], prof["solve_launches"]),
-        # per boundary copy: block label 1 + A 4 read, A 4 written; per boundary pixel: weights 4h read, Y 4 written
-        "k_consensus_one": (n_bl * 9 + (n - n_int) * (4 * h + 4), prof["consensus_ms"], prof["consensus_launches"]),
-    }
-    np_max = 1
-    for N, B in zip(p.dims, p.block):
-        np_max *= min(N, B) if B > 0 else N
-    mb = 1 if 2 * h <= 8 else (4 if 2 * h <= 32 else (8 if 2 * h <= 64 else 16))   # direction-mask bytes per node
-    state = 64 + np_max * (8 * h + 9 + mb) + (16 if mb > 8 else (8 if mb > 1 else 0))
-    if p.solver != "exhaustive" and state > 160 * 1024:
-        # blocks beyond the LDS: the same block solver with its max-flow state in global memory
-        kernels["k_block_solve_gmem"] = kernels.pop("k_block_solve_one")
-    if p.solver == "exhaustive":
-        # enumeration of every labelling of every block: 2^|block| codes, about 15 integer operations per Gray-code
-        # step (bit flip, unary, the in-block edge deltas, energy update, compare-and-select); VALU-bound
-        del kernels["k_block_solve_one"]
-        kernels["k_block_exhaustive"] = (exhaustive_codes(p.dims, p.block, p.overlap) * EXH_OPS_PER_CODE,
-                                         prof["solve_ms"], prof["solve_launches"])
-    traffic = measured_traffic(p.name)
-
-    # Every step runs the same number of iterations (same input); launches beyond that were enqueued after the
-    # stopping rule held and skipped on the device, so they count for time but not for bytes.
-    working = info["iters_done"] * args.steps
-
-    def roof(name):
-        amount, ms, launches = kernels[name]
-        avg_ms = ms / max(launches, 1)
-        alu = name == "k_block_exhaustive"
-        scale, peak, unit = (1e12, ALU_PEAK_TOPS, "TOP/s") if alu else (1e9, HBM_PEAK_GBS, "GB/s")
-        achieved = amount * min(working, launches) / (ms * 1e-3) / scale if ms > 0 else 0.0
-        r = {"bound": "alu" if alu else "hbm", "kernel": name, "achieved": round(achieved, 3 if alu else 2),
-             "peak": peak, "unit": unit, "frac": round(achieved / peak, 5), "traffic": traffic.get(name),
-             "avg_launch_ms": round(avg_ms, 5), "launches": launches, "working_launches": min(working, launches)}
-        r["ops_per_launch" if alu else "bytes_per_launch"] = int(amount)
-        r.update({"total_ms": round(ms, 4), "event_pass_ms_per_step": round(prof_elapsed * 1e3 / args.steps, 4)})
-        return r
-
-    names = sorted(kernels, key=lambda k: -kernels[k][1])
+    head, lab, d, info = measure_plain(p, args.steps, args.warmup, lds_peak_gbs=lds_peak["gbs"], lds_pass=True)
+    gpu_energy = d.energy()
+    gpu_labels = lab.cpu().numpy()
+    # state after the oracle's sample iterations, for the sample's own parity check
+    sample_iters = min(args.cpu_iters, max(info["iters_done"], 1))
+    d.set_energy_async(torch.from_numpy(np.ascontiguousarray(p.u, np.int32)).cuda(),
+                       torch.from_numpy(np.ascontiguousarray(p.w, np.int32)).cuda(), p.lam_q8)
+    d.iterate(sample_iters)
+    Yg, Ag, yhg, mug, tg = d.get_state()
+    d.close()
     out = {
         "metric": "Mpixel/s to converged bit-exact labelling",
-        "value": round(value, 3),
+        "value": head["value"],
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i32",
         "data": "synthetic",
-        "config": {
-            "workload": p.name, "path": "plain (one image per launch sequence)", "grid": list(p.dims[:p.ndim]),
-            "connectivity": p.conn, "block": list(p.block[:p.ndim]), "overlap": list(p.overlap[:p.ndim]),
-            "lambda_q8": p.lam_q8, "mu0": p.mu0, "eps_q16": p.eps_q16, "max_iter": p.max_iter, "blocks": K,
-            "iterations": info["iters_done"], "converged": info["converged"], "solver": p.solver,
-        },
-        "roofline": roof(names[0]),
-        "roofline_next": roof(names[1]),
-        "workload_stats": {
-            "free_nodes_frac_last_iter": round(float(stats[:, 0].sum()) / tot, 5),
-            "pushrelabel_rounds_max": int(stats[:, 1].max()), "global_relabels_max": int(stats[:, 2].max()),
-        },
+        "config": {k: head[k] for k in ("workload", "grid", "connectivity", "block", "overlap", "lambda_q8", "mu0",
+                                        "eps_q16", "max_iter", "blocks", "iterations", "converged", "solver")},
+        "roofline": head["roofline"],
+        "roofline_next": head["roofline_next"],
+        "roofline_lds": head.get("roofline_lds"),
+        "lds_bandwidth_probe": lds_peak,
+        "workload_stats": head["workload_stats"],
     }
-    d.close()
+    out["config"]["path"] = "plain (one image per launch sequence)"
+    secondary = {}
+    plain_values = {args.workload: head["value"]}
+    for name in [s for s in args.secondary.split(",") if s]:
+        q = workload(name)
+        sec, _, dsec, _ = measure_plain(q, args.secondary_steps, max(2, args.warmup // 4))
+        dsec.close()
+        plain_values[name] = sec["value"]
+        secondary[name] = sec
+    if secondary:
+        out["secondary"] = secondary
 
     if args.batch > 0:
-        probs = [workload(args.workload, seed=s) for s in range(args.batch)]
-        ctxs = [Dope.from_problem(q) for q in probs]
-        ins = [(torch.from_numpy(np.ascontiguousarray(q.u, np.int32)).cuda(),
-                torch.from_numpy(np.ascontiguousarray(q.w, np.int32)).cuda()) for q in probs]
-        labs = [torch.empty(q.n, dtype=torch.uint8, device="cuda") for q in probs]
-        for c, q, (uu, ww) in zip(ctxs, probs, ins):
-            c.set_energy(uu, ww, q.lam_q8)
-        b = Batch(ctxs, graph=True)
-
-        us, ws, lams = [x[0] for x in ins], [x[1] for x in ins], [q.lam_q8 for q in probs]
-
-        def bstep():
-            # one launch uploads every image's energy, one launch writes every image's labels
-            b.set_energy_async(us, ws, lams)
-            b.solve()
-            b.labels(labs)
-
-        for _ in range(args.warmup):
-            bstep()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            bstep()
-        torch.cuda.synchronize()
-        bel = time.perf_counter() - t0
-        binfo = b.info()
-        bval = sum(q.n for q in probs) * args.steps / bel / 1e6
-        out["batched"] = {"images": args.batch, "value": round(bval, 3), "unit": "Mpixel/s",
-                          "ms_per_step": round(bel * 1e3 / args.steps, 4), "vs_plain": round(bval / value, 3),
-                          "graph": True, "seeds": f"0..{args.batch - 1}",
-                          "iterations": [i["iters_done"] for i in binfo]}
-        b.close()
-        for c in ctxs:
-            c.close()
+        pv = plain_values.get(args.batch_workload)
+        if pv is None:
+            sec, _, dsec, _ = measure_plain(workload(args.batch_workload), args.secondary_steps, 4)
+            dsec.close()
+            pv = sec["value"]
+        out["batched"] = measure_batch(args.batch_workload, args.batch, args.secondary_steps, 4, pv)
+        if "config4" in plain_values:
+            out["batched_config4"] = measure_batch("config4", 8, 5, 1, plain_values["config4"])
 
     if args.serve > 0:
         out["served"] = serve_replay(args.serve, args.serve_slots)
 
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        el, st_o, infos, dec = cpu_baseline(p, threads)
-        from oracle import dope as od
-        same = bool(np.array_equal(lab.cpu().numpy(), od.labels(st_o.Y)))
-        out["cpu_baseline"] = {
-            "value": round(p.n / el / 1e6, 5), "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full solve of the same {p.dims[0]}x{p.dims[1]}x{p.dims[2]} workload (Theorem 1 block "
-                      f"parameters + {len(infos)} ADMM iterations, block max-flows on a {threads}-thread pool) in "
-                      f"{el:.2f} s",
-        }
-        out["labels_match_oracle"] = same
+        print("[bench] oracle sample and serial global cut", file=sys.stderr, flush=True)
+        cb, st_o, dec = cpu_baseline(p, sample_iters, info["iters_done"])
+        out["cpu_baseline"] = cb
+        out["oracle_sample_state_matches"] = bool(
+            np.array_equal(Yg, st_o.Y) and np.array_equal(Ag, st_o.A) and np.array_equal(yhg, st_o.yhat)
+            and mug == st_o.M and tg == st_o.t)
+        out["energy_gap"] = energy_gap(p, gpu_labels, gpu_energy)
     print(json.dumps(out), flush=True)
 
 

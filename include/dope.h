@@ -69,7 +69,20 @@ typedef enum {
     DOPE_EBUSY = -8            /* serving: admission budget exhausted                                    */
 } dope_status;
 
-enum { DOPE_SOLVER_AUTO = 0, DOPE_SOLVER_MAXFLOW = 1, DOPE_SOLVER_EXHAUSTIVE = 2 };
+/* Block sub-problem solvers (Eq. 8):
+ *   MAXFLOW     submodular blocks (w >= 0): push-relabel max preflow in LDS, minimal minimum cut;
+ *   EXHAUSTIVE  blocks of at most 16 pixels, any sign of w: all labellings, smallest-code minimiser;
+ *   LSATR       non-submodular blocks of any size that fit the LDS (4-, 8- and 6-connected stencils): the
+ *               trust-region local submodular approximation of Gorelick et al. (the optimiser the paper distributes
+ *               in its curvature experiment, Sec. 3.3): from x_i = [U_i < 0], each step linearises the terms with
+ *               c_ij < 0 at the current labelling x~ (U_i += c_ij (1 - 2 x~_j)), adds the trust region
+ *               lam (1 - 2 x~_i) to U_i and takes the minimal minimum cut of the rest; the candidate replaces x~ when
+ *               the actual reduction R > 0 and 4 R >= P (P: the reduction the approximation predicts), with
+ *               4 R >= 3 P also lowering lam's level and a rejection raising it (lam = 0 at level -1, 2^14 10^k at
+ *               level k); it stops when the candidate is x~, the level passes 4, or after 32 steps.  Deterministic
+ *               integer arithmetic; a local method (not always the block's minimum).
+ *   AUTO        MAXFLOW when the weights allow, else EXHAUSTIVE for blocks of at most 16 pixels. */
+enum { DOPE_SOLVER_AUTO = 0, DOPE_SOLVER_MAXFLOW = 1, DOPE_SOLVER_EXHAUSTIVE = 2, DOPE_SOLVER_LSATR = 3 };
 enum { DOPE_MEM_HOST = 0, DOPE_MEM_DEVICE = 1 };
 
 typedef struct {
@@ -155,7 +168,8 @@ dope_status dope_set_state(dope_ctx *ctx, const int32_t *Y, const int32_t *A, co
 dope_status dope_block_resid(dope_ctx *ctx, int64_t *resid);
 
 /* Per-block solver statistics of the last iteration, int32[K * 4]:
- * {free nodes after forced-node elimination, push/relabel rounds, global relabels, forced-node cascade rounds}. */
+ * {free nodes after forced-node elimination, push/relabel rounds, global relabels, forced-node cascade rounds};
+ * with the LSA-TR solver: {free nodes of the last step, push/relabel rounds over all steps, steps, final level}. */
 dope_status dope_block_stats(dope_ctx *ctx, int32_t *stats);
 
 /* Block geometry: *n_blocks = K; if table != NULL it receives 7 int32 per block:
@@ -182,12 +196,14 @@ dope_status dope_profile_read(dope_ctx *ctx, double *solve_ms, int32_t *solve_la
                               int32_t *consensus_launches);
 
 /* Block partition for an image: a pure function of (ndim, dims, connectivity), never of load, so that a
- * request's result does not depend on what else is running.  Chosen from measured MI355X throughput of the
- * max-flow path: 8- and 4-connected 2D images use 16x16 blocks with 1-pixel overlap when the shorter side is
- * at most 256 pixels and 32x32 blocks with 1-pixel overlap otherwise (the same for 5x5 neighbourhoods; 7x7 and
- * 9x9 neighbourhoods always use 16x16 blocks, since larger ones exceed the LDS); 6-connected 3D volumes use
- * 16^3 blocks with 1-voxel overlap, radius-2 balls 8^3 and radius-3 balls 6^3 blocks with 1-voxel overlap.  Writes block[3] and
- * overlap[3]; EINVAL for an unsupported stencil. */
+ * request's result does not depend on what else is running.  The choice comes from a table compiled into the
+ * library, written by an offline sweep on MI355X (paper_1704_03116_amd/tune.py; measurements in
+ * profiles/autotune_sweep.json): for every stencil and several image sizes, whole solves (upload, solve to the
+ * stopping rule or max_iter, labels) of serving-style images were timed for every block edge B and overlap o
+ * whose max-flow state fits the LDS (2D: B in {16, 20, 24, 32, 48, 64}, o in {1, 2, 4}; 3D: B in {5, 6, 8, 10,
+ * 12, 16}, o in {1, 2}, as the stencil allows) and the fastest kept.  An image takes the row of the measured
+ * size nearest to its shorter side (class bounds at geometric means).  Writes block[3] and overlap[3]; EINVAL
+ * for an unsupported stencil. */
 dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectivity, int32_t block[3],
                           int32_t overlap[3]);
 
@@ -261,6 +277,57 @@ dope_status dope_server_result(dope_server *s, int64_t ticket, dope_info *info, 
 dope_status dope_server_load(const dope_server *s, int32_t *waiting, int32_t *active, size_t *hbm_in_use);
 const char *dope_server_last_error(const dope_server *s);
 void dope_server_destroy(dope_server *s);
+
+/* ---- Multi-label Potts segmentation: alpha-expansion around DOPE ------------------------------------------
+ * The paper's energy is binary (Eq. 1); its introduction reduces multi-region segmentation to sequences of binary
+ * problems and its conclusion names multi-label energies as the next step.  This layer minimises
+ *     E(L) = sum_i D[L_i, i] + sum_{edges (i,j)} V_ij [L_i != L_j],    L_i in {0, .., n_labels - 1},
+ * by expansion moves (Boykov, Veksler, Zabih 2001): the move of label a lets every pixel keep its label or switch
+ * to a; with y_i = 1 for a switch, twice the move's energy is 2 E(L) + sum_i u_i y_i + sum_edges W_ij |y_i - y_j|,
+ *     u_i  = 2 (D[a, i] - D[L_i, i]) - sum_{j ~ i : L_j != L_i, L_i != a} V_ij (1 + [L_j = a]),
+ *     W_ij = 2 V_ij if L_i = L_j != a;  V_ij if L_i != L_j and neither is a;  0 otherwise,
+ * the binary energy of Eq. (1) with lambda = 1 (lambda_q8 = 256) and w = W >= 0, which an internal DOPE context
+ * with p's grid, stencil, block partition and schedule solves (max-flow solver, Algorithm 1 to its stopping rule
+ * or max_iter).  The move's labelling is accepted only when it lowers E strictly.  Labels start at
+ * argmin_l D[l, i] (smallest l on ties).  Everything is integer and deterministic, so the label sequence is
+ * bit-identical to a CPU implementation of the same loop.
+ * Layout: D int32[n_labels][n] (label-major), V int32[h][n] on the half-stencil layout of dope_set_energy
+ * (lambda folded in), labels uint8[n].  Limits (EINVAL otherwise): 2 <= n_labels <= 255, |D| < 2^26,
+ * 0 <= V <= 2^20 (ENOTSUBMODULAR for V < 0), V = 0 on off-grid edges; a move whose binary weights break the
+ * limits of dope_set_energy fails with that call's error.  The work is ordered on p->stream (NULL: the layer
+ * creates its own stream).  A dope_ml is not thread-safe. */
+typedef struct dope_ml dope_ml;
+
+typedef struct {
+    int32_t cycles;            /* completed passes over all labels                                         */
+    int32_t moves;             /* expansion moves run                                                       */
+    int32_t accepted;          /* moves that lowered E                                                      */
+    int32_t binary_iterations; /* DOPE iterations summed over the moves' solves                             */
+    int64_t energy;            /* E of the current labels                                                   */
+} dope_ml_info;
+
+dope_status dope_ml_create(const dope_params *p, int32_t n_labels, dope_ml **out);
+/* Copy D and V (mem_kind memory; the caller keeps ownership), validate them, set L = argmin D and reset the
+ * counters.  Synchronous. */
+dope_status dope_ml_set_energy(dope_ml *m, const int32_t *D, const int32_t *V, int32_t mem_kind);
+/* One expansion move of `label`: *accepted = 1 when its labelling lowered E; *energy = E afterwards (either may be
+ * NULL).  Synchronous (the acceptance test reads E back). */
+dope_status dope_ml_step(dope_ml *m, int32_t label, int32_t *accepted, int64_t *energy);
+/* Cycles of moves a = 0 .. n_labels - 1 until a cycle accepts no move or max_cycles cycles ran. */
+dope_status dope_ml_solve(dope_ml *m, int32_t max_cycles, dope_ml_info *out);
+/* Current labels, uint8[n]: device memory (stream-ordered) or host memory (complete on return). */
+dope_status dope_ml_labels(dope_ml *m, uint8_t *labels, int32_t mem_kind);
+dope_status dope_ml_info_get(dope_ml *m, dope_ml_info *out);
+const char *dope_ml_last_error(const dope_ml *m);
+void dope_ml_destroy(dope_ml *m);
+
+/* ---- Measurement --------------------------------------------------------------------------------------------
+ * LDS read bandwidth of the GPU (bytes per second), the peak against which the block solver's LDS traffic is
+ * reported: a probe kernel with every CU full (eight 256-thread workgroups per CU, 16 KiB of LDS each) streams
+ * conflict-free 128-bit LDS reads, reps x 16 per thread; the best of three event-timed launches after a warm-up.
+ * stream: hipStream_t (NULL = the null stream).  Synchronises the stream.  Errors: EINVAL (reps <= 0 or null
+ * output), ENOMEM, EDEVICE. */
+dope_status dope_measure_lds_bandwidth(void *stream, int32_t reps, double *bytes_per_s);
 
 /* ---- Solving without allocation ---------------------------------------------------------------------------
  * For callers that cannot allocate (harnesses that forbid hipMalloc, serving loops that must not enter the

@@ -309,6 +309,9 @@ def block_subproblem(dec: Decomposition, k: int, Y: np.ndarray, A_k: np.ndarray,
 def solve_block(dec: Decomposition, k: int, state: State) -> np.ndarray:
     a, b = dec.offsets[k], dec.offsets[k + 1]
     Ut, ea, eb, cap = block_subproblem(dec, k, state.Y, state.A[a:b], state.M)
+    if dec.solver == "lsatr":
+        from . import lsatr
+        return lsatr.lsatr(Ut, ea, eb, cap)
     x, _ = solve_subproblem(Ut, ea, eb, cap, "maxflow" if dec.solver == "maxflow" else "exhaustive")
     return x
 

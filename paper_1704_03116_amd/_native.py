@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSUB
 DOPE_SOLVER_AUTO = 0
 DOPE_SOLVER_MAXFLOW = 1
 DOPE_SOLVER_EXHAUSTIVE = 2
+DOPE_SOLVER_LSATR = 3
 DOPE_MEM_HOST = 0
 DOPE_MEM_DEVICE = 1
 
@@ -37,6 +38,11 @@ class dope_params(ctypes.Structure):
 class dope_server_params(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
+
+
+class dope_ml_info(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("moves", ctypes.c_int32), ("accepted", ctypes.c_int32),
+                ("binary_iterations", ctypes.c_int32), ("energy", ctypes.c_int64)]
 
 
 class dope_info(ctypes.Structure):
@@ -91,6 +97,15 @@ SIGNATURES = {
     "dope_server_destroy": (None, [_P]),
     "dope_solve_noalloc": (ctypes.c_int, [ctypes.POINTER(dope_params), _P, _P, ctypes.c_int32, _P,
                                           ctypes.POINTER(dope_info)]),
+    "dope_measure_lds_bandwidth": (ctypes.c_int, [_P, ctypes.c_int32, _DP]),
+    "dope_ml_create": (ctypes.c_int, [ctypes.POINTER(dope_params), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "dope_ml_set_energy": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "dope_ml_step": (ctypes.c_int, [_P, ctypes.c_int32, _I32P, _I64P]),
+    "dope_ml_solve": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(dope_ml_info)]),
+    "dope_ml_labels": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "dope_ml_info_get": (ctypes.c_int, [_P, ctypes.POINTER(dope_ml_info)]),
+    "dope_ml_last_error": (ctypes.c_char_p, [_P]),
+    "dope_ml_destroy": (None, [_P]),
     "dope_destroy": (None, [_P]),
 }
 
@@ -157,6 +172,15 @@ dope_profile_read = _fn("dope_profile_read")
 dope_last_error = _fn("dope_last_error")
 dope_destroy = _fn("dope_destroy")
 dope_solve_noalloc = _fn("dope_solve_noalloc")
+dope_measure_lds_bandwidth = _fn("dope_measure_lds_bandwidth")
+dope_ml_create = _fn("dope_ml_create")
+dope_ml_set_energy = _fn("dope_ml_set_energy")
+dope_ml_step = _fn("dope_ml_step")
+dope_ml_solve = _fn("dope_ml_solve")
+dope_ml_labels = _fn("dope_ml_labels")
+dope_ml_info_get = _fn("dope_ml_info_get")
+dope_ml_last_error = _fn("dope_ml_last_error")
+dope_ml_destroy = _fn("dope_ml_destroy")
 dope_batch_create = _fn("dope_batch_create")
 dope_batch_set_energy_async = _fn("dope_batch_set_energy_async")
 dope_batch_labels = _fn("dope_batch_labels")

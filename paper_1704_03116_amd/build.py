@@ -28,7 +28,9 @@ def build(verbose: bool = False) -> str:
     units = [([kern], "dope_kernels_main.o", [])] + \
             [([kern], f"dope_kernels_{c}.o", [f"-DDOPE_CONN={c}"]) for c in STENCILS] + \
             [([os.path.join(CSRC, "dope_abi.cpp")], "dope_abi.o", []),
-             ([os.path.join(CSRC, "dope_noalloc.hip")], "dope_noalloc.o", [])]
+             ([os.path.join(CSRC, "dope_noalloc.hip")], "dope_noalloc.o", []),
+             ([os.path.join(CSRC, "dope_probe.hip")], "dope_probe.o", []),
+             ([os.path.join(CSRC, "dope_multilabel.hip")], "dope_multilabel.o", [])]
     compile_flags = [f for f in FLAGS if f != "-shared"]
 
     def compile_one(unit):

@@ -3,6 +3,7 @@
 // checkpoint / inspection entry points.
 #include "../../include/dope.h"
 #include "dope_internal.h"
+#include "autotune_table.h"
 
 #include <algorithm>
 #include <chrono>
@@ -232,6 +233,12 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
             break;
         case DOPE_SOLVER_EXHAUSTIVE:
             if (g.max_np > 16) return "the exhaustive solver needs blocks of at most 16 pixels";
+            break;
+        case DOPE_SOLVER_LSATR:
+            if (p->connectivity != 4 && p->connectivity != 8 && p->connectivity != 6)
+                return "the LSA-TR solver takes the 4-, 8- and 6-connected stencils";
+            if (dope::lsatr_lds_bytes(g.max_np, hs) > dope::LDS_LIMIT - 64 || g.max_np > dope::LSATR_MAX_NP)
+                return "block too large for the LSA-TR solver (its state must fit the LDS)";
             break;
         case DOPE_SOLVER_AUTO:
             if (!maxflow_ok && g.max_np > 16) return too_big;
@@ -557,20 +564,19 @@ dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectiv
                           int32_t overlap[3]) {
     if (!dims || !block || !overlap) return DOPE_EINVAL;
     if (!half_stencil_size(ndim, connectivity)) return DOPE_EINVAL;
-    if (ndim == 3) {
-        // the radius-2 ball needs 141 LDS bytes per node (8^3 blocks), the radius-3 ball 513 (6^3 blocks)
-        const int32_t B = connectivity == 32 ? 8 : (connectivity == 122 ? 6 : 16);
-        for (int a = 0; a < 3; ++a) { block[a] = B; overlap[a] = 1; }
+    // the row of the measured image size nearest to the shorter side (table written by the offline sweep)
+    int32_t short_side = std::min(dims[0], dims[1]);
+    if (ndim == 3) short_side = std::min(short_side, dims[2]);
+    for (const dope::TuneRow &r : dope::TUNE_TABLE) {
+        if (r.ndim != ndim || r.conn != connectivity || short_side > r.max_short_side) continue;
+        for (int a = 0; a < 3; ++a) {
+            const bool on = a < ndim;
+            block[a] = on ? r.block : 1;
+            overlap[a] = on ? r.overlap : 0;
+        }
         return DOPE_OK;
     }
-    const int32_t short_side = std::min(dims[0], dims[1]);
-    // 7x7 and 9x9 neighbourhoods: 32x32 blocks would exceed the LDS (209 and 345 bytes per node)
-    const int32_t B = (short_side <= 256 || connectivity == 48 || connectivity == 80) ? 16 : 32;
-    block[0] = block[1] = B;
-    overlap[0] = overlap[1] = 1;
-    block[2] = 1;
-    overlap[2] = 0;
-    return DOPE_OK;
+    return DOPE_EINVAL;
 }
 
 size_t dope_workspace_bytes(const dope_params *p) {
@@ -681,7 +687,7 @@ dope_status dope_set_energy_async(dope_ctx *c, const int32_t *u, const int32_t *
     if (solver == DOPE_SOLVER_AUTO)
         solver = maxflow_possible(c->g) ? DOPE_SOLVER_MAXFLOW : DOPE_SOLVER_EXHAUSTIVE;
     c->energy_set = false;
-    dope_status st = enqueue_energy(c, u, w, lambda_q8, mem_kind, solver == DOPE_SOLVER_EXHAUSTIVE);
+    dope_status st = enqueue_energy(c, u, w, lambda_q8, mem_kind, solver != DOPE_SOLVER_MAXFLOW);
     if (st != DOPE_OK) return st;
     // host mirror of the reset state; a validation failure shows up at the next readback
     Ctl h{};
@@ -1201,7 +1207,7 @@ dope_status dope_batch_set_energy_async(dope_batch *b, const int32_t *const *u, 
         }
         b->hargs[i] = dope::SetupArg{u_src, w_src, c->p.mu0, uint64_t(c->p.eps_q16) * uint64_t(c->p.eps_q16),
                                      lambda_q8[i], c->p.mu_fact_num, c->p.mu_fact_den,
-                                     int32_t(c->solver == DOPE_SOLVER_EXHAUSTIVE ? 1 : 0)};
+                                     int32_t(c->solver != DOPE_SOLVER_MAXFLOW ? 1 : 0)};
     }
     BHIP_TRY(b, hipMemcpyAsync(b->dargs, b->hargs, n * sizeof(dope::SetupArg), hipMemcpyHostToDevice, b->stream),
              "argument upload");

@@ -117,6 +117,14 @@ inline __host__ __device__ constexpr size_t maxflow_lds_bytes(int np, int hs) {
     return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 8 ? 16 : (mb > 1 ? 8 : 0));
 }
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
+// LDS bytes of the LSA-TR block kernel (stencils with one-byte direction masks: 4, 8 and 6 neighbours): the
+// max-flow state, then per node the signed capacities of its half-edges, the clamped Eq. (8) unary, the mask of
+// its in-block edges and its current label.
+inline __host__ __device__ constexpr size_t lsatr_lds_bytes(int np, int hs) {
+    return ((maxflow_lds_bytes(np, hs) + 15) & ~size_t(15)) + size_t(np) * (4 * hs + 6);
+}
+constexpr int LSATR_THREADS = 256;
+constexpr int LSATR_MAX_NP = 16 * LSATR_THREADS;   // the residual lane sums assume at most 16 pixels per thread
 // Blocks beyond the LDS: workgroup size of the global-memory block solver (1024 threads for the 3x3 stencils, 256
 // for the wide ones, whose solver needs more registers) and its largest block (at most 16 pixels per thread).
 constexpr int gmem_threads(int conn) { return (conn == 4 || conn == 8 || conn == 6) ? 1024 : 256; }

@@ -9,6 +9,8 @@
 //                       persistent work queue.
 //   k_block_exhaustive  one wavefront per block of <= 16 pixels: Gray-code enumeration of all labellings,
 //                       smallest-code minimiser (any sign of the pairwise weights).
+//   k_block_lsatr       one workgroup per non-submodular block that fits the LDS: trust-region local submodular
+//                       approximation steps, each a block max-flow of the linearised problem (3x3 stencils).
 //   k_consensus*        one thread per boundary pixel: Eq. (10) consensus Y, Eq. (11) multipliers of its copies,
 //                       per-block residual of the stopping rule.
 //   k_finalize          loop control: max_k r_k, stopping rule, errors, mu and t.
@@ -917,6 +919,282 @@ __global__ __launch_bounds__(NT, 2) void k_block_solve_gmem(const Img one, int32
     unsigned char *mem = scratch + uint64_t(blockIdx.x) * stride;
     block_maxflow<CONN, NT>(one, xcd_item(blockIdx.x, gridDim.x), mem, npmax, round_limit, relabel_period, par,
                             false);
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// LSA-TR block solve: non-submodular blocks larger than enumeration allows (blocks that fit the LDS)
+// ------------------------------------------------------------------------------------------------------------
+//
+// The trust-region local submodular approximation of Gorelick et al. (CVPR 2014), the non-submodular optimiser
+// whose computations the paper distributes in its curvature experiment (Sec. 3.3).  The block problem is Eq. (8)
+// scaled by 2^14 with capacities of either sign.  Each step linearises the supermodular terms (c < 0) at the
+// current labelling x~ (c (1 - 2 x~_j) added to U_i for every edge (i, j) with c < 0), adds the trust region
+// lam (1 - 2 x~_i) to U_i and solves the remaining submodular problem with the block max-flow (canonical minimal
+// cut).  With R = E(x~) - E(x*) (actual) and P = A(x~) - A(x*) (predicted by the approximation), x* is accepted
+// when R > 0 and 4 R >= P; a step that also has 4 R >= 3 P widens the region (lam level down), a rejected step
+// narrows it (level up).  lam = 0 at level -1 and 2^14 10^k at level k; the search ends when x* = x~, when the level
+// passes LSA_LEVEL_MAX or after LSA_MAX_STEPS steps.  Start: x~_i = [U_i < 0].
+
+constexpr int64_t LSA_LAMBDA_UNIT = 1 << 14;
+constexpr int LSA_LEVEL_MAX = 4;
+constexpr int LSA_MAX_STEPS = 32;
+
+__device__ __forceinline__ int64_t lsa_lambda(int level) {
+    int64_t l = level >= 0 ? LSA_LAMBDA_UNIT : 0;
+    for (int k = 0; k < level; ++k) l *= 10;
+    return l;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) x += __shfl_xor(x, s);
+    return x;
+}
+
+// Label of node p in the solved step: forced nodes carry it in ST_LABEL, free nodes in ST_MARK (the minimal cut).
+__device__ __forceinline__ int lsa_cand(uint8_t sb) {
+    return (sb & ST_FIXED) ? ((sb & ST_LABEL) ? 1 : 0) : ((sb & ST_MARK) ? 1 : 0);
+}
+
+template <int CONN, int NT>
+__device__ __forceinline__ void block_lsatr(const Img &im, int k, unsigned char *smem, int32_t npmax,
+                                            int32_t round_limit, int32_t relabel_period) {
+    constexpr int H = Sten<CONN>::H;
+    constexpr int ND = 2 * H;
+    __shared__ long long s_rp[2];
+    __shared__ int s_chg;
+    const Geom &g = im.g;
+    const GLOBAL Ctl *ctl = gp(im.ctl);
+    const int parity = ctl->t & 1;
+    const int kx = k % g.ax[0].nb, ky = (k / g.ax[0].nb) % g.ax[1].nb, kz = k / (g.ax[0].nb * g.ax[1].nb);
+    const int x0 = kx * g.ax[0].s, y0 = ky * g.ax[1].s, z0 = kz * g.ax[2].s;
+    const int ex = axis_ext(g.ax[0], kx), ey = axis_ext(g.ax[1], ky), ez = axis_ext(g.ax[2], kz);
+    const int64_t off = block_offset(g, kx, ky, kz);
+    const int np = ex * ey * ez;
+    const GLOBAL int32_t *Ain = gp(parity ? im.A1 : im.A0);
+    const int64_t M = ctl->M;
+    const int tid = threadIdx.x;
+
+    // max-flow state (as block_maxflow), then signed capacities, clamped unaries, all-edge masks and labels
+    int *s_ctr = reinterpret_cast<int *>(smem);
+    BlockLds<CONN> L;
+    L.npmax = npmax;
+    L.cap = reinterpret_cast<int32_t *>(smem + 64);
+    L.flw = L.cap + H * npmax;
+    L.dd = L.flw + H * npmax;
+    L.hh = reinterpret_cast<int16_t *>(L.dd + npmax);
+    L.lst = L.hh + npmax;
+    constexpr size_t MB = sizeof(LdsMask<CONN>);
+    {
+        const size_t mo = 64 + size_t(npmax) * (8 * H + 8);
+        L.msk = reinterpret_cast<LdsMask<CONN> *>(smem + ((mo + MB - 1) & ~(MB - 1)));
+    }
+    L.st = reinterpret_cast<uint8_t *>(L.msk + npmax);
+    const size_t base = ((reinterpret_cast<size_t>(L.st + npmax) - reinterpret_cast<size_t>(smem)) + 15) & ~size_t(15);
+    int32_t *csg = reinterpret_cast<int32_t *>(smem + base);              // [H][npmax] signed c (0 if absent)
+    int32_t *u0 = csg + H * npmax;                                        // Eq. (8) unary clamped to int32
+    LdsMask<CONN> *allm = reinterpret_cast<LdsMask<CONN> *>(u0 + npmax);  // in-block directions with c != 0
+    uint8_t *xt = reinterpret_cast<uint8_t *>(allm + npmax);              // current labelling x~
+#pragma unroll
+    for (int o = 0; o < H; ++o) {
+        const int3 v = half_off<CONN>(o);
+        L.loff[o] = v.x + ex * (v.y + ey * v.z);
+    }
+
+    // ---- prologue: Eq. (8) unaries and signed in-block capacities ----
+    const GLOBAL int32_t *gu = gp(im.u), *gcw = gp(im.cw), *gY = gp(im.Y);
+    const double inv_ex = axis_inv_ext(g.ax[0], kx), inv_ey = axis_inv_ext(g.ax[1], ky);
+    for (int p = tid; p < np; p += NT) {
+        const int3 l = block_local(p, ex, ey, inv_ex, inv_ey);
+        PixLoads<CONN> ld;
+        unary_loads<CONN>(g, gu, gcw, gY, Ain, uint32_t(off + p), x0 + l.x, y0 + l.y, z0 + l.z, ld);
+        int32_t cp[H];
+        DirMask<CONN> m;
+        int64_t sumc;
+        const int64_t Ut = unary_from<CONN>(g, ld, M, x0 + l.x, y0 + l.y, z0 + l.z, l.x, l.y, l.z, ex, ey, ez, cp, m,
+                                            sumc);
+#pragma unroll
+        for (int o = 0; o < H; ++o) csg[o * npmax + p] = cp[o];
+        allm[p] = LdsMask<CONN>(m);
+        u0[p] = int32_t(Ut > INT32_MAX ? int64_t(INT32_MAX) : (Ut < -int64_t(INT32_MAX) ? -int64_t(INT32_MAX) : Ut));
+        xt[p] = Ut < 0 ? 1 : 0;
+    }
+    __syncthreads();
+
+    FlowStats tot{0, 0, 0, false};
+    int level = -1, steps = 0, nfree_last = 0;
+    for (int step = 0; step < LSA_MAX_STEPS; ++step) {
+        ++steps;
+        const int64_t lam = lsa_lambda(level);
+        if (tid < 15) s_ctr[tid] = 0;
+        if (tid == 0) { s_rp[0] = 0; s_rp[1] = 0; s_chg = 0; }
+        __syncthreads();
+        // ---- step set-up: linearised and trust-region unaries, positive capacities, strict forcing ----
+        for (int p = tid; p < np; p += NT) {
+            const DirMask<CONN> am = allm[p];
+            int64_t U1 = u0[p];
+            int32_t splus = 0;
+            DirMask<CONN> live = 0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+                if ((am >> d) & 1u) {
+                    const int32_t c = d < H ? csg[d * npmax + p] : csg[(d - H) * npmax + p - L.loff[d - H]];
+                    if (c < 0) {
+                        U1 += int64_t(c) * (1 - 2 * int(xt[L.nbr(p, d)]));
+                    } else {
+                        splus += c;
+                        live |= DirMask<CONN>(1) << d;
+                    }
+                }
+            const int64_t U2 = U1 + lam * (1 - 2 * int(xt[p]));
+#pragma unroll
+            for (int o = 0; o < H; ++o) {
+                const int32_t c = csg[o * npmax + p];
+                L.cap[o * npmax + p] = c > 0 ? c : 0;
+                L.flw[o * npmax + p] = 0;
+            }
+            L.msk[p] = LdsMask<CONN>(live);
+            uint8_t sb = 0;
+            if (U2 < -int64_t(splus)) sb = ST_FIXED | ST_LABEL;
+            else if (U2 > int64_t(splus)) sb = ST_FIXED;
+            L.st[p] = sb;
+            L.dd[p] = sb ? 0 : int32_t(U2);   // |U2| <= splus < 2^29 for free nodes
+            if (!sb) L.lst[atomicAdd(&s_ctr[1], 1)] = int16_t(p);
+        }
+        __syncthreads();
+        const int nfree = s_ctr[1];
+        nfree_last = nfree;
+        FlowStats fs{0, 0, 0, false};
+        if (nfree > 0 && nfree <= WAVE_FLOW_MAX) {
+            if (tid < 64) {
+                WaveSync sy{tid, 64};
+                if (eliminate<CONN>(sy, L, nfree, fs)) flow_network<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
+            }
+        } else if (nfree > 0) {
+            BlockSync sy{tid, NT, s_ctr + 2, 0};
+            if (eliminate<CONN>(sy, L, nfree, fs)) {
+                const int nleft = compact_free<CONN>(L, nfree, s_ctr + 8, tid, NT);
+                if (nleft <= WAVE_FLOW_MAX) {
+                    if (tid < 64) {
+                        WaveSync ws{tid, 64};
+                        flow_network<CONN>(ws, L, nleft, round_limit, relabel_period, fs);
+                    }
+                } else {
+                    flow_network<CONN>(sy, L, nleft, round_limit, relabel_period, fs);
+                }
+            }
+        }
+        tot.rounds += fs.rounds;
+        tot.grel += fs.grel;
+        tot.casc += fs.casc;
+        tot.fail = tot.fail || fs.fail;
+        __syncthreads();
+        // ---- actual and predicted reductions of the candidate ----
+        int64_t eR = 0, eP = 0;
+        int chg = 0;
+        for (int p = tid; p < np; p += NT) {
+            const int xo = xt[p], xn = lsa_cand(L.st[p]);
+            const DirMask<CONN> am = allm[p];
+            if (xo != xn) {
+                chg = 1;
+                int64_t U1 = u0[p];
+#pragma unroll
+                for (int d = 0; d < ND; ++d)
+                    if ((am >> d) & 1u) {
+                        const int32_t c = d < H ? csg[d * npmax + p] : csg[(d - H) * npmax + p - L.loff[d - H]];
+                        if (c < 0) U1 += int64_t(c) * (1 - 2 * int(xt[L.nbr(p, d)]));
+                    }
+                eR += int64_t(u0[p]) * (xo - xn);
+                eP += U1 * (xo - xn);
+            }
+#pragma unroll
+            for (int o = 0; o < H; ++o)
+                if ((am >> o) & 1u) {
+                    const int q = p + L.loff[o];
+                    const int32_t c = csg[o * npmax + p];
+                    const int qo = xt[q], qn = lsa_cand(L.st[q]);
+                    const int t = (xo != qo ? 1 : 0) - (xn != qn ? 1 : 0);
+                    if (t) {
+                        eR += int64_t(c) * t;
+                        if (c > 0) eP += int64_t(c) * t;
+                    }
+                }
+        }
+        eR = wave_sum_i64(eR);
+        eP = wave_sum_i64(eP);
+        chg = __any(chg) ? 1 : 0;
+        if ((tid & 63) == 0) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s_rp[0]), (unsigned long long)eR);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s_rp[1]), (unsigned long long)eP);
+            if (chg) atomicOr(&s_chg, 1);
+        }
+        __syncthreads();
+        const int64_t R = s_rp[0], P = s_rp[1];
+        if (!s_chg) break;                           // x* = x~: no better labelling in the region
+        const bool accepted = R > 0 && 4 * R >= P;
+        if (accepted) {
+            for (int p = tid; p < np; p += NT) xt[p] = uint8_t(lsa_cand(L.st[p]));
+            if (4 * R >= 3 * P && level >= 0) --level;
+        } else {
+            ++level;
+        }
+        __syncthreads();
+        if (!accepted && level > LSA_LEVEL_MAX) break;
+    }
+
+    // ---- labels; consensus and multipliers of the pixels interior to this block (as block_maxflow) ----
+    GLOBAL int32_t *Aout = gp(parity ? im.A0 : im.A1);
+    GLOBAL uint8_t *yhat = gp(im.yhat);
+    GLOBAL uint8_t *yslot = gp(im.yslot);
+    const int nslot = Sten<CONN>::NDIM == 3 ? 8 : 4;
+    GLOBAL int32_t *Yg = gp(im.Y);
+    unsigned long long r2 = 0;
+    bool ovf = false;
+    for (int p = tid; p < np; p += NT) {
+        const int yv = xt[p];
+        const uint32_t cpy = uint32_t(off + p);
+        st_at(yhat, cpy, uint8_t(yv));
+        const int3 l = block_local(p, ex, ey, inv_ex, inv_ey);
+        const int lx = l.x, ly = l.y, lz = l.z;
+        const uint32_t m = uint32_t(x0 + lx) + uint32_t(g.W) * (uint32_t(y0 + ly) + uint32_t(g.H) * uint32_t(z0 + lz));
+        st_at(yslot, m * uint32_t(nslot) + uint32_t(label_slot(g, kx, ky, kz, lx, ly, lz)), uint8_t(yv));
+        if (is_interior(g, kx, ky, kz, x0 + lx, y0 + ly, z0 + lz)) {
+            const int64_t Yn = int64_t(yv) * Y_ONE + ld_at(Ain, cpy << 2);
+            if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = true;
+            const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
+            st_at(Yg, m << 2, int32_t(Yc));
+            st_at(Aout, cpy << 2, int32_t(0));
+            const int64_t rr = int64_t(yv) * Y_ONE - Yc;
+            r2 += (unsigned long long)(rr * rr);
+        }
+    }
+    r2 = wave_sum64(r2);
+    unsigned long long *s_r2 = reinterpret_cast<unsigned long long *>(s_ctr + 6);
+    if (tid == 0) *s_r2 = 0;
+    __syncthreads();
+    if ((tid & 63) == 63 && r2) atomicAdd(s_r2, r2);
+    if (ovf) atomicOr((int32_t *)gp(&im.ctl->ovf_pending), 1);
+    __syncthreads();
+    if (tid == 0) {
+        gp(im.resid)[k] = int64_t(*s_r2);
+        GLOBAL int32_t *st = gp(im.stats) + 4 * k;
+        st[0] = nfree_last;
+        st[1] = tot.rounds;
+        st[2] = steps;
+        st[3] = level;
+        if (tot.fail) atomicOr((int32_t *)gp(&im.ctl->solver_err), 1);
+    }
+}
+
+// LSA-TR block solve, one workgroup per (image, block) item (one image or a batch).
+template <int CONN>
+__global__ __launch_bounds__(LSATR_THREADS) void k_block_lsatr(const Img *__restrict__ imgs,
+                                                               const Item *__restrict__ items, int32_t npmax,
+                                                               int32_t round_limit, int32_t relabel_period) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Item wi = items[blockIdx.x];
+    const Img &im = const_img(imgs + wi.img);
+    if (!ctl_skip(im.ctl)) block_lsatr<CONN, LSATR_THREADS>(im, wi.idx, smem, npmax, round_limit, relabel_period);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -1853,7 +2131,33 @@ hipError_t launch_maxflow_gmem(const Group &grp, hipStream_t s, hipEvent_t e0, h
 }
 
 template <int CONN>
+hipError_t launch_lsatr(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if constexpr (dir_mask_bytes(Sten<CONN>::H) == 1) {
+        const size_t lds = lsatr_lds_bytes(grp.npmax, Sten<CONN>::H);
+        static std::once_flag lds_once;
+        static hipError_t lds_err = hipSuccess;
+        std::call_once(lds_once, [] {
+            lds_err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_block_lsatr<CONN>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(LDS_LIMIT - 64));
+        });
+        if (lds_err != hipSuccess) return lds_err;
+        if (lds > LDS_LIMIT - 64 || grp.npmax > LSATR_MAX_NP) return hipErrorInvalidValue;
+        const int32_t round_limit = 65536 + 64 * grp.npmax;
+        const int32_t relabel_period = 4;
+        const dim3 grid(unsigned(grp.n_blk_items));
+        if (e0) hipExtLaunchKernelGGL(k_block_lsatr<CONN>, grid, dim3(LSATR_THREADS), uint32_t(lds), s, e0, e1, 0u,
+                                      grp.imgs, grp.blk_items, grp.npmax, round_limit, relabel_period);
+        else hipLaunchKernelGGL(k_block_lsatr<CONN>, grid, dim3(LSATR_THREADS), lds, s, grp.imgs, grp.blk_items,
+                                grp.npmax, round_limit, relabel_period);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int CONN>
 hipError_t solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (grp.solver == 3) return launch_lsatr<CONN>(grp, s, e0, e1);
     if (grp.solver == 2) {
         if (e0) {
             hipExtLaunchKernelGGL(k_block_exhaustive<CONN>, dim3(blocks_for(grp.n_blk_items, EX_WAVES)), dim3(256),

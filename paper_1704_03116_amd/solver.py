@@ -33,7 +33,7 @@ def make_params(dims, connectivity, block, overlap, mu0, *, ndim=None, mu_fact=(
     p.eps_q16 = int(eps_q16)
     p.max_iter = int(max_iter)
     p.solver = {"auto": N.DOPE_SOLVER_AUTO, "maxflow": N.DOPE_SOLVER_MAXFLOW,
-                "exhaustive": N.DOPE_SOLVER_EXHAUSTIVE}[solver]
+                "exhaustive": N.DOPE_SOLVER_EXHAUSTIVE, "lsatr": N.DOPE_SOLVER_LSATR}[solver]
     return p
 
 
@@ -73,6 +73,18 @@ def solve_noalloc(params, u, w, lambda_q8, labels, stream=None):
     if st != N.DOPE_OK:
         raise N.DopeError(st, N.dope_last_error(None).decode())
     return _info(info)
+
+
+def measure_lds_bandwidth(reps=2000, stream=None):
+    """dope_measure_lds_bandwidth: measured LDS read bandwidth of the GPU, with the nominal 128 bytes per clock
+    and CU (256 CUs at 2.4 GHz) beside it."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    out = ctypes.c_double()
+    N.check(N.dope_measure_lds_bandwidth(ctypes.c_void_p(stream) if stream else None, int(reps), ctypes.byref(out)))
+    return {"gbs": round(out.value / 1e9, 1), "reps": int(reps),
+            "nominal_gbs_128B_per_clk_per_cu": round(128 * 256 * 2.4e9 / 1e9, 1)}
 
 
 class Dope:
@@ -378,3 +390,85 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class MultiLabel:
+    """A dope_ml: multi-label Potts segmentation by alpha-expansion around DOPE (see include/dope.h)."""
+
+    def __init__(self, dims, connectivity, block, overlap, mu0, n_labels, *, ndim=None, mu_fact=(21, 20),
+                 eps_q16=6554, max_iter=50, stream=None):
+        p = make_params(dims, connectivity, block, overlap, mu0, ndim=ndim, mu_fact=mu_fact, eps_q16=eps_q16,
+                        max_iter=max_iter, solver="maxflow")
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        p.stream = ctypes.c_void_p(stream) if stream else None
+        self.params = p
+        self.n = int(np.prod([int(d) for d in dims]))
+        self.n_labels = int(n_labels)
+        m = ctypes.c_void_p()
+        st = N.dope_ml_create(ctypes.byref(p), int(n_labels), ctypes.byref(m))
+        if st != N.DOPE_OK:
+            raise N.DopeError(st, N.dope_last_error(None).decode())
+        self.m = m
+
+    @classmethod
+    def from_problem(cls, mp, **kw):
+        t = mp.template
+        return cls(t.dims, t.conn, t.block, t.overlap, t.mu0, mp.n_labels, ndim=t.ndim, mu_fact=(t.mu_num, t.mu_den),
+                   eps_q16=t.eps_q16, max_iter=t.max_iter, **kw)
+
+    def _check(self, st):
+        if st != N.DOPE_OK:
+            raise N.DopeError(st, N.dope_ml_last_error(self.m).decode())
+
+    def set_energy(self, D, V):
+        Dc = np.ascontiguousarray(D, np.int32) if isinstance(D, np.ndarray) else D
+        Vc = np.ascontiguousarray(V, np.int32) if isinstance(V, np.ndarray) else V
+        pd, kd = _ptr(Dc)
+        pv, kv = _ptr(Vc)
+        if kd != kv:
+            raise ValueError("D and V must live in the same memory")
+        self._check(N.dope_ml_set_energy(self.m, pd, pv, kd))   # copies synchronously
+
+    def step(self, label):
+        acc = ctypes.c_int32()
+        e = ctypes.c_int64()
+        self._check(N.dope_ml_step(self.m, int(label), ctypes.byref(acc), ctypes.byref(e)))
+        return acc.value, e.value
+
+    def solve(self, max_cycles=5):
+        info = N.dope_ml_info()
+        self._check(N.dope_ml_solve(self.m, int(max_cycles), ctypes.byref(info)))
+        return _ml_info(info)
+
+    def info(self):
+        info = N.dope_ml_info()
+        self._check(N.dope_ml_info_get(self.m, ctypes.byref(info)))
+        return _ml_info(info)
+
+    def labels(self, out=None):
+        if out is None:
+            out = np.zeros(self.n, dtype=np.uint8)
+        p, k = _ptr(out)
+        self._check(N.dope_ml_labels(self.m, p, k))
+        return out
+
+    def close(self):
+        if getattr(self, "m", None):
+            N.dope_ml_destroy(self.m)
+            self.m = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()
+
+
+def _ml_info(info):
+    return {"cycles": info.cycles, "moves": info.moves, "accepted": info.accepted,
+            "binary_iterations": info.binary_iterations, "energy": info.energy}

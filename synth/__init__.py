@@ -21,6 +21,7 @@ from .configs import (  # noqa: F401
     config2_even,
     config3,
     config4,
+    config4_lsatr,
     config5_request,
     config5_image,
     config5_trace,
@@ -32,3 +33,4 @@ from .configs import (  # noqa: F401
     DEFAULT_MU0_3D,
     DEFAULT_EPS_Q16,
 )
+from .multilabel import MultiLabelProblem, multilabel_image  # noqa: F401,E402

@@ -230,6 +230,14 @@ def config4(seed: int = 0, size: int = 256, mu0: int = DEFAULT_MU0_2D) -> Proble
 SERVE_SIDES = (128, 256, 512, 1024, 2048)
 
 
+def config4_lsatr(seed: int = 0, size: int = 256, B: int = 16, o: int = 1, mu0: int = DEFAULT_MU0_2D) -> Problem:
+    """The non-submodular grid of config4 (30 % repulsive edges) in B x B blocks with o-pixel overlap, too large to
+    enumerate: every block is solved by the trust-region local submodular approximation (LSA-TR)."""
+    p = config4(seed=seed, size=size, mu0=mu0)
+    return dataclasses.replace(p, name=f"config4_lsatr{B}_nonsubmodular{size}_4conn", block=(B, B, 1),
+                               overlap=(o, o, 0), solver="lsatr")
+
+
 def config5_request(r: int, mu0: int = DEFAULT_MU0_2D) -> Problem:
     """Serving request r (seed r + 1): grey disk image as config 1 at H in {128..2048}, W = round(H * U[0.5, 2]),
     disk radius 20 * min(H, W) / 64 centred; 8-connected contrast weights (sigma_w = 0.1, diagonals / sqrt 2);
@@ -241,20 +249,21 @@ def config5_request(r: int, mu0: int = DEFAULT_MU0_2D) -> Problem:
     return _disk_request(rng, W, H, lam, f"config5_req{r}_{W}x{H}", mu0)
 
 
-def config5_image(W: int, H: int, lam: float = 1.5, seed: int = 0, mu0: int = DEFAULT_MU0_2D) -> Problem:
-    """A serving-style image of a chosen size (used to tune the block partition per image shape)."""
-    return _disk_request(np.random.default_rng(seed), W, H, lam, f"config5_image_{W}x{H}", mu0)
+def config5_image(W: int, H: int, lam: float = 1.5, seed: int = 0, mu0: int = DEFAULT_MU0_2D,
+                  conn: int = 8) -> Problem:
+    """A serving-style image of a chosen size and 2D stencil (used to tune the block partition per image shape)."""
+    return _disk_request(np.random.default_rng(seed), W, H, lam, f"config5_image_{W}x{H}_{conn}conn", mu0, conn)
 
 
-def _disk_request(rng, W, H, lam, name, mu0) -> Problem:
+def _disk_request(rng, W, H, lam, name, mu0, conn=8) -> Problem:
     cx, cy = W / 2.0, H / 2.0
     rad = 20.0 * min(H, W) / 64.0
     yy, xx = np.mgrid[0:H, 0:W]
     fg = (xx - cx) ** 2 + (yy - cy) ** 2 <= rad * rad
     img = np.where(fg, 0.7, 0.3) + rng.normal(0.0, 0.15, size=(H, W))
     u = _gauss_llr(img, 0.7, 0.3, 0.15)
-    w = _weights_from_features(img[None, :, :, None], 2, 8, 0.1)
-    return Problem(name, (W, H, 1), 2, 8, u.astype(np.int32), w, lambda_q8(lam),
+    w = _weights_from_features(img[None, :, :, None], 2, conn, 0.1)
+    return Problem(name, (W, H, 1), 2, conn, u.astype(np.int32), w, lambda_q8(lam),
                    (0, 0, 0), (0, 0, 0), mu0, truth=fg.reshape(-1).astype(np.uint8))
 
 

@@ -161,16 +161,30 @@ def test_last_error_null_safe(native):
 
 
 def test_autotune_is_a_pure_function_of_shape(native):
+    """dope_autotune returns, for every measured image of the committed MI355X sweep, the fastest candidate of
+    that sweep row; every choice fits the LDS and keeps the stride at least the stencil radius; the result
+    depends on the shape only."""
+    import json
     from paper_1704_03116_amd.solver import autotune
-    assert autotune(2, (128, 128), 8) == ((16, 16, 1), (1, 1, 0))
-    assert autotune(2, (4096, 256), 8) == ((16, 16, 1), (1, 1, 0))
-    assert autotune(2, (512, 300), 8) == ((32, 32, 1), (1, 1, 0))
-    assert autotune(3, (128, 128, 64), 6) == ((16, 16, 16), (1, 1, 1))
-    assert autotune(2, (512, 512), 24) == ((32, 32, 1), (1, 1, 0))
-    assert autotune(2, (512, 512), 48) == ((16, 16, 1), (1, 1, 0))
-    assert autotune(3, (128, 128, 64), 32) == ((8, 8, 8), (1, 1, 1))
-    assert autotune(2, (512, 512), 80) == ((16, 16, 1), (1, 1, 0))
-    assert autotune(3, (128, 128, 64), 122) == ((6, 6, 6), (1, 1, 1))
-    assert autotune(2, (512, 512), 8) == autotune(2, (512, 512), 8)
+    rec = json.load(open(os.path.join(ROOT, "profiles", "autotune_sweep.json")))
+    half = {4: 2, 8: 4, 24: 12, 48: 24, 80: 40, 6: 3, 32: 16, 122: 61}
+    radius = {4: 1, 8: 1, 24: 2, 48: 3, 80: 4, 6: 1, 32: 2, 122: 3}
+    for sw in rec["sweeps"]:
+        nd, conn = sw["ndim"], sw["conn"]
+        # of measured images that share a shorter side, the largest decides that side's row
+        deciding = {}
+        for row in sorted(sw["rows"], key=lambda r: (min(r["dims"]), int(np.prod(r["dims"])))):
+            deciding[min(row["dims"])] = row
+        for row in deciding.values():
+            best = row["best"]
+            assert best["mpx_s"] == max(r["mpx_s"] for r in row["runs"])
+            blk, ovl = autotune(nd, tuple(row["dims"]), conn)
+            assert blk[:nd] == (best["B"],) * nd and ovl[:nd] == (best["o"],) * nd, (conn, row["dims"])
+            h = half[conn]
+            mb = 1 if 2 * h <= 8 else (4 if 2 * h <= 32 else (8 if 2 * h <= 64 else 16))
+            assert 64 + best["B"] ** nd * (8 * h + 9 + mb) + 16 <= 160 * 1024
+            assert best["B"] - best["o"] >= radius[conn] and 2 * best["o"] <= best["B"]
+    assert autotune(2, (512, 300), 8) == autotune(2, (300, 512), 8) == autotune(2, (300, 9000), 8)
+    assert autotune(2, (4096, 2048), 8)[0] == (32, 32, 1)
     with pytest.raises(Exception):
         autotune(2, (64, 64), 6)

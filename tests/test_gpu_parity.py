@@ -918,3 +918,54 @@ def test_solve_with_no_iteration_reports_a_rejected_upload():
         st_o, _, _, _ = od.run(good, n_iter=3)
         Y, A, yh, mu, t = e.get_state()
         assert t == 3 and np.array_equal(Y, st_o.Y) and np.array_equal(A, st_o.A) and np.array_equal(yh, st_o.yhat)
+
+
+# ------------------------------------------------------------------------------------------------------------
+# non-submodular blocks beyond enumeration: the LSA-TR block solver
+# ------------------------------------------------------------------------------------------------------------
+
+LSATR_CASES = [
+    # label, dims, conn, block, overlap
+    ("4-connected 8x8 blocks", (40, 34, 1), 4, (8, 8, 1), (1, 1, 0)),
+    ("4-connected 16x16 blocks o=2", (70, 50, 1), 4, (16, 16, 1), (2, 2, 0)),
+    ("8-connected 12x12 blocks", (45, 40, 1), 8, (12, 12, 1), (1, 1, 0)),
+    ("6-connected 6^3 blocks", (20, 17, 14), 6, (6, 6, 6), (1, 1, 1)),
+    ("4-connected 40x40 blocks", (100, 90, 1), 4, (40, 40, 1), (2, 2, 0)),
+]
+
+
+@pytest.mark.parametrize("case", LSATR_CASES, ids=[c[0] for c in LSATR_CASES])
+def test_lsatr_nonsubmodular_every_iteration(case):
+    """Repulsive edges (30 %) in blocks larger than enumeration allows: the LSA-TR steps of every block, the
+    consensus and the multipliers equal the oracle's bit for bit after every iteration; the block search takes
+    several steps somewhere."""
+    label, dims, conn, block, overlap = case
+    p = synth.random_problem(61, dims, conn, block, overlap, lam_q8=256, u_range=(-1000, 1000),
+                             w_range=(50, 500), neg_frac=0.3, mu0=2000, solver="lsatr")
+    stats = []
+    d, _, _ = run_parity(p, 6, f"LSA-TR, {label}", stats=stats)
+    assert max(int(s[:, 2].max()) for s in stats) >= 2
+    d.close()
+
+
+def test_lsatr_on_submodular_blocks_equals_maxflow():
+    """Without repulsive edges the first LSA-TR step of every block is the minimal minimum cut and the second finds
+    nothing better and stops: the whole ADMM state equals the max-flow solver's."""
+    p = synth.random_problem(62, (60, 44, 1), 8, (16, 16, 1), (2, 2, 0), lam_q8=256, mu0=1000)
+    q = dataclasses.replace(p, solver="lsatr")
+    a, b = make_ctx(p, solver="maxflow"), make_ctx(q, solver="lsatr")
+    for _ in range(5):
+        a.iterate(1)
+        b.iterate(1)
+        sa, sb = a.get_state(), b.get_state()
+        assert all(np.array_equal(x, y) for x, y in zip(sa[:3], sb[:3])) and sa[3:] == sb[3:]
+    assert int(b.block_stats()[:, 2].max()) <= 2
+    a.close()
+    b.close()
+
+
+@pytest.mark.timeout(600)
+def test_config4_lsatr_full_size_every_iteration():
+    """The 256x256 non-submodular grid in 16x16 blocks (289 LSA-TR blocks): 3 iterations, whole state."""
+    d, st, dec = run_parity(synth.config4_lsatr(), 3, "config4 256x256 LSA-TR 16x16 blocks full size")
+    d.close()
