@@ -67,6 +67,13 @@ def workload(name, seed=0):
         return synth.config_kernel(int(name[-1]), seed=seed)
     if name in ("even32", "even64", "even128"):   # the config2 image in 32 / 64 / 128 even blocks (o = 2)
         return synth.config2_even(int(name[4:]), seed=seed)
+    if name.startswith("paper2d_K"):   # paper2d_K<32|64|128>_s<00|10|25>: the 2D experiments' partitions
+        K, pct = name[len("paper2d_K"):].split("_s")
+        return synth.config2_sized(int(K), int(pct), seed=seed)
+    if name == "paper3d_K128_s10":   # the 3D experiments' partition: 128 blocks grown by 10 %
+        return synth.config3_sized(128, 10, seed=seed)
+    if name == "config4_lsatr":   # the non-submodular grid in 16x16 blocks (LSA-TR block solver)
+        return synth.config4_lsatr(seed=seed)
     if name in ("kernel5_3d", "kernel7_3d"):   # the config3 volume with the radius-2 / radius-3 ball
         return synth.config3_kernel5(seed=seed, k=int(name[6]))
     if name in ("kernel5_3d_big", "kernel7_3d_big"):   # the same with 16^3 / 12^3 blocks (beyond the LDS)
@@ -223,6 +230,9 @@ def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
     if p.solver != "exhaustive" and state > 160 * 1024:
         # blocks beyond the LDS: the same block solver with its max-flow state in global memory
         kernels["k_block_solve_gmem"] = kernels.pop("k_block_solve_one")
+    if p.solver == "lsatr":
+        # the LSA-TR block solve reads and writes what the max-flow block solve does (its steps stay in LDS)
+        kernels["k_block_lsatr"] = kernels.pop("k_block_solve_one")
     if p.solver == "exhaustive":
         # enumeration of every labelling of every block: 2^|block| codes, about 15 integer operations per Gray-code
         # step (bit flip, unary, the in-block edge deltas, energy update, compare-and-select); VALU-bound
@@ -262,7 +272,7 @@ def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
             "pushrelabel_rounds_max": int(stats[:, 1].max()), "global_relabels_max": int(stats[:, 2].max()),
         },
     }
-    if lds_pass and p.solver != "exhaustive":
+    if lds_pass and p.solver == "maxflow":
         # per-iteration solver statistics of one solve (iteration by iteration) for the algorithmic LDS bytes
         d.set_energy_async(u, w, p.lam_q8)
         lds_total, rounds_total, free_total = 0, 0, 0
@@ -325,6 +335,44 @@ def measure_batch(name, n_images, steps, warmup, plain_value):
     for c in ctxs:
         c.close()
     return out
+
+
+def measure_multilabel(steps, warmup, W=512, H=512, n_labels=4, max_cycles=5):
+    """Alpha-expansion around DOPE on a W x H image with n_labels Potts labels (8-connected contrast weights,
+    32x32 blocks with o = 2): one step = data and weights upload, expansion cycles until no move lowers the
+    energy (at most max_cycles), labels into a device tensor."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1704_03116_amd.solver import MultiLabel
+    mp = synth.multilabel_image(seed=0, W=W, H=H, n_labels=n_labels)
+    print(f"[bench] multi-label {mp.name}", file=sys.stderr, flush=True)
+    D = torch.from_numpy(np.ascontiguousarray(mp.D)).cuda()
+    V = torch.from_numpy(np.ascontiguousarray(mp.V)).cuda()
+    lab = torch.empty(W * H, dtype=torch.uint8, device="cuda")
+    m = MultiLabel.from_problem(mp)
+    info = None
+
+    def step():
+        m.set_energy(D, V)
+        i = m.solve(max_cycles)
+        m.labels(lab)
+        return i
+
+    for _ in range(warmup):
+        info = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m.close()
+    agree = float((lab.cpu().numpy() == mp.truth).mean())
+    return {"workload": mp.name, "value": round(W * H * steps / el / 1e6, 3), "unit": "Mpixel/s",
+            "ms_per_step": round(el * 1e3 / steps, 3), "labels": n_labels, "cycles": info["cycles"],
+            "moves": info["moves"], "accepted": info["accepted"], "binary_iterations": info["binary_iterations"],
+            "energy": info["energy"], "agreement_with_generating_regions": round(agree, 4)}
 
 
 # ------------------------------------------------------------------------------------------------------------
@@ -487,8 +535,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="config3")
-    ap.add_argument("--secondary", default="config2,config4",
+    ap.add_argument("--secondary", default="config2,config4,config4_lsatr,paper2d_K64_s10,paper3d_K128_s10",
                     help="comma-separated workloads measured after the headline one (plain path; '' = none)")
+    ap.add_argument("--multilabel", type=int, default=1, help="measure the alpha-expansion layer (0 = skip)")
     ap.add_argument("--secondary-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=4, help="ADMM iterations of the oracle's timed sample")
@@ -571,6 +620,9 @@ def main():
         out["batched"] = measure_batch(args.batch_workload, args.batch, args.secondary_steps, 4, pv)
         if "config4" in plain_values:
             out["batched_config4"] = measure_batch("config4", 8, 5, 1, plain_values["config4"])
+
+    if args.multilabel:
+        out["multilabel"] = measure_multilabel(max(2, args.secondary_steps // 8), 1)
 
     if args.serve > 0:
         out["served"] = serve_replay(args.serve, args.serve_slots)

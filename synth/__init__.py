@@ -19,6 +19,8 @@ from .configs import (  # noqa: F401
     config1,
     config2,
     config2_even,
+    config2_sized,
+    config3_sized,
     config3,
     config4,
     config4_lsatr,

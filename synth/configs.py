@@ -189,6 +189,39 @@ def config2_even(K: int, seed: int = 0, W: int = 512, H: int = 512, mu0: int = D
                                block=(size(W, nbx), size(H, nby), 1), overlap=(o, o, 0))
 
 
+def _sized_axis(N: int, nb: int, pct: int) -> Tuple[int, int]:
+    """Block edge and overlap of nb even blocks along an axis of length N grown by pct percent: stride s = N / nb
+    (Size_00 blocks, each pixel in one block), B = round(s (1 + pct / 100)), o = B - s."""
+    if N % nb:
+        raise ValueError("the axis must split into equal blocks")
+    s = N // nb
+    B = int(_round(np.float64(s * (1.0 + pct / 100.0)))) if pct else s
+    return B, B - s
+
+
+def config2_sized(K: int, pct: int, seed: int = 0, W: int = 512, H: int = 512, mu0: int = DEFAULT_MU0_2D) -> Problem:
+    """The config2 image in the 2D experiments' partitions (Sec. 3 set-up): K = 32, 64 or 128 even blocks (8 x 4,
+    8 x 8 or 16 x 8 along x, y) that cover the image without overlap (Size_00, pct = 0), then grown by 10 % or 25 %
+    per axis (Size_10, Size_25), so that neighbouring blocks overlap by the growth."""
+    nbx, nby = {32: (8, 4), 64: (8, 8), 128: (16, 8)}[K]
+    Bx, ox = _sized_axis(W, nbx, pct)
+    By, oy = _sized_axis(H, nby, pct)
+    base = config2(seed=seed, W=W, H=H, mu0=mu0)
+    return dataclasses.replace(base, name=f"config2_K{K}_size{pct:02d}_ellipses{W}x{H}_8conn",
+                               block=(Bx, By, 1), overlap=(ox, oy, 0))
+
+
+def config3_sized(K: int = 128, pct: int = 10, seed: int = 0, dims=(128, 128, 64), mu0: int = DEFAULT_MU0_3D) -> Problem:
+    """The config3 volume in the 3D experiments' partition: K = 64 or 128 even blocks (4 x 4 x 4 or 8 x 4 x 4 along
+    x, y, z), grown by pct percent per axis (Size_10 in the paper's 3D setting)."""
+    nb = {64: (4, 4, 4), 128: (8, 4, 4)}[K]
+    blk, ovl = zip(*[_sized_axis(N, n, pct) for N, n in zip(dims, nb)])
+    base = config3(seed=seed, dims=dims, mu0=mu0)
+    W, H, D = dims
+    return dataclasses.replace(base, name=f"config3_K{K}_size{pct:02d}_spheres{W}x{H}x{D}_6conn",
+                               block=tuple(blk), overlap=tuple(ovl))
+
+
 def config3(seed: int = 0, dims=(128, 128, 64), mu0: int = DEFAULT_MU0_3D) -> Problem:
     """128x128x64 volume with 3 random spheres (r in U[8, 24]) + N(0, 0.2^2); 6-connected constant Potts
     w = 1000; lambda = 1.5; 16^3 blocks, o = 1."""

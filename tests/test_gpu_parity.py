@@ -601,7 +601,49 @@ def test_blocks_beyond_lds_every_iteration(label, make):
     the wide ones) run the same solver with that state in the workspace: Y, A, yhat, mu, t and the block
     residuals equal the oracle's after every iteration."""
     p = make()
-    d, st_o, dec = run_parity(p, 6, f"beyond LDS, {label}")
+    stats = []
+    d, st_o, dec = run_parity(p, 6, f"beyond LDS, {label}", stats=stats)
+    d.close()
+    # the global-memory solver runs its elimination on these random weights (free nodes after the forcing test)
+    assert sum(int(s[:, 0].sum()) for s in stats) > 0
+
+
+def test_blocks_beyond_lds_smoothing_dominated_flow():
+    """Large blocks in global memory with smoothing far above the unaries: the push-relabel phase (its global-memory
+    atomics, barrier slots and list compaction) runs in every block of the first iterations, and the state still
+    equals the oracle's after every iteration."""
+    for conn, dims, block in [(8, (180, 150, 1), (100, 80, 1)), (6, (34, 30, 26), (20, 18, 16))]:
+        p = synth.random_problem(27, dims, conn, block, (2, 2, 2 if conn == 6 else 0), lam_q8=512,
+                                 u_range=(-400, 400), w_range=(200, 1000), mu0=4000)
+        stats = []
+        d, _, _ = run_parity(p, 4, f"beyond LDS, smoothing-dominated conn={conn}", stats=stats)
+        d.close()
+        assert int(stats[0][:, 0].sum()) > 0 and int(stats[0][:, 1].sum()) > 0 and int(stats[0][:, 2].sum()) > 0
+
+
+PAPER_PARTITIONS = [(32, 25), (64, 10), (64, 0), (128, 0), (128, 25)]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("K,pct", PAPER_PARTITIONS, ids=[f"K{k}_size{p:02d}" for k, p in PAPER_PARTITIONS])
+def test_paper_partitions_2d_every_iteration(K, pct):
+    """The 512x512 image in the 2D experiments' partitions (K even blocks, Size_00 / Size_10 / Size_25): blocks of
+    2048 to 12800 pixels, in LDS or beyond it; whole state after every iteration, then the labels of the solve."""
+    p = synth.config2_sized(K, pct)
+    d, st, dec = run_parity(p, 3, f"paper partition K={K} Size_{pct:02d}: block={p.block} overlap={p.overlap}")
+    d.close()
+    st_o, infos, _, _ = od.run(p, dec=dec)
+    with make_ctx(p) as e:
+        info = e.solve()
+        assert info["iters_done"] == len(infos) and np.array_equal(e.labels(), od.labels(st_o.Y))
+
+
+@pytest.mark.timeout(900)
+def test_paper_partition_3d_every_iteration():
+    """The 128x128x64 volume in 128 blocks grown by 10 % (the paper's 3D setting): 18x35x18 blocks of 11340 voxels
+    in global memory; whole state after each of 3 iterations."""
+    p = synth.config3_sized(128, 10)
+    d, st, dec = run_parity(p, 3, f"paper partition 3D K=128 Size_10: block={p.block} overlap={p.overlap}")
     d.close()
 
 
