@@ -16,9 +16,14 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 # ADMM schedule defaults in input-energy units (weights and unaries are x1000 integers).  The paper's
-# mu0 = 100 (2D) / 500 (3D) are in unstated units; with x1000 inputs the equivalent sweep picks these.
+# mu0 = 100 (2D) / 500 (3D) are in unstated units; with x1000 inputs the oracle's sweep (oracle/sweep_mu.py,
+# results in oracle/mu_sweep.json) picks these: in 2D mu0 = 1000 stops the 512x512 image after 2 iterations with
+# no energy gap; in 3D mu0 = 1500 gives the smallest gap to the global cut on the 128x128x64 volume (0.05 % against
+# 0.13-4.3 % for 500, 5000, 15000 and 50000; none meets the stopping rule within 50 iterations).  The balls keep
+# the value they were tuned with (BALL_MU0).
 DEFAULT_MU0_2D = 1000
-DEFAULT_MU0_3D = 5000
+DEFAULT_MU0_3D = 1500
+BALL_MU0 = 5000
 DEFAULT_EPS_Q16 = 6554  # eps = 0.1 in Q16.16
 DEFAULT_MAX_ITER = 50
 
@@ -328,7 +333,7 @@ def config_kernel(k: int, seed: int = 0, W: int = 512, H: int = 512, mu0: int = 
                    truth=fg.reshape(-1).astype(np.uint8))
 
 
-def config3_kernel5(seed: int = 0, dims=(128, 128, 64), mu0: int = DEFAULT_MU0_3D, k: int = 5) -> Problem:
+def config3_kernel5(seed: int = 0, dims=(128, 128, 64), mu0: int = BALL_MU0, k: int = 5) -> Problem:
     """The volume of config3 with the spherical kernel of size k: the radius-2 ball (k = 5, 32 neighbours) or the
     radius-3 ball (k = 7, 122 neighbours), distance-weighted Potts w = round(1000 / |offset|), lambda = 0.4 or
     0.16 (total smoothing per voxel near config3's 1.5 x 6 x 1000); 8^3 or 6^3 blocks with o = 1 (141 or 513 LDS
