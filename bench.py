@@ -227,7 +227,7 @@ def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
     np_max = max(sizes)
     mb = dir_mask_bytes(h)
     state = 64 + np_max * (8 * h + 9 + mb) + (16 if mb > 8 else (8 if mb > 1 else 0))
-    if p.solver != "exhaustive" and state > 160 * 1024:
+    if p.solver != "exhaustive" and state > 160 * 1024 - 1024:
         # blocks beyond the LDS: the same block solver with its max-flow state in global memory
         kernels["k_block_solve_gmem"] = kernels.pop("k_block_solve_one")
     if p.solver == "lsatr":

@@ -76,13 +76,13 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // The max-flow solver takes the partition's blocks: in LDS, or in global memory for the stencils that have that
 // solver.
 bool maxflow_possible(const Geom &g) {
-    return dope::maxflow_lds_bytes(g.max_np, g.hs) <= dope::LDS_LIMIT || g.max_np <= dope::gmem_max_np(g.conn);
+    return dope::maxflow_lds_bytes(g.max_np, g.hs) <= dope::MAXFLOW_LDS_LIMIT || g.max_np <= dope::gmem_max_np(g.conn);
 }
 
 // Per-block max-flow state in global memory when a block exceeds the LDS (0 otherwise).
 size_t gmem_stride(const Geom &g) {
     const size_t b = dope::maxflow_lds_bytes(g.max_np, g.hs);
-    return b > dope::LDS_LIMIT ? align256(b) : 0;
+    return b > dope::MAXFLOW_LDS_LIMIT ? align256(b) : 0;
 }
 
 
@@ -222,7 +222,7 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
     if (p->max_iter < 0) return "max_iter must be >= 0";
     // blocks beyond the LDS take the global-memory solver (at most 16384 pixels with the 3x3 stencils, 4096 with
     // the wide ones)
-    const bool maxflow_ok = dope::maxflow_lds_bytes(g.max_np, hs) <= dope::LDS_LIMIT ||
+    const bool maxflow_ok = dope::maxflow_lds_bytes(g.max_np, hs) <= dope::MAXFLOW_LDS_LIMIT ||
                             g.max_np <= dope::gmem_max_np(p->connectivity);
     const std::string too_big_msg = "block too large for the max-flow solver: more than " +
                                     std::to_string(dope::gmem_max_np(p->connectivity)) + " pixels beyond the LDS";

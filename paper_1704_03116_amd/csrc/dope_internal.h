@@ -117,6 +117,9 @@ inline __host__ __device__ constexpr size_t maxflow_lds_bytes(int np, int hs) {
     return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 8 ? 16 : (mb > 1 ? 8 : 0));
 }
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
+// Dynamic LDS the max-flow block kernels may take: the rest of the 160 KiB holds their static arrays (the per-axis
+// cover rows of a block).
+constexpr size_t MAXFLOW_LDS_LIMIT = LDS_LIMIT - 1024;
 // LDS bytes of the LSA-TR block kernel (stencils with one-byte direction masks: 4, 8 and 6 neighbours): the
 // max-flow state, then per node the signed capacities of its half-edges, the clamped Eq. (8) unary, the mask of
 // its in-block edges and its current label.

@@ -368,18 +368,50 @@ __device__ __forceinline__ void unary_loads(const Geom &g, const GLOBAL int32_t 
     }
 }
 
-// Eq. (8) unary of a block pixel (scaled by 2^14, unary floored) and its block-local edge data, from its loads.
-// cap_out[o] = c for in-block half-edges (0 otherwise); mask bit d set for in-block neighbours with c != 0;
-// sumc = sum of |c| over in-block neighbours.  q_j is a power of two, so (q_j - [j in k]) c (Y_i - Y_j) is a
-// 32 x 32 -> 64-bit product, a shift and a conditional subtraction.
+// log2 q of a pixel's stencil box from per-axis bit rows: bit t + R of bx is log2 of the number of blocks that
+// contain the x coordinate at offset t (0 off the grid), likewise by and bz.  A block builds the rows of its
+// coordinates once (block_lq_rows), so its pixels skip the per-pixel cover computation of BoxCov.
 template <int CONN>
-__device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN> &ld, int64_t M, int gx, int gy,
-                                              int gz, int lx, int ly, int lz, int ex, int ey, int ez,
-                                              int32_t *cap_out, DirMask<CONN> &mask, int64_t &sumc) {
+struct TabCov {
+    static constexpr int R = Sten<CONN>::R;
+    uint32_t bx, by, bz;
+    __device__ __forceinline__ int lq(int3 v) const {
+        return int((bx >> (v.x + R)) & 1u) + int((by >> (v.y + R)) & 1u) + int((bz >> (v.z + R)) & 1u);
+    }
+};
+
+// Per-axis rows of TabCov for the coordinates of one block (extents up to LQ_TAB per axis).
+constexpr int LQ_TAB = 128;
+template <int CONN, int NT>
+__device__ __forceinline__ void block_lq_rows(const Geom &g, int x0, int y0, int z0, int ex, int ey, int ez,
+                                              uint16_t (*rows)[LQ_TAB]) {
+    constexpr int R = Sten<CONN>::R;
+    for (int i = threadIdx.x; i < ex + ey + ez; i += NT) {
+        const int a = i < ex ? 0 : (i < ex + ey ? 1 : 2);
+        const int l = a == 0 ? i : (a == 1 ? i - ex : i - ex - ey);
+        uint32_t bits = 0;
+        if (a < Sten<CONN>::NDIM) {
+            AxCov c[2 * R + 1];
+            axis_cov<R>(g.ax[a], (a == 0 ? x0 : (a == 1 ? y0 : z0)) + l, c);
+#pragma unroll
+            for (int t = 0; t <= 2 * R; ++t) bits |= uint32_t(c[t].cnt >= 2 ? 1 : 0) << t;
+        }
+        rows[a][l] = uint16_t(bits);
+    }
+}
+
+// Eq. (8) unary of a block pixel (scaled by 2^14, unary floored) and its block-local edge data, from its loads and
+// the covers of its stencil box (BoxCov or TabCov).  cap_out[o] = c for in-block half-edges (0 otherwise); mask
+// bit d set for in-block neighbours with c != 0; sumc = sum of |c| over in-block neighbours.  q_j is a power of
+// two: in 2D (q_j <= 4) F = (q_j - [j in k]) c fits 32 bits and each neighbour costs one 32 x 32 -> 64-bit
+// multiply-add; in 3D (q_j <= 8) the other factor, (Y_i - Y_j)(q_j - [j in k]), fits 32 bits (|Y| <= 2^22) and
+// multiplies c the same way.
+template <int CONN, class Cov>
+__device__ __forceinline__ int64_t unary_from_cov(const Cov &bc, const PixLoads<CONN> &ld, int64_t M, int lx,
+                                                  int ly, int lz, int ex, int ey, int ez, int32_t *cap_out,
+                                                  DirMask<CONN> &mask, int64_t &sumc) {
     constexpr int H = Sten<CONN>::H;
     constexpr int ND = 2 * H;
-    BoxCov<CONN> bc;
-    bc.init(g, gx, gy, gz);
     const int lqi = bc.lq(make_int3(0, 0, 0));
     const DirMask<CONN> inb_m = inside_mask<CONN>(lx, ly, lz, ex, ey, ez);   // in the block implies on the grid
     int64_t G = 0;
@@ -392,13 +424,11 @@ __device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN
         const bool inb = (inb_m >> d) & 1u;
         const int lqj = bc.lq(v);
         if (Sten<CONN>::NDIM == 2) {
-            // q_j <= 4 in 2D, so F = (q_j - [j in k]) c stays below 2^31 in magnitude: one 32 x 32 -> 64-bit
-            // multiply-add per neighbour
             const int32_t F = c * (1 << lqj) - (inb ? c : 0);
             G += int64_t(F) * int64_t(ld.Y - ld.yj[d]);
         } else {
-            const int64_t t = int64_t(c) * int64_t(ld.Y - ld.yj[d]);
-            G += (t << lqj) - (inb ? t : 0);
+            const int32_t t = (ld.Y - ld.yj[d]) * ((1 << lqj) - (inb ? 1 : 0));
+            G += int64_t(c) * int64_t(t);
         }
         if (d < H) cap_out[d] = inb ? c : 0;
         const bool on = inb && c != 0;
@@ -408,6 +438,15 @@ __device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN
     sumc = sc;
     const int64_t mu_term = (M << 14) * int64_t(ld.a - ld.Y + Y_HALF);
     return int64_t(ld.u) * int64_t(16384 >> lqi) + ((G + mu_term) >> 16);
+}
+
+template <int CONN>
+__device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN> &ld, int64_t M, int gx, int gy,
+                                              int gz, int lx, int ly, int lz, int ex, int ey, int ez,
+                                              int32_t *cap_out, DirMask<CONN> &mask, int64_t &sumc) {
+    BoxCov<CONN> bc;
+    bc.init(g, gx, gy, gz);
+    return unary_from_cov<CONN>(bc, ld, M, lx, ly, lz, ex, ey, ez, cap_out, mask, sumc);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -745,6 +784,10 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         const int3 v = half_off<CONN>(o);
         L.loff[o] = v.x + ex * (v.y + ey * v.z);
     }
+    // covers of the block's coordinates, once per block (blocks of at most LQ_TAB pixels per axis)
+    __shared__ uint16_t s_lq[3][LQ_TAB];
+    const bool lq_tab = ex <= LQ_TAB && ey <= LQ_TAB && ez <= LQ_TAB;   // uniform
+    if (lq_tab) block_lq_rows<CONN, NT>(g, x0, y0, z0, ex, ey, ez, s_lq);
     if (tid < 15) s_ctr[tid] = 0;
     __syncthreads();
 
@@ -758,8 +801,13 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         int32_t cp[H];
         DirMask<CONN> m;
         int64_t sumc;
-        const int64_t Ut = unary_from<CONN>(g, ld, M, x0 + l.x, y0 + l.y, z0 + l.z, l.x, l.y, l.z, ex, ey, ez, cp, m,
-                                            sumc);
+        int64_t Ut;
+        if (lq_tab) {
+            const TabCov<CONN> tc{s_lq[0][l.x], s_lq[1][l.y], s_lq[2][l.z]};
+            Ut = unary_from_cov<CONN>(tc, ld, M, l.x, l.y, l.z, ex, ey, ez, cp, m, sumc);
+        } else {
+            Ut = unary_from<CONN>(g, ld, M, x0 + l.x, y0 + l.y, z0 + l.z, l.x, l.y, l.z, ex, ey, ez, cp, m, sumc);
+        }
 #pragma unroll
         for (int o = 0; o < H; ++o) {
             L.cap[o * npmax + p] = cp[o];
@@ -2084,10 +2132,10 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s, hipEvent_t e0, hipEve
                               reinterpret_cast<const void *>(&k_block_solve_one<CONN, NT>)};
         for (const void *f : fns)
             if (lds_err == hipSuccess)
-                lds_err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(LDS_LIMIT));
+                lds_err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(MAXFLOW_LDS_LIMIT));
     });
     if (lds_err != hipSuccess) return lds_err;
-    if (lds > LDS_LIMIT) return hipErrorInvalidValue;
+    if (lds > MAXFLOW_LDS_LIMIT) return hipErrorInvalidValue;
     if ((grp.npmax + NT - 1) / NT > 16) return hipErrorInvalidValue;   // the residual lane sums assume <= 16
     const int32_t round_limit = 65536 + 64 * grp.npmax;
     const int32_t workers = grp.n_workers > 0 ? (grp.n_workers < grp.n_blk_items ? grp.n_workers : grp.n_blk_items)
@@ -2174,11 +2222,11 @@ hipError_t solve_phase(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_
     // resident at once and neighbours on a CU hide each other's barrier and LDS latency.  Measured on MI355X with
     // 32x32 8-connected blocks: 289 and 1089 blocks both favour 512 threads.
     // stencils so wide that no block of more than 512 pixels fits the LDS get the 256-thread kernels only
-    if constexpr (maxflow_lds_bytes(513, Sten<CONN>::H) > LDS_LIMIT) {
+    if constexpr (maxflow_lds_bytes(513, Sten<CONN>::H) > MAXFLOW_LDS_LIMIT) {
         return launch_maxflow<CONN, 256>(grp, s, e0, e1);
     } else {
         if (grp.npmax > 512) {
-            const bool one_per_cu = maxflow_lds_bytes(grp.npmax, Sten<CONN>::H) > LDS_LIMIT / 2;
+            const bool one_per_cu = maxflow_lds_bytes(grp.npmax, Sten<CONN>::H) > MAXFLOW_LDS_LIMIT / 2;
             if (one_per_cu || grp.n_blk_items <= NUM_CUS) return launch_maxflow<CONN, 1024>(grp, s, e0, e1);
             return launch_maxflow<CONN, 512>(grp, s, e0, e1);
         }
