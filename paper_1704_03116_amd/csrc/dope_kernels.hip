@@ -177,6 +177,30 @@ __device__ __forceinline__ int3 block_local(int p, int ex, int ey, double inv_ex
     return make_int3(lx, ly, lz);
 }
 
+// Local coordinates of positions p0, p0 + stride, p0 + 2 stride, ... of a block with extents ex, ey (x fastest):
+// the first from one division, the others by adding the stride in the block's mixed radix (one carry per axis at
+// most, since each digit of the stride is below the extent).
+struct LocalWalk {
+    int lx, ly, lz, dx, dy, dz, ex, ey;
+    __device__ __forceinline__ void init(int p0, int stride, int ex_, int ey_, double inv_ex, double inv_ey) {
+        ex = ex_;
+        ey = ey_;
+        const int3 l = block_local(p0, ex, ey, inv_ex, inv_ey);
+        const int3 d = block_local(stride, ex, ey, inv_ex, inv_ey);
+        lx = l.x; ly = l.y; lz = l.z;
+        dx = d.x; dy = d.y; dz = d.z;
+    }
+    __device__ __forceinline__ void next() {
+        lx += dx;
+        const int cx = lx >= ex ? 1 : 0;
+        lx -= cx ? ex : 0;
+        ly += dy + cx;
+        const int cy = ly >= ey ? 1 : 0;
+        ly -= cy ? ey : 0;
+        lz += dz + cy;
+    }
+};
+
 // Covers of x - R .. x + R (0 <= x < N, R at most the stride s when the axis has several blocks) from one
 // division: floor((x + t) / s) differs from floor(x / s) by at most one, downwards when rem + t < 0 and upwards
 // when rem + t >= s.
@@ -794,8 +818,10 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     // ---- prologue: Eq. (8) unaries, in-block capacities, strictly forced nodes, list of the others ----
     const GLOBAL int32_t *gu = gp(im.u), *gcw = gp(im.cw), *gY = gp(im.Y);
     const double inv_ex = axis_inv_ext(g.ax[0], kx), inv_ey = axis_inv_ext(g.ax[1], ky);
-    for (int p = tid; p < np; p += NT) {
-        const int3 l = block_local(p, ex, ey, inv_ex, inv_ey);
+    LocalWalk walk;
+    walk.init(tid, NT, ex, ey, inv_ex, inv_ey);
+    for (int p = tid; p < np; p += NT, walk.next()) {
+        const int3 l = make_int3(walk.lx, walk.ly, walk.lz);
         PixLoads<CONN> ld;
         unary_loads<CONN>(g, gu, gcw, gY, Ain, uint32_t(off + p), x0 + l.x, y0 + l.y, z0 + l.z, ld);
         int32_t cp[H];
@@ -857,13 +883,13 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     GLOBAL int32_t *Yg = gp(im.Y);
     unsigned long long r2 = 0;
     bool ovf = false;
-    for (int p = tid; p < np; p += NT) {
+    walk.init(tid, NT, ex, ey, inv_ex, inv_ey);
+    for (int p = tid; p < np; p += NT, walk.next()) {
         const uint8_t sb = L.st[p];
         const int yv = (sb & ST_FIXED) ? ((sb & ST_LABEL) ? 1 : 0) : ((sb & ST_MARK) ? 1 : 0);
         const uint32_t cpy = uint32_t(off + p);
         st_at(yhat, cpy, uint8_t(yv));
-        const int3 l = block_local(p, ex, ey, inv_ex, inv_ey);
-        const int lx = l.x, ly = l.y, lz = l.z;
+        const int lx = walk.lx, ly = walk.ly, lz = walk.lz;
         const uint32_t m = uint32_t(x0 + lx) + uint32_t(g.W) * (uint32_t(y0 + ly) + uint32_t(g.H) * uint32_t(z0 + lz));
         st_at(yslot, m * uint32_t(nslot) + uint32_t(label_slot(g, kx, ky, kz, lx, ly, lz)), uint8_t(yv));
         if (is_interior(g, kx, ky, kz, x0 + lx, y0 + ly, z0 + lz)) {
