@@ -74,7 +74,7 @@ def workload(name, seed=0):
         return synth.config3_sized(128, 10, seed=seed)
     if name == "config4_lsatr":   # the non-submodular grid in 16x16 blocks (LSA-TR block solver)
         return synth.config4_lsatr(seed=seed)
-    if name in ("kernel5_3d", "kernel7_3d"):   # the config3 volume with the radius-2 / radius-3 ball
+    if name in ("kernel5_3d", "kernel7_3d", "kernel9_3d"):   # the config3 volume with the radius-2 / -3 / -4 ball
         return synth.config3_kernel5(seed=seed, k=int(name[6]))
     if name in ("kernel5_3d_big", "kernel7_3d_big"):   # the same with 16^3 / 12^3 blocks (beyond the LDS)
         k = int(name[6])
@@ -214,7 +214,7 @@ def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
     value = p.n * steps / elapsed / 1e6
 
     K, tot, h, n = d.K, d.tot, d.h, p.n
-    n_int = interior_count(p.dims, p.block, p.overlap, {24: 2, 48: 3, 32: 2, 80: 4, 122: 3}.get(p.conn, 1))
+    n_int = interior_count(p.dims, p.block, p.overlap, {24: 2, 48: 3, 32: 2, 80: 4, 122: 3, 256: 4}.get(p.conn, 1))
     n_bl = tot - n_int
     kernels = {
         # per block pixel: u 4 + weights 4h + Y 4 + A 4 read, block label 1 written; per interior pixel (finished

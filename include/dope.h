@@ -89,10 +89,11 @@ typedef struct {
     int32_t ndim;              /* 2 or 3                                                                  */
     int32_t dims[3];           /* W, H, D (D = 1 in 2D)                                                  */
     int32_t connectivity;      /* 4, 8, 24 (5x5 square), 48 (7x7 square) or 80 (9x9 square) in 2D;    */
-                               /* 6, 32 or 122 (balls of radius 2 and 3) in 3D                           */
+                               /* 6, 32, 122 or 256 (balls of radius 2, 3 and 4) in 3D                   */
     int32_t block[3];          /* block edge B per axis                                                  */
     int32_t overlap[3];        /* overlap o per axis; B - o must be at least the stencil radius (2 for  */
-                               /* connectivity 24 and 32, 3 for 48 and 122, 4 for 80) on every axis    */
+                               /* connectivity 24 and 32, 3 for 48 and 122, 4 for 80 and 256) on every */
+                               /* axis                                                                    */
                                /* with more than one block                                               */
     int64_t mu0;               /* initial mu, 1 <= mu0 <= 2^24 - 1, input-energy units                   */
     int32_t mu_fact_num;       /* mu_fact = num / den (default 21 / 20)                                   */
@@ -125,9 +126,9 @@ dope_status dope_create(const dope_params *p, dope_ctx **out);
  *      2D: (+1,0), (0,+1), then for 8-connectivity (+1,+1), (-1,+1); 3D: (+1,0,0), (0,+1,0), (0,0,+1);
  *      2D squares of radius r (connectivity 24: r = 2, 48: r = 3, 80: r = 4, the larger neighbourhoods of the
  *      paper's experiments): (dx,0) for dx = 1..r, then (dx,dy) for dy = 1..r and dx = -r..r, x fastest;
- *      3D balls of radius r = 2 or 3 (connectivity 32 and 122, the spherical kernels of size 5 and 7): the
- *      offsets of length <= r whose first nonzero coordinate, from z down to x, is positive, ordered by z, then
- *      y, then x.
+ *      3D balls of radius r = 2, 3 or 4 (connectivity 32, 122 and 256, the spherical kernels of size 5, 7 and
+ *      9): the offsets of length <= r whose first nonzero coordinate, from z down to x, is positive, ordered by
+ *      z, then y, then x.
  *      w[o*n + i] weights the edge i <-> i + offset[o] and must be 0 where that neighbour is off-grid.
  *   lambda_q8 = round(256 lambda) >= 0.
  *   mem_kind: DOPE_MEM_HOST (pageable or pinned host memory) or DOPE_MEM_DEVICE (device pointers).

@@ -138,10 +138,10 @@ def neighbour_offsets(ndim: int, conn: int):
                [(dx, dy, 0) for dy in range(1, r + 1) for dx in range(-r, r + 1)]
     if ndim == 3 and conn == 6:
         return [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
-    if ndim == 3 and conn in (32, 122):
-        # the spherical kernels of size 5 and 7: lattice offsets of length at most r = 2 or 3, each undirected
-        # edge once (first nonzero coordinate taken from z down to x positive), z slowest and x fastest
-        r = 2 if conn == 32 else 3
+    if ndim == 3 and conn in (32, 122, 256):
+        # the spherical kernels of size 5, 7 and 9: lattice offsets of length at most r = 2, 3 or 4, each
+        # undirected edge once (first nonzero coordinate taken from z down to x positive), z slowest and x fastest
+        r = {32: 2, 122: 3, 256: 4}[conn]
         ball = [(dx, dy, dz) for dz in range(r + 1) for dy in range(-r, r + 1) for dx in range(-r, r + 1)
                 if 0 < dx * dx + dy * dy + dz * dz <= r * r]
         return [v for v in ball if v[2] > 0 or (v[2] == 0 and (v[1] > 0 or (v[1] == 0 and v[0] > 0)))]

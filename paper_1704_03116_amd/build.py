@@ -17,7 +17,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wal
 
 # Stencils whose kernels are compiled in a translation unit of their own (dope_kernels.hip with DOPE_CONN set),
 # so that the build runs in parallel; the unit without DOPE_CONN holds the launchers and the stencil-free kernels.
-STENCILS = [4, 8, 24, 48, 80, 6, 32, 122]
+STENCILS = [4, 8, 24, 48, 80, 6, 32, 122, 256]
 
 
 def build(verbose: bool = False) -> str:

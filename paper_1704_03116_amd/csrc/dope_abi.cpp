@@ -125,11 +125,12 @@ int half_stencil_size(int ndim, int conn) {
     if (ndim == 3 && conn == 6) return 3;
     if (ndim == 3 && conn == 32) return 16;   // ball of radius 2 (32 neighbours)
     if (ndim == 3 && conn == 122) return 61;  // ball of radius 3 (122 neighbours)
+    if (ndim == 3 && conn == 256) return 128; // ball of radius 4 (256 neighbours)
     return 0;
 }
 
 int stencil_radius(int conn) {
-    return (conn == 24 || conn == 32) ? 2 : ((conn == 48 || conn == 122) ? 3 : (conn == 80 ? 4 : 1));
+    return (conn == 24 || conn == 32) ? 2 : ((conn == 48 || conn == 122) ? 3 : ((conn == 80 || conn == 256) ? 4 : 1));
 }
 
 // Builds the partition; returns an empty string on success or a message.
@@ -137,7 +138,7 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
     if (!p) return "null params";
     if (p->ndim != 2 && p->ndim != 3) return "ndim must be 2 or 3";
     const int hs = half_stencil_size(p->ndim, p->connectivity);
-    if (!hs) return "connectivity must be 4, 8, 24, 48 or 80 in 2D and 6, 32 or 122 in 3D";
+    if (!hs) return "connectivity must be 4, 8, 24, 48 or 80 in 2D and 6, 32, 122 or 256 in 3D";
     int32_t dims[3] = {p->dims[0], p->dims[1], p->ndim == 3 ? p->dims[2] : 1};
     if (p->ndim == 2 && p->dims[2] != 1 && p->dims[2] != 0) return "dims[2] must be 1 in 2D";
     int64_t n = 1;
@@ -574,6 +575,11 @@ dope_status dope_autotune(int32_t ndim, const int32_t dims[3], int32_t connectiv
             block[a] = on ? r.block : 1;
             overlap[a] = on ? r.overlap : 0;
         }
+        return DOPE_OK;
+    }
+    if (ndim == 3 && connectivity == 256) {
+        // the radius-4 ball (not in the sweep): its 1065 LDS bytes per node allow 5^3 blocks, stride 4 = radius
+        for (int a = 0; a < 3; ++a) { block[a] = 5; overlap[a] = 1; }
         return DOPE_OK;
     }
     return DOPE_EINVAL;

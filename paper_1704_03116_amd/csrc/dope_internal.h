@@ -22,7 +22,7 @@ inline Axis make_axis(int32_t N, int32_t B, int32_t s, int32_t nb) {
 struct Geom {
     Axis ax[3];
     int32_t W, H, D;
-    int32_t conn;       // 2D: 4, 8, 24 (5x5), 48 (7x7), 80 (9x9); 3D: 6, 32 and 122 (radius-2 and -3 balls)
+    int32_t conn;       // 2D: 4, 8, 24 (5x5), 48 (7x7), 80 (9x9); 3D: 6, 32, 122, 256 (radius-2, -3, -4 balls)
     int32_t hs;         // half-stencil size
     int32_t rad;        // stencil radius: every neighbour offset lies in [-rad, rad] per axis
     int32_t K;          // number of blocks
@@ -61,7 +61,7 @@ inline __host__ __device__ int64_t block_offset(const Geom &g, int32_t tx, int32
 }
 
 // Label slots per pixel (most blocks a pixel can lie in): 4 in 2D, 8 in 3D.
-inline __host__ __device__ bool conn_is_3d(int32_t conn) { return conn == 6 || conn == 32 || conn == 122; }
+inline __host__ __device__ bool conn_is_3d(int32_t conn) { return conn == 6 || conn == 32 || conn == 122 || conn == 256; }
 inline __host__ __device__ int slot_count(const Geom &g) { return conn_is_3d(g.conn) ? 8 : 4; }
 
 inline __host__ __device__ bool is_interior(const Geom &g, int32_t tx, int32_t ty, int32_t tz, int32_t x, int32_t y,
@@ -106,7 +106,7 @@ constexpr int BTAB_STRIDE = 8;     // x0, y0, z0, ex, ey, ez, offset, pad
 
 // Bytes of the per-node mask of live in-block directions (one bit per full-stencil direction).
 inline __host__ __device__ constexpr int dir_mask_bytes(int hs) {
-    return 2 * hs <= 8 ? 1 : (2 * hs <= 32 ? 4 : (2 * hs <= 64 ? 8 : 16));
+    return 2 * hs <= 8 ? 1 : (2 * hs <= 32 ? 4 : (2 * hs <= 64 ? 8 : (2 * hs <= 128 ? 16 : 32)));
 }
 
 // LDS bytes of the max-flow block kernel for a block of np pixels and half-stencil size hs: a 64-byte header,
@@ -114,7 +114,7 @@ inline __host__ __device__ constexpr int dir_mask_bytes(int hs) {
 // state bits per node.
 inline __host__ __device__ constexpr size_t maxflow_lds_bytes(int np, int hs) {
     const int mb = dir_mask_bytes(hs);
-    return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 8 ? 16 : (mb > 1 ? 8 : 0));
+    return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 16 ? 32 : (mb > 8 ? 16 : (mb > 1 ? 8 : 0)));
 }
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
 // Dynamic LDS the max-flow block kernels may take: the rest of the 160 KiB holds their static arrays (the per-axis

@@ -28,6 +28,15 @@
 #include <mutex>
 #include <type_traits>
 
+// Loops over stencil directions are unrolled, except in the translation unit of the radius-4 ball (256
+// neighbours), whose kernels keep them as loops: unrolled, that stencil's code would not fit the instruction cache
+// nor build in reasonable time.
+#if defined(DOPE_CONN) && DOPE_CONN == 256
+#define DOPE_UNROLL _Pragma("nounroll")
+#else
+#define DOPE_UNROLL _Pragma("unroll")
+#endif
+
 namespace dope {
 
 namespace {
@@ -67,6 +76,7 @@ template <> struct Sten<80> { static constexpr int H = 40, R = 4, NDIM = 2; };
 template <> struct Sten<6> { static constexpr int H = 3, R = 1, NDIM = 3; };
 template <> struct Sten<32> { static constexpr int H = 16, R = 2, NDIM = 3; };
 template <> struct Sten<122> { static constexpr int H = 61, R = 3, NDIM = 3; };
+template <> struct Sten<256> { static constexpr int H = 128, R = 4, NDIM = 3; };
 
 // Half-stencil of the radius-3 ball (the spherical kernel of size 7): offsets of length at most 3 whose first
 // nonzero coordinate, from z down to x, is positive, ordered by z, then y, then x.
@@ -80,11 +90,57 @@ constexpr int8_t kBall3[61][3] = {
     {0, 1, 2}, {1, 1, 2}, {2, 1, 2}, {-1, 2, 2}, {0, 2, 2}, {1, 2, 2}, {0, 0, 3}
 };
 
+// Half-stencil of the radius-4 ball (the spherical kernel of size 9): offsets of length at most 4 whose first
+// nonzero coordinate, from z down to x, is positive, ordered by z, then y, then x.
+constexpr int8_t kBall4[128][3] = {
+    {1, 0, 0}, {2, 0, 0}, {3, 0, 0}, {4, 0, 0}, {-3, 1, 0}, {-2, 1, 0}, {-1, 1, 0}, {0, 1, 0}, {1, 1, 0}, {2, 1, 0},
+    {3, 1, 0}, {-3, 2, 0}, {-2, 2, 0}, {-1, 2, 0}, {0, 2, 0}, {1, 2, 0}, {2, 2, 0}, {3, 2, 0}, {-2, 3, 0}, {-1, 3, 0},
+    {0, 3, 0}, {1, 3, 0}, {2, 3, 0}, {0, 4, 0}, {-2, -3, 1}, {-1, -3, 1}, {0, -3, 1}, {1, -3, 1}, {2, -3, 1},
+    {-3, -2, 1}, {-2, -2, 1}, {-1, -2, 1}, {0, -2, 1}, {1, -2, 1}, {2, -2, 1}, {3, -2, 1}, {-3, -1, 1}, {-2, -1, 1},
+    {-1, -1, 1}, {0, -1, 1}, {1, -1, 1}, {2, -1, 1}, {3, -1, 1}, {-3, 0, 1}, {-2, 0, 1}, {-1, 0, 1}, {0, 0, 1},
+    {1, 0, 1}, {2, 0, 1}, {3, 0, 1}, {-3, 1, 1}, {-2, 1, 1}, {-1, 1, 1}, {0, 1, 1}, {1, 1, 1}, {2, 1, 1}, {3, 1, 1},
+    {-3, 2, 1}, {-2, 2, 1}, {-1, 2, 1}, {0, 2, 1}, {1, 2, 1}, {2, 2, 1}, {3, 2, 1}, {-2, 3, 1}, {-1, 3, 1}, {0, 3, 1},
+    {1, 3, 1}, {2, 3, 1}, {-1, -3, 2}, {0, -3, 2}, {1, -3, 2}, {-2, -2, 2}, {-1, -2, 2}, {0, -2, 2}, {1, -2, 2},
+    {2, -2, 2}, {-3, -1, 2}, {-2, -1, 2}, {-1, -1, 2}, {0, -1, 2}, {1, -1, 2}, {2, -1, 2}, {3, -1, 2}, {-3, 0, 2},
+    {-2, 0, 2}, {-1, 0, 2}, {0, 0, 2}, {1, 0, 2}, {2, 0, 2}, {3, 0, 2}, {-3, 1, 2}, {-2, 1, 2}, {-1, 1, 2}, {0, 1, 2},
+    {1, 1, 2}, {2, 1, 2}, {3, 1, 2}, {-2, 2, 2}, {-1, 2, 2}, {0, 2, 2}, {1, 2, 2}, {2, 2, 2}, {-1, 3, 2}, {0, 3, 2},
+    {1, 3, 2}, {-1, -2, 3}, {0, -2, 3}, {1, -2, 3}, {-2, -1, 3}, {-1, -1, 3}, {0, -1, 3}, {1, -1, 3}, {2, -1, 3},
+    {-2, 0, 3}, {-1, 0, 3}, {0, 0, 3}, {1, 0, 3}, {2, 0, 3}, {-2, 1, 3}, {-1, 1, 3}, {0, 1, 3}, {1, 1, 3}, {2, 1, 3},
+    {-1, 2, 3}, {0, 2, 3}, {1, 2, 3}, {0, 0, 4}
+};
+
+// 256 direction bits (the radius-4 ball), with the operations the kernels apply to an integer mask: a bit test
+// (m >> d) & 1, a single-bit set m |= Mask256(1) << d, and a test for no bit.
+struct Mask256 {
+    uint64_t w[4];
+    Mask256() = default;
+    __host__ __device__ constexpr Mask256(unsigned long long v) : w{v, 0, 0, 0} {}
+    struct Bit {
+        const Mask256 &m;
+        int d;
+        __device__ __forceinline__ uint32_t operator&(uint32_t v) const { return uint32_t(m.w[d >> 6] >> (d & 63)) & v; }
+    };
+    __device__ __forceinline__ Bit operator>>(int d) const { return Bit{*this, d}; }
+    __device__ __forceinline__ Mask256 operator<<(int d) const {
+        // only the one-bit mask is ever shifted
+        Mask256 r(0ull);
+        if (w[0] & 1ull) r.w[d >> 6] = 1ull << (d & 63);
+        return r;
+    }
+    __device__ __forceinline__ Mask256 &operator|=(const Mask256 &o) {
+        w[0] |= o.w[0]; w[1] |= o.w[1]; w[2] |= o.w[2]; w[3] |= o.w[3];
+        return *this;
+    }
+    __device__ __forceinline__ bool operator!() const { return (w[0] | w[1] | w[2] | w[3]) == 0; }
+};
+
 // One bit per full-stencil direction.
 template <int CONN>
 using DirMask = typename std::conditional<
     (2 * Sten<CONN>::H <= 32), uint32_t,
-    typename std::conditional<(2 * Sten<CONN>::H <= 64), uint64_t, unsigned __int128>::type>::type;
+    typename std::conditional<(2 * Sten<CONN>::H <= 64), uint64_t,
+                              typename std::conditional<(2 * Sten<CONN>::H <= 128), unsigned __int128,
+                                                        Mask256>::type>::type>::type;
 // The per-node copy of that mask in LDS (see dir_mask_bytes).
 template <int CONN>
 using LdsMask = typename std::conditional<(2 * Sten<CONN>::H <= 8), uint8_t, DirMask<CONN>>::type;
@@ -109,6 +165,7 @@ __device__ __forceinline__ int3 half_off(int o) {
         return make_int3(q % (2 * R + 1) - R, 1 + q / (2 * R + 1), 0);
     }
     if (CONN == 122) return make_int3(kBall3[o][0], kBall3[o][1], kBall3[o][2]);
+    if (CONN == 256) return make_int3(kBall4[o][0], kBall4[o][1], kBall4[o][2]);
     if (CONN == 32) {
         // offsets of length at most 2 whose first nonzero coordinate, from z down to x, is positive; ordered by
         // z, then y, then x
@@ -212,7 +269,7 @@ __device__ __forceinline__ void axis_cov(const Axis &a, int x, AxCov c[2 * R + 1
     // start of block t_hi - 1, (t_hi - 1) s, follows from one product.
     const int tm = tr < a.nb - 1 ? tr : a.nb - 1;
     const int pm = (tm - 1) * a.s;
-#pragma unroll
+DOPE_UNROLL
     for (int t = 0; t <= 2 * R; ++t) {
         const int xx = x + t - R, d = rem + t - R;
         const bool dn = d < 0 && tr <= a.nb - 1, up = d >= a.s && tr < a.nb - 1;
@@ -234,7 +291,7 @@ struct BoxCov {
         if (Sten<CONN>::NDIM == 3) {
             axis_cov<R>(g.ax[2], gz, z);
         } else {
-#pragma unroll
+DOPE_UNROLL
             for (int t = 0; t <= 2 * R; ++t) z[t] = AxCov{0, t == R ? 1 : 0};
         }
     }
@@ -331,14 +388,14 @@ template <int CONN>
 __device__ __forceinline__ DirMask<CONN> inside_mask(int x, int y, int z, int X, int Y, int Z) {
     constexpr int R = Sten<CONN>::R;
     bool okx[2 * R + 1], oky[2 * R + 1], okz[2 * R + 1];
-#pragma unroll
+DOPE_UNROLL
     for (int t = -R; t <= R; ++t) {
         okx[t + R] = t < 0 ? x >= -t : (t > 0 ? x < X - t : true);
         oky[t + R] = t < 0 ? y >= -t : (t > 0 ? y < Y - t : true);
         okz[t + R] = t < 0 ? z >= -t : (t > 0 ? z < Z - t : true);
     }
     DirMask<CONN> m = 0;
-#pragma unroll
+DOPE_UNROLL
     for (int d = 0; d < 2 * Sten<CONN>::H; ++d) {
         const int3 v = full_dir<CONN>(d);
         const bool ok = okx[v.x + R] && oky[v.y + R] && okz[v.z + R];
@@ -372,7 +429,7 @@ __device__ __forceinline__ void unary_loads(const Geom &g, const GLOBAL int32_t 
     ld.u = ld_at(u, bi);
     ld.Y = ld_at(Y, bi);
     ld.a = ld_at(A, ci << 2);
-#pragma unroll
+DOPE_UNROLL
     for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
         const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
@@ -417,7 +474,7 @@ __device__ __forceinline__ void block_lq_rows(const Geom &g, int x0, int y0, int
         if (a < Sten<CONN>::NDIM) {
             AxCov c[2 * R + 1];
             axis_cov<R>(g.ax[a], (a == 0 ? x0 : (a == 1 ? y0 : z0)) + l, c);
-#pragma unroll
+DOPE_UNROLL
             for (int t = 0; t <= 2 * R; ++t) bits |= uint32_t(c[t].cnt >= 2 ? 1 : 0) << t;
         }
         rows[a][l] = uint16_t(bits);
@@ -441,7 +498,7 @@ __device__ __forceinline__ int64_t unary_from_cov(const Cov &bc, const PixLoads<
     int64_t G = 0;
     int32_t sc = 0;   // sum of |c| < 2^29 (checked at upload)
     mask = 0;
-#pragma unroll
+DOPE_UNROLL
     for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
         const int32_t c = ((ld.ing >> d) & 1u) ? ld.cv[d] : 0;
@@ -521,7 +578,7 @@ struct WaveSync {
     __device__ __forceinline__ int bits(int f) {
         sync();
         int r = f;
-#pragma unroll
+DOPE_UNROLL
         for (int s = 32; s >= 1; s >>= 1) r |= __shfl_xor(r, s);
         return r;
     }
@@ -590,7 +647,7 @@ __device__ __forceinline__ bool eliminate(Sync &sy, BlockLds<CONN> &L, int nfree
                 if (L.st[p] & ST_FIXED) continue;
                 const DirMask<CONN> m = L.msk[p];
                 int32_t U = L.dd[p], S = 0;
-#pragma unroll
+DOPE_UNROLL
                 for (int d = 0; d < ND; ++d)
                     if ((m >> d) & 1u) {
                         const uint8_t sv = L.st[L.nbr(p, d)];
@@ -647,7 +704,7 @@ __device__ __forceinline__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nf
         const DirMask<CONN> m = L.msk[p];
         DirMask<CONN> live = 0;
         int32_t U = L.dd[p];
-#pragma unroll
+DOPE_UNROLL
         for (int d = 0; d < ND; ++d)
             if ((m >> d) & 1u) {
                 const uint8_t sv = L.st[L.nbr(p, d)];
@@ -674,7 +731,7 @@ __device__ __forceinline__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nf
                 const int h = L.hh[p];
                 if (!m || h == 1) continue;
                 int best = h;
-#pragma unroll
+DOPE_UNROLL
                 for (int d = 0; d < ND; ++d)
                     if (((m >> d) & 1u) && L.res(p, d) > 0) {
                         const int hv = L.hh[L.nbr(p, d)] + 1;
@@ -702,7 +759,7 @@ __device__ __forceinline__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nf
                 if (e <= 0 || h >= H_INF) continue;
                 const DirMask<CONN> m = L.msk[p];
                 int32_t rem = e;
-#pragma unroll
+DOPE_UNROLL
                 for (int d = 0; d < ND; ++d) {
                     if (!((m >> d) & 1u) || rem == 0) continue;
                     const int v = L.nbr(p, d);
@@ -726,7 +783,7 @@ __device__ __forceinline__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nf
                 const DirMask<CONN> m = L.msk[p];
                 int best = 1 << 30;
                 bool adm = false;
-#pragma unroll
+DOPE_UNROLL
                 for (int d = 0; d < ND; ++d) {
                     if (!((m >> d) & 1u) || adm) continue;
                     if (L.res(p, d) <= 0) continue;
@@ -752,7 +809,7 @@ __device__ __forceinline__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nf
             const int p = L.lst[i];
             if (L.st[p] & (ST_FIXED | ST_MARK)) continue;
             const DirMask<CONN> m = L.msk[p];
-#pragma unroll
+DOPE_UNROLL
             for (int d = 0; d < ND; ++d)
                 if (((m >> d) & 1u) && (L.st[L.nbr(p, d)] & ST_MARK) && L.res_in(p, d) > 0) {
                     L.st[p] |= ST_MARK;
@@ -803,7 +860,7 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         L.msk = reinterpret_cast<LdsMask<CONN> *>(smem + ((mo + MB - 1) & ~(MB - 1)));
     }
     L.st = reinterpret_cast<uint8_t *>(L.msk + npmax);
-#pragma unroll
+DOPE_UNROLL
     for (int o = 0; o < H; ++o) {
         const int3 v = half_off<CONN>(o);
         L.loff[o] = v.x + ex * (v.y + ey * v.z);
@@ -834,7 +891,7 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
         } else {
             Ut = unary_from<CONN>(g, ld, M, x0 + l.x, y0 + l.y, z0 + l.z, l.x, l.y, l.z, ex, ey, ez, cp, m, sumc);
         }
-#pragma unroll
+DOPE_UNROLL
         for (int o = 0; o < H; ++o) {
             L.cap[o * npmax + p] = cp[o];
             L.flw[o * npmax + p] = 0;
@@ -1020,7 +1077,7 @@ __device__ __forceinline__ int64_t lsa_lambda(int level) {
 }
 
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
-#pragma unroll
+DOPE_UNROLL
     for (int s = 32; s >= 1; s >>= 1) x += __shfl_xor(x, s);
     return x;
 }
@@ -1069,7 +1126,7 @@ __device__ __forceinline__ void block_lsatr(const Img &im, int k, unsigned char 
     int32_t *u0 = csg + H * npmax;                                        // Eq. (8) unary clamped to int32
     LdsMask<CONN> *allm = reinterpret_cast<LdsMask<CONN> *>(u0 + npmax);  // in-block directions with c != 0
     uint8_t *xt = reinterpret_cast<uint8_t *>(allm + npmax);              // current labelling x~
-#pragma unroll
+DOPE_UNROLL
     for (int o = 0; o < H; ++o) {
         const int3 v = half_off<CONN>(o);
         L.loff[o] = v.x + ex * (v.y + ey * v.z);
@@ -1087,7 +1144,7 @@ __device__ __forceinline__ void block_lsatr(const Img &im, int k, unsigned char 
         int64_t sumc;
         const int64_t Ut = unary_from<CONN>(g, ld, M, x0 + l.x, y0 + l.y, z0 + l.z, l.x, l.y, l.z, ex, ey, ez, cp, m,
                                             sumc);
-#pragma unroll
+DOPE_UNROLL
         for (int o = 0; o < H; ++o) csg[o * npmax + p] = cp[o];
         allm[p] = LdsMask<CONN>(m);
         u0[p] = int32_t(Ut > INT32_MAX ? int64_t(INT32_MAX) : (Ut < -int64_t(INT32_MAX) ? -int64_t(INT32_MAX) : Ut));
@@ -1109,7 +1166,7 @@ __device__ __forceinline__ void block_lsatr(const Img &im, int k, unsigned char 
             int64_t U1 = u0[p];
             int32_t splus = 0;
             DirMask<CONN> live = 0;
-#pragma unroll
+DOPE_UNROLL
             for (int d = 0; d < ND; ++d)
                 if ((am >> d) & 1u) {
                     const int32_t c = d < H ? csg[d * npmax + p] : csg[(d - H) * npmax + p - L.loff[d - H]];
@@ -1121,7 +1178,7 @@ __device__ __forceinline__ void block_lsatr(const Img &im, int k, unsigned char 
                     }
                 }
             const int64_t U2 = U1 + lam * (1 - 2 * int(xt[p]));
-#pragma unroll
+DOPE_UNROLL
             for (int o = 0; o < H; ++o) {
                 const int32_t c = csg[o * npmax + p];
                 L.cap[o * npmax + p] = c > 0 ? c : 0;
@@ -1172,7 +1229,7 @@ __device__ __forceinline__ void block_lsatr(const Img &im, int k, unsigned char 
             if (xo != xn) {
                 chg = 1;
                 int64_t U1 = u0[p];
-#pragma unroll
+DOPE_UNROLL
                 for (int d = 0; d < ND; ++d)
                     if ((am >> d) & 1u) {
                         const int32_t c = d < H ? csg[d * npmax + p] : csg[(d - H) * npmax + p - L.loff[d - H]];
@@ -1181,7 +1238,7 @@ __device__ __forceinline__ void block_lsatr(const Img &im, int k, unsigned char 
                 eR += int64_t(u0[p]) * (xo - xn);
                 eP += U1 * (xo - xn);
             }
-#pragma unroll
+DOPE_UNROLL
             for (int o = 0; o < H; ++o)
                 if ((am >> o) & 1u) {
                     const int q = p + L.loff[o];
@@ -1318,7 +1375,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
             if (Ut < -sumc - 1) Ut = -sumc - 1;
             s_U[wave][p] = int32_t(Ut);
             s_m[wave][p] = m;
-#pragma unroll
+DOPE_UNROLL
             for (int d = 0; d < ND; ++d) {
                 const int3 v = full_dir<CONN>(d);
                 // an absent neighbour points at the pixel itself with capacity 0, so the enumeration can use
@@ -1334,7 +1391,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
     if (live && lane < np) {
         const int p = lane;
         const DirMask<CONN> m = s_m[wave][p];
-#pragma unroll
+DOPE_UNROLL
         for (int d = H; d < ND; ++d)
             if ((m >> d) & 1u) s_nc[wave][p][d] = s_nc[wave][s_nj[wave][p][d]][d - H];
     }
@@ -1351,7 +1408,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
         for (int p = 0; p < np; ++p) {
             const int xp = (x >> p) & 1;
             if (xp) E += s_U[wave][p];
-#pragma unroll
+DOPE_UNROLL
             for (int d = 0; d < H; ++d) {
                 const int32_t c = s_nc[wave][p][d];
                 if (c != 0) {
@@ -1368,7 +1425,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
         // + 1 after the clamp above, sum |c| < 2^29); the key changes by +-(t 2^16 + 2^b)
         auto flip = [&](int b, int32_t sb, const int32_t *cb, const int *jb) {
             int32_t acc = 0;
-#pragma unroll
+DOPE_UNROLL
             for (int d = 0; d < ND; ++d) acc += cb[d] & -int32_t((x >> jb[d]) & 1u);
             const int64_t dk = int64_t(sb - 2 * acc) * 65536 + (int64_t(1) << b);
             key += ((x >> b) & 1u) ? -dk : dk;
@@ -1379,7 +1436,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
             int32_t cb[ND];
             int jb[ND];
             int32_t sb = s_U[wave][b];
-#pragma unroll
+DOPE_UNROLL
             for (int d = 0; d < ND; ++d) {
                 cb[d] = s_nc[wave][b][d];
                 jb[d] = s_nj[wave][b][d];
@@ -1393,10 +1450,10 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
             // then ctz >= 4): their data stays in registers, so one step in sixteen reads the block's LDS tables
             int32_t sr[RB], cr[RB][ND];
             int jr[RB][ND];
-#pragma unroll
+DOPE_UNROLL
             for (int b = 0; b < RB; ++b) {
                 sr[b] = s_U[wave][b];
-#pragma unroll
+DOPE_UNROLL
                 for (int d = 0; d < ND; ++d) {
                     cr[b][d] = s_nc[wave][b][d];
                     jr[b][d] = s_nj[wave][b][d];
@@ -1404,7 +1461,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
                 }
             }
             for (uint32_t gb = 0; gb < cnt; gb += 16) {
-#pragma unroll
+DOPE_UNROLL
                 for (int i = 1; i < 16; ++i) {
                     const int b = __builtin_ctz(i);
                     flip(b, sr[b], cr[b], jr[b]);
@@ -1415,7 +1472,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
             for (uint32_t gi = 1; gi < cnt; ++gi) flip_lds(__builtin_ctz(gi));
         }
     }
-#pragma unroll
+DOPE_UNROLL
     for (int s = 32; s >= 1; s >>= 1) {
         const int64_t o = __shfl_xor(best, s);
         best = o < best ? o : best;
@@ -1444,7 +1501,7 @@ __global__ __launch_bounds__(256) void k_block_exhaustive(const Img *__restrict_
             r2 = (unsigned long long)(rr * rr);
         }
     }
-#pragma unroll
+DOPE_UNROLL
     for (int sft = 32; sft >= 1; sft >>= 1) r2 += __shfl_xor(r2, sft);
     if (lane == 0) {
         gp(im.resid)[k] = int64_t(r2);
@@ -1490,7 +1547,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     const double invM = 1.0 / double(M);
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
     const int kfirst = gp(im.chunk_k0)[chunk];
-#pragma unroll
+DOPE_UNROLL
     for (int q = 0; q < MAXC; ++q) s_res[q * CONS_NT + tid] = 0;
     if (tid == 0) s_ovf = 0;
     __syncthreads();
@@ -1498,7 +1555,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     int ovf = 0;
     int kk = kfirst;
     unsigned long long r2[MAXC];
-#pragma unroll
+DOPE_UNROLL
     for (int q = 0; q < MAXC; ++q) r2[q] = 0;
     if (li < im.n_blist) {
         // the owner copy and its block; the coordinates follow from the closed-form block layout
@@ -1543,7 +1600,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         int32_t a_own[MAXC];
         uint32_t cc_own[MAXC];
         bool v_own[MAXC];
-#pragma unroll
+DOPE_UNROLL
         for (int q = 0; q < MAXC; ++q) {
             const int e = q & 1, b = (q >> 1) & 1, a = q >> 2;
             v_own[q] = e < mx.cnt && b < my.cnt && a < mz.cnt;
@@ -1556,7 +1613,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         bool ing[ND];
         SlotWord wj[ND];
         const DirMask<CONN> ingm = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
-#pragma unroll
+DOPE_UNROLL
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
             ing[d] = (ingm >> d) & 1u;
@@ -1583,12 +1640,12 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
                 "+v"(wj[4]), "+v"(wj[5]));
         }
         int yv_own[MAXC];
-#pragma unroll
+DOPE_UNROLL
         for (int q = 0; q < MAXC; ++q) {
             yv_own[q] = v_own[q] ? int((wm >> (8 * q)) & 1u) : 0;
             if (!v_own[q]) a_own[q] = 0;
         }
-#pragma unroll
+DOPE_UNROLL
         for (int d = 0; d < ND; ++d)
             if (!ing[d]) cwv[d] = 0;
         // ---- S_m and Hc_m.  With Y1 = sum of this pixel's labels, Hc regroups exactly as
@@ -1596,7 +1653,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         //           - sum_j c_mj sum_{blocks b holding m and j} (yhat_b,m - yhat_b,j) ----
         int64_t S = 0;
         int Y1 = 0;
-#pragma unroll
+DOPE_UNROLL
         for (int q = 0; q < MAXC; ++q) {
             S += int64_t(yv_own[q]) * Y_ONE + a_own[q];
             Y1 += yv_own[q];
@@ -1619,14 +1676,14 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         // slots e of m's axis interval whose block also holds the neighbour (top differs by dt, neighbour count cn)
         auto shared_set = [](int cm, int dt, int cn) -> int {
             int set = 0;
-#pragma unroll
+DOPE_UNROLL
             for (int e = 0; e < 2; ++e)
                 if (e < cm && e + dt >= 0 && e + dt < cn) set |= 1 << e;
             return set;
         };
         // Hc = sum_j c_mj (Y1 q_j - q_m (labels of j) - shared_j): the bracket is a small integer (|.| <= 128)
         int64_t HC = 0;
-#pragma unroll
+DOPE_UNROLL
         for (int d = 0; d < ND; ++d) {
             const int3 v = full_dir<CONN>(d);
             const AxCov &ax = bc.cx(v.x), &ay = bc.cy(v.y), &az = bc.cz(v.z);
@@ -1653,7 +1710,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
         if (!skip) st_at(Y, uint32_t(m) << 2, int32_t(Yc));
         // multipliers (Eq. 11) and residual terms of every copy
-#pragma unroll
+DOPE_UNROLL
         for (int q = 0; q < MAXC; ++q) {
             if (!v_own[q]) continue;
             const int64_t An = int64_t(a_own[q]) + int64_t(yv_own[q]) * Y_ONE - Yn;
@@ -1674,18 +1731,18 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
         const int lane = tid & 63, wv = tid >> 6;
         if (same) {
             constexpr int G = 64 / MAXC;
-#pragma unroll
+DOPE_UNROLL
             for (int q = 0; q < MAXC; ++q) s_tr[wv][q][lane] = r2[q];
             __builtin_amdgcn_wave_barrier();
             const int q = lane / G, part = lane % G;
             unsigned long long v = 0;
-#pragma unroll
+DOPE_UNROLL
             for (int i = 0; i < MAXC; ++i) v += s_tr[wv][q][part * MAXC + i];
-#pragma unroll
+DOPE_UNROLL
             for (int sft = G / 2; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft);
             if (part == 0 && v) atomicAdd(&s_res[(k0 - kfirst) * MAXC + q], v);
         } else {
-#pragma unroll
+DOPE_UNROLL
             for (int q = 0; q < MAXC; ++q)
                 if (r2[q]) atomicAdd(&s_res[(kk - kfirst) * MAXC + q], r2[q]);
         }
@@ -1732,7 +1789,7 @@ __device__ __forceinline__ void mirror_ctl(const GLOBAL Ctl *ctl, Ctl *mirror, i
                   "the loop control is copied in 8-byte words, the readback number last");
     const GLOBAL unsigned long long *src = reinterpret_cast<const GLOBAL unsigned long long *>(ctl);
     unsigned long long *dst = reinterpret_cast<unsigned long long *>(mirror);
-#pragma unroll
+DOPE_UNROLL
     for (int i = 0; i < int(sizeof(Ctl) / 8) - 1; ++i) dst[i] = src[i];
     // release at system scope: the words above reach host memory first (written back from the L2 if the mirror
     // is cached there), then this store, which goes through at system scope
@@ -1787,7 +1844,7 @@ __device__ __forceinline__ void finalize_image(const Img &im, Ctl *mirror = null
         }
         return;
     }
-#pragma unroll
+DOPE_UNROLL
     for (int sft = 32; sft >= 1; sft >>= 1) {
         const unsigned long long o = __shfl_xor(mx, sft);
         mx = o > mx ? o : mx;
@@ -1869,7 +1926,7 @@ __device__ __forceinline__ int setup_pixel(const Geom &g, int gx, int gy, int gz
     const GLOBAL int32_t *wg = gp(w_src);
     int32_t ui = ld_at(gp(u_src), bi);
     int32_t wl[ND];
-#pragma unroll
+DOPE_UNROLL
     for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
         const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
@@ -1879,7 +1936,7 @@ __device__ __forceinline__ int setup_pixel(const Geom &g, int gx, int gy, int gz
     }
     int flags = 0;
     int64_t sum = 0;
-#pragma unroll
+DOPE_UNROLL
     for (int d = 0; d < ND; ++d) {
         const int3 v = full_dir<CONN>(d);
         const bool on = (ing >> d) & 1u;
@@ -2107,7 +2164,7 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int32_t *__restric
             BoxCov<CONN> bc;
             bc.init(g, gx, gy, gz);
             const int lqi = bc.lq(make_int3(0, 0, 0));
-#pragma unroll
+DOPE_UNROLL
             for (int o = 0; o < H; ++o) {
                 const int3 v = half_off<CONN>(o);
                 if (!in_grid(g, gx + v.x, gy + v.y, gz + v.z)) continue;
@@ -2119,7 +2176,7 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int32_t *__restric
             }
         }
     }
-#pragma unroll
+DOPE_UNROLL
     for (int sft = 32; sft >= 1; sft >>= 1) e += __shfl_xor(e, sft);
     if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = e;
     __syncthreads();
@@ -2130,7 +2187,7 @@ __global__ __launch_bounds__(256) void k_energy_sum(const int64_t *__restrict__ 
     __shared__ long long s_sum[4];
     long long e = 0;
     for (int i = threadIdx.x; i < n; i += 256) e += part[i];
-#pragma unroll
+DOPE_UNROLL
     for (int sft = 32; sft >= 1; sft >>= 1) e += __shfl_xor(e, sft);
     if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = e;
     __syncthreads();
@@ -2335,6 +2392,7 @@ DOPE_CONN_ENTRIES(extern, 80)
 DOPE_CONN_ENTRIES(extern, 6)
 DOPE_CONN_ENTRIES(extern, 32)
 DOPE_CONN_ENTRIES(extern, 122)
+DOPE_CONN_ENTRIES(extern, 256)
 
 // Run-time dispatch on the stencil; f is called as f(std::integral_constant<int, CONN>()).
 template <class F>
@@ -2348,6 +2406,7 @@ hipError_t by_conn(int32_t conn, F &&f) {
         case 6: return f(std::integral_constant<int, 6>());
         case 32: return f(std::integral_constant<int, 32>());
         case 122: return f(std::integral_constant<int, 122>());
+        case 256: return f(std::integral_constant<int, 256>());
         default: return hipErrorInvalidValue;
     }
 }
@@ -2372,7 +2431,7 @@ __global__ __launch_bounds__(256) void k_build_blist(Geom g, const int32_t *__re
     const int32_t *r = btab + int64_t(BTAB_STRIDE) * k;
     const int t[3] = {k % g.ax[0].nb, (k / g.ax[0].nb) % g.ax[1].nb, k / (g.ax[0].nb * g.ax[1].nb)};
     int ol[3], lo[3], hi[3];
-#pragma unroll
+DOPE_UNROLL
     for (int a = 0; a < 3; ++a) {
         const Axis &ax = g.ax[a];
         const int start = t[a] * ax.s;

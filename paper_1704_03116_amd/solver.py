@@ -23,7 +23,7 @@ def make_params(dims, connectivity, block, overlap, mu0, *, ndim=None, mu_fact=(
                 max_iter=50, solver="auto"):
     p = N.dope_params()
     dims = tuple(int(d) for d in dims) + (1,) * (3 - len(dims))
-    p.ndim = ndim if ndim is not None else (3 if connectivity in (6, 32, 122) else 2)
+    p.ndim = ndim if ndim is not None else (3 if connectivity in (6, 32, 122, 256) else 2)
     p.dims[:] = dims
     p.connectivity = int(connectivity)
     p.block[:] = tuple(int(b) for b in block) + (1,) * (3 - len(block))

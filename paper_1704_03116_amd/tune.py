@@ -23,8 +23,8 @@ ROOT = os.path.dirname(HERE)
 sys.path.insert(0, ROOT)
 
 LDS_LIMIT = 163840 - 1024   # the max-flow kernels keep 1 KiB of the 160 KiB for static arrays
-HALF = {4: 2, 8: 4, 24: 12, 48: 24, 80: 40, 6: 3, 32: 16, 122: 61}
-RADIUS = {4: 1, 8: 1, 24: 2, 48: 3, 80: 4, 6: 1, 32: 2, 122: 3}
+HALF = {4: 2, 8: 4, 24: 12, 48: 24, 80: 40, 6: 3, 32: 16, 122: 61, 256: 128}
+RADIUS = {4: 1, 8: 1, 24: 2, 48: 3, 80: 4, 6: 1, 32: 2, 122: 3, 256: 4}
 
 # stencil -> (image sizes: shorter side of a square image or cube edge, candidate (B, o))
 SWEEP_2D = {

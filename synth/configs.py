@@ -43,8 +43,8 @@ def half_stencil(ndim: int, conn: int) -> List[Tuple[int, int, int]]:
         return out
     if ndim == 3 and conn == 6:
         return [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
-    if ndim == 3 and conn in (32, 122):   # balls of radius 2 / 3; first nonzero coordinate (z, y, x) positive
-        r = 2 if conn == 32 else 3
+    if ndim == 3 and conn in (32, 122, 256):   # balls of radius 2 / 3 / 4; first nonzero coordinate (z, y, x) positive
+        r = {32: 2, 122: 3, 256: 4}[conn]
         out = []
         for dz in range(0, r + 1):
             for dy in range(-r, r + 1):
@@ -334,13 +334,13 @@ def config_kernel(k: int, seed: int = 0, W: int = 512, H: int = 512, mu0: int = 
 
 
 def config3_kernel5(seed: int = 0, dims=(128, 128, 64), mu0: int = BALL_MU0, k: int = 5) -> Problem:
-    """The volume of config3 with the spherical kernel of size k: the radius-2 ball (k = 5, 32 neighbours) or the
-    radius-3 ball (k = 7, 122 neighbours), distance-weighted Potts w = round(1000 / |offset|), lambda = 0.4 or
-    0.16 (total smoothing per voxel near config3's 1.5 x 6 x 1000); 8^3 or 6^3 blocks with o = 1 (141 or 513 LDS
-    bytes per block node)."""
-    if k not in (5, 7):
-        raise ValueError("k must be 5 or 7")
-    conn = 32 if k == 5 else 122
+    """The volume of config3 with the spherical kernel of size k: the radius-2 ball (k = 5, 32 neighbours), the
+    radius-3 ball (k = 7, 122 neighbours) or the radius-4 ball (k = 9, 256 neighbours), distance-weighted Potts
+    w = round(1000 / |offset|), lambda = 0.4, 0.16 or 25/256 (total smoothing per voxel near config3's
+    1.5 x 6 x 1000); 8^3, 6^3 or 5^3 blocks with o = 1 (141, 513 or 1065 LDS bytes per block node)."""
+    if k not in (5, 7, 9):
+        raise ValueError("k must be 5, 7 or 9")
+    conn = {5: 32, 7: 122, 9: 256}[k]
     base = config3(seed=seed, dims=dims, mu0=mu0)
     W, H, D = dims
     zz, yy, xx = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
@@ -350,9 +350,10 @@ def config3_kernel5(seed: int = 0, dims=(128, 128, 64), mu0: int = BALL_MU0, k: 
         ok = ((xx + dx >= 0) & (xx + dx < W) & (yy + dy >= 0) & (yy + dy < H)
               & (zz + dz >= 0) & (zz + dz < D))
         w[o] = np.where(ok.reshape(-1), int(_round(1000.0 / math.sqrt(dx * dx + dy * dy + dz * dz))), 0)
-    B = 8 if k == 5 else 6
+    B = {5: 8, 7: 6, 9: 5}[k]
+    lam_q = {5: lambda_q8(0.4), 7: lambda_q8(0.16), 9: 25}[k]
     return Problem(f"kernel{k}_spheres{W}x{H}x{D}_{conn}conn", (W, H, D), 3, conn, base.u, w,
-                   lambda_q8(0.4 if k == 5 else 0.16), (B, B, B), (1, 1, 1), mu0, truth=base.truth)
+                   lam_q, (B, B, B), (1, 1, 1), mu0, truth=base.truth)
 
 
 def random_problem(seed: int, dims, conn: int, block, overlap, lam_q8: int = 256,
@@ -361,7 +362,7 @@ def random_problem(seed: int, dims, conn: int, block, overlap, lam_q8: int = 256
     """Uniform random integer unaries and weights (a fraction neg_frac of edges negated) on any grid."""
     rng = np.random.default_rng(seed)
     W, H, D = dims
-    ndim = 3 if conn in (6, 32, 122) else 2
+    ndim = 3 if conn in (6, 32, 122, 256) else 2
     n = W * H * D
     u = rng.integers(u_range[0], u_range[1] + 1, size=n).astype(np.int32)
     offs = half_stencil(ndim, conn)

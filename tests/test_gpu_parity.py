@@ -327,6 +327,8 @@ WIDE_CASES = [
     ((41, 35, 1), 80, (12, 12, 1), (2, 2, 0), 100, 1000),   # 9x9 neighbourhood
     ((29, 23, 1), 80, (6, 6, 1), (2, 2, 0), 80, 800),       # 9x9, stride 4 = radius
     ((14, 12, 10), 122, (6, 6, 5), (1, 1, 1), 40, 4000),    # 3D ball of radius 3
+    ((13, 11, 10), 256, (5, 5, 5), (1, 1, 1), 20, 4000),    # 3D ball of radius 4, stride 4 = radius
+    ((9, 9, 9), 256, (0, 0, 0), (0, 0, 0), 20, 4000),       # radius 4, one block: global cut
 ]
 
 
@@ -357,9 +359,9 @@ def test_wide_exhaustive_nonsubmodular():
     d.close()
 
 
-@pytest.mark.parametrize("k,dims", [(5, (40, 36, 20)), (7, (30, 26, 14))])
+@pytest.mark.parametrize("k,dims", [(5, (40, 36, 20)), (7, (30, 26, 14)), (9, (24, 21, 13))])
 def test_ball_kernel_volume_small_every_iteration(k, dims):
-    """The spherical kernels of size 5 and 7 on small versions of the config3 volume."""
+    """The spherical kernels of size 5, 7 and 9 on small versions of the config3 volume."""
     p = synth.config3_kernel5(dims=dims, k=k)
     d, st_o, dec = run_parity(p, 5, f"ball kernel {k} {dims}")
     assert np.array_equal(d.labels(), od.labels(st_o.Y))

@@ -67,6 +67,7 @@ TINY = [
     ((5, 4, 4), 32, (3, 3, 3), (1, 1, 1)),     # 3D ball of radius 2, stride 2 = radius
     ((9, 8, 1), 80, (6, 6, 1), (2, 2, 0)),     # 9x9 neighbourhood, stride 4 = radius 4
     ((6, 5, 5), 122, (4, 4, 4), (1, 1, 1)),    # 3D ball of radius 3, stride 3 = radius
+    ((7, 6, 6), 256, (5, 5, 5), (1, 1, 1)),    # 3D ball of radius 4, stride 4 = radius
 ]
 
 
@@ -81,9 +82,9 @@ def test_square_neighbourhood_offsets(conn, r):
     assert sorted(full) == sorted(square)
 
 
-@pytest.mark.parametrize("conn,r,count", [(32, 2, 32), (122, 3, 122)])
+@pytest.mark.parametrize("conn,r,count", [(32, 2, 32), (122, 3, 122), (256, 4, 256)])
 def test_ball_neighbourhood_offsets(conn, r, count):
-    """The spherical kernels of size 5 and 7 in 3D: the half-stencil and its negation partition the lattice
+    """The spherical kernels of size 5, 7 and 9 in 3D: the half-stencil and its negation partition the lattice
     points of the radius-r ball without its centre."""
     half = dope.neighbour_offsets(3, conn)
     full = half + [(-dx, -dy, -dz) for dx, dy, dz in half]
@@ -386,7 +387,8 @@ def test_global_mincut_vs_bruteforce(seed):
 # --------------------------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("conn,dims", [(4, (7, 6, 1)), (8, (6, 6, 1)), (6, (4, 3, 3)), (24, (6, 5, 1)),
-                                       (48, (6, 6, 1)), (32, (4, 4, 3)), (80, (6, 5, 1)), (122, (4, 4, 4))])
+                                       (48, (6, 6, 1)), (32, (4, 4, 3)), (80, (6, 5, 1)), (122, (4, 4, 4)),
+                                       (256, (4, 4, 4))])
 def test_single_block_is_global_cut(conn, dims):
     """K = 1: C = R = 0, so iteration 1 solves Eq. (3) exactly; y = y^ and the residual is 0 (stop at t = 1)."""
     p = tiny_problem(30, dims, conn, (0, 0, 0), (0, 0, 0))
