@@ -674,6 +674,82 @@ DOPE_UNROLL
     }
 }
 
+// The same elimination with each thread's list entries (at most MAXPT of them), their unaries and their live
+// capacities held in registers across sweeps: a sweep then reads only the state bytes of the neighbours, instead
+// of the node's own state, mask, unary and capacities as well.  Nodes are fixed only by the thread that holds
+// them, so a node a thread has fixed is simply dropped from its registers.
+template <int CONN, class Sync, int MAXPT>
+__device__ __forceinline__ bool eliminate_cached(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs) {
+    constexpr int ND = 2 * Sten<CONN>::H;
+    int pn[MAXPT];
+    int32_t ub[MAXPT];
+    int32_t cb[MAXPT][ND];
+DOPE_UNROLL
+    for (int j = 0; j < MAXPT; ++j) {
+        const int i = sy.idx + j * sy.step;
+        pn[j] = -1;
+        ub[j] = 0;
+DOPE_UNROLL
+        for (int d = 0; d < ND; ++d) cb[j][d] = 0;
+        if (i < nfree) {
+            const int p = L.lst[i];
+            if (!(L.st[p] & ST_FIXED)) {
+                const DirMask<CONN> m = L.msk[p];
+                pn[j] = p;
+                ub[j] = L.dd[p];
+DOPE_UNROLL
+                for (int d = 0; d < ND; ++d) cb[j][d] = ((m >> d) & 1u) ? L.capd(p, d) : 0;
+            }
+        }
+    }
+    for (;;) {
+        int ch = 0;
+        for (;;) {
+            int wch = 0;
+DOPE_UNROLL
+            for (int j = 0; j < MAXPT; ++j) {
+                const int p = pn[j];
+                if (p < 0) continue;
+                uint8_t sv[ND];
+DOPE_UNROLL
+                for (int d = 0; d < ND; ++d) sv[d] = L.st[cb[j][d] ? L.nbr(p, d) : p];   // dead directions read p
+                int32_t U = ub[j], S = 0;
+DOPE_UNROLL
+                for (int d = 0; d < ND; ++d) {
+                    const int32_t c = cb[j][d];
+                    if (sv[d] & ST_FIXED) U += (sv[d] & ST_LABEL) ? -c : c;   // c = 0 for dead directions
+                    else S += c;
+                }
+                if (U < -S) { L.st[p] = ST_FIXED | ST_LABEL; pn[j] = -1; wch |= 1; }
+                else if (U > S) { L.st[p] = ST_FIXED; pn[j] = -1; wch |= 1; }
+                else wch |= 2;
+            }
+            if (!__any(wch & 1)) {
+                ch |= wch;
+                break;
+            }
+            ch |= wch & 1;
+        }
+        ++fs.casc;
+        const int r = sy.bits(ch);
+        if (!(r & 1)) return (r & 2) != 0;
+    }
+}
+
+// Elimination, with the register-held variant when every thread has at most MAXPT list entries and the stencil
+// has at most eight directions.  MAXPT is fixed per kernel (registers are allocated for the whole kernel): 4 for
+// 1024-thread workgroups (16^3 blocks), 2 for 512 (32x32), 1 for 256 and for a single wavefront.
+template <int CONN, int MAXPT, class Sync>
+__device__ __forceinline__ bool eliminate_fast(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs) {
+    if constexpr (2 * Sten<CONN>::H <= 8) {
+        if (nfree <= MAXPT * sy.step) return eliminate_cached<CONN, Sync, MAXPT>(sy, L, nfree, fs);
+    }
+    return eliminate<CONN>(sy, L, nfree, fs);
+}
+
+template <int NT>
+constexpr int elim_regs() { return NT >= 1024 ? 4 : (NT >= 512 ? 2 : 1); }
+
 // Keeps the list entries that are still free (order not preserved); returns their count.  The height array,
 // not yet in use, holds the survivors by list position in between.  Whole workgroup; ctr is a zeroed LDS slot.
 template <int CONN>
@@ -912,11 +988,11 @@ DOPE_UNROLL
     if (nfree > 0 && nfree <= WAVE_FLOW_MAX) {
         if (tid < 64) {
             WaveSync sy{tid, 64};
-            if (eliminate<CONN>(sy, L, nfree, fs)) flow_network<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
+            if (eliminate_fast<CONN, 1>(sy, L, nfree, fs)) flow_network<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
         }
     } else if (nfree > 0) {
         BlockSync sy{tid, NT, s_ctr + 2, 0};
-        if (eliminate<CONN>(sy, L, nfree, fs)) {
+        if (eliminate_fast<CONN, elim_regs<NT>()>(sy, L, nfree, fs)) {
             // the flow phases only visit the nodes the elimination left free; few enough go to one wavefront
             const int nleft = compact_free<CONN>(L, nfree, s_ctr + 8, tid, NT);
             if (nleft <= WAVE_FLOW_MAX) {
@@ -1199,11 +1275,11 @@ DOPE_UNROLL
         if (nfree > 0 && nfree <= WAVE_FLOW_MAX) {
             if (tid < 64) {
                 WaveSync sy{tid, 64};
-                if (eliminate<CONN>(sy, L, nfree, fs)) flow_network<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
+                if (eliminate_fast<CONN, 1>(sy, L, nfree, fs)) flow_network<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
             }
         } else if (nfree > 0) {
             BlockSync sy{tid, NT, s_ctr + 2, 0};
-            if (eliminate<CONN>(sy, L, nfree, fs)) {
+            if (eliminate_fast<CONN, elim_regs<NT>()>(sy, L, nfree, fs)) {
                 const int nleft = compact_free<CONN>(L, nfree, s_ctr + 8, tid, NT);
                 if (nleft <= WAVE_FLOW_MAX) {
                     if (tid < 64) {
