@@ -41,6 +41,7 @@ struct dope_ctx {
     int2 *blist = nullptr;
     uint8_t *yhat = nullptr, *yslot = nullptr, *labels = nullptr;
     int64_t *resid = nullptr, *epart = nullptr;
+    int2 *axrow = nullptr;             // axis cover rows (consensus of radius-1 stencils)
     unsigned char *gscr = nullptr;   // per-block max-flow state of blocks beyond the LDS
     Ctl *hctl = nullptr;       // pinned host mirror of the control block
     std::vector<int32_t> hbtab, hchunk;
@@ -68,7 +69,7 @@ namespace {
 
 struct Layout {
     size_t ctl, img, bitems, citems, queue, btab, chunk, blist, u, w, cw, Y, A0, A1, yhat, yslot, resid, stats, labels,
-        epart, gscr, total;
+        epart, axrow, gscr, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -111,6 +112,7 @@ Layout layout_for(const Geom &g) {
     L.stats = take(size_t(g.K) * 16);
     L.labels = take(size_t(g.n));
     L.epart = take(size_t(dope::ENERGY_PARTS) * 8);
+    L.axrow = take((size_t(g.W) + g.H + g.D) * 8);
     L.gscr = take(size_t(g.K) * gmem_stride(g));
     L.total = o;
     return L;
@@ -325,6 +327,7 @@ void assign_pointers(dope_ctx *c) {
     c->stats = reinterpret_cast<int32_t *>(b + L.stats);
     c->labels = reinterpret_cast<uint8_t *>(b + L.labels);
     c->epart = reinterpret_cast<int64_t *>(b + L.epart);
+    c->axrow = reinterpret_cast<int2 *>(b + L.axrow);
     c->gscr = gmem_stride(c->g) ? reinterpret_cast<unsigned char *>(b + L.gscr) : nullptr;
 }
 
@@ -346,6 +349,7 @@ dope::Img host_img(const dope_ctx *c) {
     im.resid = c->resid;
     im.ctl = c->ctl;
     im.summary = nullptr;
+    im.axrow = c->axrow;
     im.n_chunks = int32_t(c->hchunk.size());
     im.n_blist = int32_t(c->nbl);
     return im;
@@ -358,6 +362,7 @@ dope_status upload_tables(dope_ctx *c) {
         HIP_TRY(c, hipMemcpyAsync(c->chunk_k0, c->hchunk.data(), c->hchunk.size() * 4, hipMemcpyHostToDevice,
                                   c->stream), "chunk table upload");
     if (c->nbl > 0) HIP_TRY(c, dope::launch_build_blist(c->g, c->btab, c->blist, c->stream), "boundary list");
+    HIP_TRY(c, dope::launch_axis_rows(c->g, c->axrow, c->stream), "axis rows");
     // one-image launch group: descriptor, work items, zeroed queue (staged in host memory that stays alive
     // until the synchronisation at the end of this function)
     const dope::Img im = host_img(c);

@@ -152,6 +152,10 @@ struct Img {
     int64_t *resid;
     Ctl *ctl;
     int32_t *summary;   // optional: {t, halted, converged, status} written after every iteration
+    // Covers of every coordinate of each axis for offsets -1, 0, +1 (axis 0 at [0, W), axis 1 at [W, W + H), axis
+    // 2 at [W + H, W + H + D)): {top block index, codes}, codes holding per offset t (bits 4 (t + 1) ..): the number
+    // of blocks containing the coordinate x + t (0 off the axis) and top(x + t) - top(x) + 1 (2 bits each).
+    const int2 *axrow;
     int32_t n_chunks;
     int32_t n_blist;
 };
@@ -216,6 +220,8 @@ hipError_t launch_validate(Ctl *ctl, hipStream_t s);
 // Boundary list of one image (see the workspace layout): one workgroup per block writes the owner copies of the
 // block's non-interior pixels from the block's base entry btab[k][7].
 hipError_t launch_build_blist(const Geom &g, const int32_t *btab, int2 *blist, hipStream_t s);
+// Axis cover rows of one image (see Img::axrow): W + H + D entries.
+hipError_t launch_axis_rows(const Geom &g, int2 *axrow, hipStream_t s);
 hipError_t launch_setup(const Geom &g, const int32_t *u_src, const int32_t *w_src, int32_t *u_ws, int32_t *cw,
                         int32_t lam_q8, int32_t *Y, int32_t *A0, int32_t *A1, uint8_t *yhat,
                         int64_t *resid, Ctl *ctl, int64_t mu0, int32_t mu_num, int32_t mu_den, uint64_t eps2,

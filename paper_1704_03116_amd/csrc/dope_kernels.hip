@@ -295,6 +295,23 @@ DOPE_UNROLL
             for (int t = 0; t <= 2 * R; ++t) z[t] = AxCov{0, t == R ? 1 : 0};
         }
     }
+    // The same covers from the image's axis rows (stencils of radius 1): three loads instead of three divisions.
+    __device__ __forceinline__ void init_rows(const GLOBAL uint64_t *rows, const Geom &g, int gx, int gy, int gz) {
+        static_assert(R == 1, "axis rows hold offsets -1, 0, +1");
+        const uint64_t rx = rows[gx], ry = rows[g.W + gy], rz = rows[g.W + g.H + gz];
+        unpack_row(rx, x);
+        unpack_row(ry, y);
+        unpack_row(rz, z);
+    }
+    // a row is the int2 {top block, codes}: the top block in the low 32 bits
+    __device__ __forceinline__ static void unpack_row(uint64_t r, AxCov c[3]) {
+        const int top = int(uint32_t(r)), codes = int(uint32_t(r >> 32));
+DOPE_UNROLL
+        for (int t = 0; t < 3; ++t) {
+            const int code = (codes >> (4 * t)) & 15;
+            c[t] = AxCov{top + ((code >> 2) & 3) - 1, code & 3};
+        }
+    }
     // cover of the pixel itself (offset 0) and of neighbour offset v along each axis
     __device__ __forceinline__ const AxCov &cx(int dx) const { return x[dx + R]; }
     __device__ __forceinline__ const AxCov &cy(int dy) const { return y[dy + R]; }
@@ -1648,7 +1665,8 @@ DOPE_UNROLL
         const int32_t m = int32_t(lin(g, gx, gy, gz));
         // block intervals of the coordinates x - R .. x + R along each axis
         BoxCov<CONN> bc;
-        bc.init(g, gx, gy, gz);
+        if constexpr (Sten<CONN>::R == 1) bc.init_rows(gp(reinterpret_cast<const uint64_t *>(im.axrow)), g, gx, gy, gz);
+        else bc.init(g, gx, gy, gz);
         const AxCov mx = bc.cx(0), my = bc.cy(0), mz = bc.cz(0);   // m itself
         const int lqm = bc.lq(make_int3(0, 0, 0));   // q_m = 2^lqm
         // Block-major index of pixel (x, y, z) in block (tx, ty, tz).  Indices are below 2^30 (sum of block
@@ -2537,6 +2555,27 @@ DOPE_UNROLL
         run += s_wc[0] + s_wc[1] + s_wc[2] + s_wc[3];
         __syncthreads();
     }
+}
+
+// Axis cover rows (Img::axrow): one thread per coordinate of each axis, from the closed-form covers.
+__global__ __launch_bounds__(256) void k_axis_rows(Geom g, int2 *__restrict__ axrow) {
+    const int i = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (i >= g.W + g.H + g.D) return;
+    const int a = i < g.W ? 0 : (i < g.W + g.H ? 1 : 2);
+    const int x = a == 0 ? i : (a == 1 ? i - g.W : i - g.W - g.H);
+    AxCov c[3];
+    axis_cov<1>(g.ax[a], x, c);
+    int codes = 0;
+    for (int t = 0; t < 3; ++t) {
+        const int d = c[t].cnt ? c[t].thi - c[1].thi + 1 : 1;   // in 0..2 on the axis (stride >= 1)
+        codes |= (c[t].cnt | (d << 2)) << (4 * t);
+    }
+    axrow[i] = make_int2(c[1].thi, codes);
+}
+
+hipError_t launch_axis_rows(const Geom &g, int2 *axrow, hipStream_t s) {
+    hipLaunchKernelGGL(k_axis_rows, dim3(blocks_for(int64_t(g.W) + g.H + g.D, 256)), dim3(256), 0, s, g, axrow);
+    return hipGetLastError();
 }
 
 hipError_t launch_build_blist(const Geom &g, const int32_t *btab, int2 *blist, hipStream_t s) {

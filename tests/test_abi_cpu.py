@@ -82,7 +82,7 @@ def _workspace_model(dims, h, K, tot, n_int):
     chunks = (nbl + 255) // 256
     return (a(128) + a(512) + a(8 * K) + a(8 * chunks) + a(256) + a(K * 32) + a(4 * chunks) + a(8 * nbl)
             + a(4 * n) + 2 * a(4 * h * n) + a(4 * n) + 2 * a(4 * tot) + a(tot) + a(n * (8 if dims[2] > 1 else 4))
-            + a(8 * K) + a(16 * K) + a(n) + a(8 * 256))
+            + a(8 * K) + a(16 * K) + a(n) + a(8 * 256) + a(8 * (dims[0] + dims[1] + dims[2])))
 
 
 @pytest.mark.parametrize("dims,conn,block,overlap,ndim", [
