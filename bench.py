@@ -139,11 +139,7 @@ def lds_bytes_per_iteration(stats, sizes, h):
 
 
 TRAFFIC_RECORDS = {"config2_ellipses512x512_8conn": "hbm_traffic_config2_512x512.json",
-                   "config3_spheres128x128x64_6conn": "hbm_traffic_config3_128x128x64.json",
-                   "kernel5_ellipses512x512_24conn": "hbm_traffic_kernel5_512x512.json",
-                   "kernel7_ellipses512x512_48conn": "hbm_traffic_kernel7_512x512.json",
-                   "kernel9_ellipses512x512_80conn": "hbm_traffic_kernel9_512x512.json",
-                   "config2_even64_ellipses512x512_8conn": "hbm_traffic_even64_512x512.json"}
+                   "config3_spheres128x128x64_6conn": "hbm_traffic_config3_128x128x64.json"}
 
 
 def measured_traffic(workload_name):

@@ -1048,8 +1048,8 @@ DOPE_UNROLL
             const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
             st_at(Yg, m << 2, int32_t(Yc));
             st_at(Aout, cpy << 2, int32_t(0));
-            const int64_t rr = int64_t(yv) * Y_ONE - Yc;
-            r2 += (unsigned long long)(rr * rr);
+            const int32_t rr = yv * Y_ONE - int32_t(Yc);   // |rr| < 2^23
+            r2 += (unsigned long long)(int64_t(rr) * int64_t(rr));
         }
     }
     // r2 < 2^52 per lane (at most 16 pixels per thread, each square below 2^46)
@@ -1388,8 +1388,8 @@ DOPE_UNROLL
             const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
             st_at(Yg, m << 2, int32_t(Yc));
             st_at(Aout, cpy << 2, int32_t(0));
-            const int64_t rr = int64_t(yv) * Y_ONE - Yc;
-            r2 += (unsigned long long)(rr * rr);
+            const int32_t rr = yv * Y_ONE - int32_t(Yc);   // |rr| < 2^23
+            r2 += (unsigned long long)(int64_t(rr) * int64_t(rr));
         }
     }
     r2 = wave_sum64(r2);
@@ -1745,11 +1745,11 @@ DOPE_UNROLL
         // ---- S_m and Hc_m.  With Y1 = sum of this pixel's labels, Hc regroups exactly as
         //      Hc = Y1 sum_j c_mj q_j - q_m sum_j c_mj (sum of j's labels)
         //           - sum_j c_mj sum_{blocks b holding m and j} (yhat_b,m - yhat_b,j) ----
-        int64_t S = 0;
+        int32_t S = 0;   // at most 8 copies of 2^16 + 2^22 in magnitude: fits 32 bits
         int Y1 = 0;
 DOPE_UNROLL
         for (int q = 0; q < MAXC; ++q) {
-            S += int64_t(yv_own[q]) * Y_ONE + a_own[q];
+            S += yv_own[q] * Y_ONE + a_own[q];
             Y1 += yv_own[q];
         }
         // The label words hold one byte (0 or 1) per slot q = e + 2b + 4a.  A slot set along one axis is a byte
@@ -1798,7 +1798,7 @@ DOPE_UNROLL
             HC += int64_t(cwv[d]) * kd;
         }
         // floor((M S - 4 Hc) / (M q)) = floor(floor((M S - 4 Hc) / M) / q), q a power of two
-        int64_t Yn = floor_div_est(M * S - 4 * HC, M, invM);
+        int64_t Yn = floor_div_est(M * int64_t(S) - 4 * HC, M, invM);
         Yn >>= lqm;
         if (Yn >= STATE_LIMIT || Yn <= -STATE_LIMIT) ovf = 1;
         const int64_t Yc = Yn > STATE_LIMIT ? STATE_LIMIT : (Yn < -STATE_LIMIT ? -STATE_LIMIT : Yn);
@@ -1811,8 +1811,8 @@ DOPE_UNROLL
             if (An >= STATE_LIMIT || An <= -STATE_LIMIT) ovf = 1;
             const int64_t Ac = An > STATE_LIMIT ? STATE_LIMIT : (An < -STATE_LIMIT ? -STATE_LIMIT : An);
             if (!skip) st_at(Aout, cc_own[q] << 2, int32_t(Ac));
-            const int64_t rr = int64_t(yv_own[q]) * Y_ONE - Yc;
-            r2[q] = (unsigned long long)(rr * rr);
+            const int32_t rr = yv_own[q] * Y_ONE - int32_t(Yc);   // |rr| < 2^23: one 32 x 32 -> 64-bit product
+            r2[q] = (unsigned long long)(int64_t(rr) * int64_t(rr));
         }
     }
     // residual slots.  When all lanes of a wavefront share an owner block, the MAXC sums over the wavefront are
