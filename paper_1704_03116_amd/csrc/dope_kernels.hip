@@ -808,31 +808,33 @@ DOPE_UNROLL
         L.dd[p] = -U;
     }
     sy.sync();
-    // (3) push-relabel with periodic global relabelling (exact distances to the sink by monotone relaxation)
+    // (3) push-relabel with periodic global relabelling: heights become exact residual distances to the sink,
+    //     by a breadth-first search backwards from the nodes with sink capacity left, one level per barrier.
+    //     Level l's nodes (height l) hand l + 1 to every unlabelled neighbour with a residual arc into them, so a
+    //     level costs each thread a look at its nodes' heights plus the arcs of the nodes on the frontier only.
     for (;;) {
         for (int i = sy.idx; i < nfree; i += sy.step) {
             const int p = L.lst[i];
             if (!(L.st[p] & ST_FIXED)) L.hh[p] = L.dd[p] < 0 ? 1 : H_INF;
         }
         sy.sync();
-        for (;;) {
-            bool ch = false;
+        for (int lvl = 1;; ++lvl) {
+            bool grew = false;
             for (int i = sy.idx; i < nfree; i += sy.step) {
                 const int p = L.lst[i];
-                if (L.st[p] & ST_FIXED) continue;
+                if (L.hh[p] != lvl || (L.st[p] & ST_FIXED)) continue;
                 const DirMask<CONN> m = L.msk[p];
-                const int h = L.hh[p];
-                if (!m || h == 1) continue;
-                int best = h;
 DOPE_UNROLL
                 for (int d = 0; d < ND; ++d)
-                    if (((m >> d) & 1u) && L.res(p, d) > 0) {
-                        const int hv = L.hh[L.nbr(p, d)] + 1;
-                        if (hv < best) best = hv;
+                    if ((m >> d) & 1u) {
+                        const int v = L.nbr(p, d);
+                        if (L.hh[v] == H_INF && L.res_in(p, d) > 0) {
+                            L.hh[v] = int16_t(lvl + 1);
+                            grew = true;
+                        }
                     }
-                if (best < h) { L.hh[p] = int16_t(best); ch = true; }
             }
-            if (!sy.any(ch)) break;
+            if (!sy.any(grew)) break;
         }
         bool act = false;
         for (int i = sy.idx; i < nfree; i += sy.step) {
@@ -890,27 +892,35 @@ DOPE_UNROLL
             ++fs.rounds;
         }
     }
-    // (4) canonical cut: nodes reachable in the residual graph from any node holding excess
+    // (4) canonical cut: nodes reachable in the residual graph from any node holding excess, by a breadth-first
+    //     search forwards from those nodes; the heights, no longer needed, hold the search levels (-1: not
+    //     reached yet)
     for (int i = sy.idx; i < nfree; i += sy.step) {
         const int p = L.lst[i];
-        if (!(L.st[p] & ST_FIXED) && L.dd[p] > 0) L.st[p] |= ST_MARK;
+        if (L.st[p] & ST_FIXED) continue;
+        const bool ex = L.dd[p] > 0;
+        L.hh[p] = ex ? int16_t(0) : int16_t(-1);
+        if (ex) L.st[p] |= ST_MARK;
     }
     sy.sync();
-    for (;;) {
-        bool ch = false;
+    for (int lvl = 0;; ++lvl) {
+        bool grew = false;
         for (int i = sy.idx; i < nfree; i += sy.step) {
             const int p = L.lst[i];
-            if (L.st[p] & (ST_FIXED | ST_MARK)) continue;
+            if (L.hh[p] != lvl || (L.st[p] & ST_FIXED)) continue;
             const DirMask<CONN> m = L.msk[p];
 DOPE_UNROLL
             for (int d = 0; d < ND; ++d)
-                if (((m >> d) & 1u) && (L.st[L.nbr(p, d)] & ST_MARK) && L.res_in(p, d) > 0) {
-                    L.st[p] |= ST_MARK;
-                    ch = true;
-                    break;
+                if ((m >> d) & 1u) {
+                    const int v = L.nbr(p, d);
+                    if (L.hh[v] < 0 && L.res(p, d) > 0) {
+                        L.hh[v] = int16_t(lvl + 1);
+                        L.st[v] |= ST_MARK;
+                        grew = true;
+                    }
                 }
         }
-        if (!sy.any(ch)) break;
+        if (!sy.any(grew)) break;
     }
 }
 
