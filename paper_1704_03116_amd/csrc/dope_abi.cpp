@@ -217,6 +217,13 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
                 for (int tx = 0; tx < g.ax[0].nb; ++tx, ++kk)
                     if (dope::block_offset(g, tx, ty, tz) != (*btab)[size_t(kk) * dope::BTAB_STRIDE + 6])
                         return "internal: block offset formula disagrees with the partition";
+        // one-image block solves take their block from the dispatch order: a permutation of the blocks
+        std::vector<uint8_t> seen(size_t(g.K), 0);
+        for (int32_t b = 0; b < g.K; ++b) {
+            const int32_t k = dope::block_at(g, b);
+            if (k < 0 || k >= g.K || seen[size_t(k)]) return "internal: block dispatch order is not a permutation";
+            seen[size_t(k)] = 1;
+        }
     }
     if (p->mu0 < 1 || p->mu0 > dope::MU_MAX) return "mu0 must be in [1, 2^24 - 1]";
     if (p->mu_fact_num < 0 || p->mu_fact_den < 0) return "mu_fact must be positive";

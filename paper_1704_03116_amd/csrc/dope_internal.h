@@ -38,6 +38,55 @@ inline __host__ __device__ int32_t axis_ext(const Axis &a, int32_t t) {
     return e < a.B ? e : a.B;
 }
 
+// Workgroups of a launch are dispatched to the XCDs round-robin (workgroup b runs on XCD b % 8) and every XCD
+// has its own L2.  Workgroup b takes item xcd_item(b, n): XCD j gets the contiguous item range starting at
+// j * (n / 8) + min(j, n % 8), so neighbouring blocks or chunks, which read the same halo lines, share an L2
+// instead of fetching those lines once per XCD.  A bijection of [0, n).
+constexpr int NUM_XCDS = 8;
+inline __host__ __device__ int32_t xcd_item(int32_t b, int32_t n) {
+    const int32_t j = b % NUM_XCDS, slot = b / NUM_XCDS;
+    const int32_t base = n / NUM_XCDS, rem = n % NUM_XCDS;
+    return j * base + (j < rem ? j : rem) + slot;
+}
+
+// Blocks of full extent B along an axis: all but a clipped last one.
+inline __host__ __device__ int32_t axis_full(const Axis &a) { return a.nb - (axis_ext(a, a.nb - 1) < a.B ? 1 : 0); }
+
+// Block solved by workgroup b of a one-image block-solve launch.  The blocks of full extent along every axis come
+// first (raster order over their box, each XCD taking a contiguous range of them), then every other block in
+// raster order.  When the blocks outnumber the workgroups that fit the chip at once, a block's solve time grows
+// with its pixel count, so the full blocks fill the first round and the clipped blocks of the far faces, half the
+// size or less, the next; in raster order the clipped blocks are spread through both rounds.  A bijection of
+// [0, K) (the context checks it when it is created).
+inline __host__ __device__ int32_t block_at(const Geom &g, int32_t b) {
+    const int32_t nbx = g.ax[0].nb, nby = g.ax[1].nb;
+    const int32_t fx = axis_full(g.ax[0]), fy = axis_full(g.ax[1]), fz = axis_full(g.ax[2]);
+    const int32_t nf = fx * fy * fz;
+    if (b < nf) {
+        const int32_t f = xcd_item(b, nf);
+        const int32_t kx = f % fx, r = f / fx;
+        return kx + nbx * (r % fy + nby * (r / fy));
+    }
+    int32_t r = b - nf;
+    const int32_t per_layer = nbx * nby - fx * fy;   // clipped blocks in each z layer below fz
+    if (r < fz * per_layer) {
+        const int32_t kz = r / per_layer;
+        r -= kz * per_layer;
+        const int32_t px = nbx - fx;   // clipped along x in each row below fy
+        int32_t kx, ky;
+        if (r < fy * px) {
+            ky = r / px;
+            kx = fx + (r - ky * px);
+        } else {
+            r -= fy * px;
+            ky = fy + r / nbx;
+            kx = r - (ky - fy) * nbx;
+        }
+        return kx + nbx * (ky + nby * kz);
+    }
+    return (r - fz * per_layer) + nbx * nby * fz;   // the z layers from fz on
+}
+
 // A pixel is interior to block (tx, ty, tz) when it and every pixel of its stencil box (offsets up to r per axis)
 // lie in that block only.  Then both Hc terms of Eq. (10) vanish for it, S_m is its single copy, and no other
 // block reads it.  Along one axis: lo <= x < hi with lo = start + o + r (0 for the first block),

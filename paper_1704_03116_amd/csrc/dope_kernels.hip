@@ -340,16 +340,6 @@ __device__ __forceinline__ int64_t lin(const Geom &g, int x, int y, int z) {
     return int64_t(x) + int64_t(g.W) * (int64_t(y) + int64_t(g.H) * int64_t(z));
 }
 
-// Workgroups of a launch are dispatched to the XCDs round-robin (workgroup b runs on XCD b % 8) and every XCD
-// has its own L2.  Workgroup b takes item xcd_item(b, n): XCD j gets the contiguous item range starting at
-// j * (n / 8) + min(j, n % 8), so neighbouring blocks or chunks, which read the same halo lines, share an L2
-// instead of fetching those lines once per XCD.  A bijection of [0, n).
-constexpr int NUM_XCDS = 8;
-__device__ __forceinline__ int xcd_item(int b, int n) {
-    const int j = b % NUM_XCDS, slot = b / NUM_XCDS;
-    const int base = n / NUM_XCDS, rem = n % NUM_XCDS;
-    return j * base + (j < rem ? j : rem) + slot;
-}
 
 // Sum of x over the 64 lanes of a wavefront, returned in lane 63; every lane must be active.  Data-parallel
 // primitive moves, no LDS: each lane adds its three predecessors in its row of 16, then rows add the partial sums
@@ -1127,16 +1117,15 @@ __global__ __launch_bounds__(NT, 2) void k_block_solve_queue(const Img *__restri
 // One-image block solve: the image descriptor and the multiplier parity come as kernel arguments, and no
 // descriptor or loop-control load stands between the launch and the gathers (the loop control is read while they
 // are in flight; a skipped iteration stops before its first global store).  Workgroup b solves block
-// xcd_item(b, K): each XCD gets a contiguous range of blocks, so the halo lines that neighbouring blocks share are
-// fetched into one L2 (measured on MI355X: 7x7 neighbourhood 55 -> 41 us per launch, 5x5 30 -> 28 us, 512x512
-// 8-connected solve 2 % faster).  The batch kernels keep dispatch order, where whole images of hard blocks
-// would otherwise land on one XCD.
+// block_at(g, b): the blocks of full extent first, each XCD taking a contiguous range of them, so the halo lines
+// that neighbouring blocks share are fetched into one L2 (measured on MI355X: 7x7 neighbourhood 55 -> 41 us per
+// launch, 5x5 30 -> 28 us, 512x512 8-connected solve 2 % faster), then the clipped blocks.  The batch kernels
+// keep dispatch order, where whole images of hard blocks would otherwise land on one XCD.
 template <int CONN, int NT>
 __global__ __launch_bounds__(NT, 2) void k_block_solve_one(const Img one, int32_t par, int32_t npmax,
                                                         int32_t round_limit, int32_t relabel_period) {
     extern __shared__ __align__(16) unsigned char smem[];
-    block_maxflow<CONN, NT>(one, xcd_item(blockIdx.x, gridDim.x), smem, npmax, round_limit, relabel_period, par,
-                            true);
+    block_maxflow<CONN, NT>(one, block_at(one.g, blockIdx.x), smem, npmax, round_limit, relabel_period, par, true);
 }
 
 // One-image block solve for blocks whose max-flow state exceeds the LDS (large blocks of the paper's even
@@ -1151,8 +1140,7 @@ __global__ __launch_bounds__(NT, 2) void k_block_solve_gmem(const Img one, int32
     // a skipped iteration returns before the prologue, whose state would go to global memory
     if (ctl_skip(one.ctl)) return;
     unsigned char *mem = scratch + uint64_t(blockIdx.x) * stride;
-    block_maxflow<CONN, NT>(one, xcd_item(blockIdx.x, gridDim.x), mem, npmax, round_limit, relabel_period, par,
-                            false);
+    block_maxflow<CONN, NT>(one, block_at(one.g, blockIdx.x), mem, npmax, round_limit, relabel_period, par, false);
 }
 
 // ------------------------------------------------------------------------------------------------------------
