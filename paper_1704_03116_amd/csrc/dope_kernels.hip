@@ -774,16 +774,50 @@ __device__ __forceinline__ int compact_free(BlockLds<CONN> &L, int nfree, int *c
     return *ctr;
 }
 
-// Everything after the elimination for the nfree nodes of lst: flow network, push-relabel to a max preflow, and
-// the canonical cut (ST_MARK = label 1).
-template <int CONN, class Sync>
-__device__ __forceinline__ void flow_network(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t round_limit,
-                                             int32_t relabel_period, FlowStats &fs) {
+// The nodes a thread visits in the flow phases: its entries idx, idx + step, ... of the LDS list (fixed nodes
+// included, skipped at every visit) ...
+struct LdsNodes {
+    static constexpr bool FREE_ONLY = false;
+    const int16_t *lst;
+    int idx, step, n;
+    template <class F>
+    __device__ __forceinline__ void each(F &&f) const {
+        for (int i = idx; i < n; i += step) f(int(lst[i]));
+    }
+};
+
+// ... or the same entries held in registers (at most MAXPT per thread), the fixed ones dropped once: a visit then
+// costs no list load, and the loads of a thread's nodes are independent of each other.
+template <int MAXPT>
+struct RegNodes {
+    static constexpr bool FREE_ONLY = true;
+    int p[MAXPT];
+    __device__ __forceinline__ RegNodes(const int16_t *lst, const uint8_t *st, int idx, int step, int n) {
+DOPE_UNROLL
+        for (int j = 0; j < MAXPT; ++j) {
+            const int i = idx + j * step;
+            const int v = i < n ? int(lst[i]) : -1;
+            p[j] = (v >= 0 && !(st[v] & ST_FIXED)) ? v : -1;
+        }
+    }
+    template <class F>
+    __device__ __forceinline__ void each(F &&f) const {
+DOPE_UNROLL
+        for (int j = 0; j < MAXPT; ++j)
+            if (p[j] >= 0) f(p[j]);
+    }
+};
+
+// Everything after the elimination for the nfree nodes of lst (visited through nodes): flow network, push-relabel
+// to a max preflow, and the canonical cut (ST_MARK = label 1).
+template <int CONN, class Sync, class Nodes>
+__device__ __forceinline__ void flow_network(Sync &sy, BlockLds<CONN> &L, const Nodes &nodes, int nfree,
+                                             int32_t round_limit, int32_t relabel_period, FlowStats &fs) {
     constexpr int ND = 2 * Sten<CONN>::H;
+    auto fixed = [&](int p) -> bool { return !Nodes::FREE_ONLY && (L.st[p] & ST_FIXED); };
     // (2) flow network of the remaining free nodes: source excess -U and sink capacity U in one signed value
-    for (int i = sy.idx; i < nfree; i += sy.step) {
-        const int p = L.lst[i];
-        if (L.st[p] & ST_FIXED) continue;
+    nodes.each([&](int p) {
+        if (fixed(p)) return;
         const DirMask<CONN> m = L.msk[p];
         DirMask<CONN> live = 0;
         int32_t U = L.dd[p];
@@ -796,23 +830,21 @@ DOPE_UNROLL
             }
         L.msk[p] = LdsMask<CONN>(live);
         L.dd[p] = -U;
-    }
+    });
     sy.sync();
     // (3) push-relabel with periodic global relabelling: heights become exact residual distances to the sink,
     //     by a breadth-first search backwards from the nodes with sink capacity left, one level per barrier.
     //     Level l's nodes (height l) hand l + 1 to every unlabelled neighbour with a residual arc into them, so a
     //     level costs each thread a look at its nodes' heights plus the arcs of the nodes on the frontier only.
     for (;;) {
-        for (int i = sy.idx; i < nfree; i += sy.step) {
-            const int p = L.lst[i];
-            if (!(L.st[p] & ST_FIXED)) L.hh[p] = L.dd[p] < 0 ? 1 : H_INF;
-        }
+        nodes.each([&](int p) {
+            if (!fixed(p)) L.hh[p] = L.dd[p] < 0 ? 1 : H_INF;
+        });
         sy.sync();
         for (int lvl = 1;; ++lvl) {
             bool grew = false;
-            for (int i = sy.idx; i < nfree; i += sy.step) {
-                const int p = L.lst[i];
-                if (L.hh[p] != lvl || (L.st[p] & ST_FIXED)) continue;
+            nodes.each([&](int p) {
+                if (L.hh[p] != lvl || fixed(p)) return;
                 const DirMask<CONN> m = L.msk[p];
 DOPE_UNROLL
                 for (int d = 0; d < ND; ++d)
@@ -823,25 +855,23 @@ DOPE_UNROLL
                             grew = true;
                         }
                     }
-            }
+            });
             if (!sy.any(grew)) break;
         }
         bool act = false;
-        for (int i = sy.idx; i < nfree; i += sy.step) {
-            const int p = L.lst[i];
-            if (!(L.st[p] & ST_FIXED) && L.dd[p] > 0 && L.hh[p] < H_INF) act = true;
-        }
+        nodes.each([&](int p) {
+            if (!fixed(p) && L.dd[p] > 0 && L.hh[p] < H_INF) act = true;
+        });
         if (!sy.any(act)) break;
         ++fs.grel;
         if (fs.rounds >= round_limit) { fs.fail = true; break; }
         for (int r = 0; r < relabel_period; ++r) {
             // push: heights are frozen, so an edge is admissible in one direction only
-            for (int i = sy.idx; i < nfree; i += sy.step) {
-                const int p = L.lst[i];
-                if (L.st[p] & ST_FIXED) continue;
+            nodes.each([&](int p) {
+                if (fixed(p)) return;
                 const int32_t e = L.dd[p];
                 const int h = L.hh[p];
-                if (e <= 0 || h >= H_INF) continue;
+                if (e <= 0 || h >= H_INF) return;
                 const DirMask<CONN> m = L.msk[p];
                 int32_t rem = e;
 DOPE_UNROLL
@@ -857,14 +887,13 @@ DOPE_UNROLL
                     rem -= delta;
                 }
                 if (rem != e) atomicSub(&L.dd[p], e - rem);
-            }
+            });
             sy.sync();
             // relabel: active nodes without an admissible arc rise to 1 + the lowest residual neighbour
-            for (int i = sy.idx; i < nfree; i += sy.step) {
-                const int p = L.lst[i];
-                if (L.st[p] & ST_FIXED) continue;
+            nodes.each([&](int p) {
+                if (fixed(p)) return;
                 const int h = L.hh[p];
-                if (L.dd[p] <= 0 || h >= H_INF) continue;
+                if (L.dd[p] <= 0 || h >= H_INF) return;
                 const DirMask<CONN> m = L.msk[p];
                 int best = 1 << 30;
                 bool adm = false;
@@ -877,7 +906,7 @@ DOPE_UNROLL
                     else if (hv + 1 < best) best = hv + 1;
                 }
                 if (!adm) L.hh[p] = int16_t(best > nfree ? H_INF : best);   // no path of that length exists
-            }
+            });
             sy.sync();
             ++fs.rounds;
         }
@@ -885,19 +914,17 @@ DOPE_UNROLL
     // (4) canonical cut: nodes reachable in the residual graph from any node holding excess, by a breadth-first
     //     search forwards from those nodes; the heights, no longer needed, hold the search levels (-1: not
     //     reached yet)
-    for (int i = sy.idx; i < nfree; i += sy.step) {
-        const int p = L.lst[i];
-        if (L.st[p] & ST_FIXED) continue;
+    nodes.each([&](int p) {
+        if (fixed(p)) return;
         const bool ex = L.dd[p] > 0;
         L.hh[p] = ex ? int16_t(0) : int16_t(-1);
         if (ex) L.st[p] |= ST_MARK;
-    }
+    });
     sy.sync();
     for (int lvl = 0;; ++lvl) {
         bool grew = false;
-        for (int i = sy.idx; i < nfree; i += sy.step) {
-            const int p = L.lst[i];
-            if (L.hh[p] != lvl || (L.st[p] & ST_FIXED)) continue;
+        nodes.each([&](int p) {
+            if (L.hh[p] != lvl || fixed(p)) return;
             const DirMask<CONN> m = L.msk[p];
 DOPE_UNROLL
             for (int d = 0; d < ND; ++d)
@@ -909,9 +936,24 @@ DOPE_UNROLL
                         grew = true;
                     }
                 }
-        }
+        });
         if (!sy.any(grew)) break;
     }
+}
+
+// flow_network over the thread's list entries: held in registers when there are at most MAXPT per thread and the
+// stencil has at most eight directions, otherwise (and always for MAXPT = 0) read from the LDS list at every visit.
+template <int CONN, int MAXPT, class Sync>
+__device__ __forceinline__ void flow_phases(Sync &sy, BlockLds<CONN> &L, int nfree, int32_t round_limit,
+                                            int32_t relabel_period, FlowStats &fs) {
+    if constexpr (2 * Sten<CONN>::H <= 8 && MAXPT > 0) {
+        if (nfree <= MAXPT * sy.step) {
+            const RegNodes<MAXPT> nodes(L.lst, L.st, sy.idx, sy.step, nfree);
+            return flow_network<CONN>(sy, L, nodes, nfree, round_limit, relabel_period, fs);
+        }
+    }
+    const LdsNodes nodes{L.lst, sy.idx, sy.step, nfree};
+    flow_network<CONN>(sy, L, nodes, nfree, round_limit, relabel_period, fs);
 }
 
 // Free nodes up to this count are handled by one wavefront (wave-level synchronisation only).
@@ -919,8 +961,9 @@ constexpr int WAVE_FLOW_MAX = 64;
 
 // par: multiplier buffer parity (t & 1), or -1 to read it from the loop control.  spec: the caller has not
 // checked the loop control; the gathers are issued first and the block stops before its first global store when
-// the iteration is skipped.
-template <int CONN, int NT>
+// the iteration is skipped.  REGLIST: the flow phases may hold the thread's list entries in registers (the
+// global-memory variant, short of registers already, reads them from the list).
+template <int CONN, int NT, bool REGLIST = true>
 __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned char *smem, int32_t npmax,
                                               int32_t round_limit, int32_t relabel_period, int par, bool spec) {
     constexpr int H = Sten<CONN>::H;
@@ -1005,7 +1048,7 @@ DOPE_UNROLL
     if (nfree > 0 && nfree <= WAVE_FLOW_MAX) {
         if (tid < 64) {
             WaveSync sy{tid, 64};
-            if (eliminate_fast<CONN, 1>(sy, L, nfree, fs)) flow_network<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
+            if (eliminate_fast<CONN, 1>(sy, L, nfree, fs)) flow_phases<CONN, 1>(sy, L, nfree, round_limit, relabel_period, fs);
         }
     } else if (nfree > 0) {
         BlockSync sy{tid, NT, s_ctr + 2, 0};
@@ -1015,10 +1058,10 @@ DOPE_UNROLL
             if (nleft <= WAVE_FLOW_MAX) {
                 if (tid < 64) {
                     WaveSync ws{tid, 64};
-                    flow_network<CONN>(ws, L, nleft, round_limit, relabel_period, fs);
+                    flow_phases<CONN, 1>(ws, L, nleft, round_limit, relabel_period, fs);
                 }
             } else {
-                flow_network<CONN>(sy, L, nleft, round_limit, relabel_period, fs);
+                flow_phases<CONN, REGLIST ? elim_regs<NT>() : 0>(sy, L, nleft, round_limit, relabel_period, fs);
             }
         }
     }
@@ -1140,7 +1183,8 @@ __global__ __launch_bounds__(NT, 2) void k_block_solve_gmem(const Img one, int32
     // a skipped iteration returns before the prologue, whose state would go to global memory
     if (ctl_skip(one.ctl)) return;
     unsigned char *mem = scratch + uint64_t(blockIdx.x) * stride;
-    block_maxflow<CONN, NT>(one, block_at(one.g, blockIdx.x), mem, npmax, round_limit, relabel_period, par, false);
+    block_maxflow<CONN, NT, false>(one, block_at(one.g, blockIdx.x), mem, npmax, round_limit, relabel_period, par,
+                                   false);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -1290,7 +1334,7 @@ DOPE_UNROLL
         if (nfree > 0 && nfree <= WAVE_FLOW_MAX) {
             if (tid < 64) {
                 WaveSync sy{tid, 64};
-                if (eliminate_fast<CONN, 1>(sy, L, nfree, fs)) flow_network<CONN>(sy, L, nfree, round_limit, relabel_period, fs);
+                if (eliminate_fast<CONN, 1>(sy, L, nfree, fs)) flow_phases<CONN, 1>(sy, L, nfree, round_limit, relabel_period, fs);
             }
         } else if (nfree > 0) {
             BlockSync sy{tid, NT, s_ctr + 2, 0};
@@ -1299,10 +1343,10 @@ DOPE_UNROLL
                 if (nleft <= WAVE_FLOW_MAX) {
                     if (tid < 64) {
                         WaveSync ws{tid, 64};
-                        flow_network<CONN>(ws, L, nleft, round_limit, relabel_period, fs);
+                        flow_phases<CONN, 1>(ws, L, nleft, round_limit, relabel_period, fs);
                     }
                 } else {
-                    flow_network<CONN>(sy, L, nleft, round_limit, relabel_period, fs);
+                    flow_phases<CONN, elim_regs<NT>()>(sy, L, nleft, round_limit, relabel_period, fs);
                 }
             }
         }
