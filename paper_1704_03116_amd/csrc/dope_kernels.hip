@@ -511,11 +511,13 @@ DOPE_UNROLL
         const int32_t c = ((ld.ing >> d) & 1u) ? ld.cv[d] : 0;
         const bool inb = (inb_m >> d) & 1u;
         const int lqj = bc.lq(v);
+        // x (2^lqj - [j in k]) as a shift and a subtraction (the shift on the unsigned bits: |x 2^lqj| < 2^31)
         if (Sten<CONN>::NDIM == 2) {
-            const int32_t F = c * (1 << lqj) - (inb ? c : 0);
+            const int32_t F = int32_t(uint32_t(c) << lqj) - (inb ? c : 0);
             G += int64_t(F) * int64_t(ld.Y - ld.yj[d]);
         } else {
-            const int32_t t = (ld.Y - ld.yj[d]) * ((1 << lqj) - (inb ? 1 : 0));
+            const int32_t dy = ld.Y - ld.yj[d];
+            const int32_t t = int32_t(uint32_t(dy) << lqj) - (inb ? dy : 0);
             G += int64_t(c) * int64_t(t);
         }
         if (d < H) cap_out[d] = inb ? c : 0;
