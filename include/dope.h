@@ -183,6 +183,14 @@ dope_status dope_sizes(const dope_ctx *ctx, int64_t *n, int32_t *n_blocks, int64
 /* Device bytes the context needs for p (for caller-allocated workspaces and admission by HBM footprint). */
 size_t dope_workspace_bytes(const dope_params *p);
 
+/* Launch schedule of the one-image block solves for p (a host query, no device needed; not an operation of the
+ * paper but the order in which Algorithm 1's per-block solves of one iteration are handed to workgroups):
+ * *n_blocks = K; if order != NULL (host memory, int32[K]) workgroup b of a block-solve launch solves block
+ * order[b], blocks numbered x-fastest as in dope_block_table.  The blocks of full extent along every axis come
+ * first, then the blocks clipped at the far faces; within each group every XCD takes a contiguous range.
+ * EINVAL for invalid parameters (message in dope_last_error(NULL)). */
+dope_status dope_dispatch_order(const dope_params *p, int32_t *n_blocks, int32_t *order);
+
 /* Use caller-owned device memory (>= dope_workspace_bytes, 256-byte aligned) instead of allocating.
  * Must be called before dope_set_energy; the memory must outlive the context. */
 dope_status dope_bind_workspace(dope_ctx *ctx, void *dev_ptr, size_t bytes);

@@ -72,6 +72,7 @@ SIGNATURES = {
     "dope_block_table": (ctypes.c_int, [_P, _I32P, _P]),
     "dope_sizes": (ctypes.c_int, [_P, _I64P, _I32P, _I64P, _I32P]),
     "dope_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(dope_params)]),
+    "dope_dispatch_order": (ctypes.c_int, [ctypes.POINTER(dope_params), _I32P, _P]),
     "dope_autotune": (ctypes.c_int, [ctypes.c_int32, _I32P, ctypes.c_int32, _I32P, _I32P]),
     "dope_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "dope_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -165,6 +166,7 @@ dope_block_stats = _fn("dope_block_stats")
 dope_block_table = _fn("dope_block_table")
 dope_sizes = _fn("dope_sizes")
 dope_workspace_bytes = _fn("dope_workspace_bytes")
+dope_dispatch_order = _fn("dope_dispatch_order")
 dope_autotune = _fn("dope_autotune")
 dope_bind_workspace = _fn("dope_bind_workspace")
 dope_profile_enable = _fn("dope_profile_enable")

@@ -217,6 +217,8 @@ std::string make_geom(const dope_params *p, Geom &g, std::vector<int32_t> *btab)
                 for (int tx = 0; tx < g.ax[0].nb; ++tx, ++kk)
                     if (dope::block_offset(g, tx, ty, tz) != (*btab)[size_t(kk) * dope::BTAB_STRIDE + 6])
                         return "internal: block offset formula disagrees with the partition";
+    }
+    {
         // one-image block solves take their block from the dispatch order: a permutation of the blocks
         std::vector<uint8_t> seen(size_t(g.K), 0);
         for (int32_t b = 0; b < g.K; ++b) {
@@ -604,6 +606,22 @@ size_t dope_workspace_bytes(const dope_params *p) {
     if (q.mu_fact_num == 0 && q.mu_fact_den == 0) { q.mu_fact_num = 21; q.mu_fact_den = 20; }
     if (!make_geom(&q, g, nullptr).empty()) return 0;
     return layout_for(g).total;
+}
+
+dope_status dope_dispatch_order(const dope_params *p, int32_t *n_blocks, int32_t *order) {
+    Geom g{};
+    if (!p || !n_blocks) {
+        g_create_error = "null params or n_blocks";
+        return DOPE_EINVAL;
+    }
+    dope_params q = *p;
+    if (q.mu_fact_num == 0 && q.mu_fact_den == 0) { q.mu_fact_num = 21; q.mu_fact_den = 20; }
+    g_create_error = make_geom(&q, g, nullptr);
+    if (!g_create_error.empty()) return DOPE_EINVAL;
+    *n_blocks = g.K;
+    if (order)
+        for (int32_t b = 0; b < g.K; ++b) order[b] = dope::block_at(g, b);
+    return DOPE_OK;
 }
 
 dope_status dope_bind_workspace(dope_ctx *c, void *dev_ptr, size_t bytes) {

@@ -53,11 +53,11 @@ inline __host__ __device__ int32_t xcd_item(int32_t b, int32_t n) {
 inline __host__ __device__ int32_t axis_full(const Axis &a) { return a.nb - (axis_ext(a, a.nb - 1) < a.B ? 1 : 0); }
 
 // Block solved by workgroup b of a one-image block-solve launch.  The blocks of full extent along every axis come
-// first (raster order over their box, each XCD taking a contiguous range of them), then every other block in
-// raster order.  When the blocks outnumber the workgroups that fit the chip at once, a block's solve time grows
-// with its pixel count, so the full blocks fill the first round and the clipped blocks of the far faces, half the
-// size or less, the next; in raster order the clipped blocks are spread through both rounds.  A bijection of
-// [0, K) (the context checks it when it is created).
+// first (raster order over their box), then every other block (raster order over the rest); within each of the
+// two groups every XCD takes a contiguous range.  When the blocks outnumber the workgroups that fit the chip at
+// once, a block's solve time grows with its pixel count, so the full blocks fill the first round and the clipped
+// blocks of the far faces, half the size or less, the next; in raster order the clipped blocks are spread through
+// both rounds.  A bijection of [0, K) (the context checks it when it is created).
 inline __host__ __device__ int32_t block_at(const Geom &g, int32_t b) {
     const int32_t nbx = g.ax[0].nb, nby = g.ax[1].nb;
     const int32_t fx = axis_full(g.ax[0]), fy = axis_full(g.ax[1]), fz = axis_full(g.ax[2]);
@@ -67,7 +67,7 @@ inline __host__ __device__ int32_t block_at(const Geom &g, int32_t b) {
         const int32_t kx = f % fx, r = f / fx;
         return kx + nbx * (r % fy + nby * (r / fy));
     }
-    int32_t r = b - nf;
+    int32_t r = xcd_item(b - nf, g.K - nf);
     const int32_t per_layer = nbx * nby - fx * fy;   // clipped blocks in each z layer below fz
     if (r < fz * per_layer) {
         const int32_t kz = r / per_layer;

@@ -53,6 +53,15 @@ def autotune(ndim, dims, connectivity):
     return tuple(b), tuple(o)
 
 
+def dispatch_order(params):
+    """dope_dispatch_order: the block each workgroup of a one-image block-solve launch takes (int32 numpy array)."""
+    K = ctypes.c_int32()
+    N.check(N.dope_dispatch_order(ctypes.byref(params), ctypes.byref(K), None))
+    order = np.zeros(K.value, dtype=np.int32)
+    N.check(N.dope_dispatch_order(ctypes.byref(params), ctypes.byref(K), ctypes.c_void_p(order.ctypes.data)))
+    return order
+
+
 def solve_noalloc(params, u, w, lambda_q8, labels, stream=None):
     """dope_solve_noalloc: one whole solve whose device state lives in the library's static device array.
     u, w, labels are device tensors; returns the loop information (dict).  stream: HIP stream handle (None = the
