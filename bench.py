@@ -186,12 +186,23 @@ def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
         d.labels(lab)
         return info
 
-    for _ in range(warmup):
+    last = [time.perf_counter()]
+
+    def progress(what, i):
+        # slow workloads (seconds per solve) report every 10 s of steps; each solve ends with a host readback
+        now = time.perf_counter()
+        if now - last[0] > 10.0:
+            print(f"[bench] {p.name}: {what} step {i + 1}/{steps}", file=sys.stderr, flush=True)
+            last[0] = now
+
+    for i in range(warmup):
         info = step()
+        progress("warm-up", i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         info = step()
+        progress("timed", i)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     # Per-kernel durations come from HIP events recorded around every block-solve and consensus launch on the
@@ -199,8 +210,9 @@ def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
     # kernels, so the throughput pass above carries none.
     d.profile_enable(True)
     t1 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         step()
+        progress("event-timed", i)
     torch.cuda.synchronize()
     prof_elapsed = time.perf_counter() - t1
     prof = d.profile_read()

@@ -530,6 +530,70 @@ DOPE_UNROLL
     return int64_t(ld.u) * int64_t(16384 >> lqi) + ((G + mu_term) >> 16);
 }
 
+// The same unary for the wide stencils, CH directions at a time: the gathers of one chunk are in flight together
+// and a pixel never holds more than CH neighbours' values (PixLoads holds two per direction, which beyond a few
+// dozen directions spills registers).  The capacities of the in-block half-edges go straight to cap[o * npmax].
+template <int CONN, int CH, class Cov>
+__device__ __forceinline__ int64_t unary_chunked(const Geom &g, const GLOBAL int32_t *__restrict__ u,
+                                                 const GLOBAL int32_t *__restrict__ cw,
+                                                 const GLOBAL int32_t *__restrict__ Y,
+                                                 const GLOBAL int32_t *__restrict__ A, uint32_t ci, int gx, int gy,
+                                                 int gz, const Cov &bc, int64_t M, int lx, int ly, int lz, int ex,
+                                                 int ey, int ez, int32_t *cap, int npmax, DirMask<CONN> &mask,
+                                                 int64_t &sumc) {
+    constexpr int H = Sten<CONN>::H;
+    constexpr int ND = 2 * H;
+    const uint32_t i = uint32_t(gx) + uint32_t(g.W) * (uint32_t(gy) + uint32_t(g.H) * uint32_t(gz));
+    const uint32_t bi = i << 2;
+    const DirMask<CONN> ing = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
+    const int32_t uu = ld_at(u, bi), Yi = ld_at(Y, bi), a = ld_at(A, ci << 2);
+    const int lqi = bc.lq(make_int3(0, 0, 0));
+    const DirMask<CONN> inb_m = inside_mask<CONN>(lx, ly, lz, ex, ey, ez);   // in the block implies on the grid
+    int64_t G = 0;
+    int32_t sc = 0;   // sum of |c| < 2^29 (checked at upload)
+    mask = 0;
+#pragma nounroll
+    for (int d0 = 0; d0 < ND; d0 += CH) {
+        int32_t cv[CH], yj[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            // slots past the last direction gather direction ND - 1 again (unused)
+            const int d = d0 + j < ND ? d0 + j : ND - 1;
+            const int3 v = full_dir<CONN>(d);
+            const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
+            uint32_t bj = ((ing >> d) & 1u) ? bi + (uint32_t(dl) << 2) : bi;
+            asm("" : "+v"(bj));   // optimisation barrier only: keeps the loads unconditional
+            const GLOBAL int32_t *cwo = cw + int64_t(d < H ? d : d - H) * g.n;
+            cv[j] = ld_at(cwo, d < H ? bi : bj);
+            yj[j] = ld_at(Y, bj);
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int d = d0 + j;
+            if (d >= ND) break;
+            const int3 v = full_dir<CONN>(d);
+            const int32_t c = ((ing >> d) & 1u) ? cv[j] : 0;
+            const bool inb = (inb_m >> d) & 1u;
+            const int lqj = bc.lq(v);
+            if (Sten<CONN>::NDIM == 2) {
+                const int32_t F = int32_t(uint32_t(c) << lqj) - (inb ? c : 0);
+                G += int64_t(F) * int64_t(Yi - yj[j]);
+            } else {
+                const int32_t dy = Yi - yj[j];
+                const int32_t t = int32_t(uint32_t(dy) << lqj) - (inb ? dy : 0);
+                G += int64_t(c) * int64_t(t);
+            }
+            if (d < H) cap[d * npmax] = inb ? c : 0;
+            const bool on = inb && c != 0;
+            sc += on ? (c < 0 ? -c : c) : 0;
+            mask |= on ? (DirMask<CONN>(1) << d) : DirMask<CONN>(0);
+        }
+    }
+    sumc = sc;
+    const int64_t mu_term = (M << 14) * int64_t(a - Yi + Y_HALF);
+    return int64_t(uu) * int64_t(16384 >> lqi) + ((G + mu_term) >> 16);
+}
+
 template <int CONN>
 __device__ __forceinline__ int64_t unary_from(const Geom &g, const PixLoads<CONN> &ld, int64_t M, int gx, int gy,
                                               int gz, int lx, int ly, int lz, int ex, int ey, int ez,
@@ -1017,22 +1081,43 @@ DOPE_UNROLL
     walk.init(tid, NT, ex, ey, inv_ex, inv_ey);
     for (int p = tid; p < np; p += NT, walk.next()) {
         const int3 l = make_int3(walk.lx, walk.ly, walk.lz);
-        PixLoads<CONN> ld;
-        unary_loads<CONN>(g, gu, gcw, gY, Ain, uint32_t(off + p), x0 + l.x, y0 + l.y, z0 + l.z, ld);
-        int32_t cp[H];
         DirMask<CONN> m;
         int64_t sumc;
         int64_t Ut;
-        if (lq_tab) {
-            const TabCov<CONN> tc{s_lq[0][l.x], s_lq[1][l.y], s_lq[2][l.z]};
-            Ut = unary_from_cov<CONN>(tc, ld, M, l.x, l.y, l.z, ex, ey, ez, cp, m, sumc);
-        } else {
-            Ut = unary_from<CONN>(g, ld, M, x0 + l.x, y0 + l.y, z0 + l.z, l.x, l.y, l.z, ex, ey, ez, cp, m, sumc);
-        }
+        if constexpr (2 * H > 48) {
+            // the widest stencils (9x9, radius-3 and radius-4 balls): eight directions at a time, capacities
+            // written as they come (holding all directions' gathers spilled hundreds of registers there; up to
+            // the 7x7 square the one-shot gathers are faster)
+            const uint32_t ci = uint32_t(off + p);
+            const int gx = x0 + l.x, gy = y0 + l.y, gz = z0 + l.z;
+            if (lq_tab) {
+                const TabCov<CONN> tc{s_lq[0][l.x], s_lq[1][l.y], s_lq[2][l.z]};
+                Ut = unary_chunked<CONN, 8>(g, gu, gcw, gY, Ain, ci, gx, gy, gz, tc, M, l.x, l.y, l.z, ex, ey, ez,
+                                            L.cap + p, npmax, m, sumc);
+            } else {
+                BoxCov<CONN> bc;
+                bc.init(g, gx, gy, gz);
+                Ut = unary_chunked<CONN, 8>(g, gu, gcw, gY, Ain, ci, gx, gy, gz, bc, M, l.x, l.y, l.z, ex, ey, ez,
+                                            L.cap + p, npmax, m, sumc);
+            }
 DOPE_UNROLL
-        for (int o = 0; o < H; ++o) {
-            L.cap[o * npmax + p] = cp[o];
-            L.flw[o * npmax + p] = 0;
+            for (int o = 0; o < H; ++o) L.flw[o * npmax + p] = 0;
+        } else {
+            PixLoads<CONN> ld;
+            unary_loads<CONN>(g, gu, gcw, gY, Ain, uint32_t(off + p), x0 + l.x, y0 + l.y, z0 + l.z, ld);
+            int32_t cp[H];
+            if (lq_tab) {
+                const TabCov<CONN> tc{s_lq[0][l.x], s_lq[1][l.y], s_lq[2][l.z]};
+                Ut = unary_from_cov<CONN>(tc, ld, M, l.x, l.y, l.z, ex, ey, ez, cp, m, sumc);
+            } else {
+                Ut = unary_from<CONN>(g, ld, M, x0 + l.x, y0 + l.y, z0 + l.z, l.x, l.y, l.z, ex, ey, ez, cp, m,
+                                      sumc);
+            }
+DOPE_UNROLL
+            for (int o = 0; o < H; ++o) {
+                L.cap[o * npmax + p] = cp[o];
+                L.flw[o * npmax + p] = 0;
+            }
         }
         uint8_t sbits = 0;
         if (Ut < -sumc) sbits = ST_FIXED | ST_LABEL;       // label 1 in every minimiser
