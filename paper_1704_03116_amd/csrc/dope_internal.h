@@ -165,6 +165,11 @@ inline __host__ __device__ constexpr size_t maxflow_lds_bytes(int np, int hs) {
     const int mb = dir_mask_bytes(hs);
     return 64 + size_t(np) * (8 * hs + 9 + mb) + (mb > 16 ? 32 : (mb > 8 ? 16 : (mb > 1 ? 8 : 0)));
 }
+// The same layout without the per-edge arrays (capacities and flows, 8h bytes per node): the LDS part of the
+// global-memory block solver, whose edge arrays stay in global memory.
+inline __host__ __device__ constexpr size_t maxflow_node_lds_bytes(int np, int hs) {
+    return maxflow_lds_bytes(np, hs) - size_t(np) * 8 * hs;
+}
 constexpr size_t LDS_LIMIT = 163840;   // gfx950: 160 KiB per workgroup
 // Dynamic LDS the max-flow block kernels may take: the rest of the 160 KiB holds their static arrays (the per-axis
 // cover rows of a block).

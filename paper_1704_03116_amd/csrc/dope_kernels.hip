@@ -1025,13 +1025,20 @@ __device__ __forceinline__ void flow_phases(Sync &sy, BlockLds<CONN> &L, int nfr
 // Free nodes up to this count are handled by one wavefront (wave-level synchronisation only).
 constexpr int WAVE_FLOW_MAX = 64;
 
+// Per-axis rows of log2 q of the block being solved (block_lq_rows): one array per kernel, shared by the variants
+// of the block solve that a kernel inlines (a function-scope array would be allocated once per variant).
+__shared__ uint16_t s_lq_rows[3][LQ_TAB];
+
 // par: multiplier buffer parity (t & 1), or -1 to read it from the loop control.  spec: the caller has not
 // checked the loop control; the gathers are issued first and the block stops before its first global store when
 // the iteration is skipped.  REGLIST: the flow phases may hold the thread's list entries in registers (the
-// global-memory variant, short of registers already, reads them from the list).
-template <int CONN, int NT, bool REGLIST = true>
+// global-memory variant, short of registers already, reads them from the list).  SPLIT: the per-edge arrays
+// (capacities and flows) live at gedge + 64 in global memory and only the per-node arrays in smem; otherwise the
+// whole state lives in smem (the maxflow_lds_bytes layout).
+template <int CONN, int NT, bool REGLIST = true, bool SPLIT = false>
 __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned char *smem, int32_t npmax,
-                                              int32_t round_limit, int32_t relabel_period, int par, bool spec) {
+                                              int32_t round_limit, int32_t relabel_period, int par, bool spec,
+                                              unsigned char *gedge = nullptr) {
     constexpr int H = Sten<CONN>::H;
     const Geom &g = im.g;
     const GLOBAL Ctl *ctl = gp(im.ctl);
@@ -1050,15 +1057,17 @@ __device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned cha
     int *s_ctr = reinterpret_cast<int *>(smem);
     BlockLds<CONN> L;
     L.npmax = npmax;
-    L.cap = reinterpret_cast<int32_t *>(smem + 64);
+    L.cap = reinterpret_cast<int32_t *>((SPLIT ? gedge : smem) + 64);
     L.flw = L.cap + H * npmax;
-    L.dd = L.flw + H * npmax;
+    // the node arrays follow the edge arrays, or start the LDS when the edge arrays are in global memory
+    const size_t noff = SPLIT ? 64 : 64 + size_t(npmax) * 8 * H;
+    L.dd = reinterpret_cast<int32_t *>(smem + noff);
     L.hh = reinterpret_cast<int16_t *>(L.dd + npmax);
     L.lst = L.hh + npmax;
     {
         // the mask array follows the free list, aligned to its element size (maxflow_lds_bytes counts the slack)
         constexpr size_t MB = sizeof(LdsMask<CONN>);
-        const size_t mo = 64 + size_t(npmax) * (8 * H + 8);
+        const size_t mo = noff + size_t(npmax) * 8;
         L.msk = reinterpret_cast<LdsMask<CONN> *>(smem + ((mo + MB - 1) & ~(MB - 1)));
     }
     L.st = reinterpret_cast<uint8_t *>(L.msk + npmax);
@@ -1068,7 +1077,7 @@ DOPE_UNROLL
         L.loff[o] = v.x + ex * (v.y + ey * v.z);
     }
     // covers of the block's coordinates, once per block (blocks of at most LQ_TAB pixels per axis)
-    __shared__ uint16_t s_lq[3][LQ_TAB];
+    uint16_t (*s_lq)[LQ_TAB] = s_lq_rows;
     const bool lq_tab = ex <= LQ_TAB && ey <= LQ_TAB && ez <= LQ_TAB;   // uniform
     if (lq_tab) block_lq_rows<CONN, NT>(g, x0, y0, z0, ex, ey, ez, s_lq);
     if (tid < 15) s_ctr[tid] = 0;
@@ -1259,19 +1268,25 @@ __global__ __launch_bounds__(NT, 2) void k_block_solve_one(const Img one, int32_
 }
 
 // One-image block solve for blocks whose max-flow state exceeds the LDS (large blocks of the paper's even
-// partitions, or blocks of the wide stencils larger than a few hundred pixels): the same solver with its node
-// arrays in a global-memory region of the workgroup's own,
-// scratch + b * stride (stride >= maxflow_lds_bytes(npmax, h)), which stays mostly in the L2.  Barriers order
-// these accesses as they do LDS ones (workgroup-scope fences; the waves of a workgroup share one CU).
+// partitions, or blocks of the wide stencils larger than a few hundred pixels): the same solver with its state in
+// a global-memory region of the workgroup's own, scratch + b * stride (stride >= maxflow_lds_bytes(npmax, h)),
+// which stays mostly in the L2.  split != 0: only the per-edge arrays (capacities and flows, 8h bytes per node)
+// go there and the per-node arrays (excess, height, list, mask, state: 9 + m bytes per node) and the barrier slots
+// stay in dynamic LDS; otherwise everything is in the region.  Barriers order the global accesses as they do LDS
+// ones (workgroup-scope fences; the waves of a workgroup share one CU).
 template <int CONN, int NT>
 __global__ __launch_bounds__(NT, 2) void k_block_solve_gmem(const Img one, int32_t par, int32_t npmax,
                                                          int32_t round_limit, int32_t relabel_period,
-                                                         unsigned char *scratch, uint64_t stride) {
+                                                         unsigned char *scratch, uint64_t stride, int32_t split) {
+    extern __shared__ __align__(16) unsigned char smem[];
     // a skipped iteration returns before the prologue, whose state would go to global memory
     if (ctl_skip(one.ctl)) return;
     unsigned char *mem = scratch + uint64_t(blockIdx.x) * stride;
-    block_maxflow<CONN, NT, false>(one, block_at(one.g, blockIdx.x), mem, npmax, round_limit, relabel_period, par,
-                                   false);
+    const int k = block_at(one.g, blockIdx.x);
+    if (split)
+        block_maxflow<CONN, NT, false, true>(one, k, smem, npmax, round_limit, relabel_period, par, false, mem);
+    else
+        block_maxflow<CONN, NT, false>(one, k, mem, npmax, round_limit, relabel_period, par, false);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -2477,10 +2492,21 @@ hipError_t launch_maxflow_gmem(const Group &grp, hipStream_t s, hipEvent_t e0, h
     const int32_t round_limit = 65536 + 64 * grp.npmax;
     const int32_t relabel_period = 8;
     const dim3 grid(unsigned(grp.n_blk_items));
-    if (e0) hipExtLaunchKernelGGL(k_block_solve_gmem<CONN, NT>, grid, dim3(NT), 0u, s, e0, e1, 0u, *grp.one, grp.par,
-                                  grp.npmax, round_limit, relabel_period, grp.gscratch, grp.gstride);
-    else hipLaunchKernelGGL((k_block_solve_gmem<CONN, NT>), grid, dim3(NT), 0, s, *grp.one, grp.par, grp.npmax,
-                            round_limit, relabel_period, grp.gscratch, grp.gstride);
+    // the per-node arrays go to LDS when they fit there (the edge arrays are 8h of every node's 8h + 9 + m bytes)
+    static std::once_flag lds_once;
+    static hipError_t lds_err = hipSuccess;
+    std::call_once(lds_once, [] {
+        lds_err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_block_solve_gmem<CONN, NT>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(MAXFLOW_LDS_LIMIT));
+    });
+    if (lds_err != hipSuccess) return lds_err;
+    const size_t node_lds = maxflow_node_lds_bytes(grp.npmax, Sten<CONN>::H);
+    const int32_t split = node_lds <= MAXFLOW_LDS_LIMIT ? 1 : 0;
+    const uint32_t lds = split ? uint32_t(node_lds) : 0u;
+    if (e0) hipExtLaunchKernelGGL(k_block_solve_gmem<CONN, NT>, grid, dim3(NT), lds, s, e0, e1, 0u, *grp.one, grp.par,
+                                  grp.npmax, round_limit, relabel_period, grp.gscratch, grp.gstride, split);
+    else hipLaunchKernelGGL((k_block_solve_gmem<CONN, NT>), grid, dim3(NT), lds, s, *grp.one, grp.par, grp.npmax,
+                            round_limit, relabel_period, grp.gscratch, grp.gstride, split);
     return hipGetLastError();
 }
 
