@@ -1847,55 +1847,18 @@ DOPE_UNROLL
         }
         constexpr int WSH = MAXC == 8 ? 3 : 2;   // log2 of the label word size
         SlotWord wm = ld_at(ysl, uint32_t(m) << WSH);
-        int32_t cwv[ND];
-        bool ing[ND];
-        SlotWord wj[ND];
         const DirMask<CONN> ingm = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
-DOPE_UNROLL
-        for (int d = 0; d < ND; ++d) {
+        // c_mj and the label word of stencil neighbour d (an off-grid neighbour reads pixel m itself; its c is
+        // masked where it is used)
+        auto gather = [&](int d, int32_t &cv, SlotWord &w) {
             const int3 v = full_dir<CONN>(d);
-            ing[d] = (ingm >> d) & 1u;
             const int32_t dl = v.x + g.W * (v.y + g.H * v.z);
-            uint32_t j = ing[d] ? uint32_t(m) + uint32_t(dl) : uint32_t(m);
+            uint32_t j = ((ingm >> d) & 1u) ? uint32_t(m) + uint32_t(dl) : uint32_t(m);
             asm("" : "+v"(j));   // optimisation barrier only: keeps the loads unconditional
             const GLOBAL int32_t *cwd = gp(im.cw) + int64_t(d < H ? d : d - H) * g.n;
-            cwv[d] = ld_at(cwd, (d < H ? uint32_t(m) : j) << 2);
-            wj[d] = ld_at(ysl, j << WSH);
-        }
-        // optimisation barrier only: every gathered value is used after all gathers are issued
-        if constexpr (CONN == 4) {
-            asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(wm), "+v"(cwv[0]),
-                "+v"(cwv[1]), "+v"(cwv[2]), "+v"(cwv[3]), "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]));
-        } else if constexpr (CONN == 8) {
-            asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(wm), "+v"(cwv[0]),
-                "+v"(cwv[1]), "+v"(cwv[2]), "+v"(cwv[3]), "+v"(cwv[4]), "+v"(cwv[5]), "+v"(cwv[6]), "+v"(cwv[7]),
-                "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]), "+v"(wj[4]), "+v"(wj[5]), "+v"(wj[6]),
-                "+v"(wj[7]));
-        } else if constexpr (CONN == 6) {
-            asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(a_own[4]),
-                "+v"(a_own[5]), "+v"(a_own[6]), "+v"(a_own[7]), "+v"(wm), "+v"(cwv[0]), "+v"(cwv[1]), "+v"(cwv[2]),
-                "+v"(cwv[3]), "+v"(cwv[4]), "+v"(cwv[5]), "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]),
-                "+v"(wj[4]), "+v"(wj[5]));
-        }
-        int yv_own[MAXC];
-DOPE_UNROLL
-        for (int q = 0; q < MAXC; ++q) {
-            yv_own[q] = v_own[q] ? int((wm >> (8 * q)) & 1u) : 0;
-            if (!v_own[q]) a_own[q] = 0;
-        }
-DOPE_UNROLL
-        for (int d = 0; d < ND; ++d)
-            if (!ing[d]) cwv[d] = 0;
-        // ---- S_m and Hc_m.  With Y1 = sum of this pixel's labels, Hc regroups exactly as
-        //      Hc = Y1 sum_j c_mj q_j - q_m sum_j c_mj (sum of j's labels)
-        //           - sum_j c_mj sum_{blocks b holding m and j} (yhat_b,m - yhat_b,j) ----
-        int32_t S = 0;   // at most 8 copies of 2^16 + 2^22 in magnitude: fits 32 bits
-        int Y1 = 0;
-DOPE_UNROLL
-        for (int q = 0; q < MAXC; ++q) {
-            S += yv_own[q] * Y_ONE + a_own[q];
-            Y1 += yv_own[q];
-        }
+            cv = ld_at(cwd, (d < H ? uint32_t(m) : j) << 2);
+            w = ld_at(ysl, j << WSH);
+        };
         // The label words hold one byte (0 or 1) per slot q = e + 2b + 4a.  A slot set along one axis is a byte
         // mask: slot bit e of that axis allowed for e in the 2-bit set.  A neighbour's copy in the block that is
         // m's slot q sits in the neighbour's slot q + (dx + 2dy + 4dz), d_ the difference of the two pixels'
@@ -1919,27 +1882,108 @@ DOPE_UNROLL
                 if (e < cm && e + dt >= 0 && e + dt < cn) set |= 1 << e;
             return set;
         };
-        // Hc = sum_j c_mj (Y1 q_j - q_m (labels of j) - shared_j): the bracket is a small integer (|.| <= 128)
-        int64_t HC = 0;
-DOPE_UNROLL
-        for (int d = 0; d < ND; ++d) {
-            const int3 v = full_dir<CONN>(d);
-            const AxCov &ax = bc.cx(v.x), &ay = bc.cy(v.y), &az = bc.cz(v.z);
+        // the bracket of Hc for neighbour j (covers ax, ay, az along the axes, label word wjd, q_j = 2^lqj):
+        // Y1 q_j - q_m (labels of j) - (labels of m minus labels of j over the blocks holding both), |.| <= 128
+        auto hc_bracket = [&](const AxCov &ax, const AxCov &ay, const AxCov &az, SlotWord wjd, int lqj,
+                              int Y1) -> int {
             const SlotWord vj = sel(cnt_set(ax.cnt), X0, X1) & sel(cnt_set(ay.cnt), Y0, Y1m) &
                                 sel(cnt_set(az.cnt), Z0, Z1);
-            const int yj_sum = bytesum(wj[d] & vj);
+            const int yj_sum = bytesum(wjd & vj);
             const int dx = ax.thi - mx.thi, dy = ay.thi - my.thi, dz = az.thi - mz.thi;
             const SlotWord sm = sel(shared_set(mx.cnt, dx, ax.cnt), X0, X1) &
                                 sel(shared_set(my.cnt, dy, ay.cnt), Y0, Y1m) &
                                 sel(shared_set(mz.cnt, dz, az.cnt), Z0, Z1);
             const int sh = dx + 2 * dy + 4 * dz;
             // shift right by sh bytes when sh >= 0, left by -sh bytes otherwise (two shifts, no branch)
-            const SlotWord wal = SlotWord(SlotWord(wj[d] >> (8 * (sh > 0 ? sh : 0))) << (8 * (sh < 0 ? -sh : 0)));
+            const SlotWord wal = SlotWord(SlotWord(wjd >> (8 * (sh > 0 ? sh : 0))) << (8 * (sh < 0 ? -sh : 0)));
             const int shared = bytesum(wm & sm) - bytesum(wal & sm);
             // q_j and q_m are powers of two (an off-grid neighbour has c = 0, so its shift count does not matter)
-            const int lqj = bc.lq(v);
-            const int kd = (Y1 << lqj) - (yj_sum << lqm) - shared;
-            HC += int64_t(cwv[d]) * kd;
+            return (Y1 << lqj) - (yj_sum << lqm) - shared;
+        };
+        // ---- S_m and Hc_m.  With Y1 = sum of this pixel's labels, Hc regroups exactly as
+        //      Hc = Y1 sum_j c_mj q_j - q_m sum_j c_mj (sum of j's labels)
+        //           - sum_j c_mj sum_{blocks b holding m and j} (yhat_b,m - yhat_b,j) ----
+        int32_t S = 0;   // at most 8 copies of 2^16 + 2^22 in magnitude: fits 32 bits
+        int Y1 = 0;
+        int yv_own[MAXC];
+        int64_t HC = 0;
+        if constexpr (ND <= 80) {
+            // every gather of this pixel is issued before any of them is used
+            int32_t cwv[ND];
+            SlotWord wj[ND];
+DOPE_UNROLL
+            for (int d = 0; d < ND; ++d) gather(d, cwv[d], wj[d]);
+            // optimisation barrier only: every gathered value is used after all gathers are issued
+            if constexpr (CONN == 4) {
+                asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(wm), "+v"(cwv[0]),
+                    "+v"(cwv[1]), "+v"(cwv[2]), "+v"(cwv[3]), "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]));
+            } else if constexpr (CONN == 8) {
+                asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(wm), "+v"(cwv[0]),
+                    "+v"(cwv[1]), "+v"(cwv[2]), "+v"(cwv[3]), "+v"(cwv[4]), "+v"(cwv[5]), "+v"(cwv[6]),
+                    "+v"(cwv[7]), "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]), "+v"(wj[3]), "+v"(wj[4]), "+v"(wj[5]),
+                    "+v"(wj[6]), "+v"(wj[7]));
+            } else if constexpr (CONN == 6) {
+                asm("" : "+v"(a_own[0]), "+v"(a_own[1]), "+v"(a_own[2]), "+v"(a_own[3]), "+v"(a_own[4]),
+                    "+v"(a_own[5]), "+v"(a_own[6]), "+v"(a_own[7]), "+v"(wm), "+v"(cwv[0]), "+v"(cwv[1]),
+                    "+v"(cwv[2]), "+v"(cwv[3]), "+v"(cwv[4]), "+v"(cwv[5]), "+v"(wj[0]), "+v"(wj[1]), "+v"(wj[2]),
+                    "+v"(wj[3]), "+v"(wj[4]), "+v"(wj[5]));
+            }
+DOPE_UNROLL
+            for (int q = 0; q < MAXC; ++q) {
+                yv_own[q] = v_own[q] ? int((wm >> (8 * q)) & 1u) : 0;
+                if (!v_own[q]) a_own[q] = 0;
+                S += yv_own[q] * Y_ONE + a_own[q];
+                Y1 += yv_own[q];
+            }
+DOPE_UNROLL
+            for (int d = 0; d < ND; ++d) {
+                const int3 v = full_dir<CONN>(d);
+                const int32_t c = ((ingm >> d) & 1u) ? cwv[d] : 0;
+                HC += int64_t(c) * hc_bracket(bc.cx(v.x), bc.cy(v.y), bc.cz(v.z), wj[d], bc.lq(v), Y1);
+            }
+        } else {
+            // the radius-3 and radius-4 balls: eight neighbours at a time (all of them at once held two values
+            // per direction in private memory), their covers read from packed per-axis codes, so that no array is
+            // indexed by a direction that is not a compile-time constant (up to the 9x9 square, 80 directions,
+            // the one-shot gathers are faster)
+DOPE_UNROLL
+            for (int q = 0; q < MAXC; ++q) {
+                yv_own[q] = v_own[q] ? int((wm >> (8 * q)) & 1u) : 0;
+                if (!v_own[q]) a_own[q] = 0;
+                S += yv_own[q] * Y_ONE + a_own[q];
+                Y1 += yv_own[q];
+            }
+            constexpr int R = Sten<CONN>::R;
+            // per axis, 4 bits per offset t = -R..R: cover count (2 bits) and top block minus m's top plus 1
+            auto pack = [&](const AxCov *c, int top) -> uint64_t {
+                uint64_t w = 0;
+#pragma unroll
+                for (int t = 0; t <= 2 * R; ++t)
+                    w |= uint64_t((c[t].cnt & 3) | (((c[t].thi - top + 1) & 3) << 2)) << (4 * t);
+                return w;
+            };
+            const uint64_t px = pack(bc.x, mx.thi), py = pack(bc.y, my.thi), pz = pack(bc.z, mz.thi);
+            auto cov = [](uint64_t w, int off, int top) -> AxCov {
+                const int code = int((w >> (4 * (off + R))) & 15u);
+                return AxCov{top + ((code >> 2) & 3) - 1, code & 3};
+            };
+#pragma nounroll
+            for (int d0 = 0; d0 < ND; d0 += 8) {
+                int32_t cv[8];
+                SlotWord w[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) gather(d0 + j < ND ? d0 + j : ND - 1, cv[j], w[j]);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int d = d0 + j;
+                    if (d >= ND) break;
+                    const int3 v = full_dir<CONN>(d);
+                    const AxCov ax = cov(px, v.x, mx.thi), ay = cov(py, v.y, my.thi), az = cov(pz, v.z, mz.thi);
+                    const int lqj = max(ax.cnt - 1, 0) + max(ay.cnt - 1, 0) + max(az.cnt - 1, 0);
+                    const int32_t c = ((ingm >> d) & 1u) ? cv[j] : 0;
+                    HC += int64_t(c) * hc_bracket(ax, ay, az, w[j], lqj, Y1);
+                }
+            }
         }
         // floor((M S - 4 Hc) / (M q)) = floor(floor((M S - 4 Hc) / M) / q), q a power of two
         int64_t Yn = floor_div_est(M * int64_t(S) - 4 * HC, M, invM);
