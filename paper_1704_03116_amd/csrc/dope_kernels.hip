@@ -850,6 +850,14 @@ struct LdsNodes {
     __device__ __forceinline__ void each(F &&f) const {
         for (int i = idx; i < n; i += step) f(int(lst[i]));
     }
+    // f on the nodes for which pred holds
+    template <class P, class F>
+    __device__ __forceinline__ void each_where(P &&pred, F &&f) const {
+        for (int i = idx; i < n; i += step) {
+            const int p = lst[i];
+            if (pred(p)) f(p);
+        }
+    }
 };
 
 // ... or the same entries held in registers (at most MAXPT per thread), the fixed ones dropped once: a visit then
@@ -858,7 +866,10 @@ template <int MAXPT>
 struct RegNodes {
     static constexpr bool FREE_ONLY = true;
     int p[MAXPT];
-    __device__ __forceinline__ RegNodes(const int16_t *lst, const uint8_t *st, int idx, int step, int n) {
+    int16_t *lst;
+    int idx, step;
+    __device__ __forceinline__ RegNodes(int16_t *lst_, const uint8_t *st, int idx_, int step_, int n)
+        : lst(lst_), idx(idx_), step(step_) {
 DOPE_UNROLL
         for (int j = 0; j < MAXPT; ++j) {
             const int i = idx + j * step;
@@ -871,6 +882,37 @@ DOPE_UNROLL
 DOPE_UNROLL
         for (int j = 0; j < MAXPT; ++j)
             if (p[j] >= 0) f(p[j]);
+    }
+    // f on the nodes for which pred holds, spread over the lanes of the wavefront: the wavefront's candidates are
+    // packed (ballot and prefix count) into its own list entries, which nothing reads once the nodes are held in
+    // registers, and lane l takes candidates l, l + 64, ...  A sparse frontier or active set then costs the
+    // wavefront one pass over its candidates instead of one pass per register slot in which any lane has one.
+    // The entries used are the wavefront's first n positions in (slot, lane) order, all below the list length.
+    template <class P, class F>
+    __device__ __forceinline__ void each_where(P &&pred, F &&f) const {
+        if constexpr (MAXPT == 1) {
+            // one slot: the wavefront passes over it once whichever lanes hold candidates
+            if (p[0] >= 0 && pred(p[0])) f(p[0]);
+            return;
+        }
+        const int lane = idx & 63, wbase = idx - lane;
+        int n = 0;
+DOPE_UNROLL
+        for (int j = 0; j < MAXPT; ++j) {
+            const bool c = p[j] >= 0 && pred(p[j]);
+            const unsigned long long bal = __ballot(c);
+            if (c) {
+                const int i = n + int(__builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u)));
+                lst[wbase + (i & 63) + (i >> 6) * step] = int16_t(p[j]);
+            }
+            n += __popcll(bal);
+        }
+        // the entries written by other lanes of this wavefront are read below
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int i = lane; i < n; i += 64) f(int(lst[wbase + (i & 63) + (i >> 6) * step]));
     }
 };
 
@@ -909,8 +951,7 @@ DOPE_UNROLL
         sy.sync();
         for (int lvl = 1;; ++lvl) {
             bool grew = false;
-            nodes.each([&](int p) {
-                if (L.hh[p] != lvl || fixed(p)) return;
+            nodes.each_where([&](int p) { return L.hh[p] == lvl && !fixed(p); }, [&](int p) {
                 const DirMask<CONN> m = L.msk[p];
 DOPE_UNROLL
                 for (int d = 0; d < ND; ++d)
@@ -932,9 +973,10 @@ DOPE_UNROLL
         ++fs.grel;
         if (fs.rounds >= round_limit) { fs.fail = true; break; }
         for (int r = 0; r < relabel_period; ++r) {
-            // push: heights are frozen, so an edge is admissible in one direction only
-            nodes.each([&](int p) {
-                if (fixed(p)) return;
+            // push: heights are frozen, so an edge is admissible in one direction only; a node's excess only
+            // grows until it pushes, so a node active when the active set is taken is still active here
+            auto active = [&](int p) { return !fixed(p) && L.dd[p] > 0 && L.hh[p] < H_INF; };
+            nodes.each_where(active, [&](int p) {
                 const int32_t e = L.dd[p];
                 const int h = L.hh[p];
                 if (e <= 0 || h >= H_INF) return;
@@ -956,8 +998,7 @@ DOPE_UNROLL
             });
             sy.sync();
             // relabel: active nodes without an admissible arc rise to 1 + the lowest residual neighbour
-            nodes.each([&](int p) {
-                if (fixed(p)) return;
+            nodes.each_where(active, [&](int p) {
                 const int h = L.hh[p];
                 if (L.dd[p] <= 0 || h >= H_INF) return;
                 const DirMask<CONN> m = L.msk[p];
@@ -989,8 +1030,7 @@ DOPE_UNROLL
     sy.sync();
     for (int lvl = 0;; ++lvl) {
         bool grew = false;
-        nodes.each([&](int p) {
-            if (L.hh[p] != lvl || fixed(p)) return;
+        nodes.each_where([&](int p) { return L.hh[p] == lvl && !fixed(p); }, [&](int p) {
             const DirMask<CONN> m = L.msk[p];
 DOPE_UNROLL
             for (int d = 0; d < ND; ++d)
