@@ -623,6 +623,29 @@ def test_blocks_beyond_lds_smoothing_dominated_flow():
         assert int(stats[0][:, 0].sum()) > 0 and int(stats[0][:, 1].sum()) > 0 and int(stats[0][:, 2].sum()) > 0
 
 
+# blocks whose per-node arrays alone exceed the LDS too (9 + m bytes per node: 16384-pixel blocks with the 3x3
+# stencils, 16^3 blocks of the radius-4 ball), so the whole max-flow state stays in the workspace
+GLOBAL_STATE_CASES = [
+    ("8-connected 2x2 blocks of 128x128", 8, (250, 250, 1), (128, 128, 1), (2, 2, 0), 1),
+    ("radius-4 ball 2x2x1 blocks of 16^3", 256, (24, 24, 16), (16, 16, 16), (4, 4, 4), 32),
+]
+
+
+@pytest.mark.parametrize("label,conn,dims,block,overlap,mb", GLOBAL_STATE_CASES, ids=[c[0] for c in GLOBAL_STATE_CASES])
+def test_blocks_with_all_state_in_global_memory(label, conn, dims, block, overlap, mb):
+    """The global-memory block solver keeps its per-node arrays in LDS when they fit; these blocks are too large
+    even for that, so the whole state (and the barrier slots) lives in the workspace.  Smoothing well above the
+    unaries makes the push-relabel phase run; the state equals the oracle's after every iteration."""
+    np_max = block[0] * block[1] * block[2]
+    assert 64 + np_max * (9 + mb) > 160 * 1024 - 1024   # beyond the LDS for the per-node arrays alone
+    p = synth.random_problem(28, dims, conn, block, overlap, lam_q8=512 if conn == 8 else 64,
+                             u_range=(-400, 400), w_range=(200, 1000) if conn == 8 else (20, 100), mu0=4000)
+    stats = []
+    d, _, _ = run_parity(p, 3, f"all state in global memory, {label}", stats=stats)
+    d.close()
+    assert int(stats[0][:, 0].sum()) > 0 and int(stats[0][:, 1].sum()) > 0
+
+
 PAPER_PARTITIONS = [(32, 25), (64, 10), (64, 0), (128, 0), (128, 25)]
 
 
