@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # int32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane and clock
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 EXH_OPS_PER_CODE = 15
-# host threads for the oracle: the CPU share of a one-GPU machine is 16 cores
+# host threads for the oracle: the cores available to the process, at most 16 (a one-GPU host's share)
 HOST_THREAD_CAP = 16
 
 

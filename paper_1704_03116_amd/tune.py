@@ -7,9 +7,9 @@ stays a pure function of the image shape and stencil.
 
 Candidates are the blocks whose max-flow state fits the LDS (batches and the server take only those) with stride
 B - o at least the stencil radius.  Images: the serving workload's grey disk at each size (2D; contrast weights of
-the stencil) and the sphere volume (3D).  Run from the repository root on the GPU machine:
+the stencil) and the sphere volume (3D).  Run from the repository root on an MI355X:
 
-    python paper_1704_03116_amd/tune.py --json gpurun_out/autotune_sweep.json --header gpurun_out/autotune_table.h
+    python paper_1704_03116_amd/tune.py --json autotune_sweep.json --header autotune_table.h
 """
 import argparse
 import json

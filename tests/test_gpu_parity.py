@@ -52,7 +52,7 @@ def assert_state_equal(d, S, info_o, t, dec):
     assert np.array_equal(d.block_resid(), info_o.resid2), f"iteration {t}: residuals differ"
 
 
-# host threads for the oracle's block solves (the GPU machine's CPU share is 16 cores)
+# host threads for the oracle's block solves (at most 16, a one-GPU host's share of cores)
 ORACLE_THREADS = min(16, os.cpu_count() or 1)
 
 
