@@ -1795,6 +1795,7 @@ DOPE_UNROLL
 // ------------------------------------------------------------------------------------------------------------
 
 constexpr int CONS_NT = CHUNK;   // boundary pixels per workgroup
+constexpr int CONS_SPAN = 64;    // owner blocks of a chunk with residual slots in LDS
 
 // One thread per boundary pixel m (a pixel that is not interior to its block), listed through its owner copy:
 // the copy in the block with the highest index along every axis.  The thread gathers yhat and A of every copy
@@ -1813,7 +1814,9 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     // speculative chunk: the loop control is read here but only the stores wait for it
     const bool skip = spec && ctl_skip(im.ctl);
     GLOBAL int32_t *__restrict__ Y = gp(im.Y);
-    __shared__ unsigned long long s_res[CONS_NT * MAXC];   // slot (owner block - kfirst) * MAXC + copy
+    // slot (owner block - kfirst) * MAXC + copy for the first CONS_SPAN owner blocks of the chunk (a chunk of
+    // boundary pixels listed by owner block rarely spans more; later owners add to the global residuals directly)
+    __shared__ unsigned long long s_res[CONS_SPAN * MAXC];
     __shared__ unsigned long long s_tr[CONS_NT / 64][MAXC][64];   // per wavefront: residual of copy q by lane
     __shared__ int s_ovf;
     const int tid = threadIdx.x;
@@ -1825,7 +1828,7 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
     const int kfirst = gp(im.chunk_k0)[chunk];
 DOPE_UNROLL
-    for (int q = 0; q < MAXC; ++q) s_res[q * CONS_NT + tid] = 0;
+    for (int q = 0; q < CONS_SPAN * MAXC / CONS_NT; ++q) s_res[q * CONS_NT + tid] = 0;
     if (tid == 0) s_ovf = 0;
     __syncthreads();
     const int64_t li = int64_t(chunk) * CONS_NT + tid;
@@ -2048,6 +2051,17 @@ DOPE_UNROLL
     // sums one copy index (MAXC values per lane, then log2 G shuffle steps).  Otherwise every lane adds its
     // residuals to the slots with LDS atomics.
     {
+        const int nbx = AX.nb, nbxy = AX.nb * AY.nb;
+        // r_k of the block holding copy q of a pixel whose owner block is kown
+        auto add_res = [&](int kown, int q, unsigned long long v) {
+            const int rel = kown - kfirst;
+            if (rel < CONS_SPAN) {
+                atomicAdd(&s_res[rel * MAXC + q], v);
+            } else if (!skip) {
+                const int kq = kown - (q & 1) - ((q >> 1) & 1) * nbx - (q >> 2) * nbxy;
+                atomicAdd((unsigned long long *)gp(im.resid + kq), v);
+            }
+        };
         const int k0 = __shfl(kk, 0);
         const bool same = __all(kk == k0);
         const int lane = tid & 63, wv = tid >> 6;
@@ -2062,11 +2076,11 @@ DOPE_UNROLL
             for (int i = 0; i < MAXC; ++i) v += s_tr[wv][q][part * MAXC + i];
 DOPE_UNROLL
             for (int sft = G / 2; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft);
-            if (part == 0 && v) atomicAdd(&s_res[(k0 - kfirst) * MAXC + q], v);
+            if (part == 0 && v) add_res(k0, q, v);
         } else {
 DOPE_UNROLL
             for (int q = 0; q < MAXC; ++q)
-                if (r2[q]) atomicAdd(&s_res[(kk - kfirst) * MAXC + q], r2[q]);
+                if (r2[q]) add_res(kk, q, r2[q]);
         }
     }
     if (ovf) s_ovf = 1;
@@ -2074,7 +2088,7 @@ DOPE_UNROLL
     if (skip) return;   // uniform
     {
         const int klast = (chunk + 1 < im.n_chunks) ? gp(im.chunk_k0)[chunk + 1] : g.K - 1;
-        const int span = min(klast - kfirst + 1, CONS_NT) * MAXC;
+        const int span = min(klast - kfirst + 1, CONS_SPAN) * MAXC;
         const int nbx = AX.nb, nbxy = AX.nb * AY.nb;
         for (int b = tid; b < span; b += CONS_NT) {
             if (!s_res[b]) continue;
