@@ -395,10 +395,10 @@ def _gen_request(r):
     return r, p.dims, np.ascontiguousarray(p.u, np.int32), np.ascontiguousarray(p.w, np.int32), p.lam_q8, p.mu0
 
 
-def serve_replay(n_req, slots):
+def serve_replay(n_req, slots, iters=1):
     """Replay the first n_req requests of the serving trace (Poisson arrivals, 200 req/s) twice: continuous
-    batching (up to `slots` requests admitted, one batched ADMM iteration per tick) and the plain path (one request
-    at a time, FIFO).  Also runs both closed-loop (every request queued at t = 0) for capacity.  Request inputs are
+    batching (up to `slots` requests admitted, `iters` batched ADMM iterations per tick) and the plain path (one
+    request at a time, FIFO, the same ticks).  Also runs both closed-loop (every request queued at t = 0) for capacity.  Request inputs are
     generated in worker processes (host memory holds a few requests at a time) and staged in HBM before the
     replay; block partitions come from dope_autotune."""
     import multiprocessing as mp
@@ -440,7 +440,7 @@ def serve_replay(n_req, slots):
     def run(n, max_active, closed, label):
         """The first n requests of the trace; closed: every request queued at t = 0."""
         budget = 96 << 30
-        srv = Server(budget, max_active)
+        srv = Server(budget, max_active, iters)
         lat = [None] * n
         owner = {}
         t0 = time.perf_counter()
@@ -477,7 +477,7 @@ def serve_replay(n_req, slots):
     plain_cap = run(n_req, 1, True, "plain, closed loop")
     return {
         "requests": n_req, "trace": "Poisson 200 req/s, sides {128..2048}, aspect U[0.5, 2], 8-connected, lambda U[0.5, 3]",
-        "mpx_total": round(total_px / 1e6, 1), "slots": slots, "staging_s": round(gen_s, 1),
+        "mpx_total": round(total_px / 1e6, 1), "slots": slots, "iters_per_step": iters, "staging_s": round(gen_s, 1),
         "served_p50_ms": served["p50_ms"], "served_p99_ms": served["p99_ms"], "served_mpx_s": served["mpx_s"],
         "plain_p50_ms": plain["p50_ms"], "plain_p99_ms": plain["p99_ms"], "plain_mpx_s": plain["mpx_s"],
         "served_capacity_mpx_s": served_cap["mpx_s"], "plain_capacity_mpx_s": plain_cap["mpx_s"],
@@ -554,6 +554,7 @@ def main():
     ap.add_argument("--serve", type=int, default=2000,
                     help="requests of the serving replay (first requests of the 2000-request trace; 0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=64, help="max admitted requests when serving")
+    ap.add_argument("--serve-iters", type=int, default=4, help="batched ADMM iterations per serving tick")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a 256 MiB device-to-device copy three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -633,7 +634,7 @@ def main():
         out["multilabel"] = measure_multilabel(max(2, args.secondary_steps // 8), 1)
 
     if args.serve > 0:
-        out["served"] = serve_replay(args.serve, args.serve_slots)
+        out["served"] = serve_replay(args.serve, args.serve_slots, args.serve_iters)
 
     if not args.no_cpu_baseline:
         print("[bench] oracle sample and serial global cut", file=sys.stderr, flush=True)

@@ -254,9 +254,10 @@ void dope_batch_destroy(dope_batch *b);
 /* ---- Serving: continuous batching of solve requests -----------------------------------------------------
  * A server owns one device arena of hbm_budget bytes.  Submitted requests wait in arrival order; each call to
  * dope_server_step admits waiting requests while their workspace (dope_workspace_bytes) fits in the free arena
- * and fewer than max_active are admitted, runs ONE batched ADMM iteration for all admitted requests together
- * (requests join and leave between iterations), and retires the requests that met their stopping rule, reached
- * max_iter or failed, writing their labels.  Their ADMM state stays resident on the device between steps.
+ * and fewer than max_active are admitted, runs iters_per_step batched ADMM iterations (one by default) for all
+ * admitted requests together (requests join and leave between steps; a request that meets its stopping rule or
+ * max_iter inside a step stops there on the device), and retires the requests that met their stopping rule,
+ * reached max_iter or failed, writing their labels.  Their ADMM state stays resident on the device between steps.
  * Every request's result is the one it gets when solved alone.  All requests of a server share connectivity;
  * the solver of each request resolves as in dope_set_energy_async.  A server is not thread-safe. */
 typedef struct dope_server dope_server;
@@ -264,7 +265,8 @@ typedef struct dope_server dope_server;
 typedef struct {
     size_t hbm_budget;         /* bytes of device memory for request workspaces                           */
     int32_t max_active;        /* most requests admitted at once                                          */
-    int32_t pad;
+    int32_t iters_per_step;    /* batched iterations per dope_server_step (0 = 1; at most 1024): fewer
+                                  host round trips and membership changes, later admission               */
     void *stream;              /* hipStream_t; NULL = the server creates its own                          */
 } dope_server_params;
 
@@ -276,7 +278,7 @@ dope_status dope_server_create(const dope_server_params *sp, dope_server **out);
 dope_status dope_server_submit(dope_server *s, const dope_params *p, const int32_t *u, const int32_t *w,
                                int32_t lambda_q8, int32_t mem_kind, uint8_t *labels_out, int32_t labels_mem_kind,
                                int64_t *ticket);
-/* One tick (admit, one batched iteration, retire).  The tickets finished during the tick are written to
+/* One tick (admit, iters_per_step batched iterations, retire).  The tickets finished during the tick are written to
  * finished (at most max_finished; *n_finished receives their number).  Labels written to device memory are
  * ordered on the server stream; to host memory they are complete on return. */
 dope_status dope_server_step(dope_server *s, int64_t *finished, int32_t max_finished, int32_t *n_finished);

@@ -36,7 +36,7 @@ class dope_params(ctypes.Structure):
 
 
 class dope_server_params(ctypes.Structure):
-    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int32), ("pad", ctypes.c_int32),
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int32), ("iters_per_step", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 

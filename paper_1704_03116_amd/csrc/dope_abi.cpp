@@ -1416,6 +1416,7 @@ struct SrvReq {
 struct dope_server {
     size_t budget = 0;
     int32_t max_active = 0;
+    int32_t iters = 1;   // batched iterations per step
     hipStream_t stream = nullptr;
     bool own_stream = false;
     char *arena = nullptr;
@@ -1487,12 +1488,15 @@ void srv_retire(dope_server *s, SrvReq *r, int32_t status) {
 extern "C" {
 
 dope_status dope_server_create(const dope_server_params *sp, dope_server **out) {
-    if (!sp || !out || sp->hbm_budget == 0 || sp->max_active <= 0) return DOPE_EINVAL;
+    if (!sp || !out || sp->hbm_budget == 0 || sp->max_active <= 0 || sp->iters_per_step < 0 ||
+        sp->iters_per_step > 1024)
+        return DOPE_EINVAL;
     *out = nullptr;
     dope_server *s = new (std::nothrow) dope_server();
     if (!s) return DOPE_ENOMEM;
     s->budget = sp->hbm_budget & ~size_t(255);
     s->max_active = sp->max_active;
+    s->iters = sp->iters_per_step > 0 ? sp->iters_per_step : 1;
     if (sp->stream) {
         s->stream = static_cast<hipStream_t>(sp->stream);
     } else {
@@ -1597,7 +1601,9 @@ dope_status dope_server_step(dope_server *s, int64_t *finished, int32_t max_fini
         if (st != DOPE_OK) return sfail(s, st, b->err);
         s->dirty = false;
     }
-    dope_status st = batch_run_iteration(b);
+    // the step's iterations back to back; requests that halt among them are skipped on the device
+    dope_status st = DOPE_OK;
+    for (int32_t it = 0; it < s->iters && st == DOPE_OK; ++it) st = batch_run_iteration(b);
     if (st == DOPE_OK) st = batch_sync(b);
     if (st != DOPE_OK) return sfail(s, st, b->err);
     // retire

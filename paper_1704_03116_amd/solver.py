@@ -334,12 +334,13 @@ class Batch:
 
 
 class Server:
-    """A dope_server: FIFO admission by HBM footprint, one batched iteration per step()."""
+    """A dope_server: FIFO admission by HBM footprint, iters_per_step batched iterations per step()."""
 
-    def __init__(self, hbm_budget, max_active):
+    def __init__(self, hbm_budget, max_active, iters_per_step=1):
         sp = N.dope_server_params()
         sp.hbm_budget = int(hbm_budget)
         sp.max_active = int(max_active)
+        sp.iters_per_step = int(iters_per_step)
         sp.stream = None
         s = ctypes.c_void_p()
         st = N.dope_server_create(ctypes.byref(sp), ctypes.byref(s))

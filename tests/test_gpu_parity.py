@@ -833,17 +833,18 @@ def _serve_requests():
     return reqs
 
 
-def test_serving_mix_equals_alone():
+@pytest.mark.parametrize("iters_per_step", [1, 3])
+def test_serving_mix_equals_alone(iters_per_step):
     import torch
     from paper_1704_03116_amd.solver import Server, params_from_problem
     reqs = _serve_requests()
-    announce(f"serving {len(reqs)} requests, staggered submission")
+    announce(f"serving {len(reqs)} requests, staggered submission, {iters_per_step} iterations per step")
     outs = [torch.zeros(p.n, dtype=torch.uint8, device="cuda") for p in reqs]
     ins = [(torch.from_numpy(np.ascontiguousarray(p.u)).cuda(), torch.from_numpy(np.ascontiguousarray(p.w)).cuda())
            for p in reqs]
     torch.cuda.synchronize()
     done, tickets = {}, {}
-    with Server(hbm_budget=64 << 20, max_active=5) as srv:
+    with Server(hbm_budget=64 << 20, max_active=5, iters_per_step=iters_per_step) as srv:
         nxt = 0
         for tick in range(200):
             if nxt < len(reqs) and tick % 2 == 0:            # a request arrives every other tick
