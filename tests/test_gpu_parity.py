@@ -623,6 +623,18 @@ def test_blocks_beyond_lds_smoothing_dominated_flow():
         assert int(stats[0][:, 0].sum()) > 0 and int(stats[0][:, 1].sum()) > 0 and int(stats[0][:, 2].sum()) > 0
 
 
+@pytest.mark.parametrize("conn,dims,block,overlap", [(8, (40, 30, 1), (2, 2, 1), (1, 1, 0)),
+                                                     (6, (14, 12, 10), (2, 2, 2), (1, 1, 1))],
+                         ids=["8-connected 2x2 blocks", "6-connected 2x2x2 blocks"])
+def test_tiny_blocks_every_iteration(conn, dims, block, overlap):
+    """Blocks of 2 pixels per axis overlapping by 1: every pixel is a boundary pixel owned by its own block, so a
+    256-pixel consensus chunk spans far more owner blocks than it keeps residual slots for in LDS and most residuals
+    go to the global sums directly.  Whole state equal to the oracle's after every iteration."""
+    p = synth.random_problem(29, dims, conn, block, overlap)
+    d, _, _ = run_parity(p, 4, f"tiny blocks conn={conn}")
+    d.close()
+
+
 # blocks whose per-node arrays alone exceed the LDS too (9 + m bytes per node: 16384-pixel blocks with the 3x3
 # stencils, 16^3 blocks of the radius-4 ball), so the whole max-flow state stays in the workspace
 GLOBAL_STATE_CASES = [
