@@ -433,7 +433,6 @@ __device__ __forceinline__ void unary_loads(const Geom &g, const GLOBAL int32_t 
     const uint32_t i = uint32_t(gx) + uint32_t(g.W) * (uint32_t(gy) + uint32_t(g.H) * uint32_t(gz));
     const uint32_t bi = i << 2;
     ld.ing = inside_mask<CONN>(gx, gy, gz, g.W, g.H, g.D);
-    ld.u = ld_at(u, bi);
     ld.Y = ld_at(Y, bi);
     ld.a = ld_at(A, ci << 2);
 DOPE_UNROLL
@@ -446,6 +445,9 @@ DOPE_UNROLL
         ld.cv[d] = ld_at(cwo, d < H ? bi : bj);
         ld.yj[d] = ld_at(Y, bj);
     }
+    // last: under register pressure the compiler reloads this base from the kernel arguments inside the pixel
+    // loop, and the wait for that reload then holds back only this gather
+    ld.u = ld_at(u, bi);
     // 3D (four voxels per thread, four wavefronts per SIMD): an optimisation barrier makes every value wait
     // until all loads are issued, so the compiler cannot wait for one gather before issuing the next (measured
     // 10 % faster there; in 2D, with two wavefronts per SIMD, the compiler's interleaving is faster)
