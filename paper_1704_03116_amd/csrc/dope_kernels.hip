@@ -1811,6 +1811,11 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     constexpr int NDIM = Sten<CONN>::NDIM;
     constexpr int MAXC = 1 << NDIM;   // most blocks a pixel can lie in
     const Geom &g = im.g;
+    const int tid = threadIdx.x;
+    // the boundary-list record first: every gather of the pixel waits on it, the loop control does not
+    const int64_t li = int64_t(chunk) * CONS_NT + tid;
+    const bool in_list = li < im.n_blist;
+    const uint64_t rec = in_list ? gp(reinterpret_cast<const uint64_t *>(im.blist))[li] : 0;
     const GLOBAL Ctl *ctl = gp(im.ctl);
     if (!spec && ctl_skip(im.ctl)) return;
     // speculative chunk: the loop control is read here but only the stores wait for it
@@ -1821,7 +1826,6 @@ __device__ __forceinline__ void consensus_chunk(const Img &im, int chunk, int pa
     __shared__ unsigned long long s_res[CONS_SPAN * MAXC];
     __shared__ unsigned long long s_tr[CONS_NT / 64][MAXC][64];   // per wavefront: residual of copy q by lane
     __shared__ int s_ovf;
-    const int tid = threadIdx.x;
     if (par < 0) par = ctl->t & 1;
     const GLOBAL int32_t *Ain = gp(par ? im.A1 : im.A0);
     GLOBAL int32_t *Aout = gp(par ? im.A0 : im.A1);
@@ -1833,17 +1837,16 @@ DOPE_UNROLL
     for (int q = 0; q < CONS_SPAN * MAXC / CONS_NT; ++q) s_res[q * CONS_NT + tid] = 0;
     if (tid == 0) s_ovf = 0;
     __syncthreads();
-    const int64_t li = int64_t(chunk) * CONS_NT + tid;
     int ovf = 0;
     int kk = kfirst;
     unsigned long long r2[MAXC];
 DOPE_UNROLL
     for (int q = 0; q < MAXC; ++q) r2[q] = 0;
-    if (li < im.n_blist) {
-        // the owner copy and its block; the coordinates follow from the closed-form block layout
-        const GLOBAL int32_t *rec = gp(reinterpret_cast<const int32_t *>(im.blist)) + 2 * li;
-        const int32_t c = rec[0];
-        kk = rec[1];
+    if (in_list) {
+        // the owner copy and its block (the record's two int32, copy first); the coordinates follow from the
+        // closed-form block layout
+        const int32_t c = int32_t(uint32_t(rec));
+        kk = int32_t(uint32_t(rec >> 32));
         int kx, ky;
         const int kyz = qdiv(kk, AX.nb, AX.inv_nb, kx);
         const int kz = qdiv(kyz, AY.nb, AY.inv_nb, ky);
