@@ -3,10 +3,11 @@
 //   k_setup             energy upload: copy of u, c_ij = lambda w 64 / (q_i q_j) with validation bits, initial
 //                       state (Y = 1/2, A = 0) and loop control.
 //   k_block_solve*      one workgroup per block: Eq. (8) unaries from Theorem 1's coupling terms, strictly forced
-//                       nodes, forced-node elimination, push-relabel max preflow in LDS, canonical minimal cut ->
-//                       yhat_k; Eq. (10)/(11) for the pixels interior to their block.  Variants: one image
-//                       (descriptor as kernel argument), a batch (one workgroup per item), a batch over a
-//                       persistent work queue.
+//                       nodes, forced-node elimination, push-relabel max preflow in LDS with breadth-first global
+//                       relabels, canonical minimal cut -> yhat_k; Eq. (10)/(11) for the pixels interior to their
+//                       block.  Variants: one image (descriptor as kernel argument, full blocks dispatched
+//                       first), a batch (one workgroup per item), a batch over a persistent work queue, and one
+//                       image with blocks beyond the LDS (edge arrays, or the whole state, in the workspace).
 //   k_block_exhaustive  one wavefront per block of <= 16 pixels: Gray-code enumeration of all labellings,
 //                       smallest-code minimiser (any sign of the pairwise weights).
 //   k_block_lsatr       one workgroup per non-submodular block that fits the LDS: trust-region local submodular
@@ -18,8 +19,8 @@
 //   k_build_blist       the consensus work list (owner copies of the pixels not interior to their block).
 //   k_setup_batch, k_labels_batch, k_batch_setup, k_ctl_setup: the same set-up and outputs over a batch.
 //
-// Every kernel is a template over the stencil (CONN): 4- and 8-connected, 5x5 and 7x7 squares in 2D; 6-connected
-// and the radius-2 ball in 3D.  All arithmetic is integer; every kernel checks the device loop control, so the
+// Every kernel is a template over the stencil (CONN): 4- and 8-connected, 5x5, 7x7 and 9x9 squares in 2D;
+// 6-connected and the radius-2, -3 and -4 balls in 3D.  All arithmetic is integer; every kernel checks the device loop control, so the
 // host can enqueue several iterations ahead of the stopping rule without reading anything back.
 #include "dope_internal.h"
 
