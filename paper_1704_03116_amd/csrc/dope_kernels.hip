@@ -812,19 +812,86 @@ DOPE_UNROLL
     }
 }
 
+// The same elimination for lists longer than the registers hold, B list entries per thread at a time: the
+// entries' state, masks, unaries, capacities and neighbour states are all loaded before any of them is tested,
+// so the loads of a batch overlap (with the capacities in global memory, one round trip per batch instead of one
+// per entry).  A test may then miss a neighbour fixed earlier in the same batch; the sweep that follows sees it,
+// as it sees any other update, and the fixed point is the same.
+template <int CONN, class Sync, int B>
+__device__ __forceinline__ bool eliminate_batched(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs) {
+    constexpr int ND = 2 * Sten<CONN>::H;
+    for (;;) {
+        int ch = 0;
+        for (;;) {
+            int wch = 0;
+            for (int i0 = sy.idx; i0 < nfree; i0 += B * sy.step) {
+                int pb[B];
+                int32_t ub[B], cb[B][ND];
+                uint8_t sv[B][ND];
+DOPE_UNROLL
+                for (int j = 0; j < B; ++j) {
+                    const int i = i0 + j * sy.step;
+                    pb[j] = i < nfree ? int(L.lst[i]) : -1;
+                }
+DOPE_UNROLL
+                for (int j = 0; j < B; ++j) {
+                    const int p = pb[j];
+                    const bool live = p >= 0 && !(L.st[p] & ST_FIXED);
+                    const DirMask<CONN> m = live ? DirMask<CONN>(L.msk[p]) : DirMask<CONN>(0);
+                    ub[j] = live ? L.dd[p] : 0;
+                    if (!live) pb[j] = -1;
+DOPE_UNROLL
+                    for (int d = 0; d < ND; ++d) {
+                        const bool on = (m >> d) & 1u;
+                        cb[j][d] = on ? L.capd(p, d) : 0;
+                        sv[j][d] = on ? L.st[L.nbr(p, d)] : uint8_t(0);
+                    }
+                }
+DOPE_UNROLL
+                for (int j = 0; j < B; ++j) {
+                    const int p = pb[j];
+                    if (p < 0) continue;
+                    int32_t U = ub[j], S = 0;
+DOPE_UNROLL
+                    for (int d = 0; d < ND; ++d) {
+                        const int32_t c = cb[j][d];
+                        if (sv[j][d] & ST_FIXED) U += (sv[j][d] & ST_LABEL) ? -c : c;
+                        else S += c;
+                    }
+                    if (U < -S) { L.st[p] = ST_FIXED | ST_LABEL; wch |= 1; }
+                    else if (U > S) { L.st[p] = ST_FIXED; wch |= 1; }
+                    else wch |= 2;
+                }
+            }
+            if (!__any(wch & 1)) {
+                ch |= wch;
+                break;
+            }
+            ch |= wch & 1;
+        }
+        ++fs.casc;
+        const int r = sy.bits(ch);
+        if (!(r & 1)) return (r & 2) != 0;
+    }
+}
+
 // Elimination, with the register-held variant when every thread has at most MAXPT list entries and the stencil
 // has at most eight directions.  MAXPT is fixed per kernel (registers are allocated for the whole kernel): 4 for
-// 1024-thread workgroups (16^3 blocks), 2 for 512 (32x32), 1 for 256 and for a single wavefront.
-template <int CONN, int MAXPT, class Sync>
+// 1024-thread workgroups (16^3 blocks), 2 for 512 (32x32), 1 for 256 and for a single wavefront.  Longer lists
+// with such a stencil take the batched variant (B > 0 entries per thread at a time).
+template <int CONN, int MAXPT, class Sync, int B = 0>
 __device__ __forceinline__ bool eliminate_fast(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs) {
     if constexpr (2 * Sten<CONN>::H <= 8) {
         if (nfree <= MAXPT * sy.step) return eliminate_cached<CONN, Sync, MAXPT>(sy, L, nfree, fs);
+        if constexpr (B > 0) return eliminate_batched<CONN, Sync, B>(sy, L, nfree, fs);
     }
     return eliminate<CONN>(sy, L, nfree, fs);
 }
 
 template <int NT>
 constexpr int elim_regs() { return NT >= 1024 ? 4 : (NT >= 512 ? 2 : 1); }
+// list entries per thread loaded together by the batched elimination of the global-memory variant
+constexpr int ELIM_BATCH = 4;
 
 // Keeps the list entries that are still free (order not preserved); returns their count.  The height array,
 // not yet in use, holds the survivors by list position in between.  Whole workgroup; ctr is a zeroed LDS slot.
@@ -1191,7 +1258,7 @@ DOPE_UNROLL
         }
     } else if (nfree > 0) {
         BlockSync sy{tid, NT, s_ctr + 2, 0};
-        if (eliminate_fast<CONN, elim_regs<NT>()>(sy, L, nfree, fs)) {
+        if (eliminate_fast<CONN, elim_regs<NT>(), BlockSync, REGLIST ? 0 : ELIM_BATCH>(sy, L, nfree, fs)) {
             // the flow phases only visit the nodes the elimination left free; few enough go to one wavefront
             const int nleft = compact_free<CONN>(L, nfree, s_ctr + 8, tid, NT);
             if (nleft <= WAVE_FLOW_MAX) {
