@@ -815,11 +815,18 @@ DOPE_UNROLL
 // The same elimination for lists longer than the registers hold, B list entries per thread at a time: the
 // entries' state, masks, unaries, capacities and neighbour states are all loaded before any of them is tested,
 // so the loads of a batch overlap (with the capacities in global memory, one round trip per batch instead of one
-// per entry).  A test may then miss a neighbour fixed earlier in the same batch; the sweep that follows sees it,
-// as it sees any other update, and the fixed point is the same.
+// per entry).  A test may then miss a neighbour fixed earlier in the same batch; a later sweep sees it, as it sees
+// any other update, and the fixed point is the same.
+// Only nodes with a neighbour fixed since their last test can change, so a node is tested again only when its
+// flag in the height array (unused until the flow phases) is set: every listed node starts flagged, and fixing a
+// node flags its in-block neighbours.  A flag set while its node is being tested may be lost; so a pass without
+// changes is followed by one that tests every free node, and only a full pass without changes ends the loop.
 template <int CONN, class Sync, int B>
 __device__ __forceinline__ bool eliminate_batched(Sync &sy, BlockLds<CONN> &L, int nfree, FlowStats &fs) {
     constexpr int ND = 2 * Sten<CONN>::H;
+    for (int i = sy.idx; i < nfree; i += sy.step) L.hh[L.lst[i]] = 1;
+    sy.sync();
+    bool full = false;
     for (;;) {
         int ch = 0;
         for (;;) {
@@ -828,6 +835,7 @@ __device__ __forceinline__ bool eliminate_batched(Sync &sy, BlockLds<CONN> &L, i
                 int pb[B];
                 int32_t ub[B], cb[B][ND];
                 uint8_t sv[B][ND];
+                DirMask<CONN> mb[B];
 DOPE_UNROLL
                 for (int j = 0; j < B; ++j) {
                     const int i = i0 + j * sy.step;
@@ -836,8 +844,10 @@ DOPE_UNROLL
 DOPE_UNROLL
                 for (int j = 0; j < B; ++j) {
                     const int p = pb[j];
-                    const bool live = p >= 0 && !(L.st[p] & ST_FIXED);
+                    const bool live = p >= 0 && !(L.st[p] & ST_FIXED) && (full || L.hh[p] != 0);
+                    if (live) L.hh[p] = 0;
                     const DirMask<CONN> m = live ? DirMask<CONN>(L.msk[p]) : DirMask<CONN>(0);
+                    mb[j] = m;
                     ub[j] = live ? L.dd[p] : 0;
                     if (!live) pb[j] = -1;
 DOPE_UNROLL
@@ -858,9 +868,18 @@ DOPE_UNROLL
                         if (sv[j][d] & ST_FIXED) U += (sv[j][d] & ST_LABEL) ? -c : c;
                         else S += c;
                     }
-                    if (U < -S) { L.st[p] = ST_FIXED | ST_LABEL; wch |= 1; }
-                    else if (U > S) { L.st[p] = ST_FIXED; wch |= 1; }
-                    else wch |= 2;
+                    uint8_t fx = 0;
+                    if (U < -S) fx = ST_FIXED | ST_LABEL;
+                    else if (U > S) fx = ST_FIXED;
+                    if (fx) {
+                        L.st[p] = fx;
+                        wch |= 1;
+DOPE_UNROLL
+                        for (int d = 0; d < ND; ++d)
+                            if ((mb[j] >> d) & 1u) L.hh[L.nbr(p, d)] = 1;
+                    } else {
+                        wch |= 2;
+                    }
                 }
             }
             if (!__any(wch & 1)) {
@@ -871,7 +890,13 @@ DOPE_UNROLL
         }
         ++fs.casc;
         const int r = sy.bits(ch);
-        if (!(r & 1)) return (r & 2) != 0;
+        if (r & 1) {
+            full = false;
+        } else {
+            // bit 1 is exact only when the pass tested every free node
+            if (full) return (r & 2) != 0;
+            full = true;
+        }
     }
 }
 
@@ -890,8 +915,82 @@ __device__ __forceinline__ bool eliminate_fast(Sync &sy, BlockLds<CONN> &L, int 
 
 template <int NT>
 constexpr int elim_regs() { return NT >= 1024 ? 4 : (NT >= 512 ? 2 : 1); }
+
+// Forced-node elimination over the nodes p0 <= p < p1 of a block only, for the workgroups of k_block_prep_gmem that
+// share a block: the neighbours outside the slice count as free (their capacities and states belong to another
+// workgroup).  That only weakens the test -- a fixed neighbour moves its capacity from the free total into the
+// unary -- so every node fixed here is fixed by the whole block's elimination as well, which then starts from
+// these states and reaches the same fixed point.  s_lst / s_sum: the slice's list (nf entries, at most MAXPT per
+// thread) and each entry's total in-block capacity; s_st: the slice's states (index p - p0).  The entries, their
+// unaries and the capacities towards the slice are held in registers across sweeps, as in eliminate_cached.
+template <int CONN, int MAXPT>
+__device__ __forceinline__ void eliminate_slice(BlockSync &sy, const BlockLds<CONN> &G, uint8_t *s_st,
+                                                const int16_t *s_lst, const int32_t *s_sum, int nf, int p0, int p1) {
+    constexpr int ND = 2 * Sten<CONN>::H;
+    int pn[MAXPT];
+    int32_t ub[MAXPT], sb[MAXPT];
+    int32_t cb[MAXPT][ND];   // capacity towards in-slice neighbours, 0 otherwise
+DOPE_UNROLL
+    for (int j = 0; j < MAXPT; ++j) {
+        const int i = sy.idx + j * sy.step;
+        pn[j] = -1;
+        ub[j] = 0;
+        sb[j] = 0;
+DOPE_UNROLL
+        for (int d = 0; d < ND; ++d) cb[j][d] = 0;
+        if (i < nf) {
+            const int p = s_lst[i];
+            const DirMask<CONN> m = G.msk[p];
+            pn[j] = p;
+            ub[j] = G.dd[p];
+            sb[j] = s_sum[i];
+DOPE_UNROLL
+            for (int d = 0; d < ND; ++d) {
+                const int q = G.nbr(p, d);
+                cb[j][d] = (((m >> d) & 1u) && q >= p0 && q < p1) ? G.capd(p, d) : 0;
+            }
+        }
+    }
+    for (;;) {
+        int ch = 0;
+        for (;;) {
+            int wch = 0;
+DOPE_UNROLL
+            for (int j = 0; j < MAXPT; ++j) {
+                const int p = pn[j];
+                if (p < 0) continue;
+                uint8_t sv[ND];
+DOPE_UNROLL
+                for (int d = 0; d < ND; ++d) sv[d] = s_st[(cb[j][d] ? G.nbr(p, d) : p) - p0];   // p for the rest
+                int32_t U = ub[j], S = sb[j];
+DOPE_UNROLL
+                for (int d = 0; d < ND; ++d) {
+                    const int32_t c = cb[j][d];
+                    if (sv[d] & ST_FIXED) {
+                        U += (sv[d] & ST_LABEL) ? -c : c;
+                        S -= c;
+                    }
+                }
+                if (U < -S) { s_st[p - p0] = ST_FIXED | ST_LABEL; pn[j] = -1; wch |= 1; }
+                else if (U > S) { s_st[p - p0] = ST_FIXED; pn[j] = -1; wch |= 1; }
+                else wch |= 2;
+            }
+            if (!__any(wch & 1)) {
+                ch |= wch;
+                break;
+            }
+            ch |= wch & 1;
+        }
+        if (!(sy.bits(ch) & 1)) return;
+    }
+}
+
 // list entries per thread loaded together by the batched elimination of the global-memory variant
 constexpr int ELIM_BATCH = 4;
+// The two-launch global-memory solve (k_block_prep_gmem): at most PREP_SLICE_MAX nodes per slice and
+// PREP_SLICES_MAX slices per block (their free counts fill int32 slots 1..8 of the block region's header).
+constexpr int PREP_SLICE_MAX = 4096;
+constexpr int PREP_SLICES_MAX = 8;
 
 // Keeps the list entries that are still free (order not preserved); returns their count.  The height array,
 // not yet in use, holds the survivors by list position in between.  Whole workgroup; ctr is a zeroed LDS slot.
@@ -1139,66 +1238,65 @@ constexpr int WAVE_FLOW_MAX = 64;
 // of the block solve that a kernel inlines (a function-scope array would be allocated once per variant).
 __shared__ uint16_t s_lq_rows[3][LQ_TAB];
 
-// par: multiplier buffer parity (t & 1), or -1 to read it from the loop control.  spec: the caller has not
-// checked the loop control; the gathers are issued first and the block stops before its first global store when
-// the iteration is skipped.  REGLIST: the flow phases may hold the thread's list entries in registers (the
-// global-memory variant, short of registers already, reads them from the list).  SPLIT: the per-edge arrays
-// (capacities and flows) live at gedge + 64 in global memory and only the per-node arrays in smem; otherwise the
-// whole state lives in smem (the maxflow_lds_bytes layout).
-template <int CONN, int NT, bool REGLIST = true, bool SPLIT = false>
-__device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned char *smem, int32_t npmax,
-                                              int32_t round_limit, int32_t relabel_period, int par, bool spec,
-                                              unsigned char *gedge = nullptr) {
+// The per-node arrays of the maxflow_lds_bytes layout, starting noff bytes into base: unary / excess (4 B),
+// height (2), free list (2), then the direction masks aligned to their size, then the state bytes.
+template <int CONN>
+__device__ __forceinline__ void bind_nodes(BlockLds<CONN> &L, unsigned char *base, size_t noff) {
+    L.dd = reinterpret_cast<int32_t *>(base + noff);
+    L.hh = reinterpret_cast<int16_t *>(L.dd + L.npmax);
+    L.lst = L.hh + L.npmax;
+    constexpr size_t MB = sizeof(LdsMask<CONN>);
+    const size_t mo = noff + size_t(L.npmax) * 8;
+    L.msk = reinterpret_cast<LdsMask<CONN> *>(base + ((mo + MB - 1) & ~(MB - 1)));
+    L.st = reinterpret_cast<uint8_t *>(L.msk + L.npmax);
+}
+
+// Block k of the partition (closed form, no table load on the critical path) and its multiplier input.
+struct BlockAt {
+    int kx, ky, kz, x0, y0, z0, ex, ey, ez, np;
+    int64_t off, M;
+    double inv_ex, inv_ey;
+    const GLOBAL int32_t *Ain;
+};
+
+__device__ __forceinline__ BlockAt block_place(const Img &im, int k, int parity) {
+    const Geom &g = im.g;
+    BlockAt b;
+    b.kx = k % g.ax[0].nb;
+    b.ky = (k / g.ax[0].nb) % g.ax[1].nb;
+    b.kz = k / (g.ax[0].nb * g.ax[1].nb);
+    b.x0 = b.kx * g.ax[0].s;
+    b.y0 = b.ky * g.ax[1].s;
+    b.z0 = b.kz * g.ax[2].s;
+    b.ex = axis_ext(g.ax[0], b.kx);
+    b.ey = axis_ext(g.ax[1], b.ky);
+    b.ez = axis_ext(g.ax[2], b.kz);
+    b.off = block_offset(g, b.kx, b.ky, b.kz);
+    b.np = b.ex * b.ey * b.ez;
+    b.Ain = gp(parity ? im.A1 : im.A0);
+    b.M = gp(im.ctl)->M;
+    b.inv_ex = axis_inv_ext(g.ax[0], b.kx);
+    b.inv_ey = axis_inv_ext(g.ax[1], b.ky);
+    return b;
+}
+
+// Prologue of the block solve over the block's nodes pbeg <= p < pend: Eq. (8) unaries, in-block capacities,
+// strictly forced nodes (state, mask and unary into L's arrays), and the others appended to flst through the
+// counter fctr.  fsum (when not null) receives each listed node's total in-block capacity at its list position,
+// sst (when not null) every node's state at index p - pbeg.  walk: the caller's coordinate walk, set to
+// pbeg + threadIdx.x with stride NT.
+template <int CONN, int NT>
+__device__ __forceinline__ void block_prologue(const Img &im, const BlockAt &b, BlockLds<CONN> &L, bool lq_tab,
+                                               uint16_t (*s_lq)[LQ_TAB], LocalWalk &walk, int pbeg, int pend,
+                                               int16_t *flst, int *fctr, int32_t *fsum, uint8_t *sst) {
     constexpr int H = Sten<CONN>::H;
     const Geom &g = im.g;
-    const GLOBAL Ctl *ctl = gp(im.ctl);
-    const int parity = par >= 0 ? par : (ctl->t & 1);
-    // block geometry from the closed-form partition (no table load on the critical path)
-    const int kx = k % g.ax[0].nb, ky = (k / g.ax[0].nb) % g.ax[1].nb, kz = k / (g.ax[0].nb * g.ax[1].nb);
-    const int x0 = kx * g.ax[0].s, y0 = ky * g.ax[1].s, z0 = kz * g.ax[2].s;
-    const int ex = axis_ext(g.ax[0], kx), ey = axis_ext(g.ax[1], ky), ez = axis_ext(g.ax[2], kz);
-    const int64_t off = block_offset(g, kx, ky, kz);
-    const int np = ex * ey * ez;
-    const GLOBAL int32_t *Ain = gp(parity ? im.A1 : im.A0);
-    const int64_t M = ctl->M;
-    const int tid = threadIdx.x;
-
-    // scalar slots 0..14: 1 free-list length, 2..4 barrier flags, 6..7 a 64-bit residual sum, 8 compaction count
-    int *s_ctr = reinterpret_cast<int *>(smem);
-    BlockLds<CONN> L;
-    L.npmax = npmax;
-    L.cap = reinterpret_cast<int32_t *>((SPLIT ? gedge : smem) + 64);
-    L.flw = L.cap + H * npmax;
-    // the node arrays follow the edge arrays, or start the LDS when the edge arrays are in global memory
-    const size_t noff = SPLIT ? 64 : 64 + size_t(npmax) * 8 * H;
-    L.dd = reinterpret_cast<int32_t *>(smem + noff);
-    L.hh = reinterpret_cast<int16_t *>(L.dd + npmax);
-    L.lst = L.hh + npmax;
-    {
-        // the mask array follows the free list, aligned to its element size (maxflow_lds_bytes counts the slack)
-        constexpr size_t MB = sizeof(LdsMask<CONN>);
-        const size_t mo = noff + size_t(npmax) * 8;
-        L.msk = reinterpret_cast<LdsMask<CONN> *>(smem + ((mo + MB - 1) & ~(MB - 1)));
-    }
-    L.st = reinterpret_cast<uint8_t *>(L.msk + npmax);
-DOPE_UNROLL
-    for (int o = 0; o < H; ++o) {
-        const int3 v = half_off<CONN>(o);
-        L.loff[o] = v.x + ex * (v.y + ey * v.z);
-    }
-    // covers of the block's coordinates, once per block (blocks of at most LQ_TAB pixels per axis)
-    uint16_t (*s_lq)[LQ_TAB] = s_lq_rows;
-    const bool lq_tab = ex <= LQ_TAB && ey <= LQ_TAB && ez <= LQ_TAB;   // uniform
-    if (lq_tab) block_lq_rows<CONN, NT>(g, x0, y0, z0, ex, ey, ez, s_lq);
-    if (tid < 15) s_ctr[tid] = 0;
-    __syncthreads();
-
-    // ---- prologue: Eq. (8) unaries, in-block capacities, strictly forced nodes, list of the others ----
+    const int npmax = L.npmax;
+    const int x0 = b.x0, y0 = b.y0, z0 = b.z0, ex = b.ex, ey = b.ey, ez = b.ez;
+    const int64_t off = b.off, M = b.M;
+    const GLOBAL int32_t *Ain = b.Ain;
     const GLOBAL int32_t *gu = gp(im.u), *gcw = gp(im.cw), *gY = gp(im.Y);
-    const double inv_ex = axis_inv_ext(g.ax[0], kx), inv_ey = axis_inv_ext(g.ax[1], ky);
-    LocalWalk walk;
-    walk.init(tid, NT, ex, ey, inv_ex, inv_ey);
-    for (int p = tid; p < np; p += NT, walk.next()) {
+    for (int p = pbeg + int(threadIdx.x); p < pend; p += NT, walk.next()) {
         const int3 l = make_int3(walk.lx, walk.ly, walk.lz);
         DirMask<CONN> m;
         int64_t sumc;
@@ -1242,13 +1340,109 @@ DOPE_UNROLL
         if (Ut < -sumc) sbits = ST_FIXED | ST_LABEL;       // label 1 in every minimiser
         else if (Ut > sumc) sbits = ST_FIXED;              // label 0 in every minimiser
         L.st[p] = sbits;
+        if (sst) sst[p - pbeg] = sbits;
         L.msk[p] = LdsMask<CONN>(m);
         L.dd[p] = sbits ? 0 : int32_t(Ut);                 // |Ut| <= sumc < 2^29 for free nodes
-        if (!sbits) L.lst[atomicAdd(&s_ctr[1], 1)] = int16_t(p);
+        if (!sbits) {
+            const int at = atomicAdd(fctr, 1);
+            flst[at] = int16_t(p);
+            if (fsum) fsum[at] = int32_t(sumc);
+        }
+    }
+}
+
+// par: multiplier buffer parity (t & 1), or -1 to read it from the loop control.  spec: the caller has not
+// checked the loop control; the gathers are issued first and the block stops before its first global store when
+// the iteration is skipped.  REGLIST: the flow phases may hold the thread's list entries in registers (the
+// global-memory variant, short of registers already, reads them from the list).  SPLIT: the per-edge arrays
+// (capacities and flows) live at gedge + 64 in global memory and only the per-node arrays in smem; otherwise the
+// whole state lives in smem (the maxflow_lds_bytes layout).  STAGED (with SPLIT): k_block_prep_gmem has run the
+// prologue and a first elimination already and left the whole maxflow_lds_bytes layout at gedge; the block copies
+// the node arrays into smem and lists the nodes still free instead of running the prologue.
+template <int CONN, int NT, bool REGLIST = true, bool SPLIT = false, bool STAGED = false>
+__device__ __forceinline__ void block_maxflow(const Img &im, int k, unsigned char *smem, int32_t npmax,
+                                              int32_t round_limit, int32_t relabel_period, int par, bool spec,
+                                              unsigned char *gedge = nullptr) {
+    constexpr int H = Sten<CONN>::H;
+    static_assert(SPLIT || !STAGED, "the staged solve keeps its node arrays in smem");
+    const Geom &g = im.g;
+    const GLOBAL Ctl *ctl = gp(im.ctl);
+    const int parity = par >= 0 ? par : (ctl->t & 1);
+    // block geometry from the closed-form partition (no table load on the critical path)
+    const int kx = k % g.ax[0].nb, ky = (k / g.ax[0].nb) % g.ax[1].nb, kz = k / (g.ax[0].nb * g.ax[1].nb);
+    const int x0 = kx * g.ax[0].s, y0 = ky * g.ax[1].s, z0 = kz * g.ax[2].s;
+    const int ex = axis_ext(g.ax[0], kx), ey = axis_ext(g.ax[1], ky), ez = axis_ext(g.ax[2], kz);
+    const int64_t off = block_offset(g, kx, ky, kz);
+    const int np = ex * ey * ez;
+    const GLOBAL int32_t *Ain = gp(parity ? im.A1 : im.A0);
+    const int64_t M = ctl->M;
+    const int tid = threadIdx.x;
+
+    // scalar slots 0..14: 1 free-list length, 2..4 barrier flags, 6..7 a 64-bit residual sum, 8 compaction count
+    int *s_ctr = reinterpret_cast<int *>(smem);
+    BlockLds<CONN> L;
+    L.npmax = npmax;
+    L.cap = reinterpret_cast<int32_t *>((SPLIT ? gedge : smem) + 64);
+    L.flw = L.cap + H * npmax;
+    // the node arrays follow the edge arrays, or start the LDS when the edge arrays are in global memory
+    bind_nodes<CONN>(L, smem, SPLIT ? 64 : 64 + size_t(npmax) * 8 * H);
+DOPE_UNROLL
+    for (int o = 0; o < H; ++o) {
+        const int3 v = half_off<CONN>(o);
+        L.loff[o] = v.x + ex * (v.y + ey * v.z);
+    }
+    // covers of the block's coordinates, once per block (blocks of at most LQ_TAB pixels per axis)
+    uint16_t (*s_lq)[LQ_TAB] = s_lq_rows;
+    const bool lq_tab = !STAGED && ex <= LQ_TAB && ey <= LQ_TAB && ez <= LQ_TAB;   // uniform
+    if (lq_tab) block_lq_rows<CONN, NT>(g, x0, y0, z0, ex, ey, ez, s_lq);
+    if (tid < 15) s_ctr[tid] = 0;
+    __syncthreads();
+
+    const double inv_ex = axis_inv_ext(g.ax[0], kx), inv_ey = axis_inv_ext(g.ax[1], ky);
+    LocalWalk walk;
+    int nfree_stat = 0;   // free nodes after the prologue's forcing test (the statistics' count)
+    if constexpr (STAGED) {
+        // ---- the prologue kernel's node arrays into smem; list of the nodes its elimination left free ----
+        // (four nodes per thread loaded before any is stored, so that their global loads overlap)
+        BlockLds<CONN> G = L;
+        bind_nodes<CONN>(G, gedge, 64 + size_t(npmax) * 8 * H);
+        constexpr int CP = 4;
+        for (int p0 = tid; p0 < np; p0 += CP * NT) {
+            uint8_t sb[CP];
+            LdsMask<CONN> mb[CP];
+            int32_t db[CP];
+DOPE_UNROLL
+            for (int j = 0; j < CP; ++j) {
+                const int p = p0 + j * NT;
+                if (p < np) {
+                    sb[j] = G.st[p];
+                    mb[j] = G.msk[p];
+                    db[j] = G.dd[p];
+                }
+            }
+DOPE_UNROLL
+            for (int j = 0; j < CP; ++j) {
+                const int p = p0 + j * NT;
+                if (p < np) {
+                    L.st[p] = sb[j];
+                    L.msk[p] = mb[j];
+                    L.dd[p] = db[j];
+                    if (!(sb[j] & ST_FIXED)) L.lst[atomicAdd(&s_ctr[1], 1)] = int16_t(p);
+                }
+            }
+        }
+        const GLOBAL int32_t *hdr = gp(reinterpret_cast<const int32_t *>(gedge));
+        for (int s = 0; s < PREP_SLICES_MAX; ++s) nfree_stat += hdr[1 + s];
+    } else {
+        // ---- prologue: Eq. (8) unaries, in-block capacities, strictly forced nodes, list of the others ----
+        const BlockAt b{kx, ky, kz, x0, y0, z0, ex, ey, ez, np, off, M, inv_ex, inv_ey, Ain};
+        walk.init(tid, NT, ex, ey, inv_ex, inv_ey);
+        block_prologue<CONN, NT>(im, b, L, lq_tab, s_lq, walk, 0, np, L.lst, &s_ctr[1], nullptr, nullptr);
     }
     __syncthreads();
     if (spec && ctl_skip(im.ctl)) return;   // uniform: every thread reads the same loop control
     const int nfree = s_ctr[1];
+    if constexpr (!STAGED) nfree_stat = nfree;
 
     FlowStats fs{0, 0, 0, false};
     if (nfree > 0 && nfree <= WAVE_FLOW_MAX) {
@@ -1310,7 +1504,7 @@ DOPE_UNROLL
     if (tid == 0) {
         gp(im.resid)[k] = int64_t(*s_r2);    // the consensus kernel adds the other pixels of the block
         GLOBAL int32_t *st = gp(im.stats) + 4 * k;
-        st[0] = nfree;
+        st[0] = nfree_stat;
         st[1] = fs.rounds;
         st[2] = fs.grel;
         st[3] = fs.casc;
@@ -1397,6 +1591,79 @@ __global__ __launch_bounds__(NT, 2) void k_block_solve_gmem(const Img one, int32
         block_maxflow<CONN, NT, false, true>(one, k, smem, npmax, round_limit, relabel_period, par, false, mem);
     else
         block_maxflow<CONN, NT, false>(one, k, mem, npmax, round_limit, relabel_period, par, false);
+}
+
+// Blocks beyond the LDS with the 3x3 stencils, in two launches so that more than one CU works on each block's
+// prologue (a partition of 128 large blocks would otherwise leave half the CUs idle while its prologue and
+// elimination, most of the solve after the first iteration, run).  k_block_prep_gmem: workgroup w takes slice
+// w / nb (of nslice) of block w % nb, runs the prologue over the slice's nodes into the whole maxflow_lds_bytes
+// layout at the block's global region, then the elimination over the slice alone (eliminate_slice), and stores
+// the slice's states and its prologue free count (int32 slot 1 + slice of the region's 64-byte header).
+// k_block_flow_gmem then runs the rest of the block solve from that state, one workgroup per block.
+template <int CONN, int NT>
+__global__ __launch_bounds__(NT) void k_block_prep_gmem(const Img one, int32_t par, int32_t npmax,
+                                                      unsigned char *scratch, uint64_t stride, int32_t nb,
+                                                      int32_t nslice) {
+    constexpr int H = Sten<CONN>::H;
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (ctl_skip(one.ctl)) return;
+    const int w = blockIdx.x, bi = w % nb, sl = w / nb;
+    unsigned char *mem = scratch + uint64_t(bi) * stride;
+    const int k = block_at(one.g, bi);
+    const int parity = par >= 0 ? par : (gp(one.ctl)->t & 1);
+    const BlockAt b = block_place(one, k, parity);
+    const int p0 = int(int64_t(b.np) * sl / nslice), p1 = int(int64_t(b.np) * (sl + 1) / nslice);
+    const int tid = threadIdx.x;
+    // smem: 16 counters, the slice's list (int16) and capacity totals (int32), its states (bytes)
+    int *s_ctr = reinterpret_cast<int *>(smem);
+    int16_t *s_lst = reinterpret_cast<int16_t *>(smem + 64);
+    int32_t *s_sum = reinterpret_cast<int32_t *>(smem + 64 + 2 * PREP_SLICE_MAX);
+    uint8_t *s_st = smem + 64 + 6 * PREP_SLICE_MAX;
+    BlockLds<CONN> G;
+    G.npmax = npmax;
+    G.cap = reinterpret_cast<int32_t *>(mem + 64);
+    G.flw = G.cap + H * npmax;
+    bind_nodes<CONN>(G, mem, 64 + size_t(npmax) * 8 * H);
+DOPE_UNROLL
+    for (int o = 0; o < H; ++o) {
+        const int3 v = half_off<CONN>(o);
+        G.loff[o] = v.x + b.ex * (v.y + b.ey * v.z);
+    }
+    uint16_t (*s_lq)[LQ_TAB] = s_lq_rows;
+    const bool lq_tab = b.ex <= LQ_TAB && b.ey <= LQ_TAB && b.ez <= LQ_TAB;   // uniform
+    if (lq_tab) block_lq_rows<CONN, NT>(one.g, b.x0, b.y0, b.z0, b.ex, b.ey, b.ez, s_lq);
+    if (tid < 16) s_ctr[tid] = 0;
+    __syncthreads();
+    LocalWalk walk;
+    walk.init(p0 + tid, NT, b.ex, b.ey, b.inv_ex, b.inv_ey);
+    block_prologue<CONN, NT>(one, b, G, lq_tab, s_lq, walk, p0, p1, s_lst, &s_ctr[1], s_sum, s_st);
+    __syncthreads();   // the slice's capacities (global) and states are complete for the workgroup
+    const int nf = s_ctr[1];
+    if (tid == 0) {
+        GLOBAL int32_t *hdr = gp(reinterpret_cast<int32_t *>(mem));
+        hdr[1 + sl] = nf;
+        if (sl == 0)
+            for (int s = nslice; s < PREP_SLICES_MAX; ++s) hdr[1 + s] = 0;
+    }
+    if (nf == 0) return;   // uniform; the prologue stored every state of the slice
+    BlockSync sy{tid, NT, s_ctr + 2, 0};
+    eliminate_slice<CONN, PREP_SLICE_MAX / NT>(sy, G, s_st, s_lst, s_sum, nf, p0, p1);
+    __syncthreads();
+    for (int i = tid; i < nf; i += NT) {
+        const int p = s_lst[i];
+        G.st[p] = s_st[p - p0];
+    }
+}
+
+template <int CONN, int NT>
+__global__ __launch_bounds__(NT) void k_block_flow_gmem(const Img one, int32_t par, int32_t npmax,
+                                                      int32_t round_limit, int32_t relabel_period,
+                                                      unsigned char *scratch, uint64_t stride) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (ctl_skip(one.ctl)) return;
+    unsigned char *mem = scratch + uint64_t(blockIdx.x) * stride;
+    const int k = block_at(one.g, blockIdx.x);
+    block_maxflow<CONN, NT, false, true, true>(one, k, smem, npmax, round_limit, relabel_period, par, false, mem);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -2655,6 +2922,24 @@ hipError_t launch_maxflow(const Group &grp, hipStream_t s, hipEvent_t e0, hipEve
     return hipGetLastError();
 }
 
+// Slices per block of k_block_prep_gmem: at most PREP_SLICE_MAX nodes each, and as many as fill the last round of
+// workgroups best (one 1024-thread workgroup per CU at a time): 128 blocks of 11340 nodes take 4 slices (two full
+// rounds) rather than 3 (a round and a half).
+inline int32_t prep_slices(int32_t npmax, int32_t nb) {
+    const int32_t lo = (npmax + PREP_SLICE_MAX - 1) / PREP_SLICE_MAX;
+    int32_t best = lo;
+    double best_fill = 0.0;
+    for (int32_t n = lo; n <= PREP_SLICES_MAX; ++n) {
+        const int64_t wgs = int64_t(nb) * n;
+        const double fill = double(wgs) / double(((wgs + NUM_CUS - 1) / NUM_CUS) * NUM_CUS);
+        if (fill > best_fill + 1e-9) {
+            best = n;
+            best_fill = fill;
+        }
+    }
+    return best;
+}
+
 template <int CONN>
 hipError_t launch_maxflow_gmem(const Group &grp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     constexpr int NT = gmem_threads(CONN);
@@ -2674,6 +2959,37 @@ hipError_t launch_maxflow_gmem(const Group &grp, hipStream_t s, hipEvent_t e0, h
     const size_t node_lds = maxflow_node_lds_bytes(grp.npmax, Sten<CONN>::H);
     const int32_t split = node_lds <= MAXFLOW_LDS_LIMIT ? 1 : 0;
     const uint32_t lds = split ? uint32_t(node_lds) : 0u;
+    if constexpr (2 * Sten<CONN>::H <= 8) {
+        if (split) {
+            // two launches: slices of every block's prologue and elimination on several CUs, then the rest
+            static std::once_flag flow_once;
+            static hipError_t flow_err = hipSuccess;
+            std::call_once(flow_once, [] {
+                flow_err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_block_flow_gmem<CONN, NT>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(MAXFLOW_LDS_LIMIT));
+            });
+            if (flow_err != hipSuccess) return flow_err;
+            const int32_t nb = grp.n_blk_items;
+            const int32_t nslice = prep_slices(grp.npmax, nb);
+            if (nslice < 1 || nslice > PREP_SLICES_MAX || (grp.npmax + nslice - 1) / nslice > PREP_SLICE_MAX)
+                return hipErrorInvalidValue;
+            const uint32_t plds = uint32_t(64 + 7 * PREP_SLICE_MAX);
+            const dim3 pgrid(unsigned(nb) * unsigned(nslice));
+            if (e0) {
+                hipExtLaunchKernelGGL(k_block_prep_gmem<CONN, NT>, pgrid, dim3(NT), plds, s, e0, nullptr, 0u,
+                                      *grp.one, grp.par, grp.npmax, grp.gscratch, grp.gstride, nb, nslice);
+                hipExtLaunchKernelGGL(k_block_flow_gmem<CONN, NT>, grid, dim3(NT), lds, s, nullptr, e1, 0u,
+                                      *grp.one, grp.par, grp.npmax, round_limit, relabel_period, grp.gscratch,
+                                      grp.gstride);
+            } else {
+                hipLaunchKernelGGL((k_block_prep_gmem<CONN, NT>), pgrid, dim3(NT), plds, s, *grp.one, grp.par,
+                                   grp.npmax, grp.gscratch, grp.gstride, nb, nslice);
+                hipLaunchKernelGGL((k_block_flow_gmem<CONN, NT>), grid, dim3(NT), lds, s, *grp.one, grp.par,
+                                   grp.npmax, round_limit, relabel_period, grp.gscratch, grp.gstride);
+            }
+            return hipGetLastError();
+        }
+    }
     if (e0) hipExtLaunchKernelGGL(k_block_solve_gmem<CONN, NT>, grid, dim3(NT), lds, s, e0, e1, 0u, *grp.one, grp.par,
                                   grp.npmax, round_limit, relabel_period, grp.gscratch, grp.gstride, split);
     else hipLaunchKernelGGL((k_block_solve_gmem<CONN, NT>), grid, dim3(NT), lds, s, *grp.one, grp.par, grp.npmax,
