@@ -236,8 +236,13 @@ def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
     mb = dir_mask_bytes(h)
     state = 64 + np_max * (8 * h + 9 + mb) + (16 if mb > 8 else (8 if mb > 1 else 0))
     if p.solver != "exhaustive" and state > 160 * 1024 - 1024:
-        # blocks beyond the LDS: the same block solver with its max-flow state in global memory
-        kernels["k_block_solve_gmem"] = kernels.pop("k_block_solve_one")
+        # blocks beyond the LDS: the same block solver with its max-flow state in global memory; with the 3x3
+        # stencils and the node arrays in LDS, two launches (prologue and first elimination on several
+        # workgroups per block, then the rest), timed together
+        node_state = state - np_max * 8 * h
+        staged = p.conn in (4, 6, 8) and node_state <= 160 * 1024 - 1024
+        name = "k_block_prep_gmem+k_block_flow_gmem" if staged else "k_block_solve_gmem"
+        kernels[name] = kernels.pop("k_block_solve_one")
     if p.solver == "lsatr":
         # the LSA-TR block solve reads and writes what the max-flow block solve does (its steps stay in LDS)
         kernels["k_block_lsatr"] = kernels.pop("k_block_solve_one")
@@ -290,7 +295,8 @@ def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
             lds_total += lds_bytes_per_iteration(st, sizes, h)
             rounds_total += int(st[:, 1].sum())
             free_total += int(st[:, 0].sum())
-        amount, ms, launches = kernels[names[0]] if names[0].startswith("k_block_solve") else (0, 0.0, 0)
+        amount, ms, launches = (kernels[names[0]] if names[0].startswith(("k_block_solve", "k_block_prep_gmem"))
+                                else (0, 0.0, 0))
         avg_bytes = lds_total / max(info["iters_done"], 1)
         avg_ms = ms / max(min(working, launches), 1)
         ach = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
