@@ -240,7 +240,7 @@ def measure_plain(p, steps, warmup, lds_peak_gbs=None, lds_pass=False):
         # stencils and the node arrays in LDS, two launches (prologue and first elimination on several
         # workgroups per block, then the rest), timed together
         node_state = state - np_max * 8 * h
-        staged = p.conn in (4, 6, 8) and node_state <= 160 * 1024 - 1024
+        staged = p.conn in (4, 6, 8) and node_state <= 160 * 1024 - 1024 and np_max > 8192
         name = "k_block_prep_gmem+k_block_flow_gmem" if staged else "k_block_solve_gmem"
         kernels[name] = kernels.pop("k_block_solve_one")
     if p.solver == "lsatr":

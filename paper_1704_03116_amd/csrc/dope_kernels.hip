@@ -991,6 +991,9 @@ constexpr int ELIM_BATCH = 4;
 // PREP_SLICES_MAX slices per block (their free counts fill int32 slots 1..8 of the block region's header).
 constexpr int PREP_SLICE_MAX = 4096;
 constexpr int PREP_SLICES_MAX = 8;
+// Blocks of at most this many nodes keep the one-launch solver: the second launch and the copy of the node arrays
+// cost more than the spread prologue gains there (64 blocks of 70x70 pixels, one iteration: 14 vs 18 us).
+constexpr int PREP_MIN_NP = 8192;
 
 // Keeps the list entries that are still free (order not preserved); returns their count.  The height array,
 // not yet in use, holds the survivors by list position in between.  Whole workgroup; ctr is a zeroed LDS slot.
@@ -2960,7 +2963,7 @@ hipError_t launch_maxflow_gmem(const Group &grp, hipStream_t s, hipEvent_t e0, h
     const int32_t split = node_lds <= MAXFLOW_LDS_LIMIT ? 1 : 0;
     const uint32_t lds = split ? uint32_t(node_lds) : 0u;
     if constexpr (2 * Sten<CONN>::H <= 8) {
-        if (split) {
+        if (split && grp.npmax > PREP_MIN_NP) {
             // two launches: slices of every block's prologue and elimination on several CUs, then the rest
             static std::once_flag flow_once;
             static hipError_t flow_err = hipSuccess;

@@ -614,7 +614,10 @@ def test_blocks_beyond_lds_smoothing_dominated_flow():
     """Large blocks in global memory with smoothing far above the unaries: the push-relabel phase (its global-memory
     atomics, barrier slots and list compaction) runs in every block of the first iterations, and the state still
     equals the oracle's after every iteration."""
-    for conn, dims, block in [(8, (180, 150, 1), (100, 80, 1)), (6, (34, 30, 26), (20, 18, 16))]:
+    # 8000 and 5760 nodes: one launch per block; 9000 (above 8192): the prologue and a first elimination spread
+    # over several workgroups per block, then the flow phases
+    for conn, dims, block in [(8, (180, 150, 1), (100, 80, 1)), (6, (34, 30, 26), (20, 18, 16)),
+                              (8, (190, 170, 1), (100, 90, 1))]:
         p = synth.random_problem(27, dims, conn, block, (2, 2, 2 if conn == 6 else 0), lam_q8=512,
                                  u_range=(-400, 400), w_range=(200, 1000), mu0=4000)
         stats = []
