@@ -561,6 +561,8 @@ def main():
                     help="requests of the serving replay (first requests of the 2000-request trace; 0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=64, help="max admitted requests when serving")
     ap.add_argument("--serve-iters", type=int, default=4, help="batched ADMM iterations per serving tick")
+    ap.add_argument("--metrics", default="",
+                    help="also write per-iteration metrics of one headline solve (untimed) to this JSON-lines file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a 256 MiB device-to-device copy three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -592,6 +594,11 @@ def main():
                        torch.from_numpy(np.ascontiguousarray(p.w, np.int32)).cuda(), p.lam_q8)
     d.iterate(sample_iters)
     Yg, Ag, yhg, mug, tg = d.get_state()
+    if args.metrics:
+        # one more solve of the same input, iteration by iteration, after the timed region
+        d.set_energy_async(torch.from_numpy(np.ascontiguousarray(p.u, np.int32)).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(p.w, np.int32)).cuda(), p.lam_q8)
+        d.iterate_metrics(p.max_iter, args.metrics)
     d.close()
     out = {
         "metric": "Mpixel/s to converged bit-exact labelling",

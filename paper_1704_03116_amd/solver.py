@@ -186,6 +186,47 @@ class Dope:
         N.check(N.dope_solve(self.ctx, ctypes.byref(info)), self.ctx)
         return _info(info)
 
+    def iterate_metrics(self, n_iter, path=None):
+        """Runs up to n_iter iterations one at a time and returns one record per iteration: t, status, the
+        stopping test (max_k r_k, converged), mu, and the block solves' statistics (free nodes, push-relabel
+        rounds, global relabels, elimination passes: sum and max over blocks) with the block of the largest
+        residual.  Stops after the iteration that meets the stopping test (Algorithm 1's while-condition), when
+        the loop halts (t no longer advances) or when an iteration fails.  path: also written there as JSON
+        lines."""
+        import json
+        out = []
+        fh = open(path, "w") if path else None
+        try:
+            t_prev = None
+            for _ in range(int(n_iter)):
+                status, info = self.iterate_status(1)
+                if status != N.DOPE_OK:
+                    out.append({"t": info["iters_done"], "status": int(status)})
+                    if fh:
+                        fh.write(json.dumps(out[-1]) + "\n")
+                    break
+                if info["iters_done"] == t_prev:
+                    break
+                t_prev = info["iters_done"]
+                st = self.block_stats()
+                r = self.block_resid()
+                rec = {"t": info["iters_done"], "status": 0, "max_resid2": int(info["max_resid2"]),
+                       "converged": info["converged"], "mu": int(info["mu"]),
+                       "worst_block": int(np.argmax(r)) if len(r) else -1,
+                       "free_nodes": {"sum": int(st[:, 0].sum()), "max": int(st[:, 0].max())},
+                       "pushrelabel_rounds": {"sum": int(st[:, 1].sum()), "max": int(st[:, 1].max())},
+                       "global_relabels_max": int(st[:, 2].max()),
+                       "elimination_passes_max": int(st[:, 3].max())}
+                out.append(rec)
+                if fh:
+                    fh.write(json.dumps(rec) + "\n")
+                if rec["converged"]:
+                    break
+        finally:
+            if fh:
+                fh.close()
+        return out
+
     def labels(self, out=None):
         if out is None:
             out = np.zeros(self.n, dtype=np.uint8)

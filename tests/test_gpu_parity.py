@@ -134,6 +134,36 @@ def test_random_shapes_every_iteration(case):
     d.close()
 
 
+@pytest.mark.parametrize("which", ["config1", "config2_small"])
+def test_per_iteration_metrics_match_the_oracle(which, tmp_path):
+    """iterate_metrics: one record per iteration whose t, max_k r_k, stopping flag, mu and block of the largest
+    residual equal the oracle's, iteration by iteration; the loop that converges stops at the oracle's iteration;
+    the JSON-lines file holds the same records."""
+    import json
+    p = synth.config1() if which == "config1" else synth.config2(W=100, H=90)
+    n_max = 8
+    dec = od.decompose(p)
+    st = od.initial_state(dec, p.mu0)
+    expect = []
+    for _ in range(n_max):
+        st, inf = od.iterate(dec, st, threads=ORACLE_THREADS, mu_num=p.mu_num, mu_den=p.mu_den, eps_q16=p.eps_q16)
+        expect.append((st.t, int(np.max(inf.resid2)), inf.converged, st.M, int(np.argmax(inf.resid2))))
+        if inf.converged:
+            break
+    d = make_ctx(p)
+    try:
+        path = tmp_path / "metrics.jsonl"
+        recs = d.iterate_metrics(n_max, str(path))
+    finally:
+        d.close()
+    got = [(r["t"], r["max_resid2"], r["converged"], r["mu"], r["worst_block"]) for r in recs]
+    assert got == expect
+    assert all(r["status"] == 0 for r in recs)
+    assert [json.loads(line) for line in path.read_text().splitlines()] == recs
+    if which == "config2_small":
+        assert recs[-1]["converged"] and len(recs) < n_max
+
+
 def test_smoothing_dominated_blocks():
     """Weak unaries, strong edges: almost no node is forced, so push-relabel does all the work."""
     p = synth.random_problem(12, (48, 40, 1), 8, (16, 16, 1), (1, 1, 0), lam_q8=768, u_range=(-400, 400),
