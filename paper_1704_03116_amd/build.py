@@ -20,7 +20,14 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wal
 STENCILS = [4, 8, 24, 48, 80, 6, 32, 122, 256]
 
 
-def build(verbose: bool = False) -> str:
+# The instrumented variant: the block max-flow of the 3x3 stencils checks its cut (DOPE_DEBUG) and reports a
+# violation as a solver error; every other unit is the normal build's object.
+DEBUG_OUT = os.path.join(HERE, "libdope_debug.so")
+DEBUG_STENCILS = [4, 8, 6]
+
+
+def build(verbose: bool = False, debug: bool = True) -> str:
+    """Builds libdope.so and, unless debug is False, libdope_debug.so.  Returns the path of libdope.so."""
     from concurrent.futures import ThreadPoolExecutor
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -31,6 +38,8 @@ def build(verbose: bool = False) -> str:
              ([os.path.join(CSRC, "dope_noalloc.hip")], "dope_noalloc.o", []),
              ([os.path.join(CSRC, "dope_probe.hip")], "dope_probe.o", []),
              ([os.path.join(CSRC, "dope_multilabel.hip")], "dope_multilabel.o", [])]
+    debug_units = [([kern], f"dope_kernels_{c}_debug.o", [f"-DDOPE_CONN={c}", "-DDOPE_DEBUG"])
+                   for c in DEBUG_STENCILS] if debug else []
     compile_flags = [f for f in FLAGS if f != "-shared"]
 
     def compile_one(unit):
@@ -41,15 +50,22 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         return os.path.join(objdir, obj)
 
-    workers = max(1, min(len(units), os.cpu_count() or 1))
+    def link(objs, out):
+        tmp = out + ".tmp"
+        cmd = [HIPCC, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, out)
+
+    workers = max(1, min(len(units) + len(debug_units), os.cpu_count() or 1))
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        objs = list(ex.map(compile_one, units))
-    tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp] + objs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, OUT)
+        objs = list(ex.map(compile_one, units + debug_units))
+    link(objs[:len(units)], OUT)
+    if debug:
+        swap = {f"dope_kernels_{c}.o": f"dope_kernels_{c}_debug.o" for c in DEBUG_STENCILS}
+        link([os.path.join(objdir, swap.get(os.path.basename(o), os.path.basename(o))) for o in objs[:len(units)]],
+             DEBUG_OUT)
     return OUT
 
 

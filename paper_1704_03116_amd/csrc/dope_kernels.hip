@@ -1217,6 +1217,24 @@ DOPE_UNROLL
         });
         if (!sy.any(grew)) break;
     }
+#ifdef DOPE_DEBUG
+    // (5) debug builds only: the marked set is the canonical cut of a maximum preflow -- every node holding
+    //     excess is marked, no residual arc leaves the marked set, and no marked node has sink capacity left
+    //     (dd < 0: an augmenting path from an excess) -- else the block reports a solver error
+    bool bad = false;
+    nodes.each([&](int p) {
+        if (fixed(p)) return;
+        const bool mk = (L.st[p] & ST_MARK) != 0;
+        if (L.dd[p] > 0 && !mk) bad = true;
+        if (!mk) return;
+        if (L.dd[p] < 0) bad = true;
+        const DirMask<CONN> m = L.msk[p];
+DOPE_UNROLL
+        for (int d = 0; d < ND; ++d)
+            if (((m >> d) & 1u) && L.res(p, d) > 0 && !(L.st[L.nbr(p, d)] & ST_MARK)) bad = true;
+    });
+    if (sy.any(bad)) fs.fail = true;
+#endif
 }
 
 // flow_network over the thread's list entries: held in registers when there are at most MAXPT per thread and the

@@ -164,6 +164,26 @@ def test_per_iteration_metrics_match_the_oracle(which, tmp_path):
         assert recs[-1]["converged"] and len(recs) < n_max
 
 
+@pytest.mark.timeout(600)
+def test_debug_build_cut_checks_hold():
+    """The instrumented build (libdope_debug.so: the block max-flow of the 3x3 stencils checks that its marked set
+    contains every excess, is closed under residual arcs and holds no sink capacity, else the iteration fails with
+    a solver error) runs push-relabel-heavy and tie-prone problems, in LDS and in the two-launch global-memory
+    solve, with every iteration succeeding and the whole state equal to the oracle's (in a process of its own,
+    which loads that library)."""
+    import subprocess
+    import sys
+    lib = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1704_03116_amd",
+                       "libdope_debug.so")
+    if not os.path.exists(lib):
+        pytest.skip("libdope_debug.so not built (the library build makes it)")
+    child = os.path.join(os.path.dirname(os.path.abspath(__file__)), "debug_build_child.py")
+    r = subprocess.run([sys.executable, "-u", child], capture_output=True, text=True, timeout=540)
+    announce(r.stdout.strip())
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.strip().endswith("debug build ok")
+
+
 def test_smoothing_dominated_blocks():
     """Weak unaries, strong edges: almost no node is forced, so push-relabel does all the work."""
     p = synth.random_problem(12, (48, 40, 1), 8, (16, 16, 1), (1, 1, 0), lam_q8=768, u_range=(-400, 400),
