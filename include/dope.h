@@ -169,7 +169,8 @@ dope_status dope_set_state(dope_ctx *ctx, const int32_t *Y, const int32_t *A, co
 dope_status dope_block_resid(dope_ctx *ctx, int64_t *resid);
 
 /* Per-block solver statistics of the last iteration, int32[K * 4]:
- * {free nodes after forced-node elimination, push/relabel rounds, global relabels, forced-node cascade rounds};
+ * {free nodes after the strict forcing test (|U~| > sum of capacities; before the cascading elimination),
+ *  push/relabel rounds, global relabels, elimination passes of the block's workgroup};
  * with the LSA-TR solver: {free nodes of the last step, push/relabel rounds over all steps, steps, final level}. */
 dope_status dope_block_stats(dope_ctx *ctx, int32_t *stats);
 

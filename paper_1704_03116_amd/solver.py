@@ -188,9 +188,9 @@ class Dope:
 
     def iterate_metrics(self, n_iter, path=None):
         """Runs up to n_iter iterations one at a time and returns one record per iteration: t, status, the
-        stopping test (max_k r_k, converged), mu, and the block solves' statistics (free nodes, push-relabel
-        rounds, global relabels, elimination passes: sum and max over blocks) with the block of the largest
-        residual.  Stops after the iteration that meets the stopping test (Algorithm 1's while-condition), when
+        stopping test (max_k r_k, converged), mu, and the block solves' statistics (free nodes after the strict
+        forcing test, push-relabel rounds, global relabels, elimination passes: sum and max over blocks) with the
+        block of the largest residual.  Stops after the iteration that meets the stopping test (Algorithm 1's while-condition), when
         the loop halts (t no longer advances) or when an iteration fails.  path: also written there as JSON
         lines."""
         import json
